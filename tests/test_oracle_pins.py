@@ -1,0 +1,497 @@
+"""Pins of the FP64 oracle against facts the paper's model fixes (CPU only).
+
+Each test names the pin it implements and what a plausible mistake in the
+oracle would break.  None of them re-types the oracle's own formulas: they
+use closed forms of the discrete scheme, symmetries, conservation laws and
+brute-force enumeration.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1710_10420_amd.inputs import splitmix64, uniform_field, uniform_sites
+from tests import fields as F
+
+import os
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- inputs ----
+
+def test_splitmix64_known_answer():
+    """Initial-field generator: the published SplitMix64 sequence (seed 1234567)."""
+    want = [int(l) for l in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt"))
+            if l.strip() and not l.startswith("#")]
+    got = [int(v) for v in splitmix64(1234567, np.arange(1, 6, dtype=np.uint64))]
+    assert got == want
+
+
+def test_uniform_field_properties():
+    """Values are odd multiples of 2^-24 in (-1, 1), never 0, mean ~ 0, and a
+    site's value does not depend on how the index range is split."""
+    v = uniform_sites(7, 0, 1 << 18)
+    assert v.dtype == np.float32
+    k = (v.astype(np.float64) + 1.0) * 2.0 ** 24
+    assert np.all(k == np.round(k)) and np.all(np.round(k) % 2 == 1)
+    assert np.all(np.abs(v) < 1.0) and np.all(v != 0.0)
+    assert abs(float(v.mean())) < 4.0 / math.sqrt(v.size)          # 4 sigma
+    assert abs(float((v.astype(np.float64) ** 2).mean()) - 1.0 / 3.0) < 0.01
+    np.testing.assert_array_equal(uniform_sites(7, 1000, 50), v[1000:1050])
+    f = uniform_field((5, 3, 2), 9)
+    assert f.shape == (2, 3, 5)
+    np.testing.assert_array_equal(f.reshape(-1), uniform_sites(9, 0, 30))
+
+
+# --------------------------------------------------- P1 vacuum, P2 Z2 -------
+
+@pytest.mark.parametrize("shape", [(8, 6), (4, 5, 3)])
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_p1_vacuum_is_static_bitwise(shape, sign):
+    """P1: phi = +-phi0 and phi_dot = 0 stay exactly static for any damping
+    (V'(+-1) = 0 and the Laplacian of a constant is 0); no wall is seen."""
+    p = O.params(shape, deta=0.25, alpha=3.0, m=2.0, W0=5.0)
+    phi = np.full(int(np.prod(shape)), sign)
+    pi = np.zeros_like(phi)
+    ph, pp, recs = O.run(p, phi, pi, 40, diag_every=10)
+    np.testing.assert_array_equal(ph, phi)
+    np.testing.assert_array_equal(pp, pi)
+    for r in recs:
+        assert r["links"] == 0 and r["wall_sites"] == 0 and r["area_density"] == 0.0
+        assert r["gv2"] == 0.0 and r["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("shape", [(16, 12), (6, 5, 7)])
+def test_p2_z2_symmetry_bitwise(shape):
+    """P2: phi -> -phi commutes with the evolution bit for bit (the potential
+    is even and IEEE rounding is sign symmetric); link counts are unchanged."""
+    p = O.params(shape, deta=0.25, m=1.0, W0=4.0)
+    phi = uniform_field(shape, 11).astype(np.float64).reshape(-1)
+    pi = np.zeros_like(phi)
+    a, pa, ra = O.run(p, phi, pi, 30, diag_every=5)
+    b, pb, rb = O.run(p, -phi, -pi, 30, diag_every=5)
+    np.testing.assert_array_equal(a, -b)
+    np.testing.assert_array_equal(pa, -pb)
+    for x, y in zip(ra, rb):
+        assert x["links_dir"] == y["links_dir"] and x["wall_sites"] == y["wall_sites"]
+        assert x["area_density"] == y["area_density"] and x["gv2"] == y["gv2"]
+
+
+# ---------------------------------------- P3 translation, P4 reflection -----
+
+@pytest.mark.parametrize("shape,shift", [((20, 14), (7, 3)), ((9, 7, 6), (4, 2, 5))])
+def test_p3_translation_bitwise(shape, shift):
+    """P3: a periodic shift commutes with the evolution bit for bit; catches
+    wrong neighbour indices and boundary wrap."""
+    p = O.params(shape, deta=0.25, m=1.0, W0=5.0)
+    phi = uniform_field(shape, 5).astype(np.float64)
+    pi = np.zeros_like(phi)
+    axes = tuple(range(len(shape) - 1, -1, -1))        # numpy axis of x, y, z
+    roll = lambda a: np.roll(a.reshape(phi.shape), shift, axis=axes)
+    a, pa, ra = O.run(p, phi, pi, 25, diag_every=5)
+    b, pb, rb = O.run(p, roll(phi), roll(pi), 25, diag_every=5)
+    np.testing.assert_array_equal(roll(a).reshape(-1), b)
+    np.testing.assert_array_equal(roll(pa).reshape(-1), pb)
+    for x, y in zip(ra, rb):
+        assert x["links_dir"] == y["links_dir"] and x["wall_sites"] == y["wall_sites"]
+
+
+@pytest.mark.parametrize("shape", [(15, 10), (7, 6, 5)])
+def test_p4_reflection_bitwise(shape):
+    """P4: x -> -x (mod N) commutes with the evolution bit for bit, because
+    each axis contributes the commutative pair sum (phi_+ + phi_-)."""
+    p = O.params(shape, deta=0.25, m=1.0, W0=5.0)
+    phi = uniform_field(shape, 8).astype(np.float64)
+    pi = np.zeros_like(phi)
+    xa = phi.ndim - 1
+
+    def refl(a):
+        a = a.reshape(phi.shape)
+        return np.roll(np.flip(a, axis=xa), 1, axis=xa)   # x -> (N - x) mod N
+
+    a, pa, _ = O.run(p, phi, pi, 25)
+    b, pb, _ = O.run(p, refl(phi), refl(pi), 25)
+    np.testing.assert_array_equal(refl(a).reshape(-1), b)
+    np.testing.assert_array_equal(refl(pa).reshape(-1), pb)
+
+
+# ----------------------------------------------------- P5 static kinks ------
+
+def antisymmetric_pair(shape, W0):
+    """Wall pair at x1 = N/4 - 1/2 and x1 + N/2, made exactly antisymmetric
+    under x -> 2 x1 - x by mirroring one half."""
+    nx = shape[0]
+    x1 = nx / 4.0 - 0.5
+    x = F.coords(shape)[0].astype(np.float64)
+    u = np.mod(x - x1, nx)                       # in (0, N)
+    v = np.where(u < nx / 2.0, u, u - nx / 2.0)  # distance from the wall on the left
+    g = np.tanh(math.pi * v / W0) * np.tanh(math.pi * (nx / 2.0 - v) / W0)
+    return np.where(u < nx / 2.0, g, -g), x1
+
+
+@pytest.mark.parametrize("shape", [(128, 4), (64, 4, 3)])
+def test_p5_static_kink_pair(shape):
+    """P5: in flat space (alpha = 0) the tanh wall of width W0/pi with
+    V0 = pi^2/(2 W0^2) is static up to discretisation error; the crossing
+    stays exactly at x1 (antisymmetry is preserved bit for bit), the links
+    stay 2 N^(D-1) and rho = 2/N exactly (transverse gradients vanish)."""
+    W0 = 10.0
+    p = O.params(shape, deta=0.25, alpha=0.0, m=1.0, W0=W0)
+    phi0, x1 = antisymmetric_pair(shape, W0)
+    pi0 = np.zeros_like(phi0)
+    nx = shape[0]
+    xa = phi0.ndim - 1
+    # x -> 2 x1 - x = (N/2 - 1) - x  (mod N)
+    idx = (nx // 2 - 1 - np.arange(nx)) % nx
+    phi, pi = phi0.reshape(-1), pi0.reshape(-1)
+    drift = []
+    n = 0
+    transverse = int(np.prod(shape[1:]))
+    for chunk in [500] * 16:
+        phi, pi, recs = O.run(p, phi, pi, chunk, n0=n, diag_every=250)
+        n += chunk
+        f = phi.reshape(phi0.shape)
+        np.testing.assert_array_equal(f, -np.take(f, idx, axis=xa))
+        drift.append(float(np.max(np.abs(phi - phi0.reshape(-1)))))
+        for r in recs:
+            assert r["links"] == 2 * transverse and r["links_dir"][0] == 2 * transverse
+            assert r["area_density"] == 2.0 / nx
+    # the continuum profile relaxes onto the lattice kink and breathes around
+    # it with an O(dx^2/w^2) amplitude (~0.01 at w = W0/pi = 3.2) that stays
+    # bounded over 8000 steps; a potential 10 % too strong or too weak already
+    # moves the field by ~0.04
+    assert max(drift) < 1.5e-2
+
+
+# ------------------------------------------------ P6 energy conservation ----
+
+def energy_series(p, phi, pi, steps):
+    out = []
+    for n in range(steps):
+        phi_next, pi_next = O.step(p, n, phi, pi)
+        out.append(O.energy(p, phi, pi, pi_next))
+        phi, pi = phi_next, pi_next
+    return np.array(out)
+
+
+@pytest.mark.parametrize("shape", [(24, 20), (8, 7, 6)])
+def test_p6_free_field_energy_exact(shape):
+    """P6a: with V0 = 0 and alpha = 0 the leapfrog conserves
+    E = sum[1/2 pi^{n-1/2} pi^{n+1/2} + 1/2 (grad phi)^2] to roundoff."""
+    p = O.params(shape, deta=0.2, alpha=0.0, m=1.0, W0=math.inf)
+    phi = uniform_field(shape, 4).astype(np.float64).reshape(-1)
+    pi = 0.3 * uniform_field(shape, 5).astype(np.float64).reshape(-1)
+    e = energy_series(p, phi, pi, 300)
+    assert np.max(np.abs(e - e[0])) / abs(e[0]) < 1e-12
+
+
+def test_p6_kink_energy_bounded():
+    """P6b: with the quartic potential the leapfrog energy stays bounded with
+    no drift (a wrong force sign or coefficient breaks this at once)."""
+    shape = (128, 16)
+    W0 = 10.0
+    p = O.params(shape, deta=0.25, alpha=0.0, m=1.0, W0=W0)
+    phi, _ = antisymmetric_pair(shape, W0)
+    phi = phi + 0.05 * F.cosine_mode(shape, (3, 1))
+    phi = phi.reshape(-1)
+    pi = np.zeros_like(phi)
+    e = energy_series(p, phi, pi, 2000)
+    spread = (e.max() - e.min()) / abs(e.mean())
+    assert spread < 1e-4
+    # no secular drift between the first and the last quarter
+    q = len(e) // 4
+    assert abs(e[-q:].mean() - e[:q].mean()) / abs(e.mean()) < 2e-5
+
+
+# -------------------------------------------------- P7 linear dispersion ----
+
+def dispersion_check(shape, ks, dx, deta, W0, base, eps, steps):
+    p = O.params(shape, deta=deta, alpha=0.0, m=1.0, W0=W0, dx=dx)
+    mode = F.cosine_mode(shape, ks, base=0.0, eps=1.0)
+    phi = (base + eps * mode).reshape(-1)
+    pi = np.zeros_like(phi)
+    # omega^2 of the discrete operator: sum_d 4 sin^2(pi k_d / n_d)/dx^2 + V''(base)
+    w2 = sum(4.0 * math.sin(math.pi * k / n) ** 2 for k, n in zip(ks, shape)) / dx ** 2
+    w2 += 4.0 * p.V0 * (3.0 * base * base - 1.0) if p.V0 else 0.0
+    s = deta * math.sqrt(w2) / 2.0
+    assert s < 1.0
+    theta = 2.0 * math.asin(s)
+    worst = 0.0
+    for n in range(1, steps + 1):
+        phi, pi = O.step(p, n - 1, phi, pi)
+        want = base + eps * mode.reshape(-1) * math.cos((n + 0.5) * theta) / math.cos(theta / 2)
+        worst = max(worst, float(np.max(np.abs(phi - want))) / eps)
+    return worst
+
+
+@pytest.mark.parametrize("shape,ks,dx,deta", [
+    ((24, 16), (3, 2), 0.5, 0.1),
+    ((12, 10, 8), (1, 2, 3), 1.0, 0.2),
+])
+def test_p7_free_dispersion(shape, ks, dx, deta):
+    """P7a: with V0 = 0 a Fourier mode follows the closed form of the
+    discrete scheme, cos((n+1/2) theta)/cos(theta/2), with
+    sin(theta/2) = (deta/2) sqrt(sum_d 4 sin^2(k_d dx/2)/dx^2).  Pins every
+    Laplacian coefficient, the 1/dx^2 and the kick/drift staggering."""
+    assert dispersion_check(shape, ks, dx, deta, math.inf, 0.0, 1.0, 60) < 1e-12
+
+
+@pytest.mark.parametrize("shape,ks", [((16, 12), (2, 1)), ((8, 8, 6), (1, 0, 1))])
+def test_p7_vacuum_dispersion(shape, ks):
+    """P7b: a small mode on the vacuum phi = 1 oscillates with
+    omega^2 = lattice k^2 + V''(1), V''(1) = 8 V0, pinning the force."""
+    assert dispersion_check(shape, ks, 1.0, 0.2, 5.0, 1.0, 1e-6, 80) < 1e-4
+
+
+# ------------------------------------------------------------ P8 damping ----
+
+@pytest.mark.parametrize("alpha,m", [(3.0, 1.0), (3.0, 2.0), (3.0, 0.5)])
+def test_p8_damping_power_law(alpha, m):
+    """P8: for a homogeneous free field phi_dot decays like eta^(-alpha m):
+    pi^{n+1/2} / pi^{-1/2} -> (eta_{n+1/2} / eta_{-1/2})^(-alpha m) at
+    O(deta^2).  Pins delta = alpha deta m / (2 eta_n) and its time level (using
+    eta_{n+1} instead of eta_n is off by ~3 % here)."""
+    deta = 0.005
+    p = O.params((4, 4), deta=deta, alpha=alpha, m=m, W0=math.inf)
+    phi = np.full(16, 0.3)
+    pi = np.full(16, 0.7)
+    steps = 1800
+    ph, pp, _ = O.run(p, phi, pi, steps)
+    eta_half = 1.0 + (steps - 0.5) * deta
+    want = 0.7 * (eta_half / (1.0 - 0.5 * deta)) ** (-alpha * m)
+    assert np.all(pp == pp[0])
+    assert abs(pp[0] / want - 1.0) < 1e-3
+    # phi integrates phi_dot exactly: phi^S = phi^0 + deta * sum pi^{n+1/2}
+    assert abs(ph[0] - 0.3) > 0.0
+
+
+# ------------------------------------------------------ P9 link counting ----
+
+def brute_counts(signs, shape):
+    """Enumerate the D * N^D forward links (site, +e_d) of the periodic
+    lattice and the sites touching a crossing link, straight from the
+    definition."""
+    D = len(shape)
+    n = int(np.prod(shape))
+    strides = [int(np.prod(shape[:d])) for d in range(D)]
+    coords = lambda i: [(i // strides[d]) % shape[d] for d in range(D)]
+    index = lambda c: sum(c[d] * strides[d] for d in range(D))
+    per_dir = [0] * 3
+    wall = [False] * n
+    for i in range(n):
+        c = coords(i)
+        for d in range(D):
+            cj = list(c)
+            cj[d] = (cj[d] + 1) % shape[d]
+            j = index(cj)
+            if signs[i] != signs[j]:
+                per_dir[d] += 1
+                wall[i] = wall[j] = True
+    return per_dir, sum(wall)
+
+
+@pytest.mark.parametrize("shape,limit", [
+    ((1, 1), None), ((2, 1), None), ((2, 2), None), ((3, 3), None), ((4, 3), None),
+    ((4, 4), 3000), ((5, 5), 800), ((5, 2), None),
+    ((1, 1, 1), None), ((2, 2, 2), None), ((3, 2, 2), None), ((3, 3, 3), 600),
+])
+def test_p9_link_counts_brute_force(shape, limit):
+    """P9: crossing-link and wall-site counts equal brute-force enumeration
+    over sign patterns (all of them where feasible), including N = 1
+    (self links never cross) and N = 2 (i+1 and i-1 coincide)."""
+    n = int(np.prod(shape))
+    p = O.params(shape, deta=0.25)
+    patterns = range(1 << n)
+    if limit is not None:
+        rng = np.random.default_rng(n)
+        patterns = [int(b) for b in rng.integers(0, 1 << n, size=limit, dtype=np.int64)]
+    for bits in patterns:
+        phi = F.signs_to_field(bits, shape).reshape(-1) * 0.5
+        r = O.stats(p, phi, np.zeros(n))
+        signs = [bool((bits >> i) & 1) for i in range(n)]
+        per_dir, walls = brute_counts(signs, shape)
+        assert r["links_dir"] == per_dir, (shape, bits)
+        assert r["wall_sites"] == walls, (shape, bits)
+        assert r["links"] == sum(per_dir)
+
+
+def test_p9_zero_tiebreak():
+    """A zero value (either sign of zero) counts as non-negative."""
+    p = O.params((4, 1), deta=0.25)
+    r = O.stats(p, np.array([0.0, -0.0, -1e-300, 1.0]), np.zeros(4))
+    # signs: + + - +  -> links (1,2) and (2,3)
+    assert r["links_dir"][0] == 2
+
+
+def test_nonfinite_count():
+    p = O.params((4, 2), deta=0.25)
+    phi = np.full(8, 0.5)
+    pi = np.zeros(8)
+    phi[3] = np.nan
+    pi[5] = np.inf
+    assert O.stats(p, phi, pi)["nonfinite"] == 2
+
+
+# --------------------------------------------------- P10 area closed forms --
+
+@pytest.mark.parametrize("shape", [(32, 32), (16, 16, 16)])
+def test_p10_axis_aligned_walls(shape):
+    """P10a: two flat walls normal to x give rho = 2/N (weights exactly 1)."""
+    x = F.coords(shape)[0]
+    phi = np.where((x >= shape[0] // 4) & (x < 3 * shape[0] // 4), 0.8, -0.6)
+    r = O.stats(O.params(shape, deta=0.25), phi.reshape(-1), np.zeros(phi.size))
+    assert r["area_density"] == pytest.approx(2.0 / shape[0], rel=1e-15)
+
+
+@pytest.mark.parametrize("shape", [(32, 32), (12, 12, 12)])
+def test_p10_diagonal_walls(shape):
+    """P10b: walls normal to (1,1[,1]) give rho = 2 sqrt(D)/N: each crossing
+    site has D crossing links of weight 1/sqrt(D)."""
+    N = shape[0]
+    s = sum(F.coords(shape)) % N
+    phi = np.where(s < N // 2, 0.7, -0.7)
+    r = O.stats(O.params(shape, deta=0.25), phi.reshape(-1), np.zeros(phi.size))
+    D = len(shape)
+    assert r["area_density"] == pytest.approx(2.0 * math.sqrt(D) / N, rel=1e-14)
+
+
+def test_p10_area_scales_with_dx():
+    """rho carries dx^(D-1)/dx^D = 1/dx for the same site pattern."""
+    shape = (16, 16)
+    x = F.coords(shape)[0]
+    phi = np.where(x < 8, 1.0, -1.0).reshape(-1)
+    r1 = O.stats(O.params(shape, deta=0.25, dx=1.0), phi, np.zeros(256))
+    r2 = O.stats(O.params(shape, deta=0.25, dx=0.5), phi, np.zeros(256))
+    assert r2["area_density"] == pytest.approx(2.0 * r1["area_density"], rel=1e-15)
+
+
+# ----------------------------------------------- P11 velocity closed form ---
+
+@pytest.mark.parametrize("shape", [(64, 8), (32, 6, 5)])
+@pytest.mark.parametrize("gv", [0.3, 2.0])
+def test_p11_boosted_wall_velocity(shape, gv):
+    """P11: a wall boosted to gamma v has phi_dot = -(gamma v / w) sech^2 with
+    w = W0/pi, i.e. phi_dot = -(gamma v/w)(1 - phi^2); then (1/2) phi_dot^2/V
+    equals (gamma v)^2 at every site, so Eq. (8) returns (gamma v)^2."""
+    W0 = 6.0
+    wdt = W0 / math.pi
+    phi, _ = antisymmetric_pair(shape, W0)
+    phi = phi.reshape(-1)
+    pi = -(gv / wdt) * (1.0 - phi * phi)
+    r = O.stats(O.params(shape, deta=0.25, W0=W0), phi, pi)
+    assert r["wall_sites"] == 4 * int(np.prod(shape[1:]))
+    assert r["gv2"] == pytest.approx(gv * gv, rel=1e-12)
+
+
+def test_p11_mean_over_wall_sites_only():
+    """Eq. (8) averages over the wall sites only: phi_dot placed away from the
+    walls does not enter, and the mean uses the wall-site count."""
+    shape = (16, 4)
+    x = F.coords(shape)[0]
+    phi = np.where((x >= 4) & (x < 12), 0.5, -0.5).reshape(-1)
+    V0 = O.v0_of_w0(10.0)
+    Vh = V0 * (0.25 - 1.0) ** 2
+    pi = np.zeros(64)
+    xs = x.reshape(-1)
+    pi[xs == 4] = 1.0           # wall sites: x = 3, 4, 11, 12
+    pi[xs == 7] = 100.0         # interior: ignored
+    r = O.stats(O.params(shape, deta=0.25, W0=10.0), phi, pi)
+    assert r["wall_sites"] == 16
+    assert r["gv2"] == pytest.approx((4 * 0.5 / Vh) / 16, rel=1e-14)
+
+
+# ------------------------------------------------------- split / cadence ----
+
+def test_split_run_equivalence_and_cadence():
+    """run(a+b) == run(a); run(b) bit for bit, and records fall on n % K == 0."""
+    shape = (20, 18)
+    p = O.params(shape, deta=0.25, m=1.0)
+    phi = uniform_field(shape, 2).astype(np.float64).reshape(-1)
+    pi = np.zeros_like(phi)
+    a, pa, ra = O.run(p, phi, pi, 37, diag_every=10)
+    b1, pb1, rb1 = O.run(p, phi, pi, 13, diag_every=10)
+    b, pb, rb2 = O.run(p, b1, pb1, 24, n0=13, diag_every=10)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(pa, pb)
+    assert [r["step"] for r in ra] == [0, 10, 20, 30]
+    assert ra == rb1 + rb2
+
+
+# ------------------------------------------------------------ Eq. 9 fit -----
+
+def test_fit_recovers_power_law():
+    eta = np.linspace(2.0, 500.0, 97)
+    assert O.fit_exponent(eta, 3.0 * eta ** -0.93) == pytest.approx(-0.93, abs=1e-12)
+    recs = [{"eta": e, "area_density": 2.0 / e, "gv2": 0.4 * e ** -0.08} for e in eta]
+    mu, nu = O.scaling_exponents(recs, eta_min=math.exp(2.58))
+    assert mu == pytest.approx(-1.0, abs=1e-12) and nu == pytest.approx(-0.04, abs=1e-12)
+
+
+# -------------------------------------------------------------- adjoint -----
+
+def fd_loss(p, phi, pi, steps):
+    ph, _, _ = O.run(p, phi, pi, steps)
+    return O.loss(p, ph)
+
+
+@pytest.mark.parametrize("steps", [16, 48])
+def test_adjoint_matches_finite_differences(steps):
+    """P13(i): the FP64 adjoint equals central finite differences of the
+    forward oracle (walls still present at these step counts)."""
+    shape = (32, 32)
+    p = O.params(shape, deta=0.25, m=1.0, W0=10.0)
+    phi = uniform_field(shape, 3).astype(np.float64).reshape(-1)
+    pi = np.zeros_like(phi)
+    adj = O.adjoint(p, phi, pi, steps, ckpt_every=7)
+    assert adj["loss"] == pytest.approx(fd_loss(p, phi, pi, steps), rel=1e-15)
+    g = adj["grad_phi"]
+    scale = np.max(np.abs(g))
+    eps = 1e-5
+    rng = np.random.default_rng(1)
+    for i in rng.choice(phi.size, size=6, replace=False):
+        e = np.zeros_like(phi)
+        e[i] = eps
+        fd = (fd_loss(p, phi + e, pi, steps) - fd_loss(p, phi - e, pi, steps)) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * scale, (i, fd, g[i])
+        fdp = (fd_loss(p, phi, pi + e, steps) - fd_loss(p, phi, pi - e, steps)) / (2 * eps)
+        assert abs(fdp - adj["grad_pi"][i]) <= 1e-6 * max(scale, np.max(np.abs(adj["grad_pi"])))
+    # wall thickness W0 (enters only through V0 = pi^2/(2 W0^2))
+    lw = lambda W: fd_loss(O.params(shape, deta=0.25, m=1.0, W0=W), phi, pi, steps)
+    fdw = (lw(10.0 + eps) - lw(10.0 - eps)) / (2 * eps)
+    assert adj["grad_W0"] == pytest.approx(fdw, rel=1e-6)
+
+
+def test_adjoint_dot_product_3d():
+    """P13(ii): <grad, v> equals the directional finite difference, in 3D."""
+    shape = (8, 7, 6)
+    p = O.params(shape, deta=0.2, m=2.0, W0=5.0)
+    phi = uniform_field(shape, 6).astype(np.float64).reshape(-1)
+    pi = 0.1 * uniform_field(shape, 7).astype(np.float64).reshape(-1)
+    v = uniform_field(shape, 8).astype(np.float64).reshape(-1)
+    u = uniform_field(shape, 9).astype(np.float64).reshape(-1)
+    steps = 20
+    adj = O.adjoint(p, phi, pi, steps, ckpt_every=64)
+    # central differences converge as eps^2 (1e-2 -> 1.9e-5, 1e-3 -> 1.9e-7);
+    # below ~1e-5 the loss's rounding takes over
+    eps = 1e-4
+    fd = (fd_loss(p, phi + eps * v, pi + eps * u, steps)
+          - fd_loss(p, phi - eps * v, pi - eps * u, steps)) / (2 * eps)
+    dot = float(adj["grad_phi"] @ v + adj["grad_pi"] @ u)
+    assert dot == pytest.approx(fd, rel=1e-7)
+
+
+def test_adjoint_checkpoint_interval_invariant():
+    """Recomputation from checkpoints reproduces the trajectory exactly, so
+    the gradient does not depend on the checkpoint interval."""
+    shape = (12, 10)
+    p = O.params(shape, deta=0.25, m=1.0, W0=10.0)
+    phi = uniform_field(shape, 4).astype(np.float64).reshape(-1)
+    pi = np.zeros_like(phi)
+    ref = O.adjoint(p, phi, pi, 30, ckpt_every=1)
+    for K in (4, 7, 30, 64):
+        got = O.adjoint(p, phi, pi, 30, ckpt_every=K)
+        np.testing.assert_array_equal(got["grad_phi"], ref["grad_phi"])
+        np.testing.assert_array_equal(got["grad_pi"], ref["grad_pi"])
+        assert got["dL_dV0"] == ref["dL_dV0"]
