@@ -1,0 +1,169 @@
+"""Benchmark of the PRS domain-wall hot path on one MI355X.
+
+One benchmark step is one whole run of the 2D matter-era workload: a
+8192^2 periodic lattice, W0 = 10, m = 2, deta = 0.25, eta 1 -> 4096
+(16380 leapfrog steps), seeded uniform initial field, wall diagnostics fused
+every 64 steps plus the final state, and the scaling-exponent fit over the
+last decade.  The metric is lattice-site updates per second (sites x steps /
+wall time), with the inputs already in HBM when the timed region starts.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects for how
+the kernel and the oracle were measured).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_UPDATE = 16          # read phi, phi_dot; write phi^{n+1}, phi_dot (FP32)
+
+WORKLOAD = {
+    "name": "2D PRS 8192^2, matter era m=2, W0=10, deta=0.25, eta 1->4096 (16380 steps), "
+            "diagnostics every 64 steps + final, exponent fit over the last decade",
+    "shape": (8192, 8192), "m": 2.0, "W0": 10.0, "deta": 0.25, "eta_end": 4096.0,
+    "diag_every": 64, "seed": 1,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def n_steps(w):
+    return int(round((w["eta_end"] - 1.0) / w["deta"]))
+
+
+def one_run(sim, prs, w, S, stream_handle):
+    """Reset to the seeded initial field and run the whole evolution."""
+    cur_phi = prs.prs_get_state(sim.ctx)[0]
+    prs.prs_fill_uniform(cur_phi, sim.phi_a.numel(), w["seed"], stream_handle)
+    sim.dphi.zero_()
+    prs.prs_set_state(sim.ctx, None, None, 0)
+    recs = sim.step_n(S)
+    recs.append(sim.wall_stats())
+    mu, nu = prs.prs_fit_scaling(recs, w["eta_end"] / 10.0)
+    return recs, mu, nu
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The FP64 oracle on the host cores over a bounded prefix of the same
+    run (the first steps from the same seeded field)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1710_10420_amd.inputs import uniform_field
+
+    shape = w["shape"]
+    op = O.params(shape, deta=w["deta"], m=w["m"], W0=w["W0"])
+    phi = uniform_field(shape, w["seed"]).astype(np.float64).reshape(-1)
+    pi = np.zeros_like(phi)
+    threads = len(os.sched_getaffinity(0))
+    O.set_threads(threads)
+    sites = phi.size
+    t0 = time.perf_counter()
+    O.run(op, phi, pi, 1)                       # calibration step
+    per = time.perf_counter() - t0
+    steps = max(2, min(64, int(budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    O.run(op, phi, pi, steps, diag_every=w["diag_every"])
+    dt = time.perf_counter() - t0
+    return {"value": sites * steps / dt, "unit": "site-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "FP64 oracle, first %d of %d steps of the same 8192^2 run "
+                      "(diagnostics every 64 included), %.1f s" % (steps, n_steps(w), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the PRS path is built and timed on a single "
+              "MI355X (no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1710_10420_amd import prs
+
+    w = WORKLOAD
+    S = n_steps(w)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sh = prs._stream_handle(stream)
+    gp = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"],
+                         diag_every=w["diag_every"])
+    sites = prs.sites(gp)
+    sim = prs.Sim(gp, seed=w["seed"])
+    log("tiling", sim.tiling(), "steps/run", S)
+
+    for i in range(args.warmup):
+        log("warmup run", i)
+        one_run(sim, prs, w, S, sh)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    results = []
+    for i in range(args.steps):
+        results.append(one_run(sim, prs, w, S, sh))
+        log("timed run", i, "done")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+
+    updates = float(sites) * S * args.steps
+    value = updates / wall
+    # dominant kernel: the fused step (S launches per run); its average
+    # duration from the stream events over the timed region is an upper bound
+    # (the region also holds the 258 diagnostic finalize launches and the
+    # initial-field fill of each run)
+    launches = S * args.steps
+    avg_launch_s = ev_ms / 1e3 / launches
+    achieved = BYTES_PER_UPDATE * sites / avg_launch_s / 1e9
+    recs, mu, nu = results[-1]
+    out = {
+        "metric": "site-updates/s (PRS forward step, fused wall diagnostics)",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded uniform(-1,1) initial field (SplitMix64), phi_dot = 0",
+        "config": {"workload": w["name"], "sites": sites, "steps_per_run": S,
+                   "records_per_run": len(recs), "tiling": list(sim.tiling())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step<2,4,1,update> (fused Laplacian+kick+drift[+diagnostics])",
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "result": {"mu": mu, "nu": nu, "final_links": recs[-1]["links"],
+                   "final_area_density": recs[-1]["area_density"]},
+    }
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

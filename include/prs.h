@@ -1,0 +1,265 @@
+/*
+ * prs.h -- C ABI of the MI355X (gfx950) Press-Ryden-Spergel domain-wall
+ * evolution library (libprs.so).
+ *
+ * The method is that of Correia & Martins, "General purpose graphics-
+ * processing-unit implementation of cosmological domain wall network
+ * evolution" (arXiv:1710.10420), Sec. II:
+ *
+ *   Eq. (1)  V(phi) = V0 (phi^2/phi0^2 - 1)^2
+ *   Eq. (2)  phi'' + alpha (d ln a/d ln eta) phi'/eta - Lap phi = -a^beta dV/dphi,
+ *            with the PRS choice beta = 0, alpha = 3
+ *   Eq. (3)  Lap phi_i = sum_d (phi_{i+e_d} + phi_{i-e_d}) - 2 D phi_i   (/dx^2)
+ *   Eq. (4)  phi_dot^{n+1/2} = [(1-delta) phi_dot^{n-1/2}
+ *                               + deta (Lap phi^n - V'(phi^n))] / (1+delta)
+ *   Eq. (5)  phi^{n+1} = phi^n + deta phi_dot^{n+1/2}
+ *   Eq. (6)  delta = (1/2) alpha (deta/eta) (d ln a/d ln eta)
+ *   Eq. (7)  rho = A/V: sum over sign-changing links of
+ *            |grad phi| / (|phi_,x| + |phi_,y| + |phi_,z|), times dx^(D-1)/V
+ *   Eq. (8)  (gamma v)^2 = (1/N) sum over wall sites of (1/2) phi_dot^2 / V(phi)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All functions are extern "C", never throw and return a prs_status.  On
+ *   failure prs_last_error() holds a message (thread local).
+ * - Fields are float32 device arrays (HBM) of n[0]*n[1]*n[2] sites (n[2] = 1
+ *   in 2D), x fastest: site (x,y,z) is element x + nx*(y + ny*z).  Boundaries
+ *   are periodic.  Field pointers must be 16-byte aligned.  The caller owns
+ *   every device buffer it passes; the library never frees them.
+ * - All device work is enqueued on the caller's HIP stream (a hipStream_t
+ *   passed as void*; NULL is the default stream).  Calls that return host
+ *   results synchronise that stream before returning.
+ * - The state after n steps is (phi^n, phi_dot^{n-1/2}); eta_n = eta0 + n*deta.
+ * - Arguments are validated before any launch; invalid ones give PRS_EINVAL
+ *   and leave every buffer untouched.  A failed HIP call gives PRS_EDEVICE.
+ */
+#ifndef PRS_H
+#define PRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t prs_status;
+#define PRS_OK 0
+#define PRS_EINVAL (-1)        /* invalid argument (checked before any launch) */
+#define PRS_ENOMEM (-2)        /* workspace too small or host allocation failed */
+#define PRS_EDEVICE (-3)       /* a HIP runtime call failed */
+#define PRS_ESTATE (-4)        /* call not valid in the object's current state */
+#define PRS_EUNSUPPORTED (-5)  /* valid physics this library does not implement */
+
+/* Run parameters (Sec. II).  V0 is derived as pi^2 / (2 W0^2), the height for
+ * which the continuum kink tanh(pi x / W0) solves the static equation;
+ * W0 = +inf gives V0 = 0 (free field). */
+typedef struct prs_params {
+    int32_t ndim;        /* 2 or 3 */
+    int32_t diag_every;  /* K > 0: record diagnostics of every state n with
+                            n % K == 0 (fused into step n); 0: none */
+    int64_t n[3];        /* lattice sides nx, ny, nz (nz ignored in 2D), >= 1 */
+    double dx;           /* lattice spacing, > 0 */
+    double deta;         /* conformal time step, > 0 */
+    double eta0;         /* conformal time of step 0, > 0 */
+    double alpha;        /* damping coefficient of Eq. (2); PRS uses 3 */
+    double beta;         /* scale-factor power of the force; only 0 (PRS) */
+    double m;            /* era exponent d ln a / d ln eta (a ~ eta^m), >= 0 */
+    double W0;           /* wall thickness parameter, > 0 (may be +inf) */
+    double phi0;         /* vacuum value, > 0 */
+} prs_params;
+
+/* One diagnostic record (Eqs. 7-8) of the state (phi^n, phi_dot^{n-1/2}). */
+typedef struct prs_stats {
+    int64_t step;            /* n */
+    double eta;              /* eta_n */
+    uint64_t links;          /* forward links (i, i+e_d) whose sign changes */
+    uint64_t links_dir[3];   /* the same per direction d */
+    uint64_t wall_sites;     /* sites touching at least one such link */
+    uint64_t nonfinite;      /* sites where phi or phi_dot is NaN or inf */
+    double area_density;     /* rho = A/V, Eq. (7) */
+    double gv2;              /* (gamma v)^2, Eq. (8); 0 when no wall site */
+} prs_stats;
+
+typedef struct prs_ctx prs_ctx;
+
+/* ---- single run ------------------------------------------------------- */
+
+/* Bytes of device workspace prs_init needs for these parameters (per-wave
+ * diagnostic partial sums and the record buffer); 0 if p is invalid. */
+size_t prs_workspace_bytes(const prs_params* p);
+
+/* Create a run context over caller-owned device buffers.
+ *   phi_a, phi_b : two fields; phi_a holds phi^0 on entry, the evolution
+ *                  ping-pongs between them (prs_get_state names the current)
+ *   dphi         : phi_dot^{-1/2} on entry, updated in place
+ *   workspace    : >= prs_workspace_bytes(p) bytes of device memory, 256-byte
+ *                  aligned, owned by the caller and used only by this context
+ * Validation (PRS_EINVAL): ndim, sides >= 1, dx, deta, eta0, W0, phi0 > 0,
+ * m >= 0, alpha >= 0; the step must be stable for the linearised scheme,
+ * deta * sqrt(4 D / dx^2 + 8 V0/phi0^2) < 2, and the first damping factor
+ * must satisfy delta_0 = alpha m deta / (2 eta0) < 1.  beta != 0 gives
+ * PRS_EUNSUPPORTED.  The context starts at step 0. */
+prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi,
+                    void* workspace, size_t ws_bytes, void* hip_stream, prs_ctx** out);
+
+/* Number of diagnostic records prs_step_n(ctx at step n0, nsteps) produces:
+ * the count of n in [n0, n0+nsteps) with n % diag_every == 0. */
+int64_t prs_records_in(const prs_params* p, int64_t n0, int64_t nsteps);
+
+/* Advance nsteps steps (Eqs. 3-6), one fused kernel launch per step.  When
+ * series is non-NULL the diagnostics of every state n with n % diag_every == 0
+ * are computed inside that step's kernel (on its input state) and written to
+ * series[0 .. *n_written-1]; cap must be at least prs_records_in(...), else
+ * PRS_EINVAL.  With series == NULL no diagnostics are computed.  Splitting a
+ * call into two consecutive calls gives bit-identical fields and records.
+ * Synchronises the stream when series is non-NULL. */
+prs_status prs_step_n(prs_ctx* ctx, int64_t nsteps, prs_stats* series, int64_t cap,
+                      int64_t* n_written);
+
+/* Diagnostics (Eqs. 7-8) of the current state; synchronises the stream.
+ * Bit-identical to the record prs_step_n fuses for the same state. */
+prs_status prs_wall_stats(prs_ctx* ctx, prs_stats* out);
+
+/* Current state: device pointers of phi^n and phi_dot^{n-1/2}, n and eta_n.
+ * Any output pointer may be NULL. */
+prs_status prs_get_state(prs_ctx* ctx, void** phi, void** dphi, int64_t* step, double* eta);
+
+/* Replace the state: copies the given device fields (any 16-byte aligned
+ * device pointers; NULL keeps that field) into the context's buffers and sets
+ * the step counter to `step` (>= 0). */
+prs_status prs_set_state(prs_ctx* ctx, const void* phi, const void* dphi, int64_t step);
+
+/* Choose the kernel tiling of this context (mainly for tests and the
+ * autotuner).  vec: sites per lane along x (1, 2 or 4, must divide nx);
+ * rows: planes per wave along the marching axis (y in 2D, z in 3D), 1..4096;
+ * ty: rows per wave along y in 3D (1, 2 or 4; must be 1 in 2D).
+ * Results are bit-identical for every tiling except the rounding order of the
+ * two floating-point diagnostic sums. */
+prs_status prs_set_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
+prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
+
+/* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
+void prs_destroy(prs_ctx* ctx);
+
+/* ---- adjoint (reverse-mode gradient through the evolution) ----------- */
+
+/* Differentiable path: the loss of a run of nsteps steps from the context's
+ * current state (phi^{n0}, phi_dot^{n0-1/2}) is
+ *     L = sum_i V(phi_i^S)/V0 = sum_i (phi_i^2/phi0^2 - 1)^2,   S = n0 + nsteps,
+ * and its gradient is taken with respect to phi^{n0}, phi_dot^{n0-1/2} and W0
+ * (through V0 = pi^2/(2 W0^2) in the force of Eq. 4).  The reverse sweep is the
+ * hand-derived transpose of Eqs. (3)-(6): with w the adjoint of
+ * phi_dot^{n+1/2}, mu^n = mu^{n+1} + b_n (Lap w - V''(phi^n) w) and the
+ * previous w = a_n w + deta mu^n (a_n = (1-delta_n)/(1+delta_n),
+ * b_n = deta/(1+delta_n)).
+ *
+ * Memory: (phi, phi_dot) is checkpointed every ckpt_every steps; in reverse,
+ * each segment is recomputed from its checkpoint and then swept backwards.
+ * All of it lives in a caller-owned device workspace of
+ * prs_adjoint_workspace_bytes(...) bytes (256-byte aligned), about
+ * (2 nsteps/K + K + 4) fields. */
+size_t prs_adjoint_workspace_bytes(const prs_params* p, int64_t nsteps, int32_t ckpt_every);
+
+/* Forward half: advances the context by nsteps (no diagnostics), storing the
+ * checkpoints in `work`, and returns the loss (synchronises the stream).
+ * nsteps >= 1, ckpt_every >= 1, else PRS_EINVAL; PRS_ENOMEM if work_bytes is
+ * too small. */
+prs_status prs_adjoint_forward(prs_ctx* ctx, int64_t nsteps, int32_t ckpt_every, void* work,
+                               size_t work_bytes, double* loss);
+
+/* Reverse half: must follow prs_adjoint_forward with the same workspace
+ * (PRS_ESTATE otherwise; each forward allows one backward).  Writes
+ * dL/dphi^{n0} to grad_phi0 and dL/dphi_dot^{n0-1/2} to grad_dphi0 (float32
+ * device fields; either may be NULL) and dL/dW0 to *grad_W0 (may be NULL).
+ * Leaves the context state at step S.  Synchronises the stream. */
+prs_status prs_adjoint_backward(prs_ctx* ctx, void* work, size_t work_bytes, void* grad_phi0,
+                                void* grad_dphi0, double* grad_W0);
+
+/* Both halves in one call. */
+prs_status prs_adjoint(prs_ctx* ctx, int64_t nsteps, int32_t ckpt_every, void* work,
+                       size_t work_bytes, void* grad_phi0, void* grad_dphi0, double* grad_W0,
+                       double* loss);
+
+/* ---- batched ensemble -------------------------------------------------- */
+
+/* An ensemble of independent realisations -- mixed 2D/3D lattices, sizes,
+ * eras m, wall widths W0, time steps and step counts -- advanced together,
+ * as needed for the large sets of production runs and the model calibration
+ * the paper motivates (Secs. I and IV).  Each realisation follows exactly the
+ * single-run method (same kernels per tile), so its fields and records are
+ * bitwise those of the same realisation run alone with the same tiling. */
+typedef struct prs_batch_item {
+    prs_params p;        /* this realisation's parameters (diag_every: its cadence) */
+    int64_t nsteps;      /* steps to run, >= 0 */
+    uint64_t seed;       /* initial field seed (prs_fill_uniform) */
+    int32_t init_from_seed;  /* 1: every run starts from the seeded field and
+                                dphi = 0; 0: from the buffers' contents */
+    int32_t reserved;
+    void* phi_a;         /* caller-owned fields as in prs_init; phi^n ends in */
+    void* phi_b;         /*   phi_a when n is even, phi_b when n is odd */
+    void* dphi;
+} prs_batch_item;
+
+typedef struct prs_batch prs_batch;
+
+#define PRS_BATCH_PERSISTENT_GRAPH 0  /* one persistent launch, captured in a hipGraph (default) */
+#define PRS_BATCH_PERSISTENT 1        /* the same launch sequence without the graph */
+#define PRS_BATCH_PER_STEP 2          /* one launch per step over all realisations */
+
+/* Device workspace (descriptors, coefficient tables, record partials and the
+ * records themselves); 0 if any item is invalid. */
+size_t prs_batch_workspace_bytes(const prs_batch_item* items, int32_t count);
+
+/* Validates every item (as prs_init, PRS_EINVAL naming the item) and builds
+ * the ensemble over caller-owned buffers and a 256-byte aligned workspace. */
+prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* workspace,
+                            size_t ws_bytes, void* hip_stream, prs_batch** out);
+
+/* Records of item r occupy series[offsets[r] .. offsets[r+1]-1]: the states
+ * n % diag_every == 0 for n < nsteps, then the final state n = nsteps.
+ * offsets has count+1 entries. */
+prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
+
+/* Tiling of one item (vec, rows, ty as in prs_set_tiling; in 3D ty = 2 only
+ * with vec <= 2). */
+prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
+prs_status prs_batch_set_mode(prs_batch* b, int32_t mode);
+
+/* Runs the whole ensemble (initial fields if init_from_seed, all steps, all
+ * records) and synchronises the stream.  series may be NULL; otherwise cap
+ * must hold offsets[count] records.  The persistent kernel's grid barrier
+ * waits at most 5 s per step; if the grid is not co-resident the run stops
+ * with PRS_EDEVICE instead of hanging. */
+prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap);
+
+void prs_batch_destroy(prs_batch* b);
+
+/* ---- initial conditions ---------------------------------------------- */
+
+/* Fill count float32 values at device pointer phi with the seeded initial
+ * field: site i gets (2k+1)/2^24 - 1 where k is the top 24 bits of the
+ * SplitMix64 output for counter i+1 under `seed` (Steele, Lea & Flood 2014),
+ * i.e. i.i.d. uniform on (-1, 1), exact in float32 and never 0.  The paper
+ * generates its random initial conditions once in single precision and feeds
+ * them to every run (Sec. III).  Asynchronous on the stream. */
+prs_status prs_fill_uniform(void* phi, int64_t count, uint64_t seed, void* hip_stream);
+
+/* ---- scaling exponents (Eq. 9) --------------------------------------- */
+
+/* Unweighted least-squares slopes mu of ln rho and nu of ln(gamma v) against
+ * ln eta (Eq. 9), over the records with eta_min <= eta <= eta_max and
+ * positive values (pass 0 / +inf for no bound).  Host-only. */
+prs_status prs_fit_scaling(const prs_stats* series, int64_t count, double eta_min,
+                           double eta_max, double* mu, double* nu);
+
+/* ---- errors ----------------------------------------------------------- */
+
+const char* prs_strerror(prs_status s);
+const char* prs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRS_H */

@@ -1,0 +1,917 @@
+// prs_api.cpp -- host side of the C ABI declared in include/prs.h: argument
+// validation, run contexts, the FP64 coefficient schedule of Eqs. (4)-(6)
+// and the Eq. (9) exponent fit.  Every step of the evolution runs in the
+// kernels of prs_kernels.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "prs.h"
+#include "prs_internal.h"
+
+using namespace prs;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+prs_status fail(prs_status s, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+prs_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(PRS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kRecCap = 1024;   // device records buffered before a flush
+constexpr int64_t kMinRows = 16;    // smallest marching tile the workspace allows
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+double v0_of(const prs_params& p)
+{
+    return std::isinf(p.W0) ? 0.0 : M_PI * M_PI / (2.0 * p.W0 * p.W0);
+}
+
+int64_t sites_of(const prs_params& p)
+{
+    return p.n[0] * p.n[1] * (p.ndim == 3 ? p.n[2] : 1);
+}
+
+prs_status validate(const prs_params* p)
+{
+    if (!p) return fail(PRS_EINVAL, "params is NULL");
+    if (p->ndim != 2 && p->ndim != 3) return fail(PRS_EINVAL, "ndim must be 2 or 3 (got %d)", p->ndim);
+    for (int d = 0; d < p->ndim; ++d)
+        if (p->n[d] < 1) return fail(PRS_EINVAL, "lattice side n[%d] = %lld must be >= 1", d, (long long)p->n[d]);
+    const double lim = 1.0 * (1ll << 40);
+    double sites = 1.0;
+    for (int d = 0; d < p->ndim; ++d) sites *= (double)p->n[d];
+    if (sites > lim) return fail(PRS_EINVAL, "lattice too large (%.3g sites)", sites);
+    if (p->ndim == 3 && (double)p->n[0] * (double)p->n[1] > 2147483647.0)
+        return fail(PRS_EINVAL, "3D plane nx*ny exceeds 2^31");
+    if (!(p->dx > 0) || !std::isfinite(p->dx)) return fail(PRS_EINVAL, "dx must be finite and > 0");
+    if (!(p->deta > 0) || !std::isfinite(p->deta)) return fail(PRS_EINVAL, "deta must be finite and > 0");
+    if (!(p->eta0 > 0) || !std::isfinite(p->eta0)) return fail(PRS_EINVAL, "eta0 must be finite and > 0");
+    if (!(p->alpha >= 0) || !std::isfinite(p->alpha)) return fail(PRS_EINVAL, "alpha must be finite and >= 0");
+    if (!(p->m >= 0) || !std::isfinite(p->m)) return fail(PRS_EINVAL, "m must be finite and >= 0");
+    if (!(p->W0 > 0)) return fail(PRS_EINVAL, "W0 must be > 0");
+    if (!(p->phi0 > 0) || !std::isfinite(p->phi0)) return fail(PRS_EINVAL, "phi0 must be finite and > 0");
+    if (p->diag_every < 0) return fail(PRS_EINVAL, "diag_every must be >= 0");
+    if (p->beta != 0.0)
+        return fail(PRS_EUNSUPPORTED, "only the PRS force (beta = 0) is implemented (got beta = %g)", p->beta);
+    const double V0 = v0_of(*p);
+    const double w2 = 4.0 * p->ndim / (p->dx * p->dx) + 8.0 * V0 / (p->phi0 * p->phi0);
+    if (!(p->deta * std::sqrt(w2) < 2.0))
+        return fail(PRS_EINVAL, "unstable step: deta*sqrt(4D/dx^2 + 8 V0/phi0^2) = %g must be < 2",
+                    p->deta * std::sqrt(w2));
+    const double d0 = 0.5 * p->alpha * (p->deta / p->eta0) * p->m;
+    if (!(d0 < 1.0)) return fail(PRS_EINVAL, "first damping factor delta_0 = %g must be < 1", d0);
+    return PRS_OK;
+}
+
+Tiling default_tiling(const Geometry& g)
+{
+    Tiling t;
+    if (g.nx % 4 == 0 && g.nx >= 256) t.vec = 4;
+    else if (g.nx % 2 == 0 && g.nx >= 128) t.vec = 2;
+    else if (g.nx % 4 == 0) t.vec = 4;
+    else if (g.nx % 2 == 0) t.vec = 2;
+    else t.vec = 1;
+    t.ty = g.ndim == 3 ? 2 : 1;
+    t.rows = 32;
+    return t;
+}
+
+int64_t partial_capacity(const Geometry& g)
+{
+    Tiling t{1, (int)kMinRows, 1};
+    return tile_counts(g, t).ntiles;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+struct prs_ctx {
+    prs_params p;
+    Geometry geo;
+    Tiling til;
+    double V0;
+    float* phi[2];
+    int cur;
+    float* pi;
+    WavePartial* partials;
+    int64_t partial_cap;
+    prs_stats* drec;
+    prs_stats* hrec;   // pinned staging buffer
+    hipStream_t stream;
+    int64_t step;
+    // adjoint bookkeeping between prs_adjoint_forward and _backward
+    bool adj_ready;
+    int64_t adj_n0, adj_nsteps;
+    int32_t adj_K;
+    void* adj_work;
+    size_t adj_bytes;
+    double* adj_host;   // pinned: loss, G
+};
+
+namespace {
+
+StepCoef coef_for(const prs_ctx* c, int64_t n)
+{
+    const prs_params& p = c->p;
+    const double eta = p.eta0 + (double)n * p.deta;
+    const double delta = 0.5 * p.alpha * (p.deta / eta) * p.m;   // Eq. (6)
+    StepCoef k;
+    k.a = (float)((1.0 - delta) / (1.0 + delta));
+    k.b = (float)(p.deta / (1.0 + delta));
+    k.deta = (float)p.deta;
+    k.F = (float)(4.0 * c->V0 / (p.phi0 * p.phi0));
+    k.kc = (float)(1.0 / (p.phi0 * p.phi0));
+    k.inv_dx2 = (float)(1.0 / (p.dx * p.dx));
+    return k;
+}
+
+DiagCoef diag_coef(const prs_ctx* c)
+{
+    DiagCoef d;
+    d.V0 = c->V0;
+    d.kc = 1.0 / (c->p.phi0 * c->p.phi0);
+    return d;
+}
+
+double area_scale(const prs_params& p)
+{
+    // Eq. (7): Delta A = dx^(D-1) per link over the volume sites * dx^D
+    return std::pow(p.dx, p.ndim - 1) / ((double)sites_of(p) * std::pow(p.dx, p.ndim));
+}
+
+prs_status flush(prs_ctx* c, int64_t count, prs_stats* dst)
+{
+    if (count == 0) return PRS_OK;
+    HIP_TRY(hipMemcpyAsync(c->hrec, c->drec, (size_t)count * sizeof(prs_stats),
+                           hipMemcpyDeviceToHost, c->stream),
+            "record copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    std::memcpy(dst, c->hrec, (size_t)count * sizeof(prs_stats));
+    return PRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t prs_workspace_bytes(const prs_params* p)
+{
+    if (validate(p) != PRS_OK) return 0;
+    const Geometry g = geometry_of(*p);
+    return align_up((size_t)partial_capacity(g) * sizeof(WavePartial)) +
+           align_up((size_t)kRecCap * sizeof(prs_stats));
+}
+
+prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, void* workspace,
+                    size_t ws_bytes, void* hip_stream, prs_ctx** out)
+{
+    if (!out) return fail(PRS_EINVAL, "out is NULL");
+    *out = nullptr;
+    prs_status st = validate(p);
+    if (st != PRS_OK) return st;
+    if (!phi_a || !phi_b || !dphi || !workspace) return fail(PRS_EINVAL, "NULL buffer");
+    if (!aligned16(phi_a) || !aligned16(phi_b) || !aligned16(dphi))
+        return fail(PRS_EINVAL, "field buffers must be 16-byte aligned");
+    if (((uintptr_t)workspace % kAlign) != 0) return fail(PRS_EINVAL, "workspace must be 256-byte aligned");
+    if (phi_a == phi_b || phi_a == dphi || phi_b == dphi)
+        return fail(PRS_EINVAL, "phi_a, phi_b and dphi must be distinct buffers");
+    const size_t need = prs_workspace_bytes(p);
+    if (ws_bytes < need)
+        return fail(PRS_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+
+    prs_ctx* c = new (std::nothrow) prs_ctx();
+    if (!c) return fail(PRS_ENOMEM, "host allocation failed");
+    c->p = *p;
+    c->geo = geometry_of(*p);
+    c->til = default_tiling(c->geo);
+    c->V0 = v0_of(*p);
+    c->phi[0] = static_cast<float*>(phi_a);
+    c->phi[1] = static_cast<float*>(phi_b);
+    c->cur = 0;
+    c->pi = static_cast<float*>(dphi);
+    c->partial_cap = partial_capacity(c->geo);
+    c->partials = static_cast<WavePartial*>(workspace);
+    c->drec = reinterpret_cast<prs_stats*>(
+        static_cast<char*>(workspace) + align_up((size_t)c->partial_cap * sizeof(WavePartial)));
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->step = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hrec), (size_t)kRecCap * sizeof(prs_stats),
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "pinned record buffer");
+    }
+    *out = c;
+    return PRS_OK;
+}
+
+int64_t prs_records_in(const prs_params* p, int64_t n0, int64_t nsteps)
+{
+    if (!p || p->diag_every <= 0 || nsteps <= 0 || n0 < 0) return 0;
+    const int64_t K = p->diag_every;
+    const int64_t first = (n0 + K - 1) / K * K;
+    const int64_t last = n0 + nsteps - 1;
+    return last < first ? 0 : (last - first) / K + 1;
+}
+
+prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap, int64_t* n_written)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (n_written) *n_written = 0;
+    if (nsteps < 0) return fail(PRS_EINVAL, "nsteps must be >= 0");
+    const bool want = series != nullptr && c->p.diag_every > 0;
+    const int64_t need = want ? prs_records_in(&c->p, c->step, nsteps) : 0;
+    if (want && cap < need)
+        return fail(PRS_EINVAL, "series capacity %lld < %lld records", (long long)cap, (long long)need);
+    const DiagCoef dc = diag_coef(c);
+    const double ascale = area_scale(c->p);
+    const TileCounts tc = tile_counts(c->geo, c->til);
+    int64_t pending = 0, written = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t n = c->step;
+        const bool diag = want && (n % c->p.diag_every == 0);
+        HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi, coef_for(c, n),
+                            true, diag, c->partials, dc, c->stream),
+                "step kernel launch");
+        if (diag) {
+            HIP_TRY(launch_finalize(c->partials, tc.ntiles, c->drec + pending, n,
+                                    c->p.eta0 + (double)n * c->p.deta, ascale, c->stream),
+                    "finalize launch");
+            if (++pending == kRecCap) {
+                prs_status s = flush(c, pending, series + written);
+                if (s != PRS_OK) return s;
+                written += pending;
+                pending = 0;
+            }
+        }
+        c->cur ^= 1;
+        c->step += 1;
+    }
+    if (want) {
+        prs_status s = flush(c, pending, series + written);
+        if (s != PRS_OK) return s;
+        written += pending;
+    }
+    if (n_written) *n_written = written;
+    return PRS_OK;
+}
+
+prs_status prs_wall_stats(prs_ctx* c, prs_stats* out)
+{
+    if (!c || !out) return fail(PRS_EINVAL, "NULL argument");
+    const TileCounts tc = tile_counts(c->geo, c->til);
+    const int64_t n = c->step;
+    HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], nullptr, c->pi, coef_for(c, n), false, true,
+                        c->partials, diag_coef(c), c->stream),
+            "diagnostics kernel launch");
+    HIP_TRY(launch_finalize(c->partials, tc.ntiles, c->drec, n, c->p.eta0 + (double)n * c->p.deta,
+                            area_scale(c->p), c->stream),
+            "finalize launch");
+    return flush(c, 1, out);
+}
+
+prs_status prs_get_state(prs_ctx* c, void** phi, void** dphi, int64_t* step, double* eta)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (phi) *phi = c->phi[c->cur];
+    if (dphi) *dphi = c->pi;
+    if (step) *step = c->step;
+    if (eta) *eta = c->p.eta0 + (double)c->step * c->p.deta;
+    return PRS_OK;
+}
+
+prs_status prs_set_state(prs_ctx* c, const void* phi, const void* dphi, int64_t step)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (step < 0) return fail(PRS_EINVAL, "step must be >= 0");
+    if ((phi && !aligned16(phi)) || (dphi && !aligned16(dphi)))
+        return fail(PRS_EINVAL, "state buffers must be 16-byte aligned");
+    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    if (phi && phi != c->phi[c->cur])
+        HIP_TRY(hipMemcpyAsync(c->phi[c->cur], phi, bytes, hipMemcpyDeviceToDevice, c->stream), "phi copy");
+    if (dphi && dphi != c->pi)
+        HIP_TRY(hipMemcpyAsync(c->pi, dphi, bytes, hipMemcpyDeviceToDevice, c->stream), "dphi copy");
+    c->step = step;
+    return PRS_OK;
+}
+
+prs_status prs_set_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t ty)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    Tiling t{vec, rows, ty};
+    if (!tiling_supported(c->geo, t))
+        return fail(PRS_EINVAL, "tiling vec=%d rows=%d ty=%d not supported for this lattice", vec, rows, ty);
+    if (tile_counts(c->geo, t).ntiles > c->partial_cap)
+        return fail(PRS_EINVAL, "tiling has more wave tiles than the workspace holds (rows >= %lld)",
+                    (long long)kMinRows);
+    c->til = t;
+    return PRS_OK;
+}
+
+prs_status prs_get_tiling(prs_ctx* c, int32_t* vec, int32_t* rows, int32_t* ty)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (vec) *vec = c->til.vec;
+    if (rows) *rows = c->til.rows;
+    if (ty) *ty = c->til.ty;
+    return PRS_OK;
+}
+
+void prs_destroy(prs_ctx* c)
+{
+    if (!c) return;
+    if (c->hrec) (void)hipHostFree(c->hrec);
+    if (c->adj_host) (void)hipHostFree(c->adj_host);
+    delete c;
+}
+
+prs_status prs_fill_uniform(void* phi, int64_t count, uint64_t seed, void* hip_stream)
+{
+    if (count < 0) return fail(PRS_EINVAL, "count must be >= 0");
+    if (count > 0 && !phi) return fail(PRS_EINVAL, "phi is NULL");
+    HIP_TRY(launch_fill_uniform(static_cast<float*>(phi), count, seed,
+                                static_cast<hipStream_t>(hip_stream)),
+            "fill kernel launch");
+    return PRS_OK;
+}
+
+prs_status prs_fit_scaling(const prs_stats* series, int64_t count, double eta_min, double eta_max,
+                           double* mu, double* nu)
+{
+    if (!series || count < 0 || !mu || !nu) return fail(PRS_EINVAL, "invalid fit arguments");
+    // least-squares slope of ln y against ln eta over the selected records
+    // (two passes, centred, for accuracy)
+    auto slope = [&](bool area) {
+        std::vector<double> lx, ly;
+        for (int64_t i = 0; i < count; ++i) {
+            const prs_stats& r = series[i];
+            const double y = area ? r.area_density : r.gv2;
+            if (!(r.eta >= eta_min && r.eta <= eta_max && y > 0 && r.eta > 0)) continue;
+            lx.push_back(std::log(r.eta));
+            ly.push_back(std::log(y));
+        }
+        const size_t k = lx.size();
+        if (k < 2) return std::nan("");
+        double mx = 0, my = 0;
+        for (size_t i = 0; i < k; ++i) { mx += lx[i]; my += ly[i]; }
+        mx /= (double)k;
+        my /= (double)k;
+        double sxy = 0, sxx = 0;
+        for (size_t i = 0; i < k; ++i) {
+            sxy += (lx[i] - mx) * (ly[i] - my);
+            sxx += (lx[i] - mx) * (lx[i] - mx);
+        }
+        return sxx > 0 ? sxy / sxx : std::nan("");
+    };
+    *mu = slope(true);
+    *nu = 0.5 * slope(false);   // gamma v = sqrt((gamma v)^2)
+    return PRS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of the checkpointed adjoint (all offsets 256-byte aligned):
+//   nseg checkpoints of (phi, phi_dot), the K-1 recomputed fields phi^{n_s+1..}
+//   of one segment, a phi_dot scratch for recomputation, mu, w (x2), the
+//   per-wave dL/dV0 accumulators, the loss partials and two FP64 scalars.
+struct AdjLayout {
+    size_t fb;
+    int64_t nseg, K;
+    size_t ck_phi, ck_pi, seg, pis, mu, w0, w1, gacc, lpart, scal, total;
+};
+
+constexpr int kSeedBlocks = 1024;
+
+AdjLayout adj_layout(const prs_params& p, int64_t nsteps, int64_t K, int64_t partial_cap)
+{
+    AdjLayout L;
+    L.fb = align_up((size_t)sites_of(p) * sizeof(float));
+    L.K = K;
+    L.nseg = (nsteps + K - 1) / K;
+    size_t o = 0;
+    L.ck_phi = o; o += L.fb * (size_t)L.nseg;
+    L.ck_pi = o; o += L.fb * (size_t)L.nseg;
+    L.seg = o; o += L.fb * (size_t)(K > 1 ? K - 1 : 0);
+    L.pis = o; o += L.fb;
+    L.mu = o; o += L.fb;
+    L.w0 = o; o += L.fb;
+    L.w1 = o; o += L.fb;
+    L.gacc = o; o += align_up((size_t)partial_cap * sizeof(double));
+    L.lpart = o; o += align_up((size_t)kSeedBlocks * sizeof(double));
+    L.scal = o; o += align_up(2 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+template <class T>
+T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+
+prs_status check_adj_args(const prs_ctx* c, int64_t nsteps, int32_t K)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (nsteps < 1) return fail(PRS_EINVAL, "adjoint needs nsteps >= 1");
+    if (K < 1) return fail(PRS_EINVAL, "checkpoint interval must be >= 1");
+    return PRS_OK;
+}
+
+AdjCoef adj_coef(const prs_ctx* c, int64_t n, bool last)
+{
+    const prs_params& p = c->p;
+    const double eta = p.eta0 + (double)n * p.deta;
+    const double delta = 0.5 * p.alpha * (p.deta / eta) * p.m;
+    const double b = p.deta / (1.0 + delta);
+    const double kc = 1.0 / (p.phi0 * p.phi0);
+    AdjCoef k;
+    k.a = (float)((1.0 - delta) / (1.0 + delta));
+    k.b = (float)b;
+    k.cw = last ? 0.0f : (float)p.deta;
+    k.F = (float)(4.0 * c->V0 * kc);
+    k.kc = (float)kc;
+    k.inv_dx2 = (float)(1.0 / (p.dx * p.dx));
+    k.gscale = -4.0 * kc * b;
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t prs_adjoint_workspace_bytes(const prs_params* p, int64_t nsteps, int32_t ckpt_every)
+{
+    if (validate(p) != PRS_OK || nsteps < 1 || ckpt_every < 1) return 0;
+    return adj_layout(*p, nsteps, ckpt_every, partial_capacity(geometry_of(*p))).total;
+}
+
+prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, void* work,
+                               size_t work_bytes, double* loss)
+{
+    prs_status st = check_adj_args(c, nsteps, ckpt_every);
+    if (st != PRS_OK) return st;
+    if (!work || ((uintptr_t)work % kAlign) != 0) return fail(PRS_EINVAL, "work must be 256-byte aligned");
+    const AdjLayout L = adj_layout(c->p, nsteps, ckpt_every, c->partial_cap);
+    if (work_bytes < L.total)
+        return fail(PRS_ENOMEM, "adjoint workspace too small: %zu bytes given, %zu needed", work_bytes, L.total);
+    if (!c->adj_host) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->adj_host), 2 * sizeof(double), hipHostMallocDefault),
+                "pinned scalars");
+    }
+    c->adj_ready = false;
+    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    const int64_t n0 = c->step;
+    for (int64_t sg = 0; sg < L.nseg; ++sg) {
+        HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_phi + L.fb * sg), c->phi[c->cur], bytes,
+                               hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+        HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_pi + L.fb * sg), c->pi, bytes,
+                               hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+        const int64_t len = std::min<int64_t>(L.K, nsteps - sg * L.K);
+        for (int64_t k = 0; k < len; ++k) {
+            HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi,
+                                coef_for(c, c->step), true, false, nullptr, DiagCoef{}, c->stream),
+                    "step kernel launch");
+            c->cur ^= 1;
+            c->step += 1;
+        }
+    }
+    const float kc = (float)(1.0 / (c->p.phi0 * c->p.phi0));
+    HIP_TRY(launch_adj_seed(c->phi[c->cur], sites_of(c->p), kc, (float)c->p.deta, at<float>(work, L.mu),
+                            at<float>(work, L.w0), at<double>(work, L.lpart), kSeedBlocks, c->stream),
+            "adjoint seed launch");
+    HIP_TRY(launch_sum_f64(at<double>(work, L.lpart), kSeedBlocks, at<double>(work, L.scal), c->stream),
+            "loss reduce launch");
+    HIP_TRY(hipMemcpyAsync(c->adj_host, at<double>(work, L.scal), sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream), "loss copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    if (loss) *loss = c->adj_host[0];
+    c->adj_ready = true;
+    c->adj_n0 = n0;
+    c->adj_nsteps = nsteps;
+    c->adj_K = ckpt_every;
+    c->adj_work = work;
+    c->adj_bytes = work_bytes;
+    return PRS_OK;
+}
+
+prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void* grad_phi0,
+                                void* grad_dphi0, double* grad_W0)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (!c->adj_ready || work != c->adj_work || work_bytes != c->adj_bytes)
+        return fail(PRS_ESTATE, "prs_adjoint_backward needs the workspace of a preceding prs_adjoint_forward");
+    if ((grad_phi0 && !aligned16(grad_phi0)) || (grad_dphi0 && !aligned16(grad_dphi0)))
+        return fail(PRS_EINVAL, "gradient buffers must be 16-byte aligned");
+    const AdjLayout L = adj_layout(c->p, c->adj_nsteps, c->adj_K, c->partial_cap);
+    const int64_t n0 = c->adj_n0;
+    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    const TileCounts tc = tile_counts(c->geo, c->til);
+    double* gacc = at<double>(work, L.gacc);
+    HIP_TRY(launch_zero_f64(gacc, tc.ntiles, c->stream), "zero launch");
+    float* mu = at<float>(work, L.mu);
+    float* wcur = at<float>(work, L.w0);
+    float* wnxt = at<float>(work, L.w1);
+    float* pis = at<float>(work, L.pis);
+    auto seg = [&](int64_t k) { return at<float>(work, L.seg + L.fb * (size_t)(k - 1)); };
+    for (int64_t sg = L.nseg - 1; sg >= 0; --sg) {
+        const int64_t ns = n0 + sg * L.K;
+        const int64_t len = std::min<int64_t>(L.K, c->adj_nsteps - sg * L.K);
+        float* ckphi = at<float>(work, L.ck_phi + L.fb * sg);
+        // recompute phi^{ns+1 .. ns+len-1} from the checkpoint
+        if (len > 1) {
+            HIP_TRY(hipMemcpyAsync(pis, at<float>(work, L.ck_pi + L.fb * sg), bytes,
+                                   hipMemcpyDeviceToDevice, c->stream), "checkpoint restore");
+        }
+        const float* prev = ckphi;
+        for (int64_t k = 1; k < len; ++k) {
+            HIP_TRY(launch_step(c->geo, c->til, prev, seg(k), pis, coef_for(c, ns + k - 1), true, false,
+                                nullptr, DiagCoef{}, c->stream),
+                    "recompute launch");
+            prev = seg(k);
+        }
+        for (int64_t k = len - 1; k >= 0; --k) {
+            const int64_t n = ns + k;
+            const float* phin = k == 0 ? ckphi : seg(k);
+            HIP_TRY(launch_adjoint(c->geo, c->til, wcur, wnxt, mu, phin, gacc, adj_coef(c, n, n == n0),
+                                   c->stream),
+                    "adjoint launch");
+            std::swap(wcur, wnxt);
+        }
+    }
+    if (grad_phi0)
+        HIP_TRY(hipMemcpyAsync(grad_phi0, mu, bytes, hipMemcpyDeviceToDevice, c->stream), "gradient copy");
+    if (grad_dphi0)
+        HIP_TRY(hipMemcpyAsync(grad_dphi0, wcur, bytes, hipMemcpyDeviceToDevice, c->stream), "gradient copy");
+    HIP_TRY(launch_sum_f64(gacc, tc.ntiles, at<double>(work, L.scal) + 1, c->stream), "G reduce launch");
+    HIP_TRY(hipMemcpyAsync(c->adj_host + 1, at<double>(work, L.scal) + 1, sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream), "G copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+    const double G = c->adj_host[1];   // dL/dV0
+    if (grad_W0) *grad_W0 = std::isinf(c->p.W0) ? 0.0 : G * (-2.0 * c->V0 / c->p.W0);
+    c->adj_ready = false;
+    return PRS_OK;
+}
+
+prs_status prs_adjoint(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, void* work, size_t work_bytes,
+                       void* grad_phi0, void* grad_dphi0, double* grad_W0, double* loss)
+{
+    prs_status st = prs_adjoint_forward(c, nsteps, ckpt_every, work, work_bytes, loss);
+    if (st != PRS_OK) return st;
+    return prs_adjoint_backward(c, work, work_bytes, grad_phi0, grad_dphi0, grad_W0);
+}
+
+}  // extern "C"
+
+
+// ------------------------------------------------------- batched ensemble --
+
+struct prs_batch {
+    int32_t count;
+    std::vector<prs_batch_item> items;
+    std::vector<Geometry> geo;
+    std::vector<Tiling> til;
+    std::vector<int64_t> rec_off;       // count + 1 record offsets
+    std::vector<int64_t> part_cap;      // partial capacity per realisation
+    std::vector<size_t> coef_off, part_off;
+    hipStream_t stream;
+    void* ws;
+    size_t ws_bytes;
+    size_t off_desc, off_coef, off_part, off_rec, off_ctl;
+    int64_t total_tiles, tmax, total_recs;
+    prs_stats* hrec;     // pinned
+    int* herr;           // pinned
+    int32_t mode;
+    int grid_blocks;
+    uint64_t timeout_ticks;
+    bool dirty;          // descriptors need uploading / graph rebuilding
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t desc, coef, part, rec, ctl, total;
+    std::vector<size_t> coef_off, part_off;
+    std::vector<int64_t> rec_off, part_cap;
+};
+
+int64_t batch_records_of(const prs_batch_item& it)
+{
+    return prs_records_in(&it.p, 0, it.nsteps) + 1;   // + the final state
+}
+
+prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout& L)
+{
+    if (!items || count < 1) return fail(PRS_EINVAL, "batch needs at least one item");
+    size_t o = align_up(batch_desc_bytes() * (size_t)count);
+    L.desc = 0;
+    L.coef = o;
+    L.coef_off.assign(count, 0);
+    for (int32_t r = 0; r < count; ++r) {
+        prs_status st = validate(&items[r].p);
+        if (st != PRS_OK) {
+            char why[sizeof g_err];
+            std::snprintf(why, sizeof why, "%s", g_err);
+            return fail(st, "batch item %d: %s", r, why);
+        }
+        if (items[r].nsteps < 0) return fail(PRS_EINVAL, "batch item %d: nsteps < 0", r);
+        L.coef_off[r] = o - L.coef;
+        o += align_up((size_t)std::max<int64_t>(items[r].nsteps, 1) * 2 * sizeof(float));
+    }
+    L.part = o;
+    L.part_off.assign(count, 0);
+    L.part_cap.assign(count, 0);
+    for (int32_t r = 0; r < count; ++r) {
+        L.part_cap[r] = partial_capacity(geometry_of(items[r].p));
+        L.part_off[r] = o - L.part;
+        o += 2 * align_up((size_t)L.part_cap[r] * sizeof(WavePartial));
+    }
+    L.rec = o;
+    L.rec_off.assign(count + 1, 0);
+    for (int32_t r = 0; r < count; ++r) L.rec_off[r + 1] = L.rec_off[r] + batch_records_of(items[r]);
+    o += align_up((size_t)L.rec_off[count] * sizeof(prs_stats));
+    L.ctl = o;
+    o += align_up((size_t)batch_ctl_bytes());
+    L.total = o;
+    return PRS_OK;
+}
+
+void batch_release_graph(prs_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+prs_status batch_upload(prs_batch* b)
+{
+    // coefficient tables and descriptors, built on the host (same FP64 ->
+    // float32 schedule as a single run) and copied synchronously
+    std::vector<char> desc(batch_desc_bytes() * (size_t)b->count);
+    char* base = static_cast<char*>(b->ws);
+    int64_t tile_base = 0;
+    for (int32_t r = 0; r < b->count; ++r) {
+        const prs_batch_item& it = b->items[r];
+        prs_ctx tmp{};
+        tmp.p = it.p;
+        tmp.V0 = v0_of(it.p);
+        std::vector<float> coef((size_t)std::max<int64_t>(it.nsteps, 1) * 2, 0.0f);
+        for (int64_t n = 0; n < it.nsteps; ++n) {
+            const StepCoef k = coef_for(&tmp, n);
+            coef[2 * n] = k.a;
+            coef[2 * n + 1] = k.b;
+        }
+        float2* dcoef = reinterpret_cast<float2*>(base + b->off_coef + b->coef_off[r]);
+        HIP_TRY(hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice),
+                "coefficient upload");
+        WavePartial* p0 = reinterpret_cast<WavePartial*>(base + b->off_part + b->part_off[r]);
+        WavePartial* p1 = p0 + (align_up((size_t)b->part_cap[r] * sizeof(WavePartial)) / sizeof(WavePartial));
+        prs_stats* recs = reinterpret_cast<prs_stats*>(base + b->off_rec) + b->rec_off[r];
+        const TileCounts tc = tile_counts(b->geo[r], b->til[r]);
+        batch_fill_desc(desc.data() + batch_desc_bytes() * r, b->geo[r], b->til[r],
+                        static_cast<float*>(it.phi_a), static_cast<float*>(it.phi_b),
+                        static_cast<float*>(it.dphi), dcoef, p0, p1, recs, it.nsteps, tile_base,
+                        prs_records_in(&it.p, 0, it.nsteps), it.p.eta0, it.p.deta, area_scale(it.p),
+                        it.p.diag_every, coef_for(&tmp, 0), diag_coef(&tmp));
+        tile_base += tc.ntiles;
+    }
+    b->total_tiles = tile_base;
+    HIP_TRY(hipMemcpy(base + b->off_desc, desc.data(), desc.size(), hipMemcpyHostToDevice), "descriptor upload");
+    return PRS_OK;
+}
+
+// The whole ensemble as a sequence on the stream: initial fields, then the
+// steps (one persistent launch, or one launch pair per step), then the
+// records and the error flag to pinned host memory.
+prs_status batch_enqueue(prs_batch* b, bool persistent)
+{
+    char* base = static_cast<char*>(b->ws);
+    for (int32_t r = 0; r < b->count; ++r) {
+        const prs_batch_item& it = b->items[r];
+        if (!it.init_from_seed) continue;
+        const int64_t n = sites_of(it.p);
+        HIP_TRY(launch_fill_uniform(static_cast<float*>(it.phi_a), n, it.seed, b->stream), "fill launch");
+        HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), n, b->stream), "zero launch");
+    }
+    void* ctl = base + b->off_ctl;
+    HIP_TRY(launch_batch_reset(ctl, b->stream), "reset launch");
+    const void* desc = base + b->off_desc;
+    if (persistent) {
+        int blocks = (int)std::min<int64_t>(b->grid_blocks, (b->total_tiles + 3) / 4);
+        if (blocks < 1) blocks = 1;
+        HIP_TRY(launch_batch_persistent(desc, b->count, b->total_tiles, b->tmax, ctl, b->timeout_ticks, blocks,
+                                        b->stream),
+                "persistent launch");
+    } else {
+        for (int64_t t = 0; t <= b->tmax; ++t)
+            HIP_TRY(launch_batch_step(desc, b->count, b->total_tiles, t, b->stream), "batch step launch");
+    }
+    HIP_TRY(hipMemcpyAsync(b->hrec, base + b->off_rec, (size_t)b->total_recs * sizeof(prs_stats),
+                           hipMemcpyDeviceToHost, b->stream), "record copy");
+    HIP_TRY(hipMemcpyAsync(b->herr, static_cast<char*>(ctl) + 2 * sizeof(unsigned), sizeof(int),
+                           hipMemcpyDeviceToHost, b->stream), "flag copy");
+    return PRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t prs_batch_workspace_bytes(const prs_batch_item* items, int32_t count)
+{
+    BatchLayout L;
+    if (batch_layout(items, count, L) != PRS_OK) return 0;
+    return L.total;
+}
+
+prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* workspace, size_t ws_bytes,
+                            void* hip_stream, prs_batch** out)
+{
+    if (!out) return fail(PRS_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchLayout L;
+    prs_status st = batch_layout(items, count, L);
+    if (st != PRS_OK) return st;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
+        return fail(PRS_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(PRS_ENOMEM, "batch workspace too small: %zu bytes given, %zu needed", ws_bytes, L.total);
+    for (int32_t r = 0; r < count; ++r) {
+        const prs_batch_item& it = items[r];
+        if (!it.phi_a || !it.phi_b || !it.dphi || !aligned16(it.phi_a) || !aligned16(it.phi_b) ||
+            !aligned16(it.dphi) || it.phi_a == it.phi_b || it.phi_a == it.dphi || it.phi_b == it.dphi)
+            return fail(PRS_EINVAL, "batch item %d: three distinct 16-byte aligned fields required", r);
+    }
+    prs_batch* b = new (std::nothrow) prs_batch();
+    if (!b) return fail(PRS_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->items.assign(items, items + count);
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->ws = workspace;
+    b->ws_bytes = ws_bytes;
+    b->off_desc = L.desc;
+    b->off_coef = L.coef;
+    b->off_part = L.part;
+    b->off_rec = L.rec;
+    b->off_ctl = L.ctl;
+    b->coef_off = L.coef_off;
+    b->part_off = L.part_off;
+    b->part_cap = L.part_cap;
+    b->rec_off = L.rec_off;
+    b->total_recs = L.rec_off[count];
+    b->tmax = 0;
+    for (int32_t r = 0; r < count; ++r) {
+        b->geo.push_back(geometry_of(items[r].p));
+        Tiling t = default_tiling(b->geo.back());
+        if (!batch_tiling_supported(b->geo.back(), t)) t.ty = 1;
+        b->til.push_back(t);
+        b->tmax = std::max(b->tmax, items[r].nsteps);
+    }
+    b->mode = PRS_BATCH_PERSISTENT_GRAPH;
+    int khz = 0;
+    hipError_t e = batch_max_blocks(&b->grid_blocks);
+    if (e == hipSuccess) e = batch_clock_rate_khz(&khz);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->hrec),
+                                           (size_t)b->total_recs * sizeof(prs_stats), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->herr), sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        prs_batch_destroy(b);
+        return hip_fail(e, "batch setup");
+    }
+    // a step of the largest ensemble takes well under 0.1 s; 5 s means the
+    // grid is not co-resident
+    b->timeout_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 1000ull * 5ull;
+    b->dirty = true;
+    *out = b;
+    return PRS_OK;
+}
+
+prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty)
+{
+    if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
+    Tiling t{vec, rows, ty};
+    if (!batch_tiling_supported(b->geo[item], t))
+        return fail(PRS_EINVAL, "tiling vec=%d rows=%d ty=%d not available in batched runs", vec, rows, ty);
+    if (tile_counts(b->geo[item], t).ntiles > b->part_cap[item])
+        return fail(PRS_EINVAL, "tiling has more wave tiles than the workspace holds");
+    b->til[item] = t;
+    b->dirty = true;
+    return PRS_OK;
+}
+
+prs_status prs_batch_set_mode(prs_batch* b, int32_t mode)
+{
+    if (!b) return fail(PRS_EINVAL, "batch is NULL");
+    if (mode != PRS_BATCH_PERSISTENT_GRAPH && mode != PRS_BATCH_PERSISTENT && mode != PRS_BATCH_PER_STEP)
+        return fail(PRS_EINVAL, "unknown batch mode %d", mode);
+    b->mode = mode;
+    return PRS_OK;
+}
+
+prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets)
+{
+    if (!b || !offsets) return fail(PRS_EINVAL, "NULL argument");
+    for (int32_t r = 0; r <= b->count; ++r) offsets[r] = b->rec_off[r];
+    return PRS_OK;
+}
+
+prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
+{
+    if (!b) return fail(PRS_EINVAL, "batch is NULL");
+    if (series && cap < b->total_recs)
+        return fail(PRS_EINVAL, "series capacity %lld < %lld records", (long long)cap, (long long)b->total_recs);
+    if (b->dirty) {
+        batch_release_graph(b);
+        prs_status st = batch_upload(b);
+        if (st != PRS_OK) return st;
+        b->dirty = false;
+    }
+    *b->herr = 0;
+    if (b->mode == PRS_BATCH_PERSISTENT_GRAPH) {
+        if (!b->exec) {
+            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "graph capture");
+            prs_status st = batch_enqueue(b, true);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            if (st != PRS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(e, "graph capture end");
+            b->graph = g;
+            e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                batch_release_graph(b);
+                return hip_fail(e, "graph instantiate");
+            }
+        }
+        HIP_TRY(hipGraphLaunch(b->exec, b->stream), "graph launch");
+    } else {
+        prs_status st = batch_enqueue(b, b->mode == PRS_BATCH_PERSISTENT);
+        if (st != PRS_OK) return st;
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
+    if (*b->herr != 0)
+        return fail(PRS_EDEVICE, "batched run aborted: the grid barrier timed out (workgroups not co-resident)");
+    if (series) std::memcpy(series, b->hrec, (size_t)b->total_recs * sizeof(prs_stats));
+    return PRS_OK;
+}
+
+void prs_batch_destroy(prs_batch* b)
+{
+    if (!b) return;
+    batch_release_graph(b);
+    if (b->hrec) (void)hipHostFree(b->hrec);
+    if (b->herr) (void)hipHostFree(b->herr);
+    delete b;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+const char* prs_strerror(prs_status s)
+{
+    switch (s) {
+    case PRS_OK: return "ok";
+    case PRS_EINVAL: return "invalid argument";
+    case PRS_ENOMEM: return "out of memory or workspace too small";
+    case PRS_EDEVICE: return "HIP device error";
+    case PRS_ESTATE: return "invalid state for this call";
+    case PRS_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* prs_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal interface between the host API (prs_api.cpp) and the device code
+// (prs_kernels.hip).  Not installed; the public contract is include/prs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "prs.h"
+
+namespace prs {
+
+// Per-step coefficients of Eqs. (4)-(6), rounded to float32 from the FP64
+// schedule: a = (1-delta_n)/(1+delta_n), b = deta/(1+delta_n),
+// F = 4 V0/phi0^2, kc = 1/phi0^2, so that the kick reads
+// pi' = a pi + b (Lap phi - F phi (kc phi^2 - 1)).
+struct StepCoef {
+    float a, b, deta, F, kc, inv_dx2;
+};
+
+// FP64 constants of the diagnostics (Eq. 8 needs V(phi) = V0 (kc phi^2 - 1)^2).
+struct DiagCoef {
+    double V0, kc;
+};
+
+// Per-wave partial sums of one diagnostic pass; reduced in a fixed order.
+struct WavePartial {
+    uint32_t links[3];
+    uint32_t walls;
+    uint32_t nonfinite;
+    uint32_t pad;
+    double area;   // sum over crossing links of the Eq. (7) weight
+    double ek;     // sum over wall sites of (1/2) phi_dot^2 / V
+};
+
+// Lattice seen by the kernels: x (fastest), a middle axis of Q rows (y in
+// 3D, absent = 1 in 2D) and the marching axis of M planes (y in 2D, z in 3D).
+struct Geometry {
+    int ndim;
+    int64_t nx, Q, M;
+};
+
+struct Tiling {
+    int vec;    // sites per lane along x: 1, 2, 4
+    int rows;   // planes per wave along the marching axis
+    int ty;     // rows per wave along the middle axis (1 in 2D)
+};
+
+struct TileCounts {
+    int64_t tiles_x, tiles_q, tiles_s, ntiles;
+};
+
+Geometry geometry_of(const prs_params& p);
+TileCounts tile_counts(const Geometry& g, const Tiling& t);
+bool tiling_supported(const Geometry& g, const Tiling& t);
+
+// One fused step over the whole lattice: reads phi_in and pi, writes
+// phi_out and pi (in place) when update; writes one WavePartial per wave tile
+// when diag.  update == false && diag == true computes the diagnostics only.
+hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                       float* pi, const StepCoef& k, bool update, bool diag,
+                       WavePartial* partials, const DiagCoef& dc, hipStream_t s);
+
+// Reduces `count` partials in a fixed order into one record at `rec`.
+hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,
+                           int64_t step, double eta, double area_scale, hipStream_t s);
+
+hipError_t launch_fill_uniform(float* phi, int64_t count, uint64_t seed, hipStream_t s);
+
+// Coefficients of one reverse step n: a_n, b_n as in StepCoef, cw = deta
+// (0 on the final reverse step), gscale = -4 kc b_n in FP64.
+struct AdjCoef {
+    float a, b, cw, F, kc, inv_dx2;
+    double gscale;
+};
+
+// One reverse step: reads w_in (with halo), mu and phi^n; writes w_out and mu
+// (in place); adds this step's dL/dV0 contribution to gacc[wave tile].
+hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const float* w_in, float* w_out,
+                          float* mu, const float* phi_n, double* gacc, const AdjCoef& c,
+                          hipStream_t s);
+
+// mu = dL/dphi^S, w = deta*mu from the final field; FP64 loss partial per block.
+hipError_t launch_adj_seed(const float* phi, int64_t count, float kc, float deta, float* mu,
+                           float* w, double* partial, int nblocks, hipStream_t s);
+hipError_t launch_sum_f64(const double* v, int64_t count, double* out, hipStream_t s);
+hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s);
+
+// Batched ensemble (descriptor layout is private to the kernel file).
+size_t batch_desc_bytes();
+int batch_ctl_bytes();
+void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0, float* phi1, float* pi,
+                     const float2* coef, WavePartial* part0, WavePartial* part1, prs_stats* recs,
+                     int64_t nsteps, int64_t tile_base, int64_t nrec_regular, double eta0, double deta,
+                     double area_scale, int diag_every, const StepCoef& k, const DiagCoef& dc);
+bool batch_tiling_supported(const Geometry& g, const Tiling& t);
+hipError_t batch_max_blocks(int* blocks);
+hipError_t batch_clock_rate_khz(int* khz);
+hipError_t launch_batch_reset(void* ctl, hipStream_t s);
+hipError_t launch_batch_persistent(const void* descs, int nreal, int64_t total_tiles, int64_t tmax,
+                                   void* ctl, uint64_t timeout, int blocks, hipStream_t s);
+hipError_t launch_batch_step(const void* descs, int nreal, int64_t total_tiles, int64_t t, hipStream_t s);
+hipError_t launch_zero_f32(float* v, int64_t count, hipStream_t s);
+
+}  // namespace prs

@@ -1,0 +1,1204 @@
+// prs_kernels.hip -- gfx950 kernels of the PRS domain-wall evolution
+// (arXiv:1710.10420, Sec. II, Eqs. 3-8).
+//
+// One kernel does a whole step: the Laplacian (Eq. 3), the damped kick
+// (Eqs. 4, 6) and the drift (Eq. 5), and on diagnostic steps the wall area
+// (Eq. 7) and velocity (Eq. 8) sums of the step's input state.  The paper ran
+// these as separate kernels through global memory and named fusing them as
+// the next step; here each field value crosses HBM once per step: phi^n and
+// phi_dot are read once, phi^{n+1} and phi_dot written once (16 B per site).
+//
+// Work decomposition.  A wave (64 lanes) owns a tile of
+//   64*VEC sites along x  x  TY rows along the middle axis (3D only)
+// and marches along the slowest axis (y in 2D, z in 3D) through `rows`
+// planes.  The three planes s-1, s, s+1 it needs stay in registers and the
+// plane s+2 is already in flight while s is computed, so every phi value is
+// loaded from HBM once per tile.  x-neighbours come from the adjacent lane
+// (ds_bpermute shuffles); only the two wave-edge lanes load a halo scalar.
+// In 3D the rows above and below the tile are loaded per plane and are
+// served by L2, because the waves of a workgroup hold consecutive rows and
+// consecutive workgroups of one XCD hold consecutive tiles (xcd_remap).
+// Waves are independent: no LDS, no barriers.
+//
+// Arithmetic.  Every site runs the same inline sequence (explicit fmaf,
+// -ffp-contract=off), so results are bitwise independent of the tiling, of
+// the lane a site lands in and of the batch it runs in.  Neighbour sums are
+// grouped as (phi_- + phi_+) pairs, which makes x -> -x reflections and
+// phi -> -phi exact symmetries of the float32 update as well.
+//
+// Diagnostics.  Sign bits s = (phi >= 0) give the crossing links; counts are
+// per-lane 32-bit, reduced per wave with butterfly shuffles; the Eq. (7)
+// weight and the Eq. (8) ratio are evaluated in FP64 only at sites that
+// touch a wall.  Each wave writes one WavePartial; a single-workgroup
+// finalize kernel adds them in index order, so the record is deterministic.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "prs_internal.h"
+
+namespace prs {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcds = 8;
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
+// XCD b % 8).  Give each XCD a contiguous range of logical blocks so that
+// tiles that share halo rows run on the same XCD, close in time, and their
+// shared rows hit that XCD's L2.  Bijective for any grid size.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    int64_t xcd = b % kXcds, k = b / kXcds;
+    int64_t per = nb / kXcds, rem = nb % kXcds;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+__device__ __forceinline__ int64_t wrap(int64_t v, int64_t n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <int VEC>
+__device__ __forceinline__ void load_vec(const float* p, float (&v)[VEC])
+{
+    if constexpr (VEC == 4) {
+        float4 t = *reinterpret_cast<const float4*>(p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (VEC == 2) {
+        float2 t = *reinterpret_cast<const float2*>(p);
+        v[0] = t.x; v[1] = t.y;
+    } else {
+        v[0] = *p;
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void store_vec(float* p, const float (&v)[VEC])
+{
+    if constexpr (VEC == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (VEC == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+    } else {
+        *p = v[0];
+    }
+}
+
+// Eq. (3) (2D) and its 3D extension, times 1/dx^2.
+__device__ __forceinline__ float lap2(float c, float xm, float xp, float ym, float yp, float inv_dx2)
+{
+    float s = (xm + xp) + (ym + yp);
+    return fmaf(-4.0f, c, s) * inv_dx2;
+}
+
+__device__ __forceinline__ float lap3(float c, float xm, float xp, float ym, float yp, float zm,
+                                      float zp, float inv_dx2)
+{
+    float s = ((xm + xp) + (ym + yp)) + (zm + zp);
+    return fmaf(-6.0f, c, s) * inv_dx2;
+}
+
+// Eqs. (4)-(5) with the FP64-derived coefficients of StepCoef.
+__device__ __forceinline__ void kick_drift(float c, float lap, float pi, const StepCoef& k,
+                                           float& pi_new, float& phi_new)
+{
+    float q = c * c * k.kc - 1.0f;
+    float dv = (k.F * c) * q;                 // V'(phi)
+    pi_new = fmaf(k.a, pi, k.b * (lap - dv));  // Eq. (4)
+    phi_new = fmaf(k.deta, pi_new, c);         // Eq. (5)
+}
+
+struct DiagAcc {
+    uint32_t links[3];
+    uint32_t walls;
+    uint32_t nonfinite;
+    double area;
+    double ek;
+};
+
+// Eqs. (7)-(8) contribution of one site: forward links along each axis,
+// the wall flag from forward and backward links, the area weight
+// |g| / sum|g_d| from centred differences (the 1/(2 dx) factor cancels), and
+// (1/2) phi_dot^2 / V at wall sites.
+template <int D>
+__device__ __forceinline__ void site_diag(float c, float pi, const float (&nm)[D],
+                                          const float (&np)[D], const DiagCoef& dc, DiagAcc& a)
+{
+    const bool sc = c >= 0.0f;
+    int cross = 0;
+    bool wall = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const bool fwd = sc != (np[d] >= 0.0f);
+        const bool bwd = sc != (nm[d] >= 0.0f);
+        a.links[d] += fwd ? 1u : 0u;
+        cross += fwd ? 1 : 0;
+        wall = wall || fwd || bwd;
+    }
+    if (!(__builtin_isfinite(c) && __builtin_isfinite(pi))) a.nonfinite += 1u;
+    if (cross) {
+        double gsq = 0.0, gabs = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            double h = (double)np[d] - (double)nm[d];
+            gsq += h * h;
+            gabs += fabs(h);
+        }
+        double w = gabs > 0.0 ? sqrt(gsq) / gabs : 1.0;
+        a.area += (double)cross * w;
+    }
+    if (wall) {
+        a.walls += 1u;
+        double cd = (double)c;
+        double q = cd * cd * dc.kc - 1.0;
+        double V = dc.V0 * q * q;
+        if (V > 0.0) {
+            double pd = (double)pi;
+            a.ek += 0.5 * pd * pd / V;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+struct StepArgs {
+    const float* phi_in;
+    float* phi_out;
+    float* pi;
+    WavePartial* partials;
+    int64_t nx, Q, M;
+    int64_t tiles_x, tiles_q, ntiles;
+    int64_t rows;
+    StepCoef k;
+    DiagCoef dc;
+};
+
+template <int VEC, int TY>
+struct Plane {
+    float v[TY][VEC];
+    float hl[TY];   // x-halo left of lane 0
+    float hr[TY];   // x-halo right of the last lane
+};
+
+template <int VEC>
+struct Halo {
+    float lo[VEC];  // row q0-1 (3D)
+    float hi[VEC];  // row q0+nvalid (3D)
+};
+
+struct LaneGeom {
+    int64_t x0, xl, xr;
+    bool active, need_left, need_right;
+};
+
+template <int D, int VEC, int TY>
+__device__ __forceinline__ void load_plane(const float* __restrict__ phi, int64_t s,
+                                           const StepArgs& A, const LaneGeom& g, int64_t q0,
+                                           int nvalid, Plane<VEC, TY>& P, Halo<VEC>& H)
+{
+    const int64_t sw = wrap(s, A.M);
+    const float* base = phi + sw * (A.nx * A.Q);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+        if (t < nvalid) {
+            const float* row = base + (q0 + t) * A.nx;
+            if (g.active) load_vec<VEC>(row + g.x0, P.v[t]);
+            if (g.need_left) P.hl[t] = row[g.xl];
+            if (g.need_right) P.hr[t] = row[g.xr];
+        }
+    }
+    if constexpr (D == 3) {
+        if (g.active) {
+            load_vec<VEC>(base + wrap(q0 - 1, A.Q) * A.nx + g.x0, H.lo);
+            load_vec<VEC>(base + wrap(q0 + nvalid, A.Q) * A.nx + g.x0, H.hi);
+        }
+    }
+}
+
+template <int VEC, int TY>
+__device__ __forceinline__ void load_pi(const float* pi, int64_t s, const StepArgs& A,
+                                        const LaneGeom& g, int64_t q0, int nvalid,
+                                        float (&v)[TY][VEC])
+{
+    const float* base = pi + s * (A.nx * A.Q);
+#pragma unroll
+    for (int t = 0; t < TY; ++t)
+        if (t < nvalid && g.active) load_vec<VEC>(base + (q0 + t) * A.nx + g.x0, v[t]);
+}
+
+// One wave's tile of one step (see the file header).  `tile` must be below
+// A.ntiles and uniform across the wave.
+template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
+__device__ __forceinline__ void step_tile(const StepArgs& A, int64_t tile)
+{
+    static_assert(D == 3 || TY == 1, "2D tiles have one row");
+    const int lane = threadIdx.x & (kWave - 1);
+
+    const int64_t tq = tile % A.tiles_q;
+    const int64_t rest = tile / A.tiles_q;
+    const int64_t tx = rest % A.tiles_x;
+    const int64_t ts = rest / A.tiles_x;
+
+    LaneGeom g;
+    g.x0 = tx * (kWave * VEC) + (int64_t)lane * VEC;
+    g.active = g.x0 < A.nx;
+    g.need_left = g.active && lane == 0;
+    g.need_right = g.active && (lane == kWave - 1 || g.x0 + VEC >= A.nx);
+    g.xl = g.x0 == 0 ? A.nx - 1 : g.x0 - 1;
+    g.xr = g.x0 + VEC >= A.nx ? 0 : g.x0 + VEC;
+
+    const int64_t q0 = tq * TY;
+    const int nvalid = (int)((A.Q - q0) < TY ? (A.Q - q0) : TY);
+    const int64_t s0 = ts * A.rows;
+    const int64_t s1 = (s0 + A.rows) < A.M ? (s0 + A.rows) : A.M;
+    const int64_t pstride = A.nx * A.Q;
+
+    Plane<VEC, TY> Pm, Pc, Pn, Pnn;
+    Halo<VEC> Hc, Hn, Hnn, Hdummy;
+    float pic[TY][VEC], pin[TY][VEC];
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            Pm.v[t][j] = Pc.v[t][j] = Pn.v[t][j] = Pnn.v[t][j] = 0.0f;
+            pic[t][j] = pin[t][j] = 0.0f;
+        }
+        Pc.hl[t] = Pc.hr[t] = Pn.hl[t] = Pn.hr[t] = Pnn.hl[t] = Pnn.hr[t] = 0.0f;
+        Pm.hl[t] = Pm.hr[t] = 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j)
+        Hc.lo[j] = Hc.hi[j] = Hn.lo[j] = Hn.hi[j] = Hnn.lo[j] = Hnn.hi[j] = 0.0f;
+
+    load_plane<D, VEC, TY>(A.phi_in, s0 - 1, A, g, q0, nvalid, Pm, Hdummy);
+    load_plane<D, VEC, TY>(A.phi_in, s0, A, g, q0, nvalid, Pc, Hc);
+    load_plane<D, VEC, TY>(A.phi_in, s0 + 1, A, g, q0, nvalid, Pn, Hn);
+    load_pi<VEC, TY>(A.pi, s0, A, g, q0, nvalid, pic);
+
+    DiagAcc acc;
+    if constexpr (DIAG) {
+        acc.links[0] = acc.links[1] = acc.links[2] = 0u;
+        acc.walls = acc.nonfinite = 0u;
+        acc.area = acc.ek = 0.0;
+    }
+
+    for (int64_t s = s0; s < s1; ++s) {
+        if (s + 1 < s1) {
+            load_plane<D, VEC, TY>(A.phi_in, s + 2, A, g, q0, nvalid, Pnn, Hnn);
+            load_pi<VEC, TY>(A.pi, s + 1, A, g, q0, nvalid, pin);
+        }
+
+        float left[TY], right[TY];
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+            left[t] = __shfl_up(Pc.v[t][VEC - 1], 1, kWave);
+            right[t] = __shfl_down(Pc.v[t][0], 1, kWave);
+            if (lane == 0) left[t] = Pc.hl[t];
+            if (g.need_right) right[t] = Pc.hr[t];
+        }
+
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+            if (t >= nvalid) continue;
+            float out_phi[VEC], out_pi[VEC];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const float c = Pc.v[t][j];
+                const float xm = j > 0 ? Pc.v[t][j - 1] : left[t];
+                const float xp = j < VEC - 1 ? Pc.v[t][j + 1] : right[t];
+                float nm[D], np[D];
+                nm[0] = xm;
+                np[0] = xp;
+                if constexpr (D == 3) {
+                    nm[1] = t > 0 ? Pc.v[t > 0 ? t - 1 : 0][j] : Hc.lo[j];
+                    np[1] = (t + 1 < nvalid) ? Pc.v[t + 1 < TY ? t + 1 : t][j] : Hc.hi[j];
+                    nm[2] = Pm.v[t][j];
+                    np[2] = Pn.v[t][j];
+                } else {
+                    nm[1] = Pm.v[t][j];
+                    np[1] = Pn.v[t][j];
+                }
+                if constexpr (UPDATE) {
+                    float lap;
+                    if constexpr (D == 3)
+                        lap = lap3(c, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.k.inv_dx2);
+                    else
+                        lap = lap2(c, nm[0], np[0], nm[1], np[1], A.k.inv_dx2);
+                    kick_drift(c, lap, pic[t][j], A.k, out_pi[j], out_phi[j]);
+                }
+                if constexpr (DIAG) {
+                    if (g.active) site_diag<D>(c, pic[t][j], nm, np, A.dc, acc);
+                }
+            }
+            if constexpr (UPDATE) {
+                if (g.active) {
+                    const int64_t off = s * pstride + (q0 + t) * A.nx + g.x0;
+                    store_vec<VEC>(A.phi_out + off, out_phi);
+                    store_vec<VEC>(A.pi + off, out_pi);
+                }
+            }
+        }
+
+        Pm = Pc;
+        Pc = Pn;
+        Pn = Pnn;
+        Hc = Hn;
+        Hn = Hnn;
+#pragma unroll
+        for (int t = 0; t < TY; ++t)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) pic[t][j] = pin[t][j];
+    }
+
+    if constexpr (DIAG) {
+        WavePartial w;
+        w.links[0] = wave_sum_u32(acc.links[0]);
+        w.links[1] = wave_sum_u32(acc.links[1]);
+        w.links[2] = wave_sum_u32(acc.links[2]);
+        w.walls = wave_sum_u32(acc.walls);
+        w.nonfinite = wave_sum_u32(acc.nonfinite);
+        w.pad = 0u;
+        w.area = wave_sum_f64(acc.area);
+        w.ek = wave_sum_f64(acc.ek);
+        if (lane == 0) A.partials[tile] = w;
+    }
+}
+
+template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs A)
+{
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    if (tile >= A.ntiles) return;   // whole wave leaves; shuffles stay uniform
+    step_tile<D, VEC, TY, UPDATE, DIAG>(A, tile);
+}
+
+// Adds `count` wave partials into one record, with one wave, in a fixed
+// order: lane l sums partials l, l+64, l+128, ... and the 64 lane sums are
+// combined by a fixed butterfly.  Every path that produces a record (single
+// run, standalone diagnostics, batched ensemble) calls this function, so a
+// record depends only on the partials, never on which kernel reduced them.
+__device__ __forceinline__ void finalize_wave(const WavePartial* __restrict__ parts, int64_t count,
+                                              prs_stats* __restrict__ rec, int64_t step, double eta,
+                                              double area_scale)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t l0 = 0, l1 = 0, l2 = 0, wl = 0, nf = 0;
+    double ar = 0.0, ek = 0.0;
+    for (int64_t i = lane; i < count; i += kWave) {
+        const WavePartial p = parts[i];
+        l0 += p.links[0];
+        l1 += p.links[1];
+        l2 += p.links[2];
+        wl += p.walls;
+        nf += p.nonfinite;
+        ar += p.area;
+        ek += p.ek;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        l0 += __shfl_xor(l0, o, kWave);
+        l1 += __shfl_xor(l1, o, kWave);
+        l2 += __shfl_xor(l2, o, kWave);
+        wl += __shfl_xor(wl, o, kWave);
+        nf += __shfl_xor(nf, o, kWave);
+        ar += __shfl_xor(ar, o, kWave);
+        ek += __shfl_xor(ek, o, kWave);
+    }
+    if (lane == 0) {
+        prs_stats r;
+        r.step = step;
+        r.eta = eta;
+        r.links_dir[0] = l0;
+        r.links_dir[1] = l1;
+        r.links_dir[2] = l2;
+        r.links = l0 + l1 + l2;
+        r.wall_sites = wl;
+        r.nonfinite = nf;
+        r.area_density = ar * area_scale;
+        r.gv2 = wl ? ek / (double)wl : 0.0;
+        *rec = r;
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_finalize(const WavePartial* __restrict__ parts,
+                                                     int64_t count, prs_stats* __restrict__ rec,
+                                                     int64_t step, double eta, double area_scale)
+{
+    finalize_wave(parts, count, rec, step, eta, area_scale);
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) evaluated at counter i+1, top 24
+// bits k mapped to (2k+1)/2^24 - 1.
+__global__ __launch_bounds__(kBlock) void k_fill_uniform(float* __restrict__ phi, int64_t count,
+                                                          uint64_t seed)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z = z ^ (z >> 31);
+        const int32_t k = (int32_t)(z >> 40);
+        phi[i] = (float)(2 * k + 1 - (1 << 24)) * 0x1p-24f;
+    }
+}
+
+
+// ---------------------------------------------------------------- adjoint --
+//
+// Reverse sweep of one step n of Eqs. (3)-(6).  The carried adjoint state is
+// (mu, w): mu = dL/dphi^{n+1} and w = nu + deta*mu, the total adjoint of
+// phi_dot^{n+1/2} (nu being its adjoint through later kicks).  Differentiating
+// the kick and drift gives, per site,
+//     mu^n    = mu^{n+1} + b_n (Lap w - V''(phi^n) w)     (Lap is symmetric)
+//     w_{n-1} = a_n w + cw * mu^n                          (cw = deta; 0 on the
+//                                                           last reverse step,
+//                                                           which leaves nu = a w)
+//     dL/dV0 += -b_n sum_i w_i d V'(phi_i)/dV0,  dV'/dV0 = 4 kc phi (kc phi^2 - 1)
+// Same march and tiling as the forward kernel: w is the stencil field (read
+// with halo, written to the other buffer), mu is updated in place and phi^n
+// is read once.  20 bytes of HBM traffic per site.
+
+struct AdjArgs {
+    const float* w_in;
+    float* w_out;
+    float* mu;
+    const float* phi_n;
+    double* gacc;       // one accumulator per wave tile, persistent across steps
+    int64_t nx, Q, M;
+    int64_t tiles_x, tiles_q, ntiles;
+    int64_t rows;
+    float a, b, cw, F, kc, inv_dx2;
+    double gscale;      // -4 kc b_n
+};
+
+template <int VEC, int TY>
+__device__ __forceinline__ void load_point(const float* f, int64_t s, int64_t nx, int64_t Q,
+                                           const LaneGeom& g, int64_t q0, int nvalid,
+                                           float (&v)[TY][VEC])
+{
+    const float* base = f + s * (nx * Q);
+#pragma unroll
+    for (int t = 0; t < TY; ++t)
+        if (t < nvalid && g.active) load_vec<VEC>(base + (q0 + t) * nx + g.x0, v[t]);
+}
+
+template <int D, int VEC, int TY>
+__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    if (tile >= A.ntiles) return;
+
+    const int64_t tq = tile % A.tiles_q;
+    const int64_t rest = tile / A.tiles_q;
+    const int64_t tx = rest % A.tiles_x;
+    const int64_t ts = rest / A.tiles_x;
+
+    LaneGeom g;
+    g.x0 = tx * (kWave * VEC) + (int64_t)lane * VEC;
+    g.active = g.x0 < A.nx;
+    g.need_left = g.active && lane == 0;
+    g.need_right = g.active && (lane == kWave - 1 || g.x0 + VEC >= A.nx);
+    g.xl = g.x0 == 0 ? A.nx - 1 : g.x0 - 1;
+    g.xr = g.x0 + VEC >= A.nx ? 0 : g.x0 + VEC;
+
+    const int64_t q0 = tq * TY;
+    const int nvalid = (int)((A.Q - q0) < TY ? (A.Q - q0) : TY);
+    const int64_t s0 = ts * A.rows;
+    const int64_t s1 = (s0 + A.rows) < A.M ? (s0 + A.rows) : A.M;
+    const int64_t pstride = A.nx * A.Q;
+
+    // geometry view for the shared plane loader
+    StepArgs G;
+    G.nx = A.nx;
+    G.Q = A.Q;
+    G.M = A.M;
+
+    Plane<VEC, TY> Pm, Pc, Pn, Pnn;
+    Halo<VEC> Hc, Hn, Hnn, Hdummy;
+    float muc[TY][VEC], mun[TY][VEC], phc[TY][VEC], phn[TY][VEC];
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            Pm.v[t][j] = Pc.v[t][j] = Pn.v[t][j] = Pnn.v[t][j] = 0.0f;
+            muc[t][j] = mun[t][j] = phc[t][j] = phn[t][j] = 0.0f;
+        }
+        Pm.hl[t] = Pm.hr[t] = Pc.hl[t] = Pc.hr[t] = 0.0f;
+        Pn.hl[t] = Pn.hr[t] = Pnn.hl[t] = Pnn.hr[t] = 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j)
+        Hc.lo[j] = Hc.hi[j] = Hn.lo[j] = Hn.hi[j] = Hnn.lo[j] = Hnn.hi[j] = 0.0f;
+
+    load_plane<D, VEC, TY>(A.w_in, s0 - 1, G, g, q0, nvalid, Pm, Hdummy);
+    load_plane<D, VEC, TY>(A.w_in, s0, G, g, q0, nvalid, Pc, Hc);
+    load_plane<D, VEC, TY>(A.w_in, s0 + 1, G, g, q0, nvalid, Pn, Hn);
+    load_point<VEC, TY>(A.mu, s0, A.nx, A.Q, g, q0, nvalid, muc);
+    load_point<VEC, TY>(A.phi_n, s0, A.nx, A.Q, g, q0, nvalid, phc);
+
+    double gsum = 0.0;
+    for (int64_t s = s0; s < s1; ++s) {
+        if (s + 1 < s1) {
+            load_plane<D, VEC, TY>(A.w_in, s + 2, G, g, q0, nvalid, Pnn, Hnn);
+            load_point<VEC, TY>(A.mu, s + 1, A.nx, A.Q, g, q0, nvalid, mun);
+            load_point<VEC, TY>(A.phi_n, s + 1, A.nx, A.Q, g, q0, nvalid, phn);
+        }
+        float left[TY], right[TY];
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+            left[t] = __shfl_up(Pc.v[t][VEC - 1], 1, kWave);
+            right[t] = __shfl_down(Pc.v[t][0], 1, kWave);
+            if (lane == 0) left[t] = Pc.hl[t];
+            if (g.need_right) right[t] = Pc.hr[t];
+        }
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+            if (t >= nvalid) continue;
+            float out_w[VEC], out_mu[VEC];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const float w = Pc.v[t][j];
+                const float xm = j > 0 ? Pc.v[t][j - 1] : left[t];
+                const float xp = j < VEC - 1 ? Pc.v[t][j + 1] : right[t];
+                float lap;
+                if constexpr (D == 3) {
+                    const float ym = t > 0 ? Pc.v[t > 0 ? t - 1 : 0][j] : Hc.lo[j];
+                    const float yp = (t + 1 < nvalid) ? Pc.v[t + 1 < TY ? t + 1 : t][j] : Hc.hi[j];
+                    lap = lap3(w, xm, xp, ym, yp, Pm.v[t][j], Pn.v[t][j], A.inv_dx2);
+                } else {
+                    lap = lap2(w, xm, xp, Pm.v[t][j], Pn.v[t][j], A.inv_dx2);
+                }
+                const float ph = phc[t][j];
+                const float q = ph * ph * A.kc - 1.0f;
+                const float v2 = A.F * (3.0f * ph * ph * A.kc - 1.0f);   // V''(phi)
+                const float mu_new = fmaf(A.b, lap - v2 * w, muc[t][j]);
+                out_mu[j] = mu_new;
+                out_w[j] = fmaf(A.cw, mu_new, A.a * w);
+                if (g.active) gsum += (double)(w * (ph * q));
+            }
+            if (g.active) {
+                const int64_t off = s * pstride + (q0 + t) * A.nx + g.x0;
+                store_vec<VEC>(A.w_out + off, out_w);
+                store_vec<VEC>(A.mu + off, out_mu);
+            }
+        }
+        Pm = Pc;
+        Pc = Pn;
+        Pn = Pnn;
+        Hc = Hn;
+        Hn = Hnn;
+#pragma unroll
+        for (int t = 0; t < TY; ++t)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                muc[t][j] = mun[t][j];
+                phc[t][j] = phn[t][j];
+            }
+    }
+    gsum = wave_sum_f64(gsum);
+    if (lane == 0) A.gacc[tile] += A.gscale * gsum;
+}
+
+// Seed of the reverse sweep and the loss sum V/V0 = (kc phi^2 - 1)^2 over the
+// final field: mu = dL/dphi = 4 kc phi (kc phi^2 - 1), w = deta * mu (the
+// final phi_dot does not enter the loss).  Fixed grid; one FP64 partial per
+// workgroup.
+__global__ __launch_bounds__(kBlock) void k_adj_seed(const float* __restrict__ phi, int64_t count,
+                                                      float kc, float deta, float* __restrict__ mu,
+                                                      float* __restrict__ w,
+                                                      double* __restrict__ partial)
+{
+    __shared__ double sh[kBlock];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+        const float f = phi[i];
+        const float q = f * f * kc - 1.0f;
+        const float m = (4.0f * kc) * f * q;
+        mu[i] = m;
+        w[i] = deta * m;
+        const double qd = (double)f * (double)f * (double)kc - 1.0;
+        acc += qd * qd;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Sum of `count` doubles in a fixed order into *out.
+__global__ __launch_bounds__(kBlock) void k_sum_f64(const double* __restrict__ v, int64_t count,
+                                                     double* __restrict__ out)
+{
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += kBlock) acc += v[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// Fills count doubles with 0 (a kernel rather than a memset, so the sequence
+// can also live inside a captured graph).
+__global__ __launch_bounds__(kBlock) void k_zero_f64(double* __restrict__ v, int64_t count)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) v[i] = 0.0;
+}
+
+template <int D, int VEC, int TY>
+hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s)
+{
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL((k_adjoint<D, VEC, TY>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------------- batched ensemble --
+//
+// Many independent realisations (different sizes, dimensions, eras, wall
+// widths and step counts) advance together.  Step t's work list is every
+// wave tile of every realisation with t <= S_r: a realisation steps while
+// t < S_r (fused diagnostics when t % K_r == 0) and gets a diagnostics-only
+// pass of its final state at t == S_r.  Each tile runs step_tile, the same
+// code as a single run, so a realisation's fields and records are bitwise
+// those of the same realisation run alone with the same tiling.
+//
+// Persistent mode: one launch whose workgroups stay resident for the whole
+// ensemble; a wave walks the global tile list with stride = number of waves,
+// then all workgroups meet at a software grid barrier before step t+1.  The
+// records of step t are reduced by one wave per realisation right after
+// that barrier.  The barrier's wait is bounded: if it does not complete within
+// the time limit (workgroups not co-resident), an error flag is raised and
+// every workgroup leaves, so the kernel always finishes.
+
+struct BatchDesc {
+    StepArgs A;              // geometry, tiling and constant coefficients
+    float* phi[2];           // phi^n lives in phi[n & 1]
+    const float2* coef;      // (a_n, b_n) for n = 0 .. nsteps-1
+    WavePartial* part[2];    // alternate record partial buffers
+    prs_stats* recs;         // nrec_regular + 1 records
+    int64_t nsteps;
+    int64_t tile_base;       // first global tile of this realisation
+    int64_t nrec_regular;    // records of states n < nsteps
+    double eta0, deta, area_scale;
+    int32_t ndim, vec, ty, diag_every;
+};
+
+struct BatchCtl {
+    unsigned int arrive;
+    unsigned int gen;
+    int err;
+    int pad;
+};
+
+// Record index of state t of realisation d, if it has one.
+__device__ __forceinline__ bool record_index(const BatchDesc& d, int64_t t, int64_t& j)
+{
+    if (t == d.nsteps) {
+        j = d.nrec_regular;
+        return true;
+    }
+    if (t < d.nsteps && d.diag_every > 0 && t % d.diag_every == 0) {
+        j = t / d.diag_every;
+        return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ int find_real(const BatchDesc* __restrict__ D, int nreal, int64_t tile)
+{
+    int lo = 0, hi = nreal - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (D[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D, int VEC, int TY>
+__device__ __forceinline__ void tile_mode(const StepArgs& A, int64_t tile, bool update, bool diag)
+{
+    if (update && diag) step_tile<D, VEC, TY, true, true>(A, tile);
+    else if (update) step_tile<D, VEC, TY, true, false>(A, tile);
+    else step_tile<D, VEC, TY, false, true>(A, tile);
+}
+
+// Tilings available inside the batched kernels (every instance is inlined
+// into them, so the set is kept small to bound register pressure).
+__device__ __forceinline__ void dispatch_tile(int ndim, int vec, int ty, const StepArgs& A,
+                                              int64_t tile, bool update, bool diag)
+{
+    if (ndim == 2) {
+        if (vec == 4) tile_mode<2, 4, 1>(A, tile, update, diag);
+        else if (vec == 2) tile_mode<2, 2, 1>(A, tile, update, diag);
+        else tile_mode<2, 1, 1>(A, tile, update, diag);
+    } else if (ty == 2) {
+        if (vec == 2) tile_mode<3, 2, 2>(A, tile, update, diag);
+        else tile_mode<3, 1, 2>(A, tile, update, diag);
+    } else {
+        if (vec == 4) tile_mode<3, 4, 1>(A, tile, update, diag);
+        else if (vec == 2) tile_mode<3, 2, 1>(A, tile, update, diag);
+        else tile_mode<3, 1, 1>(A, tile, update, diag);
+    }
+}
+
+// Work of global tile i at step t.
+__device__ __forceinline__ void batch_tile(const BatchDesc* __restrict__ Dd, int nreal, int64_t i,
+                                           int64_t t)
+{
+    const BatchDesc& d = Dd[find_real(Dd, nreal, i)];
+    if (t > d.nsteps) return;
+    const bool update = t < d.nsteps;
+    int64_t j = 0;
+    const bool diag = record_index(d, t, j);
+    StepArgs A = d.A;
+    A.phi_in = d.phi[t & 1];
+    A.phi_out = d.phi[(t + 1) & 1];
+    if (update) {
+        const float2 c = d.coef[t];
+        A.k.a = c.x;
+        A.k.b = c.y;
+    }
+    A.partials = diag ? d.part[j & 1] : nullptr;
+    dispatch_tile(d.ndim, d.vec, d.ty, A, i - d.tile_base, update, diag);
+}
+
+// Records of state t, one wave per realisation (waves w, w+nw, ...).
+__device__ __forceinline__ void batch_records(const BatchDesc* __restrict__ Dd, int nreal, int64_t t,
+                                              int64_t wave, int64_t nwaves)
+{
+    for (int64_t r = wave; r < nreal; r += nwaves) {
+        const BatchDesc& d = Dd[r];
+        int64_t j;
+        if (record_index(d, t, j))
+            finalize_wave(d.part[j & 1], d.A.ntiles, d.recs + j, t, d.eta0 + (double)t * d.deta,
+                          d.area_scale);
+    }
+}
+
+// Grid-wide barrier for a resident grid.  Arrivals count up monotonically;
+// the last arrival of generation g publishes g+1.  Release/acquire fences at
+// agent scope make every field written before the barrier visible to every
+// XCD after it.  Returns false (and raises ctl->err) when the wait exceeds
+// `timeout` wall-clock ticks or another workgroup has already failed.
+__device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned gen,
+                                             uint64_t timeout)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        const unsigned prev =
+            __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev + 1u == (gen + 1u) * nblocks) {
+            __hip_atomic_store(&ctl->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <= gen) {
+                if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > timeout) {
+                    __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_persistent(const BatchDesc* __restrict__ Dd,
+                                                              int nreal, int64_t total_tiles,
+                                                              int64_t tmax, BatchCtl* ctl,
+                                                              uint64_t timeout)
+{
+    const int64_t wave = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    unsigned gen = 0;
+    for (int64_t t = 0; t <= tmax + 1; ++t) {
+        if (t > 0) batch_records(Dd, nreal, t - 1, wave, nwaves);
+        if (t > tmax) break;
+        for (int64_t i = wave; i < total_tiles; i += nwaves) batch_tile(Dd, nreal, i, t);
+        if (!grid_barrier(ctl, gridDim.x, gen, timeout)) return;
+        ++gen;
+    }
+}
+
+// Fallback without a resident grid: one launch per step over all tiles,
+// then one launch for that step's records.
+__global__ __launch_bounds__(kBlock) void k_batch_step(const BatchDesc* __restrict__ Dd, int nreal,
+                                                        int64_t total_tiles, int64_t t)
+{
+    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + threadIdx.x / kWave;
+    if (i >= total_tiles) return;
+    batch_tile(Dd, nreal, i, t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_records(const BatchDesc* __restrict__ Dd, int nreal,
+                                                           int64_t t)
+{
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    batch_records(Dd, nreal, t, wave, (int64_t)gridDim.x * kWavesPerBlock);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_f32(float* __restrict__ v, int64_t count)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) v[i] = 0.0f;
+}
+
+__global__ void k_batch_reset(BatchCtl* ctl)
+{
+    if (threadIdx.x == 0) {
+        ctl->arrive = 0u;
+        ctl->gen = 0u;
+        ctl->err = 0;
+        ctl->pad = 0;
+    }
+}
+
+template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
+hipError_t launch_t(const StepArgs& A, hipStream_t s)
+{
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL((k_step<D, VEC, TY, UPDATE, DIAG>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                       s, A);
+    return hipGetLastError();
+}
+
+template <int D, int VEC, int TY>
+hipError_t launch_mode(const StepArgs& A, bool update, bool diag, hipStream_t s)
+{
+    if (update && diag) return launch_t<D, VEC, TY, true, true>(A, s);
+    if (update) return launch_t<D, VEC, TY, true, false>(A, s);
+    if (diag) return launch_t<D, VEC, TY, false, true>(A, s);
+    return hipSuccess;
+}
+
+template <int D, int VEC>
+hipError_t launch_ty(const StepArgs& A, int ty, bool update, bool diag, hipStream_t s)
+{
+    if constexpr (D == 2) {
+        return launch_mode<2, VEC, 1>(A, update, diag, s);
+    } else {
+        switch (ty) {
+        case 1: return launch_mode<3, VEC, 1>(A, update, diag, s);
+        case 2: return launch_mode<3, VEC, 2>(A, update, diag, s);
+        case 4: return launch_mode<3, VEC, 4>(A, update, diag, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+}  // namespace
+
+Geometry geometry_of(const prs_params& p)
+{
+    Geometry g;
+    g.ndim = p.ndim;
+    g.nx = p.n[0];
+    if (p.ndim == 2) {
+        g.Q = 1;
+        g.M = p.n[1];
+    } else {
+        g.Q = p.n[1];
+        g.M = p.n[2];
+    }
+    return g;
+}
+
+TileCounts tile_counts(const Geometry& g, const Tiling& t)
+{
+    TileCounts c;
+    c.tiles_x = (g.nx + (int64_t)kWave * t.vec - 1) / ((int64_t)kWave * t.vec);
+    c.tiles_q = (g.Q + t.ty - 1) / t.ty;
+    c.tiles_s = (g.M + t.rows - 1) / t.rows;
+    c.ntiles = c.tiles_x * c.tiles_q * c.tiles_s;
+    return c;
+}
+
+bool tiling_supported(const Geometry& g, const Tiling& t)
+{
+    if (t.vec != 1 && t.vec != 2 && t.vec != 4) return false;
+    if (g.nx % t.vec != 0) return false;
+    if (t.rows < 1 || t.rows > 4096) return false;
+    if (g.ndim == 2) return t.ty == 1;
+    return t.ty == 1 || t.ty == 2 || t.ty == 4;
+}
+
+hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                       float* pi, const StepCoef& k, bool update, bool diag,
+                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
+{
+    const TileCounts c = tile_counts(g, t);
+    StepArgs A;
+    A.phi_in = phi_in;
+    A.phi_out = phi_out;
+    A.pi = pi;
+    A.partials = partials;
+    A.nx = g.nx;
+    A.Q = g.Q;
+    A.M = g.M;
+    A.tiles_x = c.tiles_x;
+    A.tiles_q = c.tiles_q;
+    A.ntiles = c.ntiles;
+    A.rows = t.rows;
+    A.k = k;
+    A.dc = dc;
+    if (g.ndim == 2) {
+        switch (t.vec) {
+        case 1: return launch_ty<2, 1>(A, 1, update, diag, s);
+        case 2: return launch_ty<2, 2>(A, 1, update, diag, s);
+        case 4: return launch_ty<2, 4>(A, 1, update, diag, s);
+        }
+    } else {
+        switch (t.vec) {
+        case 1: return launch_ty<3, 1>(A, t.ty, update, diag, s);
+        case 2: return launch_ty<3, 2>(A, t.ty, update, diag, s);
+        case 4: return launch_ty<3, 4>(A, t.ty, update, diag, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,
+                           int64_t step, double eta, double area_scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWave), 0, s, partials, count, rec, step, eta,
+                       area_scale);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const float* w_in, float* w_out,
+                          float* mu, const float* phi_n, double* gacc, const AdjCoef& c,
+                          hipStream_t s)
+{
+    const TileCounts tc = tile_counts(g, t);
+    AdjArgs A;
+    A.w_in = w_in;
+    A.w_out = w_out;
+    A.mu = mu;
+    A.phi_n = phi_n;
+    A.gacc = gacc;
+    A.nx = g.nx;
+    A.Q = g.Q;
+    A.M = g.M;
+    A.tiles_x = tc.tiles_x;
+    A.tiles_q = tc.tiles_q;
+    A.ntiles = tc.ntiles;
+    A.rows = t.rows;
+    A.a = c.a;
+    A.b = c.b;
+    A.cw = c.cw;
+    A.F = c.F;
+    A.kc = c.kc;
+    A.inv_dx2 = c.inv_dx2;
+    A.gscale = c.gscale;
+    if (g.ndim == 2) {
+        switch (t.vec) {
+        case 1: return launch_adj_t<2, 1, 1>(A, s);
+        case 2: return launch_adj_t<2, 2, 1>(A, s);
+        case 4: return launch_adj_t<2, 4, 1>(A, s);
+        }
+    } else {
+#define PRS_ADJ3(V)                                          \
+    switch (t.ty) {                                          \
+    case 1: return launch_adj_t<3, V, 1>(A, s);              \
+    case 2: return launch_adj_t<3, V, 2>(A, s);              \
+    case 4: return launch_adj_t<3, V, 4>(A, s);              \
+    }                                                        \
+    break;
+        switch (t.vec) {
+        case 1: PRS_ADJ3(1)
+        case 2: PRS_ADJ3(2)
+        case 4: PRS_ADJ3(4)
+        }
+#undef PRS_ADJ3
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_seed(const float* phi, int64_t count, float kc, float deta, float* mu,
+                           float* w, double* partial, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_seed, dim3(nblocks), dim3(kBlock), 0, s, phi, count, kc, deta, mu, w,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_f64(const double* v, int64_t count, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(kBlock), 0, s, v, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)blocks), dim3(kBlock), 0, s, v, count);
+    return hipGetLastError();
+}
+
+
+// ---- batched ensemble launchers ----
+
+size_t batch_desc_bytes() { return sizeof(BatchDesc); }
+
+void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0, float* phi1, float* pi,
+                     const float2* coef, WavePartial* part0, WavePartial* part1, prs_stats* recs,
+                     int64_t nsteps, int64_t tile_base, int64_t nrec_regular, double eta0, double deta,
+                     double area_scale, int diag_every, const StepCoef& k, const DiagCoef& dc)
+{
+    const TileCounts c = tile_counts(g, t);
+    BatchDesc d;
+    d.A.phi_in = nullptr;
+    d.A.phi_out = nullptr;
+    d.A.pi = pi;
+    d.A.partials = nullptr;
+    d.A.nx = g.nx;
+    d.A.Q = g.Q;
+    d.A.M = g.M;
+    d.A.tiles_x = c.tiles_x;
+    d.A.tiles_q = c.tiles_q;
+    d.A.ntiles = c.ntiles;
+    d.A.rows = t.rows;
+    d.A.k = k;
+    d.A.dc = dc;
+    d.phi[0] = phi0;
+    d.phi[1] = phi1;
+    d.coef = coef;
+    d.part[0] = part0;
+    d.part[1] = part1;
+    d.recs = recs;
+    d.nsteps = nsteps;
+    d.tile_base = tile_base;
+    d.nrec_regular = nrec_regular;
+    d.eta0 = eta0;
+    d.deta = deta;
+    d.area_scale = area_scale;
+    d.ndim = g.ndim;
+    d.vec = t.vec;
+    d.ty = t.ty;
+    d.diag_every = diag_every;
+    *static_cast<BatchDesc*>(out) = d;
+}
+
+bool batch_tiling_supported(const Geometry& g, const Tiling& t)
+{
+    if (!tiling_supported(g, t)) return false;
+    if (g.ndim == 2) return true;
+    return t.ty == 1 || (t.ty == 2 && t.vec <= 2);
+}
+
+hipError_t batch_max_blocks(int* blocks)
+{
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_persistent, kBlock, 0);
+    if (e != hipSuccess) return e;
+    *blocks = cus * per;
+    return hipSuccess;
+}
+
+hipError_t batch_clock_rate_khz(int* khz)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    return hipDeviceGetAttribute(khz, hipDeviceAttributeWallClockRate, dev);
+}
+
+hipError_t launch_batch_reset(void* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kWave), 0, s, static_cast<BatchCtl*>(ctl));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_persistent(const void* descs, int nreal, int64_t total_tiles, int64_t tmax,
+                                   void* ctl, uint64_t timeout, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_persistent, dim3(blocks), dim3(kBlock), 0, s,
+                       static_cast<const BatchDesc*>(descs), nreal, total_tiles, tmax,
+                       static_cast<BatchCtl*>(ctl), timeout);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const void* descs, int nreal, int64_t total_tiles, int64_t t, hipStream_t s)
+{
+    const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_batch_step, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       static_cast<const BatchDesc*>(descs), nreal, total_tiles, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rb = (nreal + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_batch_records, dim3(rb), dim3(kBlock), 0, s, static_cast<const BatchDesc*>(descs),
+                       nreal, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float* v, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)blocks), dim3(kBlock), 0, s, v, count);
+    return hipGetLastError();
+}
+
+int batch_ctl_bytes() { return (int)sizeof(BatchCtl); }
+
+hipError_t launch_fill_uniform(float* phi, int64_t count, uint64_t seed, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_uniform, dim3((unsigned)blocks), dim3(kBlock), 0, s, phi, count,
+                       seed);
+    return hipGetLastError();
+}
+
+}  // namespace prs

@@ -77,3 +77,10 @@ def ensemble_draw(master_seed=2017, n2d=48, n3d=16,
         items.append({"ndim": 3 if three else 2, "N": N, "m": m, "W0": W0,
                       "deta": deta, "steps": steps, "seed": 1000 + r})
     return items
+
+
+def uniform_at(seed, index):
+    """float32 initial-field values at arbitrary linear site indices."""
+    idx = np.asarray(index, dtype=np.uint64) + np.uint64(1)
+    k = (splitmix64(seed, idx) >> np.uint64(40)).astype(np.int64)
+    return ((2 * k + 1 - (1 << 24)).astype(np.float32) * np.float32(2.0 ** -24))

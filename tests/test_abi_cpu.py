@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/prs.h declares, and rejects invalid arguments before any
+launch."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+prs = pytest.importorskip("paper_1710_10420_amd.prs")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(prs_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert {"prs_init", "prs_step_n", "prs_wall_stats"} <= names
+    for n in sorted(names):
+        assert hasattr(prs._lib, n), n
+    assert names <= set(prs.EXPORTED) | set(getattr(prs, "EXPORTED_EXTRA", []))
+
+
+def c1():
+    return prs.make_params((256, 256), deta=0.25, m=1.0, W0=10.0, diag_every=10)
+
+
+def test_workspace_and_records():
+    p = c1()
+    assert prs.prs_workspace_bytes(p) > 0
+    assert prs.prs_records_in(p, 0, 508) == 51
+    assert prs.prs_records_in(p, 0, 500) == 50
+    assert prs.prs_records_in(p, 3, 8) == 1           # n = 10
+    assert prs.prs_records_in(p, 11, 9) == 0
+    p.diag_every = 0
+    assert prs.prs_records_in(p, 0, 100) == 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("ndim", 4, prs.PRS_EINVAL),
+    ("deta", 1.5, prs.PRS_EINVAL),          # unstable: deta*sqrt(8 + 8 V0) > 2
+    ("deta", -0.1, prs.PRS_EINVAL),
+    ("eta0", 0.0, prs.PRS_EINVAL),
+    ("m", -1.0, prs.PRS_EINVAL),
+    ("W0", 0.0, prs.PRS_EINVAL),
+    ("beta", 2.0, prs.PRS_EUNSUPPORTED),
+    ("phi0", -1.0, prs.PRS_EINVAL),
+])
+def test_invalid_params_rejected_before_launch(field, value, code):
+    p = c1()
+    setattr(p, field, value)
+    assert prs.prs_workspace_bytes(p) == 0
+    with pytest.raises(prs.PRSError) as e:
+        prs.prs_init(p, 16, 32, 48, 256, 1 << 30, None)
+    assert e.value.status == code
+
+
+def test_first_damping_factor_bound():
+    p = c1()
+    p.m, p.eta0, p.deta = 2.0, 0.5, 0.25     # delta_0 = 0.75 * 2 = 1.5
+    with pytest.raises(prs.PRSError) as e:
+        prs.prs_init(p, 16, 32, 48, 256, 1 << 30, None)
+    assert e.value.status == prs.PRS_EINVAL and "delta_0" in str(e.value)
+
+
+def test_buffer_checks_before_launch():
+    p = c1()
+    with pytest.raises(prs.PRSError):
+        prs.prs_init(p, 0, 32, 48, 256, 1 << 30, None)          # NULL phi
+    with pytest.raises(prs.PRSError):
+        prs.prs_init(p, 17, 32, 48, 256, 1 << 30, None)         # misaligned
+    with pytest.raises(prs.PRSError):
+        prs.prs_init(p, 16, 16, 48, 256, 1 << 30, None)         # aliasing
+    with pytest.raises(prs.PRSError) as e:
+        prs.prs_init(p, 16, 32, 48, 256, 10, None)              # workspace too small
+    assert e.value.status == prs.PRS_ENOMEM
+
+
+def test_fit_matches_oracle_fit():
+    rng = np.random.default_rng(0)
+    eta = np.linspace(1.0, 4096.0, 257)
+    recs = []
+    for i, e in enumerate(eta):
+        recs.append({"step": i, "eta": e, "links": 0, "links_dir": [0, 0, 0], "wall_sites": 0,
+                     "nonfinite": 0, "area_density": 2.0 * e ** -0.95 * (1 + 0.01 * rng.standard_normal()),
+                     "gv2": 0.3 * e ** -0.1 * (1 + 0.01 * rng.standard_normal())})
+    mu, nu = prs.prs_fit_scaling(recs, 409.6, 4096.0)
+    omu, onu = O.scaling_exponents(recs, 409.6, 4096.0)
+    assert mu == pytest.approx(omu, abs=1e-12) and nu == pytest.approx(onu, abs=1e-12)
+    assert mu == pytest.approx(-0.95, abs=0.02)
+    mu, nu = prs.prs_fit_scaling(recs[:1])
+    assert math.isnan(mu)

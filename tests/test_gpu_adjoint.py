@@ -1,0 +1,125 @@
+"""Parity of the GPU adjoint (prs_adjoint*, PRSLoss) with the FP64 oracle
+adjoint.  The GPU differentiates its own float32 trajectory and the oracle
+its float64 one, so gradients agree to the trajectory's rounding: relative L2
+<= 1e-4 for runs of up to 64 steps (the oracle adjoint itself is pinned to
+central finite differences in test_oracle_pins)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1710_10420_amd.inputs import uniform_field
+from tests.gpu_util import gpu_prs, host, params_pair, say, to_dev, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_adjoint(gp, phi0, nsteps, K, tiling=None):
+    torch = torch_mod()
+    prs = gpu_prs()
+    sim = prs.Sim(gp, phi0=to_dev(phi0))
+    if tiling is not None:
+        sim.set_tiling(*tiling)
+    nb = prs.prs_adjoint_workspace_bytes(gp, nsteps, K)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    gphi = torch.empty_like(sim.phi_a)
+    gdphi = torch.empty_like(sim.phi_a)
+    loss, gw = prs.prs_adjoint(sim.ctx, nsteps, K, work.data_ptr(), nb, gphi.data_ptr(),
+                               gdphi.data_ptr())
+    return loss, host(gphi), host(gdphi), gw, sim
+
+
+@pytest.mark.parametrize("shape,nsteps,K", [
+    ((32, 32), 16, 7), ((32, 32), 48, 16), ((256, 256), 64, 16), ((24, 20, 18), 20, 6),
+    ((100, 37), 33, 10), ((37, 20, 11), 12, 64),
+])
+def test_adjoint_matches_oracle(shape, nsteps, K):
+    say("adjoint", shape, nsteps, K)
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp, op = params_pair(shape, deta, m=1.0, W0=10.0)
+    phi0 = uniform_field(shape, 3)
+    loss, gphi, gdphi, gw, _ = gpu_adjoint(gp, phi0, nsteps, K)
+    ref = O.adjoint(op, phi0.astype(np.float64).reshape(-1), np.zeros(phi0.size), nsteps,
+                    ckpt_every=K)
+    assert loss == pytest.approx(ref["loss"], rel=1e-5)
+    assert rel_l2(gphi, ref["grad_phi"]) <= 1e-4
+    assert rel_l2(gdphi, ref["grad_pi"]) <= 1e-4
+    assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
+
+
+def test_adjoint_checkpoint_interval_bitwise():
+    """Recomputation is bit-exact, so the gradient does not depend on K."""
+    say("adjoint K invariance")
+    shape = (200, 130)
+    gp, _ = params_pair(shape, 0.25, m=2.0, W0=5.0)
+    phi0 = uniform_field(shape, 4)
+    ref = gpu_adjoint(gp, phi0, 40, 1)
+    for K in (3, 16, 40, 64):
+        got = gpu_adjoint(gp, phi0, 40, K)
+        np.testing.assert_array_equal(got[1], ref[1])
+        np.testing.assert_array_equal(got[2], ref[2])
+        assert got[3] == ref[3] and got[0] == ref[0]
+
+
+def test_adjoint_backward_requires_forward():
+    prs = gpu_prs()
+    torch = torch_mod()
+    shape = (64, 64)
+    gp, _ = params_pair(shape, 0.25)
+    sim = prs.Sim(gp, seed=1)
+    nb = prs.prs_adjoint_workspace_bytes(gp, 8, 4)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    with pytest.raises(prs.PRSError) as e:
+        prs.prs_adjoint_backward(sim.ctx, work.data_ptr(), nb, None, None)
+    assert e.value.status == prs.PRS_ESTATE
+    with pytest.raises(prs.PRSError) as e:
+        prs.prs_adjoint_forward(sim.ctx, 8, 4, work.data_ptr(), nb - 256)
+    assert e.value.status == prs.PRS_ENOMEM
+
+
+def test_prsloss_autograd():
+    """PRSLoss routes loss.backward() through the hand-written adjoint."""
+    say("PRSLoss autograd")
+    torch = torch_mod()
+    prs = gpu_prs()
+    shape = (128, 96)
+    gp, op = params_pair(shape, 0.25, m=1.0, W0=8.0)
+    phi0_np = uniform_field(shape, 12)
+    phi0 = to_dev(phi0_np).requires_grad_(True)
+    W0 = torch.tensor(8.0, dtype=torch.float64, requires_grad=True)
+    loss = prs.PRSLoss.apply(phi0, W0, gp, 30, 8)
+    (2.0 * loss).backward()
+    ref = O.adjoint(op, phi0_np.astype(np.float64).reshape(-1), np.zeros(phi0_np.size), 30,
+                    ckpt_every=8)
+    assert float(loss) == pytest.approx(ref["loss"], rel=1e-5)
+    assert rel_l2(host(phi0.grad) / 2.0, ref["grad_phi"]) <= 1e-4
+    assert float(W0.grad) / 2.0 == pytest.approx(ref["grad_W0"], rel=1e-3)
+
+
+@pytest.mark.parametrize("shape,nsteps,K", [((2048, 2048), 64, 64), ((256, 256, 256), 16, 8)])
+def test_adjoint_full_size(shape, nsteps, K):
+    """The adjoint at the full lattice sizes (2048^2, 256^3) and the tiling
+    the benchmark uses, over runs the oracle finishes in seconds."""
+    say("adjoint full size", shape)
+    torch = torch_mod()
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp, op = params_pair(shape, deta, m=1.0, W0=10.0)
+    phi0 = uniform_field(shape, 7)
+    loss, gphi, gdphi, gw, sim = gpu_adjoint(gp, phi0, nsteps, K)
+    say("  tiling", sim.tiling())
+    O.set_threads(16)
+    ref = O.adjoint(op, phi0.astype(np.float64).reshape(-1), np.zeros(phi0.size), nsteps,
+                    ckpt_every=K)
+    assert loss == pytest.approx(ref["loss"], rel=1e-5)
+    assert rel_l2(gphi, ref["grad_phi"]) <= 1e-4
+    assert rel_l2(gdphi, ref["grad_pi"]) <= 1e-4
+    assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
+    del sim
+    torch.cuda.empty_cache()

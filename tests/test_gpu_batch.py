@@ -1,0 +1,104 @@
+"""Batched ensemble: every realisation inside the batch reproduces the same
+realisation run alone (fields, counts and records bit for bit with the same
+tiling), for uneven sizes, dimensions, eras and step counts, in every launch
+mode, and across graph replays."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1710_10420_amd.inputs import uniform_field
+from tests.gpu_util import assert_stats_match, gpu_prs, host, say, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    dict(shape=(256, 256), deta=0.25, m=0.5, W0=5.0, nsteps=50, diag_every=10, seed=1000),
+    dict(shape=(300, 70), deta=0.25, m=1.0, W0=10.0, nsteps=37, diag_every=8, seed=1001),
+    dict(shape=(512, 512), deta=0.25, m=2.0, W0=10.0, nsteps=80, diag_every=16, seed=1002),
+    dict(shape=(40, 30, 20), deta=0.2, m=1.0, W0=5.0, nsteps=23, diag_every=5, seed=1003),
+    dict(shape=(64, 64, 64), deta=0.2, m=0.5, W0=10.0, nsteps=31, diag_every=10, seed=1004),
+    dict(shape=(33, 17), deta=0.25, m=1.0, W0=5.0, nsteps=0, diag_every=4, seed=1005),
+    dict(shape=(128, 96), deta=0.25, m=1.0, W0=10.0, nsteps=1, diag_every=1, seed=1006),
+]
+
+TILINGS = [(4, 32, 1), (2, 17, 1), (4, 64, 1), (2, 16, 2), (4, 32, 1), (1, 16, 1), (4, 16, 1)]
+
+
+def single_run(prs, sp, tiling):
+    p = prs.make_params(sp["shape"], deta=sp["deta"], m=sp["m"], W0=sp["W0"],
+                        diag_every=sp["diag_every"])
+    sim = prs.Sim(p, seed=sp["seed"])
+    sim.set_tiling(*tiling)
+    recs = sim.step_n(sp["nsteps"])
+    recs.append(sim.wall_stats())
+    phi, dphi = sim.state()
+    return host(phi), host(dphi), recs
+
+
+@pytest.fixture(scope="module")
+def singles():
+    prs = gpu_prs()
+    out = []
+    for sp, t in zip(SPECS, TILINGS):
+        say("single", sp["shape"], sp["nsteps"])
+        out.append(single_run(prs, sp, t))
+    return out
+
+
+def make_batch(prs):
+    b = prs.Batch(SPECS)
+    for r, t in enumerate(TILINGS):
+        b.set_tiling(r, *t)
+    return b
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_equals_single_runs(singles, mode):
+    say("batch mode", mode)
+    prs = gpu_prs()
+    b = make_batch(prs)
+    b.set_mode(mode)
+    for rep in range(2):                 # the graph is replayed on the second run
+        recs = b.run()
+        for r, sp in enumerate(SPECS):
+            phi, dphi = b.final_state(r)
+            s_phi, s_dphi, s_recs = singles[r]
+            np.testing.assert_array_equal(host(phi), s_phi)
+            np.testing.assert_array_equal(host(dphi), s_dphi)
+            assert recs[r] == s_recs, (mode, rep, r)
+    b.close()
+
+
+def test_batch_records_match_oracle_on_final_state(singles):
+    """Final-state records of the ensemble equal the oracle diagnostics of
+    that state (counts bitwise)."""
+    say("batch vs oracle")
+    prs = gpu_prs()
+    b = make_batch(prs)
+    recs = b.run()
+    for r, sp in enumerate(SPECS):
+        phi, dphi = b.final_state(r)
+        op = O.params(sp["shape"], deta=sp["deta"], m=sp["m"], W0=sp["W0"])
+        o = O.stats(op, host(phi).astype(np.float64), host(dphi).astype(np.float64), sp["nsteps"])
+        assert_stats_match(recs[r][-1], o, ctx=str(sp["shape"]))
+    b.close()
+
+
+def test_batch_initial_fields_from_seeds():
+    prs = gpu_prs()
+    sp = dict(shape=(100, 60), deta=0.25, m=1.0, W0=10.0, nsteps=0, diag_every=1, seed=77)
+    b = prs.Batch([sp])
+    b.run()
+    phi, dphi = b.final_state(0)
+    np.testing.assert_array_equal(host(phi), uniform_field((100, 60), 77).reshape(-1))
+    assert float(host(dphi).max()) == 0.0 and float(host(dphi).min()) == 0.0
+    b.close()
+
+
+def test_batch_rejects_invalid_item():
+    prs = gpu_prs()
+    bad = dict(SPECS[0])
+    bad["deta"] = 2.0
+    with pytest.raises(prs.PRSError) as e:
+        prs.Batch([SPECS[1], bad])
+    assert e.value.status == prs.PRS_EINVAL and "item 1" in str(e.value)
