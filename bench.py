@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -81,12 +83,97 @@ def cpu_baseline(w, budget_s=20.0):
                       "(diagnostics every 64 included), %.1f s" % (steps, n_steps(w), dt)}
 
 
+ADJOINT = [
+    dict(name="2D 2048^2", shape=(2048, 2048), deta=0.25),
+    dict(name="3D 256^3", shape=(256, 256, 256), deta=0.2),
+]
+ADJ_STEPS, ADJ_K = 1024, 64
+
+
+def adjoint_leg(prs, torch, reps=3):
+    """Checkpointed adjoint of 1024 steps (m = 1, W0 = 10), loss = sum V/V0
+    of the final field: forward-with-checkpoints and reverse sweep timed
+    separately with stream events."""
+    out = {"workload": "adjoint, 1024 steps from seed 7, m=1, W0=10, checkpoints every 64, "
+                       "loss = sum V(phi)/V0; grad w.r.t. phi0 and W0",
+           "bytes_per_site_update": {"forward": 16, "reverse": 36}}
+    stream = torch.cuda.current_stream()
+    for cfg in ADJOINT:
+        p = prs.make_params(cfg["shape"], deta=cfg["deta"], m=1.0, W0=10.0)
+        sites = prs.sites(p)
+        nb = prs.prs_adjoint_workspace_bytes(p, ADJ_STEPS, ADJ_K)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        gphi = torch.empty(sites, dtype=torch.float32, device="cuda")
+        sim = prs.Sim(p, seed=7)
+        phi0 = sim.phi_a.clone()
+        fwd, bwd = [], []
+        for r in range(reps + 1):
+            sim.set_state(phi0, torch.zeros_like(phi0), 0)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            loss = prs.prs_adjoint_forward(sim.ctx, ADJ_STEPS, ADJ_K, work.data_ptr(), nb)
+            e1.record(stream)
+            gw = prs.prs_adjoint_backward(sim.ctx, work.data_ptr(), nb, gphi.data_ptr(), None)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                fwd.append(e0.elapsed_time(e1))
+                bwd.append(e1.elapsed_time(e2))
+        tf, tb = min(fwd), min(bwd)
+        su = float(sites) * ADJ_STEPS
+        out[cfg["name"]] = {
+            "forward_ms": tf, "backward_ms": tb, "backward_over_forward": tb / tf,
+            "total_over_forward": (tf + tb) / tf,
+            "forward_site_updates_per_s": su / (tf / 1e3),
+            "adjoint_site_updates_per_s": su / (tb / 1e3),
+            "forward_hbm_frac": su * 16 / (tf / 1e3) / (HBM_PEAK_GBS * 1e9),
+            "reverse_hbm_frac": su * 36 / (tb / 1e3) / (HBM_PEAK_GBS * 1e9),
+            "loss": loss, "grad_W0": gw, "tiling": list(sim.tiling()),
+        }
+        log("adjoint", cfg["name"], "fwd %.2f ms bwd %.2f ms" % (tf, tb))
+        sim.close()
+        del work, gphi, sim, phi0
+        torch.cuda.empty_cache()
+    return out
+
+
+def batch_leg(prs, torch, reps=2):
+    """The seeded ensemble: 48 2D realisations (512^2/1024^2/2048^2) and 16 3D
+    (128^3/256^3), m in {0.5,1,2}, W0 in {5,10}, each to eta = N/2, run as one
+    persistent launch replayed from a hipGraph."""
+    from paper_1710_10420_amd.inputs import ensemble_draw
+    items = ensemble_draw(2017)
+    specs = [dict(shape=(it["N"],) * it["ndim"], deta=it["deta"], m=it["m"], W0=it["W0"],
+                  nsteps=it["steps"], diag_every=64 if it["ndim"] == 2 else 50, seed=it["seed"])
+             for it in items]
+    b = prs.Batch(specs)
+    su = float(sum(int(np.prod(sp["shape"])) * sp["nsteps"] for sp in specs))
+    b.run()                                   # builds and instantiates the graph
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        recs = b.run()
+        times.append(time.perf_counter() - t0)
+    t = min(times)
+    out = {"workload": "ensemble of 64 realisations (master seed 2017): 48 2D from "
+                       "{512^2,1024^2,2048^2}, 16 3D from {128^3,256^3}, m in {0.5,1,2}, "
+                       "W0 in {5,10}, each to eta = N/2, diagnostics every 64 (2D) / 50 (3D)",
+           "realisations": len(specs), "site_updates": su, "ms_per_run": t * 1e3,
+           "site_updates_per_s": su / t, "hbm_frac": su * 16 / t / (HBM_PEAK_GBS * 1e9),
+           "records": sum(len(r) for r in recs), "mode": "persistent+hipGraph"}
+    log("batch %.1f ms" % (t * 1e3))
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and ensemble legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the PRS path is built and timed on a single "
@@ -159,6 +246,12 @@ def main():
         "result": {"mu": mu, "nu": nu, "final_links": recs[-1]["links"],
                    "final_area_density": recs[-1]["area_density"]},
     }
+    if not args.no_extra:
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_leg(prs, torch)
+        out["batch"] = batch_leg(prs, torch)
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -139,6 +139,23 @@ prs_status prs_set_state(prs_ctx* ctx, const void* phi, const void* dphi, int64_
 prs_status prs_set_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
 prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
 
+/* Autotuner.  Times every supported tiling for this lattice on the
+ * context's own state (saved before and restored after each candidate; the
+ * library allocates two temporary fields with hipMalloc for that), applies the
+ * fastest to the context and records it in the JSON file cache_path (created
+ * or updated; NULL or "" for no cache).  A cached entry for the same GPU
+ * architecture, dimension, lattice size and tiling set is applied without
+ * timing unless flags has PRS_TUNE_FORCE.  PRS_TUNE_BATCH restricts the
+ * candidates to the tilings batched runs support.  *best_us (may be NULL)
+ * receives the time of one step with the chosen tiling.  Synchronises. */
+#define PRS_TUNE_FORCE 1
+#define PRS_TUNE_BATCH 2
+prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, double* best_us);
+
+/* Cached tiling for these parameters (no GPU work); PRS_ESTATE if absent. */
+prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t flags, int32_t* vec,
+                            int32_t* rows, int32_t* ty);
+
 /* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
 void prs_destroy(prs_ctx* ctx);
 
@@ -221,8 +238,7 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
  * offsets has count+1 entries. */
 prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
 
-/* Tiling of one item (vec, rows, ty as in prs_set_tiling; in 3D ty = 2 only
- * with vec <= 2). */
+/* Tiling of one item (vec and rows as in prs_set_tiling; ty must be 1). */
 prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
 prs_status prs_batch_set_mode(prs_batch* b, int32_t mode);
 

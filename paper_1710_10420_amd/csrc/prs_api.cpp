@@ -9,8 +9,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "prs.h"
@@ -44,7 +47,7 @@ prs_status hip_fail(hipError_t e, const char* what)
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kRecCap = 1024;   // device records buffered before a flush
-constexpr int64_t kMinRows = 16;    // smallest marching tile the workspace allows
+constexpr int64_t kMinRows = 8;     // smallest marching tile the workspace allows
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -68,8 +71,8 @@ prs_status validate(const prs_params* p)
     double sites = 1.0;
     for (int d = 0; d < p->ndim; ++d) sites *= (double)p->n[d];
     if (sites > lim) return fail(PRS_EINVAL, "lattice too large (%.3g sites)", sites);
-    if (p->ndim == 3 && (double)p->n[0] * (double)p->n[1] > 2147483647.0)
-        return fail(PRS_EINVAL, "3D plane nx*ny exceeds 2^31");
+    if ((double)p->n[0] * (double)(p->ndim == 3 ? p->n[1] : 1) > 2147483647.0)
+        return fail(PRS_EINVAL, "a lattice plane (nx in 2D, nx*ny in 3D) must hold fewer than 2^31 sites");
     if (!(p->dx > 0) || !std::isfinite(p->dx)) return fail(PRS_EINVAL, "dx must be finite and > 0");
     if (!(p->deta > 0) || !std::isfinite(p->deta)) return fail(PRS_EINVAL, "deta must be finite and > 0");
     if (!(p->eta0 > 0) || !std::isfinite(p->eta0)) return fail(PRS_EINVAL, "eta0 must be finite and > 0");
@@ -613,6 +616,9 @@ struct prs_batch {
     bool dirty;          // descriptors need uploading / graph rebuilding
     hipGraph_t graph;
     hipGraphExec_t exec;
+    hipStream_t capture;  // private stream the graph is captured on (the
+                          // caller's stream may be the legacy NULL stream,
+                          // which cannot be captured)
 };
 
 namespace {
@@ -712,33 +718,33 @@ prs_status batch_upload(prs_batch* b)
 // The whole ensemble as a sequence on the stream: initial fields, then the
 // steps (one persistent launch, or one launch pair per step), then the
 // records and the error flag to pinned host memory.
-prs_status batch_enqueue(prs_batch* b, bool persistent)
+prs_status batch_enqueue(prs_batch* b, bool persistent, hipStream_t stream)
 {
     char* base = static_cast<char*>(b->ws);
     for (int32_t r = 0; r < b->count; ++r) {
         const prs_batch_item& it = b->items[r];
         if (!it.init_from_seed) continue;
         const int64_t n = sites_of(it.p);
-        HIP_TRY(launch_fill_uniform(static_cast<float*>(it.phi_a), n, it.seed, b->stream), "fill launch");
-        HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), n, b->stream), "zero launch");
+        HIP_TRY(launch_fill_uniform(static_cast<float*>(it.phi_a), n, it.seed, stream), "fill launch");
+        HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), n, stream), "zero launch");
     }
     void* ctl = base + b->off_ctl;
-    HIP_TRY(launch_batch_reset(ctl, b->stream), "reset launch");
+    HIP_TRY(launch_batch_reset(ctl, stream), "reset launch");
     const void* desc = base + b->off_desc;
     if (persistent) {
         int blocks = (int)std::min<int64_t>(b->grid_blocks, (b->total_tiles + 3) / 4);
         if (blocks < 1) blocks = 1;
         HIP_TRY(launch_batch_persistent(desc, b->count, b->total_tiles, b->tmax, ctl, b->timeout_ticks, blocks,
-                                        b->stream),
+                                        stream),
                 "persistent launch");
     } else {
         for (int64_t t = 0; t <= b->tmax; ++t)
-            HIP_TRY(launch_batch_step(desc, b->count, b->total_tiles, t, b->stream), "batch step launch");
+            HIP_TRY(launch_batch_step(desc, b->count, b->total_tiles, t, stream), "batch step launch");
     }
     HIP_TRY(hipMemcpyAsync(b->hrec, base + b->off_rec, (size_t)b->total_recs * sizeof(prs_stats),
-                           hipMemcpyDeviceToHost, b->stream), "record copy");
+                           hipMemcpyDeviceToHost, stream), "record copy");
     HIP_TRY(hipMemcpyAsync(b->herr, static_cast<char*>(ctl) + 2 * sizeof(unsigned), sizeof(int),
-                           hipMemcpyDeviceToHost, b->stream), "flag copy");
+                           hipMemcpyDeviceToHost, stream), "flag copy");
     return PRS_OK;
 }
 
@@ -858,10 +864,12 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     *b->herr = 0;
     if (b->mode == PRS_BATCH_PERSISTENT_GRAPH) {
         if (!b->exec) {
-            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "graph capture");
-            prs_status st = batch_enqueue(b, true);
+            if (!b->capture)
+                HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+            HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "graph capture");
+            prs_status st = batch_enqueue(b, true, b->capture);
             hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            hipError_t e = hipStreamEndCapture(b->capture, &g);
             if (st != PRS_OK) {
                 if (g) (void)hipGraphDestroy(g);
                 return st;
@@ -876,7 +884,7 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
         }
         HIP_TRY(hipGraphLaunch(b->exec, b->stream), "graph launch");
     } else {
-        prs_status st = batch_enqueue(b, b->mode == PRS_BATCH_PERSISTENT);
+        prs_status st = batch_enqueue(b, b->mode == PRS_BATCH_PERSISTENT, b->stream);
         if (st != PRS_OK) return st;
     }
     HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
@@ -890,9 +898,207 @@ void prs_batch_destroy(prs_batch* b)
 {
     if (!b) return;
     batch_release_graph(b);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->hrec) (void)hipHostFree(b->hrec);
     if (b->herr) (void)hipHostFree(b->herr);
     delete b;
+}
+
+}  // extern "C"
+
+
+// -------------------------------------------------------------- autotuner --
+//
+// Candidate tilings are timed on the context's own state (saved and restored
+// around every candidate, so the run is unchanged), and the fastest is kept
+// and written to a small JSON cache keyed by GPU architecture, dimension,
+// lattice size and tiling set.  The paper notes that a new card needs the
+// code re-optimised (Sec. IV); this does it per lattice shape.
+
+namespace {
+
+constexpr const char* kTuneVersion = "k1";
+
+std::string tune_key(const prs_params& p, bool batch_set)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|%dD|%lldx%lldx%lld|%s|%s", arch.c_str(), p.ndim,
+                  (long long)p.n[0], (long long)p.n[1], (long long)(p.ndim == 3 ? p.n[2] : 1),
+                  batch_set ? "batch" : "single", kTuneVersion);
+    return buf;
+}
+
+struct TuneEntry {
+    int vec, rows, ty;
+    double us;
+};
+
+// The cache is written by tune_write only: one entry per line,
+//   "key": {"vec": V, "rows": R, "ty": T, "us": U},
+std::map<std::string, TuneEntry> tune_read(const char* path)
+{
+    std::map<std::string, TuneEntry> m;
+    FILE* f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return m;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        const char* q1 = std::strchr(line, '"');
+        if (!q1) continue;
+        const char* q2 = std::strchr(q1 + 1, '"');
+        if (!q2) continue;
+        TuneEntry e;
+        if (std::sscanf(q2 + 1, ": {\"vec\": %d, \"rows\": %d, \"ty\": %d, \"us\": %lf", &e.vec, &e.rows,
+                        &e.ty, &e.us) == 4)
+            m[std::string(q1 + 1, q2)] = e;
+    }
+    std::fclose(f);
+    return m;
+}
+
+bool tune_write(const char* path, const std::map<std::string, TuneEntry>& m)
+{
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m) {
+        std::fprintf(f, "\"%s\": {\"vec\": %d, \"rows\": %d, \"ty\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
+                     kv.second.vec, kv.second.rows, kv.second.ty, kv.second.us, ++i < m.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+std::vector<Tiling> tune_candidates(const Geometry& g, bool batch_set)
+{
+    std::vector<Tiling> out;
+    for (int vec : {1, 2, 4})
+        for (int rows : {8, 16, 32, 64, 128})
+            for (int ty : {1, 2, 4}) {
+                Tiling t{vec, rows, ty};
+                if (rows < kMinRows && rows < g.M) continue;
+                if (!tiling_supported(g, t)) continue;
+                if (batch_set && !batch_tiling_supported(g, t)) continue;
+                out.push_back(t);
+            }
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t flags, int32_t* vec,
+                            int32_t* rows, int32_t* ty)
+{
+    prs_status st = validate(p);
+    if (st != PRS_OK) return st;
+    const auto m = tune_read(cache_path);
+    const auto it = m.find(tune_key(*p, (flags & PRS_TUNE_BATCH) != 0));
+    if (it == m.end()) return fail(PRS_ESTATE, "no cached tiling for this lattice");
+    if (vec) *vec = it->second.vec;
+    if (rows) *rows = it->second.rows;
+    if (ty) *ty = it->second.ty;
+    return PRS_OK;
+}
+
+prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, double* best_us)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    const bool batch_set = (flags & PRS_TUNE_BATCH) != 0;
+    const std::string key = tune_key(c->p, batch_set);
+    auto cache = tune_read(cache_path);
+    if (!(flags & PRS_TUNE_FORCE)) {
+        const auto it = cache.find(key);
+        if (it != cache.end()) {
+            prs_status st = prs_set_tiling(c, it->second.vec, it->second.rows, it->second.ty);
+            if (st == PRS_OK) {
+                if (best_us) *best_us = it->second.us;
+                return PRS_OK;
+            }
+        }
+    }
+    const std::vector<Tiling> cand = tune_candidates(c->geo, batch_set);
+    if (cand.empty()) return fail(PRS_EUNSUPPORTED, "no tiling candidates");
+    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    float *save_phi = nullptr, *save_pi = nullptr;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&save_phi), bytes), "tuner allocation");
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&save_pi), bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(save_phi);
+        return hip_fail(e, "tuner allocation");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const double sites = (double)sites_of(c->p);
+    const int timed = (int)std::max(4.0, std::min(40.0, 4e9 / std::max(sites, 1.0)));
+    const int64_t n0 = c->step;
+    const int cur0 = c->cur;
+    const char* env = std::getenv("PRS_TUNE_LOG");
+    const bool log_each = env && env[0] == '1';
+    Tiling best = c->til;
+    double best_t = 1e300;
+    prs_status result = PRS_OK;
+    auto run = [&](const Tiling& t, int steps) -> hipError_t {
+        for (int k = 0; k < steps; ++k) {
+            hipError_t err = launch_step(c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi,
+                                         coef_for(c, n0 + k), true, false, nullptr, DiagCoef{}, c->stream);
+            if (err != hipSuccess) return err;
+            c->cur ^= 1;
+        }
+        return hipSuccess;
+    };
+    e = hipMemcpyAsync(save_phi, c->phi[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(save_pi, c->pi, bytes, hipMemcpyDeviceToDevice, c->stream);
+    for (const Tiling& t : cand) {
+        if (e != hipSuccess) break;
+        if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
+        e = run(t, 2);
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = run(t, timed);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && log_each)
+            std::fprintf(stderr, "prs_autotune: vec=%d rows=%d ty=%d %.2f us/step\n", t.vec, t.rows, t.ty,
+                         ms / timed * 1e3);
+        if (e == hipSuccess && ms / timed < best_t) {
+            best_t = ms / timed;
+            best = t;
+        }
+        // restore the state for the next candidate (and for the caller)
+        c->cur = cur0;
+        if (e == hipSuccess) e = hipMemcpyAsync(c->phi[cur0], save_phi, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->pi, save_pi, bytes, hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) result = hip_fail(e, "autotune");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(save_phi);
+    (void)hipFree(save_pi);
+    c->cur = cur0;
+    c->step = n0;
+    if (result != PRS_OK) return result;
+    c->til = best;
+    if (best_us) *best_us = best_t * 1e3;
+    if (cache_path && cache_path[0]) {
+        cache[key] = TuneEntry{best.vec, best.rows, best.ty, best_t * 1e3};
+        if (!tune_write(cache_path, cache)) return fail(PRS_EINVAL, "cannot write tuning cache %s", cache_path);
+    }
+    return PRS_OK;
 }
 
 }  // extern "C"

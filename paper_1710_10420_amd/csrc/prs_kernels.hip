@@ -58,6 +58,22 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
+// Index of this wave within its workgroup, as a wave-uniform (scalar) value:
+// the compiler cannot prove threadIdx.x / 64 uniform on its own, and every
+// address derived from it would otherwise be computed per lane.
+__device__ __forceinline__ int wave_in_block()
+{
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
+// Makes a wave-uniform 64-bit value visibly uniform to the compiler.
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int64_t wrap(int64_t v, int64_t n)
 {
     v %= n;
@@ -191,181 +207,268 @@ struct StepArgs {
     DiagCoef dc;
 };
 
+// One plane of a wave's tile: TY rows of VEC sites per lane, the two x-halo
+// scalars (used by lane 0 / the last active lane) and, in 3D, the rows just
+// above and below the tile.
 template <int VEC, int TY>
 struct Plane {
     float v[TY][VEC];
-    float hl[TY];   // x-halo left of lane 0
-    float hr[TY];   // x-halo right of the last lane
+    float hl[TY];
+    float hr[TY];
+    float lo[VEC];
+    float hi[VEC];
 };
 
-template <int VEC>
-struct Halo {
-    float lo[VEC];  // row q0-1 (3D)
-    float hi[VEC];  // row q0+nvalid (3D)
-};
-
-struct LaneGeom {
-    int64_t x0, xl, xr;
+// Everything a wave needs to walk its tile, computed once.  In-plane offsets
+// are unsigned 32-bit (a plane holds fewer than 2^31 sites), plane bases are
+// wave-uniform 64-bit pointers, so the march needs no division and loads use
+// the scalar-base + vector-offset form.
+template <int TY>
+struct TileSetup {
+    uint32_t x0, xl, xr;     // this lane's first site and its x-halo sites
     bool active, need_left, need_right;
+    uint32_t off[TY];        // (q0 + t) * nx + x0
+    uint32_t offl[TY];       // (q0 + t) * nx + xl
+    uint32_t offr[TY];       // (q0 + t) * nx + xr
+    uint32_t lo, hi;         // rows above / below the tile (3D), + x0
+    int nvalid;              // rows of the tile inside the lattice
+    int64_t s0, s1;          // marching range
+    int64_t M, pstride;
 };
 
-template <int D, int VEC, int TY>
-__device__ __forceinline__ void load_plane(const float* __restrict__ phi, int64_t s,
-                                           const StepArgs& A, const LaneGeom& g, int64_t q0,
-                                           int nvalid, Plane<VEC, TY>& P, Halo<VEC>& H)
+// Plane index wrapped into [0, M) for v in [-1, 2M]: no division.
+__device__ __forceinline__ int64_t wrap_plane(int64_t v, int64_t M)
 {
-    const int64_t sw = wrap(s, A.M);
-    const float* base = phi + sw * (A.nx * A.Q);
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        if (t < nvalid) {
-            const float* row = base + (q0 + t) * A.nx;
-            if (g.active) load_vec<VEC>(row + g.x0, P.v[t]);
-            if (g.need_left) P.hl[t] = row[g.xl];
-            if (g.need_right) P.hr[t] = row[g.xr];
-        }
-    }
-    if constexpr (D == 3) {
-        if (g.active) {
-            load_vec<VEC>(base + wrap(q0 - 1, A.Q) * A.nx + g.x0, H.lo);
-            load_vec<VEC>(base + wrap(q0 + nvalid, A.Q) * A.nx + g.x0, H.hi);
-        }
-    }
+    if (v < 0) v += M;
+    if (v >= M) v -= M;
+    if (v >= M) v -= M;
+    return v;
 }
 
 template <int VEC, int TY>
-__device__ __forceinline__ void load_pi(const float* pi, int64_t s, const StepArgs& A,
-                                        const LaneGeom& g, int64_t q0, int nvalid,
-                                        float (&v)[TY][VEC])
+__device__ __forceinline__ TileSetup<TY> tile_setup(int64_t nx64, int64_t Q64, int64_t M,
+                                                    int64_t tiles_x, int64_t tiles_q, int64_t rows,
+                                                    int64_t tile)
 {
-    const float* base = pi + s * (A.nx * A.Q);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t tq = tl % (uint32_t)tiles_q;
+    const uint32_t rest = tl / (uint32_t)tiles_q;
+    const uint32_t tx = rest % (uint32_t)tiles_x;
+    const uint32_t ts = rest / (uint32_t)tiles_x;
+    const uint32_t nx = (uint32_t)nx64, Q = (uint32_t)Q64;
+    TileSetup<TY> S;
+    S.x0 = tx * (kWave * VEC) + lane * VEC;
+    S.active = S.x0 < nx;
+    S.need_left = S.active && lane == 0;
+    S.need_right = S.active && (lane == kWave - 1 || S.x0 + VEC >= nx);
+    S.xl = S.x0 == 0 ? nx - 1 : S.x0 - 1;
+    S.xr = S.x0 + VEC >= nx ? 0 : S.x0 + VEC;
+    const uint32_t q0 = tq * TY;
+    S.nvalid = (int)((Q - q0) < (uint32_t)TY ? (Q - q0) : (uint32_t)TY);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+        const uint32_t r = (q0 + t) * nx;
+        S.off[t] = r + S.x0;
+        S.offl[t] = r + S.xl;
+        S.offr[t] = r + S.xr;
+    }
+    uint32_t lo = q0 == 0 ? Q - 1 : q0 - 1;
+    uint32_t hi = q0 + (uint32_t)S.nvalid;
+    while (hi >= Q) hi -= Q;          // Q >= 1; a few iterations at most when Q < TY
+    S.lo = lo * nx + S.x0;
+    S.hi = hi * nx + S.x0;
+    S.s0 = (int64_t)ts * rows;
+    S.s1 = (S.s0 + rows) < M ? (S.s0 + rows) : M;
+    S.M = M;
+    S.pstride = nx64 * Q64;
+    return S;
+}
+
+template <int D, int VEC, int TY>
+__device__ __forceinline__ void load_plane(const float* __restrict__ f, int64_t s,
+                                           const TileSetup<TY>& S, Plane<VEC, TY>& P)
+{
+    const float* base = f + wrap_plane(s, S.M) * S.pstride;
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+        if (t < S.nvalid) {
+            if (S.active) load_vec<VEC>(base + S.off[t], P.v[t]);
+            if (S.need_left) P.hl[t] = base[S.offl[t]];
+            if (S.need_right) P.hr[t] = base[S.offr[t]];
+        }
+    }
+    if constexpr (D == 3) {
+        if (S.active) {
+            load_vec<VEC>(base + S.lo, P.lo);
+            load_vec<VEC>(base + S.hi, P.hi);
+        }
+    }
+}
+
+// A plane that is only needed for its values along the marching axis (s-1):
+// no x-halo scalars, no y-halo rows.
+template <int VEC, int TY>
+__device__ __forceinline__ void load_plane_values(const float* __restrict__ f, int64_t s,
+                                                  const TileSetup<TY>& S, Plane<VEC, TY>& P)
+{
+    const float* base = f + wrap_plane(s, S.M) * S.pstride;
 #pragma unroll
     for (int t = 0; t < TY; ++t)
-        if (t < nvalid && g.active) load_vec<VEC>(base + (q0 + t) * A.nx + g.x0, v[t]);
+        if (t < S.nvalid && S.active) load_vec<VEC>(base + S.off[t], P.v[t]);
+}
+
+// Point-wise field values of plane s (s inside the lattice) for every row.
+template <int VEC, int TY>
+__device__ __forceinline__ void load_point(const float* __restrict__ f, int64_t s,
+                                           const TileSetup<TY>& S, float (&v)[TY][VEC])
+{
+    const float* base = f + s * S.pstride;
+#pragma unroll
+    for (int t = 0; t < TY; ++t)
+        if (t < S.nvalid && S.active) load_vec<VEC>(base + S.off[t], v[t]);
+}
+
+template <int VEC, int TY>
+__device__ __forceinline__ void zero_plane(Plane<VEC, TY>& P)
+{
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) P.v[t][j] = 0.0f;
+        P.hl[t] = P.hr[t] = 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) P.lo[j] = P.hi[j] = 0.0f;
+}
+
+template <int VEC, int TY>
+__device__ __forceinline__ void zero_rows(float (&v)[TY][VEC])
+{
+#pragma unroll
+    for (int t = 0; t < TY; ++t)
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) v[t][j] = 0.0f;
+}
+
+// x-neighbours of the first and last site of each row of the current plane.
+template <int VEC, int TY>
+__device__ __forceinline__ void x_neighbours(const Plane<VEC, TY>& P, const TileSetup<TY>& S,
+                                             float (&left)[TY], float (&right)[TY])
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+        left[t] = __shfl_up(P.v[t][VEC - 1], 1, kWave);
+        right[t] = __shfl_down(P.v[t][0], 1, kWave);
+        if (lane == 0) left[t] = P.hl[t];
+        if (S.need_right) right[t] = P.hr[t];
+    }
+}
+
+// The 2D neighbours (minus, plus) of site j of row t of the current plane.
+template <int D, int VEC, int TY>
+__device__ __forceinline__ void neighbours(const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
+                                           const Plane<VEC, TY>& Pn, const float (&left)[TY],
+                                           const float (&right)[TY], int nvalid, int t, int j,
+                                           float (&nm)[D], float (&np)[D])
+{
+    nm[0] = j > 0 ? Pc.v[t][j > 0 ? j - 1 : 0] : left[t];
+    np[0] = j < VEC - 1 ? Pc.v[t][j < VEC - 1 ? j + 1 : j] : right[t];
+    if constexpr (D == 3) {
+        nm[1] = t > 0 ? Pc.v[t > 0 ? t - 1 : 0][j] : Pc.lo[j];
+        np[1] = (t + 1 < nvalid) ? Pc.v[t + 1 < TY ? t + 1 : t][j] : Pc.hi[j];
+        nm[2] = Pm.v[t][j];
+        np[2] = Pn.v[t][j];
+    } else {
+        nm[1] = Pm.v[t][j];
+        np[1] = Pn.v[t][j];
+    }
+}
+
+// Plane s of a forward tile: prefetch plane s+2 (and phi_dot of s+1), then
+// update plane s from (Pm, Pc, Pn) = planes (s-1, s, s+1).
+template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
+__device__ __forceinline__ void step_plane(const StepArgs& A, const TileSetup<TY>& S, int64_t s,
+                                           const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
+                                           const Plane<VEC, TY>& Pn, Plane<VEC, TY>& Pnn,
+                                           const float (&pic)[TY][VEC], float (&pin)[TY][VEC],
+                                           DiagAcc& acc)
+{
+    if (s + 1 < S.s1) {
+        load_plane<D, VEC, TY>(A.phi_in, s + 2, S, Pnn);
+        load_point<VEC, TY>(A.pi, s + 1, S, pin);
+    }
+    float left[TY], right[TY];
+    x_neighbours<VEC, TY>(Pc, S, left, right);
+    float* phi_out = A.phi_out + s * S.pstride;
+    float* pi_out = A.pi + s * S.pstride;
+#pragma unroll
+    for (int t = 0; t < TY; ++t) {
+        if (t >= S.nvalid) continue;
+        float out_phi[VEC], out_pi[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = Pc.v[t][j];
+            float nm[D], np[D];
+            neighbours<D, VEC, TY>(Pm, Pc, Pn, left, right, S.nvalid, t, j, nm, np);
+            if constexpr (UPDATE) {
+                float lap;
+                if constexpr (D == 3)
+                    lap = lap3(c, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.k.inv_dx2);
+                else
+                    lap = lap2(c, nm[0], np[0], nm[1], np[1], A.k.inv_dx2);
+                kick_drift(c, lap, pic[t][j], A.k, out_pi[j], out_phi[j]);
+            }
+            if constexpr (DIAG) {
+                if (S.active) site_diag<D>(c, pic[t][j], nm, np, A.dc, acc);
+            }
+        }
+        if constexpr (UPDATE) {
+            if (S.active) {
+                store_vec<VEC>(phi_out + S.off[t], out_phi);
+                store_vec<VEC>(pi_out + S.off[t], out_pi);
+            }
+        }
+    }
 }
 
 // One wave's tile of one step (see the file header).  `tile` must be below
-// A.ntiles and uniform across the wave.
+// A.ntiles and uniform across the wave.  The march is unrolled by four over a
+// ring of four plane buffers, so no plane is ever copied between registers.
 template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
 __device__ __forceinline__ void step_tile(const StepArgs& A, int64_t tile)
 {
     static_assert(D == 3 || TY == 1, "2D tiles have one row");
     const int lane = threadIdx.x & (kWave - 1);
+    const TileSetup<TY> S = tile_setup<VEC, TY>(A.nx, A.Q, A.M, A.tiles_x, A.tiles_q, A.rows, tile);
 
-    const int64_t tq = tile % A.tiles_q;
-    const int64_t rest = tile / A.tiles_q;
-    const int64_t tx = rest % A.tiles_x;
-    const int64_t ts = rest / A.tiles_x;
-
-    LaneGeom g;
-    g.x0 = tx * (kWave * VEC) + (int64_t)lane * VEC;
-    g.active = g.x0 < A.nx;
-    g.need_left = g.active && lane == 0;
-    g.need_right = g.active && (lane == kWave - 1 || g.x0 + VEC >= A.nx);
-    g.xl = g.x0 == 0 ? A.nx - 1 : g.x0 - 1;
-    g.xr = g.x0 + VEC >= A.nx ? 0 : g.x0 + VEC;
-
-    const int64_t q0 = tq * TY;
-    const int nvalid = (int)((A.Q - q0) < TY ? (A.Q - q0) : TY);
-    const int64_t s0 = ts * A.rows;
-    const int64_t s1 = (s0 + A.rows) < A.M ? (s0 + A.rows) : A.M;
-    const int64_t pstride = A.nx * A.Q;
-
-    Plane<VEC, TY> Pm, Pc, Pn, Pnn;
-    Halo<VEC> Hc, Hn, Hnn, Hdummy;
-    float pic[TY][VEC], pin[TY][VEC];
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            Pm.v[t][j] = Pc.v[t][j] = Pn.v[t][j] = Pnn.v[t][j] = 0.0f;
-            pic[t][j] = pin[t][j] = 0.0f;
-        }
-        Pc.hl[t] = Pc.hr[t] = Pn.hl[t] = Pn.hr[t] = Pnn.hl[t] = Pnn.hr[t] = 0.0f;
-        Pm.hl[t] = Pm.hr[t] = 0.0f;
-    }
-#pragma unroll
-    for (int j = 0; j < VEC; ++j)
-        Hc.lo[j] = Hc.hi[j] = Hn.lo[j] = Hn.hi[j] = Hnn.lo[j] = Hnn.hi[j] = 0.0f;
-
-    load_plane<D, VEC, TY>(A.phi_in, s0 - 1, A, g, q0, nvalid, Pm, Hdummy);
-    load_plane<D, VEC, TY>(A.phi_in, s0, A, g, q0, nvalid, Pc, Hc);
-    load_plane<D, VEC, TY>(A.phi_in, s0 + 1, A, g, q0, nvalid, Pn, Hn);
-    load_pi<VEC, TY>(A.pi, s0, A, g, q0, nvalid, pic);
+    Plane<VEC, TY> P0, P1, P2, P3;
+    float pi0[TY][VEC], pi1[TY][VEC];
+    zero_plane(P0);
+    zero_plane(P1);
+    zero_plane(P2);
+    zero_plane(P3);
+    zero_rows<VEC, TY>(pi0);
+    zero_rows<VEC, TY>(pi1);
+    load_plane_values<VEC, TY>(A.phi_in, S.s0 - 1, S, P0);
+    load_plane<D, VEC, TY>(A.phi_in, S.s0, S, P1);
+    load_plane<D, VEC, TY>(A.phi_in, S.s0 + 1, S, P2);
+    load_point<VEC, TY>(A.pi, S.s0, S, pi0);
 
     DiagAcc acc;
-    if constexpr (DIAG) {
-        acc.links[0] = acc.links[1] = acc.links[2] = 0u;
-        acc.walls = acc.nonfinite = 0u;
-        acc.area = acc.ek = 0.0;
-    }
+    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
+    acc.walls = acc.nonfinite = 0u;
+    acc.area = acc.ek = 0.0;
 
-    for (int64_t s = s0; s < s1; ++s) {
-        if (s + 1 < s1) {
-            load_plane<D, VEC, TY>(A.phi_in, s + 2, A, g, q0, nvalid, Pnn, Hnn);
-            load_pi<VEC, TY>(A.pi, s + 1, A, g, q0, nvalid, pin);
-        }
-
-        float left[TY], right[TY];
-#pragma unroll
-        for (int t = 0; t < TY; ++t) {
-            left[t] = __shfl_up(Pc.v[t][VEC - 1], 1, kWave);
-            right[t] = __shfl_down(Pc.v[t][0], 1, kWave);
-            if (lane == 0) left[t] = Pc.hl[t];
-            if (g.need_right) right[t] = Pc.hr[t];
-        }
-
-#pragma unroll
-        for (int t = 0; t < TY; ++t) {
-            if (t >= nvalid) continue;
-            float out_phi[VEC], out_pi[VEC];
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                const float c = Pc.v[t][j];
-                const float xm = j > 0 ? Pc.v[t][j - 1] : left[t];
-                const float xp = j < VEC - 1 ? Pc.v[t][j + 1] : right[t];
-                float nm[D], np[D];
-                nm[0] = xm;
-                np[0] = xp;
-                if constexpr (D == 3) {
-                    nm[1] = t > 0 ? Pc.v[t > 0 ? t - 1 : 0][j] : Hc.lo[j];
-                    np[1] = (t + 1 < nvalid) ? Pc.v[t + 1 < TY ? t + 1 : t][j] : Hc.hi[j];
-                    nm[2] = Pm.v[t][j];
-                    np[2] = Pn.v[t][j];
-                } else {
-                    nm[1] = Pm.v[t][j];
-                    np[1] = Pn.v[t][j];
-                }
-                if constexpr (UPDATE) {
-                    float lap;
-                    if constexpr (D == 3)
-                        lap = lap3(c, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.k.inv_dx2);
-                    else
-                        lap = lap2(c, nm[0], np[0], nm[1], np[1], A.k.inv_dx2);
-                    kick_drift(c, lap, pic[t][j], A.k, out_pi[j], out_phi[j]);
-                }
-                if constexpr (DIAG) {
-                    if (g.active) site_diag<D>(c, pic[t][j], nm, np, A.dc, acc);
-                }
-            }
-            if constexpr (UPDATE) {
-                if (g.active) {
-                    const int64_t off = s * pstride + (q0 + t) * A.nx + g.x0;
-                    store_vec<VEC>(A.phi_out + off, out_phi);
-                    store_vec<VEC>(A.pi + off, out_pi);
-                }
-            }
-        }
-
-        Pm = Pc;
-        Pc = Pn;
-        Pn = Pnn;
-        Hc = Hn;
-        Hn = Hnn;
-#pragma unroll
-        for (int t = 0; t < TY; ++t)
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) pic[t][j] = pin[t][j];
+    for (int64_t s = S.s0; s < S.s1; s += 4) {
+        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s, P0, P1, P2, P3, pi0, pi1, acc);
+        if (s + 1 >= S.s1) break;
+        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s + 1, P1, P2, P3, P0, pi1, pi0, acc);
+        if (s + 2 >= S.s1) break;
+        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s + 2, P2, P3, P0, P1, pi0, pi1, acc);
+        if (s + 3 >= S.s1) break;
+        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s + 3, P3, P0, P1, P2, pi1, pi0, acc);
     }
 
     if constexpr (DIAG) {
@@ -385,7 +488,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& A, int64_t tile)
 template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs A)
 {
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
     if (tile >= A.ntiles) return;   // whole wave leaves; shuffles stay uniform
     step_tile<D, VEC, TY, UPDATE, DIAG>(A, tile);
 }
@@ -402,6 +505,7 @@ __device__ __forceinline__ void finalize_wave(const WavePartial* __restrict__ pa
     const int lane = threadIdx.x & (kWave - 1);
     uint64_t l0 = 0, l1 = 0, l2 = 0, wl = 0, nf = 0;
     double ar = 0.0, ek = 0.0;
+#pragma unroll 8
     for (int64_t i = lane; i < count; i += kWave) {
         const WavePartial p = parts[i];
         l0 += p.links[0];
@@ -490,130 +594,86 @@ struct AdjArgs {
     double gscale;      // -4 kc b_n
 };
 
-template <int VEC, int TY>
-__device__ __forceinline__ void load_point(const float* f, int64_t s, int64_t nx, int64_t Q,
-                                           const LaneGeom& g, int64_t q0, int nvalid,
-                                           float (&v)[TY][VEC])
+// Plane s of a reverse tile (same ring scheme as step_plane).
+template <int D, int VEC, int TY>
+__device__ __forceinline__ void adj_plane(const AdjArgs& A, const TileSetup<TY>& S, int64_t s,
+                                          const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
+                                          const Plane<VEC, TY>& Pn, Plane<VEC, TY>& Pnn,
+                                          const float (&muc)[TY][VEC], float (&mun)[TY][VEC],
+                                          const float (&phc)[TY][VEC], float (&phn)[TY][VEC],
+                                          double& gsum)
 {
-    const float* base = f + s * (nx * Q);
+    if (s + 1 < S.s1) {
+        load_plane<D, VEC, TY>(A.w_in, s + 2, S, Pnn);
+        load_point<VEC, TY>(A.mu, s + 1, S, mun);
+        load_point<VEC, TY>(A.phi_n, s + 1, S, phn);
+    }
+    float left[TY], right[TY];
+    x_neighbours<VEC, TY>(Pc, S, left, right);
+    float* w_out = A.w_out + s * S.pstride;
+    float* mu_out = A.mu + s * S.pstride;
 #pragma unroll
-    for (int t = 0; t < TY; ++t)
-        if (t < nvalid && g.active) load_vec<VEC>(base + (q0 + t) * nx + g.x0, v[t]);
+    for (int t = 0; t < TY; ++t) {
+        if (t >= S.nvalid) continue;
+        float out_w[VEC], out_mu[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float w = Pc.v[t][j];
+            float nm[D], np[D];
+            neighbours<D, VEC, TY>(Pm, Pc, Pn, left, right, S.nvalid, t, j, nm, np);
+            float lap;
+            if constexpr (D == 3)
+                lap = lap3(w, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.inv_dx2);
+            else
+                lap = lap2(w, nm[0], np[0], nm[1], np[1], A.inv_dx2);
+            const float ph = phc[t][j];
+            const float q = ph * ph * A.kc - 1.0f;
+            const float v2 = A.F * (3.0f * ph * ph * A.kc - 1.0f);   // V''(phi)
+            const float mu_new = fmaf(A.b, lap - v2 * w, muc[t][j]);
+            out_mu[j] = mu_new;
+            out_w[j] = fmaf(A.cw, mu_new, A.a * w);
+            if (S.active) gsum += (double)(w * (ph * q));
+        }
+        if (S.active) {
+            store_vec<VEC>(w_out + S.off[t], out_w);
+            store_vec<VEC>(mu_out + S.off[t], out_mu);
+        }
+    }
 }
 
 template <int D, int VEC, int TY>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
     if (tile >= A.ntiles) return;
+    const TileSetup<TY> S = tile_setup<VEC, TY>(A.nx, A.Q, A.M, A.tiles_x, A.tiles_q, A.rows, tile);
 
-    const int64_t tq = tile % A.tiles_q;
-    const int64_t rest = tile / A.tiles_q;
-    const int64_t tx = rest % A.tiles_x;
-    const int64_t ts = rest / A.tiles_x;
-
-    LaneGeom g;
-    g.x0 = tx * (kWave * VEC) + (int64_t)lane * VEC;
-    g.active = g.x0 < A.nx;
-    g.need_left = g.active && lane == 0;
-    g.need_right = g.active && (lane == kWave - 1 || g.x0 + VEC >= A.nx);
-    g.xl = g.x0 == 0 ? A.nx - 1 : g.x0 - 1;
-    g.xr = g.x0 + VEC >= A.nx ? 0 : g.x0 + VEC;
-
-    const int64_t q0 = tq * TY;
-    const int nvalid = (int)((A.Q - q0) < TY ? (A.Q - q0) : TY);
-    const int64_t s0 = ts * A.rows;
-    const int64_t s1 = (s0 + A.rows) < A.M ? (s0 + A.rows) : A.M;
-    const int64_t pstride = A.nx * A.Q;
-
-    // geometry view for the shared plane loader
-    StepArgs G;
-    G.nx = A.nx;
-    G.Q = A.Q;
-    G.M = A.M;
-
-    Plane<VEC, TY> Pm, Pc, Pn, Pnn;
-    Halo<VEC> Hc, Hn, Hnn, Hdummy;
-    float muc[TY][VEC], mun[TY][VEC], phc[TY][VEC], phn[TY][VEC];
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            Pm.v[t][j] = Pc.v[t][j] = Pn.v[t][j] = Pnn.v[t][j] = 0.0f;
-            muc[t][j] = mun[t][j] = phc[t][j] = phn[t][j] = 0.0f;
-        }
-        Pm.hl[t] = Pm.hr[t] = Pc.hl[t] = Pc.hr[t] = 0.0f;
-        Pn.hl[t] = Pn.hr[t] = Pnn.hl[t] = Pnn.hr[t] = 0.0f;
-    }
-#pragma unroll
-    for (int j = 0; j < VEC; ++j)
-        Hc.lo[j] = Hc.hi[j] = Hn.lo[j] = Hn.hi[j] = Hnn.lo[j] = Hnn.hi[j] = 0.0f;
-
-    load_plane<D, VEC, TY>(A.w_in, s0 - 1, G, g, q0, nvalid, Pm, Hdummy);
-    load_plane<D, VEC, TY>(A.w_in, s0, G, g, q0, nvalid, Pc, Hc);
-    load_plane<D, VEC, TY>(A.w_in, s0 + 1, G, g, q0, nvalid, Pn, Hn);
-    load_point<VEC, TY>(A.mu, s0, A.nx, A.Q, g, q0, nvalid, muc);
-    load_point<VEC, TY>(A.phi_n, s0, A.nx, A.Q, g, q0, nvalid, phc);
+    Plane<VEC, TY> P0, P1, P2, P3;
+    float mu0[TY][VEC], mu1[TY][VEC], ph0[TY][VEC], ph1[TY][VEC];
+    zero_plane(P0);
+    zero_plane(P1);
+    zero_plane(P2);
+    zero_plane(P3);
+    zero_rows<VEC, TY>(mu0);
+    zero_rows<VEC, TY>(mu1);
+    zero_rows<VEC, TY>(ph0);
+    zero_rows<VEC, TY>(ph1);
+    load_plane_values<VEC, TY>(A.w_in, S.s0 - 1, S, P0);
+    load_plane<D, VEC, TY>(A.w_in, S.s0, S, P1);
+    load_plane<D, VEC, TY>(A.w_in, S.s0 + 1, S, P2);
+    load_point<VEC, TY>(A.mu, S.s0, S, mu0);
+    load_point<VEC, TY>(A.phi_n, S.s0, S, ph0);
 
     double gsum = 0.0;
-    for (int64_t s = s0; s < s1; ++s) {
-        if (s + 1 < s1) {
-            load_plane<D, VEC, TY>(A.w_in, s + 2, G, g, q0, nvalid, Pnn, Hnn);
-            load_point<VEC, TY>(A.mu, s + 1, A.nx, A.Q, g, q0, nvalid, mun);
-            load_point<VEC, TY>(A.phi_n, s + 1, A.nx, A.Q, g, q0, nvalid, phn);
-        }
-        float left[TY], right[TY];
-#pragma unroll
-        for (int t = 0; t < TY; ++t) {
-            left[t] = __shfl_up(Pc.v[t][VEC - 1], 1, kWave);
-            right[t] = __shfl_down(Pc.v[t][0], 1, kWave);
-            if (lane == 0) left[t] = Pc.hl[t];
-            if (g.need_right) right[t] = Pc.hr[t];
-        }
-#pragma unroll
-        for (int t = 0; t < TY; ++t) {
-            if (t >= nvalid) continue;
-            float out_w[VEC], out_mu[VEC];
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                const float w = Pc.v[t][j];
-                const float xm = j > 0 ? Pc.v[t][j - 1] : left[t];
-                const float xp = j < VEC - 1 ? Pc.v[t][j + 1] : right[t];
-                float lap;
-                if constexpr (D == 3) {
-                    const float ym = t > 0 ? Pc.v[t > 0 ? t - 1 : 0][j] : Hc.lo[j];
-                    const float yp = (t + 1 < nvalid) ? Pc.v[t + 1 < TY ? t + 1 : t][j] : Hc.hi[j];
-                    lap = lap3(w, xm, xp, ym, yp, Pm.v[t][j], Pn.v[t][j], A.inv_dx2);
-                } else {
-                    lap = lap2(w, xm, xp, Pm.v[t][j], Pn.v[t][j], A.inv_dx2);
-                }
-                const float ph = phc[t][j];
-                const float q = ph * ph * A.kc - 1.0f;
-                const float v2 = A.F * (3.0f * ph * ph * A.kc - 1.0f);   // V''(phi)
-                const float mu_new = fmaf(A.b, lap - v2 * w, muc[t][j]);
-                out_mu[j] = mu_new;
-                out_w[j] = fmaf(A.cw, mu_new, A.a * w);
-                if (g.active) gsum += (double)(w * (ph * q));
-            }
-            if (g.active) {
-                const int64_t off = s * pstride + (q0 + t) * A.nx + g.x0;
-                store_vec<VEC>(A.w_out + off, out_w);
-                store_vec<VEC>(A.mu + off, out_mu);
-            }
-        }
-        Pm = Pc;
-        Pc = Pn;
-        Pn = Pnn;
-        Hc = Hn;
-        Hn = Hnn;
-#pragma unroll
-        for (int t = 0; t < TY; ++t)
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                muc[t][j] = mun[t][j];
-                phc[t][j] = phn[t][j];
-            }
+    for (int64_t s = S.s0; s < S.s1; s += 4) {
+        adj_plane<D, VEC, TY>(A, S, s, P0, P1, P2, P3, mu0, mu1, ph0, ph1, gsum);
+        if (s + 1 >= S.s1) break;
+        adj_plane<D, VEC, TY>(A, S, s + 1, P1, P2, P3, P0, mu1, mu0, ph1, ph0, gsum);
+        if (s + 2 >= S.s1) break;
+        adj_plane<D, VEC, TY>(A, S, s + 2, P2, P3, P0, P1, mu0, mu1, ph0, ph1, gsum);
+        if (s + 3 >= S.s1) break;
+        adj_plane<D, VEC, TY>(A, S, s + 3, P3, P0, P1, P2, mu1, mu0, ph1, ph0, gsum);
     }
     gsum = wave_sum_f64(gsum);
     if (lane == 0) A.gacc[tile] += A.gscale * gsum;
@@ -762,9 +822,6 @@ __device__ __forceinline__ void dispatch_tile(int ndim, int vec, int ty, const S
         if (vec == 4) tile_mode<2, 4, 1>(A, tile, update, diag);
         else if (vec == 2) tile_mode<2, 2, 1>(A, tile, update, diag);
         else tile_mode<2, 1, 1>(A, tile, update, diag);
-    } else if (ty == 2) {
-        if (vec == 2) tile_mode<3, 2, 2>(A, tile, update, diag);
-        else tile_mode<3, 1, 2>(A, tile, update, diag);
     } else {
         if (vec == 4) tile_mode<3, 4, 1>(A, tile, update, diag);
         else if (vec == 2) tile_mode<3, 2, 1>(A, tile, update, diag);
@@ -850,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(const BatchDesc* __
                                                               int64_t tmax, BatchCtl* ctl,
                                                               uint64_t timeout)
 {
-    const int64_t wave = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t wave = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     unsigned gen = 0;
     for (int64_t t = 0; t <= tmax + 1; ++t) {
@@ -867,7 +924,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(const BatchDesc* __
 __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchDesc* __restrict__ Dd, int nreal,
                                                         int64_t total_tiles, int64_t t)
 {
-    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
     if (i >= total_tiles) return;
     batch_tile(Dd, nreal, i, t);
 }
@@ -875,7 +932,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchDesc* __restri
 __global__ __launch_bounds__(kBlock) void k_batch_records(const BatchDesc* __restrict__ Dd, int nreal,
                                                            int64_t t)
 {
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
     batch_records(Dd, nreal, t, wave, (int64_t)gridDim.x * kWavesPerBlock);
 }
 
@@ -1126,9 +1183,7 @@ void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0,
 
 bool batch_tiling_supported(const Geometry& g, const Tiling& t)
 {
-    if (!tiling_supported(g, t)) return false;
-    if (g.ndim == 2) return true;
-    return t.ty == 1 || (t.ty == 2 && t.vec <= 2);
+    return tiling_supported(g, t) && t.ty == 1;
 }
 
 hipError_t batch_max_blocks(int* blocks)

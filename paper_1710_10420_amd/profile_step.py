@@ -1,0 +1,56 @@
+"""Fixed short workloads for kernel profiling (rocprofv3 kernel traces and
+hardware-counter passes).
+
+    python -m paper_1710_10420_amd.profile_step --workload 2d8192 --steps 40
+
+Runs `steps` plain leapfrog steps (no diagnostics) of the chosen lattice in
+its default tiling, then `copies` copies of a 256 MiB float32 buffer with
+torch (a plain copy kernel of known size: 256 MiB read + 256 MiB written per
+dispatch), which calibrates the byte counters against a kernel whose traffic
+is known exactly.
+"""
+import argparse
+import sys
+
+import torch
+
+from paper_1710_10420_amd import prs
+
+WORKLOADS = {
+    "2d8192": dict(shape=(8192, 8192), deta=0.25, m=2.0, W0=10.0),
+    "3d1024": dict(shape=(1024, 1024, 1024), deta=0.2, m=1.0, W0=10.0),
+    "2d2048": dict(shape=(2048, 2048), deta=0.25, m=1.0, W0=10.0),
+    "3d256": dict(shape=(256, 256, 256), deta=0.2, m=1.0, W0=10.0),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="2d8192", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--copies", type=int, default=10)
+    ap.add_argument("--adjoint", action="store_true", help="also run a 64-step adjoint (K = 64)")
+    args = ap.parse_args()
+    w = WORKLOADS[args.workload]
+    p = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"])
+    sim = prs.Sim(p, seed=1)
+    print("workload", args.workload, "tiling", sim.tiling(), flush=True)
+    sim.step_n(args.steps, diag=False)
+    torch.cuda.synchronize()
+    if args.adjoint:
+        nb = prs.prs_adjoint_workspace_bytes(p, 64, 64)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        g = torch.empty_like(sim.phi_a)
+        prs.prs_adjoint(sim.ctx, 64, 64, work.data_ptr(), nb, g.data_ptr(), None)
+        torch.cuda.synchronize()
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.copies):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("done", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -129,6 +129,9 @@ _decl("prs_batch_set_tiling", _i32, _vp, _i32, _i32, _i32, _i32)
 _decl("prs_batch_set_mode", _i32, _vp, _i32)
 _decl("prs_batch_run", _i32, _vp, _S, _i64)
 _decl("prs_batch_destroy", None, _vp)
+_decl("prs_autotune", _i32, _vp, ctypes.c_char_p, _i32, ctypes.POINTER(_d))
+_decl("prs_tuned_tiling", _i32, _P, ctypes.c_char_p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+      ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
 _decl("prs_last_error", ctypes.c_char_p)
 
@@ -138,8 +141,11 @@ EXPORTED = [
     "prs_fill_uniform", "prs_fit_scaling", "prs_strerror", "prs_last_error",
     "prs_adjoint_workspace_bytes", "prs_adjoint_forward", "prs_adjoint_backward", "prs_adjoint",
     "prs_batch_workspace_bytes", "prs_batch_create", "prs_batch_offsets", "prs_batch_set_tiling",
-    "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy",
+    "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy", "prs_autotune", "prs_tuned_tiling",
 ]
+
+PRS_TUNE_FORCE = 1
+PRS_TUNE_BATCH = 2
 
 
 class PRSError(RuntimeError):
@@ -312,6 +318,25 @@ def prs_batch_run(b, total_records):
 
 def prs_batch_destroy(b):
     _lib.prs_batch_destroy(b)
+
+
+def prs_autotune(ctx, cache_path=None, flags=0):
+    """Returns the time of one step (us) with the chosen tiling."""
+    us = _d()
+    path = cache_path.encode() if cache_path else None
+    _check(_lib.prs_autotune(ctx, path, flags, ctypes.byref(us)), "prs_autotune")
+    return us.value
+
+
+def prs_tuned_tiling(p, cache_path, flags=0):
+    """Cached (vec, rows, ty) or None."""
+    v, r, t = _i32(), _i32(), _i32()
+    st = _lib.prs_tuned_tiling(ctypes.byref(p), cache_path.encode(), flags, ctypes.byref(v),
+                               ctypes.byref(r), ctypes.byref(t))
+    if st == PRS_ESTATE:
+        return None
+    _check(st, "prs_tuned_tiling")
+    return v.value, r.value, t.value
 
 
 # ---- convenience object over torch-owned buffers ----------------------

@@ -21,7 +21,7 @@ SPECS = [
     dict(shape=(128, 96), deta=0.25, m=1.0, W0=10.0, nsteps=1, diag_every=1, seed=1006),
 ]
 
-TILINGS = [(4, 32, 1), (2, 17, 1), (4, 64, 1), (2, 16, 2), (4, 32, 1), (1, 16, 1), (4, 16, 1)]
+TILINGS = [(4, 32, 1), (2, 17, 1), (4, 64, 1), (2, 16, 1), (4, 32, 1), (1, 16, 1), (4, 8, 1)]
 
 
 def single_run(prs, sp, tiling):
