@@ -105,6 +105,7 @@ def adjoint_leg(prs, torch, reps=3):
         work = torch.empty(nb, dtype=torch.uint8, device="cuda")
         gphi = torch.empty(sites, dtype=torch.float32, device="cuda")
         sim = prs.Sim(p, seed=7)
+        prs.prs_autotune(sim.ctx, None, 0)
         phi0 = sim.phi_a.clone()
         fwd, bwd = [], []
         for r in range(reps + 1):
@@ -147,6 +148,16 @@ def batch_leg(prs, torch, reps=2):
                   nsteps=it["steps"], diag_every=64 if it["ndim"] == 2 else 50, seed=it["seed"])
              for it in items]
     b = prs.Batch(specs)
+    tuned = {}
+    for r, sp in enumerate(specs):            # one tuning per distinct lattice
+        key = sp["shape"]
+        if key not in tuned:
+            p = prs.make_params(sp["shape"], deta=sp["deta"], m=sp["m"], W0=sp["W0"])
+            t = prs.Sim(p, seed=1)
+            prs.prs_autotune(t.ctx, None, prs.PRS_TUNE_BATCH)
+            tuned[key] = t.tiling()
+            t.close()
+        b.set_tiling(r, *tuned[key])
     su = float(sum(int(np.prod(sp["shape"])) * sp["nsteps"] for sp in specs))
     b.run()                                   # builds and instantiates the graph
     torch.cuda.synchronize()
@@ -161,7 +172,8 @@ def batch_leg(prs, torch, reps=2):
                        "W0 in {5,10}, each to eta = N/2, diagnostics every 64 (2D) / 50 (3D)",
            "realisations": len(specs), "site_updates": su, "ms_per_run": t * 1e3,
            "site_updates_per_s": su / t, "hbm_frac": su * 16 / t / (HBM_PEAK_GBS * 1e9),
-           "records": sum(len(r) for r in recs), "mode": "persistent+hipGraph"}
+           "records": sum(len(r) for r in recs), "mode": "persistent+hipGraph",
+           "tilings": {"x".join(map(str, k)): list(v) for k, v in tuned.items()}}
     log("batch %.1f ms" % (t * 1e3))
     b.close()
     return out
@@ -193,7 +205,9 @@ def main():
                          diag_every=w["diag_every"])
     sites = prs.sites(gp)
     sim = prs.Sim(gp, seed=w["seed"])
-    log("tiling", sim.tiling(), "steps/run", S)
+    tune_us = prs.prs_autotune(sim.ctx, None, 0)     # before the timed region
+    log("tiling", sim.tiling(), "steps/pass", sim.time_blocking(), "tuned %.1f us/step" % tune_us,
+        "steps/run", S)
 
     for i in range(args.warmup):
         log("warmup run", i)
@@ -238,7 +252,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic: seeded uniform(-1,1) initial field (SplitMix64), phi_dot = 0",
         "config": {"workload": w["name"], "sites": sites, "steps_per_run": S,
-                   "records_per_run": len(recs), "tiling": list(sim.tiling())},
+                   "records_per_run": len(recs), "tiling": list(sim.tiling()),
+                   "steps_per_pass": sim.time_blocking()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_step<2,4,1,update> (fused Laplacian+kick+drift[+diagnostics])",

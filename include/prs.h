@@ -86,7 +86,8 @@ typedef struct prs_ctx prs_ctx;
 /* ---- single run ------------------------------------------------------- */
 
 /* Bytes of device workspace prs_init needs for these parameters (per-wave
- * diagnostic partial sums and the record buffer); 0 if p is invalid. */
+ * diagnostic partial sums, the record buffer and, in 2D, a second phi_dot
+ * field for two-step passes); 0 if p is invalid. */
 size_t prs_workspace_bytes(const prs_params* p);
 
 /* Create a run context over caller-owned device buffers.
@@ -155,6 +156,16 @@ prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, dou
 /* Cached tiling for these parameters (no GPU work); PRS_ESTATE if absent. */
 prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t flags, int32_t* vec,
                             int32_t* rows, int32_t* ty);
+
+/* Temporal blocking (2D): with steps_per_pass = 2 (the default for 2D
+ * lattices) prs_step_n advances two steps per pass over HBM wherever no
+ * record falls on the intermediate state, reading each value about once per
+ * two steps; results are bitwise those of single steps.  The second phi_dot
+ * buffer it needs lives in the workspace; every prs_step_n call still ends
+ * with phi_dot in the caller's dphi buffer.  3D lattices support only 1
+ * (PRS_EUNSUPPORTED). */
+prs_status prs_set_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
+prs_status prs_get_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
 
 /* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
 void prs_destroy(prs_ctx* ctx);

@@ -112,6 +112,47 @@ def _load():
     return _lib
 
 
+class using_library:
+    """Context manager that points this module at another build of the
+    oracle source (used by the mutation tests, which compile deliberately
+    wrong copies and check that the pins reject them)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        _load()
+        self.saved = _lib
+        lib = ctypes.CDLL(self.path)
+        for name in ("orc_step", "orc_stats", "orc_run", "orc_energy", "orc_loss", "orc_adjoint",
+                     "orc_delta"):
+            f, g = getattr(self.saved, name), getattr(lib, name)
+            g.argtypes, g.restype = f.argtypes, f.restype
+        _lib = lib
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def build_variant(source_text, out_path):
+    """Compile a modified oracle source to out_path (test use only)."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(source_text)
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                    "-shared", "-std=c11", "-o", out_path, src, "-lm"], check=True)
+    return out_path
+
+
+def source_text():
+    with open(_SRC) as f:
+        return f.read()
+
+
 def set_threads(n):
     """Set the OpenMP thread count used by the oracle's loops."""
     libgomp = ctypes.CDLL("libgomp.so.1")

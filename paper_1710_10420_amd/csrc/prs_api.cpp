@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <cstddef>
 #include <map>
 #include <new>
 #include <string>
@@ -128,6 +129,8 @@ struct prs_ctx {
     int64_t partial_cap;
     prs_stats* drec;
     prs_stats* hrec;   // pinned staging buffer
+    float* pi_alt;     // second phi_dot buffer (workspace, 2D) for two-step passes
+    int32_t tblock;    // steps per pass: 1, or 2 (2D only)
     hipStream_t stream;
     int64_t step;
     // adjoint bookkeeping between prs_adjoint_forward and _backward
@@ -189,8 +192,10 @@ size_t prs_workspace_bytes(const prs_params* p)
 {
     if (validate(p) != PRS_OK) return 0;
     const Geometry g = geometry_of(*p);
-    return align_up((size_t)partial_capacity(g) * sizeof(WavePartial)) +
-           align_up((size_t)kRecCap * sizeof(prs_stats));
+    size_t b = align_up((size_t)partial_capacity(g) * sizeof(WavePartial)) +
+               align_up((size_t)kRecCap * sizeof(prs_stats));
+    if (p->ndim == 2) b += align_up((size_t)sites_of(*p) * sizeof(float));   // second phi_dot
+    return b;
 }
 
 prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, void* workspace,
@@ -224,6 +229,13 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, v
     c->partials = static_cast<WavePartial*>(workspace);
     c->drec = reinterpret_cast<prs_stats*>(
         static_cast<char*>(workspace) + align_up((size_t)c->partial_cap * sizeof(WavePartial)));
+    c->pi_alt = nullptr;
+    c->tblock = 1;
+    if (p->ndim == 2) {
+        c->pi_alt = reinterpret_cast<float*>(reinterpret_cast<char*>(c->drec) +
+                                             align_up((size_t)kRecCap * sizeof(prs_stats)));
+        c->tblock = 2;
+    }
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->step = 0;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hrec), (size_t)kRecCap * sizeof(prs_stats),
@@ -257,33 +269,85 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const DiagCoef dc = diag_coef(c);
     const double ascale = area_scale(c->p);
     const TileCounts tc = tile_counts(c->geo, c->til);
+    const int64_t K = c->p.diag_every;
+    const int64_t end = c->step + nsteps;
+
+    // Plan: steps n and n+1 go through one two-step pass unless the state
+    // n+1 needs a record; the number of passes is kept even so phi_dot ends
+    // in the caller's buffer.
+    const bool pairs_ok = c->tblock == 2 && c->pi_alt != nullptr && c->til.ty == 1;
+    std::vector<uint8_t> plan;   // 2: pair starting here, 1: single step
+    int64_t npairs = 0;
+    for (int64_t n = c->step; n < end;) {
+        const bool pair = pairs_ok && n + 1 < end && !(want && (n + 1) % K == 0);
+        plan.push_back(pair ? 2 : 1);
+        npairs += pair ? 1 : 0;
+        n += pair ? 2 : 1;
+    }
+    if (npairs % 2 == 1) {
+        for (size_t i = plan.size(); i-- > 0;)
+            if (plan[i] == 2) {
+                plan[i] = 1;
+                plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)1);
+                break;
+            }
+    }
+
+    float* pi_cur = c->pi;
+    float* pi_oth = c->pi_alt;
     int64_t pending = 0, written = 0;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    for (uint8_t kind : plan) {
         const int64_t n = c->step;
-        const bool diag = want && (n % c->p.diag_every == 0);
-        HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi, coef_for(c, n),
-                            true, diag, c->partials, dc, c->stream),
-                "step kernel launch");
+        const bool diag = want && (n % K == 0);
+        WavePartial* parts = diag ? c->partials : nullptr;
+        if (kind == 2) {
+            HIP_TRY(launch_pair2d(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, pi_oth,
+                                  coef_for(c, n), coef_for(c, n + 1), diag, parts, dc, c->stream),
+                    "two-step kernel launch");
+            std::swap(pi_cur, pi_oth);
+        } else {
+            HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, coef_for(c, n),
+                                true, diag, parts, dc, c->stream),
+                    "step kernel launch");
+        }
         if (diag) {
             HIP_TRY(launch_finalize(c->partials, tc.ntiles, c->drec + pending, n,
                                     c->p.eta0 + (double)n * c->p.deta, ascale, c->stream),
                     "finalize launch");
             if (++pending == kRecCap) {
-                prs_status s = flush(c, pending, series + written);
-                if (s != PRS_OK) return s;
+                prs_status st = flush(c, pending, series + written);
+                if (st != PRS_OK) return st;
                 written += pending;
                 pending = 0;
             }
         }
         c->cur ^= 1;
-        c->step += 1;
+        c->step += kind;
     }
     if (want) {
-        prs_status s = flush(c, pending, series + written);
-        if (s != PRS_OK) return s;
+        prs_status st = flush(c, pending, series + written);
+        if (st != PRS_OK) return st;
         written += pending;
     }
     if (n_written) *n_written = written;
+    return PRS_OK;
+}
+
+prs_status prs_set_time_blocking(prs_ctx* c, int32_t steps_per_pass)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (steps_per_pass != 1 && steps_per_pass != 2)
+        return fail(PRS_EINVAL, "steps per pass must be 1 or 2");
+    if (steps_per_pass == 2 && c->p.ndim != 2)
+        return fail(PRS_EUNSUPPORTED, "two-step passes are implemented for 2D lattices");
+    c->tblock = steps_per_pass;
+    return PRS_OK;
+}
+
+prs_status prs_get_time_blocking(prs_ctx* c, int32_t* steps_per_pass)
+{
+    if (!c || !steps_per_pass) return fail(PRS_EINVAL, "NULL argument");
+    *steps_per_pass = c->tblock;
     return PRS_OK;
 }
 
@@ -919,7 +983,7 @@ namespace {
 
 constexpr const char* kTuneVersion = "k1";
 
-std::string tune_key(const prs_params& p, bool batch_set)
+std::string tune_key(const prs_params& p, bool batch_set, int tblock)
 {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -930,9 +994,9 @@ std::string tune_key(const prs_params& p, bool batch_set)
         if (colon != std::string::npos) arch = arch.substr(0, colon);
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|%dD|%lldx%lldx%lld|%s|%s", arch.c_str(), p.ndim,
+    std::snprintf(buf, sizeof buf, "%s|%dD|%lldx%lldx%lld|%s|t%d|%s", arch.c_str(), p.ndim,
                   (long long)p.n[0], (long long)p.n[1], (long long)(p.ndim == 3 ? p.n[2] : 1),
-                  batch_set ? "batch" : "single", kTuneVersion);
+                  batch_set ? "batch" : "single", tblock, kTuneVersion);
     return buf;
 }
 
@@ -1004,7 +1068,8 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
     prs_status st = validate(p);
     if (st != PRS_OK) return st;
     const auto m = tune_read(cache_path);
-    const auto it = m.find(tune_key(*p, (flags & PRS_TUNE_BATCH) != 0));
+    const int tb = (flags & PRS_TUNE_BATCH) || p->ndim != 2 ? 1 : 2;
+    const auto it = m.find(tune_key(*p, (flags & PRS_TUNE_BATCH) != 0, tb));
     if (it == m.end()) return fail(PRS_ESTATE, "no cached tiling for this lattice");
     if (vec) *vec = it->second.vec;
     if (rows) *rows = it->second.rows;
@@ -1016,7 +1081,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
 {
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");
     const bool batch_set = (flags & PRS_TUNE_BATCH) != 0;
-    const std::string key = tune_key(c->p, batch_set);
+    const std::string key = tune_key(c->p, batch_set, batch_set ? 1 : c->tblock);
     auto cache = tune_read(cache_path);
     if (!(flags & PRS_TUNE_FORCE)) {
         const auto it = cache.find(key);
@@ -1050,10 +1115,24 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     Tiling best = c->til;
     double best_t = 1e300;
     prs_status result = PRS_OK;
-    auto run = [&](const Tiling& t, int steps) -> hipError_t {
-        for (int k = 0; k < steps; ++k) {
-            hipError_t err = launch_step(c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi,
-                                         coef_for(c, n0 + k), true, false, nullptr, DiagCoef{}, c->stream);
+    // with two-step passes enabled, a candidate is timed on passes (two
+    // steps each) and its per-step time is half a pass
+    const bool pairs = !batch_set && c->tblock == 2 && c->pi_alt != nullptr;
+    const int per = pairs ? 2 : 1;
+    auto run = [&](const Tiling& t, int passes) -> hipError_t {
+        float* pa = c->pi;
+        float* pb = c->pi_alt;
+        for (int k = 0; k < passes; ++k) {
+            hipError_t err;
+            if (pairs) {
+                err = launch_pair2d(c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], pa, pb,
+                                    coef_for(c, n0 + 2 * k), coef_for(c, n0 + 2 * k + 1), false, nullptr,
+                                    DiagCoef{}, c->stream);
+                std::swap(pa, pb);
+            } else {
+                err = launch_step(c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi, coef_for(c, n0 + k),
+                                  true, false, nullptr, DiagCoef{}, c->stream);
+            }
             if (err != hipSuccess) return err;
             c->cur ^= 1;
         }
@@ -1071,11 +1150,12 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double per_step = ms / ((double)timed * per);
         if (e == hipSuccess && log_each)
-            std::fprintf(stderr, "prs_autotune: vec=%d rows=%d ty=%d %.2f us/step\n", t.vec, t.rows, t.ty,
-                         ms / timed * 1e3);
-        if (e == hipSuccess && ms / timed < best_t) {
-            best_t = ms / timed;
+            std::fprintf(stderr, "prs_autotune: vec=%d rows=%d ty=%d steps/pass=%d %.2f us/step\n", t.vec, t.rows,
+                         t.ty, per, per_step * 1e3);
+        if (e == hipSuccess && per_step < best_t) {
+            best_t = per_step;
             best = t;
         }
         // restore the state for the next candidate (and for the caller)

@@ -62,6 +62,13 @@ hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, 
                        float* pi, const StepCoef& k, bool update, bool diag,
                        WavePartial* partials, const DiagCoef& dc, hipStream_t s);
 
+// Two steps n, n+1 of a 2D lattice in one pass (temporal blocking): reads
+// phi_in, pi_in; writes phi^{n+2} to phi_out and phi_dot^{n+3/2} to pi_out
+// (pi_out != pi_in).  With diag, the partials are those of the input state.
+hipError_t launch_pair2d(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                         const float* pi_in, float* pi_out, const StepCoef& k1, const StepCoef& k2,
+                         bool diag, WavePartial* partials, const DiagCoef& dc, hipStream_t s);
+
 // Reduces `count` partials in a fixed order into one record at `rec`.
 hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,
                            int64_t step, double eta, double area_scale, hipStream_t s);

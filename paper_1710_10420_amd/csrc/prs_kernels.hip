@@ -952,6 +952,265 @@ __global__ void k_batch_reset(BatchCtl* ctl)
     }
 }
 
+
+// ------------------------------------------------ two steps per HBM pass --
+//
+// 2D kernel that advances phi^n -> phi^{n+2} in one pass (temporal blocking).
+// While a wave marches along y, level 1 computes phi^{n+1}, phi_dot^{n+1/2}
+// of row y from the phi^n rows y-1..y+1 held in registers, and level 2 then
+// computes phi^{n+2}, phi_dot^{n+3/2} of row y-1 from the level-1 rows
+// y-2..y.  Only level 2 is stored, so each value crosses HBM about once per
+// two steps.  Level 2 needs level-1 values one site beyond the wave on each
+// side: the wave's first lane and its last active lane evaluate that extra
+// site (from two halo scalars of phi^n and one of phi_dot per row), and the
+// tile evaluates level 1 on one extra row above and below.  Every site uses
+// the same kick_drift/lap2 sequence as the single-step kernel, so the result
+// is bitwise that of two single steps.  phi_dot is read from one buffer and
+// written to another (a neighbouring tile may still read the old values).
+// Diagnostics, when requested, are those of the input state (level 1).
+
+template <int VEC>
+struct PairRow {          // one phi^n row: values plus two halo scalars per side
+    float v[VEC];
+    float l1, l2;         // phi at x0-1, x0-2 (first lane)
+    float r1, r2;         // phi at x0+VEC, x0+VEC+1 (last active lane)
+};
+
+template <int VEC>
+struct PairPi {           // phi_dot^{n-1/2} of one row plus the edge sites
+    float v[VEC];
+    float l, r;
+};
+
+template <int VEC>
+struct PairU {            // level-1 phi^{n+1} of one row plus the edge sites
+    float v[VEC];
+    float l, r;
+};
+
+struct PairArgs {
+    const float* phi_in;
+    float* phi_out;
+    const float* pi_in;
+    float* pi_out;
+    WavePartial* partials;
+    int64_t nx, ny;
+    int64_t tiles_x, ntiles;
+    int64_t rows;
+    StepCoef k1, k2;      // coefficients of steps n and n+1
+    DiagCoef dc;
+};
+
+struct PairLane {
+    uint32_t x0, xl1, xl2, xr1, xr2;
+    bool active, first, last;
+    int64_t s0, s1, M;
+    uint32_t nx;
+};
+
+__device__ __forceinline__ int64_t wrap_any(int64_t v, int64_t M)
+{
+    while (v < 0) v += M;
+    while (v >= M) v -= M;
+    return v;
+}
+
+template <int VEC>
+__device__ __forceinline__ void pair_load_row(const float* __restrict__ f, int64_t y, const PairLane& L,
+                                              PairRow<VEC>& R)
+{
+    const float* row = f + wrap_any(y, L.M) * (int64_t)L.nx;
+    if (L.active) load_vec<VEC>(row + L.x0, R.v);
+    if (L.first) {
+        R.l1 = row[L.xl1];
+        R.l2 = row[L.xl2];
+    }
+    if (L.last) {
+        R.r1 = row[L.xr1];
+        R.r2 = row[L.xr2];
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void pair_load_pi(const float* __restrict__ f, int64_t y, const PairLane& L,
+                                             PairPi<VEC>& P)
+{
+    const float* row = f + wrap_any(y, L.M) * (int64_t)L.nx;
+    if (L.active) load_vec<VEC>(row + L.x0, P.v);
+    if (L.first) P.l = row[L.xl1];
+    if (L.last) P.r = row[L.xr1];
+}
+
+template <int VEC>
+__device__ __forceinline__ void pair_zero(PairRow<VEC>& R)
+{
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) R.v[j] = 0.0f;
+    R.l1 = R.l2 = R.r1 = R.r2 = 0.0f;
+}
+
+template <int VEC>
+__device__ __forceinline__ void pair_zero(PairPi<VEC>& P)
+{
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) P.v[j] = 0.0f;
+    P.l = P.r = 0.0f;
+}
+
+template <int VEC>
+__device__ __forceinline__ void pair_zero(PairU<VEC>& U)
+{
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) U.v[j] = 0.0f;
+    U.l = U.r = 0.0f;
+}
+
+// Iteration y of the pair march.  In: phi^n rows y-1 (Pm), y (Pc), y+1 (Pn),
+// phi_dot^{n-1/2} row y (pic), level-1 rows y-2 (Ua), y-1 (Ub) and
+// phi_dot^{n+1/2} row y-1 (p1b).  Out: the prefetch of phi^n row y+2 (Pnn)
+// and phi_dot row y+1 (pin), level-1 row y (Uc, p1c), and, for y-1 inside the
+// tile, the stored phi^{n+2}, phi_dot^{n+3/2} of row y-1.
+template <int VEC, bool DIAG>
+__device__ __forceinline__ void pair_iter(const PairArgs& A, const PairLane& L, int64_t y,
+                                          const PairRow<VEC>& Pm, const PairRow<VEC>& Pc,
+                                          const PairRow<VEC>& Pn, PairRow<VEC>& Pnn,
+                                          const PairPi<VEC>& pic, PairPi<VEC>& pin,
+                                          const PairU<VEC>& Ua, const PairU<VEC>& Ub, PairU<VEC>& Uc,
+                                          const float (&p1b)[VEC], float (&p1c)[VEC], DiagAcc& acc)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    if (y + 1 <= L.s1) {
+        pair_load_row<VEC>(A.phi_in, y + 2, L, Pnn);
+        pair_load_pi<VEC>(A.pi_in, y + 1, L, pin);
+    }
+    // level 1: row y, step n
+    float left = __shfl_up(Pc.v[VEC - 1], 1, kWave);
+    float right = __shfl_down(Pc.v[0], 1, kWave);
+    if (lane == 0) left = Pc.l1;
+    if (L.last) right = Pc.r1;
+    const bool inside = y >= L.s0 && y < L.s1;
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = Pc.v[j];
+        const float xm = j > 0 ? Pc.v[j > 0 ? j - 1 : 0] : left;
+        const float xp = j < VEC - 1 ? Pc.v[j < VEC - 1 ? j + 1 : j] : right;
+        const float lap = lap2(c, xm, xp, Pm.v[j], Pn.v[j], A.k1.inv_dx2);
+        kick_drift(c, lap, pic.v[j], A.k1, p1c[j], Uc.v[j]);
+        if constexpr (DIAG) {
+            if (inside && L.active) {
+                const float nm[2] = {xm, Pm.v[j]};
+                const float np[2] = {xp, Pn.v[j]};
+                site_diag<2>(c, pic.v[j], nm, np, A.dc, acc);
+            }
+        }
+    }
+    {   // level-1 sites one beyond the wave (first lane: x0-1; last lane: x0+VEC)
+        float pl, pr;
+        const float lapl = lap2(Pc.l1, Pc.l2, Pc.v[0], Pm.l1, Pn.l1, A.k1.inv_dx2);
+        kick_drift(Pc.l1, lapl, pic.l, A.k1, pl, Uc.l);
+        const float lapr = lap2(Pc.r1, Pc.v[VEC - 1], Pc.r2, Pm.r1, Pn.r1, A.k1.inv_dx2);
+        kick_drift(Pc.r1, lapr, pic.r, A.k1, pr, Uc.r);
+    }
+    // level 2: row y-1, step n+1
+    if (y - 1 >= L.s0) {
+        float l2 = __shfl_up(Ub.v[VEC - 1], 1, kWave);
+        float r2 = __shfl_down(Ub.v[0], 1, kWave);
+        if (lane == 0) l2 = Ub.l;
+        if (L.last) r2 = Ub.r;
+        float out_phi[VEC], out_pi[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = Ub.v[j];
+            const float xm = j > 0 ? Ub.v[j > 0 ? j - 1 : 0] : l2;
+            const float xp = j < VEC - 1 ? Ub.v[j < VEC - 1 ? j + 1 : j] : r2;
+            const float lap = lap2(c, xm, xp, Ua.v[j], Uc.v[j], A.k2.inv_dx2);
+            kick_drift(c, lap, p1b[j], A.k2, out_pi[j], out_phi[j]);
+        }
+        if (L.active) {
+            const int64_t off = (y - 1) * (int64_t)L.nx + L.x0;
+            store_vec<VEC>(A.phi_out + off, out_phi);
+            store_vec<VEC>(A.pi_out + off, out_pi);
+        }
+    }
+}
+
+template <int VEC, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_pair2d(PairArgs A)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    const uint32_t tl = (uint32_t)tile;
+    const uint32_t tx = tl % (uint32_t)A.tiles_x;
+    const uint32_t ts = tl / (uint32_t)A.tiles_x;
+    PairLane L;
+    L.nx = (uint32_t)A.nx;
+    L.M = A.ny;
+    L.x0 = tx * (kWave * VEC) + (uint32_t)lane * VEC;
+    L.active = L.x0 < L.nx;
+    L.first = L.active && lane == 0;
+    L.last = L.active && (lane == kWave - 1 || L.x0 + VEC >= L.nx);
+    L.xl1 = (uint32_t)wrap_any((int64_t)L.x0 - 1, L.nx);
+    L.xl2 = (uint32_t)wrap_any((int64_t)L.x0 - 2, L.nx);
+    L.xr1 = (uint32_t)wrap_any((int64_t)L.x0 + VEC, L.nx);
+    L.xr2 = (uint32_t)wrap_any((int64_t)L.x0 + VEC + 1, L.nx);
+    L.s0 = (int64_t)ts * A.rows;
+    L.s1 = (L.s0 + A.rows) < A.ny ? (L.s0 + A.rows) : A.ny;
+
+    PairRow<VEC> P0, P1, P2, P3;
+    PairPi<VEC> q0, q1;
+    PairU<VEC> U0, U1, U2, U3;
+    float r0[VEC], r1[VEC];
+    pair_zero(P0);
+    pair_zero(P1);
+    pair_zero(P2);
+    pair_zero(P3);
+    pair_zero(q0);
+    pair_zero(q1);
+    pair_zero(U0);
+    pair_zero(U1);
+    pair_zero(U2);
+    pair_zero(U3);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) r0[j] = r1[j] = 0.0f;
+
+    // rows y-1, y, y+1 of the first iteration y = s0-1, and phi_dot row s0-1
+    pair_load_row<VEC>(A.phi_in, L.s0 - 2, L, P0);
+    pair_load_row<VEC>(A.phi_in, L.s0 - 1, L, P1);
+    pair_load_row<VEC>(A.phi_in, L.s0, L, P2);
+    pair_load_pi<VEC>(A.pi_in, L.s0 - 1, L, q0);
+
+    DiagAcc acc;
+    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
+    acc.walls = acc.nonfinite = 0u;
+    acc.area = acc.ek = 0.0;
+
+    // level-1 rows live in U (ring of 4: y-2, y-1, y and the next), their
+    // phi_dot^{n+1/2} in r (ring of 2)
+    for (int64_t y = L.s0 - 1; y <= L.s1; y += 4) {
+        pair_iter<VEC, DIAG>(A, L, y, P0, P1, P2, P3, q0, q1, U0, U1, U2, r0, r1, acc);
+        if (y + 1 > L.s1) break;
+        pair_iter<VEC, DIAG>(A, L, y + 1, P1, P2, P3, P0, q1, q0, U1, U2, U3, r1, r0, acc);
+        if (y + 2 > L.s1) break;
+        pair_iter<VEC, DIAG>(A, L, y + 2, P2, P3, P0, P1, q0, q1, U2, U3, U0, r0, r1, acc);
+        if (y + 3 > L.s1) break;
+        pair_iter<VEC, DIAG>(A, L, y + 3, P3, P0, P1, P2, q1, q0, U3, U0, U1, r1, r0, acc);
+    }
+
+    if constexpr (DIAG) {
+        WavePartial w;
+        w.links[0] = wave_sum_u32(acc.links[0]);
+        w.links[1] = wave_sum_u32(acc.links[1]);
+        w.links[2] = 0u;
+        w.walls = wave_sum_u32(acc.walls);
+        w.nonfinite = wave_sum_u32(acc.nonfinite);
+        w.pad = 0u;
+        w.area = wave_sum_f64(acc.area);
+        w.ek = wave_sum_f64(acc.ek);
+        if (lane == 0) A.partials[tile] = w;
+    }
+}
+
 template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
 hipError_t launch_t(const StepArgs& A, hipStream_t s)
 {
@@ -1245,6 +1504,43 @@ hipError_t launch_zero_f32(float* v, int64_t count, hipStream_t s)
 }
 
 int batch_ctl_bytes() { return (int)sizeof(BatchCtl); }
+
+
+hipError_t launch_pair2d(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                         const float* pi_in, float* pi_out, const StepCoef& k1, const StepCoef& k2,
+                         bool diag, WavePartial* partials, const DiagCoef& dc, hipStream_t s)
+{
+    if (g.ndim != 2 || t.ty != 1) return hipErrorInvalidValue;
+    const TileCounts c = tile_counts(g, t);
+    PairArgs A;
+    A.phi_in = phi_in;
+    A.phi_out = phi_out;
+    A.pi_in = pi_in;
+    A.pi_out = pi_out;
+    A.partials = partials;
+    A.nx = g.nx;
+    A.ny = g.M;
+    A.tiles_x = c.tiles_x;
+    A.ntiles = c.ntiles;
+    A.rows = t.rows;
+    A.k1 = k1;
+    A.k2 = k2;
+    A.dc = dc;
+    const int64_t blocks = (c.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+#define PRS_PAIR(V)                                                                                   \
+    if (diag)                                                                                         \
+        hipLaunchKernelGGL((k_pair2d<V, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);       \
+    else                                                                                              \
+        hipLaunchKernelGGL((k_pair2d<V, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);      \
+    return hipGetLastError();
+    switch (t.vec) {
+    case 1: { PRS_PAIR(1) }
+    case 2: { PRS_PAIR(2) }
+    case 4: { PRS_PAIR(4) }
+    }
+#undef PRS_PAIR
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_fill_uniform(float* phi, int64_t count, uint64_t seed, hipStream_t s)
 {

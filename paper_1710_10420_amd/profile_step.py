@@ -30,11 +30,17 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--copies", type=int, default=10)
     ap.add_argument("--adjoint", action="store_true", help="also run a 64-step adjoint (K = 64)")
+    ap.add_argument("--tiling", default=None, help="vec,rows,ty (default: the library default)")
+    ap.add_argument("--steps-per-pass", type=int, default=None, help="1 or 2 (2D only)")
     args = ap.parse_args()
     w = WORKLOADS[args.workload]
     p = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"])
     sim = prs.Sim(p, seed=1)
-    print("workload", args.workload, "tiling", sim.tiling(), flush=True)
+    if args.tiling:
+        sim.set_tiling(*[int(v) for v in args.tiling.split(",")])
+    if args.steps_per_pass:
+        sim.set_time_blocking(args.steps_per_pass)
+    print("workload", args.workload, "tiling", sim.tiling(), "steps/pass", sim.time_blocking(), flush=True)
     sim.step_n(args.steps, diag=False)
     torch.cuda.synchronize()
     if args.adjoint:

@@ -132,6 +132,8 @@ _decl("prs_batch_destroy", None, _vp)
 _decl("prs_autotune", _i32, _vp, ctypes.c_char_p, _i32, ctypes.POINTER(_d))
 _decl("prs_tuned_tiling", _i32, _P, ctypes.c_char_p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
       ctypes.POINTER(_i32))
+_decl("prs_set_time_blocking", _i32, _vp, _i32)
+_decl("prs_get_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
 _decl("prs_last_error", ctypes.c_char_p)
 
@@ -142,6 +144,7 @@ EXPORTED = [
     "prs_adjoint_workspace_bytes", "prs_adjoint_forward", "prs_adjoint_backward", "prs_adjoint",
     "prs_batch_workspace_bytes", "prs_batch_create", "prs_batch_offsets", "prs_batch_set_tiling",
     "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy", "prs_autotune", "prs_tuned_tiling",
+    "prs_set_time_blocking", "prs_get_time_blocking",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -233,6 +236,16 @@ def prs_get_tiling(ctx):
     _check(_lib.prs_get_tiling(ctx, ctypes.byref(v), ctypes.byref(r), ctypes.byref(t)),
            "prs_get_tiling")
     return v.value, r.value, t.value
+
+
+def prs_set_time_blocking(ctx, steps_per_pass):
+    _check(_lib.prs_set_time_blocking(ctx, steps_per_pass), "prs_set_time_blocking")
+
+
+def prs_get_time_blocking(ctx):
+    v = _i32()
+    _check(_lib.prs_get_time_blocking(ctx, ctypes.byref(v)), "prs_get_time_blocking")
+    return v.value
 
 
 def prs_destroy(ctx):
@@ -412,6 +425,12 @@ class Sim:
 
     def tiling(self):
         return prs_get_tiling(self.ctx)
+
+    def set_time_blocking(self, steps_per_pass):
+        prs_set_time_blocking(self.ctx, steps_per_pass)
+
+    def time_blocking(self):
+        return prs_get_time_blocking(self.ctx)
 
 
 class PRSLoss(torch.autograd.Function):

@@ -320,9 +320,12 @@ def test_p9_link_counts_brute_force(shape, limit):
 def test_p9_zero_tiebreak():
     """A zero value (either sign of zero) counts as non-negative."""
     p = O.params((4, 1), deta=0.25)
+    r = O.stats(p, np.array([0.0, -0.5, -0.5, -0.5]), np.zeros(4))
+    assert r["links_dir"][0] == 2 and r["wall_sites"] == 3      # + - - -
+    r = O.stats(p, np.array([-0.0, 0.5, 0.5, 0.5]), np.zeros(4))
+    assert r["links_dir"][0] == 0 and r["wall_sites"] == 0      # + + + +
     r = O.stats(p, np.array([0.0, -0.0, -1e-300, 1.0]), np.zeros(4))
-    # signs: + + - +  -> links (1,2) and (2,3)
-    assert r["links_dir"][0] == 2
+    assert r["links_dir"][0] == 2                                # + + - +
 
 
 def test_nonfinite_count():
