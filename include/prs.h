@@ -151,21 +151,28 @@ prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty
  * receives the time of one step with the chosen tiling.  Synchronises. */
 #define PRS_TUNE_FORCE 1
 #define PRS_TUNE_BATCH 2
+#define PRS_TUNE_ADJOINT 4   /* tune the reverse-sweep kernel's tiling instead */
 prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, double* best_us);
 
 /* Cached tiling for these parameters (no GPU work); PRS_ESTATE if absent. */
 prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t flags, int32_t* vec,
                             int32_t* rows, int32_t* ty);
 
-/* Temporal blocking (2D): with steps_per_pass = 2 (the default for 2D
- * lattices) prs_step_n advances two steps per pass over HBM wherever no
- * record falls on the intermediate state, reading each value about once per
- * two steps; results are bitwise those of single steps.  The second phi_dot
- * buffer it needs lives in the workspace; every prs_step_n call still ends
- * with phi_dot in the caller's dphi buffer.  3D lattices support only 1
- * (PRS_EUNSUPPORTED). */
+/* Temporal blocking (2D): with steps_per_pass = T in 2..4 (default 2 for 2D
+ * lattices; the autotuner may pick another) prs_step_n advances up to T steps
+ * per pass over HBM -- a pass never has a recorded state inside it -- so each
+ * value is read about once per T steps.  Results are bitwise those of single
+ * steps.  The second phi_dot buffer this needs lives in the workspace; every
+ * prs_step_n call still ends with phi_dot in the caller's dphi buffer.  3D
+ * lattices support only 1 (PRS_EUNSUPPORTED otherwise). */
 prs_status prs_set_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
 prs_status prs_get_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
+
+/* Tiling of the reverse-sweep (adjoint) kernel, chosen independently of the
+ * forward tiling (same parameters and rules as prs_set_tiling; the
+ * recomputation inside prs_adjoint_backward uses the forward tiling). */
+prs_status prs_set_adjoint_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
+prs_status prs_get_adjoint_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
 
 /* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
 void prs_destroy(prs_ctx* ctx);
@@ -224,8 +231,8 @@ typedef struct prs_batch_item {
     int32_t init_from_seed;  /* 1: every run starts from the seeded field and
                                 dphi = 0; 0: from the buffers' contents */
     int32_t reserved;
-    void* phi_a;         /* caller-owned fields as in prs_init; phi^n ends in */
-    void* phi_b;         /*   phi_a when n is even, phi_b when n is odd */
+    void* phi_a;         /* caller-owned fields as in prs_init: phi_a holds phi^0; */
+    void* phi_b;         /*   prs_batch_state names the buffer of the final phi */
     void* dphi;
 } prs_batch_item;
 
@@ -235,8 +242,9 @@ typedef struct prs_batch prs_batch;
 #define PRS_BATCH_PERSISTENT 1        /* the same launch sequence without the graph */
 #define PRS_BATCH_PER_STEP 2          /* one launch per step over all realisations */
 
-/* Device workspace (descriptors, coefficient tables, record partials and the
- * records themselves); 0 if any item is invalid. */
+/* Device workspace (descriptors, coefficient and pass tables, the second
+ * phi_dot field of 2D items, record partials and the records themselves); 0 if
+ * any item is invalid. */
 size_t prs_batch_workspace_bytes(const prs_batch_item* items, int32_t count);
 
 /* Validates every item (as prs_init, PRS_EINVAL naming the item) and builds
@@ -251,6 +259,14 @@ prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
 
 /* Tiling of one item (vec and rows as in prs_set_tiling; ty must be 1). */
 prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
+
+/* Steps per pass of one item: 1, or 2 (the default for 2D items; 2D only).
+ * The second phi_dot field two-step passes need lives in the workspace. */
+prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass);
+
+/* Device pointers of item `item`'s final phi and phi_dot after prs_batch_run
+ * (phi_dot is always the item's dphi buffer). */
+prs_status prs_batch_state(const prs_batch* b, int32_t item, void** phi, void** dphi);
 prs_status prs_batch_set_mode(prs_batch* b, int32_t mode);
 
 /* Runs the whole ensemble (initial fields if init_from_seed, all steps, all

@@ -49,6 +49,7 @@ prs_status hip_fail(hipError_t e, const char* what)
 constexpr size_t kAlign = 256;
 constexpr int64_t kRecCap = 1024;   // device records buffered before a flush
 constexpr int64_t kMinRows = 8;     // smallest marching tile the workspace allows
+constexpr int kMaxPassSteps = 4;    // most leapfrog steps fused into one pass (2D)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -103,14 +104,16 @@ Tiling default_tiling(const Geometry& g)
     else if (g.nx % 2 == 0) t.vec = 2;
     else t.vec = 1;
     t.ty = g.ndim == 3 ? 2 : 1;
-    t.rows = 32;
+    t.rows = g.ndim == 3 ? 32 : 16;
     return t;
 }
 
 int64_t partial_capacity(const Geometry& g)
 {
     Tiling t{1, (int)kMinRows, 1};
-    return tile_counts(g, t).ntiles;
+    int64_t n = tile_counts(g, t).ntiles;
+    if (g.ndim == 2) n = std::max<int64_t>(n, tb_tiles(g, t, kMaxPassSteps));
+    return n;
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
@@ -130,6 +133,7 @@ struct prs_ctx {
     prs_stats* drec;
     prs_stats* hrec;   // pinned staging buffer
     float* pi_alt;     // second phi_dot buffer (workspace, 2D) for two-step passes
+    Tiling adj_til;    // tiling of the reverse-sweep kernel
     int32_t tblock;    // steps per pass: 1, or 2 (2D only)
     hipStream_t stream;
     int64_t step;
@@ -230,6 +234,7 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, v
     c->drec = reinterpret_cast<prs_stats*>(
         static_cast<char*>(workspace) + align_up((size_t)c->partial_cap * sizeof(WavePartial)));
     c->pi_alt = nullptr;
+    c->adj_til = c->til;
     c->tblock = 1;
     if (p->ndim == 2) {
         c->pi_alt = reinterpret_cast<float*>(reinterpret_cast<char*>(c->drec) +
@@ -272,23 +277,28 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int64_t K = c->p.diag_every;
     const int64_t end = c->step + nsteps;
 
-    // Plan: steps n and n+1 go through one two-step pass unless the state
-    // n+1 needs a record; the number of passes is kept even so phi_dot ends
-    // in the caller's buffer.
-    const bool pairs_ok = c->tblock == 2 && c->pi_alt != nullptr && c->til.ty == 1;
-    std::vector<uint8_t> plan;   // 2: pair starting here, 1: single step
-    int64_t npairs = 0;
+    // Plan: passes of up to tblock steps (2D), never with a recorded state
+    // strictly inside a pass; the number of multi-step passes is kept even
+    // so phi_dot ends in the caller's buffer.
+    const int T = (c->pi_alt != nullptr && c->til.ty == 1) ? c->tblock : 1;
+    std::vector<uint8_t> plan;   // steps of each pass
+    int64_t nmulti = 0;
     for (int64_t n = c->step; n < end;) {
-        const bool pair = pairs_ok && n + 1 < end && !(want && (n + 1) % K == 0);
-        plan.push_back(pair ? 2 : 1);
-        npairs += pair ? 1 : 0;
-        n += pair ? 2 : 1;
+        int64_t L = std::min<int64_t>(T, end - n);
+        if (want) {
+            const int64_t next_rec = (n / K + 1) * K;     // first record state after n
+            L = std::min<int64_t>(L, next_rec - n);
+        }
+        plan.push_back((uint8_t)L);
+        nmulti += L > 1 ? 1 : 0;
+        n += L;
     }
-    if (npairs % 2 == 1) {
+    if (nmulti % 2 == 1) {
         for (size_t i = plan.size(); i-- > 0;)
-            if (plan[i] == 2) {
-                plan[i] = 1;
-                plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)1);
+            if (plan[i] > 1) {
+                const int L = plan[i];
+                plan.erase(plan.begin() + (std::ptrdiff_t)i);
+                plan.insert(plan.begin() + (std::ptrdiff_t)i, (size_t)L, (uint8_t)1);
                 break;
             }
     }
@@ -296,22 +306,26 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     float* pi_cur = c->pi;
     float* pi_oth = c->pi_alt;
     int64_t pending = 0, written = 0;
-    for (uint8_t kind : plan) {
+    for (uint8_t L : plan) {
         const int64_t n = c->step;
         const bool diag = want && (n % K == 0);
         WavePartial* parts = diag ? c->partials : nullptr;
-        if (kind == 2) {
-            HIP_TRY(launch_pair2d(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, pi_oth,
-                                  coef_for(c, n), coef_for(c, n + 1), diag, parts, dc, c->stream),
-                    "two-step kernel launch");
+        int64_t ntiles = tc.ntiles;
+        if (L > 1) {
+            StepCoef k[kMaxPassSteps];
+            for (int i = 0; i < L; ++i) k[i] = coef_for(c, n + i);
+            HIP_TRY(launch_tb2d(L, c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, pi_oth, k, diag,
+                                parts, dc, c->stream),
+                    "multi-step kernel launch");
             std::swap(pi_cur, pi_oth);
+            ntiles = tb_tiles(c->geo, c->til, L);
         } else {
-            HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, coef_for(c, n),
-                                true, diag, parts, dc, c->stream),
+            HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, pi_cur,
+                                coef_for(c, n), true, diag, parts, dc, c->stream),
                     "step kernel launch");
         }
         if (diag) {
-            HIP_TRY(launch_finalize(c->partials, tc.ntiles, c->drec + pending, n,
+            HIP_TRY(launch_finalize(c->partials, ntiles, c->drec + pending, n,
                                     c->p.eta0 + (double)n * c->p.deta, ascale, c->stream),
                     "finalize launch");
             if (++pending == kRecCap) {
@@ -322,7 +336,7 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
             }
         }
         c->cur ^= 1;
-        c->step += kind;
+        c->step += L;
     }
     if (want) {
         prs_status st = flush(c, pending, series + written);
@@ -336,10 +350,10 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
 prs_status prs_set_time_blocking(prs_ctx* c, int32_t steps_per_pass)
 {
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");
-    if (steps_per_pass != 1 && steps_per_pass != 2)
-        return fail(PRS_EINVAL, "steps per pass must be 1 or 2");
-    if (steps_per_pass == 2 && c->p.ndim != 2)
-        return fail(PRS_EUNSUPPORTED, "two-step passes are implemented for 2D lattices");
+    if (steps_per_pass < 1 || steps_per_pass > kMaxPassSteps)
+        return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
+    if (steps_per_pass > 1 && c->p.ndim != 2)
+        return fail(PRS_EUNSUPPORTED, "multi-step passes are implemented for 2D lattices");
     c->tblock = steps_per_pass;
     return PRS_OK;
 }
@@ -356,7 +370,7 @@ prs_status prs_wall_stats(prs_ctx* c, prs_stats* out)
     if (!c || !out) return fail(PRS_EINVAL, "NULL argument");
     const TileCounts tc = tile_counts(c->geo, c->til);
     const int64_t n = c->step;
-    HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], nullptr, c->pi, coef_for(c, n), false, true,
+    HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], nullptr, c->pi, nullptr, coef_for(c, n), false, true,
                         c->partials, diag_coef(c), c->stream),
             "diagnostics kernel launch");
     HIP_TRY(launch_finalize(c->partials, tc.ntiles, c->drec, n, c->p.eta0 + (double)n * c->p.deta,
@@ -400,6 +414,28 @@ prs_status prs_set_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t ty)
         return fail(PRS_EINVAL, "tiling has more wave tiles than the workspace holds (rows >= %lld)",
                     (long long)kMinRows);
     c->til = t;
+    return PRS_OK;
+}
+
+prs_status prs_set_adjoint_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t ty)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    Tiling t{vec, rows, ty};
+    if (!tiling_supported(c->geo, t))
+        return fail(PRS_EINVAL, "tiling vec=%d rows=%d ty=%d not supported for this lattice", vec, rows, ty);
+    if (tile_counts(c->geo, t).ntiles > c->partial_cap)
+        return fail(PRS_EINVAL, "tiling has more wave tiles than the workspace holds (rows >= %lld)",
+                    (long long)kMinRows);
+    c->adj_til = t;
+    return PRS_OK;
+}
+
+prs_status prs_get_adjoint_tiling(prs_ctx* c, int32_t* vec, int32_t* rows, int32_t* ty)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (vec) *vec = c->adj_til.vec;
+    if (rows) *rows = c->adj_til.rows;
+    if (ty) *ty = c->adj_til.ty;
     return PRS_OK;
 }
 
@@ -555,19 +591,34 @@ prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, v
     c->adj_ready = false;
     const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
     const int64_t n0 = c->step;
-    for (int64_t sg = 0; sg < L.nseg; ++sg) {
-        HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_phi + L.fb * sg), c->phi[c->cur], bytes,
-                               hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
-        HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_pi + L.fb * sg), c->pi, bytes,
-                               hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
-        const int64_t len = std::min<int64_t>(L.K, nsteps - sg * L.K);
-        for (int64_t k = 0; k < len; ++k) {
-            HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi,
-                                coef_for(c, c->step), true, false, nullptr, DiagCoef{}, c->stream),
-                    "step kernel launch");
-            c->cur ^= 1;
-            c->step += 1;
+    // Checkpoint 0 is a copy of the starting state.  Checkpoint s >= 1 is
+    // written directly by the step that produces it, and the next step reads
+    // it from there (phi_dot out of place), so no further copies are made.
+    HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_phi), c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream),
+            "checkpoint copy");
+    HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_pi), c->pi, bytes, hipMemcpyDeviceToDevice, c->stream),
+            "checkpoint copy");
+    const float* phi_in = c->phi[c->cur];
+    const float* pi_in = c->pi;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t n = n0 + k;
+        float* phi_out;
+        float* pi_out;
+        if ((k + 1) % L.K == 0 && k + 1 < nsteps) {           // produces checkpoint (k+1)/K
+            const int64_t sg = (k + 1) / L.K;
+            phi_out = at<float>(work, L.ck_phi + L.fb * sg);
+            pi_out = at<float>(work, L.ck_pi + L.fb * sg);
+        } else {
+            phi_out = c->phi[c->cur ^ 1];
+            pi_out = c->pi;
         }
+        HIP_TRY(launch_step(c->geo, c->til, phi_in, phi_out, pi_in, pi_out, coef_for(c, n), true, false, nullptr,
+                            DiagCoef{}, c->stream),
+                "step kernel launch");
+        if (phi_out == c->phi[c->cur ^ 1]) c->cur ^= 1;
+        phi_in = phi_out;
+        pi_in = pi_out;
+        c->step += 1;
     }
     const float kc = (float)(1.0 / (c->p.phi0 * c->p.phi0));
     HIP_TRY(launch_adj_seed(c->phi[c->cur], sites_of(c->p), kc, (float)c->p.deta, at<float>(work, L.mu),
@@ -599,7 +650,7 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     const AdjLayout L = adj_layout(c->p, c->adj_nsteps, c->adj_K, c->partial_cap);
     const int64_t n0 = c->adj_n0;
     const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
-    const TileCounts tc = tile_counts(c->geo, c->til);
+    const TileCounts tc = tile_counts(c->geo, c->adj_til);
     double* gacc = at<double>(work, L.gacc);
     HIP_TRY(launch_zero_f64(gacc, tc.ntiles, c->stream), "zero launch");
     float* mu = at<float>(work, L.mu);
@@ -611,22 +662,21 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
         const int64_t ns = n0 + sg * L.K;
         const int64_t len = std::min<int64_t>(L.K, c->adj_nsteps - sg * L.K);
         float* ckphi = at<float>(work, L.ck_phi + L.fb * sg);
-        // recompute phi^{ns+1 .. ns+len-1} from the checkpoint
-        if (len > 1) {
-            HIP_TRY(hipMemcpyAsync(pis, at<float>(work, L.ck_pi + L.fb * sg), bytes,
-                                   hipMemcpyDeviceToDevice, c->stream), "checkpoint restore");
-        }
+        // recompute phi^{ns+1 .. ns+len-1} from the checkpoint (the first
+        // step reads the checkpointed phi_dot and writes the scratch copy)
         const float* prev = ckphi;
+        const float* pprev = at<float>(work, L.ck_pi + L.fb * sg);
         for (int64_t k = 1; k < len; ++k) {
-            HIP_TRY(launch_step(c->geo, c->til, prev, seg(k), pis, coef_for(c, ns + k - 1), true, false,
+            HIP_TRY(launch_step(c->geo, c->til, prev, seg(k), pprev, pis, coef_for(c, ns + k - 1), true, false,
                                 nullptr, DiagCoef{}, c->stream),
                     "recompute launch");
             prev = seg(k);
+            pprev = pis;
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const int64_t n = ns + k;
             const float* phin = k == 0 ? ckphi : seg(k);
-            HIP_TRY(launch_adjoint(c->geo, c->til, wcur, wnxt, mu, phin, gacc, adj_coef(c, n, n == n0),
+            HIP_TRY(launch_adjoint(c->geo, c->adj_til, wcur, wnxt, mu, phin, gacc, adj_coef(c, n, n == n0),
                                    c->stream),
                     "adjoint launch");
             std::swap(wcur, wnxt);
@@ -664,13 +714,15 @@ struct prs_batch {
     std::vector<prs_batch_item> items;
     std::vector<Geometry> geo;
     std::vector<Tiling> til;
+    std::vector<int32_t> tblock;        // steps per pass (1, or 2 for 2D items)
+    std::vector<int64_t> npasses;       // per item, including the final record pass
     std::vector<int64_t> rec_off;       // count + 1 record offsets
     std::vector<int64_t> part_cap;      // partial capacity per realisation
-    std::vector<size_t> coef_off, part_off;
+    std::vector<size_t> coef_off, pass_off, alt_off, part_off;
     hipStream_t stream;
     void* ws;
     size_t ws_bytes;
-    size_t off_desc, off_coef, off_part, off_rec, off_ctl;
+    size_t off_desc, off_coef, off_pass, off_alt, off_part, off_rec, off_ctl;
     int64_t total_tiles, tmax, total_recs;
     prs_stats* hrec;     // pinned
     int* herr;           // pinned
@@ -687,9 +739,13 @@ struct prs_batch {
 
 namespace {
 
+struct PassEntry {
+    int32_t first, steps, rec, alt;
+};
+
 struct BatchLayout {
-    size_t desc, coef, part, rec, ctl, total;
-    std::vector<size_t> coef_off, part_off;
+    size_t desc, coef, pass, alt, part, rec, ctl, total;
+    std::vector<size_t> coef_off, pass_off, alt_off, part_off;
     std::vector<int64_t> rec_off, part_cap;
 };
 
@@ -701,10 +757,6 @@ int64_t batch_records_of(const prs_batch_item& it)
 prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout& L)
 {
     if (!items || count < 1) return fail(PRS_EINVAL, "batch needs at least one item");
-    size_t o = align_up(batch_desc_bytes() * (size_t)count);
-    L.desc = 0;
-    L.coef = o;
-    L.coef_off.assign(count, 0);
     for (int32_t r = 0; r < count; ++r) {
         prs_status st = validate(&items[r].p);
         if (st != PRS_OK) {
@@ -713,8 +765,27 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
             return fail(st, "batch item %d: %s", r, why);
         }
         if (items[r].nsteps < 0) return fail(PRS_EINVAL, "batch item %d: nsteps < 0", r);
+        if (items[r].nsteps > 0x3fffffff) return fail(PRS_EINVAL, "batch item %d: too many steps", r);
+    }
+    size_t o = align_up(batch_desc_bytes() * (size_t)count);
+    L.desc = 0;
+    L.coef = o;
+    L.coef_off.assign(count, 0);
+    for (int32_t r = 0; r < count; ++r) {
         L.coef_off[r] = o - L.coef;
-        o += align_up((size_t)std::max<int64_t>(items[r].nsteps, 1) * 2 * sizeof(float));
+        o += align_up((size_t)(items[r].nsteps + 1) * 2 * sizeof(float));
+    }
+    L.pass = o;
+    L.pass_off.assign(count, 0);
+    for (int32_t r = 0; r < count; ++r) {
+        L.pass_off[r] = o - L.pass;
+        o += align_up((size_t)(items[r].nsteps + 1) * sizeof(PassEntry));
+    }
+    L.alt = o;
+    L.alt_off.assign(count, 0);
+    for (int32_t r = 0; r < count; ++r) {
+        L.alt_off[r] = o - L.alt;
+        if (items[r].p.ndim == 2) o += align_up((size_t)sites_of(items[r].p) * sizeof(float));
     }
     L.part = o;
     L.part_off.assign(count, 0);
@@ -734,6 +805,43 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
     return PRS_OK;
 }
 
+// Pass table of one realisation: passes of up to T steps (never with a
+// recorded state inside), an even number of two-step passes (phi_dot ends in
+// the caller's buffer), then the diagnostics-only pass of the final state.
+std::vector<PassEntry> batch_plan(const prs_batch_item& it, int T)
+{
+    const int64_t S = it.nsteps, K = it.p.diag_every;
+    std::vector<int> len;
+    int64_t nmulti = 0;
+    for (int64_t n = 0; n < S;) {
+        int64_t L = std::min<int64_t>(T, S - n);
+        if (K > 0) L = std::min<int64_t>(L, (n / K + 1) * K - n);
+        len.push_back((int)L);
+        nmulti += L > 1 ? 1 : 0;
+        n += L;
+    }
+    if (nmulti % 2 == 1) {
+        for (size_t i = len.size(); i-- > 0;)
+            if (len[i] > 1) {
+                const int L = len[i];
+                len.erase(len.begin() + (std::ptrdiff_t)i);
+                len.insert(len.begin() + (std::ptrdiff_t)i, (size_t)L, 1);
+                break;
+            }
+    }
+    std::vector<PassEntry> out;
+    int64_t n = 0, rec = 0;
+    int alt = 0;
+    for (int L : len) {
+        const bool r = K > 0 && n % K == 0;
+        out.push_back(PassEntry{(int32_t)n, L, r ? (int32_t)rec++ : -1, alt});
+        if (L > 1) alt ^= 1;
+        n += L;
+    }
+    out.push_back(PassEntry{(int32_t)S, 0, (int32_t)rec, alt});   // final state
+    return out;
+}
+
 void batch_release_graph(prs_batch* b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -744,17 +852,18 @@ void batch_release_graph(prs_batch* b)
 
 prs_status batch_upload(prs_batch* b)
 {
-    // coefficient tables and descriptors, built on the host (same FP64 ->
-    // float32 schedule as a single run) and copied synchronously
+    // coefficient tables, pass tables and descriptors, built on the host
+    // (same FP64 -> float32 schedule as a single run) and copied synchronously
     std::vector<char> desc(batch_desc_bytes() * (size_t)b->count);
     char* base = static_cast<char*>(b->ws);
     int64_t tile_base = 0;
+    b->tmax = 0;
     for (int32_t r = 0; r < b->count; ++r) {
         const prs_batch_item& it = b->items[r];
         prs_ctx tmp{};
         tmp.p = it.p;
         tmp.V0 = v0_of(it.p);
-        std::vector<float> coef((size_t)std::max<int64_t>(it.nsteps, 1) * 2, 0.0f);
+        std::vector<float> coef((size_t)(it.nsteps + 1) * 2, 0.0f);
         for (int64_t n = 0; n < it.nsteps; ++n) {
             const StepCoef k = coef_for(&tmp, n);
             coef[2 * n] = k.a;
@@ -763,16 +872,21 @@ prs_status batch_upload(prs_batch* b)
         float2* dcoef = reinterpret_cast<float2*>(base + b->off_coef + b->coef_off[r]);
         HIP_TRY(hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice),
                 "coefficient upload");
+        const std::vector<PassEntry> plan = batch_plan(it, b->tblock[r]);
+        void* dpass = base + b->off_pass + b->pass_off[r];
+        HIP_TRY(hipMemcpy(dpass, plan.data(), plan.size() * sizeof(PassEntry), hipMemcpyHostToDevice),
+                "pass table upload");
+        b->npasses[r] = (int64_t)plan.size();
+        b->tmax = std::max<int64_t>(b->tmax, (int64_t)plan.size() - 1);
+        float* alt = it.p.ndim == 2 ? reinterpret_cast<float*>(base + b->off_alt + b->alt_off[r]) : nullptr;
         WavePartial* p0 = reinterpret_cast<WavePartial*>(base + b->off_part + b->part_off[r]);
         WavePartial* p1 = p0 + (align_up((size_t)b->part_cap[r] * sizeof(WavePartial)) / sizeof(WavePartial));
         prs_stats* recs = reinterpret_cast<prs_stats*>(base + b->off_rec) + b->rec_off[r];
-        const TileCounts tc = tile_counts(b->geo[r], b->til[r]);
         batch_fill_desc(desc.data() + batch_desc_bytes() * r, b->geo[r], b->til[r],
                         static_cast<float*>(it.phi_a), static_cast<float*>(it.phi_b),
-                        static_cast<float*>(it.dphi), dcoef, p0, p1, recs, it.nsteps, tile_base,
-                        prs_records_in(&it.p, 0, it.nsteps), it.p.eta0, it.p.deta, area_scale(it.p),
-                        it.p.diag_every, coef_for(&tmp, 0), diag_coef(&tmp));
-        tile_base += tc.ntiles;
+                        static_cast<float*>(it.dphi), alt, dcoef, dpass, (int64_t)plan.size(), p0, p1, recs,
+                        tile_base, it.p.eta0, it.p.deta, area_scale(it.p), coef_for(&tmp, 0), diag_coef(&tmp));
+        tile_base += batch_tiles_max(b->geo[r], b->til[r]);
     }
     b->total_tiles = tile_base;
     HIP_TRY(hipMemcpy(base + b->off_desc, desc.data(), desc.size(), hipMemcpyHostToDevice), "descriptor upload");
@@ -780,7 +894,7 @@ prs_status batch_upload(prs_batch* b)
 }
 
 // The whole ensemble as a sequence on the stream: initial fields, then the
-// steps (one persistent launch, or one launch pair per step), then the
+// phases (one persistent launch, or one launch pair per phase), then the
 // records and the error flag to pinned host memory.
 prs_status batch_enqueue(prs_batch* b, bool persistent, hipStream_t stream)
 {
@@ -803,7 +917,7 @@ prs_status batch_enqueue(prs_batch* b, bool persistent, hipStream_t stream)
                 "persistent launch");
     } else {
         for (int64_t t = 0; t <= b->tmax; ++t)
-            HIP_TRY(launch_batch_step(desc, b->count, b->total_tiles, t, stream), "batch step launch");
+            HIP_TRY(launch_batch_step(desc, b->count, b->total_tiles, t, stream), "batch phase launch");
     }
     HIP_TRY(hipMemcpyAsync(b->hrec, base + b->off_rec, (size_t)b->total_recs * sizeof(prs_stats),
                            hipMemcpyDeviceToHost, stream), "record copy");
@@ -850,21 +964,25 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
     b->ws_bytes = ws_bytes;
     b->off_desc = L.desc;
     b->off_coef = L.coef;
+    b->off_pass = L.pass;
+    b->off_alt = L.alt;
     b->off_part = L.part;
     b->off_rec = L.rec;
     b->off_ctl = L.ctl;
     b->coef_off = L.coef_off;
+    b->pass_off = L.pass_off;
+    b->alt_off = L.alt_off;
     b->part_off = L.part_off;
     b->part_cap = L.part_cap;
     b->rec_off = L.rec_off;
     b->total_recs = L.rec_off[count];
-    b->tmax = 0;
+    b->npasses.assign(count, 0);
     for (int32_t r = 0; r < count; ++r) {
         b->geo.push_back(geometry_of(items[r].p));
         Tiling t = default_tiling(b->geo.back());
-        if (!batch_tiling_supported(b->geo.back(), t)) t.ty = 1;
+        t.ty = 1;
         b->til.push_back(t);
-        b->tmax = std::max(b->tmax, items[r].nsteps);
+        b->tblock.push_back(items[r].p.ndim == 2 ? 2 : 1);
     }
     b->mode = PRS_BATCH_PERSISTENT_GRAPH;
     int khz = 0;
@@ -877,7 +995,7 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
         prs_batch_destroy(b);
         return hip_fail(e, "batch setup");
     }
-    // a step of the largest ensemble takes well under 0.1 s; 5 s means the
+    // a phase of the largest ensemble takes well under 0.1 s; 5 s means the
     // grid is not co-resident
     b->timeout_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 1000ull * 5ull;
     b->dirty = true;
@@ -891,9 +1009,21 @@ prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t
     Tiling t{vec, rows, ty};
     if (!batch_tiling_supported(b->geo[item], t))
         return fail(PRS_EINVAL, "tiling vec=%d rows=%d ty=%d not available in batched runs", vec, rows, ty);
-    if (tile_counts(b->geo[item], t).ntiles > b->part_cap[item])
+    if (batch_tiles_max(b->geo[item], t) > b->part_cap[item])
         return fail(PRS_EINVAL, "tiling has more wave tiles than the workspace holds");
     b->til[item] = t;
+    b->dirty = true;
+    return PRS_OK;
+}
+
+prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass)
+{
+    if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
+    if (steps_per_pass != 1 && steps_per_pass != 2)
+        return fail(PRS_EINVAL, "batched runs use 1 or 2 steps per pass");
+    if (steps_per_pass == 2 && b->items[item].p.ndim != 2)
+        return fail(PRS_EUNSUPPORTED, "two-step passes are implemented for 2D lattices");
+    b->tblock[item] = steps_per_pass;
     b->dirty = true;
     return PRS_OK;
 }
@@ -911,6 +1041,17 @@ prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets)
 {
     if (!b || !offsets) return fail(PRS_EINVAL, "NULL argument");
     for (int32_t r = 0; r <= b->count; ++r) offsets[r] = b->rec_off[r];
+    return PRS_OK;
+}
+
+prs_status prs_batch_state(const prs_batch* b, int32_t item, void** phi, void** dphi)
+{
+    if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
+    const prs_batch_item& it = b->items[item];
+    const std::vector<PassEntry> plan = batch_plan(it, b->tblock[item]);
+    const int64_t np = (int64_t)plan.size();
+    if (phi) *phi = ((np - 1) & 1) ? it.phi_b : it.phi_a;
+    if (dphi) *dphi = it.dphi;
     return PRS_OK;
 }
 
@@ -970,7 +1111,6 @@ void prs_batch_destroy(prs_batch* b)
 
 }  // extern "C"
 
-
 // -------------------------------------------------------------- autotuner --
 //
 // Candidate tilings are timed on the context's own state (saved and restored
@@ -983,7 +1123,7 @@ namespace {
 
 constexpr const char* kTuneVersion = "k1";
 
-std::string tune_key(const prs_params& p, bool batch_set, int tblock)
+std::string tune_key(const prs_params& p, bool batch_set)
 {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -994,19 +1134,19 @@ std::string tune_key(const prs_params& p, bool batch_set, int tblock)
         if (colon != std::string::npos) arch = arch.substr(0, colon);
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|%dD|%lldx%lldx%lld|%s|t%d|%s", arch.c_str(), p.ndim,
+    std::snprintf(buf, sizeof buf, "%s|%dD|%lldx%lldx%lld|%s|%s", arch.c_str(), p.ndim,
                   (long long)p.n[0], (long long)p.n[1], (long long)(p.ndim == 3 ? p.n[2] : 1),
-                  batch_set ? "batch" : "single", tblock, kTuneVersion);
+                  batch_set ? "batch" : "single", kTuneVersion);
     return buf;
 }
 
 struct TuneEntry {
-    int vec, rows, ty;
+    int vec, rows, ty, tb;
     double us;
 };
 
 // The cache is written by tune_write only: one entry per line,
-//   "key": {"vec": V, "rows": R, "ty": T, "us": U},
+//   "key": {"vec": V, "rows": R, "ty": T, "steps_per_pass": P, "us": U},
 std::map<std::string, TuneEntry> tune_read(const char* path)
 {
     std::map<std::string, TuneEntry> m;
@@ -1019,8 +1159,8 @@ std::map<std::string, TuneEntry> tune_read(const char* path)
         const char* q2 = std::strchr(q1 + 1, '"');
         if (!q2) continue;
         TuneEntry e;
-        if (std::sscanf(q2 + 1, ": {\"vec\": %d, \"rows\": %d, \"ty\": %d, \"us\": %lf", &e.vec, &e.rows,
-                        &e.ty, &e.us) == 4)
+        if (std::sscanf(q2 + 1, ": {\"vec\": %d, \"rows\": %d, \"ty\": %d, \"steps_per_pass\": %d, \"us\": %lf",
+                        &e.vec, &e.rows, &e.ty, &e.tb, &e.us) == 5)
             m[std::string(q1 + 1, q2)] = e;
     }
     std::fclose(f);
@@ -1035,8 +1175,9 @@ bool tune_write(const char* path, const std::map<std::string, TuneEntry>& m)
     std::fprintf(f, "{\n");
     size_t i = 0;
     for (const auto& kv : m) {
-        std::fprintf(f, "\"%s\": {\"vec\": %d, \"rows\": %d, \"ty\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
-                     kv.second.vec, kv.second.rows, kv.second.ty, kv.second.us, ++i < m.size() ? "," : "");
+        std::fprintf(f, "\"%s\": {\"vec\": %d, \"rows\": %d, \"ty\": %d, \"steps_per_pass\": %d, \"us\": %.3f}%s\n",
+                     kv.first.c_str(), kv.second.vec, kv.second.rows, kv.second.ty, kv.second.tb, kv.second.us,
+                     ++i < m.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
     std::fclose(f);
@@ -1068,8 +1209,7 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
     prs_status st = validate(p);
     if (st != PRS_OK) return st;
     const auto m = tune_read(cache_path);
-    const int tb = (flags & PRS_TUNE_BATCH) || p->ndim != 2 ? 1 : 2;
-    const auto it = m.find(tune_key(*p, (flags & PRS_TUNE_BATCH) != 0, tb));
+    const auto it = m.find(tune_key(*p, (flags & PRS_TUNE_BATCH) != 0));
     if (it == m.end()) return fail(PRS_ESTATE, "no cached tiling for this lattice");
     if (vec) *vec = it->second.vec;
     if (rows) *rows = it->second.rows;
@@ -1077,16 +1217,105 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
     return PRS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Tunes the reverse-sweep kernel's tiling on scratch buffers (w, mu filled
+// from the current phi; phi^n = the current phi).
+prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, double* best_us)
+{
+    const std::string key = tune_key(c->p, false) + "|adjoint";
+    auto cache = tune_read(cache_path);
+    if (!(flags & PRS_TUNE_FORCE)) {
+        const auto it = cache.find(key);
+        if (it != cache.end() &&
+            prs_set_adjoint_tiling(c, it->second.vec, it->second.rows, it->second.ty) == PRS_OK) {
+            if (best_us) *best_us = it->second.us;
+            return PRS_OK;
+        }
+    }
+    const std::vector<Tiling> cand = tune_candidates(c->geo, false);
+    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    float* buf = nullptr;
+    double* gacc = nullptr;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), 3 * bytes), "tuner allocation");
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&gacc), (size_t)c->partial_cap * sizeof(double));
+    float* w0 = buf;
+    float* w1 = buf + sites_of(c->p);
+    float* mu = buf + 2 * sites_of(c->p);
+    if (e == hipSuccess) e = hipMemcpyAsync(w0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(mu, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const double sites = (double)sites_of(c->p);
+    const int timed = (int)std::max(4.0, std::min(40.0, 4e9 / std::max(sites, 1.0)));
+    const char* env = std::getenv("PRS_TUNE_LOG");
+    const bool log_each = env && env[0] == '1';
+    Tiling best = c->adj_til;
+    double best_t = 1e300;
+    for (const Tiling& t : cand) {
+        if (e != hipSuccess) break;
+        if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
+        float* a = w0;
+        float* b = w1;
+        auto run = [&](int steps) -> hipError_t {
+            for (int k = 0; k < steps; ++k) {
+                hipError_t err = launch_adjoint(c->geo, t, a, b, mu, c->phi[c->cur], gacc,
+                                                adj_coef(c, c->step, false), c->stream);
+                if (err != hipSuccess) return err;
+                std::swap(a, b);
+            }
+            return hipSuccess;
+        };
+        e = run(2);
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = run(timed);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double per_step = ms / timed;
+        if (e == hipSuccess && log_each)
+            std::fprintf(stderr, "prs_autotune(adjoint): vec=%d rows=%d ty=%d %.2f us/step\n", t.vec, t.rows, t.ty,
+                         per_step * 1e3);
+        if (e == hipSuccess && per_step < best_t) {
+            best_t = per_step;
+            best = t;
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    (void)hipFree(gacc);
+    if (e != hipSuccess) return hip_fail(e, "adjoint autotune");
+    c->adj_til = best;
+    if (best_us) *best_us = best_t * 1e3;
+    if (cache_path && cache_path[0]) {
+        cache[key] = TuneEntry{best.vec, best.rows, best.ty, 1, best_t * 1e3};
+        if (!tune_write(cache_path, cache)) return fail(PRS_EINVAL, "cannot write tuning cache %s", cache_path);
+    }
+    return PRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, double* best_us)
 {
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (flags & PRS_TUNE_ADJOINT) return autotune_adjoint(c, cache_path, flags, best_us);
     const bool batch_set = (flags & PRS_TUNE_BATCH) != 0;
-    const std::string key = tune_key(c->p, batch_set, batch_set ? 1 : c->tblock);
+    const std::string key = tune_key(c->p, batch_set);
     auto cache = tune_read(cache_path);
     if (!(flags & PRS_TUNE_FORCE)) {
         const auto it = cache.find(key);
         if (it != cache.end()) {
             prs_status st = prs_set_tiling(c, it->second.vec, it->second.rows, it->second.ty);
+            if (st == PRS_OK && !batch_set && it->second.tb > 1) st = prs_set_time_blocking(c, it->second.tb);
             if (st == PRS_OK) {
                 if (best_us) *best_us = it->second.us;
                 return PRS_OK;
@@ -1115,53 +1344,62 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     Tiling best = c->til;
     double best_t = 1e300;
     prs_status result = PRS_OK;
-    // with two-step passes enabled, a candidate is timed on passes (two
-    // steps each) and its per-step time is half a pass
-    const bool pairs = !batch_set && c->tblock == 2 && c->pi_alt != nullptr;
-    const int per = pairs ? 2 : 1;
+    // 2D single runs also choose the steps per pass: a candidate with T > 1
+    // is timed on T-step passes and its per-step time is a pass over T
+    int per = 1;
     auto run = [&](const Tiling& t, int passes) -> hipError_t {
         float* pa = c->pi;
         float* pb = c->pi_alt;
         for (int k = 0; k < passes; ++k) {
             hipError_t err;
-            if (pairs) {
-                err = launch_pair2d(c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], pa, pb,
-                                    coef_for(c, n0 + 2 * k), coef_for(c, n0 + 2 * k + 1), false, nullptr,
-                                    DiagCoef{}, c->stream);
+            if (per > 1) {
+                StepCoef kc[kMaxPassSteps];
+                for (int i = 0; i < per; ++i) kc[i] = coef_for(c, n0 + per * k + i);
+                err = launch_tb2d(per, c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], pa, pb, kc, false, nullptr,
+                                  DiagCoef{}, c->stream);
                 std::swap(pa, pb);
             } else {
-                err = launch_step(c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi, coef_for(c, n0 + k),
-                                  true, false, nullptr, DiagCoef{}, c->stream);
+                err = launch_step(c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], c->pi, c->pi,
+                                  coef_for(c, n0 + k), true, false, nullptr, DiagCoef{}, c->stream);
             }
             if (err != hipSuccess) return err;
             c->cur ^= 1;
         }
         return hipSuccess;
     };
+    const int max_T = (!batch_set && c->pi_alt != nullptr) ? kMaxPassSteps : 1;
+    int best_T = c->tblock;
     e = hipMemcpyAsync(save_phi, c->phi[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(save_pi, c->pi, bytes, hipMemcpyDeviceToDevice, c->stream);
-    for (const Tiling& t : cand) {
-        if (e != hipSuccess) break;
-        if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
-        e = run(t, 2);
-        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        if (e == hipSuccess) e = run(t, timed);
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        const double per_step = ms / ((double)timed * per);
-        if (e == hipSuccess && log_each)
-            std::fprintf(stderr, "prs_autotune: vec=%d rows=%d ty=%d steps/pass=%d %.2f us/step\n", t.vec, t.rows,
-                         t.ty, per, per_step * 1e3);
-        if (e == hipSuccess && per_step < best_t) {
-            best_t = per_step;
-            best = t;
+    for (int T = 1; T <= max_T; ++T) {
+        per = T;
+        for (const Tiling& t : cand) {
+            if (e != hipSuccess) break;
+            if (T > 1 && t.ty != 1) continue;
+            if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
+            if (T > 1 && tb_tiles(c->geo, t, T) > c->partial_cap) continue;
+            e = run(t, 2);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = run(t, timed);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            const double per_step = ms / ((double)timed * per);
+            if (e == hipSuccess && log_each)
+                std::fprintf(stderr, "prs_autotune: vec=%d rows=%d ty=%d steps/pass=%d %.2f us/step\n", t.vec,
+                             t.rows, t.ty, per, per_step * 1e3);
+            if (e == hipSuccess && per_step < best_t) {
+                best_t = per_step;
+                best = t;
+                best_T = T;
+            }
+            // restore the state for the next candidate (and for the caller)
+            c->cur = cur0;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->phi[cur0], save_phi, bytes, hipMemcpyDeviceToDevice, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(c->pi, save_pi, bytes, hipMemcpyDeviceToDevice, c->stream);
         }
-        // restore the state for the next candidate (and for the caller)
-        c->cur = cur0;
-        if (e == hipSuccess) e = hipMemcpyAsync(c->phi[cur0], save_phi, bytes, hipMemcpyDeviceToDevice, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(c->pi, save_pi, bytes, hipMemcpyDeviceToDevice, c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) result = hip_fail(e, "autotune");
@@ -1173,9 +1411,10 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     c->step = n0;
     if (result != PRS_OK) return result;
     c->til = best;
+    if (!batch_set) c->tblock = best_T;
     if (best_us) *best_us = best_t * 1e3;
     if (cache_path && cache_path[0]) {
-        cache[key] = TuneEntry{best.vec, best.rows, best.ty, best_t * 1e3};
+        cache[key] = TuneEntry{best.vec, best.rows, best.ty, batch_set ? 1 : best_T, best_t * 1e3};
         if (!tune_write(cache_path, cache)) return fail(PRS_EINVAL, "cannot write tuning cache %s", cache_path);
     }
     return PRS_OK;

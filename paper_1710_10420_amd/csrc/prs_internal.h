@@ -56,18 +56,22 @@ TileCounts tile_counts(const Geometry& g, const Tiling& t);
 bool tiling_supported(const Geometry& g, const Tiling& t);
 
 // One fused step over the whole lattice: reads phi_in and pi, writes
-// phi_out and pi (in place) when update; writes one WavePartial per wave tile
-// when diag.  update == false && diag == true computes the diagnostics only.
+// phi_out and pi_out (pi_out == pi updates in place) when update; writes one
+// WavePartial per wave tile when diag.  update == false && diag == true
+// computes the diagnostics only.
 hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       float* pi, const StepCoef& k, bool update, bool diag,
+                       const float* pi, float* pi_out, const StepCoef& k, bool update, bool diag,
                        WavePartial* partials, const DiagCoef& dc, hipStream_t s);
 
-// Two steps n, n+1 of a 2D lattice in one pass (temporal blocking): reads
-// phi_in, pi_in; writes phi^{n+2} to phi_out and phi_dot^{n+3/2} to pi_out
+// T = 2..4 steps n .. n+T-1 of a 2D lattice in one pass (temporal blocking)
+// with overlapped wave tiles; k holds the T step coefficients.  Reads phi_in
+// and pi_in, writes phi^{n+T} to phi_out and phi_dot^{n+T-1/2} to pi_out
 // (pi_out != pi_in).  With diag, the partials are those of the input state.
-hipError_t launch_pair2d(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                         const float* pi_in, float* pi_out, const StepCoef& k1, const StepCoef& k2,
-                         bool diag, WavePartial* partials, const DiagCoef& dc, hipStream_t s);
+hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
+                       WavePartial* partials, const DiagCoef& dc, hipStream_t s);
+// Number of wave tiles (and partials) of a T-step pass.
+int64_t tb_tiles(const Geometry& g, const Tiling& t, int T);
 
 // Reduces `count` partials in a fixed order into one record at `rec`.
 hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,
@@ -97,10 +101,14 @@ hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s);
 // Batched ensemble (descriptor layout is private to the kernel file).
 size_t batch_desc_bytes();
 int batch_ctl_bytes();
+// passes: device array of int4 (first step, steps 0/1/2, record index or -1,
+// phi_dot read from pi_alt) with npasses entries (the last: diagnostics only).
 void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0, float* phi1, float* pi,
-                     const float2* coef, WavePartial* part0, WavePartial* part1, prs_stats* recs,
-                     int64_t nsteps, int64_t tile_base, int64_t nrec_regular, double eta0, double deta,
-                     double area_scale, int diag_every, const StepCoef& k, const DiagCoef& dc);
+                     float* pi_alt, const float2* coef, const void* passes, int64_t npasses,
+                     WavePartial* part0, WavePartial* part1, prs_stats* recs, int64_t tile_base,
+                     double eta0, double deta, double area_scale, const StepCoef& k, const DiagCoef& dc);
+// Tiles reserved per phase for one realisation.
+int64_t batch_tiles_max(const Geometry& g, const Tiling& t);
 bool batch_tiling_supported(const Geometry& g, const Tiling& t);
 hipError_t batch_max_blocks(int* blocks);
 hipError_t batch_clock_rate_khz(int* khz);

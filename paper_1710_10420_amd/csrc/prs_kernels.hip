@@ -34,6 +34,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "prs_internal.h"
@@ -198,7 +199,8 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 struct StepArgs {
     const float* phi_in;
     float* phi_out;
-    float* pi;
+    const float* pi;       // phi_dot^{n-1/2} (read)
+    float* pi_out;         // phi_dot^{n+1/2} (written; may equal pi)
     WavePartial* partials;
     int64_t nx, Q, M;
     int64_t tiles_x, tiles_q, ntiles;
@@ -402,7 +404,7 @@ __device__ __forceinline__ void step_plane(const StepArgs& A, const TileSetup<TY
     float left[TY], right[TY];
     x_neighbours<VEC, TY>(Pc, S, left, right);
     float* phi_out = A.phi_out + s * S.pstride;
-    float* pi_out = A.pi + s * S.pstride;
+    float* pi_out = A.pi_out + s * S.pstride;
 #pragma unroll
     for (int t = 0; t < TY; ++t) {
         if (t >= S.nvalid) continue;
@@ -742,35 +744,247 @@ hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s)
 }
 
 
+// ----------------------------------------- T steps per HBM pass (2D) --------
+//
+// Temporal blocking: T = 2, 3 or 4 leapfrog steps per pass over HBM, with
+// overlapped wave tiles.  A wave's 64 lanes hold 64*VEC consecutive sites; the first and
+// last H = ceil(T/VEC) lanes are halo lanes whose sites belong to the
+// neighbouring tiles.  Level k (step n+k-1) is computed for every lane from
+// level k-1 of the lanes on either side (plain shuffles), so the sites within
+// k of the wave's ends become stale at level k; halo lanes are never stored
+// and H*VEC >= T keeps every owned site exact.  Along y the levels are
+// pipelined inside the march: at iteration y level k computes row y-k+1 from
+// level k-1 rows y-k .. y-k+2, so level k needs T-k extra rows on each side
+// of the tile.  Only level T is written.  All levels use the single-step
+// arithmetic, so the result is bitwise that of T single steps.
+
+__device__ __forceinline__ int64_t wrap_any(int64_t v, int64_t M)
+{
+    while (v < 0) v += M;
+    while (v >= M) v -= M;
+    return v;
+}
+
+template <int T>
+struct TBArgs {
+    const float* phi_in;
+    float* phi_out;
+    const float* pi_in;
+    float* pi_out;
+    WavePartial* partials;
+    int64_t nx, ny;
+    int64_t tiles_x, ntiles;
+    int64_t rows;
+    StepCoef k[T];
+    DiagCoef dc;
+};
+
+__device__ __forceinline__ int64_t tb_owned_width_d(int vec, int T)
+{
+    const int H = (T + vec - 1) / vec;
+    return (int64_t)(kWave - 2 * H) * vec;
+}
+
+template <int VEC, int T>
+struct TBState {
+    float in[4][VEC];          // phi^n rows, ring over the march
+    float pin[2][VEC];         // phi_dot^{n-1/2} rows
+    float lv[T][4][VEC];       // level k rows (k = 1 .. T-1 used)
+    float pl[T][2][VEC];       // level k phi_dot rows
+};
+
+struct TBLane {
+    int64_t x0;                // unwrapped first site of this lane
+    uint32_t xw;               // wrapped into [0, nx)
+    bool store;                // owned lane inside the lattice
+    int64_t s0, s1;
+    uint32_t nx;
+    int64_t M;
+};
+
+template <int VEC>
+__device__ __forceinline__ void tb_load(const float* __restrict__ f, int64_t y, const TBLane& L,
+                                        float (&v)[VEC])
+{
+    load_vec<VEC>(f + wrap_any(y, L.M) * (int64_t)L.nx + L.xw, v);
+}
+
+template <int VEC, int T, bool DIAG, int U>
+__device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int64_t y,
+                                        TBState<VEC, T>& S, DiagAcc& acc)
+{
+    const int64_t ylast = L.s1 + T - 2;   // last iteration
+    // prefetch phi^n row y+2 and phi_dot row y+1
+    if (y + 2 <= L.s1 + T - 1) tb_load<VEC>(A.phi_in, y + 2, L, S.in[(U + 2) & 3]);
+    if (y + 1 <= ylast) tb_load<VEC>(A.pi_in, y + 1, L, S.pin[(U + 1) & 1]);
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        const int64_t r = y - k + 1;                     // row of level k
+        if (r < L.s0 - (T - k) || r > L.s1 - 1 + (T - k)) continue;
+        const float* cm;
+        const float* cc;
+        const float* cp;
+        const float* pp;
+        if (k == 1) {
+            cm = S.in[(U + 3) & 3];
+            cc = S.in[U & 3];
+            cp = S.in[(U + 1) & 3];
+            pp = S.pin[U & 1];
+        } else {
+            cm = S.lv[k - 1][(U + 2) & 3];
+            cc = S.lv[k - 1][(U + 3) & 3];
+            cp = S.lv[k - 1][U & 3];
+            pp = S.pl[k - 1][(U + 1) & 1];
+        }
+        float left = __shfl_up(cc[VEC - 1], 1, kWave);
+        float right = __shfl_down(cc[0], 1, kWave);
+        float out_phi[VEC], out_pi[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = cc[j];
+            const float xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
+            const float xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
+            const float lap = lap2(c, xm, xp, cm[j], cp[j], A.k[k - 1].inv_dx2);
+            kick_drift(c, lap, pp[j], A.k[k - 1], out_pi[j], out_phi[j]);
+            if constexpr (DIAG) {
+                if (k == 1 && L.store && r >= L.s0 && r < L.s1) {
+                    const float nm[2] = {xm, cm[j]};
+                    const float np[2] = {xp, cp[j]};
+                    site_diag<2>(c, pp[j], nm, np, A.dc, acc);
+                }
+            }
+        }
+        if (k < T) {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.lv[k < T ? k : 0][U & 3][j] = out_phi[j];
+                S.pl[k < T ? k : 0][U & 1][j] = out_pi[j];
+            }
+        } else if (L.store && r >= L.s0 && r < L.s1) {
+            const int64_t off = r * (int64_t)L.nx + L.xw;
+            store_vec<VEC>(A.phi_out + off, out_phi);
+            store_vec<VEC>(A.pi_out + off, out_pi);
+        }
+    }
+}
+
+// One wave's tile of a T-step pass; `tile` must be below A.ntiles and
+// wave-uniform.
+template <int VEC, int T, bool DIAG>
+__device__ __forceinline__ void tb_tile(const TBArgs<T>& A, int64_t tile)
+{
+    constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
+    constexpr int W = (kWave - 2 * H) * VEC;       // owned sites per wave
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t tx = tl % (uint32_t)A.tiles_x;
+    const uint32_t ts = tl / (uint32_t)A.tiles_x;
+    TBLane L;
+    L.nx = (uint32_t)A.nx;
+    L.M = A.ny;
+    L.x0 = (int64_t)tx * W + (int64_t)(lane - H) * VEC;
+    L.xw = (uint32_t)wrap_any(L.x0, L.nx);
+    L.store = lane >= H && lane < kWave - H && L.x0 < (int64_t)L.nx;
+    L.s0 = (int64_t)ts * A.rows;
+    L.s1 = (L.s0 + A.rows) < A.ny ? (L.s0 + A.rows) : A.ny;
+
+    TBState<VEC, T> S;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            S.in[a][j] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < T; ++k) S.lv[k][a][j] = 0.0f;
+        }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            S.pin[a][j] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < T; ++k) S.pl[k][a][j] = 0.0f;
+        }
+
+    // first iteration y0 = s0-T+1 needs phi^n rows y0-1, y0, y0+1 and phi_dot row y0
+    const int64_t y0 = L.s0 - T + 1;
+    tb_load<VEC>(A.phi_in, y0 - 1, L, S.in[3]);
+    tb_load<VEC>(A.phi_in, y0, L, S.in[0]);
+    tb_load<VEC>(A.phi_in, y0 + 1, L, S.in[1]);
+    tb_load<VEC>(A.pi_in, y0, L, S.pin[0]);
+
+    DiagAcc acc;
+    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
+    acc.walls = acc.nonfinite = 0u;
+    acc.area = acc.ek = 0.0;
+
+    const int64_t ylast = L.s1 + T - 2;
+    for (int64_t y = y0; y <= ylast; y += 4) {
+        tb_iter<VEC, T, DIAG, 0>(A, L, y, S, acc);
+        if (y + 1 > ylast) break;
+        tb_iter<VEC, T, DIAG, 1>(A, L, y + 1, S, acc);
+        if (y + 2 > ylast) break;
+        tb_iter<VEC, T, DIAG, 2>(A, L, y + 2, S, acc);
+        if (y + 3 > ylast) break;
+        tb_iter<VEC, T, DIAG, 3>(A, L, y + 3, S, acc);
+    }
+
+    if constexpr (DIAG) {
+        WavePartial w;
+        w.links[0] = wave_sum_u32(acc.links[0]);
+        w.links[1] = wave_sum_u32(acc.links[1]);
+        w.links[2] = 0u;
+        w.walls = wave_sum_u32(acc.walls);
+        w.nonfinite = wave_sum_u32(acc.nonfinite);
+        w.pad = 0u;
+        w.area = wave_sum_f64(acc.area);
+        w.ek = wave_sum_f64(acc.ek);
+        if (lane == 0) A.partials[tile] = w;
+    }
+}
+
+template <int VEC, int T, bool DIAG>
+__global__ __launch_bounds__(kBlock) void k_tb2d(TBArgs<T> A)
+{
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    tb_tile<VEC, T, DIAG>(A, tile);
+}
+
 // ------------------------------------------------------- batched ensemble --
 //
 // Many independent realisations (different sizes, dimensions, eras, wall
-// widths and step counts) advance together.  Step t's work list is every
-// wave tile of every realisation with t <= S_r: a realisation steps while
-// t < S_r (fused diagnostics when t % K_r == 0) and gets a diagnostics-only
-// pass of its final state at t == S_r.  Each tile runs step_tile, the same
-// code as a single run, so a realisation's fields and records are bitwise
-// those of the same realisation run alone with the same tiling.
+// widths and step counts) advance together.  Each realisation carries a
+// table of passes made on the host: a pass advances 1 or 2 steps (two-step
+// passes for 2D lattices, never with a recorded state inside), may record the
+// diagnostics of its input state, and the last entry is a diagnostics-only
+// pass over the final state.  Phase t runs pass t of every realisation that
+// has one; each tile runs step_tile or tb_tile, the code of a single run, so
+// a realisation's fields and records are bitwise those of the same
+// realisation run alone with the same tiling and steps per pass.
 //
 // Persistent mode: one launch whose workgroups stay resident for the whole
 // ensemble; a wave walks the global tile list with stride = number of waves,
-// then all workgroups meet at a software grid barrier before step t+1.  The
-// records of step t are reduced by one wave per realisation right after
-// that barrier.  The barrier's wait is bounded: if it does not complete within
-// the time limit (workgroups not co-resident), an error flag is raised and
-// every workgroup leaves, so the kernel always finishes.
+// then all workgroups meet at a software grid barrier before the next phase.
+// The records of phase t are reduced by one wave per realisation right after
+// that barrier.  The barrier's wait is bounded: if it does not complete
+// within the time limit (workgroups not co-resident), an error flag is raised
+// and every workgroup leaves, so the kernel always finishes.
 
 struct BatchDesc {
     StepArgs A;              // geometry, tiling and constant coefficients
-    float* phi[2];           // phi^n lives in phi[n & 1]
+    float* phi[2];           // phase t reads phi[t & 1]
+    float* pi_alt;           // second phi_dot buffer for two-step passes (2D)
     const float2* coef;      // (a_n, b_n) for n = 0 .. nsteps-1
+    const int4* passes;      // (first step, steps (0: diagnostics only), record or -1, phi_dot in pi_alt)
     WavePartial* part[2];    // alternate record partial buffers
-    prs_stats* recs;         // nrec_regular + 1 records
-    int64_t nsteps;
+    prs_stats* recs;
+    int64_t npasses;         // including the final diagnostics-only pass
     int64_t tile_base;       // first global tile of this realisation
-    int64_t nrec_regular;    // records of states n < nsteps
+    int64_t tiles_max;       // tiles reserved per phase (the larger pass kind)
+    int64_t tiles_multi;     // tiles of a two-step pass (2D)
     double eta0, deta, area_scale;
-    int32_t ndim, vec, ty, diag_every;
+    int32_t ndim, vec, ty, pad;
 };
 
 struct BatchCtl {
@@ -779,20 +993,6 @@ struct BatchCtl {
     int err;
     int pad;
 };
-
-// Record index of state t of realisation d, if it has one.
-__device__ __forceinline__ bool record_index(const BatchDesc& d, int64_t t, int64_t& j)
-{
-    if (t == d.nsteps) {
-        j = d.nrec_regular;
-        return true;
-    }
-    if (t < d.nsteps && d.diag_every > 0 && t % d.diag_every == 0) {
-        j = t / d.diag_every;
-        return true;
-    }
-    return false;
-}
 
 __device__ __forceinline__ int find_real(const BatchDesc* __restrict__ D, int nreal, int64_t tile)
 {
@@ -815,8 +1015,8 @@ __device__ __forceinline__ void tile_mode(const StepArgs& A, int64_t tile, bool 
 
 // Tilings available inside the batched kernels (every instance is inlined
 // into them, so the set is kept small to bound register pressure).
-__device__ __forceinline__ void dispatch_tile(int ndim, int vec, int ty, const StepArgs& A,
-                                              int64_t tile, bool update, bool diag)
+__device__ __forceinline__ void dispatch_tile(int ndim, int vec, const StepArgs& A, int64_t tile,
+                                              bool update, bool diag)
 {
     if (ndim == 2) {
         if (vec == 4) tile_mode<2, 4, 1>(A, tile, update, diag);
@@ -829,37 +1029,82 @@ __device__ __forceinline__ void dispatch_tile(int ndim, int vec, int ty, const S
     }
 }
 
-// Work of global tile i at step t.
+__device__ __forceinline__ void dispatch_pair(int vec, const TBArgs<2>& A, int64_t tile, bool diag)
+{
+    if (vec == 4) {
+        if (diag) tb_tile<4, 2, true>(A, tile);
+        else tb_tile<4, 2, false>(A, tile);
+    } else if (vec == 2) {
+        if (diag) tb_tile<2, 2, true>(A, tile);
+        else tb_tile<2, 2, false>(A, tile);
+    } else {
+        if (diag) tb_tile<1, 2, true>(A, tile);
+        else tb_tile<1, 2, false>(A, tile);
+    }
+}
+
+// Work of global tile i in phase t.
 __device__ __forceinline__ void batch_tile(const BatchDesc* __restrict__ Dd, int nreal, int64_t i,
                                            int64_t t)
 {
     const BatchDesc& d = Dd[find_real(Dd, nreal, i)];
-    if (t > d.nsteps) return;
-    const bool update = t < d.nsteps;
-    int64_t j = 0;
-    const bool diag = record_index(d, t, j);
+    if (t >= d.npasses) return;
+    const int4 ps = d.passes[t];
+    const int64_t local = i - d.tile_base;
+    const bool diag = ps.z >= 0;
+    const float* pin = ps.w ? d.pi_alt : d.A.pi_out;
+    if (ps.y == 2) {
+        if (local >= d.tiles_multi) return;
+        TBArgs<2> A;
+        A.phi_in = d.phi[t & 1];
+        A.phi_out = d.phi[(t + 1) & 1];
+        A.pi_in = pin;
+        A.pi_out = ps.w ? d.A.pi_out : d.pi_alt;
+        A.partials = diag ? d.part[ps.z & 1] : nullptr;
+        A.nx = d.A.nx;
+        A.ny = d.A.M;
+        A.tiles_x = (d.A.nx + tb_owned_width_d(d.vec, 2) - 1) / tb_owned_width_d(d.vec, 2);
+        A.ntiles = d.tiles_multi;
+        A.rows = d.A.rows;
+        A.k[0] = d.A.k;
+        A.k[1] = d.A.k;
+        const float2 c0 = d.coef[ps.x], c1 = d.coef[ps.x + 1];
+        A.k[0].a = c0.x;
+        A.k[0].b = c0.y;
+        A.k[1].a = c1.x;
+        A.k[1].b = c1.y;
+        A.dc = d.A.dc;
+        dispatch_pair(d.vec, A, local, diag);
+        return;
+    }
+    if (local >= d.A.ntiles) return;
     StepArgs A = d.A;
     A.phi_in = d.phi[t & 1];
     A.phi_out = d.phi[(t + 1) & 1];
+    A.pi = pin;
+    A.pi_out = const_cast<float*>(pin);
+    const bool update = ps.y == 1;
     if (update) {
-        const float2 c = d.coef[t];
+        const float2 c = d.coef[ps.x];
         A.k.a = c.x;
         A.k.b = c.y;
     }
-    A.partials = diag ? d.part[j & 1] : nullptr;
-    dispatch_tile(d.ndim, d.vec, d.ty, A, i - d.tile_base, update, diag);
+    A.partials = diag ? d.part[ps.z & 1] : nullptr;
+    dispatch_tile(d.ndim, d.vec, A, local, update, diag);
 }
 
-// Records of state t, one wave per realisation (waves w, w+nw, ...).
+// Records of phase t, one wave per realisation (waves w, w+nw, ...).
 __device__ __forceinline__ void batch_records(const BatchDesc* __restrict__ Dd, int nreal, int64_t t,
                                               int64_t wave, int64_t nwaves)
 {
     for (int64_t r = wave; r < nreal; r += nwaves) {
         const BatchDesc& d = Dd[r];
-        int64_t j;
-        if (record_index(d, t, j))
-            finalize_wave(d.part[j & 1], d.A.ntiles, d.recs + j, t, d.eta0 + (double)t * d.deta,
-                          d.area_scale);
+        if (t >= d.npasses) continue;
+        const int4 ps = d.passes[t];
+        if (ps.z < 0) continue;
+        const int64_t count = ps.y == 2 ? d.tiles_multi : d.A.ntiles;
+        finalize_wave(d.part[ps.z & 1], count, d.recs + ps.z, ps.x, d.eta0 + (double)ps.x * d.deta,
+                      d.area_scale);
     }
 }
 
@@ -907,7 +1152,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(const BatchDesc* __
                                                               int64_t tmax, BatchCtl* ctl,
                                                               uint64_t timeout)
 {
-    const int64_t wave = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
+    const int64_t wave = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     unsigned gen = 0;
     for (int64_t t = 0; t <= tmax + 1; ++t) {
@@ -919,12 +1164,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(const BatchDesc* __
     }
 }
 
-// Fallback without a resident grid: one launch per step over all tiles,
-// then one launch for that step's records.
+// Fallback without a resident grid: one launch per phase over all tiles,
+// then one launch for that phase's records.
 __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchDesc* __restrict__ Dd, int nreal,
                                                         int64_t total_tiles, int64_t t)
 {
-    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
+    const int64_t i = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     if (i >= total_tiles) return;
     batch_tile(Dd, nreal, i, t);
 }
@@ -932,7 +1177,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchDesc* __restri
 __global__ __launch_bounds__(kBlock) void k_batch_records(const BatchDesc* __restrict__ Dd, int nreal,
                                                            int64_t t)
 {
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int64_t wave = uniform64((int64_t)blockIdx.x * kWavesPerBlock + wave_in_block());
     batch_records(Dd, nreal, t, wave, (int64_t)gridDim.x * kWavesPerBlock);
 }
 
@@ -949,265 +1194,6 @@ __global__ void k_batch_reset(BatchCtl* ctl)
         ctl->gen = 0u;
         ctl->err = 0;
         ctl->pad = 0;
-    }
-}
-
-
-// ------------------------------------------------ two steps per HBM pass --
-//
-// 2D kernel that advances phi^n -> phi^{n+2} in one pass (temporal blocking).
-// While a wave marches along y, level 1 computes phi^{n+1}, phi_dot^{n+1/2}
-// of row y from the phi^n rows y-1..y+1 held in registers, and level 2 then
-// computes phi^{n+2}, phi_dot^{n+3/2} of row y-1 from the level-1 rows
-// y-2..y.  Only level 2 is stored, so each value crosses HBM about once per
-// two steps.  Level 2 needs level-1 values one site beyond the wave on each
-// side: the wave's first lane and its last active lane evaluate that extra
-// site (from two halo scalars of phi^n and one of phi_dot per row), and the
-// tile evaluates level 1 on one extra row above and below.  Every site uses
-// the same kick_drift/lap2 sequence as the single-step kernel, so the result
-// is bitwise that of two single steps.  phi_dot is read from one buffer and
-// written to another (a neighbouring tile may still read the old values).
-// Diagnostics, when requested, are those of the input state (level 1).
-
-template <int VEC>
-struct PairRow {          // one phi^n row: values plus two halo scalars per side
-    float v[VEC];
-    float l1, l2;         // phi at x0-1, x0-2 (first lane)
-    float r1, r2;         // phi at x0+VEC, x0+VEC+1 (last active lane)
-};
-
-template <int VEC>
-struct PairPi {           // phi_dot^{n-1/2} of one row plus the edge sites
-    float v[VEC];
-    float l, r;
-};
-
-template <int VEC>
-struct PairU {            // level-1 phi^{n+1} of one row plus the edge sites
-    float v[VEC];
-    float l, r;
-};
-
-struct PairArgs {
-    const float* phi_in;
-    float* phi_out;
-    const float* pi_in;
-    float* pi_out;
-    WavePartial* partials;
-    int64_t nx, ny;
-    int64_t tiles_x, ntiles;
-    int64_t rows;
-    StepCoef k1, k2;      // coefficients of steps n and n+1
-    DiagCoef dc;
-};
-
-struct PairLane {
-    uint32_t x0, xl1, xl2, xr1, xr2;
-    bool active, first, last;
-    int64_t s0, s1, M;
-    uint32_t nx;
-};
-
-__device__ __forceinline__ int64_t wrap_any(int64_t v, int64_t M)
-{
-    while (v < 0) v += M;
-    while (v >= M) v -= M;
-    return v;
-}
-
-template <int VEC>
-__device__ __forceinline__ void pair_load_row(const float* __restrict__ f, int64_t y, const PairLane& L,
-                                              PairRow<VEC>& R)
-{
-    const float* row = f + wrap_any(y, L.M) * (int64_t)L.nx;
-    if (L.active) load_vec<VEC>(row + L.x0, R.v);
-    if (L.first) {
-        R.l1 = row[L.xl1];
-        R.l2 = row[L.xl2];
-    }
-    if (L.last) {
-        R.r1 = row[L.xr1];
-        R.r2 = row[L.xr2];
-    }
-}
-
-template <int VEC>
-__device__ __forceinline__ void pair_load_pi(const float* __restrict__ f, int64_t y, const PairLane& L,
-                                             PairPi<VEC>& P)
-{
-    const float* row = f + wrap_any(y, L.M) * (int64_t)L.nx;
-    if (L.active) load_vec<VEC>(row + L.x0, P.v);
-    if (L.first) P.l = row[L.xl1];
-    if (L.last) P.r = row[L.xr1];
-}
-
-template <int VEC>
-__device__ __forceinline__ void pair_zero(PairRow<VEC>& R)
-{
-#pragma unroll
-    for (int j = 0; j < VEC; ++j) R.v[j] = 0.0f;
-    R.l1 = R.l2 = R.r1 = R.r2 = 0.0f;
-}
-
-template <int VEC>
-__device__ __forceinline__ void pair_zero(PairPi<VEC>& P)
-{
-#pragma unroll
-    for (int j = 0; j < VEC; ++j) P.v[j] = 0.0f;
-    P.l = P.r = 0.0f;
-}
-
-template <int VEC>
-__device__ __forceinline__ void pair_zero(PairU<VEC>& U)
-{
-#pragma unroll
-    for (int j = 0; j < VEC; ++j) U.v[j] = 0.0f;
-    U.l = U.r = 0.0f;
-}
-
-// Iteration y of the pair march.  In: phi^n rows y-1 (Pm), y (Pc), y+1 (Pn),
-// phi_dot^{n-1/2} row y (pic), level-1 rows y-2 (Ua), y-1 (Ub) and
-// phi_dot^{n+1/2} row y-1 (p1b).  Out: the prefetch of phi^n row y+2 (Pnn)
-// and phi_dot row y+1 (pin), level-1 row y (Uc, p1c), and, for y-1 inside the
-// tile, the stored phi^{n+2}, phi_dot^{n+3/2} of row y-1.
-template <int VEC, bool DIAG>
-__device__ __forceinline__ void pair_iter(const PairArgs& A, const PairLane& L, int64_t y,
-                                          const PairRow<VEC>& Pm, const PairRow<VEC>& Pc,
-                                          const PairRow<VEC>& Pn, PairRow<VEC>& Pnn,
-                                          const PairPi<VEC>& pic, PairPi<VEC>& pin,
-                                          const PairU<VEC>& Ua, const PairU<VEC>& Ub, PairU<VEC>& Uc,
-                                          const float (&p1b)[VEC], float (&p1c)[VEC], DiagAcc& acc)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    if (y + 1 <= L.s1) {
-        pair_load_row<VEC>(A.phi_in, y + 2, L, Pnn);
-        pair_load_pi<VEC>(A.pi_in, y + 1, L, pin);
-    }
-    // level 1: row y, step n
-    float left = __shfl_up(Pc.v[VEC - 1], 1, kWave);
-    float right = __shfl_down(Pc.v[0], 1, kWave);
-    if (lane == 0) left = Pc.l1;
-    if (L.last) right = Pc.r1;
-    const bool inside = y >= L.s0 && y < L.s1;
-#pragma unroll
-    for (int j = 0; j < VEC; ++j) {
-        const float c = Pc.v[j];
-        const float xm = j > 0 ? Pc.v[j > 0 ? j - 1 : 0] : left;
-        const float xp = j < VEC - 1 ? Pc.v[j < VEC - 1 ? j + 1 : j] : right;
-        const float lap = lap2(c, xm, xp, Pm.v[j], Pn.v[j], A.k1.inv_dx2);
-        kick_drift(c, lap, pic.v[j], A.k1, p1c[j], Uc.v[j]);
-        if constexpr (DIAG) {
-            if (inside && L.active) {
-                const float nm[2] = {xm, Pm.v[j]};
-                const float np[2] = {xp, Pn.v[j]};
-                site_diag<2>(c, pic.v[j], nm, np, A.dc, acc);
-            }
-        }
-    }
-    {   // level-1 sites one beyond the wave (first lane: x0-1; last lane: x0+VEC)
-        float pl, pr;
-        const float lapl = lap2(Pc.l1, Pc.l2, Pc.v[0], Pm.l1, Pn.l1, A.k1.inv_dx2);
-        kick_drift(Pc.l1, lapl, pic.l, A.k1, pl, Uc.l);
-        const float lapr = lap2(Pc.r1, Pc.v[VEC - 1], Pc.r2, Pm.r1, Pn.r1, A.k1.inv_dx2);
-        kick_drift(Pc.r1, lapr, pic.r, A.k1, pr, Uc.r);
-    }
-    // level 2: row y-1, step n+1
-    if (y - 1 >= L.s0) {
-        float l2 = __shfl_up(Ub.v[VEC - 1], 1, kWave);
-        float r2 = __shfl_down(Ub.v[0], 1, kWave);
-        if (lane == 0) l2 = Ub.l;
-        if (L.last) r2 = Ub.r;
-        float out_phi[VEC], out_pi[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const float c = Ub.v[j];
-            const float xm = j > 0 ? Ub.v[j > 0 ? j - 1 : 0] : l2;
-            const float xp = j < VEC - 1 ? Ub.v[j < VEC - 1 ? j + 1 : j] : r2;
-            const float lap = lap2(c, xm, xp, Ua.v[j], Uc.v[j], A.k2.inv_dx2);
-            kick_drift(c, lap, p1b[j], A.k2, out_pi[j], out_phi[j]);
-        }
-        if (L.active) {
-            const int64_t off = (y - 1) * (int64_t)L.nx + L.x0;
-            store_vec<VEC>(A.phi_out + off, out_phi);
-            store_vec<VEC>(A.pi_out + off, out_pi);
-        }
-    }
-}
-
-template <int VEC, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_pair2d(PairArgs A)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
-    if (tile >= A.ntiles) return;
-    const uint32_t tl = (uint32_t)tile;
-    const uint32_t tx = tl % (uint32_t)A.tiles_x;
-    const uint32_t ts = tl / (uint32_t)A.tiles_x;
-    PairLane L;
-    L.nx = (uint32_t)A.nx;
-    L.M = A.ny;
-    L.x0 = tx * (kWave * VEC) + (uint32_t)lane * VEC;
-    L.active = L.x0 < L.nx;
-    L.first = L.active && lane == 0;
-    L.last = L.active && (lane == kWave - 1 || L.x0 + VEC >= L.nx);
-    L.xl1 = (uint32_t)wrap_any((int64_t)L.x0 - 1, L.nx);
-    L.xl2 = (uint32_t)wrap_any((int64_t)L.x0 - 2, L.nx);
-    L.xr1 = (uint32_t)wrap_any((int64_t)L.x0 + VEC, L.nx);
-    L.xr2 = (uint32_t)wrap_any((int64_t)L.x0 + VEC + 1, L.nx);
-    L.s0 = (int64_t)ts * A.rows;
-    L.s1 = (L.s0 + A.rows) < A.ny ? (L.s0 + A.rows) : A.ny;
-
-    PairRow<VEC> P0, P1, P2, P3;
-    PairPi<VEC> q0, q1;
-    PairU<VEC> U0, U1, U2, U3;
-    float r0[VEC], r1[VEC];
-    pair_zero(P0);
-    pair_zero(P1);
-    pair_zero(P2);
-    pair_zero(P3);
-    pair_zero(q0);
-    pair_zero(q1);
-    pair_zero(U0);
-    pair_zero(U1);
-    pair_zero(U2);
-    pair_zero(U3);
-#pragma unroll
-    for (int j = 0; j < VEC; ++j) r0[j] = r1[j] = 0.0f;
-
-    // rows y-1, y, y+1 of the first iteration y = s0-1, and phi_dot row s0-1
-    pair_load_row<VEC>(A.phi_in, L.s0 - 2, L, P0);
-    pair_load_row<VEC>(A.phi_in, L.s0 - 1, L, P1);
-    pair_load_row<VEC>(A.phi_in, L.s0, L, P2);
-    pair_load_pi<VEC>(A.pi_in, L.s0 - 1, L, q0);
-
-    DiagAcc acc;
-    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
-    acc.walls = acc.nonfinite = 0u;
-    acc.area = acc.ek = 0.0;
-
-    // level-1 rows live in U (ring of 4: y-2, y-1, y and the next), their
-    // phi_dot^{n+1/2} in r (ring of 2)
-    for (int64_t y = L.s0 - 1; y <= L.s1; y += 4) {
-        pair_iter<VEC, DIAG>(A, L, y, P0, P1, P2, P3, q0, q1, U0, U1, U2, r0, r1, acc);
-        if (y + 1 > L.s1) break;
-        pair_iter<VEC, DIAG>(A, L, y + 1, P1, P2, P3, P0, q1, q0, U1, U2, U3, r1, r0, acc);
-        if (y + 2 > L.s1) break;
-        pair_iter<VEC, DIAG>(A, L, y + 2, P2, P3, P0, P1, q0, q1, U2, U3, U0, r0, r1, acc);
-        if (y + 3 > L.s1) break;
-        pair_iter<VEC, DIAG>(A, L, y + 3, P3, P0, P1, P2, q1, q0, U3, U0, U1, r1, r0, acc);
-    }
-
-    if constexpr (DIAG) {
-        WavePartial w;
-        w.links[0] = wave_sum_u32(acc.links[0]);
-        w.links[1] = wave_sum_u32(acc.links[1]);
-        w.links[2] = 0u;
-        w.walls = wave_sum_u32(acc.walls);
-        w.nonfinite = wave_sum_u32(acc.nonfinite);
-        w.pad = 0u;
-        w.area = wave_sum_f64(acc.area);
-        w.ek = wave_sum_f64(acc.ek);
-        if (lane == 0) A.partials[tile] = w;
     }
 }
 
@@ -1281,7 +1267,7 @@ bool tiling_supported(const Geometry& g, const Tiling& t)
 }
 
 hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       float* pi, const StepCoef& k, bool update, bool diag,
+                       const float* pi, float* pi_out, const StepCoef& k, bool update, bool diag,
                        WavePartial* partials, const DiagCoef& dc, hipStream_t s)
 {
     const TileCounts c = tile_counts(g, t);
@@ -1289,6 +1275,7 @@ hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, 
     A.phi_in = phi_in;
     A.phi_out = phi_out;
     A.pi = pi;
+    A.pi_out = pi_out;
     A.partials = partials;
     A.nx = g.nx;
     A.Q = g.Q;
@@ -1402,15 +1389,16 @@ hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s)
 size_t batch_desc_bytes() { return sizeof(BatchDesc); }
 
 void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0, float* phi1, float* pi,
-                     const float2* coef, WavePartial* part0, WavePartial* part1, prs_stats* recs,
-                     int64_t nsteps, int64_t tile_base, int64_t nrec_regular, double eta0, double deta,
-                     double area_scale, int diag_every, const StepCoef& k, const DiagCoef& dc)
+                     float* pi_alt, const float2* coef, const void* passes, int64_t npasses,
+                     WavePartial* part0, WavePartial* part1, prs_stats* recs, int64_t tile_base,
+                     double eta0, double deta, double area_scale, const StepCoef& k, const DiagCoef& dc)
 {
     const TileCounts c = tile_counts(g, t);
     BatchDesc d;
     d.A.phi_in = nullptr;
     d.A.phi_out = nullptr;
     d.A.pi = pi;
+    d.A.pi_out = pi;
     d.A.partials = nullptr;
     d.A.nx = g.nx;
     d.A.Q = g.Q;
@@ -1423,21 +1411,30 @@ void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0,
     d.A.dc = dc;
     d.phi[0] = phi0;
     d.phi[1] = phi1;
+    d.pi_alt = pi_alt;
     d.coef = coef;
+    d.passes = static_cast<const int4*>(passes);
     d.part[0] = part0;
     d.part[1] = part1;
     d.recs = recs;
-    d.nsteps = nsteps;
+    d.npasses = npasses;
     d.tile_base = tile_base;
-    d.nrec_regular = nrec_regular;
+    d.tiles_multi = g.ndim == 2 ? tb_tiles(g, t, 2) : 0;
+    d.tiles_max = std::max<int64_t>(c.ntiles, d.tiles_multi);
     d.eta0 = eta0;
     d.deta = deta;
     d.area_scale = area_scale;
     d.ndim = g.ndim;
     d.vec = t.vec;
     d.ty = t.ty;
-    d.diag_every = diag_every;
+    d.pad = 0;
     *static_cast<BatchDesc*>(out) = d;
+}
+
+int64_t batch_tiles_max(const Geometry& g, const Tiling& t)
+{
+    const int64_t a = tile_counts(g, t).ntiles;
+    return g.ndim == 2 ? std::max<int64_t>(a, tb_tiles(g, t, 2)) : a;
 }
 
 bool batch_tiling_supported(const Geometry& g, const Tiling& t)
@@ -1506,13 +1503,18 @@ hipError_t launch_zero_f32(float* v, int64_t count, hipStream_t s)
 int batch_ctl_bytes() { return (int)sizeof(BatchCtl); }
 
 
-hipError_t launch_pair2d(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                         const float* pi_in, float* pi_out, const StepCoef& k1, const StepCoef& k2,
-                         bool diag, WavePartial* partials, const DiagCoef& dc, hipStream_t s)
+int64_t tb_owned_width(int vec, int T)
 {
-    if (g.ndim != 2 || t.ty != 1) return hipErrorInvalidValue;
-    const TileCounts c = tile_counts(g, t);
-    PairArgs A;
+    const int H = (T + vec - 1) / vec;
+    return (int64_t)(kWave - 2 * H) * vec;
+}
+
+template <int VEC, int T>
+hipError_t launch_tb_t(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
+                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
+{
+    TBArgs<T> A;
     A.phi_in = phi_in;
     A.phi_out = phi_out;
     A.pi_in = pi_in;
@@ -1520,25 +1522,49 @@ hipError_t launch_pair2d(const Geometry& g, const Tiling& t, const float* phi_in
     A.partials = partials;
     A.nx = g.nx;
     A.ny = g.M;
-    A.tiles_x = c.tiles_x;
-    A.ntiles = c.ntiles;
+    const int64_t W = tb_owned_width(VEC, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.ntiles = A.tiles_x * ((g.M + t.rows - 1) / t.rows);
     A.rows = t.rows;
-    A.k1 = k1;
-    A.k2 = k2;
+    for (int i = 0; i < T; ++i) A.k[i] = k[i];
     A.dc = dc;
-    const int64_t blocks = (c.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-#define PRS_PAIR(V)                                                                                   \
-    if (diag)                                                                                         \
-        hipLaunchKernelGGL((k_pair2d<V, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);       \
-    else                                                                                              \
-        hipLaunchKernelGGL((k_pair2d<V, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);      \
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (diag)
+        hipLaunchKernelGGL((k_tb2d<VEC, T, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tb2d<VEC, T, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
     return hipGetLastError();
-    switch (t.vec) {
-    case 1: { PRS_PAIR(1) }
-    case 2: { PRS_PAIR(2) }
-    case 4: { PRS_PAIR(4) }
+}
+
+template <int VEC>
+hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
+                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
+{
+    switch (T) {
+    case 2: return launch_tb_t<VEC, 2>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    case 3: return launch_tb_t<VEC, 3>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    case 4: return launch_tb_t<VEC, 4>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     }
-#undef PRS_PAIR
+    return hipErrorInvalidValue;
+}
+
+int64_t tb_tiles(const Geometry& g, const Tiling& t, int T)
+{
+    const int64_t W = tb_owned_width(t.vec, T);
+    return ((g.nx + W - 1) / W) * ((g.M + t.rows - 1) / t.rows);
+}
+
+hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
+                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
+                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
+{
+    if (g.ndim != 2 || t.ty != 1) return hipErrorInvalidValue;
+    switch (t.vec) {
+    case 1: return launch_tb_v<1>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    case 2: return launch_tb_v<2>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    case 4: return launch_tb_v<4>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    }
     return hipErrorInvalidValue;
 }
 

@@ -127,12 +127,16 @@ _decl("prs_batch_create", _i32, _BI, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp))
 _decl("prs_batch_offsets", _i32, _vp, ctypes.POINTER(_i64))
 _decl("prs_batch_set_tiling", _i32, _vp, _i32, _i32, _i32, _i32)
 _decl("prs_batch_set_mode", _i32, _vp, _i32)
+_decl("prs_batch_set_time_blocking", _i32, _vp, _i32, _i32)
+_decl("prs_batch_state", _i32, _vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp))
 _decl("prs_batch_run", _i32, _vp, _S, _i64)
 _decl("prs_batch_destroy", None, _vp)
 _decl("prs_autotune", _i32, _vp, ctypes.c_char_p, _i32, ctypes.POINTER(_d))
 _decl("prs_tuned_tiling", _i32, _P, ctypes.c_char_p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
       ctypes.POINTER(_i32))
 _decl("prs_set_time_blocking", _i32, _vp, _i32)
+_decl("prs_set_adjoint_tiling", _i32, _vp, _i32, _i32, _i32)
+_decl("prs_get_adjoint_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _decl("prs_get_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
 _decl("prs_last_error", ctypes.c_char_p)
@@ -143,12 +147,15 @@ EXPORTED = [
     "prs_fill_uniform", "prs_fit_scaling", "prs_strerror", "prs_last_error",
     "prs_adjoint_workspace_bytes", "prs_adjoint_forward", "prs_adjoint_backward", "prs_adjoint",
     "prs_batch_workspace_bytes", "prs_batch_create", "prs_batch_offsets", "prs_batch_set_tiling",
-    "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy", "prs_autotune", "prs_tuned_tiling",
-    "prs_set_time_blocking", "prs_get_time_blocking",
+    "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy", "prs_batch_set_time_blocking",
+    "prs_batch_state", "prs_autotune", "prs_tuned_tiling",
+    "prs_set_time_blocking", "prs_get_time_blocking", "prs_set_adjoint_tiling",
+    "prs_get_adjoint_tiling",
 ]
 
 PRS_TUNE_FORCE = 1
 PRS_TUNE_BATCH = 2
+PRS_TUNE_ADJOINT = 4
 
 
 class PRSError(RuntimeError):
@@ -248,6 +255,17 @@ def prs_get_time_blocking(ctx):
     return v.value
 
 
+def prs_set_adjoint_tiling(ctx, vec, rows, ty=1):
+    _check(_lib.prs_set_adjoint_tiling(ctx, vec, rows, ty), "prs_set_adjoint_tiling")
+
+
+def prs_get_adjoint_tiling(ctx):
+    v, r, t = _i32(), _i32(), _i32()
+    _check(_lib.prs_get_adjoint_tiling(ctx, ctypes.byref(v), ctypes.byref(r), ctypes.byref(t)),
+           "prs_get_adjoint_tiling")
+    return v.value, r.value, t.value
+
+
 def prs_destroy(ctx):
     _lib.prs_destroy(ctx)
 
@@ -321,6 +339,16 @@ def prs_batch_set_tiling(b, item, vec, rows, ty=1):
 
 def prs_batch_set_mode(b, mode):
     _check(_lib.prs_batch_set_mode(b, mode), "prs_batch_set_mode")
+
+
+def prs_batch_set_time_blocking(b, item, steps_per_pass):
+    _check(_lib.prs_batch_set_time_blocking(b, item, steps_per_pass), "prs_batch_set_time_blocking")
+
+
+def prs_batch_state(b, item):
+    phi, dphi = _vp(), _vp()
+    _check(_lib.prs_batch_state(b, item, ctypes.byref(phi), ctypes.byref(dphi)), "prs_batch_state")
+    return phi.value, dphi.value
 
 
 def prs_batch_run(b, total_records):
@@ -516,6 +544,9 @@ class Batch:
     def set_mode(self, mode):
         prs_batch_set_mode(self.b, mode)
 
+    def set_time_blocking(self, item, steps_per_pass):
+        prs_batch_set_time_blocking(self.b, item, steps_per_pass)
+
     def run(self):
         """Runs the ensemble; returns one record list per realisation."""
         recs = prs_batch_run(self.b, self.offsets[-1])
@@ -524,7 +555,8 @@ class Batch:
     def final_state(self, r):
         """(phi, dphi) tensors of realisation r after its last step."""
         f = self.fields[r]
-        return (f[0] if self.items[r].nsteps % 2 == 0 else f[1]), f[2]
+        phi_ptr, _ = prs_batch_state(self.b, r)
+        return (f[0] if phi_ptr == f[0].data_ptr() else f[1]), f[2]
 
     def close(self):
         if self.b is not None:

@@ -123,3 +123,30 @@ def test_adjoint_full_size(shape, nsteps, K):
     assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
     del sim
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("shape", [(200, 130), (40, 36, 30)])
+def test_adjoint_tiling_independent(shape):
+    """The reverse-sweep kernel's tiling changes nothing but the summation
+    order of dL/dW0: gradient fields are bitwise equal."""
+    say("adjoint tilings", shape)
+    torch = torch_mod()
+    prs = gpu_prs()
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp, _ = params_pair(shape, deta, m=1.0, W0=8.0)
+    phi0 = uniform_field(shape, 5)
+    nb = prs.prs_adjoint_workspace_bytes(gp, 20, 8)
+    ref = None
+    for t in [(1, 8, 1), (2, 17, 1), (4, 64, 1)] + ([(2, 16, 2), (1, 32, 4)] if len(shape) == 3 else []):
+        if shape[0] % t[0]:
+            continue
+        sim = prs.Sim(gp, phi0=to_dev(phi0))
+        prs.prs_set_adjoint_tiling(sim.ctx, *t)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        g = torch.empty_like(sim.phi_a)
+        loss, gw = prs.prs_adjoint(sim.ctx, 20, 8, work.data_ptr(), nb, g.data_ptr(), None)
+        if ref is None:
+            ref = (host(g), gw, loss)
+            continue
+        np.testing.assert_array_equal(host(g), ref[0])
+        assert gw == pytest.approx(ref[1], rel=1e-12) and loss == ref[2]

@@ -19,9 +19,14 @@ SPECS = [
     dict(shape=(64, 64, 64), deta=0.2, m=0.5, W0=10.0, nsteps=31, diag_every=10, seed=1004),
     dict(shape=(33, 17), deta=0.25, m=1.0, W0=5.0, nsteps=0, diag_every=4, seed=1005),
     dict(shape=(128, 96), deta=0.25, m=1.0, W0=10.0, nsteps=1, diag_every=1, seed=1006),
+    dict(shape=(200, 64), deta=0.25, m=1.0, W0=10.0, nsteps=29, diag_every=7, seed=1007, T=1),
 ]
 
-TILINGS = [(4, 32, 1), (2, 17, 1), (4, 64, 1), (2, 16, 1), (4, 32, 1), (1, 16, 1), (4, 8, 1)]
+TILINGS = [(4, 32, 1), (2, 17, 1), (4, 64, 1), (2, 16, 1), (4, 32, 1), (1, 16, 1), (4, 8, 1), (2, 16, 1)]
+
+
+def steps_per_pass(sp):
+    return sp.get("T", 2 if len(sp["shape"]) == 2 else 1)
 
 
 def single_run(prs, sp, tiling):
@@ -29,6 +34,7 @@ def single_run(prs, sp, tiling):
                         diag_every=sp["diag_every"])
     sim = prs.Sim(p, seed=sp["seed"])
     sim.set_tiling(*tiling)
+    sim.set_time_blocking(steps_per_pass(sp))
     recs = sim.step_n(sp["nsteps"])
     recs.append(sim.wall_stats())
     phi, dphi = sim.state()
@@ -49,6 +55,7 @@ def make_batch(prs):
     b = prs.Batch(SPECS)
     for r, t in enumerate(TILINGS):
         b.set_tiling(r, *t)
+        b.set_time_blocking(r, steps_per_pass(SPECS[r]))
     return b
 
 

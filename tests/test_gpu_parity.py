@@ -333,17 +333,17 @@ def test_full_size_3d_1024_sampled():
     torch.cuda.empty_cache()
 
 
-# ------------------------------------------------- two-step passes (2D) ----
+# ---------------------------------------------- multi-step passes (2D) ----
 
 @pytest.mark.parametrize("shape,K,steps", [
     ((300, 70), 5, 23), ((1, 7), 2, 9), ((7, 1), 3, 10), ((2, 2), 64, 11), ((66, 129), 1, 6),
-    ((1030, 9), 64, 67), ((256, 256), 10, 50), ((512, 300), 8, 37),
+    ((1030, 9), 64, 67), ((256, 256), 10, 50), ((512, 300), 8, 37), ((248, 40), 12, 31),
 ])
-def test_two_step_passes_bitwise_equal_single_steps(shape, K, steps):
-    """Temporal blocking changes only how often HBM is visited: fields and
-    records are bitwise those of single steps, for every tiling, ragged sizes,
-    every record cadence and odd step counts."""
-    say("two-step", shape, K, steps)
+def test_multi_step_passes_bitwise_equal_single_steps(shape, K, steps):
+    """Temporal blocking (2, 3 or 4 steps per pass) changes only how often
+    HBM is visited: fields and records are bitwise those of single steps, for
+    every tiling, ragged sizes, record cadences and odd step counts."""
+    say("multi-step", shape, K, steps)
     prs = gpu_prs()
     gp, _ = params_pair(shape, 0.25, m=2.0, W0=6.0, diag_every=K)
     phi0 = uniform_field(shape, 31)
@@ -351,15 +351,33 @@ def test_two_step_passes_bitwise_equal_single_steps(shape, K, steps):
     ref.set_time_blocking(1)
     r_ref = ref.step_n(steps)
     rp, rd = (host(t) for t in ref.state())
-    for t in tilings_for(shape) + [(tilings_for(shape)[0][0], 8, 1)]:
-        sim = prs.Sim(gp, phi0=to_dev(phi0))
-        assert sim.time_blocking() == 2
-        sim.set_tiling(*t)
-        r1 = sim.step_n(steps // 2)
-        r2 = sim.step_n(steps - steps // 2)
-        p, d = (host(x) for x in sim.state())
-        np.testing.assert_array_equal(p, rp, err_msg=str(t))
-        np.testing.assert_array_equal(d, rd, err_msg=str(t))
-        assert r1 + r2 == r_ref or all(a["links_dir"] == b["links_dir"] for a, b in zip(r1 + r2, r_ref))
-        assert [r["step"] for r in r1 + r2] == [r["step"] for r in r_ref]
-        assert sim.state()[1].data_ptr() == sim.dphi.data_ptr()
+    base = tilings_for(shape)
+    for T in (2, 3, 4):
+        for t in base + [(base[0][0], 8, 1)]:
+            sim = prs.Sim(gp, phi0=to_dev(phi0))
+            sim.set_time_blocking(T)
+            sim.set_tiling(*t)
+            r1 = sim.step_n(steps // 2)
+            r2 = sim.step_n(steps - steps // 2)
+            p, d = (host(x) for x in sim.state())
+            np.testing.assert_array_equal(p, rp, err_msg=str((T, t)))
+            np.testing.assert_array_equal(d, rd, err_msg=str((T, t)))
+            assert [r["step"] for r in r1 + r2] == [r["step"] for r in r_ref]
+            for a, b in zip(r1 + r2, r_ref):
+                assert_stats_match(a, b, rel=1e-13, ctx=str((T, t)))
+            assert sim.state()[1].data_ptr() == sim.dphi.data_ptr()
+
+
+def test_multi_step_default_and_limits():
+    prs = gpu_prs()
+    gp, _ = params_pair((64, 64), 0.25)
+    sim = prs.Sim(gp, seed=1)
+    assert sim.time_blocking() == 2
+    with pytest.raises(prs.PRSError):
+        sim.set_time_blocking(5)
+    gp3, _ = params_pair((16, 16, 16), 0.2)
+    sim3 = prs.Sim(gp3, seed=1)
+    assert sim3.time_blocking() == 1
+    with pytest.raises(prs.PRSError) as e:
+        sim3.set_time_blocking(2)
+    assert e.value.status == prs.PRS_EUNSUPPORTED

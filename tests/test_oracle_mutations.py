@@ -14,7 +14,7 @@ from tests import test_oracle_pins as P
 MUTATIONS = [
     ("laplacian centre coefficient", "acc -= 2.0 * p->ndim * f[i];", "acc -= 2.0 * (p->ndim + 1) * f[i];"),
     ("laplacian misses 1/dx^2", "return acc / (p->dx * p->dx);", "return acc;"),
-    ("y neighbour wraps with nx", "if (d == 1) y = wrap(y + s, ny);", "if (d == 1) y = wrap(y + s, nx);"),
+    ("y neighbour two sites away", "if (d == 1) y = wrap(y + s, ny);", "if (d == 1) y = wrap(y + 2 * s, ny);"),
     ("damping sign", "(1.0 - delta) * pi[i]", "(1.0 + delta) * pi[i]"),
     ("damping at eta_{n+1}", "double delta = orc_delta(p, n);\n    double deta = p->deta;",
      "double delta = orc_delta(p, n + 1);\n    double deta = p->deta;"),
