@@ -26,10 +26,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_UPDATE = 16          # read phi, phi_dot; write phi^{n+1}, phi_dot (FP32)
-# HBM bytes of one k_pair2d<4> launch on the 8192^2 lattice (tiling vec 4,
-# rows 16), from rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by the same
-# counters on a plain 256 MiB copy; None until measured for this kernel.
-TRAFFIC_PER_LAUNCH = None
+# HBM bytes of one launch of the dominant kernel on the 8192^2 lattice, by
+# (vec, rows, ty, steps per pass): rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB per
+# dispatch) scaled by what the same counters read for a plain 256 MiB copy
+# (factors 1.9998 and 1.0000); see profiles/k_tb2d_2d8192.md.  A
+# configuration without a measurement reports null.
+TRAFFIC_PER_LAUNCH = {
+    (4, 32, 1, 4): 1193967386,
+}
 
 WORKLOAD = {
     "name": "2D PRS 8192^2, matter era m=2, W0=10, deta=0.25, eta 1->4096 (16380 steps), "
@@ -192,6 +196,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and ensemble legs")
+    ap.add_argument("--tiling", default=None, help="vec,rows,ty for the main run (default: autotuned)")
+    ap.add_argument("--steps-per-pass", type=int, default=2, help="with --tiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the PRS path is built and timed on a single "
@@ -211,9 +217,11 @@ def main():
                          diag_every=w["diag_every"])
     sites = prs.sites(gp)
     sim = prs.Sim(gp, seed=w["seed"])
-    # the library's default tiling for this lattice (vec 4, 16 rows, two steps
-    # per pass) is the one the autotuner picks within 1.5 %; it is kept fixed
-    # here so that the hardware-counter profile describes the same launches
+    if args.tiling:
+        sim.set_tiling(*[int(v) for v in args.tiling.split(",")])
+        sim.set_time_blocking(args.steps_per_pass)
+    else:
+        prs.prs_autotune(sim.ctx, None, 0)    # tiling and steps per pass, before the timed region
     log("tiling", sim.tiling(), "steps/pass", sim.time_blocking(), "steps/run", S)
 
     for i in range(args.warmup):
@@ -237,13 +245,15 @@ def main():
 
     updates = float(sites) * S * args.steps
     value = updates / wall
-    # dominant kernel: the two-step pass (k_pair2d; S/2 launches per run, the
-    # 128 passes holding a record fuse the diagnostics).  Its average duration
-    # from the stream events over the timed region is an upper bound: the
-    # region also holds the 258 record reductions and each run's initial field.
+    # dominant kernel: the T-step pass (k_tb2d; records only at pass
+    # starts).  Its launch duration is estimated from the stream events over
+    # the timed region as the time per step times T (the region also holds
+    # the single-step passes next to records, the record reductions and each
+    # run's initial field); the kernel-trace profile gives the exact average.
     spp = sim.time_blocking()
-    launches = (S // spp) * args.steps
-    avg_launch_s = ev_ms / 1e3 / launches
+    multi, single = prs.prs_plan_passes(sim.ctx, S, True)
+    step_s = ev_ms / 1e3 / (S * args.steps)
+    avg_launch_s = step_s * spp
     alg_bytes = BYTES_PER_UPDATE * sites * spp        # algorithmic bytes of one launch
     achieved = alg_bytes / avg_launch_s / 1e9
     recs, mu, nu = results[-1]
@@ -264,9 +274,12 @@ def main():
                    "records_per_run": len(recs), "tiling": list(sim.tiling()),
                    "steps_per_pass": sim.time_blocking()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_PER_LAUNCH,
-                     "kernel": "k_pair2d<4> (two fused leapfrog steps per pass)" if spp == 2 else
-                               "k_step<2,4,1> (fused leapfrog step)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": TRAFFIC_PER_LAUNCH.get(tuple(sim.tiling()) + (spp,)),
+                     "kernel": ("k_tb2d<vec=%d,T=%d> (%d fused leapfrog steps per pass)" % (
+                         sim.tiling()[0], spp, spp)) if spp > 1 else
+                               "k_step<2,%d,1> (fused leapfrog step)" % sim.tiling()[0],
+                     "passes_per_run": {"multi_step": multi, "single_step": single},
                      "algorithmic_bytes_per_launch": alg_bytes, "site_updates_per_launch": sites * spp,
                      "avg_launch_us": avg_launch_s * 1e6},
         "result": {"mu": mu, "nu": nu, "final_links": recs[-1]["links"],

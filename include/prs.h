@@ -119,7 +119,10 @@ prs_status prs_step_n(prs_ctx* ctx, int64_t nsteps, prs_stats* series, int64_t c
                       int64_t* n_written);
 
 /* Diagnostics (Eqs. 7-8) of the current state; synchronises the stream.
- * Bit-identical to the record prs_step_n fuses for the same state. */
+ * The counts equal those of the record prs_step_n fuses for the same state;
+ * the two FP64 sums are bitwise equal to it when that record came from a
+ * single-step pass and equal up to summation order when it came from a
+ * multi-step pass (which splits the lattice into different wave tiles). */
 prs_status prs_wall_stats(prs_ctx* ctx, prs_stats* out);
 
 /* Current state: device pointers of phi^n and phi_dot^{n-1/2}, n and eta_n.
@@ -167,6 +170,11 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
  * lattices support only 1 (PRS_EUNSUPPORTED otherwise). */
 prs_status prs_set_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
 prs_status prs_get_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
+
+/* How prs_step_n(ctx, nsteps, series != NULL iff with_records) would split
+ * its steps: the number of multi-step passes and of single-step passes. */
+prs_status prs_plan_passes(const prs_ctx* ctx, int64_t nsteps, int32_t with_records, int64_t* multi_passes,
+                           int64_t* single_passes);
 
 /* Tiling of the reverse-sweep (adjoint) kernel, chosen independently of the
  * forward tiling (same parameters and rules as prs_set_tiling; the

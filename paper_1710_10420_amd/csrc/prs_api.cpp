@@ -118,6 +118,33 @@ int64_t partial_capacity(const Geometry& g)
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Steps of each pass for nsteps steps from n0 with up to T steps per pass:
+// no pass has a recorded state (n % K == 0, K > 0) strictly inside it, and
+// the number of multi-step passes is even (each flips the phi_dot buffer, so
+// phi_dot ends where it started).
+std::vector<uint8_t> plan_passes(int64_t n0, int64_t nsteps, int T, int64_t K)
+{
+    std::vector<uint8_t> plan;
+    int64_t nmulti = 0;
+    for (int64_t n = n0; n < n0 + nsteps;) {
+        int64_t L = std::min<int64_t>(T, n0 + nsteps - n);
+        if (K > 0) L = std::min<int64_t>(L, (n / K + 1) * K - n);
+        plan.push_back((uint8_t)L);
+        nmulti += L > 1 ? 1 : 0;
+        n += L;
+    }
+    if (nmulti % 2 == 1) {
+        for (size_t i = plan.size(); i-- > 0;)
+            if (plan[i] > 1) {
+                const int L = plan[i];
+                plan.erase(plan.begin() + (std::ptrdiff_t)i);
+                plan.insert(plan.begin() + (std::ptrdiff_t)i, (size_t)L, (uint8_t)1);
+                break;
+            }
+    }
+    return plan;
+}
+
 }  // namespace
 
 struct prs_ctx {
@@ -277,31 +304,8 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int64_t K = c->p.diag_every;
     const int64_t end = c->step + nsteps;
 
-    // Plan: passes of up to tblock steps (2D), never with a recorded state
-    // strictly inside a pass; the number of multi-step passes is kept even
-    // so phi_dot ends in the caller's buffer.
     const int T = (c->pi_alt != nullptr && c->til.ty == 1) ? c->tblock : 1;
-    std::vector<uint8_t> plan;   // steps of each pass
-    int64_t nmulti = 0;
-    for (int64_t n = c->step; n < end;) {
-        int64_t L = std::min<int64_t>(T, end - n);
-        if (want) {
-            const int64_t next_rec = (n / K + 1) * K;     // first record state after n
-            L = std::min<int64_t>(L, next_rec - n);
-        }
-        plan.push_back((uint8_t)L);
-        nmulti += L > 1 ? 1 : 0;
-        n += L;
-    }
-    if (nmulti % 2 == 1) {
-        for (size_t i = plan.size(); i-- > 0;)
-            if (plan[i] > 1) {
-                const int L = plan[i];
-                plan.erase(plan.begin() + (std::ptrdiff_t)i);
-                plan.insert(plan.begin() + (std::ptrdiff_t)i, (size_t)L, (uint8_t)1);
-                break;
-            }
-    }
+    const std::vector<uint8_t> plan = plan_passes(c->step, nsteps, T, want ? K : 0);
 
     float* pi_cur = c->pi;
     float* pi_oth = c->pi_alt;
@@ -355,6 +359,19 @@ prs_status prs_set_time_blocking(prs_ctx* c, int32_t steps_per_pass)
     if (steps_per_pass > 1 && c->p.ndim != 2)
         return fail(PRS_EUNSUPPORTED, "multi-step passes are implemented for 2D lattices");
     c->tblock = steps_per_pass;
+    return PRS_OK;
+}
+
+prs_status prs_plan_passes(const prs_ctx* c, int64_t nsteps, int32_t with_records, int64_t* multi_passes,
+                           int64_t* single_passes)
+{
+    if (!c || nsteps < 0) return fail(PRS_EINVAL, "invalid arguments");
+    const int T = (c->pi_alt != nullptr && c->til.ty == 1) ? c->tblock : 1;
+    const int64_t K = (with_records && c->p.diag_every > 0) ? c->p.diag_every : 0;
+    int64_t m = 0, n1 = 0;
+    for (uint8_t L : plan_passes(c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
+    if (multi_passes) *multi_passes = m;
+    if (single_passes) *single_passes = n1;
     return PRS_OK;
 }
 

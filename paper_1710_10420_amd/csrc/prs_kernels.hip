@@ -107,28 +107,51 @@ __device__ __forceinline__ void store_vec(float* p, const float (&v)[VEC])
     }
 }
 
-// Eq. (3) (2D) and its 3D extension, times 1/dx^2.
+// Eq. (3) (2D) and its 3D extension, times 1/dx^2.  UNIT (dx = 1) drops the
+// multiplication by 1, which is exact, so both forms give the same bits.
+template <bool UNIT = false>
 __device__ __forceinline__ float lap2(float c, float xm, float xp, float ym, float yp, float inv_dx2)
 {
-    float s = (xm + xp) + (ym + yp);
-    return fmaf(-4.0f, c, s) * inv_dx2;
+    const float s = (xm + xp) + (ym + yp);
+    const float r = fmaf(-4.0f, c, s);
+    return UNIT ? r : r * inv_dx2;
 }
 
+template <bool UNIT = false>
 __device__ __forceinline__ float lap3(float c, float xm, float xp, float ym, float yp, float zm,
                                       float zp, float inv_dx2)
 {
-    float s = ((xm + xp) + (ym + yp)) + (zm + zp);
-    return fmaf(-6.0f, c, s) * inv_dx2;
+    const float s = ((xm + xp) + (ym + yp)) + (zm + zp);
+    const float r = fmaf(-6.0f, c, s);
+    return UNIT ? r : r * inv_dx2;
 }
 
-// Eqs. (4)-(5) with the FP64-derived coefficients of StepCoef.
+// Eqs. (4)-(5) with the FP64-derived coefficients of StepCoef:
+// V'(phi) = F phi (kc phi^2 - 1), the bracket formed with one rounding.
+// UNIT (phi0 = 1, kc = 1) drops the exact multiplication by kc.
+template <bool UNIT = false>
 __device__ __forceinline__ void kick_drift(float c, float lap, float pi, const StepCoef& k,
                                            float& pi_new, float& phi_new)
 {
-    float q = c * c * k.kc - 1.0f;
-    float dv = (k.F * c) * q;                 // V'(phi)
+    const float ck = UNIT ? c : c * k.kc;
+    const float q = fmaf(ck, c, -1.0f);
+    const float dv = (k.F * c) * q;            // V'(phi)
     pi_new = fmaf(k.a, pi, k.b * (lap - dv));  // Eq. (4)
     phi_new = fmaf(k.deta, pi_new, c);         // Eq. (5)
+}
+
+// Value held by the lane on the left (lane - 1) / right (lane + 1) of this
+// one, by a wave-wide DPP shift; the end lane keeps its own value.
+__device__ __forceinline__ float from_left_lane(float v)
+{
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x138, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float from_right_lane(float v)
+{
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x130, 0xF, 0xF, false));
 }
 
 struct DiagAcc {
@@ -361,8 +384,8 @@ __device__ __forceinline__ void x_neighbours(const Plane<VEC, TY>& P, const Tile
     const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int t = 0; t < TY; ++t) {
-        left[t] = __shfl_up(P.v[t][VEC - 1], 1, kWave);
-        right[t] = __shfl_down(P.v[t][0], 1, kWave);
+        left[t] = from_left_lane(P.v[t][VEC - 1]);
+        right[t] = from_right_lane(P.v[t][0]);
         if (lane == 0) left[t] = P.hl[t];
         if (S.need_right) right[t] = P.hr[t];
     }
@@ -390,7 +413,7 @@ __device__ __forceinline__ void neighbours(const Plane<VEC, TY>& Pm, const Plane
 
 // Plane s of a forward tile: prefetch plane s+2 (and phi_dot of s+1), then
 // update plane s from (Pm, Pc, Pn) = planes (s-1, s, s+1).
-template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
+template <int D, int VEC, int TY, bool UPDATE, bool DIAG, bool UNIT = false>
 __device__ __forceinline__ void step_plane(const StepArgs& A, const TileSetup<TY>& S, int64_t s,
                                            const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
                                            const Plane<VEC, TY>& Pn, Plane<VEC, TY>& Pnn,
@@ -417,10 +440,10 @@ __device__ __forceinline__ void step_plane(const StepArgs& A, const TileSetup<TY
             if constexpr (UPDATE) {
                 float lap;
                 if constexpr (D == 3)
-                    lap = lap3(c, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.k.inv_dx2);
+                    lap = lap3<UNIT>(c, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.k.inv_dx2);
                 else
-                    lap = lap2(c, nm[0], np[0], nm[1], np[1], A.k.inv_dx2);
-                kick_drift(c, lap, pic[t][j], A.k, out_pi[j], out_phi[j]);
+                    lap = lap2<UNIT>(c, nm[0], np[0], nm[1], np[1], A.k.inv_dx2);
+                kick_drift<UNIT>(c, lap, pic[t][j], A.k, out_pi[j], out_phi[j]);
             }
             if constexpr (DIAG) {
                 if (S.active) site_diag<D>(c, pic[t][j], nm, np, A.dc, acc);
@@ -438,7 +461,7 @@ __device__ __forceinline__ void step_plane(const StepArgs& A, const TileSetup<TY
 // One wave's tile of one step (see the file header).  `tile` must be below
 // A.ntiles and uniform across the wave.  The march is unrolled by four over a
 // ring of four plane buffers, so no plane is ever copied between registers.
-template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
+template <int D, int VEC, int TY, bool UPDATE, bool DIAG, bool UNIT = false>
 __device__ __forceinline__ void step_tile(const StepArgs& A, int64_t tile)
 {
     static_assert(D == 3 || TY == 1, "2D tiles have one row");
@@ -464,13 +487,13 @@ __device__ __forceinline__ void step_tile(const StepArgs& A, int64_t tile)
     acc.area = acc.ek = 0.0;
 
     for (int64_t s = S.s0; s < S.s1; s += 4) {
-        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s, P0, P1, P2, P3, pi0, pi1, acc);
+        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s, P0, P1, P2, P3, pi0, pi1, acc);
         if (s + 1 >= S.s1) break;
-        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s + 1, P1, P2, P3, P0, pi1, pi0, acc);
+        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s + 1, P1, P2, P3, P0, pi1, pi0, acc);
         if (s + 2 >= S.s1) break;
-        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s + 2, P2, P3, P0, P1, pi0, pi1, acc);
+        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s + 2, P2, P3, P0, P1, pi0, pi1, acc);
         if (s + 3 >= S.s1) break;
-        step_plane<D, VEC, TY, UPDATE, DIAG>(A, S, s + 3, P3, P0, P1, P2, pi1, pi0, acc);
+        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s + 3, P3, P0, P1, P2, pi1, pi0, acc);
     }
 
     if constexpr (DIAG) {
@@ -487,12 +510,12 @@ __device__ __forceinline__ void step_tile(const StepArgs& A, int64_t tile)
     }
 }
 
-template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
+template <int D, int VEC, int TY, bool UPDATE, bool DIAG, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs A)
 {
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
     if (tile >= A.ntiles) return;   // whole wave leaves; shuffles stay uniform
-    step_tile<D, VEC, TY, UPDATE, DIAG>(A, tile);
+    step_tile<D, VEC, TY, UPDATE, DIAG, UNIT>(A, tile);
 }
 
 // Adds `count` wave partials into one record, with one wave, in a fixed
@@ -597,7 +620,7 @@ struct AdjArgs {
 };
 
 // Plane s of a reverse tile (same ring scheme as step_plane).
-template <int D, int VEC, int TY>
+template <int D, int VEC, int TY, bool UNIT>
 __device__ __forceinline__ void adj_plane(const AdjArgs& A, const TileSetup<TY>& S, int64_t s,
                                           const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
                                           const Plane<VEC, TY>& Pn, Plane<VEC, TY>& Pnn,
@@ -625,12 +648,13 @@ __device__ __forceinline__ void adj_plane(const AdjArgs& A, const TileSetup<TY>&
             neighbours<D, VEC, TY>(Pm, Pc, Pn, left, right, S.nvalid, t, j, nm, np);
             float lap;
             if constexpr (D == 3)
-                lap = lap3(w, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.inv_dx2);
+                lap = lap3<UNIT>(w, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.inv_dx2);
             else
-                lap = lap2(w, nm[0], np[0], nm[1], np[1], A.inv_dx2);
+                lap = lap2<UNIT>(w, nm[0], np[0], nm[1], np[1], A.inv_dx2);
             const float ph = phc[t][j];
-            const float q = ph * ph * A.kc - 1.0f;
-            const float v2 = A.F * (3.0f * ph * ph * A.kc - 1.0f);   // V''(phi)
+            const float phk = UNIT ? ph : ph * A.kc;
+            const float q = fmaf(phk, ph, -1.0f);
+            const float v2 = A.F * fmaf(3.0f * phk, ph, -1.0f);   // V''(phi)
             const float mu_new = fmaf(A.b, lap - v2 * w, muc[t][j]);
             out_mu[j] = mu_new;
             out_w[j] = fmaf(A.cw, mu_new, A.a * w);
@@ -643,7 +667,7 @@ __device__ __forceinline__ void adj_plane(const AdjArgs& A, const TileSetup<TY>&
     }
 }
 
-template <int D, int VEC, int TY>
+template <int D, int VEC, int TY, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -669,13 +693,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A)
 
     double gsum = 0.0;
     for (int64_t s = S.s0; s < S.s1; s += 4) {
-        adj_plane<D, VEC, TY>(A, S, s, P0, P1, P2, P3, mu0, mu1, ph0, ph1, gsum);
+        adj_plane<D, VEC, TY, UNIT>(A, S, s, P0, P1, P2, P3, mu0, mu1, ph0, ph1, gsum);
         if (s + 1 >= S.s1) break;
-        adj_plane<D, VEC, TY>(A, S, s + 1, P1, P2, P3, P0, mu1, mu0, ph1, ph0, gsum);
+        adj_plane<D, VEC, TY, UNIT>(A, S, s + 1, P1, P2, P3, P0, mu1, mu0, ph1, ph0, gsum);
         if (s + 2 >= S.s1) break;
-        adj_plane<D, VEC, TY>(A, S, s + 2, P2, P3, P0, P1, mu0, mu1, ph0, ph1, gsum);
+        adj_plane<D, VEC, TY, UNIT>(A, S, s + 2, P2, P3, P0, P1, mu0, mu1, ph0, ph1, gsum);
         if (s + 3 >= S.s1) break;
-        adj_plane<D, VEC, TY>(A, S, s + 3, P3, P0, P1, P2, mu1, mu0, ph1, ph0, gsum);
+        adj_plane<D, VEC, TY, UNIT>(A, S, s + 3, P3, P0, P1, P2, mu1, mu0, ph1, ph0, gsum);
     }
     gsum = wave_sum_f64(gsum);
     if (lane == 0) A.gacc[tile] += A.gscale * gsum;
@@ -739,7 +763,10 @@ template <int D, int VEC, int TY>
 hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s)
 {
     const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL((k_adjoint<D, VEC, TY>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    if (A.inv_dx2 == 1.0f && A.kc == 1.0f)
+        hipLaunchKernelGGL((k_adjoint<D, VEC, TY, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_adjoint<D, VEC, TY, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
     return hipGetLastError();
 }
 
@@ -809,7 +836,7 @@ __device__ __forceinline__ void tb_load(const float* __restrict__ f, int64_t y, 
     load_vec<VEC>(f + wrap_any(y, L.M) * (int64_t)L.nx + L.xw, v);
 }
 
-template <int VEC, int T, bool DIAG, int U>
+template <int VEC, int T, bool DIAG, bool UNIT, int U>
 __device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int64_t y,
                                         TBState<VEC, T>& S, DiagAcc& acc)
 {
@@ -836,16 +863,16 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int
             cp = S.lv[k - 1][U & 3];
             pp = S.pl[k - 1][(U + 1) & 1];
         }
-        float left = __shfl_up(cc[VEC - 1], 1, kWave);
-        float right = __shfl_down(cc[0], 1, kWave);
+        float left = from_left_lane(cc[VEC - 1]);
+        float right = from_right_lane(cc[0]);
         float out_phi[VEC], out_pi[VEC];
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
             const float c = cc[j];
             const float xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
             const float xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
-            const float lap = lap2(c, xm, xp, cm[j], cp[j], A.k[k - 1].inv_dx2);
-            kick_drift(c, lap, pp[j], A.k[k - 1], out_pi[j], out_phi[j]);
+            const float lap = lap2<UNIT>(c, xm, xp, cm[j], cp[j], A.k[k - 1].inv_dx2);
+            kick_drift<UNIT>(c, lap, pp[j], A.k[k - 1], out_pi[j], out_phi[j]);
             if constexpr (DIAG) {
                 if (k == 1 && L.store && r >= L.s0 && r < L.s1) {
                     const float nm[2] = {xm, cm[j]};
@@ -870,7 +897,7 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int
 
 // One wave's tile of a T-step pass; `tile` must be below A.ntiles and
 // wave-uniform.
-template <int VEC, int T, bool DIAG>
+template <int VEC, int T, bool DIAG, bool UNIT = false>
 __device__ __forceinline__ void tb_tile(const TBArgs<T>& A, int64_t tile)
 {
     constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
@@ -920,13 +947,13 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T>& A, int64_t tile)
 
     const int64_t ylast = L.s1 + T - 2;
     for (int64_t y = y0; y <= ylast; y += 4) {
-        tb_iter<VEC, T, DIAG, 0>(A, L, y, S, acc);
+        tb_iter<VEC, T, DIAG, UNIT, 0>(A, L, y, S, acc);
         if (y + 1 > ylast) break;
-        tb_iter<VEC, T, DIAG, 1>(A, L, y + 1, S, acc);
+        tb_iter<VEC, T, DIAG, UNIT, 1>(A, L, y + 1, S, acc);
         if (y + 2 > ylast) break;
-        tb_iter<VEC, T, DIAG, 2>(A, L, y + 2, S, acc);
+        tb_iter<VEC, T, DIAG, UNIT, 2>(A, L, y + 2, S, acc);
         if (y + 3 > ylast) break;
-        tb_iter<VEC, T, DIAG, 3>(A, L, y + 3, S, acc);
+        tb_iter<VEC, T, DIAG, UNIT, 3>(A, L, y + 3, S, acc);
     }
 
     if constexpr (DIAG) {
@@ -943,12 +970,12 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T>& A, int64_t tile)
     }
 }
 
-template <int VEC, int T, bool DIAG>
+template <int VEC, int T, bool DIAG, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_tb2d(TBArgs<T> A)
 {
     const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     if (tile >= A.ntiles) return;
-    tb_tile<VEC, T, DIAG>(A, tile);
+    tb_tile<VEC, T, DIAG, UNIT>(A, tile);
 }
 
 // ------------------------------------------------------- batched ensemble --
@@ -1201,8 +1228,14 @@ template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
 hipError_t launch_t(const StepArgs& A, hipStream_t s)
 {
     const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL((k_step<D, VEC, TY, UPDATE, DIAG>), dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, A);
+    // the plain update with dx = 1 and phi0 = 1 skips two exact
+    // multiplications by 1 (same bits as the general form)
+    if (UPDATE && !DIAG && A.k.inv_dx2 == 1.0f && A.k.kc == 1.0f)
+        hipLaunchKernelGGL((k_step<D, VEC, TY, UPDATE, DIAG, true>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                           s, A);
+    else
+        hipLaunchKernelGGL((k_step<D, VEC, TY, UPDATE, DIAG, false>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                           s, A);
     return hipGetLastError();
 }
 
@@ -1530,9 +1563,11 @@ hipError_t launch_tb_t(const Geometry& g, const Tiling& t, const float* phi_in, 
     A.dc = dc;
     const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
     if (diag)
-        hipLaunchKernelGGL((k_tb2d<VEC, T, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL((k_tb2d<VEC, T, true, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else if (k[0].inv_dx2 == 1.0f && k[0].kc == 1.0f)
+        hipLaunchKernelGGL((k_tb2d<VEC, T, false, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
     else
-        hipLaunchKernelGGL((k_tb2d<VEC, T, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL((k_tb2d<VEC, T, false, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
     return hipGetLastError();
 }
 

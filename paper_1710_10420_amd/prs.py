@@ -136,6 +136,7 @@ _decl("prs_tuned_tiling", _i32, _P, ctypes.c_char_p, _i32, ctypes.POINTER(_i32),
       ctypes.POINTER(_i32))
 _decl("prs_set_time_blocking", _i32, _vp, _i32)
 _decl("prs_set_adjoint_tiling", _i32, _vp, _i32, _i32, _i32)
+_decl("prs_plan_passes", _i32, _vp, _i64, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64))
 _decl("prs_get_adjoint_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _decl("prs_get_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
@@ -150,7 +151,7 @@ EXPORTED = [
     "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy", "prs_batch_set_time_blocking",
     "prs_batch_state", "prs_autotune", "prs_tuned_tiling",
     "prs_set_time_blocking", "prs_get_time_blocking", "prs_set_adjoint_tiling",
-    "prs_get_adjoint_tiling",
+    "prs_get_adjoint_tiling", "prs_plan_passes",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -264,6 +265,14 @@ def prs_get_adjoint_tiling(ctx):
     _check(_lib.prs_get_adjoint_tiling(ctx, ctypes.byref(v), ctypes.byref(r), ctypes.byref(t)),
            "prs_get_adjoint_tiling")
     return v.value, r.value, t.value
+
+
+def prs_plan_passes(ctx, nsteps, with_records=True):
+    """(multi-step passes, single-step passes) prs_step_n would launch."""
+    m, n1 = _i64(), _i64()
+    _check(_lib.prs_plan_passes(ctx, nsteps, 1 if with_records else 0, ctypes.byref(m), ctypes.byref(n1)),
+           "prs_plan_passes")
+    return m.value, n1.value
 
 
 def prs_destroy(ctx):
