@@ -167,7 +167,8 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
  * value is read about once per T steps.  Results are bitwise those of single
  * steps.  The second phi_dot buffer this needs lives in the workspace; every
  * prs_step_n call still ends with phi_dot in the caller's dphi buffer.  3D
- * lattices support only 1 (PRS_EUNSUPPORTED otherwise). */
+ * lattices support only 1 (PRS_EUNSUPPORTED otherwise); 2D lattices with
+ * nx > 2^28 keep the setting but run single-step passes. */
 prs_status prs_set_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
 prs_status prs_get_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
 
@@ -268,8 +269,9 @@ prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
 /* Tiling of one item (vec and rows as in prs_set_tiling; ty must be 1). */
 prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
 
-/* Steps per pass of one item: 1, or 2 (the default for 2D items; 2D only).
- * The second phi_dot field two-step passes need lives in the workspace. */
+/* Steps per pass of one item: 1, or 2 (the default for 2D items; 2D items
+ * with nx <= 2^28 only, PRS_EUNSUPPORTED otherwise).  The second phi_dot
+ * field two-step passes need lives in the workspace. */
 prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass);
 
 /* Device pointers of item `item`'s final phi and phi_dot after prs_batch_run

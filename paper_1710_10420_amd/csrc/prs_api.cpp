@@ -304,7 +304,7 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int64_t K = c->p.diag_every;
     const int64_t end = c->step + nsteps;
 
-    const int T = (c->pi_alt != nullptr && c->til.ty == 1) ? c->tblock : 1;
+    const int T = (c->pi_alt != nullptr && c->til.ty == 1 && tb_supported(c->geo)) ? c->tblock : 1;
     const std::vector<uint8_t> plan = plan_passes(c->step, nsteps, T, want ? K : 0);
 
     float* pi_cur = c->pi;
@@ -366,7 +366,7 @@ prs_status prs_plan_passes(const prs_ctx* c, int64_t nsteps, int32_t with_record
                            int64_t* single_passes)
 {
     if (!c || nsteps < 0) return fail(PRS_EINVAL, "invalid arguments");
-    const int T = (c->pi_alt != nullptr && c->til.ty == 1) ? c->tblock : 1;
+    const int T = (c->pi_alt != nullptr && c->til.ty == 1 && tb_supported(c->geo)) ? c->tblock : 1;
     const int64_t K = (with_records && c->p.diag_every > 0) ? c->p.diag_every : 0;
     int64_t m = 0, n1 = 0;
     for (uint8_t L : plan_passes(c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
@@ -999,7 +999,7 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
         Tiling t = default_tiling(b->geo.back());
         t.ty = 1;
         b->til.push_back(t);
-        b->tblock.push_back(items[r].p.ndim == 2 ? 2 : 1);
+        b->tblock.push_back(tb_supported(b->geo.back()) ? 2 : 1);
     }
     b->mode = PRS_BATCH_PERSISTENT_GRAPH;
     int khz = 0;
@@ -1038,8 +1038,8 @@ prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps
     if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
     if (steps_per_pass != 1 && steps_per_pass != 2)
         return fail(PRS_EINVAL, "batched runs use 1 or 2 steps per pass");
-    if (steps_per_pass == 2 && b->items[item].p.ndim != 2)
-        return fail(PRS_EUNSUPPORTED, "two-step passes are implemented for 2D lattices");
+    if (steps_per_pass == 2 && !tb_supported(b->geo[item]))
+        return fail(PRS_EUNSUPPORTED, "two-step passes are implemented for 2D lattices with nx <= 2^28");
     b->tblock[item] = steps_per_pass;
     b->dirty = true;
     return PRS_OK;
@@ -1384,7 +1384,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
         }
         return hipSuccess;
     };
-    const int max_T = (!batch_set && c->pi_alt != nullptr) ? kMaxPassSteps : 1;
+    const int max_T = (!batch_set && c->pi_alt != nullptr && tb_supported(c->geo)) ? kMaxPassSteps : 1;
     int best_T = c->tblock;
     e = hipMemcpyAsync(save_phi, c->phi[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(save_pi, c->pi, bytes, hipMemcpyDeviceToDevice, c->stream);

@@ -72,6 +72,9 @@ hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const float* p
                        WavePartial* partials, const DiagCoef& dc, hipStream_t s);
 // Number of wave tiles (and partials) of a T-step pass.
 int64_t tb_tiles(const Geometry& g, const Tiling& t, int T);
+// Multi-step passes exist for 2D lattices whose rows are shorter than 2^28
+// sites (their loads and stores address a row with 32-bit byte offsets).
+bool tb_supported(const Geometry& g);
 
 // Reduces `count` partials in a fixed order into one record at `rec`.
 hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,

@@ -785,13 +785,6 @@ hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s)
 // of the tile.  Only level T is written.  All levels use the single-step
 // arithmetic, so the result is bitwise that of T single steps.
 
-__device__ __forceinline__ int64_t wrap_any(int64_t v, int64_t M)
-{
-    while (v < 0) v += M;
-    while (v >= M) v -= M;
-    return v;
-}
-
 template <int T>
 struct TBArgs {
     const float* phi_in;
@@ -820,34 +813,113 @@ struct TBState {
     float pl[T][2][VEC];       // level k phi_dot rows
 };
 
+// Per-wave constants of a tile.  Row numbers are wave-uniform 32-bit values
+// (a plane holds fewer than 2^31 sites), so all row arithmetic stays on the
+// scalar unit.  Rows are read and written through raw buffer descriptors made
+// per row (base = row start, size = row bytes): a lane's access is the
+// descriptor plus its column offset, an access with size 0 or an offset past
+// the row is dropped by the hardware, so every load and store is issued
+// unconditionally and the memory counters the compiler waits on follow one
+// straight-line pattern per iteration.
 struct TBLane {
-    int64_t x0;                // unwrapped first site of this lane
-    uint32_t xw;               // wrapped into [0, nx)
-    bool store;                // owned lane inside the lattice
-    int64_t s0, s1;
+    uint32_t voff;             // byte offset of this lane's first site, wrapped into the row
+    uint32_t soff;             // voff for owned lanes inside the lattice, else past the row
+    int32_t s0, s1;            // output rows [s0, s1) of the tile
     uint32_t nx;
-    int64_t M;
+    uint32_t row_bytes;
+    int32_t ny;
 };
 
-template <int VEC>
-__device__ __forceinline__ void tb_load(const float* __restrict__ f, int64_t y, const TBLane& L,
-                                        float (&v)[VEC])
+// Next rows to fetch, already wrapped into [0, ny); advanced by one row per
+// iteration without division.
+struct TBRows {
+    int32_t phi, pi;
+};
+
+__device__ __forceinline__ int32_t next_row(int32_t r, int32_t ny)
 {
-    load_vec<VEC>(f + wrap_any(y, L.M) * (int64_t)L.nx + L.xw, v);
+    return r + 1 == ny ? 0 : r + 1;
 }
 
-template <int VEC, int T, bool DIAG, bool UNIT, int U>
-__device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int64_t y,
-                                        TBState<VEC, T>& S, DiagAcc& acc)
+// Any row number into [0, ny) (tile set-up only).
+__device__ __forceinline__ int32_t wrap_row(int32_t r, int32_t ny)
 {
-    const int64_t ylast = L.s1 + T - 2;   // last iteration
-    // prefetch phi^n row y+2 and phi_dot row y+1
-    if (y + 2 <= L.s1 + T - 1) tb_load<VEC>(A.phi_in, y + 2, L, S.in[(U + 2) & 3]);
-    if (y + 1 <= ylast) tb_load<VEC>(A.pi_in, y + 1, L, S.pin[(U + 1) & 1]);
+    r %= ny;
+    return r < 0 ? r + ny : r;
+}
+
+// Word 3 of a raw (unswizzled, stride 0) buffer descriptor on CDNA.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+// Offset that no row reaches (rows are shorter than 2^30 bytes).
+constexpr uint32_t kPastRow = 0xFFFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* f, int32_t row, uint32_t nx,
+                                                           uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(f) + (size_t)((uint32_t)row * nx),
+                                             (short)0, (int)bytes, kRawBufferWord3);
+}
+
+template <int VEC>
+__device__ __forceinline__ void tb_load(const float* f, int32_t row, const TBLane& L, uint32_t bytes,
+                                        float (&v)[VEC])
+{
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(f, row, L.nx, bytes);
+    if constexpr (VEC == 4) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, L.voff, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = __uint_as_float(t[j]);
+    } else if constexpr (VEC == 2) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, L.voff, 0, 0);
+        v[0] = __uint_as_float(t[0]);
+        v[1] = __uint_as_float(t[1]);
+    } else {
+        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, L.voff, 0, 0));
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void tb_store(float* f, int32_t row, const TBLane& L, uint32_t bytes,
+                                         const float (&v)[VEC])
+{
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(f, row, L.nx, bytes);
+    if constexpr (VEC == 4) {
+        __attribute__((ext_vector_type(4))) unsigned int t;
+        t[0] = __float_as_uint(v[0]);
+        t[1] = __float_as_uint(v[1]);
+        t[2] = __float_as_uint(v[2]);
+        t[3] = __float_as_uint(v[3]);
+        __builtin_amdgcn_raw_buffer_store_b128(t, r, L.soff, 0, 0);
+    } else if constexpr (VEC == 2) {
+        __attribute__((ext_vector_type(2))) unsigned int t;
+        t[0] = __float_as_uint(v[0]);
+        t[1] = __float_as_uint(v[1]);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, L.soff, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, L.soff, 0, 0);
+    }
+}
+
+// Iteration i of the march (y = s0 - T + 1 + i): level k computes row
+// s0 - T - k + 2 + i.  Level k has work from i = 2(k-1) on, the last
+// iteration is i = last for every level.  CHECK skips the levels that have no
+// row yet (the first 2T-2 iterations); without it those levels run on rows
+// that only ever feed rows outside the tile, which are never stored.
+template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, int U>
+__device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int32_t i,
+                                        int32_t last, TBRows& R, TBState<VEC, T>& S, DiagAcc& acc)
+{
+    // prefetch phi^n row y+2 and phi_dot row y+1 for the next iteration
+    // (none after the last: size 0)
+    const uint32_t nb = i < last ? L.row_bytes : 0u;
+    tb_load<VEC>(A.phi_in, R.phi, L, nb, S.in[(U + 2) & 3]);
+    tb_load<VEC>(A.pi_in, R.pi, L, nb, S.pin[(U + 1) & 1]);
+    R.phi = next_row(R.phi, L.ny);
+    R.pi = next_row(R.pi, L.ny);
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
-        const int64_t r = y - k + 1;                     // row of level k
-        if (r < L.s0 - (T - k) || r > L.s1 - 1 + (T - k)) continue;
+        if (CHECK && i < 2 * (k - 1)) continue;
         const float* cm;
         const float* cc;
         const float* cp;
@@ -866,6 +938,8 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int
         float left = from_left_lane(cc[VEC - 1]);
         float right = from_right_lane(cc[0]);
         float out_phi[VEC], out_pi[VEC];
+        // level 1 row y is inside the tile for i in [T-1, T-1 + s1 - s0)
+        const bool diag_row = DIAG && k == 1 && i >= T - 1 && i < T - 1 + (L.s1 - L.s0);
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
             const float c = cc[j];
@@ -874,7 +948,7 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int
             const float lap = lap2<UNIT>(c, xm, xp, cm[j], cp[j], A.k[k - 1].inv_dx2);
             kick_drift<UNIT>(c, lap, pp[j], A.k[k - 1], out_pi[j], out_phi[j]);
             if constexpr (DIAG) {
-                if (k == 1 && L.store && r >= L.s0 && r < L.s1) {
+                if (diag_row && L.soff != kPastRow) {
                     const float nm[2] = {xm, cm[j]};
                     const float np[2] = {xp, cp[j]};
                     site_diag<2>(c, pp[j], nm, np, A.dc, acc);
@@ -887,12 +961,30 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int
                 S.lv[k < T ? k : 0][U & 3][j] = out_phi[j];
                 S.pl[k < T ? k : 0][U & 1][j] = out_pi[j];
             }
-        } else if (L.store && r >= L.s0 && r < L.s1) {
-            const int64_t off = r * (int64_t)L.nx + L.xw;
-            store_vec<VEC>(A.phi_out + off, out_phi);
-            store_vec<VEC>(A.pi_out + off, out_pi);
+        } else {
+            // level T row s0 + i - (2T - 2), inside [s0, s1) once i >= 2T - 2
+            const int32_t row = L.s0 + i - (2 * T - 2);
+            const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.row_bytes : 0u;
+            tb_store<VEC>(A.phi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_phi);
+            tb_store<VEC>(A.pi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_pi);
         }
     }
+}
+
+// Iterations i .. i+3 (i a multiple of 4, so ring slots are compile-time);
+// false once the last iteration has run.
+template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK>
+__device__ __forceinline__ bool tb_group(const TBArgs<T>& A, const TBLane& L, int32_t i,
+                                         int32_t last, TBRows& R, TBState<VEC, T>& S, DiagAcc& acc)
+{
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 0>(A, L, i, last, R, S, acc);
+    if (i + 1 > last) return false;
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 1>(A, L, i + 1, last, R, S, acc);
+    if (i + 2 > last) return false;
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 2>(A, L, i + 2, last, R, S, acc);
+    if (i + 3 > last) return false;
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 3>(A, L, i + 3, last, R, S, acc);
+    return i + 4 <= last;
 }
 
 // One wave's tile of a T-step pass; `tile` must be below A.ntiles and
@@ -902,18 +994,23 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T>& A, int64_t tile)
 {
     constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
     constexpr int W = (kWave - 2 * H) * VEC;       // owned sites per wave
+    constexpr int WARM = (2 * T - 2 + 3) / 4;      // groups that hold pipeline fill
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
     const uint32_t tx = tl % (uint32_t)A.tiles_x;
     const uint32_t ts = tl / (uint32_t)A.tiles_x;
     TBLane L;
     L.nx = (uint32_t)A.nx;
-    L.M = A.ny;
-    L.x0 = (int64_t)tx * W + (int64_t)(lane - H) * VEC;
-    L.xw = (uint32_t)wrap_any(L.x0, L.nx);
-    L.store = lane >= H && lane < kWave - H && L.x0 < (int64_t)L.nx;
-    L.s0 = (int64_t)ts * A.rows;
-    L.s1 = (L.s0 + A.rows) < A.ny ? (L.s0 + A.rows) : A.ny;
+    L.ny = (int32_t)A.ny;
+    L.row_bytes = L.nx * 4u;
+    const int32_t rows = (int32_t)A.rows;
+    // x0 < nx + 64 VEC fits in 32 bits; lanes past a narrow lattice wrap
+    // more than once and only load
+    const int32_t x0 = (int32_t)(tx * (uint32_t)W) + (lane - H) * VEC;
+    L.voff = (uint32_t)wrap_row(x0, (int32_t)L.nx) * 4u;
+    L.soff = (lane >= H && lane < kWave - H && x0 < (int32_t)L.nx) ? L.voff : kPastRow;
+    L.s0 = (int32_t)ts * rows;
+    L.s1 = L.s0 + rows < L.ny ? L.s0 + rows : L.ny;
 
     TBState<VEC, T> S;
 #pragma unroll
@@ -933,27 +1030,32 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T>& A, int64_t tile)
             for (int k = 0; k < T; ++k) S.pl[k][a][j] = 0.0f;
         }
 
-    // first iteration y0 = s0-T+1 needs phi^n rows y0-1, y0, y0+1 and phi_dot row y0
-    const int64_t y0 = L.s0 - T + 1;
-    tb_load<VEC>(A.phi_in, y0 - 1, L, S.in[3]);
-    tb_load<VEC>(A.phi_in, y0, L, S.in[0]);
-    tb_load<VEC>(A.phi_in, y0 + 1, L, S.in[1]);
-    tb_load<VEC>(A.pi_in, y0, L, S.pin[0]);
+    // iteration 0 (y0 = s0 - T + 1) needs phi^n rows y0-1 .. y0+1 and phi_dot row y0
+    const int32_t y0 = L.s0 - T + 1;
+    tb_load<VEC>(A.phi_in, wrap_row(y0 - 1, L.ny), L, L.row_bytes, S.in[3]);
+    tb_load<VEC>(A.phi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.in[0]);
+    tb_load<VEC>(A.phi_in, wrap_row(y0 + 1, L.ny), L, L.row_bytes, S.in[1]);
+    tb_load<VEC>(A.pi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.pin[0]);
+    TBRows R;
+    R.phi = wrap_row(y0 + 2, L.ny);
+    R.pi = wrap_row(y0 + 1, L.ny);
 
     DiagAcc acc;
     acc.links[0] = acc.links[1] = acc.links[2] = 0u;
     acc.walls = acc.nonfinite = 0u;
     acc.area = acc.ek = 0.0;
 
-    const int64_t ylast = L.s1 + T - 2;
-    for (int64_t y = y0; y <= ylast; y += 4) {
-        tb_iter<VEC, T, DIAG, UNIT, 0>(A, L, y, S, acc);
-        if (y + 1 > ylast) break;
-        tb_iter<VEC, T, DIAG, UNIT, 1>(A, L, y + 1, S, acc);
-        if (y + 2 > ylast) break;
-        tb_iter<VEC, T, DIAG, UNIT, 2>(A, L, y + 2, S, acc);
-        if (y + 3 > ylast) break;
-        tb_iter<VEC, T, DIAG, UNIT, 3>(A, L, y + 3, S, acc);
+    const int32_t last = (L.s1 - L.s0) + 2 * T - 3;
+    int32_t i = 0;
+    bool more = true;
+#pragma unroll
+    for (int w = 0; w < WARM; ++w) {
+        if (more) more = tb_group<VEC, T, DIAG, UNIT, true>(A, L, i, last, R, S, acc);
+        i += 4;
+    }
+    while (more) {
+        more = tb_group<VEC, T, DIAG, UNIT, false>(A, L, i, last, R, S, acc);
+        i += 4;
     }
 
     if constexpr (DIAG) {
@@ -1584,6 +1686,11 @@ hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const float* p
     return hipErrorInvalidValue;
 }
 
+bool tb_supported(const Geometry& g)
+{
+    return g.ndim == 2 && g.nx <= ((int64_t)1 << 28);
+}
+
 int64_t tb_tiles(const Geometry& g, const Tiling& t, int T)
 {
     const int64_t W = tb_owned_width(t.vec, T);
@@ -1594,7 +1701,7 @@ hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const float* p
                        const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
                        WavePartial* partials, const DiagCoef& dc, hipStream_t s)
 {
-    if (g.ndim != 2 || t.ty != 1) return hipErrorInvalidValue;
+    if (!tb_supported(g) || t.ty != 1) return hipErrorInvalidValue;
     switch (t.vec) {
     case 1: return launch_tb_v<1>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     case 2: return launch_tb_v<2>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
