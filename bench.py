@@ -150,41 +150,57 @@ def adjoint_leg(prs, torch, reps=3):
 
 def batch_leg(prs, torch, reps=2):
     """The seeded ensemble: 48 2D realisations (512^2/1024^2/2048^2) and 16 3D
-    (128^3/256^3), m in {0.5,1,2}, W0 in {5,10}, each to eta = N/2, run as one
-    persistent launch replayed from a hipGraph."""
+    (128^3/256^3), m in {0.5,1,2}, W0 in {5,10}, each to eta = N/2.  Each
+    realisation runs its tuned single-run pass sequence (tiling and steps per
+    pass) on one of four concurrent streams.  The one-launch persistent mode
+    (replayed from a hipGraph) is timed beside it."""
     from paper_1710_10420_amd.inputs import ensemble_draw
     items = ensemble_draw(2017)
     specs = [dict(shape=(it["N"],) * it["ndim"], deta=it["deta"], m=it["m"], W0=it["W0"],
                   nsteps=it["steps"], diag_every=64 if it["ndim"] == 2 else 50, seed=it["seed"])
              for it in items]
     b = prs.Batch(specs)
-    tuned = {}
-    for r, sp in enumerate(specs):            # one tuning per distinct lattice
-        key = sp["shape"]
-        if key not in tuned:
-            p = prs.make_params(sp["shape"], deta=sp["deta"], m=sp["m"], W0=sp["W0"])
-            t = prs.Sim(p, seed=1)
-            prs.prs_autotune(t.ctx, None, prs.PRS_TUNE_BATCH)
-            tuned[key] = t.tiling()
-            t.close()
-        b.set_tiling(r, *tuned[key])
     su = float(sum(int(np.prod(sp["shape"])) * sp["nsteps"] for sp in specs))
-    b.run()                                   # builds and instantiates the graph
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        recs = b.run()
-        times.append(time.perf_counter() - t0)
-    t = min(times)
+
+    def timed(mode, flags):
+        tuned = {}
+        for r, sp in enumerate(specs):            # one tuning per distinct lattice
+            key = sp["shape"]
+            if key not in tuned:
+                p = prs.make_params(sp["shape"], deta=sp["deta"], m=sp["m"], W0=sp["W0"])
+                t = prs.Sim(p, seed=1)
+                prs.prs_autotune(t.ctx, None, flags)
+                tuned[key] = (t.tiling(), t.time_blocking() if len(key) == 2 else 1)
+                t.close()
+            til, T = tuned[key]
+            b.set_time_blocking(r, 1)
+            b.set_tiling(r, *til)
+            b.set_time_blocking(r, T if mode in (prs.PRS_BATCH_STREAMS_GRAPH, prs.PRS_BATCH_STREAMS)
+                                else min(2, 2 if len(key) == 2 else 1))
+        b.set_mode(mode)
+        b.run()                                   # builds and instantiates the graph
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            recs = b.run()
+            times.append(time.perf_counter() - t0)
+        return min(times), recs, tuned
+
+    t_p, _, tuned_p = timed(prs.PRS_BATCH_PERSISTENT_GRAPH, prs.PRS_TUNE_BATCH)
+    t, recs, tuned = timed(prs.PRS_BATCH_STREAMS, 0)
     out = {"workload": "ensemble of 64 realisations (master seed 2017): 48 2D from "
                        "{512^2,1024^2,2048^2}, 16 3D from {128^3,256^3}, m in {0.5,1,2}, "
                        "W0 in {5,10}, each to eta = N/2, diagnostics every 64 (2D) / 50 (3D)",
            "realisations": len(specs), "site_updates": su, "ms_per_run": t * 1e3,
            "site_updates_per_s": su / t, "hbm_frac": su * 16 / t / (HBM_PEAK_GBS * 1e9),
-           "records": sum(len(r) for r in recs), "mode": "persistent+hipGraph",
-           "tilings": {"x".join(map(str, k)): list(v) for k, v in tuned.items()}}
-    log("batch %.1f ms" % (t * 1e3))
+           "records": sum(len(r) for r in recs), "mode": "4 concurrent streams",
+           "tilings": {"x".join(map(str, k)): {"tiling": list(v[0]), "steps_per_pass": v[1]}
+                       for k, v in tuned.items()},
+           "persistent_kernel": {"ms_per_run": t_p * 1e3, "site_updates_per_s": su / t_p,
+                                 "tilings": {"x".join(map(str, k)): list(v[0])
+                                             for k, v in tuned_p.items()}}}
+    log("batch %.1f ms (persistent kernel %.1f ms)" % (t * 1e3, t_p * 1e3))
     b.close()
     return out
 

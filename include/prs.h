@@ -150,7 +150,9 @@ prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty
  * or updated; NULL or "" for no cache).  A cached entry for the same GPU
  * architecture, dimension, lattice size and tiling set is applied without
  * timing unless flags has PRS_TUNE_FORCE.  PRS_TUNE_BATCH restricts the
- * candidates to the tilings batched runs support.  *best_us (may be NULL)
+ * candidates to the tilings the persistent batch modes support (ty = 1, single
+ * steps); the STREAMS batch modes take the ordinary choice (tiling and steps
+ * per pass).  *best_us (may be NULL)
  * receives the time of one step with the chosen tiling.  Synchronises. */
 #define PRS_TUNE_FORCE 1
 #define PRS_TUNE_BATCH 2
@@ -247,9 +249,18 @@ typedef struct prs_batch_item {
 
 typedef struct prs_batch prs_batch;
 
-#define PRS_BATCH_PERSISTENT_GRAPH 0  /* one persistent launch, captured in a hipGraph (default) */
+/* Execution modes.  STREAMS runs every realisation with the single-run pass
+ * sequence (its own tiling and steps per pass, up to 4 in 2D) on one of a few
+ * concurrent streams, realisations assigned longest-first to the least
+ * loaded stream (the default); STREAMS_GRAPH captures that launch sequence
+ * once in a hipGraph and replays it.  The PERSISTENT modes run all
+ * realisations inside one persistent kernel with a grid barrier per phase;
+ * they take tilings with ty = 1 and at most 2 steps per pass. */
+#define PRS_BATCH_PERSISTENT_GRAPH 0  /* one persistent launch, captured in a hipGraph */
 #define PRS_BATCH_PERSISTENT 1        /* the same launch sequence without the graph */
-#define PRS_BATCH_PER_STEP 2          /* one launch per step over all realisations */
+#define PRS_BATCH_PER_STEP 2          /* one launch per phase over all realisations */
+#define PRS_BATCH_STREAMS_GRAPH 3     /* concurrent streams, captured in a hipGraph */
+#define PRS_BATCH_STREAMS 4           /* concurrent streams, launched directly (default) */
 
 /* Device workspace (descriptors, coefficient and pass tables, the second
  * phi_dot field of 2D items, record partials and the records themselves); 0 if
@@ -266,12 +277,13 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
  * offsets has count+1 entries. */
 prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
 
-/* Tiling of one item (vec and rows as in prs_set_tiling; ty must be 1). */
+/* Tiling of one item (as prs_set_tiling; the persistent modes need ty = 1). */
 prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
 
-/* Steps per pass of one item: 1, or 2 (the default for 2D items; 2D items
- * with nx <= 2^28 only, PRS_EUNSUPPORTED otherwise).  The second phi_dot
- * field two-step passes need lives in the workspace. */
+/* Steps per pass of one item: 1 .. 4 (2 is the default for 2D items; more
+ * than 1 for 2D items with nx <= 2^28 only, PRS_EUNSUPPORTED otherwise; the
+ * persistent modes take at most 2).  The second phi_dot field multi-step
+ * passes need lives in the workspace. */
 prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass);
 
 /* Device pointers of item `item`'s final phi and phi_dot after prs_batch_run
@@ -283,7 +295,8 @@ prs_status prs_batch_set_mode(prs_batch* b, int32_t mode);
  * records) and synchronises the stream.  series may be NULL; otherwise cap
  * must hold offsets[count] records.  The persistent kernel's grid barrier
  * waits at most 5 s per step; if the grid is not co-resident the run stops
- * with PRS_EDEVICE instead of hanging. */
+ * with PRS_EDEVICE instead of hanging.  PRS_EINVAL if the mode cannot run an
+ * item's tiling or steps per pass. */
 prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap);
 
 void prs_batch_destroy(prs_batch* b);

@@ -731,7 +731,7 @@ struct prs_batch {
     std::vector<prs_batch_item> items;
     std::vector<Geometry> geo;
     std::vector<Tiling> til;
-    std::vector<int32_t> tblock;        // steps per pass (1, or 2 for 2D items)
+    std::vector<int32_t> tblock;        // steps per pass (1 .. 4; more than 1 for 2D items only)
     std::vector<int64_t> npasses;       // per item, including the final record pass
     std::vector<int64_t> rec_off;       // count + 1 record offsets
     std::vector<int64_t> part_cap;      // partial capacity per realisation
@@ -746,12 +746,16 @@ struct prs_batch {
     int32_t mode;
     int grid_blocks;
     uint64_t timeout_ticks;
-    bool dirty;          // descriptors need uploading / graph rebuilding
+    bool dirty;          // persistent-mode descriptors need uploading
     hipGraph_t graph;
     hipGraphExec_t exec;
     hipStream_t capture;  // private stream the graph is captured on (the
                           // caller's stream may be the legacy NULL stream,
                           // which cannot be captured)
+    int32_t graph_mode;   // mode the graph was captured for
+    std::vector<hipStream_t> workers;   // concurrent streams (STREAMS modes)
+    hipEvent_t ev_fork;
+    std::vector<hipEvent_t> ev_join;
 };
 
 namespace {
@@ -822,36 +826,19 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
     return PRS_OK;
 }
 
-// Pass table of one realisation: passes of up to T steps (never with a
-// recorded state inside), an even number of two-step passes (phi_dot ends in
-// the caller's buffer), then the diagnostics-only pass of the final state.
+// Pass table of one realisation: the single-run pass plan (up to T steps
+// per pass, no recorded state inside a pass, an even number of multi-step
+// passes so phi_dot ends in the caller's buffer), then the diagnostics-only
+// pass of the final state.
 std::vector<PassEntry> batch_plan(const prs_batch_item& it, int T)
 {
     const int64_t S = it.nsteps, K = it.p.diag_every;
-    std::vector<int> len;
-    int64_t nmulti = 0;
-    for (int64_t n = 0; n < S;) {
-        int64_t L = std::min<int64_t>(T, S - n);
-        if (K > 0) L = std::min<int64_t>(L, (n / K + 1) * K - n);
-        len.push_back((int)L);
-        nmulti += L > 1 ? 1 : 0;
-        n += L;
-    }
-    if (nmulti % 2 == 1) {
-        for (size_t i = len.size(); i-- > 0;)
-            if (len[i] > 1) {
-                const int L = len[i];
-                len.erase(len.begin() + (std::ptrdiff_t)i);
-                len.insert(len.begin() + (std::ptrdiff_t)i, (size_t)L, 1);
-                break;
-            }
-    }
     std::vector<PassEntry> out;
     int64_t n = 0, rec = 0;
     int alt = 0;
-    for (int L : len) {
+    for (uint8_t L : plan_passes(0, S, T, K)) {
         const bool r = K > 0 && n % K == 0;
-        out.push_back(PassEntry{(int32_t)n, L, r ? (int32_t)rec++ : -1, alt});
+        out.push_back(PassEntry{(int32_t)n, (int32_t)L, r ? (int32_t)rec++ : -1, alt});
         if (L > 1) alt ^= 1;
         n += L;
     }
@@ -865,6 +852,170 @@ void batch_release_graph(prs_batch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+}
+
+bool persistent_mode(int32_t mode)
+{
+    return mode == PRS_BATCH_PERSISTENT_GRAPH || mode == PRS_BATCH_PERSISTENT || mode == PRS_BATCH_PER_STEP;
+}
+
+// Most wave tiles any pass of an item can have (single steps and, for T > 1,
+// T-step passes), which its partial buffer must hold.
+int64_t item_tiles_max(const Geometry& g, const Tiling& t, int T)
+{
+    int64_t n = tile_counts(g, t).ntiles;
+    if (T > 1) n = std::max<int64_t>(n, tb_tiles(g, t, T));
+    return n;
+}
+
+// Streams the STREAMS modes run on: one per hardware queue a process gets by
+// default.  Created once per ensemble, at the default priority.
+constexpr int kBatchStreams = 4;
+
+prs_status batch_streams_ready(prs_batch* b)
+{
+    if (!b->workers.empty()) return PRS_OK;
+    const int ns = std::min<int>(kBatchStreams, b->count);
+    HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "event create");
+    for (int i = 0; i < ns; ++i) {
+        hipStream_t w = nullptr;
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&w, hipStreamNonBlocking), "stream create");
+        b->workers.push_back(w);
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
+        b->ev_join.push_back(e);
+    }
+    return PRS_OK;
+}
+
+// One realisation's launch sequence on a stream, pass by pass: the pass
+// table of batch_plan (up to T steps per pass, records on the pass that
+// starts at a recorded state, the final state last), with the single-run
+// kernels, each record reduced into its slot of the device record array.
+struct ItemCursor {
+    int32_t item;
+    std::vector<PassEntry> plan;
+    size_t next;
+    prs_ctx coef;            // parameters for the coefficient schedule
+};
+
+prs_status batch_item_begin(prs_batch* b, int32_t r, ItemCursor& cur, hipStream_t s)
+{
+    const prs_batch_item& it = b->items[r];
+    cur.item = r;
+    cur.plan = batch_plan(it, b->tblock[r]);
+    cur.next = 0;
+    cur.coef = prs_ctx{};
+    cur.coef.p = it.p;
+    cur.coef.V0 = v0_of(it.p);
+    if (it.init_from_seed) {
+        const int64_t n = sites_of(it.p);
+        HIP_TRY(launch_fill_uniform(static_cast<float*>(it.phi_a), n, it.seed, s), "fill launch");
+        HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), n, s), "zero launch");
+    }
+    return PRS_OK;
+}
+
+prs_status batch_item_pass(prs_batch* b, ItemCursor& cur, hipStream_t s)
+{
+    const int32_t r = cur.item;
+    const prs_batch_item& it = b->items[r];
+    const Geometry& g = b->geo[r];
+    const Tiling& t = b->til[r];
+    const size_t idx = cur.next++;
+    const PassEntry& e = cur.plan[idx];
+    char* base = static_cast<char*>(b->ws);
+    float* phi[2] = {static_cast<float*>(it.phi_a), static_cast<float*>(it.phi_b)};
+    float* dphi = static_cast<float*>(it.dphi);
+    float* alt = it.p.ndim == 2 ? reinterpret_cast<float*>(base + b->off_alt + b->alt_off[r]) : nullptr;
+    float* pi_now = e.alt ? alt : dphi;
+    float* pi_next = e.alt ? dphi : alt;
+    const bool diag = e.rec >= 0;
+    WavePartial* parts = diag ? reinterpret_cast<WavePartial*>(base + b->off_part + b->part_off[r]) : nullptr;
+    const DiagCoef dc = diag_coef(&cur.coef);
+    const int64_t n = e.first;
+    float* phi_in = phi[idx & 1];
+    float* phi_out = phi[(idx + 1) & 1];
+    int64_t ntiles = tile_counts(g, t).ntiles;
+    if (e.steps > 1) {
+        StepCoef k[kMaxPassSteps];
+        for (int i = 0; i < e.steps; ++i) k[i] = coef_for(&cur.coef, n + i);
+        HIP_TRY(launch_tb2d(e.steps, g, t, phi_in, phi_out, pi_now, pi_next, k, diag, parts, dc, s),
+                "multi-step kernel launch");
+        ntiles = tb_tiles(g, t, e.steps);
+    } else if (e.steps == 1) {
+        HIP_TRY(launch_step(g, t, phi_in, phi_out, pi_now, pi_now, coef_for(&cur.coef, n), true, diag, parts, dc,
+                            s),
+                "step kernel launch");
+    } else {
+        HIP_TRY(launch_step(g, t, phi_in, nullptr, pi_now, nullptr, coef_for(&cur.coef, n), false, true, parts, dc,
+                            s),
+                "diagnostics kernel launch");
+    }
+    if (diag) {
+        prs_stats* recs = reinterpret_cast<prs_stats*>(base + b->off_rec) + b->rec_off[r];
+        HIP_TRY(launch_finalize(parts, ntiles, recs + e.rec, n, it.p.eta0 + (double)n * it.p.deta,
+                                area_scale(it.p), s),
+                "finalize launch");
+    }
+    return PRS_OK;
+}
+
+// The whole ensemble over the worker streams, forked from and joined back
+// into `main`: realisations longest-first onto the least loaded stream, the
+// launches interleaved across streams in chunks so every stream starts at
+// once, then the records to pinned host memory.
+prs_status batch_enqueue_streams(prs_batch* b, hipStream_t main)
+{
+    prs_status st = batch_streams_ready(b);
+    if (st != PRS_OK) return st;
+    const int ns = (int)b->workers.size();
+    HIP_TRY(hipEventRecord(b->ev_fork, main), "fork event");
+    for (hipStream_t w : b->workers) HIP_TRY(hipStreamWaitEvent(w, b->ev_fork, 0), "fork wait");
+
+    std::vector<int32_t> order((size_t)b->count);
+    for (int32_t r = 0; r < b->count; ++r) order[(size_t)r] = r;
+    auto cost = [&](int32_t r) { return (double)sites_of(b->items[r].p) * (double)(b->items[r].nsteps + 1); };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+    std::vector<std::vector<int32_t>> queue((size_t)ns);
+    std::vector<double> load((size_t)ns, 0.0);
+    for (int32_t r : order) {
+        const size_t w = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        queue[w].push_back(r);
+        load[w] += cost(r);
+    }
+
+    constexpr int kChunk = 16;   // passes per stream per round
+    std::vector<ItemCursor> cur((size_t)ns);
+    std::vector<size_t> qpos((size_t)ns, 0);
+    std::vector<bool> busy((size_t)ns, false);
+    bool any = true;
+    while (any) {
+        any = false;
+        for (int w = 0; w < ns; ++w) {
+            for (int c = 0; c < kChunk; ++c) {
+                if (!busy[(size_t)w]) {
+                    if (qpos[(size_t)w] >= queue[(size_t)w].size()) break;
+                    st = batch_item_begin(b, queue[(size_t)w][qpos[(size_t)w]++], cur[(size_t)w],
+                                          b->workers[(size_t)w]);
+                    if (st != PRS_OK) return st;
+                    busy[(size_t)w] = true;
+                }
+                st = batch_item_pass(b, cur[(size_t)w], b->workers[(size_t)w]);
+                if (st != PRS_OK) return st;
+                if (cur[(size_t)w].next >= cur[(size_t)w].plan.size()) busy[(size_t)w] = false;
+            }
+            if (busy[(size_t)w] || qpos[(size_t)w] < queue[(size_t)w].size()) any = true;
+        }
+    }
+    for (int w = 0; w < ns; ++w) {
+        HIP_TRY(hipEventRecord(b->ev_join[(size_t)w], b->workers[(size_t)w]), "join event");
+        HIP_TRY(hipStreamWaitEvent(main, b->ev_join[(size_t)w], 0), "join wait");
+    }
+    char* base = static_cast<char*>(b->ws);
+    HIP_TRY(hipMemcpyAsync(b->hrec, base + b->off_rec, (size_t)b->total_recs * sizeof(prs_stats),
+                           hipMemcpyDeviceToHost, main), "record copy");
+    return PRS_OK;
 }
 
 prs_status batch_upload(prs_batch* b)
@@ -1001,7 +1152,8 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
         b->til.push_back(t);
         b->tblock.push_back(tb_supported(b->geo.back()) ? 2 : 1);
     }
-    b->mode = PRS_BATCH_PERSISTENT_GRAPH;
+    b->mode = PRS_BATCH_STREAMS;
+    b->graph_mode = -1;
     int khz = 0;
     hipError_t e = batch_max_blocks(&b->grid_blocks);
     if (e == hipSuccess) e = batch_clock_rate_khz(&khz);
@@ -1024,11 +1176,12 @@ prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t
 {
     if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
     Tiling t{vec, rows, ty};
-    if (!batch_tiling_supported(b->geo[item], t))
-        return fail(PRS_EINVAL, "tiling vec=%d rows=%d ty=%d not available in batched runs", vec, rows, ty);
-    if (batch_tiles_max(b->geo[item], t) > b->part_cap[item])
+    if (!tiling_supported(b->geo[item], t))
+        return fail(PRS_EINVAL, "tiling vec=%d rows=%d ty=%d not available for item %d", vec, rows, ty, item);
+    if (item_tiles_max(b->geo[item], t, std::max(2, b->tblock[item])) > b->part_cap[item])
         return fail(PRS_EINVAL, "tiling has more wave tiles than the workspace holds");
     b->til[item] = t;
+    batch_release_graph(b);
     b->dirty = true;
     return PRS_OK;
 }
@@ -1036,11 +1189,14 @@ prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t
 prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass)
 {
     if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
-    if (steps_per_pass != 1 && steps_per_pass != 2)
-        return fail(PRS_EINVAL, "batched runs use 1 or 2 steps per pass");
-    if (steps_per_pass == 2 && !tb_supported(b->geo[item]))
-        return fail(PRS_EUNSUPPORTED, "two-step passes are implemented for 2D lattices with nx <= 2^28");
+    if (steps_per_pass < 1 || steps_per_pass > kMaxPassSteps)
+        return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
+    if (steps_per_pass > 1 && !tb_supported(b->geo[item]))
+        return fail(PRS_EUNSUPPORTED, "multi-step passes are implemented for 2D lattices with nx <= 2^28");
+    if (item_tiles_max(b->geo[item], b->til[item], std::max(2, steps_per_pass)) > b->part_cap[item])
+        return fail(PRS_EINVAL, "steps per pass need more wave tiles than the workspace holds");
     b->tblock[item] = steps_per_pass;
+    batch_release_graph(b);
     b->dirty = true;
     return PRS_OK;
 }
@@ -1048,7 +1204,7 @@ prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps
 prs_status prs_batch_set_mode(prs_batch* b, int32_t mode)
 {
     if (!b) return fail(PRS_EINVAL, "batch is NULL");
-    if (mode != PRS_BATCH_PERSISTENT_GRAPH && mode != PRS_BATCH_PERSISTENT && mode != PRS_BATCH_PER_STEP)
+    if (!persistent_mode(mode) && mode != PRS_BATCH_STREAMS_GRAPH && mode != PRS_BATCH_STREAMS)
         return fail(PRS_EINVAL, "unknown batch mode %d", mode);
     b->mode = mode;
     return PRS_OK;
@@ -1077,19 +1233,31 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     if (!b) return fail(PRS_EINVAL, "batch is NULL");
     if (series && cap < b->total_recs)
         return fail(PRS_EINVAL, "series capacity %lld < %lld records", (long long)cap, (long long)b->total_recs);
-    if (b->dirty) {
-        batch_release_graph(b);
+    const bool persistent = persistent_mode(b->mode);
+    if (persistent) {
+        for (int32_t r = 0; r < b->count; ++r)
+            if (b->til[r].ty != 1 || b->tblock[r] > 2)
+                return fail(PRS_EINVAL, "item %d: the persistent modes need ty = 1 and at most 2 steps per pass",
+                            r);
+    }
+    if (b->graph_mode != b->mode) batch_release_graph(b);
+    if (b->dirty && persistent) {
         prs_status st = batch_upload(b);
         if (st != PRS_OK) return st;
         b->dirty = false;
     }
     *b->herr = 0;
-    if (b->mode == PRS_BATCH_PERSISTENT_GRAPH) {
+    const bool graph = b->mode == PRS_BATCH_PERSISTENT_GRAPH || b->mode == PRS_BATCH_STREAMS_GRAPH;
+    if (graph) {
         if (!b->exec) {
             if (!b->capture)
                 HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+            if (!persistent) {
+                prs_status st = batch_streams_ready(b);
+                if (st != PRS_OK) return st;
+            }
             HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "graph capture");
-            prs_status st = batch_enqueue(b, true, b->capture);
+            prs_status st = persistent ? batch_enqueue(b, true, b->capture) : batch_enqueue_streams(b, b->capture);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(b->capture, &g);
             if (st != PRS_OK) {
@@ -1103,10 +1271,14 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
                 batch_release_graph(b);
                 return hip_fail(e, "graph instantiate");
             }
+            b->graph_mode = b->mode;
         }
         HIP_TRY(hipGraphLaunch(b->exec, b->stream), "graph launch");
-    } else {
+    } else if (persistent) {
         prs_status st = batch_enqueue(b, b->mode == PRS_BATCH_PERSISTENT, b->stream);
+        if (st != PRS_OK) return st;
+    } else {
+        prs_status st = batch_enqueue_streams(b, b->stream);
         if (st != PRS_OK) return st;
     }
     HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
@@ -1121,6 +1293,9 @@ void prs_batch_destroy(prs_batch* b)
     if (!b) return;
     batch_release_graph(b);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (hipStream_t w : b->workers) (void)hipStreamDestroy(w);
+    for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->hrec) (void)hipHostFree(b->hrec);
     if (b->herr) (void)hipHostFree(b->herr);
     delete b;

@@ -89,6 +89,8 @@ class prs_batch_item(ctypes.Structure):
 PRS_BATCH_PERSISTENT_GRAPH = 0
 PRS_BATCH_PERSISTENT = 1
 PRS_BATCH_PER_STEP = 2
+PRS_BATCH_STREAMS_GRAPH = 3
+PRS_BATCH_STREAMS = 4
 
 _P = ctypes.POINTER(prs_params)
 _S = ctypes.POINTER(prs_stats)

@@ -1,7 +1,9 @@
 """Batched ensemble: every realisation inside the batch reproduces the same
 realisation run alone (fields, counts and records bit for bit with the same
-tiling), for uneven sizes, dimensions, eras and step counts, in every launch
-mode, and across graph replays."""
+tiling and steps per pass), for uneven sizes, dimensions, eras and step
+counts, in every launch mode (persistent kernel with and without a graph, one
+launch per phase, concurrent streams with and without a graph), across graph
+replays and mode switches."""
 import numpy as np
 import pytest
 
@@ -59,7 +61,7 @@ def make_batch(prs):
     return b
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4])
 def test_batch_equals_single_runs(singles, mode):
     say("batch mode", mode)
     prs = gpu_prs()
@@ -109,3 +111,84 @@ def test_batch_rejects_invalid_item():
     with pytest.raises(prs.PRSError) as e:
         prs.Batch([SPECS[1], bad])
     assert e.value.status == prs.PRS_EINVAL and "item 1" in str(e.value)
+
+
+# Settings only the stream modes run: 3 and 4 steps per pass in 2D, 3D tiles
+# of 2 and 4 rows.
+SPECS_WIDE = [
+    dict(shape=(256, 256), deta=0.25, m=0.5, W0=5.0, nsteps=50, diag_every=10, seed=2000, T=4),
+    dict(shape=(300, 70), deta=0.25, m=1.0, W0=10.0, nsteps=37, diag_every=8, seed=2001, T=3),
+    dict(shape=(40, 30, 20), deta=0.2, m=1.0, W0=5.0, nsteps=23, diag_every=5, seed=2002),
+    dict(shape=(64, 64, 64), deta=0.2, m=0.5, W0=10.0, nsteps=31, diag_every=10, seed=2003),
+    dict(shape=(512, 128), deta=0.25, m=2.0, W0=10.0, nsteps=61, diag_every=0, seed=2004, T=4),
+    dict(shape=(96, 90), deta=0.25, m=1.0, W0=10.0, nsteps=9, diag_every=3, seed=2005, T=4),
+]
+TILINGS_WIDE = [(1, 16, 1), (2, 8, 1), (2, 16, 2), (1, 32, 4), (4, 16, 1), (2, 8, 1)]
+
+
+@pytest.fixture(scope="module")
+def singles_wide():
+    prs = gpu_prs()
+    out = []
+    for sp, t in zip(SPECS_WIDE, TILINGS_WIDE):
+        say("single", sp["shape"], sp["nsteps"], t, steps_per_pass(sp))
+        out.append(single_run(prs, sp, t))
+    return out
+
+
+@pytest.mark.parametrize("mode", [3, 4])
+def test_stream_modes_wide_settings(singles_wide, mode):
+    say("stream batch mode", mode)
+    prs = gpu_prs()
+    b = prs.Batch(SPECS_WIDE)
+    for r, t in enumerate(TILINGS_WIDE):
+        b.set_tiling(r, *t)
+        b.set_time_blocking(r, steps_per_pass(SPECS_WIDE[r]))
+    b.set_mode(mode)
+    for rep in range(3):
+        recs = b.run()
+        for r in range(len(SPECS_WIDE)):
+            phi, dphi = b.final_state(r)
+            s_phi, s_dphi, s_recs = singles_wide[r]
+            np.testing.assert_array_equal(host(phi), s_phi)
+            np.testing.assert_array_equal(host(dphi), s_dphi)
+            if SPECS_WIDE[r]["diag_every"] > 0:
+                assert recs[r] == s_recs, (mode, rep, r)
+            else:
+                assert recs[r] == s_recs[-1:], (mode, rep, r)
+    b.close()
+
+
+def test_persistent_modes_reject_stream_only_settings():
+    prs = gpu_prs()
+    b = prs.Batch(SPECS_WIDE[:3])
+    b.set_tiling(0, 1, 16, 1)
+    b.set_time_blocking(0, 4)
+    b.set_mode(prs.PRS_BATCH_PERSISTENT)
+    with pytest.raises(prs.PRSError) as e:
+        b.run()
+    assert e.value.status == prs.PRS_EINVAL and "item 0" in str(e.value)
+    b.set_time_blocking(0, 2)
+    b.set_tiling(2, 2, 16, 2)
+    with pytest.raises(prs.PRSError) as e:
+        b.run()
+    assert e.value.status == prs.PRS_EINVAL and "item 2" in str(e.value)
+    b.close()
+
+
+def test_mode_switches_keep_results(singles):
+    """Stream, persistent and graph modes in turn on one ensemble: each run
+    reproduces the single runs."""
+    say("batch mode switches")
+    prs = gpu_prs()
+    b = make_batch(prs)
+    for mode in (4, 0, 3, 1, 3, 2, 0):
+        b.set_mode(mode)
+        recs = b.run()
+        for r in range(len(SPECS)):
+            phi, dphi = b.final_state(r)
+            s_phi, s_dphi, s_recs = singles[r]
+            np.testing.assert_array_equal(host(phi), s_phi)
+            np.testing.assert_array_equal(host(dphi), s_dphi)
+            assert recs[r] == s_recs, (mode, r)
+    b.close()
