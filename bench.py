@@ -205,6 +205,42 @@ def batch_leg(prs, torch, reps=2):
     return out
 
 
+F64_STEPS = 2048
+
+
+def f64_leg(prs, torch, w, reps=2):
+    """The same 8192^2 lattice in float64 (the paper runs both precisions):
+    the first 2048 steps of the run with its fused records, autotuned tiling
+    and steps per pass; algorithmic bytes 32 per site-update."""
+    p = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"], diag_every=w["diag_every"],
+                        precision=prs.PRS_F64)
+    sim = prs.Sim(p, seed=w["seed"])
+    prs.prs_autotune(sim.ctx, None, 0)
+    phi0 = sim.state()[0].clone()
+    stream = torch.cuda.current_stream()
+    times = []
+    for r in range(reps + 1):
+        sim.set_state(phi0, torch.zeros_like(phi0), 0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step_n(F64_STEPS)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1) / 1e3)
+    t = min(times)
+    su = float(prs.sites(p)) * F64_STEPS
+    out = {"workload": "8192^2 in float64, first %d steps of the run (records every 64)" % F64_STEPS,
+           "site_updates_per_s": su / t, "ms": t * 1e3, "bytes_per_site_update": 32,
+           "hbm_frac_algorithmic": su * 32 / t / (HBM_PEAK_GBS * 1e9),
+           "tiling": list(sim.tiling()), "steps_per_pass": sim.time_blocking()}
+    log("f64 %.1f ms for %d steps" % (t * 1e3, F64_STEPS))
+    sim.close()
+    del phi0
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +343,7 @@ def main():
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_leg(prs, torch)
         out["batch"] = batch_leg(prs, torch)
+        out["f64"] = f64_leg(prs, torch, w)
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)

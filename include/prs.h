@@ -22,10 +22,12 @@
  * ---------------------------------------
  * - All functions are extern "C", never throw and return a prs_status.  On
  *   failure prs_last_error() holds a message (thread local).
- * - Fields are float32 device arrays (HBM) of n[0]*n[1]*n[2] sites (n[2] = 1
- *   in 2D), x fastest: site (x,y,z) is element x + nx*(y + ny*z).  Boundaries
- *   are periodic.  Field pointers must be 16-byte aligned.  The caller owns
- *   every device buffer it passes; the library never frees them.
+ * - Fields are device arrays (HBM) of n[0]*n[1]*n[2] sites (n[2] = 1 in 2D),
+ *   x fastest: site (x,y,z) is element x + nx*(y + ny*z), of float32 values
+ *   (precision PRS_F32, the default) or float64 values (PRS_F64: the paper
+ *   runs both precisions, Sec. III).  Boundaries are periodic.  Field
+ *   pointers must be 16-byte aligned.  The caller owns every device buffer it
+ *   passes; the library never frees them.
  * - All device work is enqueued on the caller's HIP stream (a hipStream_t
  *   passed as void*; NULL is the default stream).  Calls that return host
  *   results synchronise that stream before returning.
@@ -67,7 +69,12 @@ typedef struct prs_params {
     double m;            /* era exponent d ln a / d ln eta (a ~ eta^m), >= 0 */
     double W0;           /* wall thickness parameter, > 0 (may be +inf) */
     double phi0;         /* vacuum value, > 0 */
+    int32_t precision;   /* PRS_F32 (0, also a zero-initialised struct) or PRS_F64 */
+    int32_t reserved;    /* must be 0 */
 } prs_params;
+
+#define PRS_F32 0   /* float32 fields: 16 B of HBM traffic per site-update */
+#define PRS_F64 1   /* float64 fields: 32 B per site-update; tilings with vec 1 or 2 */
 
 /* One diagnostic record (Eqs. 7-8) of the state (phi^n, phi_dot^{n-1/2}). */
 typedef struct prs_stats {
@@ -100,7 +107,8 @@ size_t prs_workspace_bytes(const prs_params* p);
  * m >= 0, alpha >= 0; the step must be stable for the linearised scheme,
  * deta * sqrt(4 D / dx^2 + 8 V0/phi0^2) < 2, and the first damping factor
  * must satisfy delta_0 = alpha m deta / (2 eta0) < 1.  beta != 0 gives
- * PRS_EUNSUPPORTED.  The context starts at step 0. */
+ * PRS_EUNSUPPORTED; precision must be PRS_F32 or PRS_F64 and reserved 0.
+ * The context starts at step 0. */
 prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi,
                     void* workspace, size_t ws_bytes, void* hip_stream, prs_ctx** out);
 
@@ -135,7 +143,8 @@ prs_status prs_get_state(prs_ctx* ctx, void** phi, void** dphi, int64_t* step, d
 prs_status prs_set_state(prs_ctx* ctx, const void* phi, const void* dphi, int64_t step);
 
 /* Choose the kernel tiling of this context (mainly for tests and the
- * autotuner).  vec: sites per lane along x (1, 2 or 4, must divide nx);
+ * autotuner).  vec: sites per lane along x (1, 2 or 4 in float32, 1 or 2 in
+ * float64; must divide nx);
  * rows: planes per wave along the marching axis (y in 2D, z in 3D), 1..4096;
  * ty: rows per wave along y in 3D (1, 2 or 4; must be 1 in 2D).
  * Results are bit-identical for every tiling except the rounding order of the
@@ -310,6 +319,10 @@ void prs_batch_destroy(prs_batch* b);
  * generates its random initial conditions once in single precision and feeds
  * them to every run (Sec. III).  Asynchronous on the stream. */
 prs_status prs_fill_uniform(void* phi, int64_t count, uint64_t seed, void* hip_stream);
+
+/* The same values (exact float32 numbers) written as float64, for
+ * PRS_F64 fields. */
+prs_status prs_fill_uniform_f64(void* phi, int64_t count, uint64_t seed, void* hip_stream);
 
 /* ---- scaling exponents (Eq. 9) --------------------------------------- */
 

@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libprs.so")
 
-SOURCES = ["prs_kernels.hip", "prs_api.cpp"]
+SOURCES = ["prs_kernels.hip", "prs_kernels_f64.hip", "prs_api.cpp"]
 ARCH = os.environ.get("PRS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -62,7 +62,8 @@ def build(verbose=False):
     objs = []
     tmpdir = os.path.join(PKG, "_build")
     os.makedirs(tmpdir, exist_ok=True)
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:                       # the sources compile in parallel
         obj = os.path.join(tmpdir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), "--offload-arch=" + ARCH, "-c", os.path.join(CSRC, src), "-o", obj] + flags()
         if src.endswith(".cpp"):
@@ -70,8 +71,11 @@ def build(verbose=False):
                    os.path.join(CSRC, src), "-o", obj] + flags()
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((src, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [src for src, pr in procs if pr.wait() != 0]
+    if failed:
+        raise RuntimeError("compilation failed: " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
     rt = hip_runtime_dir()
     runtime = os.path.join(rt, "libamdhip64.so")

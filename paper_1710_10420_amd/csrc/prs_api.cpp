@@ -1,7 +1,7 @@
 // prs_api.cpp -- host side of the C ABI declared in include/prs.h: argument
 // validation, run contexts, the FP64 coefficient schedule of Eqs. (4)-(6)
 // and the Eq. (9) exponent fit.  Every step of the evolution runs in the
-// kernels of prs_kernels.hip.
+// kernels of prs_device.h (float32 and float64 instantiations).
 
 #include <hip/hip_runtime.h>
 
@@ -63,6 +63,17 @@ int64_t sites_of(const prs_params& p)
     return p.n[0] * p.n[1] * (p.ndim == 3 ? p.n[2] : 1);
 }
 
+// Bytes of one field value.
+size_t esize_of(const prs_params& p) { return p.precision == PRS_F64 ? 8 : 4; }
+
+size_t field_bytes(const prs_params& p) { return (size_t)sites_of(p) * esize_of(p); }
+
+template <typename T>
+T* byte_offset(void* base, size_t off)
+{
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
 prs_status validate(const prs_params* p)
 {
     if (!p) return fail(PRS_EINVAL, "params is NULL");
@@ -83,6 +94,9 @@ prs_status validate(const prs_params* p)
     if (!(p->W0 > 0)) return fail(PRS_EINVAL, "W0 must be > 0");
     if (!(p->phi0 > 0) || !std::isfinite(p->phi0)) return fail(PRS_EINVAL, "phi0 must be finite and > 0");
     if (p->diag_every < 0) return fail(PRS_EINVAL, "diag_every must be >= 0");
+    if (p->precision != PRS_F32 && p->precision != PRS_F64)
+        return fail(PRS_EINVAL, "precision must be PRS_F32 or PRS_F64 (got %d)", p->precision);
+    if (p->reserved != 0) return fail(PRS_EINVAL, "reserved must be 0");
     if (p->beta != 0.0)
         return fail(PRS_EUNSUPPORTED, "only the PRS force (beta = 0) is implemented (got beta = %g)", p->beta);
     const double V0 = v0_of(*p);
@@ -103,6 +117,7 @@ Tiling default_tiling(const Geometry& g)
     else if (g.nx % 4 == 0) t.vec = 4;
     else if (g.nx % 2 == 0) t.vec = 2;
     else t.vec = 1;
+    if (g.f64 && t.vec == 4) t.vec = 2;   // 16 bytes per lane at most
     t.ty = g.ndim == 3 ? 2 : 1;
     t.rows = g.ndim == 3 ? 32 : 16;
     return t;
@@ -152,16 +167,16 @@ struct prs_ctx {
     Geometry geo;
     Tiling til;
     double V0;
-    float* phi[2];
+    void* phi[2];      // float32 or float64 fields, as p.precision says
     int cur;
-    float* pi;
+    void* pi;
     WavePartial* partials;
     int64_t partial_cap;
     prs_stats* drec;
     prs_stats* hrec;   // pinned staging buffer
-    float* pi_alt;     // second phi_dot buffer (workspace, 2D) for two-step passes
+    void* pi_alt;      // second phi_dot buffer (workspace, 2D) for multi-step passes
     Tiling adj_til;    // tiling of the reverse-sweep kernel
-    int32_t tblock;    // steps per pass: 1, or 2 (2D only)
+    int32_t tblock;    // steps per pass: 1 .. 4 (more than 1 in 2D only)
     hipStream_t stream;
     int64_t step;
     // adjoint bookkeeping between prs_adjoint_forward and _backward
@@ -175,19 +190,26 @@ struct prs_ctx {
 
 namespace {
 
-StepCoef coef_for(const prs_ctx* c, int64_t n)
+StepCoef64 coef_for(const prs_ctx* c, int64_t n)
 {
     const prs_params& p = c->p;
     const double eta = p.eta0 + (double)n * p.deta;
     const double delta = 0.5 * p.alpha * (p.deta / eta) * p.m;   // Eq. (6)
-    StepCoef k;
-    k.a = (float)((1.0 - delta) / (1.0 + delta));
-    k.b = (float)(p.deta / (1.0 + delta));
-    k.deta = (float)p.deta;
-    k.F = (float)(4.0 * c->V0 / (p.phi0 * p.phi0));
-    k.kc = (float)(1.0 / (p.phi0 * p.phi0));
-    k.inv_dx2 = (float)(1.0 / (p.dx * p.dx));
+    StepCoef64 k;
+    k.a = (1.0 - delta) / (1.0 + delta);
+    k.b = p.deta / (1.0 + delta);
+    k.deta = p.deta;
+    k.F = 4.0 * c->V0 / (p.phi0 * p.phi0);
+    k.kc = 1.0 / (p.phi0 * p.phi0);
+    k.inv_dx2 = 1.0 / (p.dx * p.dx);
     return k;
+}
+
+// The float32 rounding a float32 launch applies (batched descriptors hold
+// float32 coefficients).
+StepCoef f32_of(const StepCoef64& k)
+{
+    return StepCoef{(float)k.a, (float)k.b, (float)k.deta, (float)k.F, (float)k.kc, (float)k.inv_dx2};
 }
 
 DiagCoef diag_coef(const prs_ctx* c)
@@ -225,7 +247,7 @@ size_t prs_workspace_bytes(const prs_params* p)
     const Geometry g = geometry_of(*p);
     size_t b = align_up((size_t)partial_capacity(g) * sizeof(WavePartial)) +
                align_up((size_t)kRecCap * sizeof(prs_stats));
-    if (p->ndim == 2) b += align_up((size_t)sites_of(*p) * sizeof(float));   // second phi_dot
+    if (p->ndim == 2) b += align_up(field_bytes(*p));   // second phi_dot
     return b;
 }
 
@@ -252,10 +274,10 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, v
     c->geo = geometry_of(*p);
     c->til = default_tiling(c->geo);
     c->V0 = v0_of(*p);
-    c->phi[0] = static_cast<float*>(phi_a);
-    c->phi[1] = static_cast<float*>(phi_b);
+    c->phi[0] = phi_a;
+    c->phi[1] = phi_b;
     c->cur = 0;
-    c->pi = static_cast<float*>(dphi);
+    c->pi = dphi;
     c->partial_cap = partial_capacity(c->geo);
     c->partials = static_cast<WavePartial*>(workspace);
     c->drec = reinterpret_cast<prs_stats*>(
@@ -264,8 +286,7 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, v
     c->adj_til = c->til;
     c->tblock = 1;
     if (p->ndim == 2) {
-        c->pi_alt = reinterpret_cast<float*>(reinterpret_cast<char*>(c->drec) +
-                                             align_up((size_t)kRecCap * sizeof(prs_stats)));
+        c->pi_alt = reinterpret_cast<char*>(c->drec) + align_up((size_t)kRecCap * sizeof(prs_stats));
         c->tblock = 2;
     }
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -307,8 +328,8 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int T = (c->pi_alt != nullptr && c->til.ty == 1 && tb_supported(c->geo)) ? c->tblock : 1;
     const std::vector<uint8_t> plan = plan_passes(c->step, nsteps, T, want ? K : 0);
 
-    float* pi_cur = c->pi;
-    float* pi_oth = c->pi_alt;
+    void* pi_cur = c->pi;
+    void* pi_oth = c->pi_alt;
     int64_t pending = 0, written = 0;
     for (uint8_t L : plan) {
         const int64_t n = c->step;
@@ -316,7 +337,7 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
         WavePartial* parts = diag ? c->partials : nullptr;
         int64_t ntiles = tc.ntiles;
         if (L > 1) {
-            StepCoef k[kMaxPassSteps];
+            StepCoef64 k[kMaxPassSteps];
             for (int i = 0; i < L; ++i) k[i] = coef_for(c, n + i);
             HIP_TRY(launch_tb2d(L, c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, pi_oth, k, diag,
                                 parts, dc, c->stream),
@@ -412,7 +433,7 @@ prs_status prs_set_state(prs_ctx* c, const void* phi, const void* dphi, int64_t 
     if (step < 0) return fail(PRS_EINVAL, "step must be >= 0");
     if ((phi && !aligned16(phi)) || (dphi && !aligned16(dphi)))
         return fail(PRS_EINVAL, "state buffers must be 16-byte aligned");
-    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    const size_t bytes = field_bytes(c->p);
     if (phi && phi != c->phi[c->cur])
         HIP_TRY(hipMemcpyAsync(c->phi[c->cur], phi, bytes, hipMemcpyDeviceToDevice, c->stream), "phi copy");
     if (dphi && dphi != c->pi)
@@ -477,8 +498,16 @@ prs_status prs_fill_uniform(void* phi, int64_t count, uint64_t seed, void* hip_s
 {
     if (count < 0) return fail(PRS_EINVAL, "count must be >= 0");
     if (count > 0 && !phi) return fail(PRS_EINVAL, "phi is NULL");
-    HIP_TRY(launch_fill_uniform(static_cast<float*>(phi), count, seed,
-                                static_cast<hipStream_t>(hip_stream)),
+    HIP_TRY(launch_fill_uniform(phi, count, seed, false, static_cast<hipStream_t>(hip_stream)),
+            "fill kernel launch");
+    return PRS_OK;
+}
+
+prs_status prs_fill_uniform_f64(void* phi, int64_t count, uint64_t seed, void* hip_stream)
+{
+    if (count < 0) return fail(PRS_EINVAL, "count must be >= 0");
+    if (count > 0 && !phi) return fail(PRS_EINVAL, "phi is NULL");
+    HIP_TRY(launch_fill_uniform(phi, count, seed, true, static_cast<hipStream_t>(hip_stream)),
             "fill kernel launch");
     return PRS_OK;
 }
@@ -535,7 +564,7 @@ constexpr int kSeedBlocks = 1024;
 AdjLayout adj_layout(const prs_params& p, int64_t nsteps, int64_t K, int64_t partial_cap)
 {
     AdjLayout L;
-    L.fb = align_up((size_t)sites_of(p) * sizeof(float));
+    L.fb = align_up(field_bytes(p));
     L.K = K;
     L.nseg = (nsteps + K - 1) / K;
     size_t o = 0;
@@ -564,20 +593,20 @@ prs_status check_adj_args(const prs_ctx* c, int64_t nsteps, int32_t K)
     return PRS_OK;
 }
 
-AdjCoef adj_coef(const prs_ctx* c, int64_t n, bool last)
+AdjCoef64 adj_coef(const prs_ctx* c, int64_t n, bool last)
 {
     const prs_params& p = c->p;
     const double eta = p.eta0 + (double)n * p.deta;
     const double delta = 0.5 * p.alpha * (p.deta / eta) * p.m;
     const double b = p.deta / (1.0 + delta);
     const double kc = 1.0 / (p.phi0 * p.phi0);
-    AdjCoef k;
-    k.a = (float)((1.0 - delta) / (1.0 + delta));
-    k.b = (float)b;
-    k.cw = last ? 0.0f : (float)p.deta;
-    k.F = (float)(4.0 * c->V0 * kc);
-    k.kc = (float)kc;
-    k.inv_dx2 = (float)(1.0 / (p.dx * p.dx));
+    AdjCoef64 k;
+    k.a = (1.0 - delta) / (1.0 + delta);
+    k.b = b;
+    k.cw = last ? 0.0 : p.deta;
+    k.F = 4.0 * c->V0 * kc;
+    k.kc = kc;
+    k.inv_dx2 = 1.0 / (p.dx * p.dx);
     k.gscale = -4.0 * kc * b;
     return k;
 }
@@ -606,25 +635,25 @@ prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, v
                 "pinned scalars");
     }
     c->adj_ready = false;
-    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    const size_t bytes = field_bytes(c->p);
     const int64_t n0 = c->step;
     // Checkpoint 0 is a copy of the starting state.  Checkpoint s >= 1 is
     // written directly by the step that produces it, and the next step reads
     // it from there (phi_dot out of place), so no further copies are made.
-    HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_phi), c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream),
+    HIP_TRY(hipMemcpyAsync(at<char>(work, L.ck_phi), c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream),
             "checkpoint copy");
-    HIP_TRY(hipMemcpyAsync(at<float>(work, L.ck_pi), c->pi, bytes, hipMemcpyDeviceToDevice, c->stream),
+    HIP_TRY(hipMemcpyAsync(at<char>(work, L.ck_pi), c->pi, bytes, hipMemcpyDeviceToDevice, c->stream),
             "checkpoint copy");
-    const float* phi_in = c->phi[c->cur];
-    const float* pi_in = c->pi;
+    const void* phi_in = c->phi[c->cur];
+    const void* pi_in = c->pi;
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t n = n0 + k;
-        float* phi_out;
-        float* pi_out;
+        void* phi_out;
+        void* pi_out;
         if ((k + 1) % L.K == 0 && k + 1 < nsteps) {           // produces checkpoint (k+1)/K
             const int64_t sg = (k + 1) / L.K;
-            phi_out = at<float>(work, L.ck_phi + L.fb * sg);
-            pi_out = at<float>(work, L.ck_pi + L.fb * sg);
+            phi_out = at<char>(work, L.ck_phi + L.fb * sg);
+            pi_out = at<char>(work, L.ck_pi + L.fb * sg);
         } else {
             phi_out = c->phi[c->cur ^ 1];
             pi_out = c->pi;
@@ -637,9 +666,9 @@ prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, v
         pi_in = pi_out;
         c->step += 1;
     }
-    const float kc = (float)(1.0 / (c->p.phi0 * c->p.phi0));
-    HIP_TRY(launch_adj_seed(c->phi[c->cur], sites_of(c->p), kc, (float)c->p.deta, at<float>(work, L.mu),
-                            at<float>(work, L.w0), at<double>(work, L.lpart), kSeedBlocks, c->stream),
+    const double kc = 1.0 / (c->p.phi0 * c->p.phi0);
+    HIP_TRY(launch_adj_seed(c->geo, c->phi[c->cur], sites_of(c->p), kc, c->p.deta, at<char>(work, L.mu),
+                            at<char>(work, L.w0), at<double>(work, L.lpart), kSeedBlocks, c->stream),
             "adjoint seed launch");
     HIP_TRY(launch_sum_f64(at<double>(work, L.lpart), kSeedBlocks, at<double>(work, L.scal), c->stream),
             "loss reduce launch");
@@ -666,23 +695,23 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
         return fail(PRS_EINVAL, "gradient buffers must be 16-byte aligned");
     const AdjLayout L = adj_layout(c->p, c->adj_nsteps, c->adj_K, c->partial_cap);
     const int64_t n0 = c->adj_n0;
-    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
+    const size_t bytes = field_bytes(c->p);
     const TileCounts tc = tile_counts(c->geo, c->adj_til);
     double* gacc = at<double>(work, L.gacc);
     HIP_TRY(launch_zero_f64(gacc, tc.ntiles, c->stream), "zero launch");
-    float* mu = at<float>(work, L.mu);
-    float* wcur = at<float>(work, L.w0);
-    float* wnxt = at<float>(work, L.w1);
-    float* pis = at<float>(work, L.pis);
-    auto seg = [&](int64_t k) { return at<float>(work, L.seg + L.fb * (size_t)(k - 1)); };
+    char* mu = at<char>(work, L.mu);
+    char* wcur = at<char>(work, L.w0);
+    char* wnxt = at<char>(work, L.w1);
+    char* pis = at<char>(work, L.pis);
+    auto seg = [&](int64_t k) { return at<char>(work, L.seg + L.fb * (size_t)(k - 1)); };
     for (int64_t sg = L.nseg - 1; sg >= 0; --sg) {
         const int64_t ns = n0 + sg * L.K;
         const int64_t len = std::min<int64_t>(L.K, c->adj_nsteps - sg * L.K);
-        float* ckphi = at<float>(work, L.ck_phi + L.fb * sg);
+        char* ckphi = at<char>(work, L.ck_phi + L.fb * sg);
         // recompute phi^{ns+1 .. ns+len-1} from the checkpoint (the first
         // step reads the checkpointed phi_dot and writes the scratch copy)
-        const float* prev = ckphi;
-        const float* pprev = at<float>(work, L.ck_pi + L.fb * sg);
+        const char* prev = ckphi;
+        const char* pprev = at<char>(work, L.ck_pi + L.fb * sg);
         for (int64_t k = 1; k < len; ++k) {
             HIP_TRY(launch_step(c->geo, c->til, prev, seg(k), pprev, pis, coef_for(c, ns + k - 1), true, false,
                                 nullptr, DiagCoef{}, c->stream),
@@ -692,7 +721,7 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const int64_t n = ns + k;
-            const float* phin = k == 0 ? ckphi : seg(k);
+            const char* phin = k == 0 ? ckphi : seg(k);
             HIP_TRY(launch_adjoint(c->geo, c->adj_til, wcur, wnxt, mu, phin, gacc, adj_coef(c, n, n == n0),
                                    c->stream),
                     "adjoint launch");
@@ -806,7 +835,7 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
     L.alt_off.assign(count, 0);
     for (int32_t r = 0; r < count; ++r) {
         L.alt_off[r] = o - L.alt;
-        if (items[r].p.ndim == 2) o += align_up((size_t)sites_of(items[r].p) * sizeof(float));
+        if (items[r].p.ndim == 2) o += align_up(field_bytes(items[r].p));
     }
     L.part = o;
     L.part_off.assign(count, 0);
@@ -910,8 +939,9 @@ prs_status batch_item_begin(prs_batch* b, int32_t r, ItemCursor& cur, hipStream_
     cur.coef.V0 = v0_of(it.p);
     if (it.init_from_seed) {
         const int64_t n = sites_of(it.p);
-        HIP_TRY(launch_fill_uniform(static_cast<float*>(it.phi_a), n, it.seed, s), "fill launch");
-        HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), n, s), "zero launch");
+        const bool f64 = it.p.precision == PRS_F64;
+        HIP_TRY(launch_fill_uniform(it.phi_a, n, it.seed, f64, s), "fill launch");
+        HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), f64 ? 2 * n : n, s), "zero launch");
     }
     return PRS_OK;
 }
@@ -925,20 +955,20 @@ prs_status batch_item_pass(prs_batch* b, ItemCursor& cur, hipStream_t s)
     const size_t idx = cur.next++;
     const PassEntry& e = cur.plan[idx];
     char* base = static_cast<char*>(b->ws);
-    float* phi[2] = {static_cast<float*>(it.phi_a), static_cast<float*>(it.phi_b)};
-    float* dphi = static_cast<float*>(it.dphi);
-    float* alt = it.p.ndim == 2 ? reinterpret_cast<float*>(base + b->off_alt + b->alt_off[r]) : nullptr;
-    float* pi_now = e.alt ? alt : dphi;
-    float* pi_next = e.alt ? dphi : alt;
+    void* phi[2] = {it.phi_a, it.phi_b};
+    void* dphi = it.dphi;
+    void* alt = it.p.ndim == 2 ? base + b->off_alt + b->alt_off[r] : nullptr;
+    void* pi_now = e.alt ? alt : dphi;
+    void* pi_next = e.alt ? dphi : alt;
     const bool diag = e.rec >= 0;
     WavePartial* parts = diag ? reinterpret_cast<WavePartial*>(base + b->off_part + b->part_off[r]) : nullptr;
     const DiagCoef dc = diag_coef(&cur.coef);
     const int64_t n = e.first;
-    float* phi_in = phi[idx & 1];
-    float* phi_out = phi[(idx + 1) & 1];
+    void* phi_in = phi[idx & 1];
+    void* phi_out = phi[(idx + 1) & 1];
     int64_t ntiles = tile_counts(g, t).ntiles;
     if (e.steps > 1) {
-        StepCoef k[kMaxPassSteps];
+        StepCoef64 k[kMaxPassSteps];
         for (int i = 0; i < e.steps; ++i) k[i] = coef_for(&cur.coef, n + i);
         HIP_TRY(launch_tb2d(e.steps, g, t, phi_in, phi_out, pi_now, pi_next, k, diag, parts, dc, s),
                 "multi-step kernel launch");
@@ -1033,7 +1063,7 @@ prs_status batch_upload(prs_batch* b)
         tmp.V0 = v0_of(it.p);
         std::vector<float> coef((size_t)(it.nsteps + 1) * 2, 0.0f);
         for (int64_t n = 0; n < it.nsteps; ++n) {
-            const StepCoef k = coef_for(&tmp, n);
+            const StepCoef k = f32_of(coef_for(&tmp, n));
             coef[2 * n] = k.a;
             coef[2 * n + 1] = k.b;
         }
@@ -1053,7 +1083,8 @@ prs_status batch_upload(prs_batch* b)
         batch_fill_desc(desc.data() + batch_desc_bytes() * r, b->geo[r], b->til[r],
                         static_cast<float*>(it.phi_a), static_cast<float*>(it.phi_b),
                         static_cast<float*>(it.dphi), alt, dcoef, dpass, (int64_t)plan.size(), p0, p1, recs,
-                        tile_base, it.p.eta0, it.p.deta, area_scale(it.p), coef_for(&tmp, 0), diag_coef(&tmp));
+                        tile_base, it.p.eta0, it.p.deta, area_scale(it.p), f32_of(coef_for(&tmp, 0)),
+                        diag_coef(&tmp));
         tile_base += batch_tiles_max(b->geo[r], b->til[r]);
     }
     b->total_tiles = tile_base;
@@ -1071,7 +1102,7 @@ prs_status batch_enqueue(prs_batch* b, bool persistent, hipStream_t stream)
         const prs_batch_item& it = b->items[r];
         if (!it.init_from_seed) continue;
         const int64_t n = sites_of(it.p);
-        HIP_TRY(launch_fill_uniform(static_cast<float*>(it.phi_a), n, it.seed, stream), "fill launch");
+        HIP_TRY(launch_fill_uniform(it.phi_a, n, it.seed, false, stream), "fill launch");
         HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), n, stream), "zero launch");
     }
     void* ctl = base + b->off_ctl;
@@ -1236,9 +1267,9 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     const bool persistent = persistent_mode(b->mode);
     if (persistent) {
         for (int32_t r = 0; r < b->count; ++r)
-            if (b->til[r].ty != 1 || b->tblock[r] > 2)
-                return fail(PRS_EINVAL, "item %d: the persistent modes need ty = 1 and at most 2 steps per pass",
-                            r);
+            if (b->til[r].ty != 1 || b->tblock[r] > 2 || b->items[r].p.precision != PRS_F32)
+                return fail(PRS_EINVAL,
+                            "item %d: the persistent modes need float32, ty = 1 and at most 2 steps per pass", r);
     }
     if (b->graph_mode != b->mode) batch_release_graph(b);
     if (b->dirty && persistent) {
@@ -1326,9 +1357,9 @@ std::string tune_key(const prs_params& p, bool batch_set)
         if (colon != std::string::npos) arch = arch.substr(0, colon);
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|%dD|%lldx%lldx%lld|%s|%s", arch.c_str(), p.ndim,
+    std::snprintf(buf, sizeof buf, "%s|%dD|%lldx%lldx%lld|%s%s|%s", arch.c_str(), p.ndim,
                   (long long)p.n[0], (long long)p.n[1], (long long)(p.ndim == 3 ? p.n[2] : 1),
-                  batch_set ? "batch" : "single", kTuneVersion);
+                  batch_set ? "batch" : "single", p.precision == PRS_F64 ? "|f64" : "", kTuneVersion);
     return buf;
 }
 
@@ -1428,14 +1459,14 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
         }
     }
     const std::vector<Tiling> cand = tune_candidates(c->geo, false);
-    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
-    float* buf = nullptr;
+    const size_t bytes = field_bytes(c->p);
+    char* buf = nullptr;
     double* gacc = nullptr;
     HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), 3 * bytes), "tuner allocation");
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&gacc), (size_t)c->partial_cap * sizeof(double));
-    float* w0 = buf;
-    float* w1 = buf + sites_of(c->p);
-    float* mu = buf + 2 * sites_of(c->p);
+    char* w0 = buf;
+    char* w1 = buf + bytes;
+    char* mu = buf + 2 * bytes;
     if (e == hipSuccess) e = hipMemcpyAsync(w0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(mu, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1450,8 +1481,8 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     for (const Tiling& t : cand) {
         if (e != hipSuccess) break;
         if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
-        float* a = w0;
-        float* b = w1;
+        char* a = w0;
+        char* b = w1;
         auto run = [&](int steps) -> hipError_t {
             for (int k = 0; k < steps; ++k) {
                 hipError_t err = launch_adjoint(c->geo, t, a, b, mu, c->phi[c->cur], gacc,
@@ -1516,8 +1547,8 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     }
     const std::vector<Tiling> cand = tune_candidates(c->geo, batch_set);
     if (cand.empty()) return fail(PRS_EUNSUPPORTED, "no tiling candidates");
-    const size_t bytes = (size_t)sites_of(c->p) * sizeof(float);
-    float *save_phi = nullptr, *save_pi = nullptr;
+    const size_t bytes = field_bytes(c->p);
+    void *save_phi = nullptr, *save_pi = nullptr;
     HIP_TRY(hipMalloc(reinterpret_cast<void**>(&save_phi), bytes), "tuner allocation");
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&save_pi), bytes);
     if (e != hipSuccess) {
@@ -1540,12 +1571,12 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     // is timed on T-step passes and its per-step time is a pass over T
     int per = 1;
     auto run = [&](const Tiling& t, int passes) -> hipError_t {
-        float* pa = c->pi;
-        float* pb = c->pi_alt;
+        void* pa = c->pi;
+        void* pb = c->pi_alt;
         for (int k = 0; k < passes; ++k) {
             hipError_t err;
             if (per > 1) {
-                StepCoef kc[kMaxPassSteps];
+                StepCoef64 kc[kMaxPassSteps];
                 for (int i = 0; i < per; ++i) kc[i] = coef_for(c, n0 + per * k + i);
                 err = launch_tb2d(per, c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], pa, pb, kc, false, nullptr,
                                   DiagCoef{}, c->stream);

@@ -1,5 +1,6 @@
 // Internal interface between the host API (prs_api.cpp) and the device code
-// (prs_kernels.hip).  Not installed; the public contract is include/prs.h.
+// (prs_device.h, instantiated by prs_kernels.hip and prs_kernels_f64.hip).
+// Not installed; the public contract is include/prs.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,13 +12,17 @@
 
 namespace prs {
 
-// Per-step coefficients of Eqs. (4)-(6), rounded to float32 from the FP64
-// schedule: a = (1-delta_n)/(1+delta_n), b = deta/(1+delta_n),
-// F = 4 V0/phi0^2, kc = 1/phi0^2, so that the kick reads
-// pi' = a pi + b (Lap phi - F phi (kc phi^2 - 1)).
-struct StepCoef {
-    float a, b, deta, F, kc, inv_dx2;
+// Per-step coefficients of Eqs. (4)-(6) from the FP64 schedule:
+// a = (1-delta_n)/(1+delta_n), b = deta/(1+delta_n), F = 4 V0/phi0^2,
+// kc = 1/phi0^2, so that the kick reads
+// pi' = a pi + b (Lap phi - F phi (kc phi^2 - 1)).  The host computes them in
+// FP64 (StepCoef64); a launch rounds them once to the field precision R.
+template <typename R>
+struct StepCoefT {
+    R a, b, deta, F, kc, inv_dx2;
 };
+using StepCoef = StepCoefT<float>;
+using StepCoef64 = StepCoefT<double>;
 
 // FP64 constants of the diagnostics (Eq. 8 needs V(phi) = V0 (kc phi^2 - 1)^2).
 struct DiagCoef {
@@ -38,6 +43,7 @@ struct WavePartial {
 // 3D, absent = 1 in 2D) and the marching axis of M planes (y in 2D, z in 3D).
 struct Geometry {
     int ndim;
+    int f64;    // 1: float64 fields, 0: float32
     int64_t nx, Q, M;
 };
 
@@ -55,21 +61,24 @@ Geometry geometry_of(const prs_params& p);
 TileCounts tile_counts(const Geometry& g, const Tiling& t);
 bool tiling_supported(const Geometry& g, const Tiling& t);
 
+// Field pointers below are device pointers to float32 or float64 values,
+// as the Geometry says.
+
 // One fused step over the whole lattice: reads phi_in and pi, writes
 // phi_out and pi_out (pi_out == pi updates in place) when update; writes one
 // WavePartial per wave tile when diag.  update == false && diag == true
 // computes the diagnostics only.
-hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       const float* pi, float* pi_out, const StepCoef& k, bool update, bool diag,
-                       WavePartial* partials, const DiagCoef& dc, hipStream_t s);
+hipError_t launch_step(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi,
+                       void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
+                       const DiagCoef& dc, hipStream_t s);
 
 // T = 2..4 steps n .. n+T-1 of a 2D lattice in one pass (temporal blocking)
 // with overlapped wave tiles; k holds the T step coefficients.  Reads phi_in
 // and pi_in, writes phi^{n+T} to phi_out and phi_dot^{n+T-1/2} to pi_out
 // (pi_out != pi_in).  With diag, the partials are those of the input state.
-hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
-                       WavePartial* partials, const DiagCoef& dc, hipStream_t s);
+hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                       const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                       const DiagCoef& dc, hipStream_t s);
 // Number of wave tiles (and partials) of a T-step pass.
 int64_t tb_tiles(const Geometry& g, const Tiling& t, int T);
 // Multi-step passes exist for 2D lattices whose rows are shorter than 2^28
@@ -80,26 +89,52 @@ bool tb_supported(const Geometry& g);
 hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,
                            int64_t step, double eta, double area_scale, hipStream_t s);
 
-hipError_t launch_fill_uniform(float* phi, int64_t count, uint64_t seed, hipStream_t s);
+hipError_t launch_fill_uniform(void* phi, int64_t count, uint64_t seed, bool f64, hipStream_t s);
 
-// Coefficients of one reverse step n: a_n, b_n as in StepCoef, cw = deta
-// (0 on the final reverse step), gscale = -4 kc b_n in FP64.
-struct AdjCoef {
-    float a, b, cw, F, kc, inv_dx2;
+// Coefficients of one reverse step n: a_n, b_n as in StepCoefT, cw = deta
+// (0 on the final reverse step), gscale = -4 kc b_n.
+template <typename R>
+struct AdjCoefT {
+    R a, b, cw, F, kc, inv_dx2;
     double gscale;
 };
+using AdjCoef64 = AdjCoefT<double>;
 
 // One reverse step: reads w_in (with halo), mu and phi^n; writes w_out and mu
 // (in place); adds this step's dL/dV0 contribution to gacc[wave tile].
-hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const float* w_in, float* w_out,
-                          float* mu, const float* phi_n, double* gacc, const AdjCoef& c,
-                          hipStream_t s);
+hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
+                          const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s);
 
 // mu = dL/dphi^S, w = deta*mu from the final field; FP64 loss partial per block.
-hipError_t launch_adj_seed(const float* phi, int64_t count, float kc, float deta, float* mu,
-                           float* w, double* partial, int nblocks, hipStream_t s);
+hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, double kc, double deta, void* mu,
+                           void* w, double* partial, int nblocks, hipStream_t s);
 hipError_t launch_sum_f64(const double* v, int64_t count, double* out, hipStream_t s);
 hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s);
+
+// Per-precision instantiations behind the dispatchers above (one kernel file
+// each).
+hipError_t launch_step_f32(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi,
+                           void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
+                           const DiagCoef& dc, hipStream_t s);
+hipError_t launch_step_f64(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi,
+                           void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
+                           const DiagCoef& dc, hipStream_t s);
+hipError_t launch_tb2d_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                           const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                           const DiagCoef& dc, hipStream_t s);
+hipError_t launch_tb2d_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                           const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                           const DiagCoef& dc, hipStream_t s);
+hipError_t launch_adjoint_f32(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
+                              const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s);
+hipError_t launch_adjoint_f64(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
+                              const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s);
+hipError_t launch_adj_seed_f32(const void* phi, int64_t count, double kc, double deta, void* mu, void* w,
+                               double* partial, int nblocks, hipStream_t s);
+hipError_t launch_adj_seed_f64(const void* phi, int64_t count, double kc, double deta, void* mu, void* w,
+                               double* partial, int nblocks, hipStream_t s);
+hipError_t launch_fill_f32(void* phi, int64_t count, uint64_t seed, hipStream_t s);
+hipError_t launch_fill_f64(void* phi, int64_t count, uint64_t seed, hipStream_t s);
 
 // Batched ensemble (descriptor layout is private to the kernel file).
 size_t batch_desc_bytes();

@@ -1,522 +1,12 @@
-// prs_kernels.hip -- gfx950 kernels of the PRS domain-wall evolution
-// (arXiv:1710.10420, Sec. II, Eqs. 3-8).
-//
-// One kernel does a whole step: the Laplacian (Eq. 3), the damped kick
-// (Eqs. 4, 6) and the drift (Eq. 5), and on diagnostic steps the wall area
-// (Eq. 7) and velocity (Eq. 8) sums of the step's input state.  The paper ran
-// these as separate kernels through global memory and named fusing them as
-// the next step; here each field value crosses HBM once per step: phi^n and
-// phi_dot are read once, phi^{n+1} and phi_dot written once (16 B per site).
-//
-// Work decomposition.  A wave (64 lanes) owns a tile of
-//   64*VEC sites along x  x  TY rows along the middle axis (3D only)
-// and marches along the slowest axis (y in 2D, z in 3D) through `rows`
-// planes.  The three planes s-1, s, s+1 it needs stay in registers and the
-// plane s+2 is already in flight while s is computed, so every phi value is
-// loaded from HBM once per tile.  x-neighbours come from the adjacent lane
-// (ds_bpermute shuffles); only the two wave-edge lanes load a halo scalar.
-// In 3D the rows above and below the tile are loaded per plane and are
-// served by L2, because the waves of a workgroup hold consecutive rows and
-// consecutive workgroups of one XCD hold consecutive tiles (xcd_remap).
-// Waves are independent: no LDS, no barriers.
-//
-// Arithmetic.  Every site runs the same inline sequence (explicit fmaf,
-// -ffp-contract=off), so results are bitwise independent of the tiling, of
-// the lane a site lands in and of the batch it runs in.  Neighbour sums are
-// grouped as (phi_- + phi_+) pairs, which makes x -> -x reflections and
-// phi -> -phi exact symmetries of the float32 update as well.
-//
-// Diagnostics.  Sign bits s = (phi >= 0) give the crossing links; counts are
-// per-lane 32-bit, reduced per wave with butterfly shuffles; the Eq. (7)
-// weight and the Eq. (8) ratio are evaluated in FP64 only at sites that
-// touch a wall.  Each wave writes one WavePartial; a single-workgroup
-// finalize kernel adds them in index order, so the record is deterministic.
+// prs_kernels.hip -- float32 instantiation of the PRS kernels (the device
+// templates are in prs_device.h), the record reduction, the batched-ensemble
+// kernels and the host-side dispatch by precision.
 
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cstdint>
-
-#include "prs_internal.h"
+#include "prs_device.h"
 
 namespace prs {
 
 namespace {
-
-constexpr int kWave = 64;
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kXcds = 8;
-
-// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
-// XCD b % 8).  Give each XCD a contiguous range of logical blocks so that
-// tiles that share halo rows run on the same XCD, close in time, and their
-// shared rows hit that XCD's L2.  Bijective for any grid size.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
-{
-    int64_t xcd = b % kXcds, k = b / kXcds;
-    int64_t per = nb / kXcds, rem = nb % kXcds;
-    return xcd * per + (xcd < rem ? xcd : rem) + k;
-}
-
-// Index of this wave within its workgroup, as a wave-uniform (scalar) value:
-// the compiler cannot prove threadIdx.x / 64 uniform on its own, and every
-// address derived from it would otherwise be computed per lane.
-__device__ __forceinline__ int wave_in_block()
-{
-    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-}
-
-// Makes a wave-uniform 64-bit value visibly uniform to the compiler.
-__device__ __forceinline__ int64_t uniform64(int64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ int64_t wrap(int64_t v, int64_t n)
-{
-    v %= n;
-    return v < 0 ? v + n : v;
-}
-
-template <int VEC>
-__device__ __forceinline__ void load_vec(const float* p, float (&v)[VEC])
-{
-    if constexpr (VEC == 4) {
-        float4 t = *reinterpret_cast<const float4*>(p);
-        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-    } else if constexpr (VEC == 2) {
-        float2 t = *reinterpret_cast<const float2*>(p);
-        v[0] = t.x; v[1] = t.y;
-    } else {
-        v[0] = *p;
-    }
-}
-
-template <int VEC>
-__device__ __forceinline__ void store_vec(float* p, const float (&v)[VEC])
-{
-    if constexpr (VEC == 4) {
-        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-    } else if constexpr (VEC == 2) {
-        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
-    } else {
-        *p = v[0];
-    }
-}
-
-// Eq. (3) (2D) and its 3D extension, times 1/dx^2.  UNIT (dx = 1) drops the
-// multiplication by 1, which is exact, so both forms give the same bits.
-template <bool UNIT = false>
-__device__ __forceinline__ float lap2(float c, float xm, float xp, float ym, float yp, float inv_dx2)
-{
-    const float s = (xm + xp) + (ym + yp);
-    const float r = fmaf(-4.0f, c, s);
-    return UNIT ? r : r * inv_dx2;
-}
-
-template <bool UNIT = false>
-__device__ __forceinline__ float lap3(float c, float xm, float xp, float ym, float yp, float zm,
-                                      float zp, float inv_dx2)
-{
-    const float s = ((xm + xp) + (ym + yp)) + (zm + zp);
-    const float r = fmaf(-6.0f, c, s);
-    return UNIT ? r : r * inv_dx2;
-}
-
-// Eqs. (4)-(5) with the FP64-derived coefficients of StepCoef:
-// V'(phi) = F phi (kc phi^2 - 1), the bracket formed with one rounding.
-// UNIT (phi0 = 1, kc = 1) drops the exact multiplication by kc.
-template <bool UNIT = false>
-__device__ __forceinline__ void kick_drift(float c, float lap, float pi, const StepCoef& k,
-                                           float& pi_new, float& phi_new)
-{
-    const float ck = UNIT ? c : c * k.kc;
-    const float q = fmaf(ck, c, -1.0f);
-    const float dv = (k.F * c) * q;            // V'(phi)
-    pi_new = fmaf(k.a, pi, k.b * (lap - dv));  // Eq. (4)
-    phi_new = fmaf(k.deta, pi_new, c);         // Eq. (5)
-}
-
-// Value held by the lane on the left (lane - 1) / right (lane + 1) of this
-// one, by a wave-wide DPP shift; the end lane keeps its own value.
-__device__ __forceinline__ float from_left_lane(float v)
-{
-    const int b = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x138, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ float from_right_lane(float v)
-{
-    const int b = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x130, 0xF, 0xF, false));
-}
-
-struct DiagAcc {
-    uint32_t links[3];
-    uint32_t walls;
-    uint32_t nonfinite;
-    double area;
-    double ek;
-};
-
-// Eqs. (7)-(8) contribution of one site: forward links along each axis,
-// the wall flag from forward and backward links, the area weight
-// |g| / sum|g_d| from centred differences (the 1/(2 dx) factor cancels), and
-// (1/2) phi_dot^2 / V at wall sites.
-template <int D>
-__device__ __forceinline__ void site_diag(float c, float pi, const float (&nm)[D],
-                                          const float (&np)[D], const DiagCoef& dc, DiagAcc& a)
-{
-    const bool sc = c >= 0.0f;
-    int cross = 0;
-    bool wall = false;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const bool fwd = sc != (np[d] >= 0.0f);
-        const bool bwd = sc != (nm[d] >= 0.0f);
-        a.links[d] += fwd ? 1u : 0u;
-        cross += fwd ? 1 : 0;
-        wall = wall || fwd || bwd;
-    }
-    if (!(__builtin_isfinite(c) && __builtin_isfinite(pi))) a.nonfinite += 1u;
-    if (cross) {
-        double gsq = 0.0, gabs = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            double h = (double)np[d] - (double)nm[d];
-            gsq += h * h;
-            gabs += fabs(h);
-        }
-        double w = gabs > 0.0 ? sqrt(gsq) / gabs : 1.0;
-        a.area += (double)cross * w;
-    }
-    if (wall) {
-        a.walls += 1u;
-        double cd = (double)c;
-        double q = cd * cd * dc.kc - 1.0;
-        double V = dc.V0 * q * q;
-        if (V > 0.0) {
-            double pd = (double)pi;
-            a.ek += 0.5 * pd * pd / V;
-        }
-    }
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum_f64(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-struct StepArgs {
-    const float* phi_in;
-    float* phi_out;
-    const float* pi;       // phi_dot^{n-1/2} (read)
-    float* pi_out;         // phi_dot^{n+1/2} (written; may equal pi)
-    WavePartial* partials;
-    int64_t nx, Q, M;
-    int64_t tiles_x, tiles_q, ntiles;
-    int64_t rows;
-    StepCoef k;
-    DiagCoef dc;
-};
-
-// One plane of a wave's tile: TY rows of VEC sites per lane, the two x-halo
-// scalars (used by lane 0 / the last active lane) and, in 3D, the rows just
-// above and below the tile.
-template <int VEC, int TY>
-struct Plane {
-    float v[TY][VEC];
-    float hl[TY];
-    float hr[TY];
-    float lo[VEC];
-    float hi[VEC];
-};
-
-// Everything a wave needs to walk its tile, computed once.  In-plane offsets
-// are unsigned 32-bit (a plane holds fewer than 2^31 sites), plane bases are
-// wave-uniform 64-bit pointers, so the march needs no division and loads use
-// the scalar-base + vector-offset form.
-template <int TY>
-struct TileSetup {
-    uint32_t x0, xl, xr;     // this lane's first site and its x-halo sites
-    bool active, need_left, need_right;
-    uint32_t off[TY];        // (q0 + t) * nx + x0
-    uint32_t offl[TY];       // (q0 + t) * nx + xl
-    uint32_t offr[TY];       // (q0 + t) * nx + xr
-    uint32_t lo, hi;         // rows above / below the tile (3D), + x0
-    int nvalid;              // rows of the tile inside the lattice
-    int64_t s0, s1;          // marching range
-    int64_t M, pstride;
-};
-
-// Plane index wrapped into [0, M) for v in [-1, 2M]: no division.
-__device__ __forceinline__ int64_t wrap_plane(int64_t v, int64_t M)
-{
-    if (v < 0) v += M;
-    if (v >= M) v -= M;
-    if (v >= M) v -= M;
-    return v;
-}
-
-template <int VEC, int TY>
-__device__ __forceinline__ TileSetup<TY> tile_setup(int64_t nx64, int64_t Q64, int64_t M,
-                                                    int64_t tiles_x, int64_t tiles_q, int64_t rows,
-                                                    int64_t tile)
-{
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
-    const uint32_t tq = tl % (uint32_t)tiles_q;
-    const uint32_t rest = tl / (uint32_t)tiles_q;
-    const uint32_t tx = rest % (uint32_t)tiles_x;
-    const uint32_t ts = rest / (uint32_t)tiles_x;
-    const uint32_t nx = (uint32_t)nx64, Q = (uint32_t)Q64;
-    TileSetup<TY> S;
-    S.x0 = tx * (kWave * VEC) + lane * VEC;
-    S.active = S.x0 < nx;
-    S.need_left = S.active && lane == 0;
-    S.need_right = S.active && (lane == kWave - 1 || S.x0 + VEC >= nx);
-    S.xl = S.x0 == 0 ? nx - 1 : S.x0 - 1;
-    S.xr = S.x0 + VEC >= nx ? 0 : S.x0 + VEC;
-    const uint32_t q0 = tq * TY;
-    S.nvalid = (int)((Q - q0) < (uint32_t)TY ? (Q - q0) : (uint32_t)TY);
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        const uint32_t r = (q0 + t) * nx;
-        S.off[t] = r + S.x0;
-        S.offl[t] = r + S.xl;
-        S.offr[t] = r + S.xr;
-    }
-    uint32_t lo = q0 == 0 ? Q - 1 : q0 - 1;
-    uint32_t hi = q0 + (uint32_t)S.nvalid;
-    while (hi >= Q) hi -= Q;          // Q >= 1; a few iterations at most when Q < TY
-    S.lo = lo * nx + S.x0;
-    S.hi = hi * nx + S.x0;
-    S.s0 = (int64_t)ts * rows;
-    S.s1 = (S.s0 + rows) < M ? (S.s0 + rows) : M;
-    S.M = M;
-    S.pstride = nx64 * Q64;
-    return S;
-}
-
-template <int D, int VEC, int TY>
-__device__ __forceinline__ void load_plane(const float* __restrict__ f, int64_t s,
-                                           const TileSetup<TY>& S, Plane<VEC, TY>& P)
-{
-    const float* base = f + wrap_plane(s, S.M) * S.pstride;
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        if (t < S.nvalid) {
-            if (S.active) load_vec<VEC>(base + S.off[t], P.v[t]);
-            if (S.need_left) P.hl[t] = base[S.offl[t]];
-            if (S.need_right) P.hr[t] = base[S.offr[t]];
-        }
-    }
-    if constexpr (D == 3) {
-        if (S.active) {
-            load_vec<VEC>(base + S.lo, P.lo);
-            load_vec<VEC>(base + S.hi, P.hi);
-        }
-    }
-}
-
-// A plane that is only needed for its values along the marching axis (s-1):
-// no x-halo scalars, no y-halo rows.
-template <int VEC, int TY>
-__device__ __forceinline__ void load_plane_values(const float* __restrict__ f, int64_t s,
-                                                  const TileSetup<TY>& S, Plane<VEC, TY>& P)
-{
-    const float* base = f + wrap_plane(s, S.M) * S.pstride;
-#pragma unroll
-    for (int t = 0; t < TY; ++t)
-        if (t < S.nvalid && S.active) load_vec<VEC>(base + S.off[t], P.v[t]);
-}
-
-// Point-wise field values of plane s (s inside the lattice) for every row.
-template <int VEC, int TY>
-__device__ __forceinline__ void load_point(const float* __restrict__ f, int64_t s,
-                                           const TileSetup<TY>& S, float (&v)[TY][VEC])
-{
-    const float* base = f + s * S.pstride;
-#pragma unroll
-    for (int t = 0; t < TY; ++t)
-        if (t < S.nvalid && S.active) load_vec<VEC>(base + S.off[t], v[t]);
-}
-
-template <int VEC, int TY>
-__device__ __forceinline__ void zero_plane(Plane<VEC, TY>& P)
-{
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) P.v[t][j] = 0.0f;
-        P.hl[t] = P.hr[t] = 0.0f;
-    }
-#pragma unroll
-    for (int j = 0; j < VEC; ++j) P.lo[j] = P.hi[j] = 0.0f;
-}
-
-template <int VEC, int TY>
-__device__ __forceinline__ void zero_rows(float (&v)[TY][VEC])
-{
-#pragma unroll
-    for (int t = 0; t < TY; ++t)
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) v[t][j] = 0.0f;
-}
-
-// x-neighbours of the first and last site of each row of the current plane.
-template <int VEC, int TY>
-__device__ __forceinline__ void x_neighbours(const Plane<VEC, TY>& P, const TileSetup<TY>& S,
-                                             float (&left)[TY], float (&right)[TY])
-{
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        left[t] = from_left_lane(P.v[t][VEC - 1]);
-        right[t] = from_right_lane(P.v[t][0]);
-        if (lane == 0) left[t] = P.hl[t];
-        if (S.need_right) right[t] = P.hr[t];
-    }
-}
-
-// The 2D neighbours (minus, plus) of site j of row t of the current plane.
-template <int D, int VEC, int TY>
-__device__ __forceinline__ void neighbours(const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
-                                           const Plane<VEC, TY>& Pn, const float (&left)[TY],
-                                           const float (&right)[TY], int nvalid, int t, int j,
-                                           float (&nm)[D], float (&np)[D])
-{
-    nm[0] = j > 0 ? Pc.v[t][j > 0 ? j - 1 : 0] : left[t];
-    np[0] = j < VEC - 1 ? Pc.v[t][j < VEC - 1 ? j + 1 : j] : right[t];
-    if constexpr (D == 3) {
-        nm[1] = t > 0 ? Pc.v[t > 0 ? t - 1 : 0][j] : Pc.lo[j];
-        np[1] = (t + 1 < nvalid) ? Pc.v[t + 1 < TY ? t + 1 : t][j] : Pc.hi[j];
-        nm[2] = Pm.v[t][j];
-        np[2] = Pn.v[t][j];
-    } else {
-        nm[1] = Pm.v[t][j];
-        np[1] = Pn.v[t][j];
-    }
-}
-
-// Plane s of a forward tile: prefetch plane s+2 (and phi_dot of s+1), then
-// update plane s from (Pm, Pc, Pn) = planes (s-1, s, s+1).
-template <int D, int VEC, int TY, bool UPDATE, bool DIAG, bool UNIT = false>
-__device__ __forceinline__ void step_plane(const StepArgs& A, const TileSetup<TY>& S, int64_t s,
-                                           const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
-                                           const Plane<VEC, TY>& Pn, Plane<VEC, TY>& Pnn,
-                                           const float (&pic)[TY][VEC], float (&pin)[TY][VEC],
-                                           DiagAcc& acc)
-{
-    if (s + 1 < S.s1) {
-        load_plane<D, VEC, TY>(A.phi_in, s + 2, S, Pnn);
-        load_point<VEC, TY>(A.pi, s + 1, S, pin);
-    }
-    float left[TY], right[TY];
-    x_neighbours<VEC, TY>(Pc, S, left, right);
-    float* phi_out = A.phi_out + s * S.pstride;
-    float* pi_out = A.pi_out + s * S.pstride;
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        if (t >= S.nvalid) continue;
-        float out_phi[VEC], out_pi[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const float c = Pc.v[t][j];
-            float nm[D], np[D];
-            neighbours<D, VEC, TY>(Pm, Pc, Pn, left, right, S.nvalid, t, j, nm, np);
-            if constexpr (UPDATE) {
-                float lap;
-                if constexpr (D == 3)
-                    lap = lap3<UNIT>(c, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.k.inv_dx2);
-                else
-                    lap = lap2<UNIT>(c, nm[0], np[0], nm[1], np[1], A.k.inv_dx2);
-                kick_drift<UNIT>(c, lap, pic[t][j], A.k, out_pi[j], out_phi[j]);
-            }
-            if constexpr (DIAG) {
-                if (S.active) site_diag<D>(c, pic[t][j], nm, np, A.dc, acc);
-            }
-        }
-        if constexpr (UPDATE) {
-            if (S.active) {
-                store_vec<VEC>(phi_out + S.off[t], out_phi);
-                store_vec<VEC>(pi_out + S.off[t], out_pi);
-            }
-        }
-    }
-}
-
-// One wave's tile of one step (see the file header).  `tile` must be below
-// A.ntiles and uniform across the wave.  The march is unrolled by four over a
-// ring of four plane buffers, so no plane is ever copied between registers.
-template <int D, int VEC, int TY, bool UPDATE, bool DIAG, bool UNIT = false>
-__device__ __forceinline__ void step_tile(const StepArgs& A, int64_t tile)
-{
-    static_assert(D == 3 || TY == 1, "2D tiles have one row");
-    const int lane = threadIdx.x & (kWave - 1);
-    const TileSetup<TY> S = tile_setup<VEC, TY>(A.nx, A.Q, A.M, A.tiles_x, A.tiles_q, A.rows, tile);
-
-    Plane<VEC, TY> P0, P1, P2, P3;
-    float pi0[TY][VEC], pi1[TY][VEC];
-    zero_plane(P0);
-    zero_plane(P1);
-    zero_plane(P2);
-    zero_plane(P3);
-    zero_rows<VEC, TY>(pi0);
-    zero_rows<VEC, TY>(pi1);
-    load_plane_values<VEC, TY>(A.phi_in, S.s0 - 1, S, P0);
-    load_plane<D, VEC, TY>(A.phi_in, S.s0, S, P1);
-    load_plane<D, VEC, TY>(A.phi_in, S.s0 + 1, S, P2);
-    load_point<VEC, TY>(A.pi, S.s0, S, pi0);
-
-    DiagAcc acc;
-    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
-    acc.walls = acc.nonfinite = 0u;
-    acc.area = acc.ek = 0.0;
-
-    for (int64_t s = S.s0; s < S.s1; s += 4) {
-        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s, P0, P1, P2, P3, pi0, pi1, acc);
-        if (s + 1 >= S.s1) break;
-        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s + 1, P1, P2, P3, P0, pi1, pi0, acc);
-        if (s + 2 >= S.s1) break;
-        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s + 2, P2, P3, P0, P1, pi0, pi1, acc);
-        if (s + 3 >= S.s1) break;
-        step_plane<D, VEC, TY, UPDATE, DIAG, UNIT>(A, S, s + 3, P3, P0, P1, P2, pi1, pi0, acc);
-    }
-
-    if constexpr (DIAG) {
-        WavePartial w;
-        w.links[0] = wave_sum_u32(acc.links[0]);
-        w.links[1] = wave_sum_u32(acc.links[1]);
-        w.links[2] = wave_sum_u32(acc.links[2]);
-        w.walls = wave_sum_u32(acc.walls);
-        w.nonfinite = wave_sum_u32(acc.nonfinite);
-        w.pad = 0u;
-        w.area = wave_sum_f64(acc.area);
-        w.ek = wave_sum_f64(acc.ek);
-        if (lane == 0) A.partials[tile] = w;
-    }
-}
-
-template <int D, int VEC, int TY, bool UPDATE, bool DIAG, bool UNIT>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs A)
-{
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
-    if (tile >= A.ntiles) return;   // whole wave leaves; shuffles stay uniform
-    step_tile<D, VEC, TY, UPDATE, DIAG, UNIT>(A, tile);
-}
 
 // Adds `count` wave partials into one record, with one wave, in a fixed
 // order: lane l sums partials l, l+64, l+128, ... and the 64 lane sums are
@@ -574,167 +64,6 @@ __global__ __launch_bounds__(kWave) void k_finalize(const WavePartial* __restric
     finalize_wave(parts, count, rec, step, eta, area_scale);
 }
 
-// SplitMix64 (Steele, Lea & Flood 2014) evaluated at counter i+1, top 24
-// bits k mapped to (2k+1)/2^24 - 1.
-__global__ __launch_bounds__(kBlock) void k_fill_uniform(float* __restrict__ phi, int64_t count,
-                                                          uint64_t seed)
-{
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
-        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        z = z ^ (z >> 31);
-        const int32_t k = (int32_t)(z >> 40);
-        phi[i] = (float)(2 * k + 1 - (1 << 24)) * 0x1p-24f;
-    }
-}
-
-
-// ---------------------------------------------------------------- adjoint --
-//
-// Reverse sweep of one step n of Eqs. (3)-(6).  The carried adjoint state is
-// (mu, w): mu = dL/dphi^{n+1} and w = nu + deta*mu, the total adjoint of
-// phi_dot^{n+1/2} (nu being its adjoint through later kicks).  Differentiating
-// the kick and drift gives, per site,
-//     mu^n    = mu^{n+1} + b_n (Lap w - V''(phi^n) w)     (Lap is symmetric)
-//     w_{n-1} = a_n w + cw * mu^n                          (cw = deta; 0 on the
-//                                                           last reverse step,
-//                                                           which leaves nu = a w)
-//     dL/dV0 += -b_n sum_i w_i d V'(phi_i)/dV0,  dV'/dV0 = 4 kc phi (kc phi^2 - 1)
-// Same march and tiling as the forward kernel: w is the stencil field (read
-// with halo, written to the other buffer), mu is updated in place and phi^n
-// is read once.  20 bytes of HBM traffic per site.
-
-struct AdjArgs {
-    const float* w_in;
-    float* w_out;
-    float* mu;
-    const float* phi_n;
-    double* gacc;       // one accumulator per wave tile, persistent across steps
-    int64_t nx, Q, M;
-    int64_t tiles_x, tiles_q, ntiles;
-    int64_t rows;
-    float a, b, cw, F, kc, inv_dx2;
-    double gscale;      // -4 kc b_n
-};
-
-// Plane s of a reverse tile (same ring scheme as step_plane).
-template <int D, int VEC, int TY, bool UNIT>
-__device__ __forceinline__ void adj_plane(const AdjArgs& A, const TileSetup<TY>& S, int64_t s,
-                                          const Plane<VEC, TY>& Pm, const Plane<VEC, TY>& Pc,
-                                          const Plane<VEC, TY>& Pn, Plane<VEC, TY>& Pnn,
-                                          const float (&muc)[TY][VEC], float (&mun)[TY][VEC],
-                                          const float (&phc)[TY][VEC], float (&phn)[TY][VEC],
-                                          double& gsum)
-{
-    if (s + 1 < S.s1) {
-        load_plane<D, VEC, TY>(A.w_in, s + 2, S, Pnn);
-        load_point<VEC, TY>(A.mu, s + 1, S, mun);
-        load_point<VEC, TY>(A.phi_n, s + 1, S, phn);
-    }
-    float left[TY], right[TY];
-    x_neighbours<VEC, TY>(Pc, S, left, right);
-    float* w_out = A.w_out + s * S.pstride;
-    float* mu_out = A.mu + s * S.pstride;
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        if (t >= S.nvalid) continue;
-        float out_w[VEC], out_mu[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const float w = Pc.v[t][j];
-            float nm[D], np[D];
-            neighbours<D, VEC, TY>(Pm, Pc, Pn, left, right, S.nvalid, t, j, nm, np);
-            float lap;
-            if constexpr (D == 3)
-                lap = lap3<UNIT>(w, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.inv_dx2);
-            else
-                lap = lap2<UNIT>(w, nm[0], np[0], nm[1], np[1], A.inv_dx2);
-            const float ph = phc[t][j];
-            const float phk = UNIT ? ph : ph * A.kc;
-            const float q = fmaf(phk, ph, -1.0f);
-            const float v2 = A.F * fmaf(3.0f * phk, ph, -1.0f);   // V''(phi)
-            const float mu_new = fmaf(A.b, lap - v2 * w, muc[t][j]);
-            out_mu[j] = mu_new;
-            out_w[j] = fmaf(A.cw, mu_new, A.a * w);
-            if (S.active) gsum += (double)(w * (ph * q));
-        }
-        if (S.active) {
-            store_vec<VEC>(w_out + S.off[t], out_w);
-            store_vec<VEC>(mu_out + S.off[t], out_mu);
-        }
-    }
-}
-
-template <int D, int VEC, int TY, bool UNIT>
-__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs A)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
-    if (tile >= A.ntiles) return;
-    const TileSetup<TY> S = tile_setup<VEC, TY>(A.nx, A.Q, A.M, A.tiles_x, A.tiles_q, A.rows, tile);
-
-    Plane<VEC, TY> P0, P1, P2, P3;
-    float mu0[TY][VEC], mu1[TY][VEC], ph0[TY][VEC], ph1[TY][VEC];
-    zero_plane(P0);
-    zero_plane(P1);
-    zero_plane(P2);
-    zero_plane(P3);
-    zero_rows<VEC, TY>(mu0);
-    zero_rows<VEC, TY>(mu1);
-    zero_rows<VEC, TY>(ph0);
-    zero_rows<VEC, TY>(ph1);
-    load_plane_values<VEC, TY>(A.w_in, S.s0 - 1, S, P0);
-    load_plane<D, VEC, TY>(A.w_in, S.s0, S, P1);
-    load_plane<D, VEC, TY>(A.w_in, S.s0 + 1, S, P2);
-    load_point<VEC, TY>(A.mu, S.s0, S, mu0);
-    load_point<VEC, TY>(A.phi_n, S.s0, S, ph0);
-
-    double gsum = 0.0;
-    for (int64_t s = S.s0; s < S.s1; s += 4) {
-        adj_plane<D, VEC, TY, UNIT>(A, S, s, P0, P1, P2, P3, mu0, mu1, ph0, ph1, gsum);
-        if (s + 1 >= S.s1) break;
-        adj_plane<D, VEC, TY, UNIT>(A, S, s + 1, P1, P2, P3, P0, mu1, mu0, ph1, ph0, gsum);
-        if (s + 2 >= S.s1) break;
-        adj_plane<D, VEC, TY, UNIT>(A, S, s + 2, P2, P3, P0, P1, mu0, mu1, ph0, ph1, gsum);
-        if (s + 3 >= S.s1) break;
-        adj_plane<D, VEC, TY, UNIT>(A, S, s + 3, P3, P0, P1, P2, mu1, mu0, ph1, ph0, gsum);
-    }
-    gsum = wave_sum_f64(gsum);
-    if (lane == 0) A.gacc[tile] += A.gscale * gsum;
-}
-
-// Seed of the reverse sweep and the loss sum V/V0 = (kc phi^2 - 1)^2 over the
-// final field: mu = dL/dphi = 4 kc phi (kc phi^2 - 1), w = deta * mu (the
-// final phi_dot does not enter the loss).  Fixed grid; one FP64 partial per
-// workgroup.
-__global__ __launch_bounds__(kBlock) void k_adj_seed(const float* __restrict__ phi, int64_t count,
-                                                      float kc, float deta, float* __restrict__ mu,
-                                                      float* __restrict__ w,
-                                                      double* __restrict__ partial)
-{
-    __shared__ double sh[kBlock];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
-        const float f = phi[i];
-        const float q = f * f * kc - 1.0f;
-        const float m = (4.0f * kc) * f * q;
-        mu[i] = m;
-        w[i] = deta * m;
-        const double qd = (double)f * (double)f * (double)kc - 1.0;
-        acc += qd * qd;
-    }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
-}
-
 // Sum of `count` doubles in a fixed order into *out.
 __global__ __launch_bounds__(kBlock) void k_sum_f64(const double* __restrict__ v, int64_t count,
                                                      double* __restrict__ out)
@@ -757,327 +86,6 @@ __global__ __launch_bounds__(kBlock) void k_zero_f64(double* __restrict__ v, int
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) v[i] = 0.0;
-}
-
-template <int D, int VEC, int TY>
-hipError_t launch_adj_t(const AdjArgs& A, hipStream_t s)
-{
-    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (A.inv_dx2 == 1.0f && A.kc == 1.0f)
-        hipLaunchKernelGGL((k_adjoint<D, VEC, TY, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
-    else
-        hipLaunchKernelGGL((k_adjoint<D, VEC, TY, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
-    return hipGetLastError();
-}
-
-
-// ----------------------------------------- T steps per HBM pass (2D) --------
-//
-// Temporal blocking: T = 2, 3 or 4 leapfrog steps per pass over HBM, with
-// overlapped wave tiles.  A wave's 64 lanes hold 64*VEC consecutive sites; the first and
-// last H = ceil(T/VEC) lanes are halo lanes whose sites belong to the
-// neighbouring tiles.  Level k (step n+k-1) is computed for every lane from
-// level k-1 of the lanes on either side (plain shuffles), so the sites within
-// k of the wave's ends become stale at level k; halo lanes are never stored
-// and H*VEC >= T keeps every owned site exact.  Along y the levels are
-// pipelined inside the march: at iteration y level k computes row y-k+1 from
-// level k-1 rows y-k .. y-k+2, so level k needs T-k extra rows on each side
-// of the tile.  Only level T is written.  All levels use the single-step
-// arithmetic, so the result is bitwise that of T single steps.
-
-template <int T>
-struct TBArgs {
-    const float* phi_in;
-    float* phi_out;
-    const float* pi_in;
-    float* pi_out;
-    WavePartial* partials;
-    int64_t nx, ny;
-    int64_t tiles_x, ntiles;
-    int64_t rows;
-    StepCoef k[T];
-    DiagCoef dc;
-};
-
-__device__ __forceinline__ int64_t tb_owned_width_d(int vec, int T)
-{
-    const int H = (T + vec - 1) / vec;
-    return (int64_t)(kWave - 2 * H) * vec;
-}
-
-template <int VEC, int T>
-struct TBState {
-    float in[4][VEC];          // phi^n rows, ring over the march
-    float pin[2][VEC];         // phi_dot^{n-1/2} rows
-    float lv[T][4][VEC];       // level k rows (k = 1 .. T-1 used)
-    float pl[T][2][VEC];       // level k phi_dot rows
-};
-
-// Per-wave constants of a tile.  Row numbers are wave-uniform 32-bit values
-// (a plane holds fewer than 2^31 sites), so all row arithmetic stays on the
-// scalar unit.  Rows are read and written through raw buffer descriptors made
-// per row (base = row start, size = row bytes): a lane's access is the
-// descriptor plus its column offset, an access with size 0 or an offset past
-// the row is dropped by the hardware, so every load and store is issued
-// unconditionally and the memory counters the compiler waits on follow one
-// straight-line pattern per iteration.
-struct TBLane {
-    uint32_t voff;             // byte offset of this lane's first site, wrapped into the row
-    uint32_t soff;             // voff for owned lanes inside the lattice, else past the row
-    int32_t s0, s1;            // output rows [s0, s1) of the tile
-    uint32_t nx;
-    uint32_t row_bytes;
-    int32_t ny;
-};
-
-// Next rows to fetch, already wrapped into [0, ny); advanced by one row per
-// iteration without division.
-struct TBRows {
-    int32_t phi, pi;
-};
-
-__device__ __forceinline__ int32_t next_row(int32_t r, int32_t ny)
-{
-    return r + 1 == ny ? 0 : r + 1;
-}
-
-// Any row number into [0, ny) (tile set-up only).
-__device__ __forceinline__ int32_t wrap_row(int32_t r, int32_t ny)
-{
-    r %= ny;
-    return r < 0 ? r + ny : r;
-}
-
-// Word 3 of a raw (unswizzled, stride 0) buffer descriptor on CDNA.
-constexpr int kRawBufferWord3 = 0x00020000;
-
-// Offset that no row reaches (rows are shorter than 2^30 bytes).
-constexpr uint32_t kPastRow = 0xFFFFFFF0u;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* f, int32_t row, uint32_t nx,
-                                                           uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(f) + (size_t)((uint32_t)row * nx),
-                                             (short)0, (int)bytes, kRawBufferWord3);
-}
-
-template <int VEC>
-__device__ __forceinline__ void tb_load(const float* f, int32_t row, const TBLane& L, uint32_t bytes,
-                                        float (&v)[VEC])
-{
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(f, row, L.nx, bytes);
-    if constexpr (VEC == 4) {
-        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, L.voff, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = __uint_as_float(t[j]);
-    } else if constexpr (VEC == 2) {
-        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, L.voff, 0, 0);
-        v[0] = __uint_as_float(t[0]);
-        v[1] = __uint_as_float(t[1]);
-    } else {
-        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, L.voff, 0, 0));
-    }
-}
-
-template <int VEC>
-__device__ __forceinline__ void tb_store(float* f, int32_t row, const TBLane& L, uint32_t bytes,
-                                         const float (&v)[VEC])
-{
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(f, row, L.nx, bytes);
-    if constexpr (VEC == 4) {
-        __attribute__((ext_vector_type(4))) unsigned int t;
-        t[0] = __float_as_uint(v[0]);
-        t[1] = __float_as_uint(v[1]);
-        t[2] = __float_as_uint(v[2]);
-        t[3] = __float_as_uint(v[3]);
-        __builtin_amdgcn_raw_buffer_store_b128(t, r, L.soff, 0, 0);
-    } else if constexpr (VEC == 2) {
-        __attribute__((ext_vector_type(2))) unsigned int t;
-        t[0] = __float_as_uint(v[0]);
-        t[1] = __float_as_uint(v[1]);
-        __builtin_amdgcn_raw_buffer_store_b64(t, r, L.soff, 0, 0);
-    } else {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, L.soff, 0, 0);
-    }
-}
-
-// Iteration i of the march (y = s0 - T + 1 + i): level k computes row
-// s0 - T - k + 2 + i.  Level k has work from i = 2(k-1) on, the last
-// iteration is i = last for every level.  CHECK skips the levels that have no
-// row yet (the first 2T-2 iterations); without it those levels run on rows
-// that only ever feed rows outside the tile, which are never stored.
-template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, int U>
-__device__ __forceinline__ void tb_iter(const TBArgs<T>& A, const TBLane& L, int32_t i,
-                                        int32_t last, TBRows& R, TBState<VEC, T>& S, DiagAcc& acc)
-{
-    // prefetch phi^n row y+2 and phi_dot row y+1 for the next iteration
-    // (none after the last: size 0)
-    const uint32_t nb = i < last ? L.row_bytes : 0u;
-    tb_load<VEC>(A.phi_in, R.phi, L, nb, S.in[(U + 2) & 3]);
-    tb_load<VEC>(A.pi_in, R.pi, L, nb, S.pin[(U + 1) & 1]);
-    R.phi = next_row(R.phi, L.ny);
-    R.pi = next_row(R.pi, L.ny);
-#pragma unroll
-    for (int k = 1; k <= T; ++k) {
-        if (CHECK && i < 2 * (k - 1)) continue;
-        const float* cm;
-        const float* cc;
-        const float* cp;
-        const float* pp;
-        if (k == 1) {
-            cm = S.in[(U + 3) & 3];
-            cc = S.in[U & 3];
-            cp = S.in[(U + 1) & 3];
-            pp = S.pin[U & 1];
-        } else {
-            cm = S.lv[k - 1][(U + 2) & 3];
-            cc = S.lv[k - 1][(U + 3) & 3];
-            cp = S.lv[k - 1][U & 3];
-            pp = S.pl[k - 1][(U + 1) & 1];
-        }
-        float left = from_left_lane(cc[VEC - 1]);
-        float right = from_right_lane(cc[0]);
-        float out_phi[VEC], out_pi[VEC];
-        // level 1 row y is inside the tile for i in [T-1, T-1 + s1 - s0)
-        const bool diag_row = DIAG && k == 1 && i >= T - 1 && i < T - 1 + (L.s1 - L.s0);
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const float c = cc[j];
-            const float xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
-            const float xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
-            const float lap = lap2<UNIT>(c, xm, xp, cm[j], cp[j], A.k[k - 1].inv_dx2);
-            kick_drift<UNIT>(c, lap, pp[j], A.k[k - 1], out_pi[j], out_phi[j]);
-            if constexpr (DIAG) {
-                if (diag_row && L.soff != kPastRow) {
-                    const float nm[2] = {xm, cm[j]};
-                    const float np[2] = {xp, cp[j]};
-                    site_diag<2>(c, pp[j], nm, np, A.dc, acc);
-                }
-            }
-        }
-        if (k < T) {
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                S.lv[k < T ? k : 0][U & 3][j] = out_phi[j];
-                S.pl[k < T ? k : 0][U & 1][j] = out_pi[j];
-            }
-        } else {
-            // level T row s0 + i - (2T - 2), inside [s0, s1) once i >= 2T - 2
-            const int32_t row = L.s0 + i - (2 * T - 2);
-            const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.row_bytes : 0u;
-            tb_store<VEC>(A.phi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_phi);
-            tb_store<VEC>(A.pi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_pi);
-        }
-    }
-}
-
-// Iterations i .. i+3 (i a multiple of 4, so ring slots are compile-time);
-// false once the last iteration has run.
-template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK>
-__device__ __forceinline__ bool tb_group(const TBArgs<T>& A, const TBLane& L, int32_t i,
-                                         int32_t last, TBRows& R, TBState<VEC, T>& S, DiagAcc& acc)
-{
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 0>(A, L, i, last, R, S, acc);
-    if (i + 1 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 1>(A, L, i + 1, last, R, S, acc);
-    if (i + 2 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 2>(A, L, i + 2, last, R, S, acc);
-    if (i + 3 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 3>(A, L, i + 3, last, R, S, acc);
-    return i + 4 <= last;
-}
-
-// One wave's tile of a T-step pass; `tile` must be below A.ntiles and
-// wave-uniform.
-template <int VEC, int T, bool DIAG, bool UNIT = false>
-__device__ __forceinline__ void tb_tile(const TBArgs<T>& A, int64_t tile)
-{
-    constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
-    constexpr int W = (kWave - 2 * H) * VEC;       // owned sites per wave
-    constexpr int WARM = (2 * T - 2 + 3) / 4;      // groups that hold pipeline fill
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
-    const uint32_t tx = tl % (uint32_t)A.tiles_x;
-    const uint32_t ts = tl / (uint32_t)A.tiles_x;
-    TBLane L;
-    L.nx = (uint32_t)A.nx;
-    L.ny = (int32_t)A.ny;
-    L.row_bytes = L.nx * 4u;
-    const int32_t rows = (int32_t)A.rows;
-    // x0 < nx + 64 VEC fits in 32 bits; lanes past a narrow lattice wrap
-    // more than once and only load
-    const int32_t x0 = (int32_t)(tx * (uint32_t)W) + (lane - H) * VEC;
-    L.voff = (uint32_t)wrap_row(x0, (int32_t)L.nx) * 4u;
-    L.soff = (lane >= H && lane < kWave - H && x0 < (int32_t)L.nx) ? L.voff : kPastRow;
-    L.s0 = (int32_t)ts * rows;
-    L.s1 = L.s0 + rows < L.ny ? L.s0 + rows : L.ny;
-
-    TBState<VEC, T> S;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            S.in[a][j] = 0.0f;
-#pragma unroll
-            for (int k = 0; k < T; ++k) S.lv[k][a][j] = 0.0f;
-        }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            S.pin[a][j] = 0.0f;
-#pragma unroll
-            for (int k = 0; k < T; ++k) S.pl[k][a][j] = 0.0f;
-        }
-
-    // iteration 0 (y0 = s0 - T + 1) needs phi^n rows y0-1 .. y0+1 and phi_dot row y0
-    const int32_t y0 = L.s0 - T + 1;
-    tb_load<VEC>(A.phi_in, wrap_row(y0 - 1, L.ny), L, L.row_bytes, S.in[3]);
-    tb_load<VEC>(A.phi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.in[0]);
-    tb_load<VEC>(A.phi_in, wrap_row(y0 + 1, L.ny), L, L.row_bytes, S.in[1]);
-    tb_load<VEC>(A.pi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.pin[0]);
-    TBRows R;
-    R.phi = wrap_row(y0 + 2, L.ny);
-    R.pi = wrap_row(y0 + 1, L.ny);
-
-    DiagAcc acc;
-    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
-    acc.walls = acc.nonfinite = 0u;
-    acc.area = acc.ek = 0.0;
-
-    const int32_t last = (L.s1 - L.s0) + 2 * T - 3;
-    int32_t i = 0;
-    bool more = true;
-#pragma unroll
-    for (int w = 0; w < WARM; ++w) {
-        if (more) more = tb_group<VEC, T, DIAG, UNIT, true>(A, L, i, last, R, S, acc);
-        i += 4;
-    }
-    while (more) {
-        more = tb_group<VEC, T, DIAG, UNIT, false>(A, L, i, last, R, S, acc);
-        i += 4;
-    }
-
-    if constexpr (DIAG) {
-        WavePartial w;
-        w.links[0] = wave_sum_u32(acc.links[0]);
-        w.links[1] = wave_sum_u32(acc.links[1]);
-        w.links[2] = 0u;
-        w.walls = wave_sum_u32(acc.walls);
-        w.nonfinite = wave_sum_u32(acc.nonfinite);
-        w.pad = 0u;
-        w.area = wave_sum_f64(acc.area);
-        w.ek = wave_sum_f64(acc.ek);
-        if (lane == 0) A.partials[tile] = w;
-    }
-}
-
-template <int VEC, int T, bool DIAG, bool UNIT>
-__global__ __launch_bounds__(kBlock) void k_tb2d(TBArgs<T> A)
-{
-    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
-    if (tile >= A.ntiles) return;
-    tb_tile<VEC, T, DIAG, UNIT>(A, tile);
 }
 
 // ------------------------------------------------------- batched ensemble --
@@ -1326,44 +334,6 @@ __global__ void k_batch_reset(BatchCtl* ctl)
     }
 }
 
-template <int D, int VEC, int TY, bool UPDATE, bool DIAG>
-hipError_t launch_t(const StepArgs& A, hipStream_t s)
-{
-    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    // the plain update with dx = 1 and phi0 = 1 skips two exact
-    // multiplications by 1 (same bits as the general form)
-    if (UPDATE && !DIAG && A.k.inv_dx2 == 1.0f && A.k.kc == 1.0f)
-        hipLaunchKernelGGL((k_step<D, VEC, TY, UPDATE, DIAG, true>), dim3((unsigned)blocks), dim3(kBlock), 0,
-                           s, A);
-    else
-        hipLaunchKernelGGL((k_step<D, VEC, TY, UPDATE, DIAG, false>), dim3((unsigned)blocks), dim3(kBlock), 0,
-                           s, A);
-    return hipGetLastError();
-}
-
-template <int D, int VEC, int TY>
-hipError_t launch_mode(const StepArgs& A, bool update, bool diag, hipStream_t s)
-{
-    if (update && diag) return launch_t<D, VEC, TY, true, true>(A, s);
-    if (update) return launch_t<D, VEC, TY, true, false>(A, s);
-    if (diag) return launch_t<D, VEC, TY, false, true>(A, s);
-    return hipSuccess;
-}
-
-template <int D, int VEC>
-hipError_t launch_ty(const StepArgs& A, int ty, bool update, bool diag, hipStream_t s)
-{
-    if constexpr (D == 2) {
-        return launch_mode<2, VEC, 1>(A, update, diag, s);
-    } else {
-        switch (ty) {
-        case 1: return launch_mode<3, VEC, 1>(A, update, diag, s);
-        case 2: return launch_mode<3, VEC, 2>(A, update, diag, s);
-        case 4: return launch_mode<3, VEC, 4>(A, update, diag, s);
-        default: return hipErrorInvalidValue;
-        }
-    }
-}
 
 }  // namespace
 
@@ -1371,6 +341,7 @@ Geometry geometry_of(const prs_params& p)
 {
     Geometry g;
     g.ndim = p.ndim;
+    g.f64 = p.precision == PRS_F64 ? 1 : 0;
     g.nx = p.n[0];
     if (p.ndim == 2) {
         g.Q = 1;
@@ -1395,46 +366,84 @@ TileCounts tile_counts(const Geometry& g, const Tiling& t)
 bool tiling_supported(const Geometry& g, const Tiling& t)
 {
     if (t.vec != 1 && t.vec != 2 && t.vec != 4) return false;
+    if (g.f64 && t.vec == 4) return false;          // 16 bytes per lane at most
     if (g.nx % t.vec != 0) return false;
     if (t.rows < 1 || t.rows > 4096) return false;
     if (g.ndim == 2) return t.ty == 1;
     return t.ty == 1 || t.ty == 2 || t.ty == 4;
 }
 
-hipError_t launch_step(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       const float* pi, float* pi_out, const StepCoef& k, bool update, bool diag,
-                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
+// ---- float32 instantiations ----
+
+hipError_t launch_step_f32(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi,
+                           void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
+                           const DiagCoef& dc, hipStream_t s)
 {
-    const TileCounts c = tile_counts(g, t);
-    StepArgs A;
-    A.phi_in = phi_in;
-    A.phi_out = phi_out;
-    A.pi = pi;
-    A.pi_out = pi_out;
-    A.partials = partials;
-    A.nx = g.nx;
-    A.Q = g.Q;
-    A.M = g.M;
-    A.tiles_x = c.tiles_x;
-    A.tiles_q = c.tiles_q;
-    A.ntiles = c.ntiles;
-    A.rows = t.rows;
-    A.k = k;
-    A.dc = dc;
-    if (g.ndim == 2) {
-        switch (t.vec) {
-        case 1: return launch_ty<2, 1>(A, 1, update, diag, s);
-        case 2: return launch_ty<2, 2>(A, 1, update, diag, s);
-        case 4: return launch_ty<2, 4>(A, 1, update, diag, s);
-        }
-    } else {
-        switch (t.vec) {
-        case 1: return launch_ty<3, 1>(A, t.ty, update, diag, s);
-        case 2: return launch_ty<3, 2>(A, t.ty, update, diag, s);
-        case 4: return launch_ty<3, 4>(A, t.ty, update, diag, s);
-        }
-    }
-    return hipErrorInvalidValue;
+    return launch_step_r<float>(g, t, phi_in, phi_out, pi, pi_out, k, update, diag, partials, dc, s);
+}
+
+hipError_t launch_tb2d_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                           const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                           const DiagCoef& dc, hipStream_t s)
+{
+    return launch_tb2d_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+}
+
+hipError_t launch_adjoint_f32(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
+                              const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s)
+{
+    return launch_adjoint_r<float>(g, t, w_in, w_out, mu, phi_n, gacc, c, s);
+}
+
+hipError_t launch_adj_seed_f32(const void* phi, int64_t count, double kc, double deta, void* mu, void* w,
+                               double* partial, int nblocks, hipStream_t s)
+{
+    return launch_adj_seed_r<float>(phi, count, kc, deta, mu, w, partial, nblocks, s);
+}
+
+hipError_t launch_fill_f32(void* phi, int64_t count, uint64_t seed, hipStream_t s)
+{
+    return launch_fill_r<float>(phi, count, seed, s);
+}
+
+// ---- dispatch by precision ----
+
+hipError_t launch_step(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi,
+                       void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
+                       const DiagCoef& dc, hipStream_t s)
+{
+    if (!tiling_supported(g, t)) return hipErrorInvalidValue;
+    return g.f64 ? launch_step_f64(g, t, phi_in, phi_out, pi, pi_out, k, update, diag, partials, dc, s)
+                 : launch_step_f32(g, t, phi_in, phi_out, pi, pi_out, k, update, diag, partials, dc, s);
+}
+
+hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                       const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                       const DiagCoef& dc, hipStream_t s)
+{
+    if (!tb_supported(g) || !tiling_supported(g, t) || t.ty != 1) return hipErrorInvalidValue;
+    return g.f64 ? launch_tb2d_f64(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s)
+                 : launch_tb2d_f32(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+}
+
+hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
+                          const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s)
+{
+    if (!tiling_supported(g, t)) return hipErrorInvalidValue;
+    return g.f64 ? launch_adjoint_f64(g, t, w_in, w_out, mu, phi_n, gacc, c, s)
+                 : launch_adjoint_f32(g, t, w_in, w_out, mu, phi_n, gacc, c, s);
+}
+
+hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, double kc, double deta, void* mu,
+                           void* w, double* partial, int nblocks, hipStream_t s)
+{
+    return g.f64 ? launch_adj_seed_f64(phi, count, kc, deta, mu, w, partial, nblocks, s)
+                 : launch_adj_seed_f32(phi, count, kc, deta, mu, w, partial, nblocks, s);
+}
+
+hipError_t launch_fill_uniform(void* phi, int64_t count, uint64_t seed, bool f64, hipStream_t s)
+{
+    return f64 ? launch_fill_f64(phi, count, seed, s) : launch_fill_f32(phi, count, seed, s);
 }
 
 hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,
@@ -1442,64 +451,6 @@ hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWave), 0, s, partials, count, rec, step, eta,
                        area_scale);
-    return hipGetLastError();
-}
-
-
-hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const float* w_in, float* w_out,
-                          float* mu, const float* phi_n, double* gacc, const AdjCoef& c,
-                          hipStream_t s)
-{
-    const TileCounts tc = tile_counts(g, t);
-    AdjArgs A;
-    A.w_in = w_in;
-    A.w_out = w_out;
-    A.mu = mu;
-    A.phi_n = phi_n;
-    A.gacc = gacc;
-    A.nx = g.nx;
-    A.Q = g.Q;
-    A.M = g.M;
-    A.tiles_x = tc.tiles_x;
-    A.tiles_q = tc.tiles_q;
-    A.ntiles = tc.ntiles;
-    A.rows = t.rows;
-    A.a = c.a;
-    A.b = c.b;
-    A.cw = c.cw;
-    A.F = c.F;
-    A.kc = c.kc;
-    A.inv_dx2 = c.inv_dx2;
-    A.gscale = c.gscale;
-    if (g.ndim == 2) {
-        switch (t.vec) {
-        case 1: return launch_adj_t<2, 1, 1>(A, s);
-        case 2: return launch_adj_t<2, 2, 1>(A, s);
-        case 4: return launch_adj_t<2, 4, 1>(A, s);
-        }
-    } else {
-#define PRS_ADJ3(V)                                          \
-    switch (t.ty) {                                          \
-    case 1: return launch_adj_t<3, V, 1>(A, s);              \
-    case 2: return launch_adj_t<3, V, 2>(A, s);              \
-    case 4: return launch_adj_t<3, V, 4>(A, s);              \
-    }                                                        \
-    break;
-        switch (t.vec) {
-        case 1: PRS_ADJ3(1)
-        case 2: PRS_ADJ3(2)
-        case 4: PRS_ADJ3(4)
-        }
-#undef PRS_ADJ3
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_adj_seed(const float* phi, int64_t count, float kc, float deta, float* mu,
-                           float* w, double* partial, int nblocks, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_adj_seed, dim3(nblocks), dim3(kBlock), 0, s, phi, count, kc, deta, mu, w,
-                       partial);
     return hipGetLastError();
 }
 
@@ -1517,7 +468,6 @@ hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s)
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)blocks), dim3(kBlock), 0, s, v, count);
     return hipGetLastError();
 }
-
 
 // ---- batched ensemble launchers ----
 
@@ -1644,47 +594,6 @@ int64_t tb_owned_width(int vec, int T)
     return (int64_t)(kWave - 2 * H) * vec;
 }
 
-template <int VEC, int T>
-hipError_t launch_tb_t(const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
-                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
-{
-    TBArgs<T> A;
-    A.phi_in = phi_in;
-    A.phi_out = phi_out;
-    A.pi_in = pi_in;
-    A.pi_out = pi_out;
-    A.partials = partials;
-    A.nx = g.nx;
-    A.ny = g.M;
-    const int64_t W = tb_owned_width(VEC, T);
-    A.tiles_x = (g.nx + W - 1) / W;
-    A.ntiles = A.tiles_x * ((g.M + t.rows - 1) / t.rows);
-    A.rows = t.rows;
-    for (int i = 0; i < T; ++i) A.k[i] = k[i];
-    A.dc = dc;
-    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (diag)
-        hipLaunchKernelGGL((k_tb2d<VEC, T, true, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
-    else if (k[0].inv_dx2 == 1.0f && k[0].kc == 1.0f)
-        hipLaunchKernelGGL((k_tb2d<VEC, T, false, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
-    else
-        hipLaunchKernelGGL((k_tb2d<VEC, T, false, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
-    return hipGetLastError();
-}
-
-template <int VEC>
-hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
-                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
-{
-    switch (T) {
-    case 2: return launch_tb_t<VEC, 2>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    case 3: return launch_tb_t<VEC, 3>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    case 4: return launch_tb_t<VEC, 4>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    }
-    return hipErrorInvalidValue;
-}
 
 bool tb_supported(const Geometry& g)
 {
@@ -1695,29 +604,6 @@ int64_t tb_tiles(const Geometry& g, const Tiling& t, int T)
 {
     const int64_t W = tb_owned_width(t.vec, T);
     return ((g.nx + W - 1) / W) * ((g.M + t.rows - 1) / t.rows);
-}
-
-hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const float* phi_in, float* phi_out,
-                       const float* pi_in, float* pi_out, const StepCoef* k, bool diag,
-                       WavePartial* partials, const DiagCoef& dc, hipStream_t s)
-{
-    if (!tb_supported(g) || t.ty != 1) return hipErrorInvalidValue;
-    switch (t.vec) {
-    case 1: return launch_tb_v<1>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    case 2: return launch_tb_v<2>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    case 4: return launch_tb_v<4>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_fill_uniform(float* phi, int64_t count, uint64_t seed, hipStream_t s)
-{
-    if (count <= 0) return hipSuccess;
-    int64_t blocks = (count + kBlock - 1) / kBlock;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_fill_uniform, dim3((unsigned)blocks), dim3(kBlock), 0, s, phi, count,
-                       seed);
-    return hipGetLastError();
 }
 
 }  // namespace prs

@@ -45,7 +45,13 @@ class prs_params(ctypes.Structure):
         ("m", ctypes.c_double),
         ("W0", ctypes.c_double),
         ("phi0", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
+
+
+PRS_F32 = 0
+PRS_F64 = 1
 
 
 class prs_stats(ctypes.Structure):
@@ -118,6 +124,7 @@ _decl("prs_set_tiling", _i32, _vp, _i32, _i32, _i32)
 _decl("prs_get_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _decl("prs_destroy", None, _vp)
 _decl("prs_fill_uniform", _i32, _vp, _i64, _u64, _vp)
+_decl("prs_fill_uniform_f64", _i32, _vp, _i64, _u64, _vp)
 _decl("prs_fit_scaling", _i32, _S, _i64, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d))
 _decl("prs_adjoint_workspace_bytes", _sz, _P, _i64, _i32)
 _decl("prs_adjoint_forward", _i32, _vp, _i64, _i32, _vp, _sz, ctypes.POINTER(_d))
@@ -153,7 +160,7 @@ EXPORTED = [
     "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy", "prs_batch_set_time_blocking",
     "prs_batch_state", "prs_autotune", "prs_tuned_tiling",
     "prs_set_time_blocking", "prs_get_time_blocking", "prs_set_adjoint_tiling",
-    "prs_get_adjoint_tiling", "prs_plan_passes",
+    "prs_get_adjoint_tiling", "prs_plan_passes", "prs_fill_uniform_f64",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -175,9 +182,11 @@ def _check(status, where):
 
 
 def make_params(shape, deta, eta0=1.0, alpha=3.0, m=1.0, W0=10.0, dx=1.0, phi0=1.0,
-                beta=0.0, diag_every=0):
-    """prs_params for a lattice of shape (nx, ny) or (nx, ny, nz)."""
+                beta=0.0, diag_every=0, precision=PRS_F32):
+    """prs_params for a lattice of shape (nx, ny) or (nx, ny, nz); precision
+    PRS_F32 (float32 fields) or PRS_F64 (float64 fields)."""
     p = prs_params()
+    p.precision = int(precision)
     p.ndim = len(shape)
     for d in range(3):
         p.n[d] = int(shape[d]) if d < len(shape) else 1
@@ -189,6 +198,11 @@ def make_params(shape, deta, eta0=1.0, alpha=3.0, m=1.0, W0=10.0, dx=1.0, phi0=1
 
 def sites(p):
     return p.n[0] * p.n[1] * (p.n[2] if p.ndim == 3 else 1)
+
+
+def field_dtype(p):
+    """torch dtype of the fields of a run with parameters p."""
+    return torch.float64 if p.precision == PRS_F64 else torch.float32
 
 
 def _stream_handle(stream):
@@ -283,6 +297,10 @@ def prs_destroy(ctx):
 
 def prs_fill_uniform(phi_ptr, count, seed, stream):
     _check(_lib.prs_fill_uniform(phi_ptr, count, seed, stream), "prs_fill_uniform")
+
+
+def prs_fill_uniform_f64(phi_ptr, count, seed, stream):
+    _check(_lib.prs_fill_uniform_f64(phi_ptr, count, seed, stream), "prs_fill_uniform_f64")
 
 
 def prs_fit_scaling(records, eta_min=0.0, eta_max=math.inf):
@@ -396,9 +414,11 @@ def prs_tuned_tiling(p, cache_path, flags=0):
 class Sim:
     """One PRS run on the current CUDA (HIP) device.
 
-    phi0: a float32 tensor with the initial field in site order (any shape
-    with the right number of elements), or None to draw it with
-    prs_fill_uniform(seed).  dphi0: initial phi_dot^{-1/2} (default 0)."""
+    phi0: a tensor with the initial field in site order (any shape with the
+    right number of elements; converted to the run's precision), or None to
+    draw it with prs_fill_uniform(seed).  dphi0: initial phi_dot^{-1/2}
+    (default 0).  Fields are float32, or float64 when p.precision is
+    PRS_F64."""
 
     def __init__(self, p, phi0=None, dphi0=None, seed=1, device="cuda", stream=None):
         import torch
@@ -407,20 +427,22 @@ class Sim:
         n = sites(p)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self._s = _stream_handle(self.stream)
+        self.dtype = field_dtype(p)
         with torch.cuda.stream(self.stream):
-            self.phi_a = torch.empty(n, dtype=torch.float32, device=device)
-            self.phi_b = torch.empty(n, dtype=torch.float32, device=device)
-            self.dphi = torch.zeros(n, dtype=torch.float32, device=device)
+            self.phi_a = torch.empty(n, dtype=self.dtype, device=device)
+            self.phi_b = torch.empty(n, dtype=self.dtype, device=device)
+            self.dphi = torch.zeros(n, dtype=self.dtype, device=device)
             ws = prs_workspace_bytes(p)
             if ws == 0:
                 raise PRSError(PRS_EINVAL, "prs_workspace_bytes")
             self.ws = torch.empty(ws, dtype=torch.uint8, device=device)
             if phi0 is None:
-                prs_fill_uniform(self.phi_a.data_ptr(), n, seed, self._s)
+                fill = prs_fill_uniform_f64 if p.precision == PRS_F64 else prs_fill_uniform
+                fill(self.phi_a.data_ptr(), n, seed, self._s)
             else:
-                self.phi_a.copy_(phi0.reshape(-1).to(device=device, dtype=torch.float32))
+                self.phi_a.copy_(phi0.reshape(-1).to(device=device, dtype=self.dtype))
             if dphi0 is not None:
-                self.dphi.copy_(dphi0.reshape(-1).to(device=device, dtype=torch.float32))
+                self.dphi.copy_(dphi0.reshape(-1).to(device=device, dtype=self.dtype))
         self.ctx = prs_init(p, self.phi_a.data_ptr(), self.phi_b.data_ptr(), self.dphi.data_ptr(),
                             self.ws.data_ptr(), self.ws.numel(), self._s)
 
@@ -454,8 +476,8 @@ class Sim:
 
     def set_state(self, phi, dphi, step):
         with self.torch.cuda.stream(self.stream):
-            phi = phi.reshape(-1).to(device=self.phi_a.device, dtype=self.torch.float32).contiguous()
-            dphi = dphi.reshape(-1).to(device=self.phi_a.device, dtype=self.torch.float32).contiguous()
+            phi = phi.reshape(-1).to(device=self.phi_a.device, dtype=self.dtype).contiguous()
+            dphi = dphi.reshape(-1).to(device=self.phi_a.device, dtype=self.dtype).contiguous()
             prs_set_state(self.ctx, phi.data_ptr(), dphi.data_ptr(), step)
             self.stream.synchronize()
 
@@ -481,26 +503,41 @@ class PRSLoss(torch.autograd.Function):
 
         loss = PRSLoss.apply(phi0, W0, params, nsteps, ckpt_every)
 
-    phi0: float32 CUDA tensor of the lattice's site count; W0: 0-d tensor
-    (its value replaces params.W0); params: prs_params (W0 field ignored)."""
+    phi0: CUDA tensor of the lattice's site count, float32 or float64 (the
+    run uses the precision of phi0, whatever params.precision says); W0: 0-d
+    tensor (its value replaces params.W0); params: prs_params (W0 and
+    precision fields ignored).  With float64 the whole evolution and the
+    reverse sweep run in double precision, which torch.autograd.gradcheck
+    can check against finite differences of the same GPU code."""
+
+    @staticmethod
+    def _run_forward(p, phi0, nsteps, ckpt_every):
+        sim = Sim(p, phi0=phi0, device=phi0.device)
+        nbytes = prs_adjoint_workspace_bytes(p, nsteps, ckpt_every)
+        if nbytes == 0:
+            raise PRSError(PRS_EINVAL, "prs_adjoint_workspace_bytes")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=phi0.device)
+        loss = prs_adjoint_forward(sim.ctx, nsteps, ckpt_every, work.data_ptr(), nbytes)
+        return sim, work, nbytes, loss
 
     @staticmethod
     def forward(ctx, phi0, W0, params, nsteps, ckpt_every=64):
         p = prs_params()
         ctypes.pointer(p)[0] = params
         p.W0 = float(W0)
-        sim = Sim(p, phi0=phi0.detach(), device=phi0.device)
-        nbytes = prs_adjoint_workspace_bytes(p, nsteps, ckpt_every)
-        if nbytes == 0:
-            raise PRSError(PRS_EINVAL, "prs_adjoint_workspace_bytes")
-        work = torch.empty(nbytes, dtype=torch.uint8, device=phi0.device)
-        loss = prs_adjoint_forward(sim.ctx, nsteps, ckpt_every, work.data_ptr(), nbytes)
+        p.precision = PRS_F64 if phi0.dtype == torch.float64 else PRS_F32
+        sim, work, nbytes, loss = PRSLoss._run_forward(p, phi0.detach(), nsteps, ckpt_every)
         ctx.sim, ctx.work, ctx.nbytes = sim, work, nbytes
+        ctx.p, ctx.phi0, ctx.nsteps, ctx.ckpt_every = p, phi0.detach(), nsteps, ckpt_every
         ctx.W0_dtype, ctx.W0_device = W0.dtype, W0.device
+        ctx.phi_dtype = phi0.dtype
         return torch.tensor(loss, dtype=torch.float64, device=phi0.device)
 
     @staticmethod
     def backward(ctx, grad_out):
+        if ctx.sim is None:      # a second backward over the same graph: replay the forward
+            ctx.sim, ctx.work, ctx.nbytes, _ = PRSLoss._run_forward(ctx.p, ctx.phi0, ctx.nsteps,
+                                                                    ctx.ckpt_every)
         sim = ctx.sim
         gphi = torch.empty_like(sim.phi_a)
         with torch.cuda.stream(sim.stream):
@@ -509,7 +546,7 @@ class PRSLoss(torch.autograd.Function):
         ctx.sim = None
         ctx.work = None
         g = grad_out.to(torch.float64)
-        grad_phi = (gphi.to(torch.float64) * g).to(torch.float32)
+        grad_phi = (gphi.to(torch.float64) * g).to(ctx.phi_dtype)
         grad_w0 = (g * gw0).to(dtype=ctx.W0_dtype, device=ctx.W0_device)
         return grad_phi, grad_w0, None, None, None
 
@@ -519,7 +556,8 @@ class Batch:
 
     specs: list of dicts with keys shape, deta, nsteps and optionally m, W0,
     alpha, dx, eta0, diag_every, seed (the initial field is drawn from the seed
-    at every run, dphi = 0)."""
+    at every run, dphi = 0) and precision (PRS_F32 or PRS_F64; float64 items
+    run in the stream modes)."""
 
     def __init__(self, specs, device="cuda", stream=None):
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
@@ -531,9 +569,10 @@ class Batch:
             for sp in specs:
                 p = make_params(sp["shape"], deta=sp["deta"], m=sp.get("m", 1.0), W0=sp.get("W0", 10.0),
                                 alpha=sp.get("alpha", 3.0), dx=sp.get("dx", 1.0),
-                                eta0=sp.get("eta0", 1.0), diag_every=sp.get("diag_every", 0))
+                                eta0=sp.get("eta0", 1.0), diag_every=sp.get("diag_every", 0),
+                                precision=sp.get("precision", PRS_F32))
                 n = sites(p)
-                f = [torch.empty(n, dtype=torch.float32, device=device) for _ in range(3)]
+                f = [torch.empty(n, dtype=field_dtype(p), device=device) for _ in range(3)]
                 it = prs_batch_item()
                 it.p = p
                 it.nsteps = int(sp["nsteps"])

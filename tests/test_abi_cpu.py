@@ -57,6 +57,8 @@ def test_workspace_and_records():
     ("W0", 0.0, prs.PRS_EINVAL),
     ("beta", 2.0, prs.PRS_EUNSUPPORTED),
     ("phi0", -1.0, prs.PRS_EINVAL),
+    ("precision", 2, prs.PRS_EINVAL),
+    ("reserved", 1, prs.PRS_EINVAL),
 ])
 def test_invalid_params_rejected_before_launch(field, value, code):
     p = c1()
@@ -102,3 +104,12 @@ def test_fit_matches_oracle_fit():
     assert mu == pytest.approx(-0.95, abs=0.02)
     mu, nu = prs.prs_fit_scaling(recs[:1])
     assert math.isnan(mu)
+
+
+def test_float64_workspace_holds_double_fields():
+    """The 2D workspace carries a second phi_dot field: twice as large in
+    float64 (same partials and records)."""
+    p32 = prs.make_params((512, 256), deta=0.25)
+    p64 = prs.make_params((512, 256), deta=0.25, precision=prs.PRS_F64)
+    assert prs.prs_workspace_bytes(p64) - prs.prs_workspace_bytes(p32) == 512 * 256 * 4
+    assert prs.prs_adjoint_workspace_bytes(p64, 16, 4) > prs.prs_adjoint_workspace_bytes(p32, 16, 4)
