@@ -33,6 +33,7 @@ BYTES_PER_UPDATE = 16          # read phi, phi_dot; write phi^{n+1}, phi_dot (FP
 # configuration without a measurement reports null.
 TRAFFIC_PER_LAUNCH = {
     (1, 16, 1, 4): 1279435530,
+    (2, 128, 1, 8): 1152904174,
 }
 
 WORKLOAD = {

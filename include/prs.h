@@ -172,8 +172,9 @@ prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, dou
 prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t flags, int32_t* vec,
                             int32_t* rows, int32_t* ty);
 
-/* Temporal blocking (2D): with steps_per_pass = T in 2..4 (default 2 for 2D
- * lattices; the autotuner may pick another) prs_step_n advances up to T steps
+/* Temporal blocking (2D): with steps_per_pass = T in {2, 3, 4}, or 6 or 8 in
+ * float32 (default 2 for 2D lattices; the autotuner may pick another; other
+ * values give PRS_EINVAL) prs_step_n advances up to T steps
  * per pass over HBM -- a pass never has a recorded state inside it -- so each
  * value is read about once per T steps.  Results are bitwise those of single
  * steps.  The second phi_dot buffer this needs lives in the workspace; every
@@ -289,9 +290,10 @@ prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
 /* Tiling of one item (as prs_set_tiling; the persistent modes need ty = 1). */
 prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
 
-/* Steps per pass of one item: 1 .. 4 (2 is the default for 2D items; more
- * than 1 for 2D items with nx <= 2^28 only, PRS_EUNSUPPORTED otherwise; the
- * persistent modes take at most 2).  The second phi_dot field multi-step
+/* Steps per pass of one item: 1, or a multi-step pass length as for
+ * prs_set_time_blocking (2 is the default for 2D items; more than 1 for 2D
+ * items with nx <= 2^28 only, PRS_EUNSUPPORTED otherwise; the persistent
+ * modes take at most 2).  The second phi_dot field multi-step
  * passes need lives in the workspace. */
 prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass);
 

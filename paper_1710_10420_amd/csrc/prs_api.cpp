@@ -49,7 +49,6 @@ prs_status hip_fail(hipError_t e, const char* what)
 constexpr size_t kAlign = 256;
 constexpr int64_t kRecCap = 1024;   // device records buffered before a flush
 constexpr int64_t kMinRows = 8;     // smallest marching tile the workspace allows
-constexpr int kMaxPassSteps = 4;    // most leapfrog steps fused into one pass (2D)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -134,26 +133,37 @@ int64_t partial_capacity(const Geometry& g)
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Steps of each pass for nsteps steps from n0 with up to T steps per pass:
-// no pass has a recorded state (n % K == 0, K > 0) strictly inside it, and
+// no pass has a recorded state (n % K == 0, K > 0) strictly inside it, every
+// multi-step pass has a length with a kernel (the longest that fits), and
 // the number of multi-step passes is even (each flips the phi_dot buffer, so
 // phi_dot ends where it started).
-std::vector<uint8_t> plan_passes(int64_t n0, int64_t nsteps, int T, int64_t K)
+std::vector<uint8_t> plan_passes(const Geometry& g, int64_t n0, int64_t nsteps, int T, int64_t K)
 {
     std::vector<uint8_t> plan;
     int64_t nmulti = 0;
     for (int64_t n = n0; n < n0 + nsteps;) {
         int64_t L = std::min<int64_t>(T, n0 + nsteps - n);
         if (K > 0) L = std::min<int64_t>(L, (n / K + 1) * K - n);
+        while (L > 1 && !tb_steps_supported(g, (int)L)) --L;
         plan.push_back((uint8_t)L);
         nmulti += L > 1 ? 1 : 0;
         n += L;
     }
     if (nmulti % 2 == 1) {
+        // one flip too many: split the last multi-step pass, into two halves
+        // when both are multi-step lengths (4 -> 2+2, 6 -> 3+3, 8 -> 4+4),
+        // otherwise into single steps
         for (size_t i = plan.size(); i-- > 0;)
             if (plan[i] > 1) {
                 const int L = plan[i];
+                const int a = L / 2, b = L - a;
                 plan.erase(plan.begin() + (std::ptrdiff_t)i);
-                plan.insert(plan.begin() + (std::ptrdiff_t)i, (size_t)L, (uint8_t)1);
+                if (a > 1 && tb_steps_supported(g, a) && tb_steps_supported(g, b)) {
+                    plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)b);
+                    plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)a);
+                } else {
+                    plan.insert(plan.begin() + (std::ptrdiff_t)i, (size_t)L, (uint8_t)1);
+                }
                 break;
             }
     }
@@ -326,7 +336,7 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int64_t end = c->step + nsteps;
 
     const int T = (c->pi_alt != nullptr && c->til.ty == 1 && tb_supported(c->geo)) ? c->tblock : 1;
-    const std::vector<uint8_t> plan = plan_passes(c->step, nsteps, T, want ? K : 0);
+    const std::vector<uint8_t> plan = plan_passes(c->geo, c->step, nsteps, T, want ? K : 0);
 
     void* pi_cur = c->pi;
     void* pi_oth = c->pi_alt;
@@ -379,6 +389,8 @@ prs_status prs_set_time_blocking(prs_ctx* c, int32_t steps_per_pass)
         return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
     if (steps_per_pass > 1 && c->p.ndim != 2)
         return fail(PRS_EUNSUPPORTED, "multi-step passes are implemented for 2D lattices");
+    if (steps_per_pass > 1 && tb_supported(c->geo) && !tb_steps_supported(c->geo, steps_per_pass))
+        return fail(PRS_EINVAL, "no %d-step pass kernel (2, 3, 4; 6 and 8 in float32)", steps_per_pass);
     c->tblock = steps_per_pass;
     return PRS_OK;
 }
@@ -390,7 +402,7 @@ prs_status prs_plan_passes(const prs_ctx* c, int64_t nsteps, int32_t with_record
     const int T = (c->pi_alt != nullptr && c->til.ty == 1 && tb_supported(c->geo)) ? c->tblock : 1;
     const int64_t K = (with_records && c->p.diag_every > 0) ? c->p.diag_every : 0;
     int64_t m = 0, n1 = 0;
-    for (uint8_t L : plan_passes(c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
+    for (uint8_t L : plan_passes(c->geo, c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
     if (multi_passes) *multi_passes = m;
     if (single_passes) *single_passes = n1;
     return PRS_OK;
@@ -859,13 +871,13 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
 // per pass, no recorded state inside a pass, an even number of multi-step
 // passes so phi_dot ends in the caller's buffer), then the diagnostics-only
 // pass of the final state.
-std::vector<PassEntry> batch_plan(const prs_batch_item& it, int T)
+std::vector<PassEntry> batch_plan(const prs_batch_item& it, const Geometry& g, int T)
 {
     const int64_t S = it.nsteps, K = it.p.diag_every;
     std::vector<PassEntry> out;
     int64_t n = 0, rec = 0;
     int alt = 0;
-    for (uint8_t L : plan_passes(0, S, T, K)) {
+    for (uint8_t L : plan_passes(g, 0, S, T, K)) {
         const bool r = K > 0 && n % K == 0;
         out.push_back(PassEntry{(int32_t)n, (int32_t)L, r ? (int32_t)rec++ : -1, alt});
         if (L > 1) alt ^= 1;
@@ -932,7 +944,7 @@ prs_status batch_item_begin(prs_batch* b, int32_t r, ItemCursor& cur, hipStream_
 {
     const prs_batch_item& it = b->items[r];
     cur.item = r;
-    cur.plan = batch_plan(it, b->tblock[r]);
+    cur.plan = batch_plan(it, b->geo[r], b->tblock[r]);
     cur.next = 0;
     cur.coef = prs_ctx{};
     cur.coef.p = it.p;
@@ -1070,7 +1082,7 @@ prs_status batch_upload(prs_batch* b)
         float2* dcoef = reinterpret_cast<float2*>(base + b->off_coef + b->coef_off[r]);
         HIP_TRY(hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice),
                 "coefficient upload");
-        const std::vector<PassEntry> plan = batch_plan(it, b->tblock[r]);
+        const std::vector<PassEntry> plan = batch_plan(it, b->geo[r], b->tblock[r]);
         void* dpass = base + b->off_pass + b->pass_off[r];
         HIP_TRY(hipMemcpy(dpass, plan.data(), plan.size() * sizeof(PassEntry), hipMemcpyHostToDevice),
                 "pass table upload");
@@ -1224,6 +1236,8 @@ prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps
         return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
     if (steps_per_pass > 1 && !tb_supported(b->geo[item]))
         return fail(PRS_EUNSUPPORTED, "multi-step passes are implemented for 2D lattices with nx <= 2^28");
+    if (steps_per_pass > 1 && !tb_steps_supported(b->geo[item], steps_per_pass))
+        return fail(PRS_EINVAL, "no %d-step pass kernel (2, 3, 4; 6 and 8 in float32)", steps_per_pass);
     if (item_tiles_max(b->geo[item], b->til[item], std::max(2, steps_per_pass)) > b->part_cap[item])
         return fail(PRS_EINVAL, "steps per pass need more wave tiles than the workspace holds");
     b->tblock[item] = steps_per_pass;
@@ -1252,7 +1266,7 @@ prs_status prs_batch_state(const prs_batch* b, int32_t item, void** phi, void** 
 {
     if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
     const prs_batch_item& it = b->items[item];
-    const std::vector<PassEntry> plan = batch_plan(it, b->tblock[item]);
+    const std::vector<PassEntry> plan = batch_plan(it, b->geo[item], b->tblock[item]);
     const int64_t np = (int64_t)plan.size();
     if (phi) *phi = ((np - 1) & 1) ? it.phi_b : it.phi_a;
     if (dphi) *dphi = it.dphi;
@@ -1595,6 +1609,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     e = hipMemcpyAsync(save_phi, c->phi[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(save_pi, c->pi, bytes, hipMemcpyDeviceToDevice, c->stream);
     for (int T = 1; T <= max_T; ++T) {
+        if (T > 1 && !tb_steps_supported(c->geo, T)) continue;
         per = T;
         for (const Tiling& t : cand) {
             if (e != hipSuccess) break;

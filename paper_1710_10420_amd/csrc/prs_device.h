@@ -716,8 +716,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(const R* __restrict__ phi, 
 
 // ----------------------------------------- T steps per HBM pass (2D) --------
 //
-// Temporal blocking: T = 2, 3 or 4 leapfrog steps per pass over HBM, with
-// overlapped wave tiles.  A wave's 64 lanes hold 64*VEC consecutive sites; the first and
+// Temporal blocking: T = 2, 3, 4 (and, in float32, 6 or 8) leapfrog steps
+// per pass over HBM, with overlapped wave tiles.  A wave's 64 lanes hold 64*VEC consecutive sites; the first and
 // last H = ceil(T/VEC) lanes are halo lanes whose sites belong to the
 // neighbouring tiles.  Level k (step n+k-1) is computed for every lane from
 // level k-1 of the lanes on either side (plain shuffles), so the sites within
@@ -1275,6 +1275,14 @@ hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const void* ph
     case 2: return launch_tb_t<R, VEC, 2>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     case 3: return launch_tb_t<R, VEC, 3>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     case 4: return launch_tb_t<R, VEC, 4>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    case 6:
+        if constexpr (sizeof(R) == 4)
+            return launch_tb_t<R, VEC, 6>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+        break;
+    case 8:
+        if constexpr (sizeof(R) == 4)
+            return launch_tb_t<R, VEC, 8>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+        break;
     }
     return hipErrorInvalidValue;
 }

@@ -72,7 +72,7 @@ hipError_t launch_step(const Geometry& g, const Tiling& t, const void* phi_in, v
                        void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
                        const DiagCoef& dc, hipStream_t s);
 
-// T = 2..4 steps n .. n+T-1 of a 2D lattice in one pass (temporal blocking)
+// T steps n .. n+T-1 of a 2D lattice in one pass (temporal blocking)
 // with overlapped wave tiles; k holds the T step coefficients.  Reads phi_in
 // and pi_in, writes phi^{n+T} to phi_out and phi_dot^{n+T-1/2} to pi_out
 // (pi_out != pi_in).  With diag, the partials are those of the input state.
@@ -84,6 +84,9 @@ int64_t tb_tiles(const Geometry& g, const Tiling& t, int T);
 // Multi-step passes exist for 2D lattices whose rows are shorter than 2^28
 // sites (their loads and stores address a row with 32-bit byte offsets).
 bool tb_supported(const Geometry& g);
+// Steps per multi-step pass with a kernel: 2, 3, 4, and 6, 8 in float32.
+bool tb_steps_supported(const Geometry& g, int T);
+constexpr int kMaxPassSteps = 8;   // most leapfrog steps fused into one pass
 
 // Reduces `count` partials in a fixed order into one record at `rec`.
 hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,

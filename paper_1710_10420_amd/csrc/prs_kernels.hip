@@ -421,7 +421,7 @@ hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const void* ph
                        const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
                        const DiagCoef& dc, hipStream_t s)
 {
-    if (!tb_supported(g) || !tiling_supported(g, t) || t.ty != 1) return hipErrorInvalidValue;
+    if (!tb_steps_supported(g, T) || !tiling_supported(g, t) || t.ty != 1) return hipErrorInvalidValue;
     return g.f64 ? launch_tb2d_f64(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s)
                  : launch_tb2d_f32(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
 }
@@ -598,6 +598,12 @@ int64_t tb_owned_width(int vec, int T)
 bool tb_supported(const Geometry& g)
 {
     return g.ndim == 2 && g.nx <= ((int64_t)1 << 28);
+}
+
+bool tb_steps_supported(const Geometry& g, int T)
+{
+    if (!tb_supported(g)) return false;
+    return T == 2 || T == 3 || T == 4 || (!g.f64 && (T == 6 || T == 8));
 }
 
 int64_t tb_tiles(const Geometry& g, const Tiling& t, int T)

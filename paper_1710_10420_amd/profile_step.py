@@ -31,7 +31,7 @@ def main():
     ap.add_argument("--copies", type=int, default=10)
     ap.add_argument("--adjoint", action="store_true", help="also run a 64-step adjoint (K = 64)")
     ap.add_argument("--tiling", default=None, help="vec,rows,ty (default: the library default)")
-    ap.add_argument("--steps-per-pass", type=int, default=None, help="1 or 2 (2D only)")
+    ap.add_argument("--steps-per-pass", type=int, default=None, help="steps per pass (2D)")
     args = ap.parse_args()
     w = WORKLOADS[args.workload]
     p = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"])

@@ -346,9 +346,10 @@ def test_full_size_3d_1024_sampled():
     ((1030, 9), 64, 67), ((256, 256), 10, 50), ((512, 300), 8, 37), ((248, 40), 12, 31),
 ])
 def test_multi_step_passes_bitwise_equal_single_steps(shape, K, steps):
-    """Temporal blocking (2, 3 or 4 steps per pass) changes only how often
-    HBM is visited: fields and records are bitwise those of single steps, for
-    every tiling, ragged sizes, record cadences and odd step counts."""
+    """Temporal blocking (2, 3, 4, 6 or 8 steps per pass) changes only how
+    often HBM is visited: fields and records are bitwise those of single
+    steps, for every tiling, ragged sizes, record cadences and odd step
+    counts."""
     say("multi-step", shape, K, steps)
     prs = gpu_prs()
     gp, _ = params_pair(shape, 0.25, m=2.0, W0=6.0, diag_every=K)
@@ -358,7 +359,7 @@ def test_multi_step_passes_bitwise_equal_single_steps(shape, K, steps):
     r_ref = ref.step_n(steps)
     rp, rd = (host(t) for t in ref.state())
     base = tilings_for(shape)
-    for T in (2, 3, 4):
+    for T in (2, 3, 4, 6, 8):
         for t in base + [(base[0][0], 8, 1)]:
             sim = prs.Sim(gp, phi0=to_dev(phi0))
             sim.set_time_blocking(T)
@@ -379,8 +380,16 @@ def test_multi_step_default_and_limits():
     gp, _ = params_pair((64, 64), 0.25)
     sim = prs.Sim(gp, seed=1)
     assert sim.time_blocking() == 2
-    with pytest.raises(prs.PRSError):
-        sim.set_time_blocking(5)
+    for bad in (5, 7, 9, 0):
+        with pytest.raises(prs.PRSError) as e:
+            sim.set_time_blocking(bad)
+        assert e.value.status == prs.PRS_EINVAL
+    gp64 = prs.make_params((64, 64), deta=0.25, precision=prs.PRS_F64)
+    sim64 = prs.Sim(gp64, seed=1)
+    sim64.set_time_blocking(4)
+    with pytest.raises(prs.PRSError) as e:
+        sim64.set_time_blocking(8)
+    assert e.value.status == prs.PRS_EINVAL
     gp3, _ = params_pair((16, 16, 16), 0.2)
     sim3 = prs.Sim(gp3, seed=1)
     assert sim3.time_blocking() == 1
