@@ -142,30 +142,38 @@ __device__ __forceinline__ R lap3(R c, R xm, R xp, R ym, R yp, R zm, R zp, R inv
 }
 
 // Eqs. (4)-(5) with the FP64-derived coefficients of StepCoefT:
-// V'(phi) = F phi (kc phi^2 - 1), the bracket formed with one rounding.
-// UNIT (phi0 = 1, kc = 1) drops the exact multiplication by kc.
+//   pi' = a pi + b (Lap phi - V'(phi)),  V'(phi) = F phi (kc phi^2 - 1),
+// evaluated as a pi + (b Lap phi - (b F) phi (kc phi^2 - 1)): the bracket is
+// formed with one rounding, b F is one product per launch (it is wave-uniform
+// and hoisted out of the march), and the update costs six operations per
+// site.  UNIT (phi0 = 1, kc = 1) drops the exact multiplication by kc.
 template <bool UNIT = false, typename R>
 __device__ __forceinline__ void kick_drift(R c, R lap, R pi, const StepCoefT<R>& k, R& pi_new, R& phi_new)
 {
     const R ck = UNIT ? c : c * k.kc;
     const R q = fmar(ck, c, R(-1));
-    const R dv = (k.F * c) * q;                // V'(phi)
-    pi_new = fmar(k.a, pi, k.b * (lap - dv));  // Eq. (4)
-    phi_new = fmar(k.deta, pi_new, c);         // Eq. (5)
+    const R bF = k.b * k.F;
+    const R v = fmar(-(bF * c), q, k.b * lap);   // b (Lap phi - V'(phi))
+    pi_new = fmar(k.a, pi, v);                   // Eq. (4)
+    phi_new = fmar(k.deta, pi_new, c);           // Eq. (5)
 }
 
 // Value held by the lane on the left (lane - 1) / right (lane + 1) of this
-// one, by a wave-wide DPP shift; the end lane keeps its own value.
+// one, by a wave-wide DPP shift.  The end lane (lane 0 / lane 63) has no
+// source and reads 0; every caller either replaces that value (halo loads of
+// the single-step march) or never stores the end lanes' results (overlapped
+// tiles of the multi-step passes).  Without an "old" operand the compiler can
+// fold the shift into the instruction that consumes it.
 __device__ __forceinline__ float from_left_lane(float v)
 {
     const int b = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x138, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(b, 0x138, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float from_right_lane(float v)
 {
     const int b = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x130, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(b, 0x130, 0xF, 0xF, true));
 }
 
 // The same shifts for a double: both 32-bit halves move together.
@@ -173,8 +181,8 @@ __device__ __forceinline__ double from_left_lane(double v)
 {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
     const int lo = (int)(uint32_t)b, hi = (int)(uint32_t)(b >> 32);
-    const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false);
-    const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
+    const uint32_t l = (uint32_t)__builtin_amdgcn_mov_dpp(lo, 0x138, 0xF, 0xF, true);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_mov_dpp(hi, 0x138, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((uint64_t)h << 32) | l);
 }
 
@@ -182,8 +190,8 @@ __device__ __forceinline__ double from_right_lane(double v)
 {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
     const int lo = (int)(uint32_t)b, hi = (int)(uint32_t)(b >> 32);
-    const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
-    const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
+    const uint32_t l = (uint32_t)__builtin_amdgcn_mov_dpp(lo, 0x130, 0xF, 0xF, true);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_mov_dpp(hi, 0x130, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((uint64_t)h << 32) | l);
 }
 
