@@ -170,13 +170,13 @@ def batch_leg(prs, torch, reps=2):
                 p = prs.make_params(sp["shape"], deta=sp["deta"], m=sp["m"], W0=sp["W0"])
                 t = prs.Sim(p, seed=1)
                 prs.prs_autotune(t.ctx, None, flags)
-                tuned[key] = (t.tiling(), t.time_blocking() if len(key) == 2 else 1)
+                tuned[key] = (t.tiling(), t.time_blocking())
                 t.close()
             til, T = tuned[key]
             b.set_time_blocking(r, 1)
             b.set_tiling(r, *til)
             b.set_time_blocking(r, T if mode in (prs.PRS_BATCH_STREAMS_GRAPH, prs.PRS_BATCH_STREAMS)
-                                else min(2, 2 if len(key) == 2 else 1))
+                                else (2 if len(key) == 2 else 1))
         b.set_mode(mode)
         b.run()                                   # builds and instantiates the graph
         torch.cuda.synchronize()

@@ -93,8 +93,8 @@ typedef struct prs_ctx prs_ctx;
 /* ---- single run ------------------------------------------------------- */
 
 /* Bytes of device workspace prs_init needs for these parameters (per-wave
- * diagnostic partial sums, the record buffer and, in 2D, a second phi_dot
- * field for two-step passes); 0 if p is invalid. */
+ * diagnostic partial sums, the record buffer and a second phi_dot field for
+ * multi-step passes); 0 if p is invalid. */
 size_t prs_workspace_bytes(const prs_params* p);
 
 /* Create a run context over caller-owned device buffers.
@@ -172,15 +172,19 @@ prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, dou
 prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t flags, int32_t* vec,
                             int32_t* rows, int32_t* ty);
 
-/* Temporal blocking (2D): with steps_per_pass = T in {2, 3, 4}, or 6 or 8 in
- * float32 (default 2 for 2D lattices; the autotuner may pick another; other
- * values give PRS_EINVAL) prs_step_n advances up to T steps
- * per pass over HBM -- a pass never has a recorded state inside it -- so each
- * value is read about once per T steps.  Results are bitwise those of single
- * steps.  The second phi_dot buffer this needs lives in the workspace; every
- * prs_step_n call still ends with phi_dot in the caller's dphi buffer.  3D
- * lattices support only 1 (PRS_EUNSUPPORTED otherwise); 2D lattices with
- * nx > 2^28 keep the setting but run single-step passes. */
+/* Temporal blocking: with steps_per_pass = T > 1, prs_step_n advances up to
+ * T steps per pass over HBM -- a pass never has a recorded state inside it --
+ * so each value is read about once per T steps.  T may be 2, 3, 4, and 6 or 8
+ * in float32, for 2D lattices (default 2), and 2, or 3 in float32, for 3D
+ * lattices (default 1); other values give PRS_EINVAL.  A pass uses T steps
+ * only when the tiling has a T-step kernel (2D: ty = 1; 3D: vec 1 with any
+ * ty, or vec 2 with ty 1 or 2; a wave owns 4 rows along y, 8 with ty = 4) and
+ * otherwise the longest length that has one; the autotuner picks T with the
+ * tiling.  Results are bitwise those of single steps.  The second phi_dot
+ * buffer this needs lives in the workspace; every prs_step_n call still ends
+ * with phi_dot in the caller's dphi buffer.  Lattices whose rows (2D) reach
+ * 2^28 sites or whose planes (3D) reach 2^31 bytes keep the setting but run
+ * single-step passes. */
 prs_status prs_set_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
 prs_status prs_get_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
 
@@ -291,10 +295,10 @@ prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
 prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
 
 /* Steps per pass of one item: 1, or a multi-step pass length as for
- * prs_set_time_blocking (2 is the default for 2D items; more than 1 for 2D
- * items with nx <= 2^28 only, PRS_EUNSUPPORTED otherwise; the persistent
- * modes take at most 2).  The second phi_dot field multi-step
- * passes need lives in the workspace. */
+ * prs_set_time_blocking (2 is the default for 2D items, 1 for 3D items;
+ * PRS_EUNSUPPORTED for rows or planes too long for multi-step passes; the
+ * persistent modes take at most 2 in 2D and 1 in 3D).  The second phi_dot
+ * field multi-step passes need lives in the workspace. */
 prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass);
 
 /* Device pointers of item `item`'s final phi and phi_dot after prs_batch_run

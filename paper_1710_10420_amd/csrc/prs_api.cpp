@@ -127,6 +127,7 @@ int64_t partial_capacity(const Geometry& g)
     Tiling t{1, (int)kMinRows, 1};
     int64_t n = tile_counts(g, t).ntiles;
     if (g.ndim == 2) n = std::max<int64_t>(n, tb_tiles(g, t, kMaxPassSteps));
+    else n = std::max<int64_t>(n, tb_tiles(g, t, 3));   // 3D: 4 owned rows, T <= 3
     return n;
 }
 
@@ -137,14 +138,14 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // multi-step pass has a length with a kernel (the longest that fits), and
 // the number of multi-step passes is even (each flips the phi_dot buffer, so
 // phi_dot ends where it started).
-std::vector<uint8_t> plan_passes(const Geometry& g, int64_t n0, int64_t nsteps, int T, int64_t K)
+std::vector<uint8_t> plan_passes(const Geometry& g, const Tiling& t, int64_t n0, int64_t nsteps, int T, int64_t K)
 {
     std::vector<uint8_t> plan;
     int64_t nmulti = 0;
     for (int64_t n = n0; n < n0 + nsteps;) {
         int64_t L = std::min<int64_t>(T, n0 + nsteps - n);
         if (K > 0) L = std::min<int64_t>(L, (n / K + 1) * K - n);
-        while (L > 1 && !tb_steps_supported(g, (int)L)) --L;
+        while (L > 1 && !tb_pass_supported(g, t, (int)L)) --L;
         plan.push_back((uint8_t)L);
         nmulti += L > 1 ? 1 : 0;
         n += L;
@@ -158,7 +159,7 @@ std::vector<uint8_t> plan_passes(const Geometry& g, int64_t n0, int64_t nsteps, 
                 const int L = plan[i];
                 const int a = L / 2, b = L - a;
                 plan.erase(plan.begin() + (std::ptrdiff_t)i);
-                if (a > 1 && tb_steps_supported(g, a) && tb_steps_supported(g, b)) {
+                if (a > 1 && tb_pass_supported(g, t, a) && tb_pass_supported(g, t, b)) {
                     plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)b);
                     plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)a);
                 } else {
@@ -184,9 +185,9 @@ struct prs_ctx {
     int64_t partial_cap;
     prs_stats* drec;
     prs_stats* hrec;   // pinned staging buffer
-    void* pi_alt;      // second phi_dot buffer (workspace, 2D) for multi-step passes
+    void* pi_alt;      // second phi_dot buffer (workspace) for multi-step passes
     Tiling adj_til;    // tiling of the reverse-sweep kernel
-    int32_t tblock;    // steps per pass: 1 .. 4 (more than 1 in 2D only)
+    int32_t tblock;    // steps per pass (1: single steps)
     hipStream_t stream;
     int64_t step;
     // adjoint bookkeeping between prs_adjoint_forward and _backward
@@ -257,7 +258,7 @@ size_t prs_workspace_bytes(const prs_params* p)
     const Geometry g = geometry_of(*p);
     size_t b = align_up((size_t)partial_capacity(g) * sizeof(WavePartial)) +
                align_up((size_t)kRecCap * sizeof(prs_stats));
-    if (p->ndim == 2) b += align_up(field_bytes(*p));   // second phi_dot
+    b += align_up(field_bytes(*p));   // second phi_dot for multi-step passes
     return b;
 }
 
@@ -294,11 +295,8 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, v
         static_cast<char*>(workspace) + align_up((size_t)c->partial_cap * sizeof(WavePartial)));
     c->pi_alt = nullptr;
     c->adj_til = c->til;
-    c->tblock = 1;
-    if (p->ndim == 2) {
-        c->pi_alt = reinterpret_cast<char*>(c->drec) + align_up((size_t)kRecCap * sizeof(prs_stats));
-        c->tblock = 2;
-    }
+    c->pi_alt = reinterpret_cast<char*>(c->drec) + align_up((size_t)kRecCap * sizeof(prs_stats));
+    c->tblock = p->ndim == 2 ? 2 : 1;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->step = 0;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->hrec), (size_t)kRecCap * sizeof(prs_stats),
@@ -335,8 +333,8 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int64_t K = c->p.diag_every;
     const int64_t end = c->step + nsteps;
 
-    const int T = (c->pi_alt != nullptr && c->til.ty == 1 && tb_supported(c->geo)) ? c->tblock : 1;
-    const std::vector<uint8_t> plan = plan_passes(c->geo, c->step, nsteps, T, want ? K : 0);
+    const int T = tb_supported(c->geo) ? c->tblock : 1;
+    const std::vector<uint8_t> plan = plan_passes(c->geo, c->til, c->step, nsteps, T, want ? K : 0);
 
     void* pi_cur = c->pi;
     void* pi_oth = c->pi_alt;
@@ -349,7 +347,7 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
         if (L > 1) {
             StepCoef64 k[kMaxPassSteps];
             for (int i = 0; i < L; ++i) k[i] = coef_for(c, n + i);
-            HIP_TRY(launch_tb2d(L, c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, pi_oth, k, diag,
+            HIP_TRY(launch_tb(L, c->geo, c->til, c->phi[c->cur], c->phi[c->cur ^ 1], pi_cur, pi_oth, k, diag,
                                 parts, dc, c->stream),
                     "multi-step kernel launch");
             std::swap(pi_cur, pi_oth);
@@ -387,10 +385,9 @@ prs_status prs_set_time_blocking(prs_ctx* c, int32_t steps_per_pass)
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");
     if (steps_per_pass < 1 || steps_per_pass > kMaxPassSteps)
         return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
-    if (steps_per_pass > 1 && c->p.ndim != 2)
-        return fail(PRS_EUNSUPPORTED, "multi-step passes are implemented for 2D lattices");
     if (steps_per_pass > 1 && tb_supported(c->geo) && !tb_steps_supported(c->geo, steps_per_pass))
-        return fail(PRS_EINVAL, "no %d-step pass kernel (2, 3, 4; 6 and 8 in float32)", steps_per_pass);
+        return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, and 6, 8 in float32; "
+                    "3D: 2, and 3 in float32)", steps_per_pass);
     c->tblock = steps_per_pass;
     return PRS_OK;
 }
@@ -399,10 +396,10 @@ prs_status prs_plan_passes(const prs_ctx* c, int64_t nsteps, int32_t with_record
                            int64_t* single_passes)
 {
     if (!c || nsteps < 0) return fail(PRS_EINVAL, "invalid arguments");
-    const int T = (c->pi_alt != nullptr && c->til.ty == 1 && tb_supported(c->geo)) ? c->tblock : 1;
+    const int T = tb_supported(c->geo) ? c->tblock : 1;
     const int64_t K = (with_records && c->p.diag_every > 0) ? c->p.diag_every : 0;
     int64_t m = 0, n1 = 0;
-    for (uint8_t L : plan_passes(c->geo, c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
+    for (uint8_t L : plan_passes(c->geo, c->til, c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
     if (multi_passes) *multi_passes = m;
     if (single_passes) *single_passes = n1;
     return PRS_OK;
@@ -772,7 +769,7 @@ struct prs_batch {
     std::vector<prs_batch_item> items;
     std::vector<Geometry> geo;
     std::vector<Tiling> til;
-    std::vector<int32_t> tblock;        // steps per pass (1 .. 4; more than 1 for 2D items only)
+    std::vector<int32_t> tblock;        // steps per pass (1: single steps)
     std::vector<int64_t> npasses;       // per item, including the final record pass
     std::vector<int64_t> rec_off;       // count + 1 record offsets
     std::vector<int64_t> part_cap;      // partial capacity per realisation
@@ -847,7 +844,7 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
     L.alt_off.assign(count, 0);
     for (int32_t r = 0; r < count; ++r) {
         L.alt_off[r] = o - L.alt;
-        if (items[r].p.ndim == 2) o += align_up(field_bytes(items[r].p));
+        o += align_up(field_bytes(items[r].p));
     }
     L.part = o;
     L.part_off.assign(count, 0);
@@ -871,13 +868,13 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
 // per pass, no recorded state inside a pass, an even number of multi-step
 // passes so phi_dot ends in the caller's buffer), then the diagnostics-only
 // pass of the final state.
-std::vector<PassEntry> batch_plan(const prs_batch_item& it, const Geometry& g, int T)
+std::vector<PassEntry> batch_plan(const prs_batch_item& it, const Geometry& g, const Tiling& t, int T)
 {
     const int64_t S = it.nsteps, K = it.p.diag_every;
     std::vector<PassEntry> out;
     int64_t n = 0, rec = 0;
     int alt = 0;
-    for (uint8_t L : plan_passes(g, 0, S, T, K)) {
+    for (uint8_t L : plan_passes(g, t, 0, S, T, K)) {
         const bool r = K > 0 && n % K == 0;
         out.push_back(PassEntry{(int32_t)n, (int32_t)L, r ? (int32_t)rec++ : -1, alt});
         if (L > 1) alt ^= 1;
@@ -944,7 +941,7 @@ prs_status batch_item_begin(prs_batch* b, int32_t r, ItemCursor& cur, hipStream_
 {
     const prs_batch_item& it = b->items[r];
     cur.item = r;
-    cur.plan = batch_plan(it, b->geo[r], b->tblock[r]);
+    cur.plan = batch_plan(it, b->geo[r], b->til[r], b->tblock[r]);
     cur.next = 0;
     cur.coef = prs_ctx{};
     cur.coef.p = it.p;
@@ -969,7 +966,7 @@ prs_status batch_item_pass(prs_batch* b, ItemCursor& cur, hipStream_t s)
     char* base = static_cast<char*>(b->ws);
     void* phi[2] = {it.phi_a, it.phi_b};
     void* dphi = it.dphi;
-    void* alt = it.p.ndim == 2 ? base + b->off_alt + b->alt_off[r] : nullptr;
+    void* alt = base + b->off_alt + b->alt_off[r];
     void* pi_now = e.alt ? alt : dphi;
     void* pi_next = e.alt ? dphi : alt;
     const bool diag = e.rec >= 0;
@@ -982,7 +979,7 @@ prs_status batch_item_pass(prs_batch* b, ItemCursor& cur, hipStream_t s)
     if (e.steps > 1) {
         StepCoef64 k[kMaxPassSteps];
         for (int i = 0; i < e.steps; ++i) k[i] = coef_for(&cur.coef, n + i);
-        HIP_TRY(launch_tb2d(e.steps, g, t, phi_in, phi_out, pi_now, pi_next, k, diag, parts, dc, s),
+        HIP_TRY(launch_tb(e.steps, g, t, phi_in, phi_out, pi_now, pi_next, k, diag, parts, dc, s),
                 "multi-step kernel launch");
         ntiles = tb_tiles(g, t, e.steps);
     } else if (e.steps == 1) {
@@ -1082,7 +1079,7 @@ prs_status batch_upload(prs_batch* b)
         float2* dcoef = reinterpret_cast<float2*>(base + b->off_coef + b->coef_off[r]);
         HIP_TRY(hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice),
                 "coefficient upload");
-        const std::vector<PassEntry> plan = batch_plan(it, b->geo[r], b->tblock[r]);
+        const std::vector<PassEntry> plan = batch_plan(it, b->geo[r], b->til[r], b->tblock[r]);
         void* dpass = base + b->off_pass + b->pass_off[r];
         HIP_TRY(hipMemcpy(dpass, plan.data(), plan.size() * sizeof(PassEntry), hipMemcpyHostToDevice),
                 "pass table upload");
@@ -1193,7 +1190,7 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
         Tiling t = default_tiling(b->geo.back());
         t.ty = 1;
         b->til.push_back(t);
-        b->tblock.push_back(tb_supported(b->geo.back()) ? 2 : 1);
+        b->tblock.push_back(items[r].p.ndim == 2 && tb_supported(b->geo.back()) ? 2 : 1);
     }
     b->mode = PRS_BATCH_STREAMS;
     b->graph_mode = -1;
@@ -1235,9 +1232,11 @@ prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps
     if (steps_per_pass < 1 || steps_per_pass > kMaxPassSteps)
         return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
     if (steps_per_pass > 1 && !tb_supported(b->geo[item]))
-        return fail(PRS_EUNSUPPORTED, "multi-step passes are implemented for 2D lattices with nx <= 2^28");
+        return fail(PRS_EUNSUPPORTED, "multi-step passes need rows (2D) shorter than 2^28 sites or planes (3D) "
+                    "shorter than 2^31 bytes");
     if (steps_per_pass > 1 && !tb_steps_supported(b->geo[item], steps_per_pass))
-        return fail(PRS_EINVAL, "no %d-step pass kernel (2, 3, 4; 6 and 8 in float32)", steps_per_pass);
+        return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, and 6, 8 in float32; "
+                    "3D: 2, and 3 in float32)", steps_per_pass);
     if (item_tiles_max(b->geo[item], b->til[item], std::max(2, steps_per_pass)) > b->part_cap[item])
         return fail(PRS_EINVAL, "steps per pass need more wave tiles than the workspace holds");
     b->tblock[item] = steps_per_pass;
@@ -1266,7 +1265,7 @@ prs_status prs_batch_state(const prs_batch* b, int32_t item, void** phi, void** 
 {
     if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
     const prs_batch_item& it = b->items[item];
-    const std::vector<PassEntry> plan = batch_plan(it, b->geo[item], b->tblock[item]);
+    const std::vector<PassEntry> plan = batch_plan(it, b->geo[item], b->til[item], b->tblock[item]);
     const int64_t np = (int64_t)plan.size();
     if (phi) *phi = ((np - 1) & 1) ? it.phi_b : it.phi_a;
     if (dphi) *dphi = it.dphi;
@@ -1281,9 +1280,11 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     const bool persistent = persistent_mode(b->mode);
     if (persistent) {
         for (int32_t r = 0; r < b->count; ++r)
-            if (b->til[r].ty != 1 || b->tblock[r] > 2 || b->items[r].p.precision != PRS_F32)
+            if (b->til[r].ty != 1 || b->tblock[r] > (b->items[r].p.ndim == 2 ? 2 : 1) ||
+                b->items[r].p.precision != PRS_F32)
                 return fail(PRS_EINVAL,
-                            "item %d: the persistent modes need float32, ty = 1 and at most 2 steps per pass", r);
+                            "item %d: the persistent modes need float32, ty = 1 and at most 2 steps per pass "
+                            "(single steps in 3D)", r);
     }
     if (b->graph_mode != b->mode) batch_release_graph(b);
     if (b->dirty && persistent) {
@@ -1592,7 +1593,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
             if (per > 1) {
                 StepCoef64 kc[kMaxPassSteps];
                 for (int i = 0; i < per; ++i) kc[i] = coef_for(c, n0 + per * k + i);
-                err = launch_tb2d(per, c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], pa, pb, kc, false, nullptr,
+                err = launch_tb(per, c->geo, t, c->phi[c->cur], c->phi[c->cur ^ 1], pa, pb, kc, false, nullptr,
                                   DiagCoef{}, c->stream);
                 std::swap(pa, pb);
             } else {
@@ -1604,7 +1605,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
         }
         return hipSuccess;
     };
-    const int max_T = (!batch_set && c->pi_alt != nullptr && tb_supported(c->geo)) ? kMaxPassSteps : 1;
+    const int max_T = (!batch_set && tb_supported(c->geo)) ? kMaxPassSteps : 1;
     int best_T = c->tblock;
     e = hipMemcpyAsync(save_phi, c->phi[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(save_pi, c->pi, bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -1613,7 +1614,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
         per = T;
         for (const Tiling& t : cand) {
             if (e != hipSuccess) break;
-            if (T > 1 && t.ty != 1) continue;
+            if (T > 1 && !tb_pass_supported(c->geo, t, T)) continue;
             if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
             if (T > 1 && tb_tiles(c->geo, t, T) > c->partial_cap) continue;
             e = run(t, 2);

@@ -805,11 +805,12 @@ constexpr int kRawBufferWord3 = 0x00020000;
 // Offset that no row reaches (rows are shorter than 2^30 bytes).
 constexpr uint32_t kPastRow = 0xFFFFFFF0u;
 
+// Raw buffer descriptor over [base, base + bytes): lane accesses at byte
+// offsets at or past `bytes` are dropped (loads return 0).
 template <typename R>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const R* f, int32_t row, uint32_t nx, uint32_t bytes)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const R* base, uint32_t bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(f) + (size_t)((uint32_t)row * nx), (short)0,
-                                             (int)bytes, kRawBufferWord3);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(base), (short)0, (int)bytes, kRawBufferWord3);
 }
 
 __device__ __forceinline__ double u64_as_double(uint32_t lo, uint32_t hi)
@@ -817,36 +818,37 @@ __device__ __forceinline__ double u64_as_double(uint32_t lo, uint32_t hi)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// VEC values of this lane at byte offset voff of the span [base, base+bytes).
 template <int VEC, typename R>
-__device__ __forceinline__ void tb_load(const R* f, int32_t row, const TBLane& L, uint32_t bytes, R (&v)[VEC])
+__device__ __forceinline__ void buf_load(const R* base, uint32_t bytes, uint32_t voff, R (&v)[VEC])
 {
     static_assert(VEC * sizeof(R) <= 16, "at most 16 bytes per lane and access");
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(f, row, L.nx, bytes);
+    const __amdgpu_buffer_rsrc_t r = span_rsrc(base, bytes);
     if constexpr (sizeof(R) == 8 && VEC == 2) {
-        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, L.voff, 0, 0);
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
         v[0] = u64_as_double(t[0], t[1]);
         v[1] = u64_as_double(t[2], t[3]);
     } else if constexpr (sizeof(R) == 8) {
-        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, L.voff, 0, 0);
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
         v[0] = u64_as_double(t[0], t[1]);
     } else if constexpr (VEC == 4) {
-        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, L.voff, 0, 0);
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[j] = __uint_as_float(t[j]);
     } else if constexpr (VEC == 2) {
-        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, L.voff, 0, 0);
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
         v[0] = __uint_as_float(t[0]);
         v[1] = __uint_as_float(t[1]);
     } else {
-        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, L.voff, 0, 0));
+        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
     }
 }
 
 template <int VEC, typename R>
-__device__ __forceinline__ void tb_store(R* f, int32_t row, const TBLane& L, uint32_t bytes, const R (&v)[VEC])
+__device__ __forceinline__ void buf_store(R* base, uint32_t bytes, uint32_t soff, const R (&v)[VEC])
 {
     static_assert(VEC * sizeof(R) <= 16, "at most 16 bytes per lane and access");
-    const __amdgpu_buffer_rsrc_t r = row_rsrc(f, row, L.nx, bytes);
+    const __amdgpu_buffer_rsrc_t r = span_rsrc(base, bytes);
     constexpr int W = VEC * (int)sizeof(R) / 4;   // 32-bit words per lane
     __attribute__((ext_vector_type(W == 1 ? 2 : W))) unsigned int t;
 #pragma unroll
@@ -860,12 +862,25 @@ __device__ __forceinline__ void tb_store(R* f, int32_t row, const TBLane& L, uin
         }
     }
     if constexpr (W == 4) {
-        __builtin_amdgcn_raw_buffer_store_b128(t, r, L.soff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(t, r, soff, 0, 0);
     } else if constexpr (W == 2) {
-        __builtin_amdgcn_raw_buffer_store_b64(t, r, L.soff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, soff, 0, 0);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(t[0], r, L.soff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(t[0], r, soff, 0, 0);
     }
+}
+
+// Row `row` of a 2D field through a descriptor spanning that row.
+template <int VEC, typename R>
+__device__ __forceinline__ void tb_load(const R* f, int32_t row, const TBLane& L, uint32_t bytes, R (&v)[VEC])
+{
+    buf_load<VEC>(f + (size_t)((uint32_t)row * L.nx), bytes, L.voff, v);
+}
+
+template <int VEC, typename R>
+__device__ __forceinline__ void tb_store(R* f, int32_t row, const TBLane& L, uint32_t bytes, const R (&v)[VEC])
+{
+    buf_store<VEC>(f + (size_t)((uint32_t)row * L.nx), bytes, L.soff, v);
 }
 
 // Iteration i of the march (y = s0 - T + 1 + i): level k computes row
@@ -1045,6 +1060,261 @@ __global__ __launch_bounds__(kBlock) void k_tb2d(TBArgs<T, R> A)
     const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     if (tile >= A.ntiles) return;
     tb_tile<VEC, T, DIAG, UNIT>(A, tile);
+}
+
+// ----------------------------------------- T steps per HBM pass (3D) --------
+//
+// The 2D scheme with a second in-plane axis.  A wave marches along z; for
+// every plane it holds NY = TY + 2T rows along y (rows y0-T .. y0+TY+T-1,
+// periodic) of 64*VEC sites along x, with H = ceil(T/VEC) halo lanes per side
+// as in 2D.  Level k (step n+k-1) is computed on the rows k .. NY-k-1 from
+// level k-1 held in registers: y-neighbours are the adjacent register rows,
+// x-neighbours DPP shifts, z-neighbours the planes of the pipelined march.
+// Level T covers exactly the TY owned rows, the only ones written.  Rows of a
+// ragged last tile beyond the lattice wrap around: they are computed but
+// never stored.  A plane is addressed through one raw buffer descriptor
+// spanning it (plane bytes < 2^31) and per-lane offsets of each register
+// row, computed once per tile.
+
+template <int T, typename R = float>
+struct TB3Args {
+    const R* phi_in;
+    R* phi_out;
+    const R* pi_in;
+    R* pi_out;
+    WavePartial* partials;
+    int64_t nx, ny, nz;
+    int64_t tiles_x, tiles_y, ntiles;
+    int64_t rows;               // planes per tile along z
+    StepCoefT<R> k[T];
+    DiagCoef dc;
+};
+
+template <int VEC, int T, int TY, typename R>
+struct TB3State {
+    static constexpr int NY = TY + 2 * T;
+    R in[4][NY][VEC];           // phi^n planes, ring over the march
+    R pin[2][NY][VEC];          // phi_dot^{n-1/2} planes (rows 1 .. NY-2)
+    R lv[T][4][NY][VEC];        // level k planes (k = 1 .. T-1)
+    R pl[T][2][NY][VEC];        // level k phi_dot planes
+};
+
+template <int T, int TY>
+struct TB3Lane {
+    static constexpr int NY = TY + 2 * T;
+    uint32_t lrow[NY];          // byte offset in the plane of this lane's sites in register row r
+    uint32_t srow[TY];          // the same for owned rows and lanes inside the lattice, else past the plane
+    uint32_t plane_bytes;
+    uint64_t plane;             // sites per plane
+    int32_t nz;
+    int32_t s0, s1;             // output planes [s0, s1) of the tile
+    int32_t yown;               // owned rows inside the lattice
+    bool own_lane;
+};
+
+template <int VEC, int T, int TY, typename R>
+__device__ __forceinline__ void tb3_load(const R* f, int32_t p, const TB3Lane<T, TY>& L, uint32_t bytes, int r0,
+                                         int r1, R (&v)[TY + 2 * T][VEC])
+{
+    const R* base = f + (size_t)(uint32_t)p * L.plane;
+#pragma unroll
+    for (int r = 0; r < TY + 2 * T; ++r)
+        if (r >= r0 && r < r1) buf_load<VEC>(base, bytes, L.lrow[r], v[r]);
+}
+
+// Iteration i of the z-march (z = s0 - T + 1 + i): level k computes plane
+// s0 - T - k + 2 + i, as in 2D.
+template <int VEC, int T, int TY, bool DIAG, bool UNIT, bool CHECK, int U, typename R>
+__device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T, TY>& L, int32_t i, int32_t last,
+                                         TBRows& rw, TB3State<VEC, T, TY, R>& S, DiagAcc& acc)
+{
+    constexpr int NY = TY + 2 * T;
+    // prefetch phi^n plane z+2 and phi_dot plane z+1 (none after the last)
+    const uint32_t nb = i < last ? L.plane_bytes : 0u;
+    tb3_load<VEC, T, TY>(A.phi_in, rw.phi, L, nb, 0, NY, S.in[(U + 2) & 3]);
+    tb3_load<VEC, T, TY>(A.pi_in, rw.pi, L, nb, 1, NY - 1, S.pin[(U + 1) & 1]);
+    rw.phi = next_row(rw.phi, L.nz);
+    rw.pi = next_row(rw.pi, L.nz);
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        if (CHECK && i < 2 * (k - 1)) continue;
+        const R(*cm)[VEC];
+        const R(*cc)[VEC];
+        const R(*cp)[VEC];
+        const R(*pp)[VEC];
+        if (k == 1) {
+            cm = S.in[(U + 3) & 3];
+            cc = S.in[U & 3];
+            cp = S.in[(U + 1) & 3];
+            pp = S.pin[U & 1];
+        } else {
+            cm = S.lv[k - 1][(U + 2) & 3];
+            cc = S.lv[k - 1][(U + 3) & 3];
+            cp = S.lv[k - 1][U & 3];
+            pp = S.pl[k - 1][(U + 1) & 1];
+        }
+        // level 1 plane z is inside the tile for i in [T-1, T-1 + s1 - s0)
+        const bool diag_plane = DIAG && k == 1 && i >= T - 1 && i < T - 1 + (L.s1 - L.s0);
+        // level T plane s0 + i - (2T - 2), inside [s0, s1) once i >= 2T - 2
+        const int32_t zout = L.s0 + i - (2 * T - 2);
+        const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.plane_bytes : 0u;
+        const size_t obase = (size_t)(uint32_t)(CHECK && i < 2 * T - 2 ? L.s0 : zout) * L.plane;
+#pragma unroll
+        for (int r = k; r < NY - k; ++r) {
+            const R left = from_left_lane(cc[r][VEC - 1]);
+            const R right = from_right_lane(cc[r][0]);
+            R out_phi[VEC], out_pi[VEC];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const R c = cc[r][j];
+                const R xm = j > 0 ? cc[r][j > 0 ? j - 1 : 0] : left;
+                const R xp = j < VEC - 1 ? cc[r][j < VEC - 1 ? j + 1 : j] : right;
+                const R lap = lap3<UNIT>(c, xm, xp, cc[r - 1][j], cc[r + 1][j], cm[r][j], cp[r][j],
+                                         A.k[k - 1].inv_dx2);
+                kick_drift<UNIT>(c, lap, pp[r][j], A.k[k - 1], out_pi[j], out_phi[j]);
+                if constexpr (DIAG) {
+                    if (k == 1 && r >= T && r < T + TY) {
+                        if (diag_plane && r - T < L.yown && L.own_lane) {
+                            const R nm[3] = {xm, cc[r - 1][j], cm[r][j]};
+                            const R np[3] = {xp, cc[r + 1][j], cp[r][j]};
+                            site_diag<3>(c, pp[r][j], nm, np, A.dc, acc);
+                        }
+                    }
+                }
+            }
+            if (k < T) {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    S.lv[k < T ? k : 0][U & 3][r][j] = out_phi[j];
+                    S.pl[k < T ? k : 0][U & 1][r][j] = out_pi[j];
+                }
+            } else {
+                const uint32_t so = L.srow[r - T < TY ? (r - T >= 0 ? r - T : 0) : 0];
+                buf_store<VEC>(A.phi_out + obase, sb, so, out_phi);
+                buf_store<VEC>(A.pi_out + obase, sb, so, out_pi);
+            }
+        }
+    }
+}
+
+template <int VEC, int T, int TY, bool DIAG, bool UNIT, bool CHECK, typename R>
+__device__ __forceinline__ bool tb3_group(const TB3Args<T, R>& A, const TB3Lane<T, TY>& L, int32_t i, int32_t last,
+                                          TBRows& rw, TB3State<VEC, T, TY, R>& S, DiagAcc& acc)
+{
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 0>(A, L, i, last, rw, S, acc);
+    if (i + 1 > last) return false;
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 1>(A, L, i + 1, last, rw, S, acc);
+    if (i + 2 > last) return false;
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 2>(A, L, i + 2, last, rw, S, acc);
+    if (i + 3 > last) return false;
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 3>(A, L, i + 3, last, rw, S, acc);
+    return i + 4 <= last;
+}
+
+// One wave's tile of a T-step 3D pass; `tile` must be below A.ntiles and
+// wave-uniform.
+template <int VEC, int T, int TY, bool DIAG, bool UNIT, typename R>
+__device__ __forceinline__ void tb3_tile(const TB3Args<T, R>& A, int64_t tile)
+{
+    constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
+    constexpr int W = (kWave - 2 * H) * VEC;       // owned sites per wave along x
+    constexpr int NY = TY + 2 * T;
+    constexpr int WARM = (2 * T - 2 + 3) / 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t tx = tl % (uint32_t)A.tiles_x;
+    const uint32_t rest = tl / (uint32_t)A.tiles_x;
+    const uint32_t tyi = rest % (uint32_t)A.tiles_y;
+    const uint32_t tz = rest / (uint32_t)A.tiles_y;
+    const int32_t nx = (int32_t)A.nx, ny = (int32_t)A.ny;
+    TB3Lane<T, TY> L;
+    L.nz = (int32_t)A.nz;
+    L.plane = (uint64_t)A.nx * (uint64_t)A.ny;
+    L.plane_bytes = (uint32_t)(L.plane * sizeof(R));
+    const int32_t x0 = (int32_t)(tx * (uint32_t)W) + (lane - H) * VEC;
+    const uint32_t xw = (uint32_t)wrap_row(x0, nx);
+    L.own_lane = lane >= H && lane < kWave - H && x0 < nx;
+    const int32_t y0 = (int32_t)tyi * TY;
+    L.yown = ny - y0 < TY ? ny - y0 : TY;
+#pragma unroll
+    for (int r = 0; r < NY; ++r)
+        L.lrow[r] = ((uint32_t)wrap_row(y0 - T + r, ny) * (uint32_t)nx + xw) * (uint32_t)sizeof(R);
+#pragma unroll
+    for (int r = 0; r < TY; ++r) L.srow[r] = (L.own_lane && r < L.yown) ? L.lrow[r + T] : kPastRow;
+    const int32_t rows = (int32_t)A.rows;
+    L.s0 = (int32_t)tz * rows;
+    L.s1 = L.s0 + rows < L.nz ? L.s0 + rows : L.nz;
+
+    TB3State<VEC, T, TY, R> S;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < NY; ++r)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.in[a][r][j] = R(0);
+#pragma unroll
+                for (int k = 0; k < T; ++k) S.lv[k][a][r][j] = R(0);
+            }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < NY; ++r)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.pin[a][r][j] = R(0);
+#pragma unroll
+                for (int k = 0; k < T; ++k) S.pl[k][a][r][j] = R(0);
+            }
+
+    // iteration 0 (z0 = s0 - T + 1) needs phi^n planes z0-1 .. z0+1 and phi_dot plane z0
+    const int32_t z0 = L.s0 - T + 1;
+    tb3_load<VEC, T, TY>(A.phi_in, wrap_row(z0 - 1, L.nz), L, L.plane_bytes, 0, NY, S.in[3]);
+    tb3_load<VEC, T, TY>(A.phi_in, wrap_row(z0, L.nz), L, L.plane_bytes, 0, NY, S.in[0]);
+    tb3_load<VEC, T, TY>(A.phi_in, wrap_row(z0 + 1, L.nz), L, L.plane_bytes, 0, NY, S.in[1]);
+    tb3_load<VEC, T, TY>(A.pi_in, wrap_row(z0, L.nz), L, L.plane_bytes, 1, NY - 1, S.pin[0]);
+    TBRows rw;
+    rw.phi = wrap_row(z0 + 2, L.nz);
+    rw.pi = wrap_row(z0 + 1, L.nz);
+
+    DiagAcc acc;
+    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
+    acc.walls = acc.nonfinite = 0u;
+    acc.area = acc.ek = 0.0;
+
+    const int32_t last = (L.s1 - L.s0) + 2 * T - 3;
+    int32_t i = 0;
+    bool more = true;
+#pragma unroll
+    for (int w = 0; w < WARM; ++w) {
+        if (more) more = tb3_group<VEC, T, TY, DIAG, UNIT, true>(A, L, i, last, rw, S, acc);
+        i += 4;
+    }
+    while (more) {
+        more = tb3_group<VEC, T, TY, DIAG, UNIT, false>(A, L, i, last, rw, S, acc);
+        i += 4;
+    }
+
+    if constexpr (DIAG) {
+        WavePartial w;
+        w.links[0] = wave_sum_u32(acc.links[0]);
+        w.links[1] = wave_sum_u32(acc.links[1]);
+        w.links[2] = wave_sum_u32(acc.links[2]);
+        w.walls = wave_sum_u32(acc.walls);
+        w.nonfinite = wave_sum_u32(acc.nonfinite);
+        w.pad = 0u;
+        w.area = wave_sum_f64(acc.area);
+        w.ek = wave_sum_f64(acc.ek);
+        if (lane == 0) A.partials[tile] = w;
+    }
+}
+
+template <int VEC, int T, int TY, bool DIAG, bool UNIT, typename R>
+__global__ __launch_bounds__(kBlock) void k_tb3d(TB3Args<T, R> A)
+{
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    tb3_tile<VEC, T, TY, DIAG, UNIT>(A, tile);
 }
 
 // ------------------------------------------------------ launch templates --
@@ -1292,6 +1562,74 @@ hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const void* ph
             return launch_tb_t<R, VEC, 8>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
         break;
     }
+    return hipErrorInvalidValue;
+}
+
+// Owned rows per wave of a 3D multi-step pass for the tiling's ty.
+__host__ __device__ __forceinline__ int tb3_rows(int ty)
+{
+    return ty == 4 ? 8 : 4;
+}
+
+template <typename R, int VEC, int T, int TY>
+hipError_t launch_tb3_t(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi_in,
+                        void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials, const DiagCoef& dc,
+                        hipStream_t s)
+{
+    TB3Args<T, R> A;
+    A.phi_in = static_cast<const R*>(phi_in);
+    A.phi_out = static_cast<R*>(phi_out);
+    A.pi_in = static_cast<const R*>(pi_in);
+    A.pi_out = static_cast<R*>(pi_out);
+    A.partials = partials;
+    A.nx = g.nx;
+    A.ny = g.Q;
+    A.nz = g.M;
+    const int64_t W = tb_owned_width_d(VEC, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.tiles_y = (g.Q + TY - 1) / TY;
+    A.ntiles = A.tiles_x * A.tiles_y * ((g.M + t.rows - 1) / t.rows);
+    A.rows = t.rows;
+    for (int i = 0; i < T; ++i) A.k[i] = coef_as<R>(k[i]);
+    A.dc = dc;
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (diag)
+        hipLaunchKernelGGL((k_tb3d<VEC, T, TY, true, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else if (A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1))
+        hipLaunchKernelGGL((k_tb3d<VEC, T, TY, false, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tb3d<VEC, T, TY, false, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+// 3D multi-step passes: float32 T = 2, 3 with (vec 1, 4 or 8 rows) or
+// (vec 2, 4 rows); float64 T = 2 with vec 1, 4 rows.
+template <typename R>
+constexpr bool tb3_combo_ok(int vec, int T, int TY)
+{
+    if (sizeof(R) == 8) return vec == 1 && T == 2 && TY == 4;
+    return (T == 2 || T == 3) && ((vec == 1 && (TY == 4 || TY == 8)) || (vec == 2 && TY == 4));
+}
+
+template <typename R>
+hipError_t launch_tb3d_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                         const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                         const DiagCoef& dc, hipStream_t s)
+{
+    const int TY = tb3_rows(t.ty);
+    if (!tb3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
+#define PRS_TB3(V, TT, YY)                                                                                   \
+    if (t.vec == V && T == TT && TY == YY) {                                                                  \
+        if constexpr (tb3_combo_ok<R>(V, TT, YY))                                                             \
+            return launch_tb3_t<R, V, TT, YY>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s); \
+    }
+    PRS_TB3(1, 2, 4)
+    PRS_TB3(1, 2, 8)
+    PRS_TB3(2, 2, 4)
+    PRS_TB3(1, 3, 4)
+    PRS_TB3(1, 3, 8)
+    PRS_TB3(2, 3, 4)
+#undef PRS_TB3
     return hipErrorInvalidValue;
 }
 

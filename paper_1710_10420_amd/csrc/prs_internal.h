@@ -72,20 +72,24 @@ hipError_t launch_step(const Geometry& g, const Tiling& t, const void* phi_in, v
                        void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
                        const DiagCoef& dc, hipStream_t s);
 
-// T steps n .. n+T-1 of a 2D lattice in one pass (temporal blocking)
-// with overlapped wave tiles; k holds the T step coefficients.  Reads phi_in
-// and pi_in, writes phi^{n+T} to phi_out and phi_dot^{n+T-1/2} to pi_out
-// (pi_out != pi_in).  With diag, the partials are those of the input state.
-hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                       const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
-                       const DiagCoef& dc, hipStream_t s);
+// T steps n .. n+T-1 in one pass (temporal blocking) with overlapped wave
+// tiles; k holds the T step coefficients.  Reads phi_in and pi_in, writes
+// phi^{n+T} to phi_out and phi_dot^{n+T-1/2} to pi_out (pi_out != pi_in).
+// With diag, the partials are those of the input state.
+hipError_t launch_tb(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                     const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                     const DiagCoef& dc, hipStream_t s);
 // Number of wave tiles (and partials) of a T-step pass.
 int64_t tb_tiles(const Geometry& g, const Tiling& t, int T);
 // Multi-step passes exist for 2D lattices whose rows are shorter than 2^28
-// sites (their loads and stores address a row with 32-bit byte offsets).
+// sites and for 3D lattices whose planes are shorter than 2^31 bytes (their
+// accesses use 32-bit byte offsets within a row or a plane).
 bool tb_supported(const Geometry& g);
-// Steps per multi-step pass with a kernel: 2, 3, 4, and 6, 8 in float32.
+// Steps per multi-step pass with a kernel for some tiling: 2D 2, 3, 4 and,
+// in float32, 6, 8; 3D 2 and, in float32, 3.
 bool tb_steps_supported(const Geometry& g, int T);
+// ... and for this tiling (3D: vec 1 or 2, and only some row counts).
+bool tb_pass_supported(const Geometry& g, const Tiling& t, int T);
 constexpr int kMaxPassSteps = 8;   // most leapfrog steps fused into one pass
 
 // Reduces `count` partials in a fixed order into one record at `rec`.
@@ -122,10 +126,10 @@ hipError_t launch_step_f32(const Geometry& g, const Tiling& t, const void* phi_i
 hipError_t launch_step_f64(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi,
                            void* pi_out, const StepCoef64& k, bool update, bool diag, WavePartial* partials,
                            const DiagCoef& dc, hipStream_t s);
-hipError_t launch_tb2d_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+hipError_t launch_tb_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
                            const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
                            const DiagCoef& dc, hipStream_t s);
-hipError_t launch_tb2d_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+hipError_t launch_tb_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
                            const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
                            const DiagCoef& dc, hipStream_t s);
 hipError_t launch_adjoint_f32(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,

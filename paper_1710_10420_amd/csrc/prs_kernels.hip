@@ -382,10 +382,11 @@ hipError_t launch_step_f32(const Geometry& g, const Tiling& t, const void* phi_i
     return launch_step_r<float>(g, t, phi_in, phi_out, pi, pi_out, k, update, diag, partials, dc, s);
 }
 
-hipError_t launch_tb2d_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                           const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
-                           const DiagCoef& dc, hipStream_t s)
+hipError_t launch_tb_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                         const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                         const DiagCoef& dc, hipStream_t s)
 {
+    if (g.ndim == 3) return launch_tb3d_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     return launch_tb2d_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
 }
 
@@ -417,13 +418,13 @@ hipError_t launch_step(const Geometry& g, const Tiling& t, const void* phi_in, v
                  : launch_step_f32(g, t, phi_in, phi_out, pi, pi_out, k, update, diag, partials, dc, s);
 }
 
-hipError_t launch_tb2d(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                       const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
-                       const DiagCoef& dc, hipStream_t s)
+hipError_t launch_tb(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                     const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                     const DiagCoef& dc, hipStream_t s)
 {
-    if (!tb_steps_supported(g, T) || !tiling_supported(g, t) || t.ty != 1) return hipErrorInvalidValue;
-    return g.f64 ? launch_tb2d_f64(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s)
-                 : launch_tb2d_f32(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    if (!tb_pass_supported(g, t, T)) return hipErrorInvalidValue;
+    return g.f64 ? launch_tb_f64(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s)
+                 : launch_tb_f32(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
 }
 
 hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
@@ -597,19 +598,33 @@ int64_t tb_owned_width(int vec, int T)
 
 bool tb_supported(const Geometry& g)
 {
-    return g.ndim == 2 && g.nx <= ((int64_t)1 << 28);
+    if (g.ndim == 2) return g.nx <= ((int64_t)1 << 28);
+    return g.nx * g.Q * (g.f64 ? 8 : 4) < ((int64_t)1 << 31);
 }
 
 bool tb_steps_supported(const Geometry& g, int T)
 {
     if (!tb_supported(g)) return false;
+    if (g.ndim == 3) return T == 2 || (!g.f64 && T == 3);
     return T == 2 || T == 3 || T == 4 || (!g.f64 && (T == 6 || T == 8));
+}
+
+bool tb_pass_supported(const Geometry& g, const Tiling& t, int T)
+{
+    if (!tb_steps_supported(g, T) || !tiling_supported(g, t)) return false;
+    if (g.ndim == 2) return t.ty == 1;
+    return g.f64 ? tb3_combo_ok<double>(t.vec, T, tb3_rows(t.ty)) : tb3_combo_ok<float>(t.vec, T, tb3_rows(t.ty));
 }
 
 int64_t tb_tiles(const Geometry& g, const Tiling& t, int T)
 {
     const int64_t W = tb_owned_width(t.vec, T);
-    return ((g.nx + W - 1) / W) * ((g.M + t.rows - 1) / t.rows);
+    const int64_t planes = (g.M + t.rows - 1) / t.rows;
+    if (g.ndim == 3) {
+        const int64_t TY = tb3_rows(t.ty);
+        return ((g.nx + W - 1) / W) * ((g.Q + TY - 1) / TY) * planes;
+    }
+    return ((g.nx + W - 1) / W) * planes;
 }
 
 }  // namespace prs

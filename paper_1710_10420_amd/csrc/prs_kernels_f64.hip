@@ -15,10 +15,11 @@ hipError_t launch_step_f64(const Geometry& g, const Tiling& t, const void* phi_i
     return launch_step_r<double>(g, t, phi_in, phi_out, pi, pi_out, k, update, diag, partials, dc, s);
 }
 
-hipError_t launch_tb2d_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                           const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
-                           const DiagCoef& dc, hipStream_t s)
+hipError_t launch_tb_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                         const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                         const DiagCoef& dc, hipStream_t s)
 {
+    if (g.ndim == 3) return launch_tb3d_r<double>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     return launch_tb2d_r<double>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
 }
 

@@ -339,27 +339,30 @@ def test_full_size_3d_1024_sampled():
     torch.cuda.empty_cache()
 
 
-# ---------------------------------------------- multi-step passes (2D) ----
+# --------------------------------------------------- multi-step passes ----
 
 @pytest.mark.parametrize("shape,K,steps", [
     ((300, 70), 5, 23), ((1, 7), 2, 9), ((7, 1), 3, 10), ((2, 2), 64, 11), ((66, 129), 1, 6),
     ((1030, 9), 64, 67), ((256, 256), 10, 50), ((512, 300), 8, 37), ((248, 40), 12, 31),
+    ((40, 30, 20), 5, 17), ((64, 9, 33), 8, 23), ((130, 6, 4), 3, 10), ((2, 3, 5), 64, 9),
+    ((1, 1, 1), 2, 7), ((62, 17, 12), 1, 6),
 ])
 def test_multi_step_passes_bitwise_equal_single_steps(shape, K, steps):
-    """Temporal blocking (2, 3, 4, 6 or 8 steps per pass) changes only how
-    often HBM is visited: fields and records are bitwise those of single
-    steps, for every tiling, ragged sizes, record cadences and odd step
-    counts."""
+    """Temporal blocking (2D: 2, 3, 4, 6 or 8 steps per pass; 3D: 2 or 3)
+    changes only how often HBM is visited: fields and records are bitwise
+    those of single steps, for every tiling, ragged sizes, record cadences
+    and odd step counts."""
     say("multi-step", shape, K, steps)
     prs = gpu_prs()
-    gp, _ = params_pair(shape, 0.25, m=2.0, W0=6.0, diag_every=K)
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp, _ = params_pair(shape, deta, m=2.0, W0=6.0, diag_every=K)
     phi0 = uniform_field(shape, 31)
     ref = prs.Sim(gp, phi0=to_dev(phi0))
     ref.set_time_blocking(1)
     r_ref = ref.step_n(steps)
     rp, rd = (host(t) for t in ref.state())
     base = tilings_for(shape)
-    for T in (2, 3, 4, 6, 8):
+    for T in ((2, 3, 4, 6, 8) if len(shape) == 2 else (2, 3)):
         for t in base + [(base[0][0], 8, 1)]:
             sim = prs.Sim(gp, phi0=to_dev(phi0))
             sim.set_time_blocking(T)
@@ -393,6 +396,43 @@ def test_multi_step_default_and_limits():
     gp3, _ = params_pair((16, 16, 16), 0.2)
     sim3 = prs.Sim(gp3, seed=1)
     assert sim3.time_blocking() == 1
+    sim3.set_time_blocking(3)
+    for bad in (4, 6, 8):
+        with pytest.raises(prs.PRSError) as e:
+            sim3.set_time_blocking(bad)
+        assert e.value.status == prs.PRS_EINVAL
+    gp364 = prs.make_params((16, 16, 16), deta=0.2, precision=prs.PRS_F64)
+    sim364 = prs.Sim(gp364, seed=1)
+    sim364.set_time_blocking(2)
     with pytest.raises(prs.PRSError) as e:
-        sim3.set_time_blocking(2)
-    assert e.value.status == prs.PRS_EUNSUPPORTED
+        sim364.set_time_blocking(3)
+    assert e.value.status == prs.PRS_EINVAL
+
+
+@pytest.mark.parametrize("shape,T,tiling", [((8192, 8192), 8, (2, 64, 1)), ((1024, 1024, 1024), 3, (1, 16, 4)),
+                                            ((1024, 1024, 1024), 2, (2, 32, 1))])
+def test_full_size_multi_step_bitwise(shape, T, tiling):
+    """At the full lattice sizes the multi-step passes reproduce single steps
+    bit for bit (fields compared on the device) and their fused record
+    equals the single-step record up to summation order."""
+    say("full-size multi-step", shape, T, tiling)
+    torch = torch_mod()
+    prs = gpu_prs()
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp, _ = params_pair(shape, deta, m=1.0, W0=10.0, diag_every=6)
+    steps = 2 * T
+    ref = prs.Sim(gp, seed=1)
+    ref.set_tiling(*tiling)
+    ref.set_time_blocking(1)
+    r_ref = ref.step_n(steps)
+    sim = prs.Sim(gp, seed=1)
+    sim.set_tiling(*tiling)
+    sim.set_time_blocking(T)
+    assert prs.prs_plan_passes(sim.ctx, steps)[0] >= 1
+    r = sim.step_n(steps)
+    for a, b in zip(sim.state(), ref.state()):
+        assert torch.equal(a, b)
+    for a, b in zip(r, r_ref):
+        assert_stats_match(a, b, rel=1e-12, ctx="full-size multi-step")
+    del ref, sim
+    torch.cuda.empty_cache()
