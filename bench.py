@@ -205,6 +205,22 @@ def batch_leg(prs, torch, reps=2):
     return out
 
 
+def table1_leg(prs):
+    """Table I of the paper in kind: five seeds of 2048^2 and 128^3 in single
+    and double precision, exponents fitted for ln(eta) > 2.58 (mean and
+    one-sigma error over the five runs)."""
+    from paper_1710_10420_amd import validation
+    t0 = time.perf_counter()
+    table = validation.scaling_table(prs)
+    out = {"workload": "5 seeds x {2048^2, 128^3} x {single, double}, m=1, W0=10, to eta = N/2, "
+                       "fit for ln(eta) > 2.58",
+           "seconds": time.perf_counter() - t0}
+    for name, row in table.items():
+        out[name] = {label: {"mu": r["mu"], "nu": r["nu"]} for label, r in row.items()}
+    log("table1 %.1f s" % out["seconds"])
+    return out
+
+
 F64_STEPS = 2048
 
 
@@ -344,6 +360,7 @@ def main():
         out["adjoint"] = adjoint_leg(prs, torch)
         out["batch"] = batch_leg(prs, torch)
         out["f64"] = f64_leg(prs, torch, w)
+        out["table1"] = table1_leg(prs)
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -138,14 +138,18 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // multi-step pass has a length with a kernel (the longest that fits), and
 // the number of multi-step passes is even (each flips the phi_dot buffer, so
 // phi_dot ends where it started).
-std::vector<uint8_t> plan_passes(const Geometry& g, const Tiling& t, int64_t n0, int64_t nsteps, int T, int64_t K)
+std::vector<uint8_t> plan_passes(const Geometry& g, const Tiling& t, int64_t cap, int64_t n0, int64_t nsteps, int T,
+                                 int64_t K)
 {
+    // a length needs a kernel for the tiling and at most `cap` wave tiles
+    // (the partial buffers hold that many)
+    auto ok = [&](int L) { return tb_pass_supported(g, t, L) && tb_tiles(g, t, L) <= cap; };
     std::vector<uint8_t> plan;
     int64_t nmulti = 0;
     for (int64_t n = n0; n < n0 + nsteps;) {
         int64_t L = std::min<int64_t>(T, n0 + nsteps - n);
         if (K > 0) L = std::min<int64_t>(L, (n / K + 1) * K - n);
-        while (L > 1 && !tb_pass_supported(g, t, (int)L)) --L;
+        while (L > 1 && !ok((int)L)) --L;
         plan.push_back((uint8_t)L);
         nmulti += L > 1 ? 1 : 0;
         n += L;
@@ -159,7 +163,7 @@ std::vector<uint8_t> plan_passes(const Geometry& g, const Tiling& t, int64_t n0,
                 const int L = plan[i];
                 const int a = L / 2, b = L - a;
                 plan.erase(plan.begin() + (std::ptrdiff_t)i);
-                if (a > 1 && tb_pass_supported(g, t, a) && tb_pass_supported(g, t, b)) {
+                if (a > 1 && ok(a) && ok(b)) {
                     plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)b);
                     plan.insert(plan.begin() + (std::ptrdiff_t)i, (uint8_t)a);
                 } else {
@@ -334,7 +338,7 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int64_t end = c->step + nsteps;
 
     const int T = tb_supported(c->geo) ? c->tblock : 1;
-    const std::vector<uint8_t> plan = plan_passes(c->geo, c->til, c->step, nsteps, T, want ? K : 0);
+    const std::vector<uint8_t> plan = plan_passes(c->geo, c->til, c->partial_cap, c->step, nsteps, T, want ? K : 0);
 
     void* pi_cur = c->pi;
     void* pi_oth = c->pi_alt;
@@ -399,7 +403,7 @@ prs_status prs_plan_passes(const prs_ctx* c, int64_t nsteps, int32_t with_record
     const int T = tb_supported(c->geo) ? c->tblock : 1;
     const int64_t K = (with_records && c->p.diag_every > 0) ? c->p.diag_every : 0;
     int64_t m = 0, n1 = 0;
-    for (uint8_t L : plan_passes(c->geo, c->til, c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
+    for (uint8_t L : plan_passes(c->geo, c->til, c->partial_cap, c->step, nsteps, T, K)) (L > 1 ? m : n1) += 1;
     if (multi_passes) *multi_passes = m;
     if (single_passes) *single_passes = n1;
     return PRS_OK;
@@ -560,12 +564,13 @@ namespace {
 
 // Workspace of the checkpointed adjoint (all offsets 256-byte aligned):
 //   nseg checkpoints of (phi, phi_dot), the K-1 recomputed fields phi^{n_s+1..}
-//   of one segment, a phi_dot scratch for recomputation, mu, w (x2), the
-//   per-wave dL/dV0 accumulators, the loss partials and two FP64 scalars.
+//   of one segment, two phi_dot scratch fields for the recomputation, mu (x2),
+//   w (x2), the per-wave dL/dV0 accumulators, the loss partials and two FP64
+//   scalars.
 struct AdjLayout {
     size_t fb;
     int64_t nseg, K;
-    size_t ck_phi, ck_pi, seg, pis, mu, w0, w1, gacc, lpart, scal, total;
+    size_t ck_phi, ck_pi, seg, pis, pis2, mu, mu2, w0, w1, gacc, lpart, scal, total;
 };
 
 constexpr int kSeedBlocks = 1024;
@@ -581,7 +586,9 @@ AdjLayout adj_layout(const prs_params& p, int64_t nsteps, int64_t K, int64_t par
     L.ck_pi = o; o += L.fb * (size_t)L.nseg;
     L.seg = o; o += L.fb * (size_t)(K > 1 ? K - 1 : 0);
     L.pis = o; o += L.fb;
+    L.pis2 = o; o += L.fb;
     L.mu = o; o += L.fb;
+    L.mu2 = o; o += L.fb;
     L.w0 = o; o += L.fb;
     L.w1 = o; o += L.fb;
     L.gacc = o; o += align_up((size_t)partial_cap * sizeof(double));
@@ -647,34 +654,50 @@ prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, v
     const size_t bytes = field_bytes(c->p);
     const int64_t n0 = c->step;
     // Checkpoint 0 is a copy of the starting state.  Checkpoint s >= 1 is
-    // written directly by the step that produces it, and the next step reads
-    // it from there (phi_dot out of place), so no further copies are made.
+    // written directly by the pass that ends on it, and the next pass reads
+    // it from there, so no further copies are made.  Passes take the run's
+    // steps per pass and never cross a checkpoint.
     HIP_TRY(hipMemcpyAsync(at<char>(work, L.ck_phi), c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream),
             "checkpoint copy");
     HIP_TRY(hipMemcpyAsync(at<char>(work, L.ck_pi), c->pi, bytes, hipMemcpyDeviceToDevice, c->stream),
             "checkpoint copy");
+    const int T = tb_supported(c->geo) ? c->tblock : 1;
     const void* phi_in = c->phi[c->cur];
     const void* pi_in = c->pi;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t k = 0;
+    for (uint8_t Lp : plan_passes(c->geo, c->til, c->partial_cap, 0, nsteps, T, L.K)) {
         const int64_t n = n0 + k;
+        const bool ck = (k + Lp) % L.K == 0 && k + Lp < nsteps;   // ends on checkpoint (k+Lp)/K
         void* phi_out;
         void* pi_out;
-        if ((k + 1) % L.K == 0 && k + 1 < nsteps) {           // produces checkpoint (k+1)/K
-            const int64_t sg = (k + 1) / L.K;
+        if (ck) {
+            const int64_t sg = (k + Lp) / L.K;
             phi_out = at<char>(work, L.ck_phi + L.fb * sg);
             pi_out = at<char>(work, L.ck_pi + L.fb * sg);
         } else {
             phi_out = c->phi[c->cur ^ 1];
-            pi_out = c->pi;
+            if (Lp > 1) pi_out = pi_in == c->pi ? c->pi_alt : c->pi;
+            else pi_out = (pi_in == c->pi || pi_in == c->pi_alt) ? const_cast<void*>(pi_in) : c->pi;
         }
-        HIP_TRY(launch_step(c->geo, c->til, phi_in, phi_out, pi_in, pi_out, coef_for(c, n), true, false, nullptr,
-                            DiagCoef{}, c->stream),
-                "step kernel launch");
+        if (Lp > 1) {
+            StepCoef64 kk[kMaxPassSteps];
+            for (int i = 0; i < Lp; ++i) kk[i] = coef_for(c, n + i);
+            HIP_TRY(launch_tb(Lp, c->geo, c->til, phi_in, phi_out, pi_in, pi_out, kk, false, nullptr, DiagCoef{},
+                              c->stream),
+                    "multi-step kernel launch");
+        } else {
+            HIP_TRY(launch_step(c->geo, c->til, phi_in, phi_out, pi_in, pi_out, coef_for(c, n), true, false,
+                                nullptr, DiagCoef{}, c->stream),
+                    "step kernel launch");
+        }
         if (phi_out == c->phi[c->cur ^ 1]) c->cur ^= 1;
         phi_in = phi_out;
         pi_in = pi_out;
-        c->step += 1;
+        k += Lp;
+        c->step += Lp;
     }
+    if (pi_in != c->pi)
+        HIP_TRY(hipMemcpyAsync(c->pi, pi_in, bytes, hipMemcpyDeviceToDevice, c->stream), "phi_dot copy");
     const double kc = 1.0 / (c->p.phi0 * c->p.phi0);
     HIP_TRY(launch_adj_seed(c->geo, c->phi[c->cur], sites_of(c->p), kc, c->p.deta, at<char>(work, L.mu),
                             at<char>(work, L.w0), at<double>(work, L.lpart), kSeedBlocks, c->stream),
@@ -694,8 +717,21 @@ prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, v
     return PRS_OK;
 }
 
-prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void* grad_phi0,
-                                void* grad_dphi0, double* grad_W0)
+namespace {
+
+// Longest pass of at most min(T, left) steps that the adjoint's multi-step
+// kernels support with tiling t and at most `cap` wave tiles (1: single steps).
+int adj_pass_len(const Geometry& g, const Tiling& t, int64_t cap, int T, int64_t left)
+{
+    int L = (int)std::min<int64_t>(T, left);
+    while (L > 1 && !(tba_supported(g, t, L) && tb_tiles(g, t, L) <= cap)) --L;
+    return std::max(L, 1);
+}
+
+}  // namespace
+
+prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void* grad_phi0, void* grad_dphi0,
+                                double* grad_W0)
 {
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");
     if (!c->adj_ready || work != c->adj_work || work_bytes != c->adj_bytes)
@@ -705,43 +741,76 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     const AdjLayout L = adj_layout(c->p, c->adj_nsteps, c->adj_K, c->partial_cap);
     const int64_t n0 = c->adj_n0;
     const size_t bytes = field_bytes(c->p);
-    const TileCounts tc = tile_counts(c->geo, c->adj_til);
+    const int T = tb_supported(c->geo) ? c->tblock : 1;
     double* gacc = at<double>(work, L.gacc);
-    HIP_TRY(launch_zero_f64(gacc, tc.ntiles, c->stream), "zero launch");
+    HIP_TRY(launch_zero_f64(gacc, c->partial_cap, c->stream), "zero launch");
     char* mu = at<char>(work, L.mu);
+    char* mu_oth = at<char>(work, L.mu2);
     char* wcur = at<char>(work, L.w0);
     char* wnxt = at<char>(work, L.w1);
     char* pis = at<char>(work, L.pis);
+    char* pis2 = at<char>(work, L.pis2);
     auto seg = [&](int64_t k) { return at<char>(work, L.seg + L.fb * (size_t)(k - 1)); };
     for (int64_t sg = L.nseg - 1; sg >= 0; --sg) {
         const int64_t ns = n0 + sg * L.K;
         const int64_t len = std::min<int64_t>(L.K, c->adj_nsteps - sg * L.K);
         char* ckphi = at<char>(work, L.ck_phi + L.fb * sg);
-        // recompute phi^{ns+1 .. ns+len-1} from the checkpoint (the first
-        // step reads the checkpointed phi_dot and writes the scratch copy)
-        const char* prev = ckphi;
-        const char* pprev = at<char>(work, L.ck_pi + L.fb * sg);
-        for (int64_t k = 1; k < len; ++k) {
-            HIP_TRY(launch_step(c->geo, c->til, prev, seg(k), pprev, pis, coef_for(c, ns + k - 1), true, false,
-                                nullptr, DiagCoef{}, c->stream),
-                    "recompute launch");
+        char* ckpi = at<char>(work, L.ck_pi + L.fb * sg);
+        auto phi_at = [&](int64_t j) -> const void* { return j == 0 ? ckphi : seg(j); };   // phi^{ns+j}
+        // recompute phi^{ns+1 .. ns+len-1} from the checkpoint: multi-step
+        // passes store every step's field; phi_dot goes to the scratch fields
+        const void* prev = ckphi;
+        const void* pprev = ckpi;
+        for (int64_t k = 0; k < len - 1;) {
+            const int Lp = adj_pass_len(c->geo, c->til, c->partial_cap, T, len - 1 - k);
+            if (Lp > 1) {
+                void* outs[kMaxPassSteps];
+                StepCoef64 kk[kMaxPassSteps];
+                for (int i = 0; i < Lp; ++i) {
+                    outs[i] = seg(k + 1 + i);
+                    kk[i] = coef_for(c, ns + k + i);
+                }
+                void* pout = pprev == pis ? pis2 : pis;
+                HIP_TRY(launch_tb_all(Lp, c->geo, c->til, prev, outs, pprev, pout, kk, c->stream),
+                        "recompute launch");
+                pprev = pout;
+            } else {
+                void* pout = pprev == ckpi ? pis : const_cast<void*>(pprev);
+                HIP_TRY(launch_step(c->geo, c->til, prev, seg(k + 1), pprev, pout, coef_for(c, ns + k), true, false,
+                                    nullptr, DiagCoef{}, c->stream),
+                        "recompute launch");
+                pprev = pout;
+            }
+            k += Lp;
             prev = seg(k);
-            pprev = pis;
         }
-        for (int64_t k = len - 1; k >= 0; --k) {
-            const int64_t n = ns + k;
-            const char* phin = k == 0 ? ckphi : seg(k);
-            HIP_TRY(launch_adjoint(c->geo, c->adj_til, wcur, wnxt, mu, phin, gacc, adj_coef(c, n, n == n0),
-                                   c->stream),
-                    "adjoint launch");
+        // reverse sweep over steps ns+len-1 .. ns
+        for (int64_t k = len - 1; k >= 0;) {
+            const int Lp = adj_pass_len(c->geo, c->til, c->partial_cap, T, k + 1);
+            if (Lp > 1) {
+                const void* phis[kMaxPassSteps];
+                AdjCoef64 cc[kMaxPassSteps];
+                for (int i = 0; i < Lp; ++i) {
+                    phis[i] = phi_at(k - i);
+                    cc[i] = adj_coef(c, ns + k - i, ns + k - i == n0);
+                }
+                HIP_TRY(launch_tba(Lp, c->geo, c->til, wcur, wnxt, mu, mu_oth, phis, gacc, cc, c->stream),
+                        "adjoint launch");
+                std::swap(mu, mu_oth);
+            } else {
+                HIP_TRY(launch_adjoint(c->geo, c->adj_til, wcur, wnxt, mu, phi_at(k), gacc,
+                                       adj_coef(c, ns + k, ns + k == n0), c->stream),
+                        "adjoint launch");
+            }
             std::swap(wcur, wnxt);
+            k -= Lp;
         }
     }
     if (grad_phi0)
         HIP_TRY(hipMemcpyAsync(grad_phi0, mu, bytes, hipMemcpyDeviceToDevice, c->stream), "gradient copy");
     if (grad_dphi0)
         HIP_TRY(hipMemcpyAsync(grad_dphi0, wcur, bytes, hipMemcpyDeviceToDevice, c->stream), "gradient copy");
-    HIP_TRY(launch_sum_f64(gacc, tc.ntiles, at<double>(work, L.scal) + 1, c->stream), "G reduce launch");
+    HIP_TRY(launch_sum_f64(gacc, c->partial_cap, at<double>(work, L.scal) + 1, c->stream), "G reduce launch");
     HIP_TRY(hipMemcpyAsync(c->adj_host + 1, at<double>(work, L.scal) + 1, sizeof(double),
                            hipMemcpyDeviceToHost, c->stream), "G copy");
     HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
@@ -868,13 +937,13 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
 // per pass, no recorded state inside a pass, an even number of multi-step
 // passes so phi_dot ends in the caller's buffer), then the diagnostics-only
 // pass of the final state.
-std::vector<PassEntry> batch_plan(const prs_batch_item& it, const Geometry& g, const Tiling& t, int T)
+std::vector<PassEntry> batch_plan(const prs_batch_item& it, const Geometry& g, const Tiling& t, int64_t cap, int T)
 {
     const int64_t S = it.nsteps, K = it.p.diag_every;
     std::vector<PassEntry> out;
     int64_t n = 0, rec = 0;
     int alt = 0;
-    for (uint8_t L : plan_passes(g, t, 0, S, T, K)) {
+    for (uint8_t L : plan_passes(g, t, cap, 0, S, T, K)) {
         const bool r = K > 0 && n % K == 0;
         out.push_back(PassEntry{(int32_t)n, (int32_t)L, r ? (int32_t)rec++ : -1, alt});
         if (L > 1) alt ^= 1;
@@ -941,7 +1010,7 @@ prs_status batch_item_begin(prs_batch* b, int32_t r, ItemCursor& cur, hipStream_
 {
     const prs_batch_item& it = b->items[r];
     cur.item = r;
-    cur.plan = batch_plan(it, b->geo[r], b->til[r], b->tblock[r]);
+    cur.plan = batch_plan(it, b->geo[r], b->til[r], b->part_cap[r], b->tblock[r]);
     cur.next = 0;
     cur.coef = prs_ctx{};
     cur.coef.p = it.p;
@@ -1079,7 +1148,7 @@ prs_status batch_upload(prs_batch* b)
         float2* dcoef = reinterpret_cast<float2*>(base + b->off_coef + b->coef_off[r]);
         HIP_TRY(hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice),
                 "coefficient upload");
-        const std::vector<PassEntry> plan = batch_plan(it, b->geo[r], b->til[r], b->tblock[r]);
+        const std::vector<PassEntry> plan = batch_plan(it, b->geo[r], b->til[r], b->part_cap[r], b->tblock[r]);
         void* dpass = base + b->off_pass + b->pass_off[r];
         HIP_TRY(hipMemcpy(dpass, plan.data(), plan.size() * sizeof(PassEntry), hipMemcpyHostToDevice),
                 "pass table upload");
@@ -1265,7 +1334,7 @@ prs_status prs_batch_state(const prs_batch* b, int32_t item, void** phi, void** 
 {
     if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
     const prs_batch_item& it = b->items[item];
-    const std::vector<PassEntry> plan = batch_plan(it, b->geo[item], b->til[item], b->tblock[item]);
+    const std::vector<PassEntry> plan = batch_plan(it, b->geo[item], b->til[item], b->part_cap[item], b->tblock[item]);
     const int64_t np = (int64_t)plan.size();
     if (phi) *phi = ((np - 1) & 1) ? it.phi_b : it.phi_a;
     if (dphi) *dphi = it.dphi;

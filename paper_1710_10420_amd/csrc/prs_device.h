@@ -742,6 +742,7 @@ struct TBArgs {
     R* phi_out;
     const R* pi_in;
     R* pi_out;
+    R* phi_lv[T];               // with ALL: phi^{n+k} of levels k = 1 .. T-1 (level T is phi_out)
     WavePartial* partials;
     int64_t nx, ny;
     int64_t tiles_x, ntiles;
@@ -888,7 +889,7 @@ __device__ __forceinline__ void tb_store(R* f, int32_t row, const TBLane& L, uin
 // iteration is i = last for every level.  CHECK skips the levels that have no
 // row yet (the first 2T-2 iterations); without it those levels run on rows
 // that only ever feed rows outside the tile, which are never stored.
-template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, int U, typename R>
+template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, int U, bool ALL, typename R>
 __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
                                         TBRows& rw, TBState<VEC, T, R>& S, DiagAcc& acc)
 {
@@ -943,6 +944,13 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
                 S.lv[k < T ? k : 0][U & 3][j] = out_phi[j];
                 S.pl[k < T ? k : 0][U & 1][j] = out_pi[j];
             }
+            if constexpr (ALL) {
+                // level k row s0 + i - (T + k - 2), stored when inside [s0, s1)
+                const int32_t e = i - (T + k - 2);
+                const bool in = e >= 0 && e < L.s1 - L.s0;
+                tb_store<VEC>(A.phi_lv[k < T ? k - 1 : 0], in ? L.s0 + e : L.s0, L, in ? L.row_bytes : 0u,
+                              out_phi);
+            }
         } else {
             // level T row s0 + i - (2T - 2), inside [s0, s1) once i >= 2T - 2
             const int32_t row = L.s0 + i - (2 * T - 2);
@@ -955,23 +963,24 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
 
 // Iterations i .. i+3 (i a multiple of 4, so ring slots are compile-time);
 // false once the last iteration has run.
-template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, typename R>
+template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, bool ALL, typename R>
 __device__ __forceinline__ bool tb_group(const TBArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
                                          TBRows& rw, TBState<VEC, T, R>& S, DiagAcc& acc)
 {
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 0>(A, L, i, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 0, ALL>(A, L, i, last, rw, S, acc);
     if (i + 1 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 1>(A, L, i + 1, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 1, ALL>(A, L, i + 1, last, rw, S, acc);
     if (i + 2 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 2>(A, L, i + 2, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 2, ALL>(A, L, i + 2, last, rw, S, acc);
     if (i + 3 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 3>(A, L, i + 3, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 3, ALL>(A, L, i + 3, last, rw, S, acc);
     return i + 4 <= last;
 }
 
 // One wave's tile of a T-step pass; `tile` must be below A.ntiles and
-// wave-uniform.
-template <int VEC, int T, bool DIAG, bool UNIT = false, typename R = float>
+// wave-uniform.  ALL also stores the fields of the intermediate steps
+// (phi_lv), as the recomputation of the adjoint needs them.
+template <int VEC, int T, bool DIAG, bool UNIT = false, bool ALL = false, typename R = float>
 __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
 {
     constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
@@ -1032,11 +1041,11 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
     bool more = true;
 #pragma unroll
     for (int w = 0; w < WARM; ++w) {
-        if (more) more = tb_group<VEC, T, DIAG, UNIT, true>(A, L, i, last, rw, S, acc);
+        if (more) more = tb_group<VEC, T, DIAG, UNIT, true, ALL>(A, L, i, last, rw, S, acc);
         i += 4;
     }
     while (more) {
-        more = tb_group<VEC, T, DIAG, UNIT, false>(A, L, i, last, rw, S, acc);
+        more = tb_group<VEC, T, DIAG, UNIT, false, ALL>(A, L, i, last, rw, S, acc);
         i += 4;
     }
 
@@ -1060,6 +1069,221 @@ __global__ __launch_bounds__(kBlock) void k_tb2d(TBArgs<T, R> A)
     const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     if (tile >= A.ntiles) return;
     tb_tile<VEC, T, DIAG, UNIT>(A, tile);
+}
+
+// The T-step pass storing every step's field (adjoint recomputation).
+template <int VEC, int T, bool UNIT, typename R>
+__global__ __launch_bounds__(kBlock) void k_tb2d_all(TBArgs<T, R> A)
+{
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    tb_tile<VEC, T, false, UNIT, true>(A, tile);
+}
+
+// ------------------------------- reverse sweep, T steps per pass (2D) ------
+//
+// T reverse steps m, m-1, ..., m-T+1 of the adjoint (Eqs. 3-6 differentiated,
+// as in k_adjoint) in one pass, with the overlapped tiles and the pipelined
+// y-march of the forward passes: level k is reverse step m-k+1, w is the
+// stencil field and mu the pointwise one, and level k also reads phi^{m-k+1}
+// (its own field).  w and mu are read from w_in, mu_in and written after the
+// last level to w_out, mu_out, which must be other buffers (neighbouring
+// tiles read the rows this tile overlaps).  Each level's dL/dV0 sum is kept
+// apart and added with its own coefficient.  Per site every level evaluates
+// exactly the arithmetic of k_adjoint, so w and mu are bitwise those of
+// single reverse steps; dL/dV0 differs in summation order only.
+
+template <int T, typename R = float>
+struct TBAArgs {
+    const R* w_in;
+    R* w_out;
+    const R* mu_in;
+    R* mu_out;
+    const R* phi[T];            // phi^{m-k+1} for level k = 1 .. T
+    double* gacc;               // one accumulator per wave tile of this pass shape
+    int64_t nx, ny;
+    int64_t tiles_x, ntiles;
+    int64_t rows;
+    R a[T], b[T], cw[T];
+    R F, kc, inv_dx2;
+    double gscale[T];
+};
+
+template <int VEC, int T, typename R>
+struct TBAState {
+    R in[4][VEC];               // w rows, ring over the march
+    R mi[2][VEC];               // mu rows
+    R lv[T][4][VEC];            // level k w rows (k = 1 .. T-1)
+    R ml[T][2][VEC];            // level k mu rows
+    R ph[T][2][VEC];            // phi row of each level, one iteration ahead
+};
+
+template <int VEC, int T, bool UNIT, bool CHECK, int U, typename R>
+__device__ __forceinline__ void tba_iter(const TBAArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
+                                         TBRows& rw, int32_t (&prow)[T], TBAState<VEC, T, R>& S,
+                                         double (&gs)[T])
+{
+    // prefetch for the next iteration: w row y+2, mu row y+1 and, for every
+    // level k, the phi row it computes next
+    const uint32_t nb = i < last ? L.row_bytes : 0u;
+    tb_load<VEC>(A.w_in, rw.phi, L, nb, S.in[(U + 2) & 3]);
+    tb_load<VEC>(A.mu_in, rw.pi, L, nb, S.mi[(U + 1) & 1]);
+    rw.phi = next_row(rw.phi, L.ny);
+    rw.pi = next_row(rw.pi, L.ny);
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        tb_load<VEC>(A.phi[k], prow[k], L, nb, S.ph[k][(U + 1) & 1]);
+        prow[k] = next_row(prow[k], L.ny);
+    }
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        if (CHECK && i < 2 * (k - 1)) continue;
+        const R* cm;
+        const R* cc;
+        const R* cp;
+        const R* mp;
+        if (k == 1) {
+            cm = S.in[(U + 3) & 3];
+            cc = S.in[U & 3];
+            cp = S.in[(U + 1) & 3];
+            mp = S.mi[U & 1];
+        } else {
+            cm = S.lv[k - 1][(U + 2) & 3];
+            cc = S.lv[k - 1][(U + 3) & 3];
+            cp = S.lv[k - 1][U & 3];
+            mp = S.ml[k - 1][(U + 1) & 1];
+        }
+        const R* ph = S.ph[k - 1][U & 1];
+        // level k row s0 + i - (T + k - 2) counts for dL/dV0 when inside [s0, s1)
+        const int32_t e = i - (T + k - 2);
+        const bool own_row = e >= 0 && e < L.s1 - L.s0;
+        const R left = from_left_lane(cc[VEC - 1]);
+        const R right = from_right_lane(cc[0]);
+        R out_w[VEC], out_mu[VEC];
+        double g = 0.0;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const R w = cc[j];
+            const R xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
+            const R xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
+            const R lap = lap2<UNIT>(w, xm, xp, cm[j], cp[j], A.inv_dx2);
+            const R p = ph[j];
+            const R phk = UNIT ? p : p * A.kc;
+            const R q = fmar(phk, p, R(-1));
+            const R v2 = A.F * fmar(R(3) * phk, p, R(-1));   // V''(phi)
+            const R mu_new = fmar(A.b[k - 1], lap - v2 * w, mp[j]);
+            out_mu[j] = mu_new;
+            out_w[j] = fmar(A.cw[k - 1], mu_new, A.a[k - 1] * w);
+            g += (double)(w * (p * q));
+        }
+        if (own_row && L.soff != kPastRow) gs[k - 1] += g;
+        if (k < T) {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.lv[k < T ? k : 0][U & 3][j] = out_w[j];
+                S.ml[k < T ? k : 0][U & 1][j] = out_mu[j];
+            }
+        } else {
+            const int32_t row = L.s0 + i - (2 * T - 2);
+            const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.row_bytes : 0u;
+            tb_store<VEC>(A.w_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_w);
+            tb_store<VEC>(A.mu_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_mu);
+        }
+    }
+}
+
+template <int VEC, int T, bool UNIT, bool CHECK, typename R>
+__device__ __forceinline__ bool tba_group(const TBAArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
+                                          TBRows& rw, int32_t (&prow)[T], TBAState<VEC, T, R>& S,
+                                          double (&gs)[T])
+{
+    tba_iter<VEC, T, UNIT, CHECK, 0>(A, L, i, last, rw, prow, S, gs);
+    if (i + 1 > last) return false;
+    tba_iter<VEC, T, UNIT, CHECK, 1>(A, L, i + 1, last, rw, prow, S, gs);
+    if (i + 2 > last) return false;
+    tba_iter<VEC, T, UNIT, CHECK, 2>(A, L, i + 2, last, rw, prow, S, gs);
+    if (i + 3 > last) return false;
+    tba_iter<VEC, T, UNIT, CHECK, 3>(A, L, i + 3, last, rw, prow, S, gs);
+    return i + 4 <= last;
+}
+
+template <int VEC, int T, bool UNIT, typename R>
+__global__ __launch_bounds__(kBlock) void k_tba2d(TBAArgs<T, R> A)
+{
+    constexpr int H = (T + VEC - 1) / VEC;
+    constexpr int W = (kWave - 2 * H) * VEC;
+    constexpr int WARM = (2 * T - 2 + 3) / 4;
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t tx = tl % (uint32_t)A.tiles_x;
+    const uint32_t ts = tl / (uint32_t)A.tiles_x;
+    TBLane L;
+    L.nx = (uint32_t)A.nx;
+    L.ny = (int32_t)A.ny;
+    L.row_bytes = L.nx * (uint32_t)sizeof(R);
+    const int32_t rows = (int32_t)A.rows;
+    const int32_t x0 = (int32_t)(tx * (uint32_t)W) + (lane - H) * VEC;
+    L.voff = (uint32_t)wrap_row(x0, (int32_t)L.nx) * (uint32_t)sizeof(R);
+    L.soff = (lane >= H && lane < kWave - H && x0 < (int32_t)L.nx) ? L.voff : kPastRow;
+    L.s0 = (int32_t)ts * rows;
+    L.s1 = L.s0 + rows < L.ny ? L.s0 + rows : L.ny;
+
+    TBAState<VEC, T, R> S;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            S.in[a][j] = R(0);
+#pragma unroll
+            for (int k = 0; k < T; ++k) S.lv[k][a][j] = R(0);
+        }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            S.mi[a][j] = R(0);
+#pragma unroll
+            for (int k = 0; k < T; ++k) S.ml[k][a][j] = S.ph[k][a][j] = R(0);
+        }
+
+    // iteration 0 (y0 = s0 - T + 1): w rows y0-1 .. y0+1, mu row y0, and the
+    // phi row of every level (level k computes row y0 - k + 1)
+    const int32_t y0 = L.s0 - T + 1;
+    tb_load<VEC>(A.w_in, wrap_row(y0 - 1, L.ny), L, L.row_bytes, S.in[3]);
+    tb_load<VEC>(A.w_in, wrap_row(y0, L.ny), L, L.row_bytes, S.in[0]);
+    tb_load<VEC>(A.w_in, wrap_row(y0 + 1, L.ny), L, L.row_bytes, S.in[1]);
+    tb_load<VEC>(A.mu_in, wrap_row(y0, L.ny), L, L.row_bytes, S.mi[0]);
+    int32_t prow[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        tb_load<VEC>(A.phi[k], wrap_row(y0 - k, L.ny), L, L.row_bytes, S.ph[k][0]);
+        prow[k] = wrap_row(y0 - k + 1, L.ny);
+    }
+    TBRows rw;
+    rw.phi = wrap_row(y0 + 2, L.ny);
+    rw.pi = wrap_row(y0 + 1, L.ny);
+    double gs[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) gs[k] = 0.0;
+
+    const int32_t last = (L.s1 - L.s0) + 2 * T - 3;
+    int32_t i = 0;
+    bool more = true;
+#pragma unroll
+    for (int w = 0; w < WARM; ++w) {
+        if (more) more = tba_group<VEC, T, UNIT, true>(A, L, i, last, rw, prow, S, gs);
+        i += 4;
+    }
+    while (more) {
+        more = tba_group<VEC, T, UNIT, false>(A, L, i, last, rw, prow, S, gs);
+        i += 4;
+    }
+    double gsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) gsum += A.gscale[k] * wave_sum_f64(gs[k]);
+    if (lane == 0) A.gacc[tile] += gsum;
 }
 
 // ----------------------------------------- T steps per HBM pass (3D) --------
@@ -1562,6 +1786,116 @@ hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const void* ph
             return launch_tb_t<R, VEC, 8>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
         break;
     }
+    return hipErrorInvalidValue;
+}
+
+// Multi-step passes of the adjoint (2D): the recomputation storing every
+// step and the reverse sweep, T = 2, 4 and (float32) 8, vec 1 or 2.
+template <typename R>
+constexpr bool tba_combo_ok(int vec, int T)
+{
+    return (vec == 1 || vec == 2) && (T == 2 || T == 4 || (sizeof(R) == 4 && T == 8));
+}
+
+template <typename R, int VEC, int T>
+hipError_t launch_tb_all_t(const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                           const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+{
+    TBArgs<T, R> A;
+    A.phi_in = static_cast<const R*>(phi_in);
+    A.phi_out = static_cast<R*>(phi_lv[T - 1]);
+    for (int i = 0; i < T; ++i) A.phi_lv[i] = static_cast<R*>(phi_lv[i]);
+    A.pi_in = static_cast<const R*>(pi_in);
+    A.pi_out = static_cast<R*>(pi_out);
+    A.partials = nullptr;
+    A.nx = g.nx;
+    A.ny = g.M;
+    const int64_t W = tb_owned_width_d(VEC, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.ntiles = A.tiles_x * ((g.M + t.rows - 1) / t.rows);
+    A.rows = t.rows;
+    for (int i = 0; i < T; ++i) A.k[i] = coef_as<R>(k[i]);
+    A.dc = DiagCoef{};
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1))
+        hipLaunchKernelGGL((k_tb2d_all<VEC, T, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tb2d_all<VEC, T, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tb_all_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                           const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+{
+    if (!tba_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
+#define PRS_TBALL(V, TT)                                                                       \
+    if (t.vec == V && T == TT) {                                                                \
+        if constexpr (tba_combo_ok<R>(V, TT))                                                   \
+            return launch_tb_all_t<R, V, TT>(g, t, phi_in, phi_lv, pi_in, pi_out, k, s);        \
+    }
+    PRS_TBALL(1, 2)
+    PRS_TBALL(1, 4)
+    PRS_TBALL(1, 8)
+    PRS_TBALL(2, 2)
+    PRS_TBALL(2, 4)
+    PRS_TBALL(2, 8)
+#undef PRS_TBALL
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int VEC, int T>
+hipError_t launch_tba_t(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, const void* mu_in,
+                        void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c, hipStream_t s)
+{
+    TBAArgs<T, R> A;
+    A.w_in = static_cast<const R*>(w_in);
+    A.w_out = static_cast<R*>(w_out);
+    A.mu_in = static_cast<const R*>(mu_in);
+    A.mu_out = static_cast<R*>(mu_out);
+    for (int i = 0; i < T; ++i) {
+        A.phi[i] = static_cast<const R*>(phi[i]);
+        A.a[i] = (R)c[i].a;
+        A.b[i] = (R)c[i].b;
+        A.cw[i] = (R)c[i].cw;
+        A.gscale[i] = c[i].gscale;
+    }
+    A.F = (R)c[0].F;
+    A.kc = (R)c[0].kc;
+    A.inv_dx2 = (R)c[0].inv_dx2;
+    A.gacc = gacc;
+    A.nx = g.nx;
+    A.ny = g.M;
+    const int64_t W = tb_owned_width_d(VEC, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.ntiles = A.tiles_x * ((g.M + t.rows - 1) / t.rows);
+    A.rows = t.rows;
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (A.inv_dx2 == R(1) && A.kc == R(1))
+        hipLaunchKernelGGL((k_tba2d<VEC, T, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tba2d<VEC, T, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tba_r(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out,
+                        const void* mu_in, void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c,
+                        hipStream_t s)
+{
+    if (!tba_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
+#define PRS_TBA(V, TT)                                                                          \
+    if (t.vec == V && T == TT) {                                                                 \
+        if constexpr (tba_combo_ok<R>(V, TT))                                                    \
+            return launch_tba_t<R, V, TT>(g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);    \
+    }
+    PRS_TBA(1, 2)
+    PRS_TBA(1, 4)
+    PRS_TBA(1, 8)
+    PRS_TBA(2, 2)
+    PRS_TBA(2, 4)
+    PRS_TBA(2, 8)
+#undef PRS_TBA
     return hipErrorInvalidValue;
 }
 

@@ -112,6 +112,29 @@ using AdjCoef64 = AdjCoefT<double>;
 hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
                           const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s);
 
+// Multi-step passes of the adjoint (2D; T = 2, 4, and 8 in float32; vec 1
+// or 2; ty 1).  launch_tb_all: T forward steps from (phi_in, pi_in) storing
+// phi^{n+k} to phi_lv[k-1] for k = 1 .. T and phi_dot^{n+T-1/2} to pi_out
+// (!= pi_in).  launch_tba: T reverse steps m, m-1, .. m-T+1 (coefficients
+// c[k-1] and field phi[k-1] = phi^{m-k+1} for level k) from (w_in, mu_in) to
+// (w_out, mu_out), both pairs distinct; adds the pass's dL/dV0 to
+// gacc[wave tile] (tb_tiles(g, t, T) accumulators).
+bool tba_supported(const Geometry& g, const Tiling& t, int T);
+hipError_t launch_tb_all(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                         const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
+hipError_t launch_tba(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out, const void* mu_in,
+                      void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c, hipStream_t s);
+hipError_t launch_tb_all_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                             const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
+hipError_t launch_tb_all_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                             const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
+hipError_t launch_tba_f32(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out,
+                          const void* mu_in, void* mu_out, const void* const* phi, double* gacc,
+                          const AdjCoef64* c, hipStream_t s);
+hipError_t launch_tba_f64(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out,
+                          const void* mu_in, void* mu_out, const void* const* phi, double* gacc,
+                          const AdjCoef64* c, hipStream_t s);
+
 // mu = dL/dphi^S, w = deta*mu from the final field; FP64 loss partial per block.
 hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, double kc, double deta, void* mu,
                            void* w, double* partial, int nblocks, hipStream_t s);

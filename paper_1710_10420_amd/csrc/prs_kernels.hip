@@ -402,6 +402,19 @@ hipError_t launch_adj_seed_f32(const void* phi, int64_t count, double kc, double
     return launch_adj_seed_r<float>(phi, count, kc, deta, mu, w, partial, nblocks, s);
 }
 
+hipError_t launch_tb_all_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                             const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+{
+    return launch_tb_all_r<float>(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s);
+}
+
+hipError_t launch_tba_f32(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out,
+                          const void* mu_in, void* mu_out, const void* const* phi, double* gacc,
+                          const AdjCoef64* c, hipStream_t s)
+{
+    return launch_tba_r<float>(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
+}
+
 hipError_t launch_fill_f32(void* phi, int64_t count, uint64_t seed, hipStream_t s)
 {
     return launch_fill_r<float>(phi, count, seed, s);
@@ -440,6 +453,28 @@ hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, do
 {
     return g.f64 ? launch_adj_seed_f64(phi, count, kc, deta, mu, w, partial, nblocks, s)
                  : launch_adj_seed_f32(phi, count, kc, deta, mu, w, partial, nblocks, s);
+}
+
+bool tba_supported(const Geometry& g, const Tiling& t, int T)
+{
+    if (g.ndim != 2 || !tb_supported(g) || !tiling_supported(g, t) || t.ty != 1) return false;
+    return g.f64 ? tba_combo_ok<double>(t.vec, T) : tba_combo_ok<float>(t.vec, T);
+}
+
+hipError_t launch_tb_all(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                         const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+{
+    if (!tba_supported(g, t, T)) return hipErrorInvalidValue;
+    return g.f64 ? launch_tb_all_f64(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s)
+                 : launch_tb_all_f32(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s);
+}
+
+hipError_t launch_tba(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out, const void* mu_in,
+                      void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c, hipStream_t s)
+{
+    if (!tba_supported(g, t, T)) return hipErrorInvalidValue;
+    return g.f64 ? launch_tba_f64(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s)
+                 : launch_tba_f32(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
 }
 
 hipError_t launch_fill_uniform(void* phi, int64_t count, uint64_t seed, bool f64, hipStream_t s)

@@ -35,6 +35,19 @@ hipError_t launch_adj_seed_f64(const void* phi, int64_t count, double kc, double
     return launch_adj_seed_r<double>(phi, count, kc, deta, mu, w, partial, nblocks, s);
 }
 
+hipError_t launch_tb_all_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                             const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+{
+    return launch_tb_all_r<double>(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s);
+}
+
+hipError_t launch_tba_f64(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out,
+                          const void* mu_in, void* mu_out, const void* const* phi, double* gacc,
+                          const AdjCoef64* c, hipStream_t s)
+{
+    return launch_tba_r<double>(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
+}
+
 hipError_t launch_fill_f64(void* phi, int64_t count, uint64_t seed, hipStream_t s)
 {
     return launch_fill_r<double>(phi, count, seed, s);

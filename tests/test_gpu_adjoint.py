@@ -54,18 +54,71 @@ def test_adjoint_matches_oracle(shape, nsteps, K):
     assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
 
 
+def gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling=None):
+    torch = torch_mod()
+    prs = gpu_prs()
+    sim = prs.Sim(gp, phi0=to_dev(phi0) if gp.precision == prs.PRS_F32 else
+                  torch.from_numpy(np.asarray(phi0, np.float64).reshape(-1)).cuda())
+    if tiling is not None:
+        sim.set_tiling(*tiling)
+    sim.set_time_blocking(T)
+    nb = prs.prs_adjoint_workspace_bytes(gp, nsteps, K)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    gphi = torch.empty_like(sim.phi_a)
+    gdphi = torch.empty_like(sim.phi_a)
+    loss, gw = prs.prs_adjoint(sim.ctx, nsteps, K, work.data_ptr(), nb, gphi.data_ptr(), gdphi.data_ptr())
+    return loss, host(gphi), host(gdphi), gw
+
+
 def test_adjoint_checkpoint_interval_bitwise():
-    """Recomputation is bit-exact, so the gradient does not depend on K."""
+    """Recomputation is bit-exact, so the gradient does not depend on K
+    (single steps: dL/dW0 too, bit for bit)."""
     say("adjoint K invariance")
     shape = (200, 130)
     gp, _ = params_pair(shape, 0.25, m=2.0, W0=5.0)
     phi0 = uniform_field(shape, 4)
-    ref = gpu_adjoint(gp, phi0, 40, 1)
+    ref = gpu_adjoint_T(gp, phi0, 40, 1, 1)
     for K in (3, 16, 40, 64):
-        got = gpu_adjoint(gp, phi0, 40, K)
+        got = gpu_adjoint_T(gp, phi0, 40, K, 1)
         np.testing.assert_array_equal(got[1], ref[1])
         np.testing.assert_array_equal(got[2], ref[2])
         assert got[3] == ref[3] and got[0] == ref[0]
+
+
+@pytest.mark.parametrize("shape,nsteps,K,tiling", [
+    ((200, 130), 40, 16, (1, 16, 1)), ((264, 200), 37, 10, (2, 17, 1)), ((256, 256), 64, 64, (2, 64, 1)),
+    ((130, 9), 23, 7, (2, 8, 1)), ((40, 36, 30), 21, 8, (1, 16, 4)), ((64, 9, 33), 14, 5, (2, 16, 2)),
+])
+def test_multi_step_adjoint_bitwise_equal_single_steps(shape, nsteps, K, tiling):
+    """Multi-step passes in the forward-with-checkpoints, the recomputation
+    (storing every step) and the reverse sweep leave the gradient fields bit
+    for bit those of single steps, for every steps per pass, checkpoint
+    interval and ragged segment; dL/dW0 agrees to summation order."""
+    say("multi-step adjoint", shape, nsteps, K, tiling)
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp, _ = params_pair(shape, deta, m=1.0, W0=6.0)
+    phi0 = uniform_field(shape, 8)
+    ref = gpu_adjoint_T(gp, phi0, nsteps, K, 1, tiling)
+    for T in ((2, 3, 4, 6, 8) if len(shape) == 2 else (2, 3)):
+        got = gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling)
+        np.testing.assert_array_equal(got[1], ref[1], err_msg=str(T))
+        np.testing.assert_array_equal(got[2], ref[2], err_msg=str(T))
+        assert got[0] == ref[0]
+        assert got[3] == pytest.approx(ref[3], rel=1e-11), T
+
+
+def test_multi_step_adjoint_f64():
+    say("multi-step adjoint f64")
+    prs = gpu_prs()
+    shape = (130, 96)
+    gp = prs.make_params(shape, deta=0.25, m=1.0, W0=6.0, precision=prs.PRS_F64)
+    phi0 = uniform_field(shape, 9)
+    ref = gpu_adjoint_T(gp, phi0, 30, 12, 1, (2, 16, 1))
+    for T in (2, 3, 4):
+        got = gpu_adjoint_T(gp, phi0, 30, 12, T, (2, 16, 1))
+        np.testing.assert_array_equal(got[1], ref[1], err_msg=str(T))
+        np.testing.assert_array_equal(got[2], ref[2], err_msg=str(T))
+        assert got[3] == pytest.approx(ref[3], rel=1e-13), T
 
 
 def test_adjoint_backward_requires_forward():
