@@ -193,11 +193,18 @@ prs_status prs_get_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
 prs_status prs_plan_passes(const prs_ctx* ctx, int64_t nsteps, int32_t with_records, int64_t* multi_passes,
                            int64_t* single_passes);
 
-/* Tiling of the reverse-sweep (adjoint) kernel, chosen independently of the
- * forward tiling (same parameters and rules as prs_set_tiling; the
- * recomputation inside prs_adjoint_backward uses the forward tiling). */
+/* Tiling and steps per pass of the reverse sweep (adjoint), chosen
+ * independently of the forward ones (same parameters and rules as
+ * prs_set_tiling; PRS_TUNE_ADJOINT tunes both).  The forward-with-checkpoints
+ * and the recomputation inside prs_adjoint_backward use the forward tiling
+ * and steps per pass.  Multi-step reverse passes exist for 2D lattices with
+ * T = 2, 4 and, in float32, 8 and tilings with vec 1 or 2; other settings
+ * run single reverse steps.  The default is the forward's setting at
+ * prs_init. */
 prs_status prs_set_adjoint_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
 prs_status prs_get_adjoint_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
+prs_status prs_set_adjoint_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
+prs_status prs_get_adjoint_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
 
 /* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
 void prs_destroy(prs_ctx* ctx);

@@ -191,6 +191,7 @@ struct prs_ctx {
     prs_stats* hrec;   // pinned staging buffer
     void* pi_alt;      // second phi_dot buffer (workspace) for multi-step passes
     Tiling adj_til;    // tiling of the reverse-sweep kernel
+    int32_t adj_tblock;   // steps per reverse pass
     int32_t tblock;    // steps per pass (1: single steps)
     hipStream_t stream;
     int64_t step;
@@ -299,6 +300,7 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, v
         static_cast<char*>(workspace) + align_up((size_t)c->partial_cap * sizeof(WavePartial)));
     c->pi_alt = nullptr;
     c->adj_til = c->til;
+    c->adj_tblock = p->ndim == 2 ? 2 : 1;
     c->pi_alt = reinterpret_cast<char*>(c->drec) + align_up((size_t)kRecCap * sizeof(prs_stats));
     c->tblock = p->ndim == 2 ? 2 : 1;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -478,6 +480,22 @@ prs_status prs_set_adjoint_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t
         return fail(PRS_EINVAL, "tiling has more wave tiles than the workspace holds (rows >= %lld)",
                     (long long)kMinRows);
     c->adj_til = t;
+    return PRS_OK;
+}
+
+prs_status prs_set_adjoint_time_blocking(prs_ctx* c, int32_t steps_per_pass)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (steps_per_pass < 1 || steps_per_pass > kMaxPassSteps)
+        return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
+    c->adj_tblock = steps_per_pass;
+    return PRS_OK;
+}
+
+prs_status prs_get_adjoint_time_blocking(prs_ctx* c, int32_t* steps_per_pass)
+{
+    if (!c || !steps_per_pass) return fail(PRS_EINVAL, "NULL argument");
+    *steps_per_pass = c->adj_tblock;
     return PRS_OK;
 }
 
@@ -742,6 +760,7 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     const int64_t n0 = c->adj_n0;
     const size_t bytes = field_bytes(c->p);
     const int T = tb_supported(c->geo) ? c->tblock : 1;
+    const int TA = tb_supported(c->geo) ? c->adj_tblock : 1;
     double* gacc = at<double>(work, L.gacc);
     HIP_TRY(launch_zero_f64(gacc, c->partial_cap, c->stream), "zero launch");
     char* mu = at<char>(work, L.mu);
@@ -786,7 +805,7 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
         }
         // reverse sweep over steps ns+len-1 .. ns
         for (int64_t k = len - 1; k >= 0;) {
-            const int Lp = adj_pass_len(c->geo, c->til, c->partial_cap, T, k + 1);
+            const int Lp = adj_pass_len(c->geo, c->adj_til, c->partial_cap, TA, k + 1);
             if (Lp > 1) {
                 const void* phis[kMaxPassSteps];
                 AdjCoef64 cc[kMaxPassSteps];
@@ -794,7 +813,7 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
                     phis[i] = phi_at(k - i);
                     cc[i] = adj_coef(c, ns + k - i, ns + k - i == n0);
                 }
-                HIP_TRY(launch_tba(Lp, c->geo, c->til, wcur, wnxt, mu, mu_oth, phis, gacc, cc, c->stream),
+                HIP_TRY(launch_tba(Lp, c->geo, c->adj_til, wcur, wnxt, mu, mu_oth, phis, gacc, cc, c->stream),
                         "adjoint launch");
                 std::swap(mu, mu_oth);
             } else {
@@ -1428,7 +1447,7 @@ void prs_batch_destroy(prs_batch* b)
 
 namespace {
 
-constexpr const char* kTuneVersion = "k1";
+constexpr const char* kTuneVersion = "k2";
 
 std::string tune_key(const prs_params& p, bool batch_set)
 {
@@ -1537,7 +1556,8 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     if (!(flags & PRS_TUNE_FORCE)) {
         const auto it = cache.find(key);
         if (it != cache.end() &&
-            prs_set_adjoint_tiling(c, it->second.vec, it->second.rows, it->second.ty) == PRS_OK) {
+            prs_set_adjoint_tiling(c, it->second.vec, it->second.rows, it->second.ty) == PRS_OK &&
+            prs_set_adjoint_time_blocking(c, it->second.tb) == PRS_OK) {
             if (best_us) *best_us = it->second.us;
             return PRS_OK;
         }
@@ -1546,50 +1566,76 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     const size_t bytes = field_bytes(c->p);
     char* buf = nullptr;
     double* gacc = nullptr;
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), 3 * bytes), "tuner allocation");
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), 4 * bytes), "tuner allocation");
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&gacc), (size_t)c->partial_cap * sizeof(double));
     char* w0 = buf;
     char* w1 = buf + bytes;
-    char* mu = buf + 2 * bytes;
+    char* mu0 = buf + 2 * bytes;
+    char* mu1 = buf + 3 * bytes;
     if (e == hipSuccess) e = hipMemcpyAsync(w0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(mu, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(mu0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = launch_zero_f64(gacc, c->partial_cap, c->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     const double sites = (double)sites_of(c->p);
-    const int timed = (int)std::max(4.0, std::min(40.0, 4e9 / std::max(sites, 1.0)));
+    const int timed = (int)std::max(8.0, std::min(48.0, 4e9 / std::max(sites, 1.0)));
     const char* env = std::getenv("PRS_TUNE_LOG");
     const bool log_each = env && env[0] == '1';
     Tiling best = c->adj_til;
+    int best_T = 1;
     double best_t = 1e300;
-    for (const Tiling& t : cand) {
-        if (e != hipSuccess) break;
-        if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
-        char* a = w0;
-        char* b = w1;
-        auto run = [&](int steps) -> hipError_t {
-            for (int k = 0; k < steps; ++k) {
-                hipError_t err = launch_adjoint(c->geo, t, a, b, mu, c->phi[c->cur], gacc,
-                                                adj_coef(c, c->step, false), c->stream);
-                if (err != hipSuccess) return err;
-                std::swap(a, b);
+    // single reverse steps for every tiling; multi-step reverse passes (2D)
+    // for the tilings and lengths that have kernels
+    for (int T : {1, 2, 4, 8}) {
+        for (const Tiling& t : cand) {
+            if (e != hipSuccess) break;
+            if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
+            if (T > 1 && !(tb_supported(c->geo) && tba_supported(c->geo, t, T) &&
+                           tb_tiles(c->geo, t, T) <= c->partial_cap))
+                continue;
+            char* a = w0;
+            char* b = w1;
+            char* ma = mu0;
+            char* mb = mu1;
+            auto run = [&](int steps) -> hipError_t {
+                for (int k = 0; k < steps; k += T) {
+                    hipError_t err;
+                    if (T > 1) {
+                        const void* phis[kMaxPassSteps];
+                        AdjCoef64 cc[kMaxPassSteps];
+                        for (int i = 0; i < T; ++i) {
+                            phis[i] = c->phi[c->cur];
+                            cc[i] = adj_coef(c, c->step, false);
+                        }
+                        err = launch_tba(T, c->geo, t, a, b, ma, mb, phis, gacc, cc, c->stream);
+                        std::swap(ma, mb);
+                    } else {
+                        err = launch_adjoint(c->geo, t, a, b, ma, c->phi[c->cur], gacc, adj_coef(c, c->step, false),
+                                             c->stream);
+                    }
+                    if (err != hipSuccess) return err;
+                    std::swap(a, b);
+                }
+                return hipSuccess;
+            };
+            e = run(2 * T);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = run(timed);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            const int done = (timed + T - 1) / T * T;
+            const double per_step = ms / done;
+            if (e == hipSuccess && log_each)
+                std::fprintf(stderr, "prs_autotune(adjoint): vec=%d rows=%d ty=%d steps/pass=%d %.2f us/step\n",
+                             t.vec, t.rows, t.ty, T, per_step * 1e3);
+            if (e == hipSuccess && per_step < best_t) {
+                best_t = per_step;
+                best = t;
+                best_T = T;
             }
-            return hipSuccess;
-        };
-        e = run(2);
-        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        if (e == hipSuccess) e = run(timed);
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        const double per_step = ms / timed;
-        if (e == hipSuccess && log_each)
-            std::fprintf(stderr, "prs_autotune(adjoint): vec=%d rows=%d ty=%d %.2f us/step\n", t.vec, t.rows, t.ty,
-                         per_step * 1e3);
-        if (e == hipSuccess && per_step < best_t) {
-            best_t = per_step;
-            best = t;
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1599,9 +1645,10 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     (void)hipFree(gacc);
     if (e != hipSuccess) return hip_fail(e, "adjoint autotune");
     c->adj_til = best;
+    c->adj_tblock = best_T;
     if (best_us) *best_us = best_t * 1e3;
     if (cache_path && cache_path[0]) {
-        cache[key] = TuneEntry{best.vec, best.rows, best.ty, 1, best_t * 1e3};
+        cache[key] = TuneEntry{best.vec, best.rows, best.ty, best_T, best_t * 1e3};
         if (!tune_write(cache_path, cache)) return fail(PRS_EINVAL, "cannot write tuning cache %s", cache_path);
     }
     return PRS_OK;

@@ -1306,6 +1306,7 @@ struct TB3Args {
     R* phi_out;
     const R* pi_in;
     R* pi_out;
+    R* phi_lv[T];               // with ALL: phi^{n+k} of levels k = 1 .. T-1 (level T is phi_out)
     WavePartial* partials;
     int64_t nx, ny, nz;
     int64_t tiles_x, tiles_y, ntiles;
@@ -1348,7 +1349,7 @@ __device__ __forceinline__ void tb3_load(const R* f, int32_t p, const TB3Lane<T,
 
 // Iteration i of the z-march (z = s0 - T + 1 + i): level k computes plane
 // s0 - T - k + 2 + i, as in 2D.
-template <int VEC, int T, int TY, bool DIAG, bool UNIT, bool CHECK, int U, typename R>
+template <int VEC, int T, int TY, bool DIAG, bool UNIT, bool CHECK, int U, bool ALL, typename R>
 __device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T, TY>& L, int32_t i, int32_t last,
                                          TBRows& rw, TB3State<VEC, T, TY, R>& S, DiagAcc& acc)
 {
@@ -1412,6 +1413,16 @@ __device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T
                     S.lv[k < T ? k : 0][U & 3][r][j] = out_phi[j];
                     S.pl[k < T ? k : 0][U & 1][r][j] = out_pi[j];
                 }
+                if constexpr (ALL) {
+                    // owned rows of level k, plane s0 + i - (T + k - 2) when inside [s0, s1)
+                    if (r >= T && r < T + TY) {
+                        const int32_t e = i - (T + k - 2);
+                        const bool in = e >= 0 && e < L.s1 - L.s0;
+                        const size_t lb = (size_t)(uint32_t)(in ? L.s0 + e : L.s0) * L.plane;
+                        const uint32_t so = L.srow[r - T < TY ? (r - T >= 0 ? r - T : 0) : 0];
+                        buf_store<VEC>(A.phi_lv[k < T ? k - 1 : 0] + lb, in ? L.plane_bytes : 0u, so, out_phi);
+                    }
+                }
             } else {
                 const uint32_t so = L.srow[r - T < TY ? (r - T >= 0 ? r - T : 0) : 0];
                 buf_store<VEC>(A.phi_out + obase, sb, so, out_phi);
@@ -1421,23 +1432,23 @@ __device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T
     }
 }
 
-template <int VEC, int T, int TY, bool DIAG, bool UNIT, bool CHECK, typename R>
+template <int VEC, int T, int TY, bool DIAG, bool UNIT, bool CHECK, bool ALL, typename R>
 __device__ __forceinline__ bool tb3_group(const TB3Args<T, R>& A, const TB3Lane<T, TY>& L, int32_t i, int32_t last,
                                           TBRows& rw, TB3State<VEC, T, TY, R>& S, DiagAcc& acc)
 {
-    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 0>(A, L, i, last, rw, S, acc);
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 0, ALL>(A, L, i, last, rw, S, acc);
     if (i + 1 > last) return false;
-    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 1>(A, L, i + 1, last, rw, S, acc);
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 1, ALL>(A, L, i + 1, last, rw, S, acc);
     if (i + 2 > last) return false;
-    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 2>(A, L, i + 2, last, rw, S, acc);
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 2, ALL>(A, L, i + 2, last, rw, S, acc);
     if (i + 3 > last) return false;
-    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 3>(A, L, i + 3, last, rw, S, acc);
+    tb3_iter<VEC, T, TY, DIAG, UNIT, CHECK, 3, ALL>(A, L, i + 3, last, rw, S, acc);
     return i + 4 <= last;
 }
 
 // One wave's tile of a T-step 3D pass; `tile` must be below A.ntiles and
 // wave-uniform.
-template <int VEC, int T, int TY, bool DIAG, bool UNIT, typename R>
+template <int VEC, int T, int TY, bool DIAG, bool UNIT, bool ALL, typename R>
 __device__ __forceinline__ void tb3_tile(const TB3Args<T, R>& A, int64_t tile)
 {
     constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
@@ -1511,11 +1522,11 @@ __device__ __forceinline__ void tb3_tile(const TB3Args<T, R>& A, int64_t tile)
     bool more = true;
 #pragma unroll
     for (int w = 0; w < WARM; ++w) {
-        if (more) more = tb3_group<VEC, T, TY, DIAG, UNIT, true>(A, L, i, last, rw, S, acc);
+        if (more) more = tb3_group<VEC, T, TY, DIAG, UNIT, true, ALL>(A, L, i, last, rw, S, acc);
         i += 4;
     }
     while (more) {
-        more = tb3_group<VEC, T, TY, DIAG, UNIT, false>(A, L, i, last, rw, S, acc);
+        more = tb3_group<VEC, T, TY, DIAG, UNIT, false, ALL>(A, L, i, last, rw, S, acc);
         i += 4;
     }
 
@@ -1538,7 +1549,235 @@ __global__ __launch_bounds__(kBlock) void k_tb3d(TB3Args<T, R> A)
 {
     const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     if (tile >= A.ntiles) return;
-    tb3_tile<VEC, T, TY, DIAG, UNIT>(A, tile);
+    tb3_tile<VEC, T, TY, DIAG, UNIT, false>(A, tile);
+}
+
+// The 3D T-step pass storing every step's field (adjoint recomputation).
+template <int VEC, int T, int TY, bool UNIT, typename R>
+__global__ __launch_bounds__(kBlock) void k_tb3d_all(TB3Args<T, R> A)
+{
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    tb3_tile<VEC, T, TY, false, UNIT, true>(A, tile);
+}
+
+// ------------------------------- reverse sweep, T steps per pass (3D) ------
+//
+// The 2D reverse pass (k_tba2d) on the 3D tile of k_tb3d: NY = TY + 2T rows
+// along y per plane, level k (reverse step m-k+1) on rows k .. NY-k-1 with
+// its own phi^{m-k+1} plane, w the stencil field and mu the pointwise one,
+// separate in and out buffers, one dL/dV0 sum per level.
+
+template <int T, typename R = float>
+struct TBA3Args {
+    const R* w_in;
+    R* w_out;
+    const R* mu_in;
+    R* mu_out;
+    const R* phi[T];
+    double* gacc;
+    int64_t nx, ny, nz;
+    int64_t tiles_x, tiles_y, ntiles;
+    int64_t rows;
+    R a[T], b[T], cw[T];
+    R F, kc, inv_dx2;
+    double gscale[T];
+};
+
+template <int VEC, int T, int TY, typename R>
+struct TBA3State {
+    static constexpr int NY = TY + 2 * T;
+    R in[4][NY][VEC];           // w planes
+    R mi[2][NY][VEC];           // mu planes (rows 1 .. NY-2)
+    R lv[T][4][NY][VEC];        // level k w planes
+    R ml[T][2][NY][VEC];        // level k mu planes
+    R ph[T][2][NY][VEC];        // phi plane of each level (rows k .. NY-k-1), one iteration ahead
+};
+
+template <int VEC, int T, int TY, bool UNIT, bool CHECK, int U, typename R>
+__device__ __forceinline__ void tba3_iter(const TBA3Args<T, R>& A, const TB3Lane<T, TY>& L, int32_t i,
+                                          int32_t last, TBRows& rw, int32_t (&prow)[T],
+                                          TBA3State<VEC, T, TY, R>& S, double (&gs)[T])
+{
+    constexpr int NY = TY + 2 * T;
+    const uint32_t nb = i < last ? L.plane_bytes : 0u;
+    tb3_load<VEC, T, TY>(A.w_in, rw.phi, L, nb, 0, NY, S.in[(U + 2) & 3]);
+    tb3_load<VEC, T, TY>(A.mu_in, rw.pi, L, nb, 1, NY - 1, S.mi[(U + 1) & 1]);
+    rw.phi = next_row(rw.phi, L.nz);
+    rw.pi = next_row(rw.pi, L.nz);
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        tb3_load<VEC, T, TY>(A.phi[k], prow[k], L, nb, k + 1, NY - k - 1, S.ph[k][(U + 1) & 1]);
+        prow[k] = next_row(prow[k], L.nz);
+    }
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        if (CHECK && i < 2 * (k - 1)) continue;
+        const R(*cm)[VEC];
+        const R(*cc)[VEC];
+        const R(*cp)[VEC];
+        const R(*mp)[VEC];
+        if (k == 1) {
+            cm = S.in[(U + 3) & 3];
+            cc = S.in[U & 3];
+            cp = S.in[(U + 1) & 3];
+            mp = S.mi[U & 1];
+        } else {
+            cm = S.lv[k - 1][(U + 2) & 3];
+            cc = S.lv[k - 1][(U + 3) & 3];
+            cp = S.lv[k - 1][U & 3];
+            mp = S.ml[k - 1][(U + 1) & 1];
+        }
+        const R(*ph)[VEC] = S.ph[k - 1][U & 1];
+        const int32_t e = i - (T + k - 2);
+        const bool own_plane = e >= 0 && e < L.s1 - L.s0;
+        const int32_t zout = L.s0 + i - (2 * T - 2);
+        const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.plane_bytes : 0u;
+        const size_t obase = (size_t)(uint32_t)(CHECK && i < 2 * T - 2 ? L.s0 : zout) * L.plane;
+        double g = 0.0;
+#pragma unroll
+        for (int r = k; r < NY - k; ++r) {
+            const R left = from_left_lane(cc[r][VEC - 1]);
+            const R right = from_right_lane(cc[r][0]);
+            R out_w[VEC], out_mu[VEC];
+            double gr = 0.0;
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const R w = cc[r][j];
+                const R xm = j > 0 ? cc[r][j > 0 ? j - 1 : 0] : left;
+                const R xp = j < VEC - 1 ? cc[r][j < VEC - 1 ? j + 1 : j] : right;
+                const R lap = lap3<UNIT>(w, xm, xp, cc[r - 1][j], cc[r + 1][j], cm[r][j], cp[r][j], A.inv_dx2);
+                const R p = ph[r][j];
+                const R phk = UNIT ? p : p * A.kc;
+                const R q = fmar(phk, p, R(-1));
+                const R v2 = A.F * fmar(R(3) * phk, p, R(-1));   // V''(phi)
+                const R mu_new = fmar(A.b[k - 1], lap - v2 * w, mp[r][j]);
+                out_mu[j] = mu_new;
+                out_w[j] = fmar(A.cw[k - 1], mu_new, A.a[k - 1] * w);
+                gr += (double)(w * (p * q));
+            }
+            if (r >= T && r < T + TY && r - T < L.yown) g += gr;
+            if (k < T) {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    S.lv[k < T ? k : 0][U & 3][r][j] = out_w[j];
+                    S.ml[k < T ? k : 0][U & 1][r][j] = out_mu[j];
+                }
+            } else {
+                const uint32_t so = L.srow[r - T < TY ? (r - T >= 0 ? r - T : 0) : 0];
+                buf_store<VEC>(A.w_out + obase, sb, so, out_w);
+                buf_store<VEC>(A.mu_out + obase, sb, so, out_mu);
+            }
+        }
+        if (own_plane && L.own_lane) gs[k - 1] += g;
+    }
+}
+
+template <int VEC, int T, int TY, bool UNIT, bool CHECK, typename R>
+__device__ __forceinline__ bool tba3_group(const TBA3Args<T, R>& A, const TB3Lane<T, TY>& L, int32_t i,
+                                           int32_t last, TBRows& rw, int32_t (&prow)[T],
+                                           TBA3State<VEC, T, TY, R>& S, double (&gs)[T])
+{
+    tba3_iter<VEC, T, TY, UNIT, CHECK, 0>(A, L, i, last, rw, prow, S, gs);
+    if (i + 1 > last) return false;
+    tba3_iter<VEC, T, TY, UNIT, CHECK, 1>(A, L, i + 1, last, rw, prow, S, gs);
+    if (i + 2 > last) return false;
+    tba3_iter<VEC, T, TY, UNIT, CHECK, 2>(A, L, i + 2, last, rw, prow, S, gs);
+    if (i + 3 > last) return false;
+    tba3_iter<VEC, T, TY, UNIT, CHECK, 3>(A, L, i + 3, last, rw, prow, S, gs);
+    return i + 4 <= last;
+}
+
+template <int VEC, int T, int TY, bool UNIT, typename R>
+__global__ __launch_bounds__(kBlock) void k_tba3d(TBA3Args<T, R> A)
+{
+    constexpr int H = (T + VEC - 1) / VEC;
+    constexpr int W = (kWave - 2 * H) * VEC;
+    constexpr int NY = TY + 2 * T;
+    constexpr int WARM = (2 * T - 2 + 3) / 4;
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t tx = tl % (uint32_t)A.tiles_x;
+    const uint32_t rest = tl / (uint32_t)A.tiles_x;
+    const uint32_t tyi = rest % (uint32_t)A.tiles_y;
+    const uint32_t tz = rest / (uint32_t)A.tiles_y;
+    const int32_t nx = (int32_t)A.nx, ny = (int32_t)A.ny;
+    TB3Lane<T, TY> L;
+    L.nz = (int32_t)A.nz;
+    L.plane = (uint64_t)A.nx * (uint64_t)A.ny;
+    L.plane_bytes = (uint32_t)(L.plane * sizeof(R));
+    const int32_t x0 = (int32_t)(tx * (uint32_t)W) + (lane - H) * VEC;
+    const uint32_t xw = (uint32_t)wrap_row(x0, nx);
+    L.own_lane = lane >= H && lane < kWave - H && x0 < nx;
+    const int32_t y0 = (int32_t)tyi * TY;
+    L.yown = ny - y0 < TY ? ny - y0 : TY;
+#pragma unroll
+    for (int r = 0; r < NY; ++r)
+        L.lrow[r] = ((uint32_t)wrap_row(y0 - T + r, ny) * (uint32_t)nx + xw) * (uint32_t)sizeof(R);
+#pragma unroll
+    for (int r = 0; r < TY; ++r) L.srow[r] = (L.own_lane && r < L.yown) ? L.lrow[r + T] : kPastRow;
+    const int32_t rows = (int32_t)A.rows;
+    L.s0 = (int32_t)tz * rows;
+    L.s1 = L.s0 + rows < L.nz ? L.s0 + rows : L.nz;
+
+    TBA3State<VEC, T, TY, R> S;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < NY; ++r)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.in[a][r][j] = R(0);
+#pragma unroll
+                for (int k = 0; k < T; ++k) S.lv[k][a][r][j] = R(0);
+            }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < NY; ++r)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.mi[a][r][j] = R(0);
+#pragma unroll
+                for (int k = 0; k < T; ++k) S.ml[k][a][r][j] = S.ph[k][a][r][j] = R(0);
+            }
+
+    const int32_t z0 = L.s0 - T + 1;
+    tb3_load<VEC, T, TY>(A.w_in, wrap_row(z0 - 1, L.nz), L, L.plane_bytes, 0, NY, S.in[3]);
+    tb3_load<VEC, T, TY>(A.w_in, wrap_row(z0, L.nz), L, L.plane_bytes, 0, NY, S.in[0]);
+    tb3_load<VEC, T, TY>(A.w_in, wrap_row(z0 + 1, L.nz), L, L.plane_bytes, 0, NY, S.in[1]);
+    tb3_load<VEC, T, TY>(A.mu_in, wrap_row(z0, L.nz), L, L.plane_bytes, 1, NY - 1, S.mi[0]);
+    int32_t prow[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        tb3_load<VEC, T, TY>(A.phi[k], wrap_row(z0 - k, L.nz), L, L.plane_bytes, k + 1, NY - k - 1, S.ph[k][0]);
+        prow[k] = wrap_row(z0 - k + 1, L.nz);
+    }
+    TBRows rw;
+    rw.phi = wrap_row(z0 + 2, L.nz);
+    rw.pi = wrap_row(z0 + 1, L.nz);
+    double gs[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) gs[k] = 0.0;
+
+    const int32_t last = (L.s1 - L.s0) + 2 * T - 3;
+    int32_t i = 0;
+    bool more = true;
+#pragma unroll
+    for (int w = 0; w < WARM; ++w) {
+        if (more) more = tba3_group<VEC, T, TY, UNIT, true>(A, L, i, last, rw, prow, S, gs);
+        i += 4;
+    }
+    while (more) {
+        more = tba3_group<VEC, T, TY, UNIT, false>(A, L, i, last, rw, prow, S, gs);
+        i += 4;
+    }
+    double gsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) gsum += A.gscale[k] * wave_sum_f64(gs[k]);
+    if (lane == 0) A.gacc[tile] += gsum;
 }
 
 // ------------------------------------------------------ launch templates --
@@ -1789,6 +2028,14 @@ hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const void* ph
     return hipErrorInvalidValue;
 }
 
+template <typename R>
+hipError_t launch_tb3_all_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                            const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
+template <typename R>
+hipError_t launch_tba3_r(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out,
+                         const void* mu_in, void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c,
+                         hipStream_t s);
+
 // Multi-step passes of the adjoint (2D): the recomputation storing every
 // step and the reverse sweep, T = 2, 4 and (float32) 8, vec 1 or 2.
 template <typename R>
@@ -1828,6 +2075,7 @@ template <typename R>
 hipError_t launch_tb_all_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
                            const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
 {
+    if (g.ndim == 3) return launch_tb3_all_r<R>(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s);
     if (!tba_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
 #define PRS_TBALL(V, TT)                                                                       \
     if (t.vec == V && T == TT) {                                                                \
@@ -1883,6 +2131,7 @@ hipError_t launch_tba_r(int T, const Geometry& g, const Tiling& t, const void* w
                         const void* mu_in, void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c,
                         hipStream_t s)
 {
+    if (g.ndim == 3) return launch_tba3_r<R>(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
     if (!tba_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
 #define PRS_TBA(V, TT)                                                                          \
     if (t.vec == V && T == TT) {                                                                 \
@@ -1964,6 +2213,115 @@ hipError_t launch_tb3d_r(int T, const Geometry& g, const Tiling& t, const void* 
     PRS_TB3(1, 3, 8)
     PRS_TB3(2, 3, 4)
 #undef PRS_TB3
+    return hipErrorInvalidValue;
+}
+
+// 3D multi-step passes of the adjoint: T = 2 on the 3D pass tilings.
+template <typename R>
+constexpr bool tba3_combo_ok(int vec, int T, int TY)
+{
+    return T == 2 && tb3_combo_ok<R>(vec, T, TY);
+}
+
+template <typename R, int VEC, int T, int TY>
+hipError_t launch_tb3_all_t(const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                            const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+{
+    TB3Args<T, R> A;
+    A.phi_in = static_cast<const R*>(phi_in);
+    A.phi_out = static_cast<R*>(phi_lv[T - 1]);
+    for (int i = 0; i < T; ++i) A.phi_lv[i] = static_cast<R*>(phi_lv[i]);
+    A.pi_in = static_cast<const R*>(pi_in);
+    A.pi_out = static_cast<R*>(pi_out);
+    A.partials = nullptr;
+    A.nx = g.nx;
+    A.ny = g.Q;
+    A.nz = g.M;
+    const int64_t W = tb_owned_width_d(VEC, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.tiles_y = (g.Q + TY - 1) / TY;
+    A.ntiles = A.tiles_x * A.tiles_y * ((g.M + t.rows - 1) / t.rows);
+    A.rows = t.rows;
+    for (int i = 0; i < T; ++i) A.k[i] = coef_as<R>(k[i]);
+    A.dc = DiagCoef{};
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1))
+        hipLaunchKernelGGL((k_tb3d_all<VEC, T, TY, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tb3d_all<VEC, T, TY, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename R, int VEC, int T, int TY>
+hipError_t launch_tba3_t(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, const void* mu_in,
+                         void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c, hipStream_t s)
+{
+    TBA3Args<T, R> A;
+    A.w_in = static_cast<const R*>(w_in);
+    A.w_out = static_cast<R*>(w_out);
+    A.mu_in = static_cast<const R*>(mu_in);
+    A.mu_out = static_cast<R*>(mu_out);
+    for (int i = 0; i < T; ++i) {
+        A.phi[i] = static_cast<const R*>(phi[i]);
+        A.a[i] = (R)c[i].a;
+        A.b[i] = (R)c[i].b;
+        A.cw[i] = (R)c[i].cw;
+        A.gscale[i] = c[i].gscale;
+    }
+    A.F = (R)c[0].F;
+    A.kc = (R)c[0].kc;
+    A.inv_dx2 = (R)c[0].inv_dx2;
+    A.gacc = gacc;
+    A.nx = g.nx;
+    A.ny = g.Q;
+    A.nz = g.M;
+    const int64_t W = tb_owned_width_d(VEC, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.tiles_y = (g.Q + TY - 1) / TY;
+    A.ntiles = A.tiles_x * A.tiles_y * ((g.M + t.rows - 1) / t.rows);
+    A.rows = t.rows;
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (A.inv_dx2 == R(1) && A.kc == R(1))
+        hipLaunchKernelGGL((k_tba3d<VEC, T, TY, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tba3d<VEC, T, TY, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tb3_all_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
+                            const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+{
+    const int TY = tb3_rows(t.ty);
+    if (!tba3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
+#define PRS_TB3ALL(V, TT, YY)                                                                     \
+    if (t.vec == V && T == TT && TY == YY) {                                                       \
+        if constexpr (tba3_combo_ok<R>(V, TT, YY))                                                 \
+            return launch_tb3_all_t<R, V, TT, YY>(g, t, phi_in, phi_lv, pi_in, pi_out, k, s);      \
+    }
+    PRS_TB3ALL(1, 2, 4)
+    PRS_TB3ALL(1, 2, 8)
+    PRS_TB3ALL(2, 2, 4)
+#undef PRS_TB3ALL
+    return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_tba3_r(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out,
+                         const void* mu_in, void* mu_out, const void* const* phi, double* gacc, const AdjCoef64* c,
+                         hipStream_t s)
+{
+    const int TY = tb3_rows(t.ty);
+    if (!tba3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
+#define PRS_TBA3(V, TT, YY)                                                                             \
+    if (t.vec == V && T == TT && TY == YY) {                                                             \
+        if constexpr (tba3_combo_ok<R>(V, TT, YY))                                                       \
+            return launch_tba3_t<R, V, TT, YY>(g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);       \
+    }
+    PRS_TBA3(1, 2, 4)
+    PRS_TBA3(1, 2, 8)
+    PRS_TBA3(2, 2, 4)
+#undef PRS_TBA3
     return hipErrorInvalidValue;
 }
 

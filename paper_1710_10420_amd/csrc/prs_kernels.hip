@@ -457,7 +457,12 @@ hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, do
 
 bool tba_supported(const Geometry& g, const Tiling& t, int T)
 {
-    if (g.ndim != 2 || !tb_supported(g) || !tiling_supported(g, t) || t.ty != 1) return false;
+    if (!tb_supported(g) || !tiling_supported(g, t)) return false;
+    if (g.ndim == 3) {
+        const int TY = tb3_rows(t.ty);
+        return g.f64 ? tba3_combo_ok<double>(t.vec, T, TY) : tba3_combo_ok<float>(t.vec, T, TY);
+    }
+    if (t.ty != 1) return false;
     return g.f64 ? tba_combo_ok<double>(t.vec, T) : tba_combo_ok<float>(t.vec, T);
 }
 

@@ -31,7 +31,9 @@ def main():
     ap.add_argument("--copies", type=int, default=10)
     ap.add_argument("--adjoint", action="store_true", help="also run a 64-step adjoint (K = 64)")
     ap.add_argument("--tiling", default=None, help="vec,rows,ty (default: the library default)")
-    ap.add_argument("--steps-per-pass", type=int, default=None, help="steps per pass (2D)")
+    ap.add_argument("--steps-per-pass", type=int, default=None, help="steps per forward pass")
+    ap.add_argument("--adjoint-tiling", default=None, help="vec,rows,ty of the reverse sweep")
+    ap.add_argument("--adjoint-steps-per-pass", type=int, default=None, help="steps per reverse pass")
     args = ap.parse_args()
     w = WORKLOADS[args.workload]
     p = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"])
@@ -40,6 +42,10 @@ def main():
         sim.set_tiling(*[int(v) for v in args.tiling.split(",")])
     if args.steps_per_pass:
         sim.set_time_blocking(args.steps_per_pass)
+    if args.adjoint_tiling:
+        prs.prs_set_adjoint_tiling(sim.ctx, *[int(v) for v in args.adjoint_tiling.split(",")])
+    if args.adjoint_steps_per_pass:
+        prs.prs_set_adjoint_time_blocking(sim.ctx, args.adjoint_steps_per_pass)
     print("workload", args.workload, "tiling", sim.tiling(), "steps/pass", sim.time_blocking(), flush=True)
     sim.step_n(args.steps, diag=False)
     torch.cuda.synchronize()

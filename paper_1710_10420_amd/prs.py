@@ -148,6 +148,8 @@ _decl("prs_set_adjoint_tiling", _i32, _vp, _i32, _i32, _i32)
 _decl("prs_plan_passes", _i32, _vp, _i64, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64))
 _decl("prs_get_adjoint_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _decl("prs_get_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
+_decl("prs_set_adjoint_time_blocking", _i32, _vp, _i32)
+_decl("prs_get_adjoint_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
 _decl("prs_last_error", ctypes.c_char_p)
 
@@ -161,6 +163,7 @@ EXPORTED = [
     "prs_batch_state", "prs_autotune", "prs_tuned_tiling",
     "prs_set_time_blocking", "prs_get_time_blocking", "prs_set_adjoint_tiling",
     "prs_get_adjoint_tiling", "prs_plan_passes", "prs_fill_uniform_f64",
+    "prs_set_adjoint_time_blocking", "prs_get_adjoint_time_blocking",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -281,6 +284,16 @@ def prs_get_adjoint_tiling(ctx):
     _check(_lib.prs_get_adjoint_tiling(ctx, ctypes.byref(v), ctypes.byref(r), ctypes.byref(t)),
            "prs_get_adjoint_tiling")
     return v.value, r.value, t.value
+
+
+def prs_set_adjoint_time_blocking(ctx, steps_per_pass):
+    _check(_lib.prs_set_adjoint_time_blocking(ctx, steps_per_pass), "prs_set_adjoint_time_blocking")
+
+
+def prs_get_adjoint_time_blocking(ctx):
+    v = _i32()
+    _check(_lib.prs_get_adjoint_time_blocking(ctx, ctypes.byref(v)), "prs_get_adjoint_time_blocking")
+    return v.value
 
 
 def prs_plan_passes(ctx, nsteps, with_records=True):

@@ -54,14 +54,18 @@ def test_adjoint_matches_oracle(shape, nsteps, K):
     assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
 
 
-def gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling=None):
+def gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling=None, TA=None):
+    """Adjoint with T steps per forward/recompute pass and TA (default T)
+    steps per reverse pass, both on `tiling`."""
     torch = torch_mod()
     prs = gpu_prs()
     sim = prs.Sim(gp, phi0=to_dev(phi0) if gp.precision == prs.PRS_F32 else
                   torch.from_numpy(np.asarray(phi0, np.float64).reshape(-1)).cuda())
     if tiling is not None:
         sim.set_tiling(*tiling)
+        prs.prs_set_adjoint_tiling(sim.ctx, *tiling)
     sim.set_time_blocking(T)
+    prs.prs_set_adjoint_time_blocking(sim.ctx, T if TA is None else TA)
     nb = prs.prs_adjoint_workspace_bytes(gp, nsteps, K)
     work = torch.empty(nb, dtype=torch.uint8, device="cuda")
     gphi = torch.empty_like(sim.phi_a)
@@ -100,22 +104,24 @@ def test_multi_step_adjoint_bitwise_equal_single_steps(shape, nsteps, K, tiling)
     phi0 = uniform_field(shape, 8)
     ref = gpu_adjoint_T(gp, phi0, nsteps, K, 1, tiling)
     for T in ((2, 3, 4, 6, 8) if len(shape) == 2 else (2, 3)):
-        got = gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling)
-        np.testing.assert_array_equal(got[1], ref[1], err_msg=str(T))
-        np.testing.assert_array_equal(got[2], ref[2], err_msg=str(T))
-        assert got[0] == ref[0]
-        assert got[3] == pytest.approx(ref[3], rel=1e-11), T
+        for TA in (1, T, 8 if T == 2 else 2):
+            got = gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling, TA)
+            np.testing.assert_array_equal(got[1], ref[1], err_msg=str((T, TA)))
+            np.testing.assert_array_equal(got[2], ref[2], err_msg=str((T, TA)))
+            assert got[0] == ref[0]
+            assert got[3] == pytest.approx(ref[3], rel=1e-11), (T, TA)
 
 
-def test_multi_step_adjoint_f64():
-    say("multi-step adjoint f64")
+@pytest.mark.parametrize("shape,tiling", [((130, 96), (2, 16, 1)), ((40, 36, 30), (1, 16, 2))])
+def test_multi_step_adjoint_f64(shape, tiling):
+    say("multi-step adjoint f64", shape)
     prs = gpu_prs()
-    shape = (130, 96)
-    gp = prs.make_params(shape, deta=0.25, m=1.0, W0=6.0, precision=prs.PRS_F64)
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp = prs.make_params(shape, deta=deta, m=1.0, W0=6.0, precision=prs.PRS_F64)
     phi0 = uniform_field(shape, 9)
-    ref = gpu_adjoint_T(gp, phi0, 30, 12, 1, (2, 16, 1))
-    for T in (2, 3, 4):
-        got = gpu_adjoint_T(gp, phi0, 30, 12, T, (2, 16, 1))
+    ref = gpu_adjoint_T(gp, phi0, 30, 12, 1, tiling)
+    for T in ((2, 3, 4) if len(shape) == 2 else (2,)):
+        got = gpu_adjoint_T(gp, phi0, 30, 12, T, tiling)
         np.testing.assert_array_equal(got[1], ref[1], err_msg=str(T))
         np.testing.assert_array_equal(got[2], ref[2], err_msg=str(T))
         assert got[3] == pytest.approx(ref[3], rel=1e-13), T
@@ -203,3 +209,27 @@ def test_adjoint_tiling_independent(shape):
             continue
         np.testing.assert_array_equal(host(g), ref[0])
         assert gw == pytest.approx(ref[1], rel=1e-12) and loss == ref[2]
+
+
+def test_adjoint_autotune_picks_reverse_passes():
+    """PRS_TUNE_ADJOINT chooses the reverse tiling and steps per pass
+    together; the gradient is unchanged by the choice."""
+    say("adjoint tuner")
+    prs = gpu_prs()
+    torch = torch_mod()
+    shape = (256, 192)
+    gp, _ = params_pair(shape, 0.25, m=1.0, W0=8.0)
+    phi0 = uniform_field(shape, 6)
+    ref = gpu_adjoint_T(gp, phi0, 24, 8, 1, (2, 16, 1), 1)
+    sim = prs.Sim(gp, phi0=to_dev(phi0))
+    sim.set_tiling(2, 16, 1)
+    sim.set_time_blocking(1)
+    prs.prs_autotune(sim.ctx, None, prs.PRS_TUNE_ADJOINT | prs.PRS_TUNE_FORCE)
+    TA = prs.prs_get_adjoint_time_blocking(sim.ctx)
+    assert TA in (1, 2, 4, 8)
+    nb = prs.prs_adjoint_workspace_bytes(gp, 24, 8)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    g = torch.empty_like(sim.phi_a)
+    loss, gw = prs.prs_adjoint(sim.ctx, 24, 8, work.data_ptr(), nb, g.data_ptr(), None)
+    np.testing.assert_array_equal(host(g), ref[1])
+    assert gw == pytest.approx(ref[3], rel=1e-11)
