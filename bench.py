@@ -139,7 +139,9 @@ def adjoint_leg(prs, torch, reps=3):
             "forward_hbm_frac": su * 16 / (tf / 1e3) / (HBM_PEAK_GBS * 1e9),
             "reverse_hbm_frac": su * 36 / (tb / 1e3) / (HBM_PEAK_GBS * 1e9),
             "loss": loss, "grad_W0": gw, "tiling": list(sim.tiling()),
+            "steps_per_pass": sim.time_blocking(),
             "adjoint_tiling": list(prs.prs_get_adjoint_tiling(sim.ctx)),
+            "adjoint_steps_per_pass": prs.prs_get_adjoint_time_blocking(sim.ctx),
         }
         log("adjoint", cfg["name"], "fwd %.2f ms bwd %.2f ms" % (tf, tb))
         sim.close()

@@ -198,9 +198,11 @@ prs_status prs_plan_passes(const prs_ctx* ctx, int64_t nsteps, int32_t with_reco
  * prs_set_tiling; PRS_TUNE_ADJOINT tunes both).  The forward-with-checkpoints
  * and the recomputation inside prs_adjoint_backward use the forward tiling
  * and steps per pass.  Multi-step reverse passes exist for 2D lattices with
- * T = 2, 4 and, in float32, 8 and tilings with vec 1 or 2; other settings
- * run single reverse steps.  The default is the forward's setting at
- * prs_init. */
+ * T = 2, 4 and, in float32, 8 and tilings with vec 1 or 2, and for 3D
+ * lattices with T = 2 on the tilings of the 3D multi-step passes and, in
+ * float32, T = 3 with vec 1 and ty 1 or 2; a pass runs the longest supported
+ * length up to the setting, down to single reverse steps.  The default is the
+ * forward's setting at prs_init (1 in 3D). */
 prs_status prs_set_adjoint_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
 prs_status prs_get_adjoint_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
 prs_status prs_set_adjoint_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
@@ -223,9 +225,12 @@ void prs_destroy(prs_ctx* ctx);
  *
  * Memory: (phi, phi_dot) is checkpointed every ckpt_every steps; in reverse,
  * each segment is recomputed from its checkpoint and then swept backwards.
- * All of it lives in a caller-owned device workspace of
+ * With two or more segments the recomputation of the next-older segment runs
+ * on a second stream of the context while the current one is swept, into a
+ * second segment buffer; results are the same as without the overlap.  All
+ * of it lives in a caller-owned device workspace of
  * prs_adjoint_workspace_bytes(...) bytes (256-byte aligned), about
- * (2 nsteps/K + K + 4) fields. */
+ * (2 nsteps/K + 2K + 4) fields (K + 4 with a single segment). */
 size_t prs_adjoint_workspace_bytes(const prs_params* p, int64_t nsteps, int32_t ckpt_every);
 
 /* Forward half: advances the context by nsteps (no diagnostics), storing the

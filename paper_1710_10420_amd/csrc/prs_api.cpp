@@ -202,6 +202,10 @@ struct prs_ctx {
     void* adj_work;
     size_t adj_bytes;
     double* adj_host;   // pinned: loss, G
+    // second stream and events of the backward sweep (created on first use):
+    // the recomputation of the next-older segment overlaps the reverse sweep
+    hipStream_t adj_aux;
+    hipEvent_t adj_ev[5];   // 0: forward done, 1-2: segment recomputed, 3-4: segment swept
 };
 
 namespace {
@@ -522,6 +526,10 @@ void prs_destroy(prs_ctx* c)
     if (!c) return;
     if (c->hrec) (void)hipHostFree(c->hrec);
     if (c->adj_host) (void)hipHostFree(c->adj_host);
+    if (c->adj_aux) {
+        (void)hipStreamDestroy(c->adj_aux);
+        for (hipEvent_t e : c->adj_ev) (void)hipEventDestroy(e);
+    }
     delete c;
 }
 
@@ -588,7 +596,7 @@ namespace {
 struct AdjLayout {
     size_t fb;
     int64_t nseg, K;
-    size_t ck_phi, ck_pi, seg, pis, pis2, mu, mu2, w0, w1, gacc, lpart, scal, total;
+    size_t ck_phi, ck_pi, seg, seg2, pis, pis2, mu, mu2, w0, w1, gacc, lpart, scal, total;
 };
 
 constexpr int kSeedBlocks = 1024;
@@ -603,6 +611,9 @@ AdjLayout adj_layout(const prs_params& p, int64_t nsteps, int64_t K, int64_t par
     L.ck_phi = o; o += L.fb * (size_t)L.nseg;
     L.ck_pi = o; o += L.fb * (size_t)L.nseg;
     L.seg = o; o += L.fb * (size_t)(K > 1 ? K - 1 : 0);
+    // with two or more segments a second segment buffer lets the next
+    // segment's recomputation run while this one is swept
+    L.seg2 = o; o += L.nseg > 1 ? L.fb * (size_t)(K > 1 ? K - 1 : 0) : 0;
     L.pis = o; o += L.fb;
     L.pis2 = o; o += L.fb;
     L.mu = o; o += L.fb;
@@ -738,11 +749,13 @@ prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, v
 namespace {
 
 // Longest pass of at most min(T, left) steps that the adjoint's multi-step
-// kernels support with tiling t and at most `cap` wave tiles (1: single steps).
-int adj_pass_len(const Geometry& g, const Tiling& t, int64_t cap, int T, int64_t left)
+// kernels (the reverse sweep's, else the recomputation's) support with tiling
+// t and at most `cap` wave tiles (1: single steps).
+int adj_pass_len(const Geometry& g, const Tiling& t, int64_t cap, int T, int64_t left, bool reverse)
 {
     int L = (int)std::min<int64_t>(T, left);
-    while (L > 1 && !(tba_supported(g, t, L) && tb_tiles(g, t, L) <= cap)) --L;
+    while (L > 1 && !((reverse ? tba_supported(g, t, L) : tb_all_supported(g, t, L)) && tb_tiles(g, t, L) <= cap))
+        --L;
     return std::max(L, 1);
 }
 
@@ -769,43 +782,54 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     char* wnxt = at<char>(work, L.w1);
     char* pis = at<char>(work, L.pis);
     char* pis2 = at<char>(work, L.pis2);
-    auto seg = [&](int64_t k) { return at<char>(work, L.seg + L.fb * (size_t)(k - 1)); };
-    for (int64_t sg = L.nseg - 1; sg >= 0; --sg) {
+    // phi^{ns+k} of segment sg (k = 1 .. len-1) in its segment buffer
+    auto seg_at = [&](int64_t sg, int64_t k) {
+        return at<char>(work, ((sg & 1) ? L.seg2 : L.seg) + L.fb * (size_t)(k - 1));
+    };
+    auto seg_len = [&](int64_t sg) { return std::min<int64_t>(L.K, c->adj_nsteps - sg * L.K); };
+
+    // recompute phi^{ns+1 .. ns+len-1} of segment sg from its checkpoint on
+    // stream s: multi-step passes store every step's field; phi_dot goes to
+    // the scratch fields
+    auto recompute = [&](int64_t sg, hipStream_t s) -> prs_status {
         const int64_t ns = n0 + sg * L.K;
-        const int64_t len = std::min<int64_t>(L.K, c->adj_nsteps - sg * L.K);
-        char* ckphi = at<char>(work, L.ck_phi + L.fb * sg);
-        char* ckpi = at<char>(work, L.ck_pi + L.fb * sg);
-        auto phi_at = [&](int64_t j) -> const void* { return j == 0 ? ckphi : seg(j); };   // phi^{ns+j}
-        // recompute phi^{ns+1 .. ns+len-1} from the checkpoint: multi-step
-        // passes store every step's field; phi_dot goes to the scratch fields
-        const void* prev = ckphi;
+        const int64_t len = seg_len(sg);
+        const void* prev = at<char>(work, L.ck_phi + L.fb * sg);
+        const void* ckpi = at<char>(work, L.ck_pi + L.fb * sg);
         const void* pprev = ckpi;
         for (int64_t k = 0; k < len - 1;) {
-            const int Lp = adj_pass_len(c->geo, c->til, c->partial_cap, T, len - 1 - k);
+            const int Lp = adj_pass_len(c->geo, c->til, c->partial_cap, T, len - 1 - k, false);
             if (Lp > 1) {
                 void* outs[kMaxPassSteps];
                 StepCoef64 kk[kMaxPassSteps];
                 for (int i = 0; i < Lp; ++i) {
-                    outs[i] = seg(k + 1 + i);
+                    outs[i] = seg_at(sg, k + 1 + i);
                     kk[i] = coef_for(c, ns + k + i);
                 }
                 void* pout = pprev == pis ? pis2 : pis;
-                HIP_TRY(launch_tb_all(Lp, c->geo, c->til, prev, outs, pprev, pout, kk, c->stream),
-                        "recompute launch");
+                HIP_TRY(launch_tb_all(Lp, c->geo, c->til, prev, outs, pprev, pout, kk, s), "recompute launch");
                 pprev = pout;
             } else {
                 void* pout = pprev == ckpi ? pis : const_cast<void*>(pprev);
-                HIP_TRY(launch_step(c->geo, c->til, prev, seg(k + 1), pprev, pout, coef_for(c, ns + k), true, false,
-                                    nullptr, DiagCoef{}, c->stream),
+                HIP_TRY(launch_step(c->geo, c->til, prev, seg_at(sg, k + 1), pprev, pout, coef_for(c, ns + k), true,
+                                    false, nullptr, DiagCoef{}, s),
                         "recompute launch");
                 pprev = pout;
             }
             k += Lp;
-            prev = seg(k);
+            prev = seg_at(sg, k);
         }
-        // reverse sweep over steps ns+len-1 .. ns
+        return PRS_OK;
+    };
+
+    // reverse sweep over steps ns+len-1 .. ns of segment sg on the context's stream
+    auto sweep = [&](int64_t sg) -> prs_status {
+        const int64_t ns = n0 + sg * L.K;
+        const int64_t len = seg_len(sg);
+        char* ckphi = at<char>(work, L.ck_phi + L.fb * sg);
+        auto phi_at = [&](int64_t j) -> const void* { return j == 0 ? ckphi : seg_at(sg, j); };   // phi^{ns+j}
         for (int64_t k = len - 1; k >= 0;) {
-            const int Lp = adj_pass_len(c->geo, c->adj_til, c->partial_cap, TA, k + 1);
+            const int Lp = adj_pass_len(c->geo, c->adj_til, c->partial_cap, TA, k + 1, true);
             if (Lp > 1) {
                 const void* phis[kMaxPassSteps];
                 AdjCoef64 cc[kMaxPassSteps];
@@ -824,6 +848,38 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
             std::swap(wcur, wnxt);
             k -= Lp;
         }
+        return PRS_OK;
+    };
+
+    // Segments newest first.  With two segment buffers the recomputation of
+    // segment sg-1 runs on a second stream while segment sg is swept: it
+    // waits for the sweep of sg+1 (the last reader of its buffer), and the
+    // sweep of sg waits for its own recomputation.  The results do not depend
+    // on the overlap (each kernel's inputs are complete when it starts).
+    const bool overlap = L.nseg > 1;
+    if (overlap && !c->adj_aux) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->adj_aux, hipStreamNonBlocking), "stream create");
+        for (hipEvent_t& e : c->adj_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
+    }
+    hipStream_t rs = overlap ? c->adj_aux : c->stream;
+    if (overlap) {
+        HIP_TRY(hipEventRecord(c->adj_ev[0], c->stream), "event record");
+        HIP_TRY(hipStreamWaitEvent(rs, c->adj_ev[0], 0), "stream wait");
+    }
+    prs_status st = recompute(L.nseg - 1, rs);
+    if (st != PRS_OK) return st;
+    if (overlap) HIP_TRY(hipEventRecord(c->adj_ev[1 + ((L.nseg - 1) & 1)], rs), "event record");
+    for (int64_t sg = L.nseg - 1; sg >= 0; --sg) {
+        if (overlap && sg >= 1) {
+            if (sg + 1 < L.nseg) HIP_TRY(hipStreamWaitEvent(rs, c->adj_ev[3 + ((sg + 1) & 1)], 0), "stream wait");
+            st = recompute(sg - 1, rs);
+            if (st != PRS_OK) return st;
+            HIP_TRY(hipEventRecord(c->adj_ev[1 + ((sg - 1) & 1)], rs), "event record");
+        }
+        if (overlap) HIP_TRY(hipStreamWaitEvent(c->stream, c->adj_ev[1 + (sg & 1)], 0), "stream wait");
+        st = sweep(sg);
+        if (st != PRS_OK) return st;
+        if (overlap) HIP_TRY(hipEventRecord(c->adj_ev[3 + (sg & 1)], c->stream), "event record");
     }
     if (grad_phi0)
         HIP_TRY(hipMemcpyAsync(grad_phi0, mu, bytes, hipMemcpyDeviceToDevice, c->stream), "gradient copy");
@@ -1585,9 +1641,9 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     Tiling best = c->adj_til;
     int best_T = 1;
     double best_t = 1e300;
-    // single reverse steps for every tiling; multi-step reverse passes (2D)
-    // for the tilings and lengths that have kernels
-    for (int T : {1, 2, 4, 8}) {
+    // single reverse steps for every tiling; multi-step reverse passes for
+    // the tilings and lengths that have kernels
+    for (int T : {1, 2, 3, 4, 8}) {
         for (const Tiling& t : cand) {
             if (e != hipSuccess) break;
             if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;

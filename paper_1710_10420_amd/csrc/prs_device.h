@@ -1176,7 +1176,8 @@ __device__ __forceinline__ void tba_iter(const TBAArgs<T, R>& A, const TBLane& L
             out_w[j] = fmar(A.cw[k - 1], mu_new, A.a[k - 1] * w);
             g += (double)(w * (p * q));
         }
-        if (own_row && L.soff != kPastRow) gs[k - 1] += g;
+        // own_row is wave-uniform; lanes outside the owned columns add g * 0
+        if (own_row) gs[k - 1] = fma(g, L.soff != kPastRow ? 1.0 : 0.0, gs[k - 1]);
         if (k < T) {
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
@@ -1656,7 +1657,8 @@ __device__ __forceinline__ void tba3_iter(const TBA3Args<T, R>& A, const TB3Lane
                 out_w[j] = fmar(A.cw[k - 1], mu_new, A.a[k - 1] * w);
                 gr += (double)(w * (p * q));
             }
-            if (r >= T && r < T + TY && r - T < L.yown) g += gr;
+            // owned rows only (a wave-uniform factor: no per-lane select)
+            if (r >= T && r < T + TY) g = fma(gr, r - T < L.yown ? 1.0 : 0.0, g);
             if (k < T) {
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) {
@@ -1669,7 +1671,7 @@ __device__ __forceinline__ void tba3_iter(const TBA3Args<T, R>& A, const TB3Lane
                 buf_store<VEC>(A.mu_out + obase, sb, so, out_mu);
             }
         }
-        if (own_plane && L.own_lane) gs[k - 1] += g;
+        if (own_plane) gs[k - 1] = fma(g, L.own_lane ? 1.0 : 0.0, gs[k - 1]);
     }
 }
 
@@ -2216,11 +2218,13 @@ hipError_t launch_tb3d_r(int T, const Geometry& g, const Tiling& t, const void* 
     return hipErrorInvalidValue;
 }
 
-// 3D multi-step passes of the adjoint: T = 2 on the 3D pass tilings.
+// 3D multi-step passes of the adjoint: the recomputation on every 3D pass
+// tiling (T = 2, 3); the reverse sweep with T = 2 on those tilings and, in
+// float32, T = 3 with vec 1 and 4 rows (its register rows grow with T).
 template <typename R>
 constexpr bool tba3_combo_ok(int vec, int T, int TY)
 {
-    return T == 2 && tb3_combo_ok<R>(vec, T, TY);
+    return (T == 2 && tb3_combo_ok<R>(vec, T, TY)) || (sizeof(R) == 4 && T == 3 && vec == 1 && TY == 4);
 }
 
 template <typename R, int VEC, int T, int TY>
@@ -2293,15 +2297,18 @@ hipError_t launch_tb3_all_r(int T, const Geometry& g, const Tiling& t, const voi
                             const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
 {
     const int TY = tb3_rows(t.ty);
-    if (!tba3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
+    if (!tb3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
 #define PRS_TB3ALL(V, TT, YY)                                                                     \
     if (t.vec == V && T == TT && TY == YY) {                                                       \
-        if constexpr (tba3_combo_ok<R>(V, TT, YY))                                                 \
+        if constexpr (tb3_combo_ok<R>(V, TT, YY))                                                  \
             return launch_tb3_all_t<R, V, TT, YY>(g, t, phi_in, phi_lv, pi_in, pi_out, k, s);      \
     }
     PRS_TB3ALL(1, 2, 4)
     PRS_TB3ALL(1, 2, 8)
     PRS_TB3ALL(2, 2, 4)
+    PRS_TB3ALL(1, 3, 4)
+    PRS_TB3ALL(1, 3, 8)
+    PRS_TB3ALL(2, 3, 4)
 #undef PRS_TB3ALL
     return hipErrorInvalidValue;
 }
@@ -2321,6 +2328,7 @@ hipError_t launch_tba3_r(int T, const Geometry& g, const Tiling& t, const void* 
     PRS_TBA3(1, 2, 4)
     PRS_TBA3(1, 2, 8)
     PRS_TBA3(2, 2, 4)
+    PRS_TBA3(1, 3, 4)
 #undef PRS_TBA3
     return hipErrorInvalidValue;
 }

@@ -112,14 +112,17 @@ using AdjCoef64 = AdjCoefT<double>;
 hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
                           const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s);
 
-// Multi-step passes of the adjoint (2D: T = 2, 4, and 8 in float32, vec 1
-// or 2, ty 1; 3D: T = 2 on the tilings of the 3D two-step pass).  launch_tb_all: T forward steps from (phi_in, pi_in) storing
+// Multi-step passes of the adjoint.  tb_all_supported: the recomputation
+// (2D: T = 2, 4, and 8 in float32, vec 1 or 2, ty 1; 3D: as the forward
+// passes); tba_supported: the reverse sweep (2D as the recomputation; 3D: T = 2
+// on the 3D pass tilings and, in float32, T = 3 with vec 1, 4 rows).  launch_tb_all: T forward steps from (phi_in, pi_in) storing
 // phi^{n+k} to phi_lv[k-1] for k = 1 .. T and phi_dot^{n+T-1/2} to pi_out
 // (!= pi_in).  launch_tba: T reverse steps m, m-1, .. m-T+1 (coefficients
 // c[k-1] and field phi[k-1] = phi^{m-k+1} for level k) from (w_in, mu_in) to
 // (w_out, mu_out), both pairs distinct; adds the pass's dL/dV0 to
 // gacc[wave tile] (tb_tiles(g, t, T) accumulators).
 bool tba_supported(const Geometry& g, const Tiling& t, int T);
+bool tb_all_supported(const Geometry& g, const Tiling& t, int T);
 hipError_t launch_tb_all(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
                          const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
 hipError_t launch_tba(int T, const Geometry& g, const Tiling& t, const void* w_in, void* w_out, const void* mu_in,

@@ -466,10 +466,16 @@ bool tba_supported(const Geometry& g, const Tiling& t, int T)
     return g.f64 ? tba_combo_ok<double>(t.vec, T) : tba_combo_ok<float>(t.vec, T);
 }
 
+bool tb_all_supported(const Geometry& g, const Tiling& t, int T)
+{
+    if (g.ndim == 3) return tb_pass_supported(g, t, T);
+    return tba_supported(g, t, T);
+}
+
 hipError_t launch_tb_all(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
                          const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
 {
-    if (!tba_supported(g, t, T)) return hipErrorInvalidValue;
+    if (!tb_all_supported(g, t, T)) return hipErrorInvalidValue;
     return g.f64 ? launch_tb_all_f64(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s)
                  : launch_tb_all_f32(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s);
 }

@@ -29,7 +29,9 @@ def main():
     ap.add_argument("--workload", default="2d8192", choices=sorted(WORKLOADS))
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--copies", type=int, default=10)
-    ap.add_argument("--adjoint", action="store_true", help="also run a 64-step adjoint (K = 64)")
+    ap.add_argument("--adjoint", action="store_true", help="also run an adjoint")
+    ap.add_argument("--adjoint-steps", type=int, default=64, help="steps of the adjoint run")
+    ap.add_argument("--ckpt", type=int, default=64, help="checkpoint interval of the adjoint run")
     ap.add_argument("--tiling", default=None, help="vec,rows,ty (default: the library default)")
     ap.add_argument("--steps-per-pass", type=int, default=None, help="steps per forward pass")
     ap.add_argument("--adjoint-tiling", default=None, help="vec,rows,ty of the reverse sweep")
@@ -50,10 +52,10 @@ def main():
     sim.step_n(args.steps, diag=False)
     torch.cuda.synchronize()
     if args.adjoint:
-        nb = prs.prs_adjoint_workspace_bytes(p, 64, 64)
+        nb = prs.prs_adjoint_workspace_bytes(p, args.adjoint_steps, args.ckpt)
         work = torch.empty(nb, dtype=torch.uint8, device="cuda")
         g = torch.empty_like(sim.phi_a)
-        prs.prs_adjoint(sim.ctx, 64, 64, work.data_ptr(), nb, g.data_ptr(), None)
+        prs.prs_adjoint(sim.ctx, args.adjoint_steps, args.ckpt, work.data_ptr(), nb, g.data_ptr(), None)
         torch.cuda.synchronize()
     src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)

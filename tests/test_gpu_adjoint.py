@@ -92,6 +92,7 @@ def test_adjoint_checkpoint_interval_bitwise():
 @pytest.mark.parametrize("shape,nsteps,K,tiling", [
     ((200, 130), 40, 16, (1, 16, 1)), ((264, 200), 37, 10, (2, 17, 1)), ((256, 256), 64, 64, (2, 64, 1)),
     ((130, 9), 23, 7, (2, 8, 1)), ((40, 36, 30), 21, 8, (1, 16, 4)), ((64, 9, 33), 14, 5, (2, 16, 2)),
+    ((48, 10, 21), 19, 6, (1, 8, 2)),
 ])
 def test_multi_step_adjoint_bitwise_equal_single_steps(shape, nsteps, K, tiling):
     """Multi-step passes in the forward-with-checkpoints, the recomputation
@@ -104,7 +105,7 @@ def test_multi_step_adjoint_bitwise_equal_single_steps(shape, nsteps, K, tiling)
     phi0 = uniform_field(shape, 8)
     ref = gpu_adjoint_T(gp, phi0, nsteps, K, 1, tiling)
     for T in ((2, 3, 4, 6, 8) if len(shape) == 2 else (2, 3)):
-        for TA in (1, T, 8 if T == 2 else 2):
+        for TA in (1, T, (8 if len(shape) == 2 else 3) if T == 2 else 2):
             got = gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling, TA)
             np.testing.assert_array_equal(got[1], ref[1], err_msg=str((T, TA)))
             np.testing.assert_array_equal(got[2], ref[2], err_msg=str((T, TA)))
@@ -226,7 +227,7 @@ def test_adjoint_autotune_picks_reverse_passes():
     sim.set_time_blocking(1)
     prs.prs_autotune(sim.ctx, None, prs.PRS_TUNE_ADJOINT | prs.PRS_TUNE_FORCE)
     TA = prs.prs_get_adjoint_time_blocking(sim.ctx)
-    assert TA in (1, 2, 4, 8)
+    assert TA in (1, 2, 3, 4, 8)
     nb = prs.prs_adjoint_workspace_bytes(gp, 24, 8)
     work = torch.empty(nb, dtype=torch.uint8, device="cuda")
     g = torch.empty_like(sim.phi_a)
