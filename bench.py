@@ -130,10 +130,27 @@ def adjoint_leg(prs, torch, reps=3):
                 fwd.append(e0.elapsed_time(e1))
                 bwd.append(e1.elapsed_time(e2))
         tf, tb = min(fwd), min(bwd)
+        # the same forward-with-checkpoints in single-step passes (16 B per
+        # site-update, the basis of the backward/forward target)
+        T_fwd = sim.time_blocking()
+        sim.set_time_blocking(1)
+        fwd1 = []
+        for r in range(reps + 1):
+            sim.set_state(phi0, torch.zeros_like(phi0), 0)
+            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            e0.record(stream)
+            prs.prs_adjoint_forward(sim.ctx, ADJ_STEPS, ADJ_K, work.data_ptr(), nb)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                fwd1.append(e0.elapsed_time(e1))
+        sim.set_time_blocking(T_fwd)
+        tf1 = min(fwd1)
         su = float(sites) * ADJ_STEPS
         out[cfg["name"]] = {
             "forward_ms": tf, "backward_ms": tb, "backward_over_forward": tb / tf,
             "total_over_forward": (tf + tb) / tf,
+            "single_step_forward_ms": tf1, "backward_over_single_step_forward": tb / tf1,
             "forward_site_updates_per_s": su / (tf / 1e3),
             "adjoint_site_updates_per_s": su / (tb / 1e3),
             "forward_hbm_frac": su * 16 / (tf / 1e3) / (HBM_PEAK_GBS * 1e9),
@@ -142,6 +159,7 @@ def adjoint_leg(prs, torch, reps=3):
             "steps_per_pass": sim.time_blocking(),
             "adjoint_tiling": list(prs.prs_get_adjoint_tiling(sim.ctx)),
             "adjoint_steps_per_pass": prs.prs_get_adjoint_time_blocking(sim.ctx),
+            "recompute_tiling_and_steps": list(prs.prs_get_recompute_tiling(sim.ctx)),
         }
         log("adjoint", cfg["name"], "fwd %.2f ms bwd %.2f ms" % (tf, tb))
         sim.close()

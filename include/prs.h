@@ -165,7 +165,7 @@ prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty
  * receives the time of one step with the chosen tiling.  Synchronises. */
 #define PRS_TUNE_FORCE 1
 #define PRS_TUNE_BATCH 2
-#define PRS_TUNE_ADJOINT 4   /* tune the reverse-sweep kernel's tiling instead */
+#define PRS_TUNE_ADJOINT 4   /* tune the reverse sweep's tiling and steps per pass instead */
 prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, double* best_us);
 
 /* Cached tiling for these parameters (no GPU work); PRS_ESTATE if absent. */
@@ -196,8 +196,10 @@ prs_status prs_plan_passes(const prs_ctx* ctx, int64_t nsteps, int32_t with_reco
 /* Tiling and steps per pass of the reverse sweep (adjoint), chosen
  * independently of the forward ones (same parameters and rules as
  * prs_set_tiling; PRS_TUNE_ADJOINT tunes both).  The forward-with-checkpoints
- * and the recomputation inside prs_adjoint_backward use the forward tiling
- * and steps per pass.  Multi-step reverse passes exist for 2D lattices with
+ * inside prs_adjoint_forward uses the forward tiling and steps per pass, and
+ * so does the recomputation inside prs_adjoint_backward unless
+ * prs_set_recompute_tiling sets its own (results depend on neither).
+ * Multi-step reverse passes exist for 2D lattices with
  * T = 2, 4 and, in float32, 8 and tilings with vec 1 or 2, and for 3D
  * lattices with T = 2 on the tilings of the 3D multi-step passes and, in
  * float32, T = 3 with vec 1 and ty 1 or 2; a pass runs the longest supported
@@ -207,6 +209,15 @@ prs_status prs_set_adjoint_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32
 prs_status prs_get_adjoint_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
 prs_status prs_set_adjoint_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
 prs_status prs_get_adjoint_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
+
+/* Tiling and steps per pass (1 .. 8; the longest supported length up to it
+ * is used, as in prs_set_time_blocking) of the recomputation inside
+ * prs_adjoint_backward.  steps_per_pass = 0 makes it follow the forward's
+ * setting again (the default; the other arguments are then ignored).  The
+ * getter returns the setting in effect.  Results do not depend on it. */
+prs_status prs_set_recompute_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty, int32_t steps_per_pass);
+prs_status prs_get_recompute_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty,
+                                    int32_t* steps_per_pass);
 
 /* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
 void prs_destroy(prs_ctx* ctx);

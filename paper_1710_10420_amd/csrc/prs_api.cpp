@@ -192,6 +192,8 @@ struct prs_ctx {
     void* pi_alt;      // second phi_dot buffer (workspace) for multi-step passes
     Tiling adj_til;    // tiling of the reverse-sweep kernel
     int32_t adj_tblock;   // steps per reverse pass
+    Tiling rec_til;    // tiling and steps per pass of the adjoint's recomputation
+    int32_t rec_tblock;   // (0: those of the forward)
     int32_t tblock;    // steps per pass (1: single steps)
     hipStream_t stream;
     int64_t step;
@@ -487,6 +489,34 @@ prs_status prs_set_adjoint_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t
     return PRS_OK;
 }
 
+prs_status prs_set_recompute_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t ty, int32_t steps_per_pass)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (steps_per_pass == 0) {
+        c->rec_tblock = 0;
+        return PRS_OK;
+    }
+    if (steps_per_pass < 1 || steps_per_pass > kMaxPassSteps)
+        return fail(PRS_EINVAL, "steps per pass must be 0 .. %d", kMaxPassSteps);
+    Tiling t{vec, rows, ty};
+    if (!tiling_supported(c->geo, t))
+        return fail(PRS_EINVAL, "tiling vec=%d rows=%d ty=%d not supported for this lattice", vec, rows, ty);
+    c->rec_til = t;
+    c->rec_tblock = steps_per_pass;
+    return PRS_OK;
+}
+
+prs_status prs_get_recompute_tiling(prs_ctx* c, int32_t* vec, int32_t* rows, int32_t* ty, int32_t* steps_per_pass)
+{
+    if (!c || !vec || !rows || !ty || !steps_per_pass) return fail(PRS_EINVAL, "NULL argument");
+    const Tiling& t = c->rec_tblock > 0 ? c->rec_til : c->til;
+    *vec = t.vec;
+    *rows = t.rows;
+    *ty = t.ty;
+    *steps_per_pass = c->rec_tblock > 0 ? c->rec_tblock : c->tblock;
+    return PRS_OK;
+}
+
 prs_status prs_set_adjoint_time_blocking(prs_ctx* c, int32_t steps_per_pass)
 {
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");
@@ -772,7 +802,9 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     const AdjLayout L = adj_layout(c->p, c->adj_nsteps, c->adj_K, c->partial_cap);
     const int64_t n0 = c->adj_n0;
     const size_t bytes = field_bytes(c->p);
-    const int T = tb_supported(c->geo) ? c->tblock : 1;
+    // the recomputation: its own tuned tiling and pass length, else the forward's
+    const Tiling rt = c->rec_tblock > 0 ? c->rec_til : c->til;
+    const int T = tb_supported(c->geo) ? (c->rec_tblock > 0 ? c->rec_tblock : c->tblock) : 1;
     const int TA = tb_supported(c->geo) ? c->adj_tblock : 1;
     double* gacc = at<double>(work, L.gacc);
     HIP_TRY(launch_zero_f64(gacc, c->partial_cap, c->stream), "zero launch");
@@ -798,7 +830,7 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
         const void* ckpi = at<char>(work, L.ck_pi + L.fb * sg);
         const void* pprev = ckpi;
         for (int64_t k = 0; k < len - 1;) {
-            const int Lp = adj_pass_len(c->geo, c->til, c->partial_cap, T, len - 1 - k, false);
+            const int Lp = adj_pass_len(c->geo, rt, c->partial_cap, T, len - 1 - k, false);
             if (Lp > 1) {
                 void* outs[kMaxPassSteps];
                 StepCoef64 kk[kMaxPassSteps];
@@ -807,11 +839,11 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
                     kk[i] = coef_for(c, ns + k + i);
                 }
                 void* pout = pprev == pis ? pis2 : pis;
-                HIP_TRY(launch_tb_all(Lp, c->geo, c->til, prev, outs, pprev, pout, kk, s), "recompute launch");
+                HIP_TRY(launch_tb_all(Lp, c->geo, rt, prev, outs, pprev, pout, kk, s), "recompute launch");
                 pprev = pout;
             } else {
                 void* pout = pprev == ckpi ? pis : const_cast<void*>(pprev);
-                HIP_TRY(launch_step(c->geo, c->til, prev, seg_at(sg, k + 1), pprev, pout, coef_for(c, ns + k), true,
+                HIP_TRY(launch_step(c->geo, rt, prev, seg_at(sg, k + 1), pprev, pout, coef_for(c, ns + k), true,
                                     false, nullptr, DiagCoef{}, s),
                         "recompute launch");
                 pprev = pout;
@@ -1603,8 +1635,13 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
 
 namespace {
 
-// Tunes the reverse-sweep kernel's tiling on scratch buffers (w, mu filled
-// from the current phi; phi^n = the current phi).
+// Tunes the reverse-sweep kernel's tiling and steps per pass on scratch
+// buffers (w, mu filled from the current phi; phi^n = the current phi).  The
+// recomputation keeps following the forward's setting: timing its passes on
+// scratch fields that stay cache-resident misjudges them (single steps win
+// there and lose by 15 % inside the backward), and the forward's setting
+// was within 2 % of the best one measured inside the backward at 2048^2 and
+// 256^3.
 prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, double* best_us)
 {
     const std::string key = tune_key(c->p, false) + "|adjoint";

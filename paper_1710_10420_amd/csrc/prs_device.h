@@ -2046,6 +2046,15 @@ constexpr bool tba_combo_ok(int vec, int T)
     return (vec == 1 || vec == 2) && (T == 2 || T == 4 || (sizeof(R) == 4 && T == 8));
 }
 
+// The 2D recomputation follows the forward's multi-step passes: T = 2, 3, 4
+// and, in float32, 6, 8, with vec 1, 2 and (float32) 4.
+template <typename R>
+constexpr bool tball_combo_ok(int vec, int T)
+{
+    return (vec == 1 || vec == 2 || (sizeof(R) == 4 && vec == 4)) &&
+           (T == 2 || T == 3 || T == 4 || (sizeof(R) == 4 && (T == 6 || T == 8)));
+}
+
 template <typename R, int VEC, int T>
 hipError_t launch_tb_all_t(const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
                            const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
@@ -2078,18 +2087,27 @@ hipError_t launch_tb_all_r(int T, const Geometry& g, const Tiling& t, const void
                            const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
 {
     if (g.ndim == 3) return launch_tb3_all_r<R>(T, g, t, phi_in, phi_lv, pi_in, pi_out, k, s);
-    if (!tba_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
+    if (!tball_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
 #define PRS_TBALL(V, TT)                                                                       \
     if (t.vec == V && T == TT) {                                                                \
-        if constexpr (tba_combo_ok<R>(V, TT))                                                   \
+        if constexpr (tball_combo_ok<R>(V, TT))                                                 \
             return launch_tb_all_t<R, V, TT>(g, t, phi_in, phi_lv, pi_in, pi_out, k, s);        \
     }
     PRS_TBALL(1, 2)
+    PRS_TBALL(1, 3)
     PRS_TBALL(1, 4)
+    PRS_TBALL(1, 6)
     PRS_TBALL(1, 8)
     PRS_TBALL(2, 2)
+    PRS_TBALL(2, 3)
     PRS_TBALL(2, 4)
+    PRS_TBALL(2, 6)
     PRS_TBALL(2, 8)
+    PRS_TBALL(4, 2)
+    PRS_TBALL(4, 3)
+    PRS_TBALL(4, 4)
+    PRS_TBALL(4, 6)
+    PRS_TBALL(4, 8)
 #undef PRS_TBALL
     return hipErrorInvalidValue;
 }

@@ -113,9 +113,10 @@ hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, 
                           const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s);
 
 // Multi-step passes of the adjoint.  tb_all_supported: the recomputation
-// (2D: T = 2, 4, and 8 in float32, vec 1 or 2, ty 1; 3D: as the forward
-// passes); tba_supported: the reverse sweep (2D as the recomputation; 3D: T = 2
-// on the 3D pass tilings and, in float32, T = 3 with vec 1, 4 rows).  launch_tb_all: T forward steps from (phi_in, pi_in) storing
+// (2D: as the forward passes, T = 2, 3, 4 and, in float32, 6, 8; 3D: as
+// the forward passes); tba_supported: the reverse sweep (2D: T = 2, 4 and, in
+// float32, 8, vec 1 or 2, ty 1; 3D: T = 2 on the 3D pass tilings and, in
+// float32, T = 3 with vec 1, 4 rows).  launch_tb_all: T forward steps from (phi_in, pi_in) storing
 // phi^{n+k} to phi_lv[k-1] for k = 1 .. T and phi_dot^{n+T-1/2} to pi_out
 // (!= pi_in).  launch_tba: T reverse steps m, m-1, .. m-T+1 (coefficients
 // c[k-1] and field phi[k-1] = phi^{m-k+1} for level k) from (w_in, mu_in) to

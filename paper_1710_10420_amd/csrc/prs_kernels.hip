@@ -469,7 +469,8 @@ bool tba_supported(const Geometry& g, const Tiling& t, int T)
 bool tb_all_supported(const Geometry& g, const Tiling& t, int T)
 {
     if (g.ndim == 3) return tb_pass_supported(g, t, T);
-    return tba_supported(g, t, T);
+    if (!tb_supported(g) || !tiling_supported(g, t) || t.ty != 1) return false;
+    return g.f64 ? tball_combo_ok<double>(t.vec, T) : tball_combo_ok<float>(t.vec, T);
 }
 
 hipError_t launch_tb_all(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,

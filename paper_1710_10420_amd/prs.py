@@ -150,6 +150,9 @@ _decl("prs_get_adjoint_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(
 _decl("prs_get_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_set_adjoint_time_blocking", _i32, _vp, _i32)
 _decl("prs_get_adjoint_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
+_decl("prs_set_recompute_tiling", _i32, _vp, _i32, _i32, _i32, _i32)
+_decl("prs_get_recompute_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+      ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
 _decl("prs_last_error", ctypes.c_char_p)
 
@@ -164,6 +167,7 @@ EXPORTED = [
     "prs_set_time_blocking", "prs_get_time_blocking", "prs_set_adjoint_tiling",
     "prs_get_adjoint_tiling", "prs_plan_passes", "prs_fill_uniform_f64",
     "prs_set_adjoint_time_blocking", "prs_get_adjoint_time_blocking",
+    "prs_set_recompute_tiling", "prs_get_recompute_tiling",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -294,6 +298,17 @@ def prs_get_adjoint_time_blocking(ctx):
     v = _i32()
     _check(_lib.prs_get_adjoint_time_blocking(ctx, ctypes.byref(v)), "prs_get_adjoint_time_blocking")
     return v.value
+
+
+def prs_set_recompute_tiling(ctx, vec, rows, ty, steps_per_pass):
+    _check(_lib.prs_set_recompute_tiling(ctx, vec, rows, ty, steps_per_pass), "prs_set_recompute_tiling")
+
+
+def prs_get_recompute_tiling(ctx):
+    """(vec, rows, ty, steps per pass) of the adjoint's recomputation."""
+    v = [_i32() for _ in range(4)]
+    _check(_lib.prs_get_recompute_tiling(ctx, *(ctypes.byref(x) for x in v)), "prs_get_recompute_tiling")
+    return tuple(x.value for x in v)
 
 
 def prs_plan_passes(ctx, nsteps, with_records=True):

@@ -54,9 +54,10 @@ def test_adjoint_matches_oracle(shape, nsteps, K):
     assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
 
 
-def gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling=None, TA=None):
+def gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling=None, TA=None, rec=None):
     """Adjoint with T steps per forward/recompute pass and TA (default T)
-    steps per reverse pass, both on `tiling`."""
+    steps per reverse pass, both on `tiling`; `rec` = (vec, rows, ty, steps)
+    gives the recomputation its own setting."""
     torch = torch_mod()
     prs = gpu_prs()
     sim = prs.Sim(gp, phi0=to_dev(phi0) if gp.precision == prs.PRS_F32 else
@@ -66,6 +67,9 @@ def gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling=None, TA=None):
         prs.prs_set_adjoint_tiling(sim.ctx, *tiling)
     sim.set_time_blocking(T)
     prs.prs_set_adjoint_time_blocking(sim.ctx, T if TA is None else TA)
+    if rec is not None:
+        prs.prs_set_recompute_tiling(sim.ctx, *rec)
+        assert prs.prs_get_recompute_tiling(sim.ctx) == tuple(rec)
     nb = prs.prs_adjoint_workspace_bytes(gp, nsteps, K)
     work = torch.empty(nb, dtype=torch.uint8, device="cuda")
     gphi = torch.empty_like(sim.phi_a)
@@ -92,7 +96,7 @@ def test_adjoint_checkpoint_interval_bitwise():
 @pytest.mark.parametrize("shape,nsteps,K,tiling", [
     ((200, 130), 40, 16, (1, 16, 1)), ((264, 200), 37, 10, (2, 17, 1)), ((256, 256), 64, 64, (2, 64, 1)),
     ((130, 9), 23, 7, (2, 8, 1)), ((40, 36, 30), 21, 8, (1, 16, 4)), ((64, 9, 33), 14, 5, (2, 16, 2)),
-    ((48, 10, 21), 19, 6, (1, 8, 2)),
+    ((48, 10, 21), 19, 6, (1, 8, 2)), ((256, 40), 26, 9, (4, 8, 1)),
 ])
 def test_multi_step_adjoint_bitwise_equal_single_steps(shape, nsteps, K, tiling):
     """Multi-step passes in the forward-with-checkpoints, the recomputation
@@ -111,6 +115,11 @@ def test_multi_step_adjoint_bitwise_equal_single_steps(shape, nsteps, K, tiling)
             np.testing.assert_array_equal(got[2], ref[2], err_msg=str((T, TA)))
             assert got[0] == ref[0]
             assert got[3] == pytest.approx(ref[3], rel=1e-11), (T, TA)
+    # the recomputation on a tiling and pass length of its own
+    rec = (1, 8, 1, 3) if len(shape) == 2 else (1, 8, 4, 3)
+    got = gpu_adjoint_T(gp, phi0, nsteps, K, 2, tiling, 2, rec)
+    np.testing.assert_array_equal(got[1], ref[1], err_msg=str(rec))
+    np.testing.assert_array_equal(got[2], ref[2], err_msg=str(rec))
 
 
 @pytest.mark.parametrize("shape,tiling", [((130, 96), (2, 16, 1)), ((40, 36, 30), (1, 16, 2))])
@@ -212,14 +221,15 @@ def test_adjoint_tiling_independent(shape):
         assert gw == pytest.approx(ref[1], rel=1e-12) and loss == ref[2]
 
 
-def test_adjoint_autotune_picks_reverse_passes():
+@pytest.mark.parametrize("shape", [(256, 192), (64, 40, 36)])
+def test_adjoint_autotune_picks_reverse_passes(shape):
     """PRS_TUNE_ADJOINT chooses the reverse tiling and steps per pass
     together; the gradient is unchanged by the choice."""
-    say("adjoint tuner")
+    say("adjoint tuner", shape)
     prs = gpu_prs()
     torch = torch_mod()
-    shape = (256, 192)
-    gp, _ = params_pair(shape, 0.25, m=1.0, W0=8.0)
+    deta = 0.25 if len(shape) == 2 else 0.2
+    gp, _ = params_pair(shape, deta, m=1.0, W0=8.0)
     phi0 = uniform_field(shape, 6)
     ref = gpu_adjoint_T(gp, phi0, 24, 8, 1, (2, 16, 1), 1)
     sim = prs.Sim(gp, phi0=to_dev(phi0))
