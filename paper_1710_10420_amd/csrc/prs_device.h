@@ -141,21 +141,48 @@ __device__ __forceinline__ R lap3(R c, R xm, R xp, R ym, R yp, R zm, R zp, R inv
     return UNIT ? r : r * inv_dx2;
 }
 
-// Eqs. (4)-(5) with the FP64-derived coefficients of StepCoefT:
-//   pi' = a pi + b (Lap phi - V'(phi)),  V'(phi) = F phi (kc phi^2 - 1),
-// evaluated as a pi + (b Lap phi - (b F) phi (kc phi^2 - 1)): the bracket is
-// formed with one rounding, b F is one product per launch (it is wave-uniform
-// and hoisted out of the march), and the update costs six operations per
-// site.  UNIT (phi0 = 1, kc = 1) drops the exact multiplication by kc.
-template <bool UNIT = false, typename R>
-__device__ __forceinline__ void kick_drift(R c, R lap, R pi, const StepCoefT<R>& k, R& pi_new, R& phi_new)
+// Sum of the 2D nearest neighbours of a site (the non-central part of Eq. 3).
+template <typename R>
+__device__ __forceinline__ R nsum2(R xm, R xp, R ym, R yp)
+{
+    return (xm + xp) + (ym + yp);
+}
+
+template <typename R>
+__device__ __forceinline__ R nsum3(R xm, R xp, R ym, R yp, R zm, R zp)
+{
+    return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
+
+// Eqs. (3)-(5) with the FP64-derived coefficients of StepCoefT, from the
+// neighbour sum s of a site in D dimensions:
+//   pi' = a pi + b (Lap phi - V'(phi)),  Lap phi = (s - 2D phi)/dx^2,
+//   V'(phi) = F phi (kc phi^2 - 1).
+// In 2D it is evaluated as a pi + (b/dx^2) s - phi (4 b/dx^2 + (b F)(kc phi^2 - 1)):
+// the central term of the Laplacian joins the force, six operations per site
+// after the neighbour sum; 4 b/dx^2 is exact, so a homogeneous vacuum
+// (s = 4 phi, phi^2 = 1) gets exactly zero force.  In 3D 6 b/dx^2 would be
+// rounded and a vacuum would drift, so the Laplacian is formed first,
+// (s - 6 phi)/dx^2, and the kick is a pi + (b Lap phi - (b F) phi (kc phi^2 - 1)).
+// b/dx^2, 4 b/dx^2 and b F are wave-uniform products per launch (hoisted out
+// of the march).  UNIT (dx = 1, phi0 = 1) drops the exact multiplications by 1.
+template <int D, bool UNIT = false, typename R>
+__device__ __forceinline__ void kick_drift(R c, R s, R pi, const StepCoefT<R>& k, R& pi_new, R& phi_new)
 {
     const R ck = UNIT ? c : c * k.kc;
     const R q = fmar(ck, c, R(-1));
-    const R bF = k.b * k.F;
-    const R v = fmar(-(bF * c), q, k.b * lap);   // b (Lap phi - V'(phi))
-    pi_new = fmar(k.a, pi, v);                   // Eq. (4)
-    phi_new = fmar(k.deta, pi_new, c);           // Eq. (5)
+    R v;
+    if constexpr (D == 2) {
+        const R bl = UNIT ? k.b : k.b * k.inv_dx2;
+        const R t = fmar(k.b * k.F, q, R(4) * bl);   // 4 b/dx^2 + (b F)(kc phi^2 - 1)
+        v = fmar(bl, s, -(c * t));                    // b (Lap phi - V'(phi))
+    } else {
+        const R r = fmar(R(-2 * D), c, s);
+        const R lap = UNIT ? r : r * k.inv_dx2;
+        v = fmar(-((k.b * k.F) * c), q, k.b * lap);   // b (Lap phi - V'(phi))
+    }
+    pi_new = fmar(k.a, pi, v);                         // Eq. (4)
+    phi_new = fmar(k.deta, pi_new, c);                 // Eq. (5)
 }
 
 // Value held by the lane on the left (lane - 1) / right (lane + 1) of this
@@ -480,12 +507,12 @@ __device__ __forceinline__ void step_plane(const StepArgsT<R>& A, const TileSetu
             R nm[D], np[D];
             neighbours<D, VEC, TY>(Pm, Pc, Pn, left, right, S.nvalid, t, j, nm, np);
             if constexpr (UPDATE) {
-                R lap;
+                R ns;
                 if constexpr (D == 3)
-                    lap = lap3<UNIT>(c, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.k.inv_dx2);
+                    ns = nsum3(nm[0], np[0], nm[1], np[1], nm[2], np[2]);
                 else
-                    lap = lap2<UNIT>(c, nm[0], np[0], nm[1], np[1], A.k.inv_dx2);
-                kick_drift<UNIT>(c, lap, pic[t][j], A.k, out_pi[j], out_phi[j]);
+                    ns = nsum2(nm[0], np[0], nm[1], np[1]);
+                kick_drift<D, UNIT>(c, ns, pic[t][j], A.k, out_pi[j], out_phi[j]);
             }
             if constexpr (DIAG) {
                 if (S.active) site_diag<D>(c, pic[t][j], nm, np, A.dc, acc);
@@ -928,8 +955,7 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
             const R c = cc[j];
             const R xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
             const R xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
-            const R lap = lap2<UNIT>(c, xm, xp, cm[j], cp[j], A.k[k - 1].inv_dx2);
-            kick_drift<UNIT>(c, lap, pp[j], A.k[k - 1], out_pi[j], out_phi[j]);
+            kick_drift<2, UNIT>(c, nsum2(xm, xp, cm[j], cp[j]), pp[j], A.k[k - 1], out_pi[j], out_phi[j]);
             if constexpr (DIAG) {
                 if (diag_row && L.soff != kPastRow) {
                     const R nm[2] = {xm, cm[j]};
@@ -1395,9 +1421,8 @@ __device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T
                 const R c = cc[r][j];
                 const R xm = j > 0 ? cc[r][j > 0 ? j - 1 : 0] : left;
                 const R xp = j < VEC - 1 ? cc[r][j < VEC - 1 ? j + 1 : j] : right;
-                const R lap = lap3<UNIT>(c, xm, xp, cc[r - 1][j], cc[r + 1][j], cm[r][j], cp[r][j],
-                                         A.k[k - 1].inv_dx2);
-                kick_drift<UNIT>(c, lap, pp[r][j], A.k[k - 1], out_pi[j], out_phi[j]);
+                kick_drift<3, UNIT>(c, nsum3(xm, xp, cc[r - 1][j], cc[r + 1][j], cm[r][j], cp[r][j]), pp[r][j],
+                                    A.k[k - 1], out_pi[j], out_phi[j]);
                 if constexpr (DIAG) {
                     if (k == 1 && r >= T && r < T + TY) {
                         if (diag_plane && r - T < L.yown && L.own_lane) {
