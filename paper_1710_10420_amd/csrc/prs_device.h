@@ -123,24 +123,6 @@ __device__ __forceinline__ void store_vec(R* p, const R (&v)[VEC])
     }
 }
 
-// Eq. (3) (2D) and its 3D extension, times 1/dx^2.  UNIT (dx = 1) drops the
-// multiplication by 1, which is exact, so both forms give the same bits.
-template <bool UNIT = false, typename R>
-__device__ __forceinline__ R lap2(R c, R xm, R xp, R ym, R yp, R inv_dx2)
-{
-    const R s = (xm + xp) + (ym + yp);
-    const R r = fmar(R(-4), c, s);
-    return UNIT ? r : r * inv_dx2;
-}
-
-template <bool UNIT = false, typename R>
-__device__ __forceinline__ R lap3(R c, R xm, R xp, R ym, R yp, R zm, R zp, R inv_dx2)
-{
-    const R s = ((xm + xp) + (ym + yp)) + (zm + zp);
-    const R r = fmar(R(-6), c, s);
-    return UNIT ? r : r * inv_dx2;
-}
-
 // Sum of the 2D nearest neighbours of a site (the non-central part of Eq. 3).
 template <typename R>
 __device__ __forceinline__ R nsum2(R xm, R xp, R ym, R yp)
@@ -183,6 +165,29 @@ __device__ __forceinline__ void kick_drift(R c, R s, R pi, const StepCoefT<R>& k
     }
     pi_new = fmar(k.a, pi, v);                         // Eq. (4)
     phi_new = fmar(k.deta, pi_new, c);                 // Eq. (5)
+}
+
+// One reverse step at a site (the transpose of Eqs. 3-5 for the adjoint
+// pair w = adjoint of phi_dot, mu = adjoint of phi), from the neighbour sum s
+// of w and phi = phi^n at the site:
+//   mu' = mu + b (Lap w - V''(phi) w),  w' = a w + cw mu',
+//   V''(phi) = F (3 kc phi^2 - 1),
+// with Lap w - V''(phi) w = s/dx^2 - w (3F (kc phi^2 - 1) + 2F + 2D/dx^2): the
+// central term of the Laplacian joins V'', and kc phi^2 - 1 is shared with the
+// dL/dV0 term w phi (kc phi^2 - 1), which is returned.  2F + 2D/dx^2 is one
+// wave-uniform constant per launch.
+template <int D, bool UNIT = false, typename R>
+__device__ __forceinline__ R adj_site(R w, R s, R mu, R phi, R a, R b, R cw, R F, R kc, R inv_dx2, R& w_new,
+                                      R& mu_new)
+{
+    const R pk = UNIT ? phi : phi * kc;
+    const R q = fmar(pk, phi, R(-1));                                      // kc phi^2 - 1
+    const R c1 = fmar(R(2), F, UNIT ? R(2 * D) : R(2 * D) * inv_dx2);      // 2F + 2D/dx^2
+    const R t = fmar(R(3) * F, q, c1);
+    const R x = fmar(-w, t, UNIT ? s : s * inv_dx2);                       // Lap w - V''(phi) w
+    mu_new = fmar(b, x, mu);
+    w_new = fmar(cw, mu_new, a * w);
+    return w * (phi * q);
 }
 
 // Value held by the lane on the left (lane - 1) / right (lane + 1) of this
@@ -660,19 +665,14 @@ __device__ __forceinline__ void adj_plane(const AdjArgsT<R>& A, const TileSetup<
             const R w = Pc.v[t][j];
             R nm[D], np[D];
             neighbours<D, VEC, TY>(Pm, Pc, Pn, left, right, S.nvalid, t, j, nm, np);
-            R lap;
+            R ns;
             if constexpr (D == 3)
-                lap = lap3<UNIT>(w, nm[0], np[0], nm[1], np[1], nm[2], np[2], A.inv_dx2);
+                ns = nsum3(nm[0], np[0], nm[1], np[1], nm[2], np[2]);
             else
-                lap = lap2<UNIT>(w, nm[0], np[0], nm[1], np[1], A.inv_dx2);
-            const R ph = phc[t][j];
-            const R phk = UNIT ? ph : ph * A.kc;
-            const R q = fmar(phk, ph, R(-1));
-            const R v2 = A.F * fmar(R(3) * phk, ph, R(-1));   // V''(phi)
-            const R mu_new = fmar(A.b, lap - v2 * w, muc[t][j]);
-            out_mu[j] = mu_new;
-            out_w[j] = fmar(A.cw, mu_new, A.a * w);
-            if (S.active) gsum += (double)(w * (ph * q));
+                ns = nsum2(nm[0], np[0], nm[1], np[1]);
+            const R gp = adj_site<D, UNIT>(w, ns, muc[t][j], phc[t][j], A.a, A.b, A.cw, A.F, A.kc, A.inv_dx2,
+                                           out_w[j], out_mu[j]);
+            if (S.active) gsum += (double)gp;
         }
         if (S.active) {
             store_vec<VEC>(w_out + S.off[t], out_w);
@@ -1192,15 +1192,9 @@ __device__ __forceinline__ void tba_iter(const TBAArgs<T, R>& A, const TBLane& L
             const R w = cc[j];
             const R xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
             const R xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
-            const R lap = lap2<UNIT>(w, xm, xp, cm[j], cp[j], A.inv_dx2);
-            const R p = ph[j];
-            const R phk = UNIT ? p : p * A.kc;
-            const R q = fmar(phk, p, R(-1));
-            const R v2 = A.F * fmar(R(3) * phk, p, R(-1));   // V''(phi)
-            const R mu_new = fmar(A.b[k - 1], lap - v2 * w, mp[j]);
-            out_mu[j] = mu_new;
-            out_w[j] = fmar(A.cw[k - 1], mu_new, A.a[k - 1] * w);
-            g += (double)(w * (p * q));
+            const R gp = adj_site<2, UNIT>(w, nsum2(xm, xp, cm[j], cp[j]), mp[j], ph[j], A.a[k - 1], A.b[k - 1],
+                                           A.cw[k - 1], A.F, A.kc, A.inv_dx2, out_w[j], out_mu[j]);
+            g += (double)gp;
         }
         // own_row is wave-uniform; lanes outside the owned columns add g * 0
         if (own_row) gs[k - 1] = fma(g, L.soff != kPastRow ? 1.0 : 0.0, gs[k - 1]);
@@ -1672,15 +1666,10 @@ __device__ __forceinline__ void tba3_iter(const TBA3Args<T, R>& A, const TB3Lane
                 const R w = cc[r][j];
                 const R xm = j > 0 ? cc[r][j > 0 ? j - 1 : 0] : left;
                 const R xp = j < VEC - 1 ? cc[r][j < VEC - 1 ? j + 1 : j] : right;
-                const R lap = lap3<UNIT>(w, xm, xp, cc[r - 1][j], cc[r + 1][j], cm[r][j], cp[r][j], A.inv_dx2);
-                const R p = ph[r][j];
-                const R phk = UNIT ? p : p * A.kc;
-                const R q = fmar(phk, p, R(-1));
-                const R v2 = A.F * fmar(R(3) * phk, p, R(-1));   // V''(phi)
-                const R mu_new = fmar(A.b[k - 1], lap - v2 * w, mp[r][j]);
-                out_mu[j] = mu_new;
-                out_w[j] = fmar(A.cw[k - 1], mu_new, A.a[k - 1] * w);
-                gr += (double)(w * (p * q));
+                const R gp = adj_site<3, UNIT>(w, nsum3(xm, xp, cc[r - 1][j], cc[r + 1][j], cm[r][j], cp[r][j]),
+                                               mp[r][j], ph[r][j], A.a[k - 1], A.b[k - 1], A.cw[k - 1], A.F, A.kc,
+                                               A.inv_dx2, out_w[j], out_mu[j]);
+                gr += (double)gp;
             }
             // owned rows only (a wave-uniform factor: no per-lane select)
             if (r >= T && r < T + TY) g = fma(gr, r - T < L.yown ? 1.0 : 0.0, g);
