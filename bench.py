@@ -32,8 +32,8 @@ BYTES_PER_UPDATE = 16          # read phi, phi_dot; write phi^{n+1}, phi_dot (FP
 # (factors 1.9998 and 1.0000); see profiles/k_tb2d_2d8192.md.  A
 # configuration without a measurement reports null.
 TRAFFIC_PER_LAUNCH = {
-    (2, 128, 1, 8): 1145219101,
-    (2, 64, 1, 8): 1202155025,
+    (2, 64, 1, 8): 1168620680,
+    (2, 128, 1, 8): 1139146448,
 }
 
 WORKLOAD = {

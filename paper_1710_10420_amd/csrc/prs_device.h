@@ -807,6 +807,8 @@ struct TBLane {
     uint32_t nx;
     uint32_t row_bytes;
     int32_t ny;
+    int32_t dir;               // march direction of k_tb2d: +1 up (rising y), -1 down
+    int32_t wrap_at, wrap_to;  // row after the last one in that direction, and its periodic image
 };
 
 // Next rows to fetch, already wrapped into [0, ny); advanced by one row per
@@ -818,6 +820,13 @@ struct TBRows {
 __device__ __forceinline__ int32_t next_row(int32_t r, int32_t ny)
 {
     return r + 1 == ny ? 0 : r + 1;
+}
+
+// Next row of a k_tb2d march in its direction, periodic.
+__device__ __forceinline__ int32_t step_row(int32_t r, const TBLane& L)
+{
+    const int32_t n = r + L.dir;
+    return n == L.wrap_at ? L.wrap_to : n;
 }
 
 // Any row number into [0, ny) (tile set-up only).
@@ -911,8 +920,9 @@ __device__ __forceinline__ void tb_store(R* f, int32_t row, const TBLane& L, uin
     buf_store<VEC>(f + (size_t)((uint32_t)row * L.nx), bytes, L.soff, v);
 }
 
-// Iteration i of the march (y = s0 - T + 1 + i): level k computes row
-// s0 - T - k + 2 + i.  Level k has work from i = 2(k-1) on, the last
+// Iteration i of the march (upward: y = s0 - T + 1 + i; level k computes
+// row s0 - T - k + 2 + i; a downward march mirrors the rows in the tile).
+// Level k has work from i = 2(k-1) on, the last
 // iteration is i = last for every level.  CHECK skips the levels that have no
 // row yet (the first 2T-2 iterations); without it those levels run on rows
 // that only ever feed rows outside the tile, which are never stored.
@@ -925,8 +935,8 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
     const uint32_t nb = i < last ? L.row_bytes : 0u;
     tb_load<VEC>(A.phi_in, rw.phi, L, nb, S.in[(U + 2) & 3]);
     tb_load<VEC>(A.pi_in, rw.pi, L, nb, S.pin[(U + 1) & 1]);
-    rw.phi = next_row(rw.phi, L.ny);
-    rw.pi = next_row(rw.pi, L.ny);
+    rw.phi = step_row(rw.phi, L);
+    rw.pi = step_row(rw.pi, L);
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
         if (CHECK && i < 2 * (k - 1)) continue;
@@ -971,15 +981,16 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
                 S.pl[k < T ? k : 0][U & 1][j] = out_pi[j];
             }
             if constexpr (ALL) {
-                // level k row s0 + i - (T + k - 2), stored when inside [s0, s1)
+                // level k: march row e = i - (T + k - 2) of the tile, stored when inside [0, s1 - s0)
                 const int32_t e = i - (T + k - 2);
                 const bool in = e >= 0 && e < L.s1 - L.s0;
-                tb_store<VEC>(A.phi_lv[k < T ? k - 1 : 0], in ? L.s0 + e : L.s0, L, in ? L.row_bytes : 0u,
-                              out_phi);
+                const int32_t row = L.dir > 0 ? L.s0 + e : L.s1 - 1 - e;
+                tb_store<VEC>(A.phi_lv[k < T ? k - 1 : 0], in ? row : L.s0, L, in ? L.row_bytes : 0u, out_phi);
             }
         } else {
-            // level T row s0 + i - (2T - 2), inside [s0, s1) once i >= 2T - 2
-            const int32_t row = L.s0 + i - (2 * T - 2);
+            // level T: march row e = i - (2T - 2) of the tile, inside it once i >= 2T - 2
+            const int32_t e = i - (2 * T - 2);
+            const int32_t row = L.dir > 0 ? L.s0 + e : L.s1 - 1 - e;
             const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.row_bytes : 0u;
             tb_store<VEC>(A.phi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_phi);
             tb_store<VEC>(A.pi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_pi);
@@ -1028,6 +1039,15 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
     L.soff = (lane >= H && lane < kWave - H && x0 < (int32_t)L.nx) ? L.voff : kPastRow;
     L.s0 = (int32_t)ts * rows;
     L.s1 = L.s0 + rows < L.ny ? L.s0 + rows : L.ny;
+    // Odd row tiles march down, so that two neighbouring tiles start at
+    // their common edge together or end there together: the 2T - 2 halo
+    // rows each reads of the other's rows are then fetched from HBM about
+    // once and found in L2 by the second reader.  The y-neighbour sum is
+    // symmetric, so the results are the same bits either way.  Diagnostic
+    // passes march up (their links point to rising y).
+    L.dir = (DIAG || (ts & 1u) == 0u) ? 1 : -1;
+    L.wrap_at = L.dir > 0 ? L.ny : -1;
+    L.wrap_to = L.dir > 0 ? 0 : L.ny - 1;
 
     TBState<VEC, T, R> S;
 #pragma unroll
@@ -1047,15 +1067,17 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
             for (int k = 0; k < T; ++k) S.pl[k][a][j] = R(0);
         }
 
-    // iteration 0 (y0 = s0 - T + 1) needs phi^n rows y0-1 .. y0+1 and phi_dot row y0
-    const int32_t y0 = L.s0 - T + 1;
-    tb_load<VEC>(A.phi_in, wrap_row(y0 - 1, L.ny), L, L.row_bytes, S.in[3]);
+    // iteration 0 (y0 = T - 1 rows before the tile's first row in the march
+    // direction) needs phi^n rows y0 - dir .. y0 + dir and phi_dot row y0
+    const int32_t d = L.dir;
+    const int32_t y0 = d > 0 ? L.s0 - T + 1 : L.s1 + T - 2;
+    tb_load<VEC>(A.phi_in, wrap_row(y0 - d, L.ny), L, L.row_bytes, S.in[3]);
     tb_load<VEC>(A.phi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.in[0]);
-    tb_load<VEC>(A.phi_in, wrap_row(y0 + 1, L.ny), L, L.row_bytes, S.in[1]);
+    tb_load<VEC>(A.phi_in, wrap_row(y0 + d, L.ny), L, L.row_bytes, S.in[1]);
     tb_load<VEC>(A.pi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.pin[0]);
     TBRows rw;
-    rw.phi = wrap_row(y0 + 2, L.ny);
-    rw.pi = wrap_row(y0 + 1, L.ny);
+    rw.phi = wrap_row(y0 + 2 * d, L.ny);
+    rw.pi = wrap_row(y0 + d, L.ny);
 
     DiagAcc acc;
     acc.links[0] = acc.links[1] = acc.links[2] = 0u;
@@ -1089,8 +1111,17 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
     }
 }
 
+// Waves per SIMD the register allocation of k_tb2d must leave room for: the
+// float32 eight-step pass with two sites per lane fits 128 VGPRs (four waves)
+// without spilling and is held there.
+constexpr int tb2d_min_waves(int vec, int T, int esize)
+{
+    return (esize == 4 && vec == 2 && T == 8) ? 4 : 1;
+}
+
 template <int VEC, int T, bool DIAG, bool UNIT, typename R>
-__global__ __launch_bounds__(kBlock) void k_tb2d(TBArgs<T, R> A)
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(tb2d_min_waves(VEC, T, (int)sizeof(R))))) void k_tb2d(TBArgs<T, R> A)
 {
     const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     if (tile >= A.ntiles) return;
