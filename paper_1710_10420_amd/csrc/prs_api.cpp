@@ -1659,14 +1659,33 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     const size_t bytes = field_bytes(c->p);
     char* buf = nullptr;
     double* gacc = nullptr;
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), 4 * bytes), "tuner allocation");
+    // Each reverse step reads its own phi^n in the backward; with room, the
+    // tuner gives the steps 32 (else 8) distinct phi fields in rotation, more
+    // than the last-level cache holds at the lattices the adjoint is run on
+    // (one shared field would be served from cache and flatter the
+    // multi-step passes, which read T of them per pass).
+    size_t free_b = 0, total_b = 0;
+    int nphi = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+        for (int n : {32, kMaxPassSteps})
+            if ((4 + (size_t)n) * bytes <= free_b / 2) {
+                nphi = n;
+                break;
+            }
+    }
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), (4 + nphi) * bytes), "tuner allocation");
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&gacc), (size_t)c->partial_cap * sizeof(double));
     char* w0 = buf;
     char* w1 = buf + bytes;
     char* mu0 = buf + 2 * bytes;
     char* mu1 = buf + 3 * bytes;
+    auto phi_of = [&](int n) -> const void* {
+        return nphi > 0 ? static_cast<const void*>(buf + (4 + n % nphi) * bytes) : c->phi[c->cur];
+    };
     if (e == hipSuccess) e = hipMemcpyAsync(w0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(mu0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
+    for (int i = 0; i < nphi && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(buf + (4 + i) * bytes, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = launch_zero_f64(gacc, c->partial_cap, c->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
@@ -1698,13 +1717,13 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
                         const void* phis[kMaxPassSteps];
                         AdjCoef64 cc[kMaxPassSteps];
                         for (int i = 0; i < T; ++i) {
-                            phis[i] = c->phi[c->cur];
+                            phis[i] = phi_of(k + i);
                             cc[i] = adj_coef(c, c->step, false);
                         }
                         err = launch_tba(T, c->geo, t, a, b, ma, mb, phis, gacc, cc, c->stream);
                         std::swap(ma, mb);
                     } else {
-                        err = launch_adjoint(c->geo, t, a, b, ma, c->phi[c->cur], gacc, adj_coef(c, c->step, false),
+                        err = launch_adjoint(c->geo, t, a, b, ma, phi_of(k), gacc, adj_coef(c, c->step, false),
                                              c->stream);
                     }
                     if (err != hipSuccess) return err;
