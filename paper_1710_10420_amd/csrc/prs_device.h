@@ -1185,12 +1185,12 @@ __device__ __forceinline__ void tba_iter(const TBAArgs<T, R>& A, const TBLane& L
     const uint32_t nb = i < last ? L.row_bytes : 0u;
     tb_load<VEC>(A.w_in, rw.phi, L, nb, S.in[(U + 2) & 3]);
     tb_load<VEC>(A.mu_in, rw.pi, L, nb, S.mi[(U + 1) & 1]);
-    rw.phi = next_row(rw.phi, L.ny);
-    rw.pi = next_row(rw.pi, L.ny);
+    rw.phi = step_row(rw.phi, L);
+    rw.pi = step_row(rw.pi, L);
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         tb_load<VEC>(A.phi[k], prow[k], L, nb, S.ph[k][(U + 1) & 1]);
-        prow[k] = next_row(prow[k], L.ny);
+        prow[k] = step_row(prow[k], L);
     }
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
@@ -1236,7 +1236,8 @@ __device__ __forceinline__ void tba_iter(const TBAArgs<T, R>& A, const TBLane& L
                 S.ml[k < T ? k : 0][U & 1][j] = out_mu[j];
             }
         } else {
-            const int32_t row = L.s0 + i - (2 * T - 2);
+            const int32_t e = i - (2 * T - 2);
+            const int32_t row = L.dir > 0 ? L.s0 + e : L.s1 - 1 - e;
             const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.row_bytes : 0u;
             tb_store<VEC>(A.w_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_w);
             tb_store<VEC>(A.mu_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_mu);
@@ -1281,6 +1282,10 @@ __global__ __launch_bounds__(kBlock) void k_tba2d(TBAArgs<T, R> A)
     L.soff = (lane >= H && lane < kWave - H && x0 < (int32_t)L.nx) ? L.voff : kPastRow;
     L.s0 = (int32_t)ts * rows;
     L.s1 = L.s0 + rows < L.ny ? L.s0 + rows : L.ny;
+    // odd row tiles march down, as in k_tb2d
+    L.dir = (ts & 1u) == 0u ? 1 : -1;
+    L.wrap_at = L.dir > 0 ? L.ny : -1;
+    L.wrap_to = L.dir > 0 ? 0 : L.ny - 1;
 
     TBAState<VEC, T, R> S;
 #pragma unroll
@@ -1300,22 +1305,24 @@ __global__ __launch_bounds__(kBlock) void k_tba2d(TBAArgs<T, R> A)
             for (int k = 0; k < T; ++k) S.ml[k][a][j] = S.ph[k][a][j] = R(0);
         }
 
-    // iteration 0 (y0 = s0 - T + 1): w rows y0-1 .. y0+1, mu row y0, and the
-    // phi row of every level (level k computes row y0 - k + 1)
-    const int32_t y0 = L.s0 - T + 1;
-    tb_load<VEC>(A.w_in, wrap_row(y0 - 1, L.ny), L, L.row_bytes, S.in[3]);
+    // iteration 0 (y0 = T - 1 rows before the tile's first row in the march
+    // direction d): w rows y0 - d .. y0 + d, mu row y0, and the phi row of
+    // every level (level k computes row y0 - (k - 1) d)
+    const int32_t d = L.dir;
+    const int32_t y0 = d > 0 ? L.s0 - T + 1 : L.s1 + T - 2;
+    tb_load<VEC>(A.w_in, wrap_row(y0 - d, L.ny), L, L.row_bytes, S.in[3]);
     tb_load<VEC>(A.w_in, wrap_row(y0, L.ny), L, L.row_bytes, S.in[0]);
-    tb_load<VEC>(A.w_in, wrap_row(y0 + 1, L.ny), L, L.row_bytes, S.in[1]);
+    tb_load<VEC>(A.w_in, wrap_row(y0 + d, L.ny), L, L.row_bytes, S.in[1]);
     tb_load<VEC>(A.mu_in, wrap_row(y0, L.ny), L, L.row_bytes, S.mi[0]);
     int32_t prow[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-        tb_load<VEC>(A.phi[k], wrap_row(y0 - k, L.ny), L, L.row_bytes, S.ph[k][0]);
-        prow[k] = wrap_row(y0 - k + 1, L.ny);
+        tb_load<VEC>(A.phi[k], wrap_row(y0 - k * d, L.ny), L, L.row_bytes, S.ph[k][0]);
+        prow[k] = wrap_row(y0 - (k - 1) * d, L.ny);
     }
     TBRows rw;
-    rw.phi = wrap_row(y0 + 2, L.ny);
-    rw.pi = wrap_row(y0 + 1, L.ny);
+    rw.phi = wrap_row(y0 + 2 * d, L.ny);
+    rw.pi = wrap_row(y0 + d, L.ny);
     double gs[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) gs[k] = 0.0;
