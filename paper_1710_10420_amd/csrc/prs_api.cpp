@@ -890,8 +890,25 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     // on the overlap (each kernel's inputs are complete when it starts).
     const bool overlap = L.nseg > 1;
     if (overlap && !c->adj_aux) {
-        HIP_TRY(hipStreamCreateWithFlags(&c->adj_aux, hipStreamNonBlocking), "stream create");
-        for (hipEvent_t& e : c->adj_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
+        // on the device of the context's stream, whatever device is current
+        int cur = 0;
+        hipDevice_t dev = 0;
+        HIP_TRY(hipGetDevice(&cur), "device query");
+        HIP_TRY(hipStreamGetDevice(c->stream, &dev), "stream device query");
+        HIP_TRY(hipSetDevice((int)dev), "set device");
+        hipError_t e = hipStreamCreateWithFlags(&c->adj_aux, hipStreamNonBlocking);
+        for (hipEvent_t& ev : c->adj_ev)
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        (void)hipSetDevice(cur);
+        if (e != hipSuccess) {
+            if (c->adj_aux) (void)hipStreamDestroy(c->adj_aux);
+            for (hipEvent_t& ev : c->adj_ev) {
+                if (ev) (void)hipEventDestroy(ev);
+                ev = nullptr;
+            }
+            c->adj_aux = nullptr;
+            return hip_fail(e, "stream/event create");
+        }
     }
     hipStream_t rs = overlap ? c->adj_aux : c->stream;
     if (overlap) {
