@@ -409,7 +409,8 @@ def test_multi_step_default_and_limits():
     assert e.value.status == prs.PRS_EINVAL
 
 
-@pytest.mark.parametrize("shape,T,tiling", [((8192, 8192), 8, (2, 64, 1)), ((1024, 1024, 1024), 3, (1, 16, 4)),
+@pytest.mark.parametrize("shape,T,tiling", [((8192, 8192), 8, (2, 64, 1)), ((8192, 8192), 8, (2, 128, 1)),
+                                            ((1024, 1024, 1024), 3, (1, 16, 4)), ((1024, 1024, 1024), 3, (2, 64, 2)),
                                             ((1024, 1024, 1024), 2, (2, 32, 1))])
 def test_full_size_multi_step_bitwise(shape, T, tiling):
     """At the full lattice sizes the multi-step passes reproduce single steps
