@@ -278,17 +278,23 @@ def default_tiling_of(sim):
     return sim.tiling()
 
 
-def test_full_size_2d_8192_sampled():
-    """8192^2 matter era in the tiling the benchmark uses: sampled patches
-    after 64 steps match the oracle evolved on the patch's dependence cone;
-    the full-lattice diagnostics match the oracle on the same field."""
-    say("8192^2 full size")
+@pytest.mark.parametrize("tiling,T", [((2, 64, 1), 8), ((2, 128, 1), 8), (None, None)])
+def test_full_size_2d_8192_sampled(tiling, T):
+    """8192^2 matter era in the launch configurations the benchmark's tuner
+    picks (eight-step passes, 64 or 128 rows) and the library default:
+    sampled patches after 64 steps match the oracle evolved on the patch's
+    dependence cone; the full-lattice diagnostics match the oracle on the
+    same field."""
+    say("8192^2 full size", tiling, T)
     torch = torch_mod()
     prs = gpu_prs()
     shape = (8192, 8192)
     gp, op = params_pair(shape, 0.25, m=2.0, W0=10.0, diag_every=64)
     sim = prs.Sim(gp, seed=1)
-    say("  tiling", sim.tiling())
+    if tiling is not None:
+        sim.set_tiling(*tiling)
+        sim.set_time_blocking(T)
+    say("  tiling", sim.tiling(), "steps/pass", sim.time_blocking())
     recs = sim.step_n(64)
     assert len(recs) == 1 and recs[0]["step"] == 0
     phi, dphi = sim.state()
@@ -310,16 +316,21 @@ def test_full_size_2d_8192_sampled():
     torch.cuda.empty_cache()
 
 
-def test_full_size_3d_1024_sampled():
-    """1024^3 radiation era in the benchmark's tiling: sampled patches after
-    10 steps and the full-lattice diagnostics on the same field."""
-    say("1024^3 full size")
+@pytest.mark.parametrize("tiling,T", [((2, 64, 2), 3), (None, None)])
+def test_full_size_3d_1024_sampled(tiling, T):
+    """1024^3 radiation era in the fastest three-step configuration and the
+    library default: sampled patches after 10 steps and the full-lattice
+    diagnostics on the same field."""
+    say("1024^3 full size", tiling, T)
     torch = torch_mod()
     prs = gpu_prs()
     shape = (1024, 1024, 1024)
     gp, op = params_pair(shape, 0.2, m=1.0, W0=10.0, diag_every=50)
     sim = prs.Sim(gp, seed=1)
-    say("  tiling", sim.tiling())
+    if tiling is not None:
+        sim.set_tiling(*tiling)
+        sim.set_time_blocking(T)
+    say("  tiling", sim.tiling(), "steps/pass", sim.time_blocking())
     sim.step_n(10)
     phi, dphi = sim.state()
     rng = np.random.default_rng(6)
