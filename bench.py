@@ -346,6 +346,7 @@ def main():
     alg_bytes = BYTES_PER_UPDATE * sites * spp        # algorithmic bytes of one launch
     achieved = alg_bytes / avg_launch_s / 1e9
     recs, mu, nu = results[-1]
+    traffic = TRAFFIC_PER_LAUNCH.get(tuple(sim.tiling()) + (spp,))
     out = {
         "metric": "site-updates/s (PRS forward step, fused wall diagnostics)",
         "value": value,
@@ -364,7 +365,11 @@ def main():
                    "steps_per_pass": sim.time_blocking()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": TRAFFIC_PER_LAUNCH.get(tuple(sim.tiling()) + (spp,)),
+                     "traffic": traffic,
+                     # measured HBM bytes per launch over the live launch time:
+                     # the share of the 8 TB/s peak the pass really moves
+                     "dram_gbs": traffic / avg_launch_s / 1e9 if traffic else None,
+                     "dram_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS if traffic else None,
                      "kernel": ("k_tb2d<vec=%d,T=%d> (%d fused leapfrog steps per pass)" % (
                          sim.tiling()[0], spp, spp)) if spp > 1 else
                                "k_step<2,%d,1> (fused leapfrog step)" % sim.tiling()[0],
