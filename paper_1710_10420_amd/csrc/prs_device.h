@@ -255,25 +255,33 @@ __device__ __forceinline__ void site_diag(R c, R pi, const R (&nm)[D], const R (
         wall = wall || fwd || bwd;
     }
     if (!(__builtin_isfinite(c) && __builtin_isfinite(pi))) a.nonfinite += 1u;
-    if (cross) {
-        double gsq = 0.0, gabs = 0.0;
+    a.walls += wall ? 1u : 0u;
+    // The FP64 terms are evaluated only by waves that have a crossing link
+    // (a wall site) among their lanes: walls are sparse once the network has
+    // coarsened, and without the wave-uniform test the compiler evaluates
+    // both square root and divisions on every site.
+    if (__builtin_amdgcn_ballot_w64(cross != 0)) {
+        if (cross) {
+            double gsq = 0.0, gabs = 0.0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            double h = (double)np[d] - (double)nm[d];
-            gsq += h * h;
-            gabs += fabs(h);
+            for (int d = 0; d < D; ++d) {
+                double h = (double)np[d] - (double)nm[d];
+                gsq += h * h;
+                gabs += fabs(h);
+            }
+            double w = gabs > 0.0 ? sqrt(gsq) / gabs : 1.0;
+            a.area += (double)cross * w;
         }
-        double w = gabs > 0.0 ? sqrt(gsq) / gabs : 1.0;
-        a.area += (double)cross * w;
     }
-    if (wall) {
-        a.walls += 1u;
-        double cd = (double)c;
-        double q = cd * cd * dc.kc - 1.0;
-        double V = dc.V0 * q * q;
-        if (V > 0.0) {
-            double pd = (double)pi;
-            a.ek += 0.5 * pd * pd / V;
+    if (__builtin_amdgcn_ballot_w64(wall)) {
+        if (wall) {
+            double cd = (double)c;
+            double q = cd * cd * dc.kc - 1.0;
+            double V = dc.V0 * q * q;
+            if (V > 0.0) {
+                double pd = (double)pi;
+                a.ek += 0.5 * pd * pd / V;
+            }
         }
     }
 }
