@@ -174,11 +174,12 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
 
 /* Temporal blocking: with steps_per_pass = T > 1, prs_step_n advances up to
  * T steps per pass over HBM -- a pass never has a recorded state inside it --
- * so each value is read about once per T steps.  T may be 2, 3, 4, and 6 or 8
- * in float32, for 2D lattices (default 2), and 2, or 3 in float32, for 3D
- * lattices (default 1); other values give PRS_EINVAL.  A pass uses T steps
- * only when the tiling has a T-step kernel (2D: ty = 1; 3D: vec 1 with any
- * ty, or vec 2 with ty 1 or 2; a wave owns 4 rows along y, 8 with ty = 4) and
+ * so each value is read about once per T steps.  T may be 2, 3, 4, 6 or 8 for
+ * 2D lattices (default 2), and 2, or 3 in float32, for 3D lattices (default
+ * 1); other values give PRS_EINVAL.  A pass uses T steps only when the tiling
+ * has a T-step kernel (2D: ty = 1, and in float64 vec 1 for T = 6, 8; 3D:
+ * vec 1 with any ty, or vec 2 with ty 1 or 2; a wave owns 4 rows along y, 8
+ * with ty = 4) and
  * otherwise the longest length that has one; the autotuner picks T with the
  * tiling.  Results are bitwise those of single steps.  The second phi_dot
  * buffer this needs lives in the workspace; every prs_step_n call still ends

@@ -398,7 +398,7 @@ prs_status prs_set_time_blocking(prs_ctx* c, int32_t steps_per_pass)
     if (steps_per_pass < 1 || steps_per_pass > kMaxPassSteps)
         return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
     if (steps_per_pass > 1 && tb_supported(c->geo) && !tb_steps_supported(c->geo, steps_per_pass))
-        return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, and 6, 8 in float32; "
+        return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, 6, 8; "
                     "3D: 2, and 3 in float32)", steps_per_pass);
     c->tblock = steps_per_pass;
     return PRS_OK;
@@ -1428,7 +1428,7 @@ prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps
         return fail(PRS_EUNSUPPORTED, "multi-step passes need rows (2D) shorter than 2^28 sites or planes (3D) "
                     "shorter than 2^31 bytes");
     if (steps_per_pass > 1 && !tb_steps_supported(b->geo[item], steps_per_pass))
-        return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, and 6, 8 in float32; "
+        return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, 6, 8; "
                     "3D: 2, and 3 in float32)", steps_per_pass);
     if (item_tiles_max(b->geo[item], b->til[item], std::max(2, steps_per_pass)) > b->part_cap[item])
         return fail(PRS_EINVAL, "steps per pass need more wave tiles than the workspace holds");

@@ -2079,11 +2079,11 @@ hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const void* ph
     case 3: return launch_tb_t<R, VEC, 3>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     case 4: return launch_tb_t<R, VEC, 4>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
     case 6:
-        if constexpr (sizeof(R) == 4)
+        if constexpr (sizeof(R) == 4 || VEC == 1)
             return launch_tb_t<R, VEC, 6>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
         break;
     case 8:
-        if constexpr (sizeof(R) == 4)
+        if constexpr (sizeof(R) == 4 || VEC == 1)
             return launch_tb_t<R, VEC, 8>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
         break;
     }
@@ -2107,12 +2107,21 @@ constexpr bool tba_combo_ok(int vec, int T)
 }
 
 // The 2D recomputation follows the forward's multi-step passes: T = 2, 3, 4
-// and, in float32, 6, 8, with vec 1, 2 and (float32) 4.
+// with vec 1, 2 and (float32) 4, and T = 6, 8 in float32 or with vec 1.
 template <typename R>
 constexpr bool tball_combo_ok(int vec, int T)
 {
     return (vec == 1 || vec == 2 || (sizeof(R) == 4 && vec == 4)) &&
-           (T == 2 || T == 3 || T == 4 || (sizeof(R) == 4 && (T == 6 || T == 8)));
+           (T == 2 || T == 3 || T == 4 || ((sizeof(R) == 4 || vec == 1) && (T == 6 || T == 8)));
+}
+
+// 2D forward passes with a kernel: T = 2, 3, 4 for every vec, T = 6, 8 in
+// float32 or, in float64, with vec 1 (two sites of eight bytes per lane
+// would need more than the register file).
+template <typename R>
+constexpr bool tb2_combo_ok(int vec, int T)
+{
+    return T == 2 || T == 3 || T == 4 || ((sizeof(R) == 4 || vec == 1) && (T == 6 || T == 8));
 }
 
 template <typename R, int VEC, int T>

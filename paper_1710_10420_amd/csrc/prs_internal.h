@@ -85,10 +85,11 @@ int64_t tb_tiles(const Geometry& g, const Tiling& t, int T);
 // sites and for 3D lattices whose planes are shorter than 2^31 bytes (their
 // accesses use 32-bit byte offsets within a row or a plane).
 bool tb_supported(const Geometry& g);
-// Steps per multi-step pass with a kernel for some tiling: 2D 2, 3, 4 and,
-// in float32, 6, 8; 3D 2 and, in float32, 3.
+// Steps per multi-step pass with a kernel for some tiling: 2D 2, 3, 4, 6, 8;
+// 3D 2 and, in float32, 3.
 bool tb_steps_supported(const Geometry& g, int T);
-// ... and for this tiling (3D: vec 1 or 2, and only some row counts).
+// ... and for this tiling (2D float64: 6 and 8 with vec 1 only; 3D: vec 1
+// or 2, and only some row counts).
 bool tb_pass_supported(const Geometry& g, const Tiling& t, int T);
 constexpr int kMaxPassSteps = 8;   // most leapfrog steps fused into one pass
 
@@ -113,8 +114,8 @@ hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, 
                           const void* phi_n, double* gacc, const AdjCoef64& c, hipStream_t s);
 
 // Multi-step passes of the adjoint.  tb_all_supported: the recomputation
-// (2D: as the forward passes, T = 2, 3, 4 and, in float32, 6, 8; 3D: as
-// the forward passes); tba_supported: the reverse sweep (2D: T = 2, 4 and, in
+// (2D: as the forward passes, T = 2, 3, 4 and 6, 8 in float32 or with
+// vec 1; 3D: as the forward passes); tba_supported: the reverse sweep (2D: T = 2, 4 and, in
 // float32, 8, vec 1 or 2, ty 1; 3D: T = 2 on the 3D pass tilings and, in
 // float32, T = 3 with vec 1, 4 rows).  launch_tb_all: T forward steps from (phi_in, pi_in) storing
 // phi^{n+k} to phi_lv[k-1] for k = 1 .. T and phi_dot^{n+T-1/2} to pi_out

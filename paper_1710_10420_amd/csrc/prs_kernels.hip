@@ -653,13 +653,13 @@ bool tb_steps_supported(const Geometry& g, int T)
 {
     if (!tb_supported(g)) return false;
     if (g.ndim == 3) return T == 2 || (!g.f64 && T == 3);
-    return T == 2 || T == 3 || T == 4 || (!g.f64 && (T == 6 || T == 8));
+    return T == 2 || T == 3 || T == 4 || T == 6 || T == 8;
 }
 
 bool tb_pass_supported(const Geometry& g, const Tiling& t, int T)
 {
     if (!tb_steps_supported(g, T) || !tiling_supported(g, t)) return false;
-    if (g.ndim == 2) return t.ty == 1;
+    if (g.ndim == 2) return t.ty == 1 && (g.f64 ? tb2_combo_ok<double>(t.vec, T) : tb2_combo_ok<float>(t.vec, T));
     return g.f64 ? tb3_combo_ok<double>(t.vec, T, tb3_rows(t.ty)) : tb3_combo_ok<float>(t.vec, T, tb3_rows(t.ty));
 }
 

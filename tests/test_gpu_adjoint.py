@@ -122,7 +122,8 @@ def test_multi_step_adjoint_bitwise_equal_single_steps(shape, nsteps, K, tiling)
     np.testing.assert_array_equal(got[2], ref[2], err_msg=str(rec))
 
 
-@pytest.mark.parametrize("shape,tiling", [((130, 96), (2, 16, 1)), ((40, 36, 30), (1, 16, 2))])
+@pytest.mark.parametrize("shape,tiling", [((130, 96), (2, 16, 1)), ((130, 96), (1, 8, 1)),
+                                          ((40, 36, 30), (1, 16, 2))])
 def test_multi_step_adjoint_f64(shape, tiling):
     say("multi-step adjoint f64", shape)
     prs = gpu_prs()
@@ -130,7 +131,7 @@ def test_multi_step_adjoint_f64(shape, tiling):
     gp = prs.make_params(shape, deta=deta, m=1.0, W0=6.0, precision=prs.PRS_F64)
     phi0 = uniform_field(shape, 9)
     ref = gpu_adjoint_T(gp, phi0, 30, 12, 1, tiling)
-    for T in ((2, 3, 4) if len(shape) == 2 else (2,)):
+    for T in ((2, 3, 4, 6, 8) if len(shape) == 2 else (2,)):
         got = gpu_adjoint_T(gp, phi0, 30, 12, T, tiling)
         np.testing.assert_array_equal(got[1], ref[1], err_msg=str(T))
         np.testing.assert_array_equal(got[2], ref[2], err_msg=str(T))

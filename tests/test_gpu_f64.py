@@ -100,7 +100,9 @@ def test_f64_fused_records_and_full_run():
 @pytest.mark.parametrize("shape", [(264, 200), (40, 36, 30)])
 def test_f64_tiling_and_steps_per_pass_independence(shape):
     """Fields are bitwise independent of the tiling (vec 1, 2; 3D rows of
-    1, 2, 4) and of the steps per pass (2D: 1 .. 4; 3D: 1, 2)."""
+    1, 2, 4) and of the steps per pass (2D: 1 .. 8, the six- and eight-step
+    passes with vec 1 and, asked of vec 2, the planner's shorter passes; 3D:
+    1, 2)."""
     say("f64 tilings", shape)
     prs = gpu_prs()
     deta = 0.25 if len(shape) == 2 else 0.2
@@ -111,7 +113,7 @@ def test_f64_tiling_and_steps_per_pass_independence(shape):
     for vec in (1, 2):
         for rows in (8, 17):
             for ty in tys:
-                for T in ((1, 2, 3, 4) if len(shape) == 2 else (1, 2)):
+                for T in ((1, 2, 3, 4, 6, 8) if len(shape) == 2 else (1, 2)):
                     sim = prs.Sim(gp, phi0=phi0)
                     sim.set_tiling(vec, rows, ty)
                     sim.set_time_blocking(T)

@@ -401,8 +401,9 @@ def test_multi_step_default_and_limits():
     gp64 = prs.make_params((64, 64), deta=0.25, precision=prs.PRS_F64)
     sim64 = prs.Sim(gp64, seed=1)
     sim64.set_time_blocking(4)
+    sim64.set_time_blocking(8)          # float64 eight-step passes run with vec 1
     with pytest.raises(prs.PRSError) as e:
-        sim64.set_time_blocking(8)
+        sim64.set_time_blocking(5)
     assert e.value.status == prs.PRS_EINVAL
     gp3, _ = params_pair((16, 16, 16), 0.2)
     sim3 = prs.Sim(gp3, seed=1)
