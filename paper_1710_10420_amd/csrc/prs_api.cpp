@@ -343,7 +343,6 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const double ascale = area_scale(c->p);
     const TileCounts tc = tile_counts(c->geo, c->til);
     const int64_t K = c->p.diag_every;
-    const int64_t end = c->step + nsteps;
 
     const int T = tb_supported(c->geo) ? c->tblock : 1;
     const std::vector<uint8_t> plan = plan_passes(c->geo, c->til, c->partial_cap, c->step, nsteps, T, want ? K : 0);
