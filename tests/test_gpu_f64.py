@@ -128,6 +128,33 @@ def test_f64_tiling_and_steps_per_pass_independence(shape):
                         assert_stats_match(a, b, rel=1e-13, ctx=str((vec, rows, ty, T)))
 
 
+def test_f64_full_size_sampled():
+    """8192^2 matter era in float64 in the configuration the float64
+    benchmark leg's tuner picks (one site per lane, 128 rows, eight steps per
+    pass): sampled patches after 64 steps match the FP64 oracle evolved on
+    each patch's dependence cone to the float64 gate."""
+    say("f64 8192^2 full size")
+    torch = torch_mod()
+    prs = gpu_prs()
+    from tests.gpu_util import oracle_patch
+    shape = (8192, 8192)
+    gp, op = params64(shape, 0.25, m=2.0, W0=10.0, diag_every=64)
+    sim = prs.Sim(gp, seed=1)
+    sim.set_tiling(1, 128, 1)
+    sim.set_time_blocking(8)
+    assert prs.prs_plan_passes(sim.ctx, 64)[0] >= 1
+    sim.step_n(64)
+    g = host(sim.state()[0])
+    rng = np.random.default_rng(8)
+    centers = [(0, 0), (8191, 8191), (4095, 17)] + [tuple(int(v) for v in rng.integers(0, 8192, 2))
+                                                    for _ in range(3)]
+    for c in centers:
+        idx, ref = oracle_patch(op, shape, 1, c, 64, 6)
+        assert rel_linf(g[idx], ref) <= F64_FIELD_GATE, c
+    del sim
+    torch.cuda.empty_cache()
+
+
 def test_f64_rejects_four_sites_per_lane():
     prs = gpu_prs()
     gp, _ = params64((256, 64), 0.25)
