@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
         ("V0", ctypes.c_double),
         ("W0", ctypes.c_double),
         ("phi0", ctypes.c_double),
+        ("beta", ctypes.c_double),
     ]
 
 
@@ -165,8 +166,9 @@ def v0_of_w0(W0):
     return 0.0 if math.isinf(W0) else math.pi ** 2 / (2.0 * W0 * W0)
 
 
-def params(shape, deta, eta0=1.0, alpha=3.0, m=1.0, W0=10.0, dx=1.0, phi0=1.0, V0=None):
-    """Build oracle parameters.  ``shape`` is (nx, ny) or (nx, ny, nz)."""
+def params(shape, deta, eta0=1.0, alpha=3.0, m=1.0, W0=10.0, dx=1.0, phi0=1.0, V0=None, beta=0.0):
+    """Build oracle parameters.  ``shape`` is (nx, ny) or (nx, ny, nz);
+    ``beta`` is the scale-factor power of the force (0: PRS)."""
     p = Params()
     p.ndim = len(shape)
     if p.ndim not in (2, 3):
@@ -177,6 +179,7 @@ def params(shape, deta, eta0=1.0, alpha=3.0, m=1.0, W0=10.0, dx=1.0, phi0=1.0, V
     p.W0 = W0
     p.V0 = v0_of_w0(W0) if V0 is None else V0
     p.phi0 = phi0
+    p.beta = beta
     return p
 
 

@@ -15,8 +15,9 @@
  *
  * What each function follows:
  *   orc_step      Eq. (3) Laplacian, Eq. (4) velocity kick, Eq. (5) drift,
- *                 Eq. (6) damping coefficient; Eq. (2) with beta = 0 so the
- *                 force carries no scale-factor power.
+ *                 Eq. (6) damping coefficient; the force of Eq. (2) carries the
+ *                 scale-factor power a^beta (beta = 0 for the PRS choice, where
+ *                 Eq. (4) is printed without it).
  *   orc_stats     Eq. (7) wall area per unit volume from sign-changing links
  *                 and Eq. (8) (gamma v)^2 over the sites that hold walls.
  *   orc_energy    discrete flat-space energy used as an invariant check.
@@ -37,6 +38,11 @@
  *     (1/2) phi_dot^2 / V; a wall site is a site touching at least one
  *     crossing link; sites with V = 0 add nothing but are still counted.
  *   - diagnostics of state n use (phi^n, phi_dot^{n-1/2}).
+ *   - the scale factor is a(eta) = (eta/eta0)^m, so a = 1 at the start; with
+ *     beta != 0 the force of step n is a(eta_n)^beta dV/dphi, and the
+ *     potential energy of a wall in Eq. (8) is a(eta_n)^beta V (a static
+ *     wall then has (1/2) phi'^2 = a^beta V, and a boosted one still gives
+ *     (gamma v)^2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,6 +61,7 @@ typedef struct {
     double V0;         /* potential height of Eq. (1) */
     double W0;         /* wall thickness parameter, V0 = pi^2/(2 W0^2) */
     double phi0;       /* vacuum value of Eq. (1) */
+    double beta;       /* scale-factor power of the force in Eq. (2) */
 } orc_params;
 
 typedef struct {
@@ -135,6 +142,14 @@ double orc_delta(const orc_params *p, int64_t n)
     return 0.5 * p->alpha * (p->deta / orc_eta(p, n)) * p->m;
 }
 
+/* a(eta_n)^beta with a(eta) = (eta/eta0)^m: the factor of the force in
+ * Eq. (2) at step n (exactly 1 for beta = 0). */
+double orc_force_scale(const orc_params *p, int64_t n)
+{
+    if (p->beta == 0.0) return 1.0;
+    return pow(pow(orc_eta(p, n) / p->eta0, p->m), p->beta);
+}
+
 /* One PRS step n -> n+1 (Eqs. 3-5).  phi holds phi^n (read only), pi holds
  * phi_dot^{n-1/2} on entry and phi_dot^{n+1/2} on exit, phi_next receives
  * phi^{n+1}.  Every site reads the old phi^n (Jacobi update). */
@@ -144,13 +159,14 @@ void orc_step(const orc_params *p, int64_t n, const double *phi, double *pi,
     int64_t nx = p->n[0], ny = p->n[1], nz = p->ndim == 3 ? p->n[2] : 1;
     double delta = orc_delta(p, n);
     double deta = p->deta;
+    double A = orc_force_scale(p, n);
 #pragma omp parallel for schedule(static)
     for (int64_t zy = 0; zy < ny * nz; ++zy) {
         int64_t y = zy % ny, z = zy / ny;
         for (int64_t x = 0; x < nx; ++x) {
             int64_t i = x + nx * (y + ny * z);
             double lap = laplacian_at(p, phi, x, y, z);
-            double kick = (1.0 - delta) * pi[i] + deta * (lap - dV(p, phi[i]));
+            double kick = (1.0 - delta) * pi[i] + deta * (lap - A * dV(p, phi[i]));
             pi[i] = kick / (1.0 + delta);                 /* Eq. (4) */
             phi_next[i] = phi[i] + deta * pi[i];          /* Eq. (5) */
         }
@@ -167,6 +183,7 @@ void orc_stats(const orc_params *p, int64_t n, const double *phi, const double *
      * does not depend on the thread count */
     uint64_t *rl = calloc((size_t)rows * 6, sizeof(uint64_t));
     double *rf = calloc((size_t)rows * 2, sizeof(double));
+    double A = orc_force_scale(p, n);
 #pragma omp parallel for schedule(static)
     for (int64_t zy = 0; zy < rows; ++zy) {
         int64_t y = zy % ny, z = zy / ny;
@@ -194,7 +211,7 @@ void orc_stats(const orc_params *p, int64_t n, const double *phi, const double *
             }
             if (wall) {
                 walls++;
-                double V = Vpot(p, phi[i]);
+                double V = A * Vpot(p, phi[i]);
                 if (V > 0.0) ek += 0.5 * pi[i] * pi[i] / V;
             }
         }
@@ -288,10 +305,11 @@ double orc_loss(const orc_params *p, const double *phi)
  * phi_dot^{n-1/2}, so with mu = dL/dphi^{n+1} and nu the adjoint of
  * phi_dot^{n+1/2} from later steps:
  *     w        = nu + deta * mu                          (from Eq. 5)
- *     dL/dphi^n = mu + b_n (Lap^T w - V''(phi^n) w)      (from Eqs. 3, 4)
+ *     dL/dphi^n = mu + b_n (Lap^T w - A_n V''(phi^n) w)  (from Eqs. 3, 4)
  *     nu'      = a_n w                                   (from Eq. 4)
- *     dL/dV0  += -b_n sum_i w_i * d(V'(phi_i))/dV0
- * with a_n = (1-delta_n)/(1+delta_n), b_n = deta/(1+delta_n); the periodic
+ *     dL/dV0  += -b_n A_n sum_i w_i * d(V'(phi_i))/dV0
+ * with a_n = (1-delta_n)/(1+delta_n), b_n = deta/(1+delta_n), A_n the
+ * force's scale-factor power a(eta_n)^beta; the periodic
  * Laplacian is symmetric, so Lap^T = Lap.
  *
  * Checkpointing: (phi, pi) is stored every ckpt_every steps on the way
@@ -358,6 +376,7 @@ int orc_adjoint(const orc_params *p, int64_t n0, int64_t nsteps, int32_t ckpt_ev
             double delta = orc_delta(p, n);
             double a = (1.0 - delta) / (1.0 + delta);
             double b = p->deta / (1.0 + delta);
+            double A = orc_force_scale(p, n);
             for (int64_t i = 0; i < N; ++i) w[i] = nu[i] + p->deta * mu[i];
 #pragma omp parallel for schedule(static)
             for (int64_t zy = 0; zy < ny * nz; ++zy) {
@@ -366,7 +385,7 @@ int orc_adjoint(const orc_params *p, int64_t n0, int64_t nsteps, int32_t ckpt_ev
                 for (int64_t x = 0; x < nx; ++x) {
                     int64_t i = x + nx * (y + ny * z);
                     double lw = laplacian_at(p, w, x, y, z);
-                    mu[i] = mu[i] + b * (lw - d2V(p, ph[i]) * w[i]);
+                    mu[i] = mu[i] + b * (lw - A * d2V(p, ph[i]) * w[i]);
                     double q = ph[i] * ph[i] / (p->phi0 * p->phi0) - 1.0;
                     g += w[i] * dVp_dV0_scale * ph[i] * q;
                 }
@@ -374,6 +393,7 @@ int orc_adjoint(const orc_params *p, int64_t n0, int64_t nsteps, int32_t ckpt_ev
             }
             double g = 0.0;
             for (int64_t r = 0; r < ny * nz; ++r) g += rowg[r];
+            g *= A;
             G -= b * g;
             for (int64_t i = 0; i < N; ++i) nu[i] = a * w[i];
         }

@@ -33,11 +33,17 @@ MUTATIONS = [
     ("kinetic energy without 1/2", "if (V > 0.0) ek += 0.5 * pi[i] * pi[i] / V;",
      "if (V > 0.0) ek += pi[i] * pi[i] / V;"),
     ("wall sites from forward links only", "if (sb != si) wall = 1;", ""),
-    ("adjoint V'' sign", "mu[i] = mu[i] + b * (lw - d2V(p, ph[i]) * w[i]);",
-     "mu[i] = mu[i] + b * (lw + d2V(p, ph[i]) * w[i]);"),
+    ("adjoint V'' sign", "mu[i] = mu[i] + b * (lw - A * d2V(p, ph[i]) * w[i]);",
+     "mu[i] = mu[i] + b * (lw + A * d2V(p, ph[i]) * w[i]);"),
     ("adjoint drops the damping factor", "for (int64_t i = 0; i < N; ++i) nu[i] = a * w[i];",
      "for (int64_t i = 0; i < N; ++i) nu[i] = w[i];"),
     ("adjoint V0 derivative sign", "G -= b * g;", "G += b * g;"),
+    ("force without the scale-factor power", "deta * (lap - A * dV(p, phi[i]))", "deta * (lap - dV(p, phi[i]))"),
+    ("force with a^(beta/2)", "return pow(pow(orc_eta(p, n) / p->eta0, p->m), p->beta);",
+     "return pow(pow(orc_eta(p, n) / p->eta0, p->m), 0.5 * p->beta);"),
+    ("wall potential energy without a^beta", "double V = A * Vpot(p, phi[i]);", "double V = Vpot(p, phi[i]);"),
+    ("adjoint V'' without a^beta", "mu[i] = mu[i] + b * (lw - A * d2V(p, ph[i]) * w[i]);",
+     "mu[i] = mu[i] + b * (lw - d2V(p, ph[i]) * w[i]);"),
 ]
 
 
@@ -57,7 +63,10 @@ def pins():
         ("P10 dx", P.test_p10_area_scales_with_dx),
         ("P11 velocity", lambda: P.test_p11_boosted_wall_velocity((64, 8), 0.3)),
         ("P11 wall sites", P.test_p11_mean_over_wall_sites_only),
-        ("P13 adjoint", lambda: P.test_adjoint_matches_finite_differences(16)),
+        ("P13 adjoint", lambda: P.test_adjoint_matches_finite_differences(16, 3.0, 0.0)),
+        ("P13 adjoint beta", lambda: P.test_adjoint_matches_finite_differences(24, 2.0, 2.0)),
+        ("P14 homogeneous", P.test_p14_beta_force_homogeneous_mode),
+        ("P14 velocity", lambda: P.test_p14_boosted_wall_velocity_with_beta((64, 8), 0.3)),
     ]
 
 

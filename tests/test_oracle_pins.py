@@ -407,6 +407,59 @@ def test_p11_mean_over_wall_sites_only():
 
 # ------------------------------------------------------- split / cadence ----
 
+# -------------------------------------- beta != 0: the physical force ----
+
+def test_p14_beta_force_homogeneous_mode():
+    """P14: with beta != 0 the force of Eq. (2) carries a(eta)^beta with
+    a = (eta/eta0)^m (the exact equations have alpha = beta = 2).  A
+    homogeneous field has zero Laplacian, so the lattice evolution must follow
+    the ODE phi'' + alpha m phi'/eta = -a^beta V'(phi): the oracle's leapfrog
+    (second order; phi_dot^{-1/2} = 0 is phi'(eta0) = -(deta/2) V'(phi(eta0))
+    to that order) agrees with a tight integration of the ODE to 1e-6 at
+    deta = 1e-3 (observed 8e-8, falling 4x per halving of deta), while the
+    same run with the force's power 0 or 1 misses it by more than 0.2."""
+    from scipy.integrate import solve_ivp
+    alpha, m, W0, deta, steps = 2.0, 1.0, 10.0, 1e-3, 3000
+    V0 = O.v0_of_w0(W0)
+    phi_start = 0.5
+
+    def rhs(eta, y):
+        A = (eta ** m) ** 2.0
+        return [y[1], -alpha * m * y[1] / eta - A * 4.0 * V0 * y[0] * (y[0] ** 2 - 1.0)]
+
+    y0 = [phi_start, -0.5 * deta * 4.0 * V0 * phi_start * (phi_start ** 2 - 1.0)]
+    ref = solve_ivp(rhs, (1.0, 1.0 + steps * deta), y0, rtol=1e-12, atol=1e-14, method="DOP853").y[0][-1]
+    end = {}
+    for beta in (2.0, 1.0, 0.0):
+        p = O.params((4, 4), deta=deta, alpha=alpha, m=m, W0=W0, beta=beta)
+        ph, _, _ = O.run(p, np.full(16, phi_start), np.zeros(16), steps)
+        assert np.all(ph == ph[0])            # stays homogeneous
+        end[beta] = ph[0]
+    assert abs(end[2.0] - ref) <= 1e-6
+    assert abs(end[1.0] - ref) > 0.2 and abs(end[0.0] - ref) > 0.2
+
+
+@pytest.mark.parametrize("shape,gv", [((64, 8), 0.3), ((48, 4, 3), 0.6)])
+def test_p14_boosted_wall_velocity_with_beta(shape, gv):
+    """P14: with beta != 0 a static wall solves (1/2) phi'^2 = a^beta V, i.e.
+    it is thinner by a^(beta/2); the same wall boosted to gamma v has
+    (1/2) phi_dot^2 / (a^beta V) = (gamma v)^2 at every site, so Eq. (8)
+    read with the potential energy a^beta V returns (gamma v)^2 at a state
+    where a^beta = 4 (m = 1, beta = 2, eta_n = 2)."""
+    W0 = 6.0
+    A = 4.0
+    W_eff = W0 / math.sqrt(A)
+    wdt = W_eff / math.pi
+    phi, _ = antisymmetric_pair(shape, W_eff)
+    phi = phi.reshape(-1)
+    pi = -(gv / wdt) * (1.0 - phi * phi)
+    p = O.params(shape, deta=0.25, W0=W0, m=1.0, beta=2.0)
+    n = 4                                       # eta_4 = 2, a = 2, a^beta = 4
+    r = O.stats(p, phi, pi, n)
+    assert r["wall_sites"] == 4 * int(np.prod(shape[1:]))
+    assert r["gv2"] == pytest.approx(gv * gv, rel=1e-12)
+
+
 def test_split_run_equivalence_and_cadence():
     """run(a+b) == run(a); run(b) bit for bit, and records fall on n % K == 0."""
     shape = (20, 18)
@@ -439,12 +492,13 @@ def fd_loss(p, phi, pi, steps):
     return O.loss(p, ph)
 
 
-@pytest.mark.parametrize("steps", [16, 48])
-def test_adjoint_matches_finite_differences(steps):
+@pytest.mark.parametrize("steps,alpha,beta", [(16, 3.0, 0.0), (48, 3.0, 0.0), (24, 2.0, 2.0)])
+def test_adjoint_matches_finite_differences(steps, alpha, beta):
     """P13(i): the FP64 adjoint equals central finite differences of the
-    forward oracle (walls still present at these step counts)."""
+    forward oracle (walls still present at these step counts), for the PRS
+    force and for the physical one (alpha = beta = 2)."""
     shape = (32, 32)
-    p = O.params(shape, deta=0.25, m=1.0, W0=10.0)
+    p = O.params(shape, deta=0.25, m=1.0, W0=10.0, alpha=alpha, beta=beta)
     phi = uniform_field(shape, 3).astype(np.float64).reshape(-1)
     pi = np.zeros_like(phi)
     adj = O.adjoint(p, phi, pi, steps, ckpt_every=7)
@@ -461,7 +515,7 @@ def test_adjoint_matches_finite_differences(steps):
         fdp = (fd_loss(p, phi, pi + e, steps) - fd_loss(p, phi, pi - e, steps)) / (2 * eps)
         assert abs(fdp - adj["grad_pi"][i]) <= 1e-6 * max(scale, np.max(np.abs(adj["grad_pi"])))
     # wall thickness W0 (enters only through V0 = pi^2/(2 W0^2))
-    lw = lambda W: fd_loss(O.params(shape, deta=0.25, m=1.0, W0=W), phi, pi, steps)
+    lw = lambda W: fd_loss(O.params(shape, deta=0.25, m=1.0, W0=W, alpha=alpha, beta=beta), phi, pi, steps)
     fdw = (lw(10.0 + eps) - lw(10.0 - eps)) / (2 * eps)
     assert adj["grad_W0"] == pytest.approx(fdw, rel=1e-6)
 
