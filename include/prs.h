@@ -8,15 +8,17 @@
  *
  *   Eq. (1)  V(phi) = V0 (phi^2/phi0^2 - 1)^2
  *   Eq. (2)  phi'' + alpha (d ln a/d ln eta) phi'/eta - Lap phi = -a^beta dV/dphi,
- *            with the PRS choice beta = 0, alpha = 3
+ *            with the PRS choice beta = 0, alpha = 3 (the exact equations
+ *            have alpha = beta = 2); a(eta) = (eta/eta0)^m
  *   Eq. (3)  Lap phi_i = sum_d (phi_{i+e_d} + phi_{i-e_d}) - 2 D phi_i   (/dx^2)
  *   Eq. (4)  phi_dot^{n+1/2} = [(1-delta) phi_dot^{n-1/2}
- *                               + deta (Lap phi^n - V'(phi^n))] / (1+delta)
+ *                               + deta (Lap phi^n - a_n^beta V'(phi^n))] / (1+delta)
  *   Eq. (5)  phi^{n+1} = phi^n + deta phi_dot^{n+1/2}
  *   Eq. (6)  delta = (1/2) alpha (deta/eta) (d ln a/d ln eta)
  *   Eq. (7)  rho = A/V: sum over sign-changing links of
  *            |grad phi| / (|phi_,x| + |phi_,y| + |phi_,z|), times dx^(D-1)/V
  *   Eq. (8)  (gamma v)^2 = (1/N) sum over wall sites of (1/2) phi_dot^2 / V(phi)
+ *            (with beta != 0 the wall's potential energy a_n^beta V(phi))
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -65,7 +67,7 @@ typedef struct prs_params {
     double deta;         /* conformal time step, > 0 */
     double eta0;         /* conformal time of step 0, > 0 */
     double alpha;        /* damping coefficient of Eq. (2); PRS uses 3 */
-    double beta;         /* scale-factor power of the force; only 0 (PRS) */
+    double beta;         /* scale-factor power of the force (0: PRS; 2: the exact equations) */
     double m;            /* era exponent d ln a / d ln eta (a ~ eta^m), >= 0 */
     double W0;           /* wall thickness parameter, > 0 (may be +inf) */
     double phi0;         /* vacuum value, > 0 */
@@ -106,9 +108,12 @@ size_t prs_workspace_bytes(const prs_params* p);
  * Validation (PRS_EINVAL): ndim, sides >= 1, dx, deta, eta0, W0, phi0 > 0,
  * m >= 0, alpha >= 0; the step must be stable for the linearised scheme,
  * deta * sqrt(4 D / dx^2 + 8 V0/phi0^2) < 2, and the first damping factor
- * must satisfy delta_0 = alpha m deta / (2 eta0) < 1.  beta != 0 gives
- * PRS_EUNSUPPORTED; precision must be PRS_F32 or PRS_F64 and reserved 0.
- * The context starts at step 0. */
+ * must satisfy delta_0 = alpha m deta / (2 eta0) < 1; precision must be
+ * PRS_F32 or PRS_F64 and reserved 0; beta finite.  With beta != 0 the force
+ * changes with eta, and prs_step_n, prs_adjoint_forward and prs_batch_run
+ * check the same stability bound with 8 V0 a^beta/phi0^2 at the largest
+ * force of the call (PRS_EINVAL before any launch).  The persistent batch
+ * modes take beta = 0 only.  The context starts at step 0. */
 prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi,
                     void* workspace, size_t ws_bytes, void* hip_stream, prs_ctx** out);
 

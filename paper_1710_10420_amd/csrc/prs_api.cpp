@@ -96,8 +96,7 @@ prs_status validate(const prs_params* p)
     if (p->precision != PRS_F32 && p->precision != PRS_F64)
         return fail(PRS_EINVAL, "precision must be PRS_F32 or PRS_F64 (got %d)", p->precision);
     if (p->reserved != 0) return fail(PRS_EINVAL, "reserved must be 0");
-    if (p->beta != 0.0)
-        return fail(PRS_EUNSUPPORTED, "only the PRS force (beta = 0) is implemented (got beta = %g)", p->beta);
+    if (!std::isfinite(p->beta)) return fail(PRS_EINVAL, "beta must be finite");
     const double V0 = v0_of(*p);
     const double w2 = 4.0 * p->ndim / (p->dx * p->dx) + 8.0 * V0 / (p->phi0 * p->phi0);
     if (!(p->deta * std::sqrt(w2) < 2.0))
@@ -212,6 +211,14 @@ struct prs_ctx {
 
 namespace {
 
+// a(eta_n)^beta with a(eta) = (eta/eta0)^m: the scale-factor power of the
+// force of Eq. (2) at step n; exactly 1 for the PRS choice beta = 0.
+double force_scale(const prs_params& p, int64_t n)
+{
+    if (p.beta == 0.0) return 1.0;
+    return std::pow(std::pow((p.eta0 + (double)n * p.deta) / p.eta0, p.m), p.beta);
+}
+
 StepCoef64 coef_for(const prs_ctx* c, int64_t n)
 {
     const prs_params& p = c->p;
@@ -221,10 +228,25 @@ StepCoef64 coef_for(const prs_ctx* c, int64_t n)
     k.a = (1.0 - delta) / (1.0 + delta);
     k.b = p.deta / (1.0 + delta);
     k.deta = p.deta;
-    k.F = 4.0 * c->V0 / (p.phi0 * p.phi0);
+    k.F = 4.0 * c->V0 / (p.phi0 * p.phi0) * force_scale(p, n);
     k.kc = 1.0 / (p.phi0 * p.phi0);
     k.inv_dx2 = 1.0 / (p.dx * p.dx);
     return k;
+}
+
+// With beta != 0 the force grows (beta m > 0) or shrinks with eta; the
+// linearised stability bound of prs_init, deta sqrt(4D/dx^2 + V''(phi0)
+// a^beta) < 2 with V''(phi0) = 8 V0/phi0^2, is checked at the largest force a
+// call reaches (its first or its last step).
+prs_status check_stable_until(const prs_params& p, double V0, int64_t n_last)
+{
+    if (p.beta == 0.0) return PRS_OK;
+    const double A = std::max(force_scale(p, n_last), force_scale(p, 0));
+    const double w2 = 4.0 * p.ndim / (p.dx * p.dx) + 8.0 * V0 / (p.phi0 * p.phi0) * A;
+    if (!(p.deta * std::sqrt(w2) < 2.0))
+        return fail(PRS_EINVAL, "unstable step %lld with beta = %g: deta*sqrt(4D/dx^2 + 8 V0 a^beta/phi0^2) = %g "
+                    "must be < 2", (long long)n_last, p.beta, p.deta * std::sqrt(w2));
+    return PRS_OK;
 }
 
 // The float32 rounding a float32 launch applies (batched descriptors hold
@@ -234,10 +256,12 @@ StepCoef f32_of(const StepCoef64& k)
     return StepCoef{(float)k.a, (float)k.b, (float)k.deta, (float)k.F, (float)k.kc, (float)k.inv_dx2};
 }
 
-DiagCoef diag_coef(const prs_ctx* c)
+// Diagnostics of state n: the wall's potential energy in Eq. (8) is
+// a(eta_n)^beta V (a static wall has (1/2) phi'^2 = a^beta V).
+DiagCoef diag_coef(const prs_ctx* c, int64_t n)
 {
     DiagCoef d;
-    d.V0 = c->V0;
+    d.V0 = c->V0 * force_scale(c->p, n);
     d.kc = 1.0 / (c->p.phi0 * c->p.phi0);
     return d;
 }
@@ -339,7 +363,10 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     const int64_t need = want ? prs_records_in(&c->p, c->step, nsteps) : 0;
     if (want && cap < need)
         return fail(PRS_EINVAL, "series capacity %lld < %lld records", (long long)cap, (long long)need);
-    const DiagCoef dc = diag_coef(c);
+    if (nsteps > 0) {
+        prs_status st = check_stable_until(c->p, c->V0, c->step + nsteps - 1);
+        if (st != PRS_OK) return st;
+    }
     const double ascale = area_scale(c->p);
     const TileCounts tc = tile_counts(c->geo, c->til);
     const int64_t K = c->p.diag_every;
@@ -354,6 +381,7 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
         const int64_t n = c->step;
         const bool diag = want && (n % K == 0);
         WavePartial* parts = diag ? c->partials : nullptr;
+        const DiagCoef dc = diag_coef(c, n);
         int64_t ntiles = tc.ntiles;
         if (L > 1) {
             StepCoef64 k[kMaxPassSteps];
@@ -429,7 +457,7 @@ prs_status prs_wall_stats(prs_ctx* c, prs_stats* out)
     const TileCounts tc = tile_counts(c->geo, c->til);
     const int64_t n = c->step;
     HIP_TRY(launch_step(c->geo, c->til, c->phi[c->cur], nullptr, c->pi, nullptr, coef_for(c, n), false, true,
-                        c->partials, diag_coef(c), c->stream),
+                        c->partials, diag_coef(c, n), c->stream),
             "diagnostics kernel launch");
     HIP_TRY(launch_finalize(c->partials, tc.ntiles, c->drec, n, c->p.eta0 + (double)n * c->p.deta,
                             area_scale(c->p), c->stream),
@@ -678,10 +706,11 @@ AdjCoef64 adj_coef(const prs_ctx* c, int64_t n, bool last)
     k.a = (1.0 - delta) / (1.0 + delta);
     k.b = b;
     k.cw = last ? 0.0 : p.deta;
-    k.F = 4.0 * c->V0 * kc;
+    const double A = force_scale(p, n);
+    k.F = 4.0 * c->V0 * kc * A;
     k.kc = kc;
     k.inv_dx2 = 1.0 / (p.dx * p.dx);
-    k.gscale = -4.0 * kc * b;
+    k.gscale = -4.0 * kc * b * A;
     return k;
 }
 
@@ -699,6 +728,8 @@ prs_status prs_adjoint_forward(prs_ctx* c, int64_t nsteps, int32_t ckpt_every, v
                                size_t work_bytes, double* loss)
 {
     prs_status st = check_adj_args(c, nsteps, ckpt_every);
+    if (st != PRS_OK) return st;
+    st = check_stable_until(c->p, c->V0, c->step + nsteps - 1);
     if (st != PRS_OK) return st;
     if (!work || ((uintptr_t)work % kAlign) != 0) return fail(PRS_EINVAL, "work must be 256-byte aligned");
     const AdjLayout L = adj_layout(c->p, nsteps, ckpt_every, c->partial_cap);
@@ -1163,8 +1194,8 @@ prs_status batch_item_pass(prs_batch* b, ItemCursor& cur, hipStream_t s)
     void* pi_next = e.alt ? dphi : alt;
     const bool diag = e.rec >= 0;
     WavePartial* parts = diag ? reinterpret_cast<WavePartial*>(base + b->off_part + b->part_off[r]) : nullptr;
-    const DiagCoef dc = diag_coef(&cur.coef);
     const int64_t n = e.first;
+    const DiagCoef dc = diag_coef(&cur.coef, n);
     void* phi_in = phi[idx & 1];
     void* phi_out = phi[(idx + 1) & 1];
     int64_t ntiles = tile_counts(g, t).ntiles;
@@ -1285,7 +1316,7 @@ prs_status batch_upload(prs_batch* b)
                         static_cast<float*>(it.phi_a), static_cast<float*>(it.phi_b),
                         static_cast<float*>(it.dphi), alt, dcoef, dpass, (int64_t)plan.size(), p0, p1, recs,
                         tile_base, it.p.eta0, it.p.deta, area_scale(it.p), f32_of(coef_for(&tmp, 0)),
-                        diag_coef(&tmp));
+                        diag_coef(&tmp, 0));
         tile_base += batch_tiles_max(b->geo[r], b->til[r]);
     }
     b->total_tiles = tile_base;
@@ -1470,13 +1501,20 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     if (series && cap < b->total_recs)
         return fail(PRS_EINVAL, "series capacity %lld < %lld records", (long long)cap, (long long)b->total_recs);
     const bool persistent = persistent_mode(b->mode);
+    for (int32_t r = 0; r < b->count; ++r) {
+        const prs_batch_item& it = b->items[r];
+        if (it.nsteps > 0) {
+            prs_status st = check_stable_until(it.p, v0_of(it.p), it.nsteps - 1);
+            if (st != PRS_OK) return st;
+        }
+    }
     if (persistent) {
         for (int32_t r = 0; r < b->count; ++r)
             if (b->til[r].ty != 1 || b->tblock[r] > (b->items[r].p.ndim == 2 ? 2 : 1) ||
-                b->items[r].p.precision != PRS_F32)
+                b->items[r].p.precision != PRS_F32 || b->items[r].p.beta != 0.0)
                 return fail(PRS_EINVAL,
-                            "item %d: the persistent modes need float32, ty = 1 and at most 2 steps per pass "
-                            "(single steps in 3D)", r);
+                            "item %d: the persistent modes need float32, beta = 0, ty = 1 and at most 2 steps per "
+                            "pass (single steps in 3D)", r);
     }
     if (b->graph_mode != b->mode) batch_release_graph(b);
     if (b->dirty && persistent) {

@@ -1169,8 +1169,8 @@ struct TBAArgs {
     int64_t nx, ny;
     int64_t tiles_x, ntiles;
     int64_t rows;
-    R a[T], b[T], cw[T];
-    R F, kc, inv_dx2;
+    R a[T], b[T], cw[T], F[T];  // F carries the step's a(eta)^beta
+    R kc, inv_dx2;
     double gscale[T];
 };
 
@@ -1232,7 +1232,7 @@ __device__ __forceinline__ void tba_iter(const TBAArgs<T, R>& A, const TBLane& L
             const R xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
             const R xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
             const R gp = adj_site<2, UNIT>(w, nsum2(xm, xp, cm[j], cp[j]), mp[j], ph[j], A.a[k - 1], A.b[k - 1],
-                                           A.cw[k - 1], A.F, A.kc, A.inv_dx2, out_w[j], out_mu[j]);
+                                           A.cw[k - 1], A.F[k - 1], A.kc, A.inv_dx2, out_w[j], out_mu[j]);
             g += (double)gp;
         }
         // own_row is wave-uniform; lanes outside the owned columns add g * 0
@@ -1645,8 +1645,8 @@ struct TBA3Args {
     int64_t nx, ny, nz;
     int64_t tiles_x, tiles_y, ntiles;
     int64_t rows;
-    R a[T], b[T], cw[T];
-    R F, kc, inv_dx2;
+    R a[T], b[T], cw[T], F[T];
+    R kc, inv_dx2;
     double gscale[T];
 };
 
@@ -1713,8 +1713,8 @@ __device__ __forceinline__ void tba3_iter(const TBA3Args<T, R>& A, const TB3Lane
                 const R xm = j > 0 ? cc[r][j > 0 ? j - 1 : 0] : left;
                 const R xp = j < VEC - 1 ? cc[r][j < VEC - 1 ? j + 1 : j] : right;
                 const R gp = adj_site<3, UNIT>(w, nsum3(xm, xp, cc[r - 1][j], cc[r + 1][j], cm[r][j], cp[r][j]),
-                                               mp[r][j], ph[r][j], A.a[k - 1], A.b[k - 1], A.cw[k - 1], A.F, A.kc,
-                                               A.inv_dx2, out_w[j], out_mu[j]);
+                                               mp[r][j], ph[r][j], A.a[k - 1], A.b[k - 1], A.cw[k - 1], A.F[k - 1],
+                                               A.kc, A.inv_dx2, out_w[j], out_mu[j]);
                 gr += (double)gp;
             }
             // owned rows only (a wave-uniform factor: no per-lane select)
@@ -2195,9 +2195,9 @@ hipError_t launch_tba_t(const Geometry& g, const Tiling& t, const void* w_in, vo
         A.a[i] = (R)c[i].a;
         A.b[i] = (R)c[i].b;
         A.cw[i] = (R)c[i].cw;
+        A.F[i] = (R)c[i].F;
         A.gscale[i] = c[i].gscale;
     }
-    A.F = (R)c[0].F;
     A.kc = (R)c[0].kc;
     A.inv_dx2 = (R)c[0].inv_dx2;
     A.gacc = gacc;
@@ -2357,9 +2357,9 @@ hipError_t launch_tba3_t(const Geometry& g, const Tiling& t, const void* w_in, v
         A.a[i] = (R)c[i].a;
         A.b[i] = (R)c[i].b;
         A.cw[i] = (R)c[i].cw;
+        A.F[i] = (R)c[i].F;
         A.gscale[i] = c[i].gscale;
     }
-    A.F = (R)c[0].F;
     A.kc = (R)c[0].kc;
     A.inv_dx2 = (R)c[0].inv_dx2;
     A.gacc = gacc;

@@ -583,9 +583,9 @@ class Batch:
     """An ensemble of realisations run by prs_batch_run.
 
     specs: list of dicts with keys shape, deta, nsteps and optionally m, W0,
-    alpha, dx, eta0, diag_every, seed (the initial field is drawn from the seed
-    at every run, dphi = 0) and precision (PRS_F32 or PRS_F64; float64 items
-    run in the stream modes)."""
+    alpha, beta, dx, eta0, diag_every, seed (the initial field is drawn from
+    the seed at every run, dphi = 0) and precision (PRS_F32 or PRS_F64;
+    float64 items and beta != 0 run in the stream modes)."""
 
     def __init__(self, specs, device="cuda", stream=None):
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
@@ -596,7 +596,7 @@ class Batch:
         with torch.cuda.stream(self.stream):
             for sp in specs:
                 p = make_params(sp["shape"], deta=sp["deta"], m=sp.get("m", 1.0), W0=sp.get("W0", 10.0),
-                                alpha=sp.get("alpha", 3.0), dx=sp.get("dx", 1.0),
+                                alpha=sp.get("alpha", 3.0), beta=sp.get("beta", 0.0), dx=sp.get("dx", 1.0),
                                 eta0=sp.get("eta0", 1.0), diag_every=sp.get("diag_every", 0),
                                 precision=sp.get("precision", PRS_F32))
                 n = sites(p)

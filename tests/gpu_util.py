@@ -23,11 +23,13 @@ def gpu_prs():
     return prs
 
 
-def params_pair(shape, deta, m=1.0, W0=10.0, alpha=3.0, dx=1.0, diag_every=0, eta0=1.0):
+def params_pair(shape, deta, m=1.0, W0=10.0, alpha=3.0, dx=1.0, diag_every=0, eta0=1.0, beta=0.0,
+                precision=None):
     prs = gpu_prs()
+    kw = {} if precision is None else {"precision": precision}
     gp = prs.make_params(shape, deta=deta, m=m, W0=W0, alpha=alpha, dx=dx, diag_every=diag_every,
-                         eta0=eta0)
-    op = O.params(shape, deta=deta, m=m, W0=W0, alpha=alpha, dx=dx, eta0=eta0)
+                         eta0=eta0, beta=beta, **kw)
+    op = O.params(shape, deta=deta, m=m, W0=W0, alpha=alpha, dx=dx, eta0=eta0, beta=beta)
     return gp, op
 
 

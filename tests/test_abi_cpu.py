@@ -55,7 +55,7 @@ def test_workspace_and_records():
     ("eta0", 0.0, prs.PRS_EINVAL),
     ("m", -1.0, prs.PRS_EINVAL),
     ("W0", 0.0, prs.PRS_EINVAL),
-    ("beta", 2.0, prs.PRS_EUNSUPPORTED),
+    ("beta", float("nan"), prs.PRS_EINVAL),
     ("phi0", -1.0, prs.PRS_EINVAL),
     ("precision", 2, prs.PRS_EINVAL),
     ("reserved", 1, prs.PRS_EINVAL),
@@ -67,6 +67,13 @@ def test_invalid_params_rejected_before_launch(field, value, code):
     with pytest.raises(prs.PRSError) as e:
         prs.prs_init(p, 16, 32, 48, 256, 1 << 30, None)
     assert e.value.status == code
+
+
+def test_beta_is_accepted():
+    """The physical force (alpha = beta = 2) is a valid parameter set."""
+    p = c1()
+    p.alpha, p.beta = 2.0, 2.0
+    assert prs.prs_workspace_bytes(p) > 0
 
 
 def test_first_damping_factor_bound():
