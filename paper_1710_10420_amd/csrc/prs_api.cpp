@@ -516,6 +516,35 @@ prs_status prs_set_adjoint_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t
     return PRS_OK;
 }
 
+prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows, int32_t ty,
+                         const void* phi_in, void* phi_out, const void* pi_in, void* pi_out, void* hip_stream)
+{
+    prs_status st = validate(p);
+    if (st != PRS_OK) return st;
+    if (p->ndim != 3) return fail(PRS_EINVAL, "slab passes are for 3D lattices (slabs along z)");
+    if (n0 < 0) return fail(PRS_EINVAL, "n0 must be >= 0");
+    if (!phi_in || !phi_out || !pi_in || !pi_out) return fail(PRS_EINVAL, "NULL buffer");
+    if (!aligned16(phi_in) || !aligned16(phi_out) || !aligned16(pi_in) || !aligned16(pi_out))
+        return fail(PRS_EINVAL, "field buffers must be 16-byte aligned");
+    if (phi_in == phi_out || pi_in == pi_out || phi_in == pi_in || phi_out == pi_out)
+        return fail(PRS_EINVAL, "the four slab buffers must be distinct");
+    const Geometry g = geometry_of(*p);
+    const Tiling t{vec, rows, ty};
+    if (!tb_supported(g)) return fail(PRS_EUNSUPPORTED, "slab passes need planes shorter than 2^31 bytes");
+    if (!tiling_supported(g, t) || !tb_pass_supported(g, t, steps))
+        return fail(PRS_EINVAL, "no %d-step 3D pass kernel for vec=%d rows=%d ty=%d", steps, vec, rows, ty);
+    prs_ctx tmp{};
+    tmp.p = *p;
+    tmp.V0 = v0_of(*p);
+    st = check_stable_until(*p, tmp.V0, n0 + steps - 1);
+    if (st != PRS_OK) return st;
+    StepCoef64 k[kMaxPassSteps];
+    for (int i = 0; i < steps; ++i) k[i] = coef_for(&tmp, n0 + i);
+    HIP_TRY(launch_tb_slab(steps, g, t, phi_in, phi_out, pi_in, pi_out, k, static_cast<hipStream_t>(hip_stream)),
+            "slab pass launch");
+    return PRS_OK;
+}
+
 prs_status prs_set_recompute_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t ty, int32_t steps_per_pass)
 {
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");

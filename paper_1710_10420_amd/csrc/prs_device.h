@@ -1378,6 +1378,7 @@ struct TB3Args {
     int64_t nx, ny, nz;
     int64_t tiles_x, tiles_y, ntiles;
     int64_t rows;               // planes per tile along z
+    int32_t zhalo;              // 0: periodic in z; T: a z-slab stored with T halo planes below and above
     StepCoefT<R> k[T];
     DiagCoef dc;
 };
@@ -1399,6 +1400,8 @@ struct TB3Lane {
     uint32_t plane_bytes;
     uint64_t plane;             // sites per plane
     int32_t nz;
+    int32_t zwrap;              // plane count the march wraps at (none for a slab)
+    int32_t zoff;               // stored plane of plane z is z + zoff (slab halo depth, else 0)
     int32_t s0, s1;             // output planes [s0, s1) of the tile
     int32_t yown;               // owned rows inside the lattice
     bool own_lane;
@@ -1425,8 +1428,8 @@ __device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T
     const uint32_t nb = i < last ? L.plane_bytes : 0u;
     tb3_load<VEC, T, TY>(A.phi_in, rw.phi, L, nb, 0, NY, S.in[(U + 2) & 3]);
     tb3_load<VEC, T, TY>(A.pi_in, rw.pi, L, nb, 1, NY - 1, S.pin[(U + 1) & 1]);
-    rw.phi = next_row(rw.phi, L.nz);
-    rw.pi = next_row(rw.pi, L.nz);
+    rw.phi = next_row(rw.phi, L.zwrap);
+    rw.pi = next_row(rw.pi, L.zwrap);
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
         if (CHECK && i < 2 * (k - 1)) continue;
@@ -1450,7 +1453,7 @@ __device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T
         // level T plane s0 + i - (2T - 2), inside [s0, s1) once i >= 2T - 2
         const int32_t zout = L.s0 + i - (2 * T - 2);
         const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.plane_bytes : 0u;
-        const size_t obase = (size_t)(uint32_t)(CHECK && i < 2 * T - 2 ? L.s0 : zout) * L.plane;
+        const size_t obase = (size_t)(uint32_t)((CHECK && i < 2 * T - 2 ? L.s0 : zout) + L.zoff) * L.plane;
 #pragma unroll
         for (int r = k; r < NY - k; ++r) {
             const R left = from_left_lane(cc[r][VEC - 1]);
@@ -1484,7 +1487,7 @@ __device__ __forceinline__ void tb3_iter(const TB3Args<T, R>& A, const TB3Lane<T
                     if (r >= T && r < T + TY) {
                         const int32_t e = i - (T + k - 2);
                         const bool in = e >= 0 && e < L.s1 - L.s0;
-                        const size_t lb = (size_t)(uint32_t)(in ? L.s0 + e : L.s0) * L.plane;
+                        const size_t lb = (size_t)(uint32_t)((in ? L.s0 + e : L.s0) + L.zoff) * L.plane;
                         const uint32_t so = L.srow[r - T < TY ? (r - T >= 0 ? r - T : 0) : 0];
                         buf_store<VEC>(A.phi_lv[k < T ? k - 1 : 0] + lb, in ? L.plane_bytes : 0u, so, out_phi);
                     }
@@ -1545,6 +1548,10 @@ __device__ __forceinline__ void tb3_tile(const TB3Args<T, R>& A, int64_t tile)
     const int32_t rows = (int32_t)A.rows;
     L.s0 = (int32_t)tz * rows;
     L.s1 = L.s0 + rows < L.nz ? L.s0 + rows : L.nz;
+    // a slab reads its T halo planes instead of wrapping around
+    L.zoff = A.zhalo;
+    L.zwrap = A.zhalo ? 0x7FFFFFFF : L.nz;
+    auto zplane = [&](int32_t z) { return A.zhalo ? z + A.zhalo : wrap_row(z, L.nz); };
 
     TB3State<VEC, T, TY, R> S;
 #pragma unroll
@@ -1570,13 +1577,13 @@ __device__ __forceinline__ void tb3_tile(const TB3Args<T, R>& A, int64_t tile)
 
     // iteration 0 (z0 = s0 - T + 1) needs phi^n planes z0-1 .. z0+1 and phi_dot plane z0
     const int32_t z0 = L.s0 - T + 1;
-    tb3_load<VEC, T, TY>(A.phi_in, wrap_row(z0 - 1, L.nz), L, L.plane_bytes, 0, NY, S.in[3]);
-    tb3_load<VEC, T, TY>(A.phi_in, wrap_row(z0, L.nz), L, L.plane_bytes, 0, NY, S.in[0]);
-    tb3_load<VEC, T, TY>(A.phi_in, wrap_row(z0 + 1, L.nz), L, L.plane_bytes, 0, NY, S.in[1]);
-    tb3_load<VEC, T, TY>(A.pi_in, wrap_row(z0, L.nz), L, L.plane_bytes, 1, NY - 1, S.pin[0]);
+    tb3_load<VEC, T, TY>(A.phi_in, zplane(z0 - 1), L, L.plane_bytes, 0, NY, S.in[3]);
+    tb3_load<VEC, T, TY>(A.phi_in, zplane(z0), L, L.plane_bytes, 0, NY, S.in[0]);
+    tb3_load<VEC, T, TY>(A.phi_in, zplane(z0 + 1), L, L.plane_bytes, 0, NY, S.in[1]);
+    tb3_load<VEC, T, TY>(A.pi_in, zplane(z0), L, L.plane_bytes, 1, NY - 1, S.pin[0]);
     TBRows rw;
-    rw.phi = wrap_row(z0 + 2, L.nz);
-    rw.pi = wrap_row(z0 + 1, L.nz);
+    rw.phi = zplane(z0 + 2);
+    rw.pi = zplane(z0 + 1);
 
     DiagAcc acc;
     acc.links[0] = acc.links[1] = acc.links[2] = 0u;
@@ -2246,9 +2253,10 @@ __host__ __device__ __forceinline__ int tb3_rows(int ty)
 template <typename R, int VEC, int T, int TY>
 hipError_t launch_tb3_t(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi_in,
                         void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials, const DiagCoef& dc,
-                        hipStream_t s)
+                        hipStream_t s, int zhalo = 0)
 {
     TB3Args<T, R> A;
+    A.zhalo = zhalo;
     A.phi_in = static_cast<const R*>(phi_in);
     A.phi_out = static_cast<R*>(phi_out);
     A.pi_in = static_cast<const R*>(pi_in);
@@ -2283,17 +2291,20 @@ constexpr bool tb3_combo_ok(int vec, int T, int TY)
     return (T == 2 || T == 3) && ((vec == 1 && (TY == 4 || TY == 8)) || (vec == 2 && TY == 4));
 }
 
+// zhalo = T: the lattice is a z-slab stored with T halo planes below and
+// above (plane z at z + T), which the march reads instead of wrapping.
 template <typename R>
 hipError_t launch_tb3d_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
                          const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
-                         const DiagCoef& dc, hipStream_t s)
+                         const DiagCoef& dc, hipStream_t s, int zhalo = 0)
 {
     const int TY = tb3_rows(t.ty);
     if (!tb3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
 #define PRS_TB3(V, TT, YY)                                                                                   \
     if (t.vec == V && T == TT && TY == YY) {                                                                  \
         if constexpr (tb3_combo_ok<R>(V, TT, YY))                                                             \
-            return launch_tb3_t<R, V, TT, YY>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s); \
+            return launch_tb3_t<R, V, TT, YY>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, \
+                                              zhalo);                                                         \
     }
     PRS_TB3(1, 2, 4)
     PRS_TB3(1, 2, 8)
@@ -2319,6 +2330,7 @@ hipError_t launch_tb3_all_t(const Geometry& g, const Tiling& t, const void* phi_
                             const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
 {
     TB3Args<T, R> A;
+    A.zhalo = 0;
     A.phi_in = static_cast<const R*>(phi_in);
     A.phi_out = static_cast<R*>(phi_lv[T - 1]);
     for (int i = 0; i < T; ++i) A.phi_lv[i] = static_cast<R*>(phi_lv[i]);

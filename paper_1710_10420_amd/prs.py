@@ -151,6 +151,7 @@ _decl("prs_get_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_set_adjoint_time_blocking", _i32, _vp, _i32)
 _decl("prs_get_adjoint_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_set_recompute_tiling", _i32, _vp, _i32, _i32, _i32, _i32)
+_decl("prs_slab_pass", _i32, _P, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp)
 _decl("prs_get_recompute_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
       ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
@@ -167,7 +168,7 @@ EXPORTED = [
     "prs_set_time_blocking", "prs_get_time_blocking", "prs_set_adjoint_tiling",
     "prs_get_adjoint_tiling", "prs_plan_passes", "prs_fill_uniform_f64",
     "prs_set_adjoint_time_blocking", "prs_get_adjoint_time_blocking",
-    "prs_set_recompute_tiling", "prs_get_recompute_tiling",
+    "prs_set_recompute_tiling", "prs_get_recompute_tiling", "prs_slab_pass",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -309,6 +310,13 @@ def prs_get_recompute_tiling(ctx):
     v = [_i32() for _ in range(4)]
     _check(_lib.prs_get_recompute_tiling(ctx, *(ctypes.byref(x) for x in v)), "prs_get_recompute_tiling")
     return tuple(x.value for x in v)
+
+
+def prs_slab_pass(p, n0, steps, tiling, phi_in, phi_out, pi_in, pi_out, stream):
+    """One multi-step pass over a 3D z-slab stored with `steps` halo planes
+    below and above (device pointers; see include/prs.h)."""
+    _check(_lib.prs_slab_pass(ctypes.byref(p), n0, steps, tiling[0], tiling[1], tiling[2], phi_in, phi_out,
+                              pi_in, pi_out, stream), "prs_slab_pass")
 
 
 def prs_plan_passes(ctx, nsteps, with_records=True):
