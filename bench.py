@@ -242,6 +242,55 @@ def table1_leg(prs):
     return out
 
 
+SLAB = dict(shape=(1024, 1024, 128), deta=0.2, m=1.0, W0=10.0, T=3, tiling=(2, 64, 2), passes=20)
+XGMI_LINK_GBS = 153.0          # one MI355X xGMI link, per direction (published)
+
+
+def slab_leg(prs, torch, reps=2):
+    """The per-device kernel of a 1024^3 lattice sharded along z over eight
+    devices: a 1024 x 1024 x 128 slab stored with T = 3 halo planes below and
+    above, advanced by three-step slab passes (the halos are those a neighbour
+    would send; here they stay as initialised).  Reports the slab's
+    site-update rate and what one halo exchange per pass would cost on one
+    xGMI link."""
+    nx, ny, nz = SLAB["shape"]
+    T = SLAB["T"]
+    p = prs.make_params(SLAB["shape"], deta=SLAB["deta"], m=SLAB["m"], W0=SLAB["W0"])
+    n_ext = nx * ny * (nz + 2 * T)
+    f = [torch.empty(n_ext, dtype=torch.float32, device="cuda") for _ in range(4)]
+    stream = torch.cuda.current_stream()
+    s = prs._stream_handle(stream)
+    prs.prs_fill_uniform(f[0].data_ptr(), n_ext, 1, s)
+    f[2].zero_()
+    f[1].copy_(f[0])
+    f[3].zero_()
+    times = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        a, b, pa, pb = f
+        for k in range(SLAB["passes"]):
+            prs.prs_slab_pass(p, k * T, T, SLAB["tiling"], a.data_ptr(), b.data_ptr(), pa.data_ptr(),
+                              pb.data_ptr(), s)
+            a, b, pa, pb = b, a, pb, pa
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1))
+    ms = min(times)
+    su = float(nx * ny * nz) * T * SLAB["passes"]
+    halo_bytes = 2 * 2 * T * nx * ny * 4          # phi and phi_dot, T planes, both faces
+    out = {"workload": "1024x1024x128 z-slab (1/8 of 1024^3) with 3 halo planes per face, three-step passes, "
+                       "tiling (2, 64, 2), 20 passes",
+           "ms_per_pass": ms / SLAB["passes"], "site_updates_per_s": su / (ms / 1e3),
+           "halo_bytes_per_pass": halo_bytes,
+           "halo_exchange_ms_one_link": halo_bytes / (XGMI_LINK_GBS * 1e9) * 1e3}
+    log("slab %.3f ms per pass" % (ms / SLAB["passes"]))
+    del f
+    torch.cuda.empty_cache()
+    return out
+
+
 F64_STEPS = 2048
 
 
@@ -387,6 +436,7 @@ def main():
         out["batch"] = batch_leg(prs, torch)
         out["f64"] = f64_leg(prs, torch, w)
         out["table1"] = table1_leg(prs)
+        out["slab"] = slab_leg(prs, torch)
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
