@@ -173,26 +173,43 @@ def test_prsloss_autograd():
     assert float(W0.grad) / 2.0 == pytest.approx(ref["grad_W0"], rel=1e-3)
 
 
-@pytest.mark.parametrize("shape,nsteps,K", [((2048, 2048), 64, 64), ((256, 256, 256), 16, 8)])
-def test_adjoint_full_size(shape, nsteps, K):
-    """The adjoint at the full lattice sizes (2048^2, 256^3) and the tiling
-    the benchmark uses, over runs the oracle finishes in seconds."""
+@pytest.mark.parametrize("shape,nsteps,K,tuned", [
+    ((2048, 2048), 64, 64, ((2, 16, 1), 8, (1, 32, 1), 8)),
+    ((256, 256, 256), 16, 8, ((1, 16, 4), 3, (1, 16, 2), 3)),
+])
+def test_adjoint_full_size(shape, nsteps, K, tuned):
+    """The adjoint at the full lattice sizes (2048^2, 256^3), over runs the
+    oracle finishes in seconds, with the library defaults and with the
+    configuration the benchmark's tuners pick (forward and recomputation
+    tiling and steps per pass, reverse tiling and steps per pass)."""
     say("adjoint full size", shape)
     torch = torch_mod()
+    prs = gpu_prs()
     deta = 0.25 if len(shape) == 2 else 0.2
     gp, op = params_pair(shape, deta, m=1.0, W0=10.0)
     phi0 = uniform_field(shape, 7)
-    loss, gphi, gdphi, gw, sim = gpu_adjoint(gp, phi0, nsteps, K)
-    say("  tiling", sim.tiling())
     O.set_threads(16)
     ref = O.adjoint(op, phi0.astype(np.float64).reshape(-1), np.zeros(phi0.size), nsteps,
                     ckpt_every=K)
-    assert loss == pytest.approx(ref["loss"], rel=1e-5)
-    assert rel_l2(gphi, ref["grad_phi"]) <= 1e-4
-    assert rel_l2(gdphi, ref["grad_pi"]) <= 1e-4
-    assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
-    del sim
-    torch.cuda.empty_cache()
+    for cfg in (None, tuned):
+        sim = prs.Sim(gp, phi0=to_dev(phi0))
+        if cfg is not None:
+            sim.set_tiling(*cfg[0])
+            sim.set_time_blocking(cfg[1])
+            prs.prs_set_adjoint_tiling(sim.ctx, *cfg[2])
+            prs.prs_set_adjoint_time_blocking(sim.ctx, cfg[3])
+        say("  tiling", sim.tiling(), "steps/pass", sim.time_blocking())
+        nb = prs.prs_adjoint_workspace_bytes(gp, nsteps, K)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        gphi = torch.empty_like(sim.phi_a)
+        gdphi = torch.empty_like(sim.phi_a)
+        loss, gw = prs.prs_adjoint(sim.ctx, nsteps, K, work.data_ptr(), nb, gphi.data_ptr(), gdphi.data_ptr())
+        assert loss == pytest.approx(ref["loss"], rel=1e-5), cfg
+        assert rel_l2(host(gphi), ref["grad_phi"]) <= 1e-4, cfg
+        assert rel_l2(host(gdphi), ref["grad_pi"]) <= 1e-4, cfg
+        assert gw == pytest.approx(ref["grad_W0"], rel=1e-3), cfg
+        del sim, work, gphi, gdphi
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("shape", [(200, 130), (40, 36, 30)])
