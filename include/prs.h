@@ -225,19 +225,20 @@ prs_status prs_set_recompute_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int
 prs_status prs_get_recompute_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty,
                                     int32_t* steps_per_pass);
 
-/* One multi-step pass over a z-slab of a 3D lattice: the per-device kernel
- * of a lattice sharded along z (each device holds a slab and exchanges halo
- * planes with its neighbours between passes; this library does not
- * communicate).  p describes the slab: n[0] x n[1] sites per plane, n[2]
- * interior planes, and the run's physics; n0 is the global step of the
- * pass's first step (it sets the coefficients).  phi_in/pi_in hold
- * phi^{n0} and phi_dot^{n0-1/2} on n[2] + 2*steps planes: plane k is global
- * plane z0 - steps + k, so the first and last `steps` planes are the halo
- * the caller filled from the neighbouring slabs (for a single slab of a
- * periodic lattice: its periodic images).  phi_out/pi_out, with the same
- * layout, receive phi^{n0+steps} and phi_dot^{n0+steps-1/2} on their
- * interior planes steps .. steps+n[2]-1 only; y and x stay periodic.  steps
- * and the tiling must have a 3D multi-step kernel (see
+/* One multi-step pass over a slab of a lattice cut along its last axis
+ * (y in 2D, z in 3D): the per-device kernel of a lattice sharded along that
+ * axis (each device holds a slab and exchanges halo rows or planes with its
+ * neighbours between passes; this library does not communicate).  p
+ * describes the slab: n[ndim-1] interior rows (2D) or planes (3D) of the
+ * other extents, and the run's physics; n0 is the global step of the pass's
+ * first step (it sets the coefficients).  phi_in/pi_in hold phi^{n0} and
+ * phi_dot^{n0-1/2} on n[ndim-1] + 2*steps rows or planes: row or plane k is
+ * global z0 - steps + k, so the first and last `steps` are the halo the
+ * caller filled from the neighbouring slabs (for a single slab of a periodic
+ * lattice: its periodic images).  phi_out/pi_out, with the same layout,
+ * receive phi^{n0+steps} and phi_dot^{n0+steps-1/2} on the interior
+ * steps .. steps+n[ndim-1]-1 only; the other axes stay periodic.  steps and
+ * the tiling must have a multi-step kernel for this dimension (see
  * prs_set_time_blocking); the four buffers are distinct device buffers of
  * the precision p names, 16-byte aligned.  No diagnostics.  Enqueued on
  * hip_stream; results are bitwise those of the same steps on the whole

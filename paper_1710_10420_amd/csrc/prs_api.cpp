@@ -521,7 +521,6 @@ prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t
 {
     prs_status st = validate(p);
     if (st != PRS_OK) return st;
-    if (p->ndim != 3) return fail(PRS_EINVAL, "slab passes are for 3D lattices (slabs along z)");
     if (n0 < 0) return fail(PRS_EINVAL, "n0 must be >= 0");
     if (!phi_in || !phi_out || !pi_in || !pi_out) return fail(PRS_EINVAL, "NULL buffer");
     if (!aligned16(phi_in) || !aligned16(phi_out) || !aligned16(pi_in) || !aligned16(pi_out))
@@ -532,7 +531,8 @@ prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t
     const Tiling t{vec, rows, ty};
     if (!tb_supported(g)) return fail(PRS_EUNSUPPORTED, "slab passes need planes shorter than 2^31 bytes");
     if (!tiling_supported(g, t) || !tb_pass_supported(g, t, steps))
-        return fail(PRS_EINVAL, "no %d-step 3D pass kernel for vec=%d rows=%d ty=%d", steps, vec, rows, ty);
+        return fail(PRS_EINVAL, "no %d-step %dD pass kernel for vec=%d rows=%d ty=%d", steps, p->ndim, vec, rows,
+                    ty);
     prs_ctx tmp{};
     tmp.p = *p;
     tmp.V0 = v0_of(*p);

@@ -782,6 +782,7 @@ struct TBArgs {
     int64_t nx, ny;
     int64_t tiles_x, ntiles;
     int64_t rows;
+    int32_t yhalo;              // 0: periodic in y; T: a y-slab stored with T halo rows below and above
     StepCoefT<R> k[T];
     DiagCoef dc;
 };
@@ -817,6 +818,7 @@ struct TBLane {
     int32_t ny;
     int32_t dir;               // march direction of k_tb2d: +1 up (rising y), -1 down
     int32_t wrap_at, wrap_to;  // row after the last one in that direction, and its periodic image
+    int32_t yoff;              // k_tb2d: stored row of row y is y + yoff (slab halo depth, else 0)
 };
 
 // Next rows to fetch, already wrapped into [0, ny); advanced by one row per
@@ -919,13 +921,13 @@ __device__ __forceinline__ void buf_store(R* base, uint32_t bytes, uint32_t soff
 template <int VEC, typename R>
 __device__ __forceinline__ void tb_load(const R* f, int32_t row, const TBLane& L, uint32_t bytes, R (&v)[VEC])
 {
-    buf_load<VEC>(f + (size_t)((uint32_t)row * L.nx), bytes, L.voff, v);
+    buf_load<VEC>(f + (size_t)(uint32_t)row * L.nx, bytes, L.voff, v);
 }
 
 template <int VEC, typename R>
 __device__ __forceinline__ void tb_store(R* f, int32_t row, const TBLane& L, uint32_t bytes, const R (&v)[VEC])
 {
-    buf_store<VEC>(f + (size_t)((uint32_t)row * L.nx), bytes, L.soff, v);
+    buf_store<VEC>(f + (size_t)(uint32_t)row * L.nx, bytes, L.soff, v);
 }
 
 // Iteration i of the march (upward: y = s0 - T + 1 + i; level k computes
@@ -992,13 +994,13 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
                 // level k: march row e = i - (T + k - 2) of the tile, stored when inside [0, s1 - s0)
                 const int32_t e = i - (T + k - 2);
                 const bool in = e >= 0 && e < L.s1 - L.s0;
-                const int32_t row = L.dir > 0 ? L.s0 + e : L.s1 - 1 - e;
+                const int32_t row = (L.dir > 0 ? L.s0 + e : L.s1 - 1 - e) + L.yoff;
                 tb_store<VEC>(A.phi_lv[k < T ? k - 1 : 0], in ? row : L.s0, L, in ? L.row_bytes : 0u, out_phi);
             }
         } else {
             // level T: march row e = i - (2T - 2) of the tile, inside it once i >= 2T - 2
             const int32_t e = i - (2 * T - 2);
-            const int32_t row = L.dir > 0 ? L.s0 + e : L.s1 - 1 - e;
+            const int32_t row = (L.dir > 0 ? L.s0 + e : L.s1 - 1 - e) + L.yoff;
             const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.row_bytes : 0u;
             tb_store<VEC>(A.phi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_phi);
             tb_store<VEC>(A.pi_out, CHECK && i < 2 * T - 2 ? L.s0 : row, L, sb, out_pi);
@@ -1054,8 +1056,14 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
     // symmetric, so the results are the same bits either way.  Diagnostic
     // passes march up (their links point to rising y).
     L.dir = (DIAG || (ts & 1u) == 0u) ? 1 : -1;
-    L.wrap_at = L.dir > 0 ? L.ny : -1;
-    L.wrap_to = L.dir > 0 ? 0 : L.ny - 1;
+    // A slab reads its T halo rows instead of wrapping around: its rows are
+    // stored T up, and the march never leaves them except by loads of size 0
+    // (the wrap below keeps even those inside the buffer).
+    L.yoff = A.yhalo;
+    const int32_t stored = L.ny + 2 * A.yhalo;
+    L.wrap_at = L.dir > 0 ? stored : -1;
+    L.wrap_to = L.dir > 0 ? 0 : stored - 1;
+    auto yrow = [&](int32_t y) { return A.yhalo ? y + A.yhalo : wrap_row(y, L.ny); };
 
     TBState<VEC, T, R> S;
 #pragma unroll
@@ -1079,13 +1087,13 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
     // direction) needs phi^n rows y0 - dir .. y0 + dir and phi_dot row y0
     const int32_t d = L.dir;
     const int32_t y0 = d > 0 ? L.s0 - T + 1 : L.s1 + T - 2;
-    tb_load<VEC>(A.phi_in, wrap_row(y0 - d, L.ny), L, L.row_bytes, S.in[3]);
-    tb_load<VEC>(A.phi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.in[0]);
-    tb_load<VEC>(A.phi_in, wrap_row(y0 + d, L.ny), L, L.row_bytes, S.in[1]);
-    tb_load<VEC>(A.pi_in, wrap_row(y0, L.ny), L, L.row_bytes, S.pin[0]);
+    tb_load<VEC>(A.phi_in, yrow(y0 - d), L, L.row_bytes, S.in[3]);
+    tb_load<VEC>(A.phi_in, yrow(y0), L, L.row_bytes, S.in[0]);
+    tb_load<VEC>(A.phi_in, yrow(y0 + d), L, L.row_bytes, S.in[1]);
+    tb_load<VEC>(A.pi_in, yrow(y0), L, L.row_bytes, S.pin[0]);
     TBRows rw;
-    rw.phi = wrap_row(y0 + 2 * d, L.ny);
-    rw.pi = wrap_row(y0 + d, L.ny);
+    rw.phi = yrow(y0 + 2 * d);
+    rw.pi = yrow(y0 + d);
 
     DiagAcc acc;
     acc.links[0] = acc.links[1] = acc.links[2] = 0u;
@@ -1550,7 +1558,7 @@ __device__ __forceinline__ void tb3_tile(const TB3Args<T, R>& A, int64_t tile)
     L.s1 = L.s0 + rows < L.nz ? L.s0 + rows : L.nz;
     // a slab reads its T halo planes instead of wrapping around
     L.zoff = A.zhalo;
-    L.zwrap = A.zhalo ? 0x7FFFFFFF : L.nz;
+    L.zwrap = L.nz + 2 * A.zhalo;   // stored planes: the wrap only ever meets loads of size 0 in a slab
     auto zplane = [&](int32_t z) { return A.zhalo ? z + A.zhalo : wrap_row(z, L.nz); };
 
     TB3State<VEC, T, TY, R> S;
@@ -2050,9 +2058,10 @@ hipError_t launch_fill_r(void* phi, int64_t count, uint64_t seed, hipStream_t s)
 template <typename R, int VEC, int T>
 hipError_t launch_tb_t(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi_in,
                        void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials, const DiagCoef& dc,
-                       hipStream_t s)
+                       hipStream_t s, int yhalo = 0)
 {
     TBArgs<T, R> A;
+    A.yhalo = yhalo;
     A.phi_in = static_cast<const R*>(phi_in);
     A.phi_out = static_cast<R*>(phi_out);
     A.pi_in = static_cast<const R*>(pi_in);
@@ -2079,19 +2088,19 @@ hipError_t launch_tb_t(const Geometry& g, const Tiling& t, const void* phi_in, v
 template <typename R, int VEC>
 hipError_t launch_tb_v(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
                        const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
-                       const DiagCoef& dc, hipStream_t s)
+                       const DiagCoef& dc, hipStream_t s, int yhalo = 0)
 {
     switch (T) {
-    case 2: return launch_tb_t<R, VEC, 2>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    case 3: return launch_tb_t<R, VEC, 3>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    case 4: return launch_tb_t<R, VEC, 4>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    case 2: return launch_tb_t<R, VEC, 2>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
+    case 3: return launch_tb_t<R, VEC, 3>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
+    case 4: return launch_tb_t<R, VEC, 4>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
     case 6:
         if constexpr (sizeof(R) == 4 || VEC == 1)
-            return launch_tb_t<R, VEC, 6>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+            return launch_tb_t<R, VEC, 6>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
         break;
     case 8:
         if constexpr (sizeof(R) == 4 || VEC == 1)
-            return launch_tb_t<R, VEC, 8>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+            return launch_tb_t<R, VEC, 8>(g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
         break;
     }
     return hipErrorInvalidValue;
@@ -2136,6 +2145,7 @@ hipError_t launch_tb_all_t(const Geometry& g, const Tiling& t, const void* phi_i
                            const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
 {
     TBArgs<T, R> A;
+    A.yhalo = 0;
     A.phi_in = static_cast<const R*>(phi_in);
     A.phi_out = static_cast<R*>(phi_lv[T - 1]);
     for (int i = 0; i < T; ++i) A.phi_lv[i] = static_cast<R*>(phi_lv[i]);
@@ -2432,17 +2442,19 @@ hipError_t launch_tba3_r(int T, const Geometry& g, const Tiling& t, const void* 
     return hipErrorInvalidValue;
 }
 
+// yhalo = T: the lattice is a y-slab stored with T halo rows below and
+// above (row y at y + T), which the march reads instead of wrapping.
 template <typename R>
 hipError_t launch_tb2d_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
                          const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
-                         const DiagCoef& dc, hipStream_t s)
+                         const DiagCoef& dc, hipStream_t s, int yhalo = 0)
 {
     switch (t.vec) {
-    case 1: return launch_tb_v<R, 1>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
-    case 2: return launch_tb_v<R, 2>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+    case 1: return launch_tb_v<R, 1>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
+    case 2: return launch_tb_v<R, 2>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
     case 4:
         if constexpr (vec_ok<R>(4))
-            return launch_tb_v<R, 4>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
+            return launch_tb_v<R, 4>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, yhalo);
         break;
     }
     return hipErrorInvalidValue;

@@ -316,6 +316,30 @@ def test_full_size_2d_8192_sampled(tiling, T):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("tiling,T", [((2, 128, 1), 8), ((1, 64, 1), 1)])
+def test_2d_lattice_past_2_32_sites(tiling, T):
+    """A 65536 x 65600 lattice holds more than 2^32 sites, so row offsets of
+    its last 64 rows exceed 32 bits: sampled patches there and elsewhere
+    after 16 steps match the oracle on their dependence cones."""
+    say("2D past 2^32 sites", tiling, T)
+    torch = torch_mod()
+    prs = gpu_prs()
+    shape = (65536, 65600)
+    assert shape[0] * shape[1] > 1 << 32
+    gp, op = params_pair(shape, 0.25, m=2.0, W0=10.0)
+    sim = prs.Sim(gp, seed=1)
+    sim.set_tiling(*tiling)
+    sim.set_time_blocking(T)
+    sim.step_n(16, diag=False)
+    phi, _ = sim.state()
+    for c in [(0, 65599), (65535, 65590), (100, 65540), (40000, 65536), (30000, 32768), (5, 0)]:
+        idx, ref = oracle_patch(op, shape, 1, c, 16, 5)
+        got = host(phi.index_select(0, torch.from_numpy(idx).cuda()))
+        assert rel_linf(got, ref) <= 1e-5, c
+    del sim, phi
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("tiling,T", [((2, 64, 2), 3), (None, None)])
 def test_full_size_3d_1024_sampled(tiling, T):
     """1024^3 radiation era in the fastest three-step configuration and the

@@ -1,17 +1,22 @@
-"""Slab passes: the per-device kernel of a 3D lattice sharded along z.  A
-slab stored with T halo planes below and above, filled here with the
-periodic images a neighbouring device would send, must advance its interior
-exactly as the whole periodic lattice does (same kernel arithmetic, so
-bitwise), for both precisions and the physical force."""
+"""Slab passes: the per-device kernel of a lattice sharded along its last
+axis (y in 2D, z in 3D).  A slab stored with T halo rows or planes below and
+above, filled here with the periodic images a neighbouring device would
+send, must advance its interior exactly as the whole periodic lattice does
+(same kernel arithmetic, so bitwise), for both precisions and the physical
+force."""
 import numpy as np
 import pytest
 
-from tests.gpu_util import gpu_prs, host, torch_mod
+from tests.gpu_util import gpu_prs, host, say, torch_mod
 
 pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("shape,T,tiling,nslab,f64,beta", [
+    ((96, 64), 8, (2, 16, 1), 2, False, 0.0),
+    ((80, 60), 3, (1, 8, 1), 3, False, 2.0),
+    ((72, 48), 4, (4, 8, 1), 2, False, 0.0),
+    ((40, 36), 6, (1, 8, 1), 2, True, 0.0),
     ((64, 40, 32), 3, (1, 8, 2), 2, False, 0.0),
     ((48, 36, 30), 2, (2, 8, 1), 3, False, 0.0),
     ((48, 36, 30), 3, (1, 8, 4), 3, False, 2.0),
@@ -20,7 +25,9 @@ pytestmark = pytest.mark.gpu
 def test_slab_passes_equal_the_whole_lattice(shape, T, tiling, nslab, f64, beta):
     torch = torch_mod()
     prs = gpu_prs()
-    NX, NY, NZ = shape
+    say("slab", shape, T, tiling, nslab, f64, beta)
+    lay = tuple(reversed(shape))                    # (z,) y, x
+    NZ, plane = lay[0], lay[1:]
     kw = dict(deta=0.2 if beta == 0.0 else 0.1, m=1.0, W0=8.0, alpha=3.0 if beta == 0.0 else 2.0, beta=beta,
               precision=prs.PRS_F64 if f64 else prs.PRS_F32)
     gp = prs.make_params(shape, **kw)
@@ -31,26 +38,27 @@ def test_slab_passes_equal_the_whole_lattice(shape, T, tiling, nslab, f64, beta)
     sim.set_tiling(*tiling)
     sim.set_time_blocking(T)
     sim.step_n(T)
-    ref_phi, ref_pi = (host(t).reshape(NZ, NY, NX) for t in sim.state())
+    ref_phi, ref_pi = (host(t).reshape(lay) for t in sim.state())
     nz = NZ // nslab
     stream = prs._stream_handle(torch.cuda.current_stream())
     for sl in range(nslab):
         z0 = sl * nz
         planes = torch.tensor([(z0 - T + k) % NZ for k in range(nz + 2 * T)], device="cuda")
-        phi_in = phi5.view(NZ, NY, NX).index_select(0, planes).contiguous()
-        pi_in = pi5.view(NZ, NY, NX).index_select(0, planes).contiguous()
+        phi_in = phi5.view(lay).index_select(0, planes).contiguous()
+        pi_in = pi5.view(lay).index_select(0, planes).contiguous()
         phi_out = torch.zeros_like(phi_in)
         pi_out = torch.zeros_like(pi_in)
-        ps = prs.make_params((NX, NY, nz), **kw)
+        ps = prs.make_params(tuple(shape[:-1]) + (nz,), **kw)
         prs.prs_slab_pass(ps, 5, T, tiling, phi_in.data_ptr(), phi_out.data_ptr(), pi_in.data_ptr(),
                           pi_out.data_ptr(), stream)
         torch.cuda.synchronize()
-        got_phi = host(phi_out).reshape(nz + 2 * T, NY, NX)
-        got_pi = host(pi_out).reshape(nz + 2 * T, NY, NX)
+        got_phi = host(phi_out).reshape((nz + 2 * T,) + plane)
+        got_pi = host(pi_out).reshape((nz + 2 * T,) + plane)
         np.testing.assert_array_equal(got_phi[T:T + nz], ref_phi[z0:z0 + nz], err_msg=str(sl))
         np.testing.assert_array_equal(got_pi[T:T + nz], ref_pi[z0:z0 + nz], err_msg=str(sl))
-        # the halo planes of the outputs are left alone
+        # the halo rows or planes of the outputs are left alone
         assert not np.any(got_phi[:T]) and not np.any(got_phi[T + nz:])
+        assert not np.any(got_pi[:T]) and not np.any(got_pi[T + nz:])
 
 
 def test_slab_pass_rejects_bad_arguments():
@@ -61,7 +69,8 @@ def test_slab_pass_rejects_bad_arguments():
     ptrs = [b.data_ptr() for b in bufs]
     p3 = prs.make_params((32, 16, 10), deta=0.2)
     p2 = prs.make_params((32, 16), deta=0.2)
-    for args in ((p2, 0, 2, (1, 8, 2)), (p3, 0, 4, (1, 8, 2)), (p3, -1, 2, (1, 8, 2)), (p3, 0, 2, (4, 8, 2))):
+    for args in ((p2, 0, 2, (1, 8, 2)), (p2, 0, 5, (1, 8, 1)), (p3, 0, 4, (1, 8, 2)), (p3, -1, 2, (1, 8, 2)),
+                 (p3, 0, 2, (4, 8, 2))):
         with pytest.raises(prs.PRSError) as e:
             prs.prs_slab_pass(*args, *ptrs, stream)
         assert e.value.status == prs.PRS_EINVAL
