@@ -32,8 +32,8 @@ BYTES_PER_UPDATE = 16          # read phi, phi_dot; write phi^{n+1}, phi_dot (FP
 # (factors 1.9998 and 1.0000); see profiles/k_tb2d_2d8192.md.  A
 # configuration without a measurement reports null.
 TRAFFIC_PER_LAUNCH = {
-    (2, 64, 1, 8): 1168620680,
-    (2, 128, 1, 8): 1139146448,
+    (2, 64, 1, 8): 1157492691,
+    (2, 128, 1, 8): 1133803299,
 }
 
 WORKLOAD = {
@@ -242,21 +242,31 @@ def table1_leg(prs):
     return out
 
 
-SLAB = dict(shape=(1024, 1024, 128), deta=0.2, m=1.0, W0=10.0, T=3, tiling=(2, 64, 2), passes=20)
+SLABS = {
+    "3d": dict(shape=(1024, 1024, 128), deta=0.2, m=1.0, W0=10.0, T=3, tiling=(2, 64, 2), passes=20,
+               name="1024x1024x128 z-slab (1/8 of 1024^3) with 3 halo planes per face, three-step passes, "
+                    "tiling (2, 64, 2), 20 passes"),
+    "2d": dict(shape=(8192, 1024), deta=0.25, m=2.0, W0=10.0, T=8, tiling=(2, 64, 1), passes=40,
+               name="8192x1024 y-slab (1/8 of 8192^2) with 8 halo rows per face, eight-step passes, "
+                    "tiling (2, 64, 1), 40 passes"),
+}
 XGMI_LINK_GBS = 153.0          # one MI355X xGMI link, per direction (published)
 
 
-def slab_leg(prs, torch, reps=2):
-    """The per-device kernel of a 1024^3 lattice sharded along z over eight
-    devices: a 1024 x 1024 x 128 slab stored with T = 3 halo planes below and
-    above, advanced by three-step slab passes (the halos are those a neighbour
-    would send; here they stay as initialised).  Reports the slab's
-    site-update rate and what one halo exchange per pass would cost on one
-    xGMI link."""
-    nx, ny, nz = SLAB["shape"]
-    T = SLAB["T"]
-    p = prs.make_params(SLAB["shape"], deta=SLAB["deta"], m=SLAB["m"], W0=SLAB["W0"])
-    n_ext = nx * ny * (nz + 2 * T)
+def slab_leg(prs, torch, cfg, reps=2):
+    """The per-device kernel of a lattice sharded along its last axis over
+    eight devices (1024^3 along z, 8192^2 along y): a slab stored with T halo
+    planes or rows below and above, advanced by T-step slab passes (the halos
+    are those a neighbour would send; here they stay as initialised).
+    Reports the slab's site-update rate and what one halo exchange per pass
+    would cost on one xGMI link."""
+    shape = cfg["shape"]
+    T = cfg["T"]
+    p = prs.make_params(shape, deta=cfg["deta"], m=cfg["m"], W0=cfg["W0"])
+    face = 1
+    for n in shape[:-1]:
+        face *= n
+    n_ext = face * (shape[-1] + 2 * T)
     f = [torch.empty(n_ext, dtype=torch.float32, device="cuda") for _ in range(4)]
     stream = torch.cuda.current_stream()
     s = prs._stream_handle(stream)
@@ -269,8 +279,8 @@ def slab_leg(prs, torch, reps=2):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         a, b, pa, pb = f
-        for k in range(SLAB["passes"]):
-            prs.prs_slab_pass(p, k * T, T, SLAB["tiling"], a.data_ptr(), b.data_ptr(), pa.data_ptr(),
+        for k in range(cfg["passes"]):
+            prs.prs_slab_pass(p, k * T, T, cfg["tiling"], a.data_ptr(), b.data_ptr(), pa.data_ptr(),
                               pb.data_ptr(), s)
             a, b, pa, pb = b, a, pb, pa
         e1.record(stream)
@@ -278,14 +288,13 @@ def slab_leg(prs, torch, reps=2):
         if r > 0:
             times.append(e0.elapsed_time(e1))
     ms = min(times)
-    su = float(nx * ny * nz) * T * SLAB["passes"]
-    halo_bytes = 2 * 2 * T * nx * ny * 4          # phi and phi_dot, T planes, both faces
-    out = {"workload": "1024x1024x128 z-slab (1/8 of 1024^3) with 3 halo planes per face, three-step passes, "
-                       "tiling (2, 64, 2), 20 passes",
-           "ms_per_pass": ms / SLAB["passes"], "site_updates_per_s": su / (ms / 1e3),
+    su = float(face * shape[-1]) * T * cfg["passes"]
+    halo_bytes = 2 * 2 * T * face * 4          # phi and phi_dot, T planes or rows, both faces
+    out = {"workload": cfg["name"],
+           "ms_per_pass": ms / cfg["passes"], "site_updates_per_s": su / (ms / 1e3),
            "halo_bytes_per_pass": halo_bytes,
            "halo_exchange_ms_one_link": halo_bytes / (XGMI_LINK_GBS * 1e9) * 1e3}
-    log("slab %.3f ms per pass" % (ms / SLAB["passes"]))
+    log("slab %dD %.3f ms per pass" % (len(shape), ms / cfg["passes"]))
     del f
     torch.cuda.empty_cache()
     return out
@@ -436,7 +445,8 @@ def main():
         out["batch"] = batch_leg(prs, torch)
         out["f64"] = f64_leg(prs, torch, w)
         out["table1"] = table1_leg(prs)
-        out["slab"] = slab_leg(prs, torch)
+        out["slab"] = slab_leg(prs, torch, SLABS["3d"])
+        out["slab_2d"] = slab_leg(prs, torch, SLABS["2d"])
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
