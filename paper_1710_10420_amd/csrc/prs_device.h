@@ -782,7 +782,7 @@ struct TBArgs {
     int64_t nx, ny;
     int64_t tiles_x, ntiles;
     int64_t rows;
-    int32_t yhalo;              // 0: periodic in y; T: a y-slab stored with T halo rows below and above
+    int32_t yhalo = 0;          // 0: periodic in y; T: a y-slab stored with T halo rows below and above
     StepCoefT<R> k[T];
     DiagCoef dc;
 };
@@ -1386,7 +1386,7 @@ struct TB3Args {
     int64_t nx, ny, nz;
     int64_t tiles_x, tiles_y, ntiles;
     int64_t rows;               // planes per tile along z
-    int32_t zhalo;              // 0: periodic in z; T: a z-slab stored with T halo planes below and above
+    int32_t zhalo = 0;          // 0: periodic in z; T: a z-slab stored with T halo planes below and above
     StepCoefT<R> k[T];
     DiagCoef dc;
 };

@@ -313,8 +313,9 @@ def prs_get_recompute_tiling(ctx):
 
 
 def prs_slab_pass(p, n0, steps, tiling, phi_in, phi_out, pi_in, pi_out, stream):
-    """One multi-step pass over a 3D z-slab stored with `steps` halo planes
-    below and above (device pointers; see include/prs.h)."""
+    """One multi-step pass over a slab of a lattice cut along its last axis
+    (y in 2D, z in 3D), stored with `steps` halo rows or planes below and
+    above (device pointers; see include/prs.h)."""
     _check(_lib.prs_slab_pass(ctypes.byref(p), n0, steps, tiling[0], tiling[1], tiling[2], phi_in, phi_out,
                               pi_in, pi_out, stream), "prs_slab_pass")
 
