@@ -17,10 +17,13 @@ pytestmark = pytest.mark.gpu
     ((80, 60), 3, (1, 8, 1), 3, False, 2.0),
     ((72, 48), 4, (4, 8, 1), 2, False, 0.0),
     ((40, 36), 6, (1, 8, 1), 2, True, 0.0),
+    ((48, 32), 8, (1, 16, 1), 2, True, 2.0),
+    ((64, 12), 8, (1, 8, 1), 4, False, 0.0),      # slabs of 3 rows, thinner than their halos
     ((64, 40, 32), 3, (1, 8, 2), 2, False, 0.0),
     ((48, 36, 30), 2, (2, 8, 1), 3, False, 0.0),
     ((48, 36, 30), 3, (1, 8, 4), 3, False, 2.0),
     ((40, 24, 20), 2, (1, 8, 2), 2, True, 0.0),
+    ((32, 16, 8), 3, (1, 8, 1), 4, False, 0.0),   # slabs of 2 planes, thinner than their halos
 ])
 def test_slab_passes_equal_the_whole_lattice(shape, T, tiling, nslab, f64, beta):
     torch = torch_mod()
