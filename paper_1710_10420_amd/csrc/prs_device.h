@@ -821,7 +821,8 @@ struct TBLane {
     int32_t yoff;              // k_tb2d: stored row of row y is y + yoff (slab halo depth, else 0)
 };
 
-// Next rows to fetch, already wrapped into [0, ny); advanced by one row per
+// Next rows to fetch, already wrapped into the stored rows ([0, ny), or
+// [0, ny + 2T) for a slab with T halo rows per face); advanced by one row per
 // iteration without division.
 struct TBRows {
     int32_t phi, pi;
@@ -1298,8 +1299,9 @@ __global__ __launch_bounds__(kBlock) void k_tba2d(TBAArgs<T, R> A)
     L.soff = (lane >= H && lane < kWave - H && x0 < (int32_t)L.nx) ? L.voff : kPastRow;
     L.s0 = (int32_t)ts * rows;
     L.s1 = L.s0 + rows < L.ny ? L.s0 + rows : L.ny;
-    // odd row tiles march down, as in k_tb2d
+    // odd row tiles march down, as in k_tb2d (periodic: no halo rows)
     L.dir = (ts & 1u) == 0u ? 1 : -1;
+    L.yoff = 0;
     L.wrap_at = L.dir > 0 ? L.ny : -1;
     L.wrap_to = L.dir > 0 ? 0 : L.ny - 1;
 

@@ -93,10 +93,11 @@ bool tb_steps_supported(const Geometry& g, int T);
 bool tb_pass_supported(const Geometry& g, const Tiling& t, int T);
 constexpr int kMaxPassSteps = 8;   // most leapfrog steps fused into one pass
 
-// A T-step pass over a 3D z-slab (the per-device kernel of a lattice sharded
-// along z): the fields are stored with T halo planes below and above the
-// g.M interior planes (plane z at z + T), read in place of the periodic
-// wrap; only the interior planes of phi_out and pi_out are written.
+// A T-step pass over a slab along the last axis (the per-device kernel of a
+// lattice sharded along y in 2D, z in 3D): the fields are stored with T halo
+// rows or planes below and above the g.M interior ones (row or plane z at
+// z + T), read in place of the periodic wrap; only the interior rows or
+// planes of phi_out and pi_out are written.
 hipError_t launch_tb_slab(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
                           const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
 hipError_t launch_tb_slab_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
