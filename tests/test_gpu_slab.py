@@ -80,3 +80,47 @@ def test_slab_pass_rejects_bad_arguments():
     with pytest.raises(prs.PRSError) as e:
         prs.prs_slab_pass(p3, 0, 2, (1, 8, 2), ptrs[0], ptrs[0], ptrs[2], ptrs[3], stream)
     assert e.value.status == prs.PRS_EINVAL
+
+
+@pytest.mark.parametrize("shape,T,tiling,nslab", [
+    ((8192, 8192), 8, (2, 64, 1), 8),
+    ((1024, 1024, 1024), 3, (2, 64, 2), 8),
+])
+def test_slab_full_size_in_the_benchmark_configurations(shape, T, tiling, nslab):
+    """The slabs the benchmark times (one eighth of 8192^2 along y, eight-step
+    passes; one eighth of 1024^3 along z, three-step passes), in its launch
+    configurations: the first, a middle and the last slab of the whole lattice
+    advance bit for bit as the whole lattice does."""
+    torch = torch_mod()
+    prs = gpu_prs()
+    say("slab full size", shape, T, tiling, nslab)
+    kw = dict(deta=0.25, m=2.0, W0=10.0) if len(shape) == 2 else dict(deta=0.2, m=1.0, W0=10.0)
+    lay = tuple(reversed(shape))
+    NZ = lay[0]
+    gp = prs.make_params(shape, **kw)
+    sim = prs.Sim(gp, seed=1)
+    sim.set_time_blocking(1)
+    sim.step_n(3, diag=False)                       # phi_dot != 0 from here
+    phi3, pi3 = (t.clone() for t in sim.state())
+    sim.set_tiling(*tiling)
+    sim.set_time_blocking(T)
+    sim.step_n(T, diag=False)
+    ref_phi, ref_pi = (t.view(lay) for t in sim.state())
+    nz = NZ // nslab
+    stream = prs._stream_handle(torch.cuda.current_stream())
+    ps = prs.make_params(tuple(shape[:-1]) + (nz,), **kw)
+    for sl in (0, nslab // 2, nslab - 1):
+        z0 = sl * nz
+        planes = torch.tensor([(z0 - T + k) % NZ for k in range(nz + 2 * T)], device="cuda")
+        phi_in = phi3.view(lay).index_select(0, planes).contiguous()
+        pi_in = pi3.view(lay).index_select(0, planes).contiguous()
+        phi_out = torch.zeros_like(phi_in)
+        pi_out = torch.zeros_like(pi_in)
+        prs.prs_slab_pass(ps, 3, T, tiling, phi_in.data_ptr(), phi_out.data_ptr(), pi_in.data_ptr(),
+                          pi_out.data_ptr(), stream)
+        torch.cuda.synchronize()
+        assert torch.equal(phi_out[T:T + nz], ref_phi[z0:z0 + nz]), sl
+        assert torch.equal(pi_out[T:T + nz], ref_pi[z0:z0 + nz]), sl
+        del phi_in, pi_in, phi_out, pi_out
+    del sim, phi3, pi3, ref_phi, ref_pi
+    torch.cuda.empty_cache()
