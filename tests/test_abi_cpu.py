@@ -97,6 +97,34 @@ def test_buffer_checks_before_launch():
     assert e.value.status == prs.PRS_ENOMEM
 
 
+def test_slab_pass_checks_before_launch():
+    """Every rejected slab pass fails in validation, before any launch."""
+    p2 = prs.make_params((64, 32), deta=0.2)
+    p3 = prs.make_params((32, 16, 8), deta=0.2)
+    ok = (16, 32, 48, 64)
+    cases = [
+        (p2, 0, 2, (1, 8, 1), (0, 32, 48, 64)),       # NULL buffer
+        (p2, 0, 2, (1, 8, 1), (16, 36, 48, 64)),      # misaligned
+        (p2, 0, 2, (1, 8, 1), (16, 16, 48, 64)),      # phi_in aliases phi_out
+        (p2, 0, 2, (1, 8, 1), (16, 32, 16, 64)),      # phi_in aliases pi_in
+        (p2, -1, 2, (1, 8, 1), ok),                   # negative first step
+        (p2, 0, 5, (1, 8, 1), ok),                    # no five-step 2D pass
+        (p2, 0, 2, (1, 8, 2), ok),                    # 2D tilings have ty = 1
+        (p2, 0, 2, (3, 8, 1), ok),                    # vec must be 1, 2 or 4
+        (p3, 0, 4, (1, 8, 2), ok),                    # no four-step 3D pass
+        (p3, 0, 2, (4, 8, 2), ok),                    # no vec-4 3D pass
+    ]
+    for p, n0, steps, til, bufs in cases:
+        with pytest.raises(prs.PRSError) as e:
+            prs.prs_slab_pass(p, n0, steps, til, *bufs, None)
+        assert e.value.status == prs.PRS_EINVAL, (n0, steps, til, bufs)
+    bad = prs.make_params((64, 32), deta=0.2)
+    bad.deta = 2.0                                    # unstable step
+    with pytest.raises(prs.PRSError) as e:
+        prs.prs_slab_pass(bad, 0, 2, (1, 8, 1), *ok, None)
+    assert e.value.status == prs.PRS_EINVAL
+
+
 def test_fit_matches_oracle_fit():
     rng = np.random.default_rng(0)
     eta = np.linspace(1.0, 4096.0, 257)
