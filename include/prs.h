@@ -246,6 +246,27 @@ prs_status prs_get_recompute_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, i
 prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows, int32_t ty,
                          const void* phi_in, void* phi_out, const void* pi_in, void* pi_out, void* hip_stream);
 
+/* The same pass with the wall diagnostics (Eqs. 7-8, as prs_wall_stats
+ * defines them) of the slab's input state phi^{n0}, phi_dot^{n0-1/2} fused
+ * in, over its interior sites: links point to rising coordinates, so a link
+ * crossing the upper face into the halo counts in this slab and one crossing
+ * the lower face in the slab below; wall sites see both halos.  The record
+ * is that of the slab as a lattice of its own: links, links_dir, wall_sites
+ * and nonfinite add up over the slabs of a lattice; area_density is
+ * per interior site (weight by the slab's sites to combine) and gv2 per wall
+ * site (weight by wall_sites).  scratch is a device buffer of at least
+ * prs_slab_scratch_bytes(p, steps, vec, rows, ty) bytes, 16-byte aligned,
+ * used by this call only.  Synchronises hip_stream and writes *record (host).
+ * Errors as prs_slab_pass, plus PRS_EINVAL for a NULL record or scratch and
+ * PRS_ENOMEM for a short scratch buffer. */
+prs_status prs_slab_pass_stats(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows,
+                               int32_t ty, const void* phi_in, void* phi_out, const void* pi_in, void* pi_out,
+                               void* scratch, size_t scratch_bytes, prs_stats* record, void* hip_stream);
+
+/* Scratch bytes prs_slab_pass_stats needs for this slab, pass length and
+ * tiling; 0 when the parameters are invalid or no such pass kernel exists. */
+size_t prs_slab_scratch_bytes(const prs_params* p, int32_t steps, int32_t vec, int32_t rows, int32_t ty);
+
 /* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
 void prs_destroy(prs_ctx* ctx);
 

@@ -516,8 +516,17 @@ prs_status prs_set_adjoint_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t
     return PRS_OK;
 }
 
-prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows, int32_t ty,
-                         const void* phi_in, void* phi_out, const void* pi_in, void* pi_out, void* hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Bytes of the record slot at the start of a slab-diagnostics scratch buffer
+// (the wave partials follow it).
+constexpr size_t kSlabRecBytes = 256;
+
+prs_status slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows, int32_t ty,
+                     const void* phi_in, void* phi_out, const void* pi_in, void* pi_out, void* scratch,
+                     size_t scratch_bytes, prs_stats* record, void* hip_stream)
 {
     prs_status st = validate(p);
     if (st != PRS_OK) return st;
@@ -533,6 +542,14 @@ prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t
     if (!tiling_supported(g, t) || !tb_pass_supported(g, t, steps))
         return fail(PRS_EINVAL, "no %d-step %dD pass kernel for vec=%d rows=%d ty=%d", steps, p->ndim, vec, rows,
                     ty);
+    const bool diag = record != nullptr;
+    const int64_t ntiles = tb_tiles(g, t, steps);
+    if (diag) {
+        if (!scratch || !aligned16(scratch)) return fail(PRS_EINVAL, "scratch must be a 16-byte aligned buffer");
+        const size_t need = kSlabRecBytes + (size_t)ntiles * sizeof(WavePartial);
+        if (scratch_bytes < need)
+            return fail(PRS_ENOMEM, "slab scratch needs %zu bytes (got %zu)", need, scratch_bytes);
+    }
     prs_ctx tmp{};
     tmp.p = *p;
     tmp.V0 = v0_of(*p);
@@ -540,9 +557,47 @@ prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t
     if (st != PRS_OK) return st;
     StepCoef64 k[kMaxPassSteps];
     for (int i = 0; i < steps; ++i) k[i] = coef_for(&tmp, n0 + i);
-    HIP_TRY(launch_tb_slab(steps, g, t, phi_in, phi_out, pi_in, pi_out, k, static_cast<hipStream_t>(hip_stream)),
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    prs_stats* drec = static_cast<prs_stats*>(scratch);
+    WavePartial* parts =
+        diag ? reinterpret_cast<WavePartial*>(static_cast<char*>(scratch) + kSlabRecBytes) : nullptr;
+    HIP_TRY(launch_tb_slab(steps, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, parts,
+                           diag ? diag_coef(&tmp, n0) : DiagCoef{}, s),
             "slab pass launch");
+    if (!diag) return PRS_OK;
+    HIP_TRY(launch_finalize(parts, ntiles, drec, n0, p->eta0 + (double)n0 * p->deta, area_scale(*p), s),
+            "finalize launch");
+    HIP_TRY(hipMemcpyAsync(record, drec, sizeof(prs_stats), hipMemcpyDeviceToHost, s), "record copy");
+    HIP_TRY(hipStreamSynchronize(s), "record sync");
     return PRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+prs_status prs_slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows, int32_t ty,
+                         const void* phi_in, void* phi_out, const void* pi_in, void* pi_out, void* hip_stream)
+{
+    return slab_pass(p, n0, steps, vec, rows, ty, phi_in, phi_out, pi_in, pi_out, nullptr, 0, nullptr, hip_stream);
+}
+
+size_t prs_slab_scratch_bytes(const prs_params* p, int32_t steps, int32_t vec, int32_t rows, int32_t ty)
+{
+    if (validate(p) != PRS_OK) return 0;
+    const Geometry g = geometry_of(*p);
+    const Tiling t{vec, rows, ty};
+    if (!tb_supported(g) || !tiling_supported(g, t) || !tb_pass_supported(g, t, steps)) return 0;
+    return kSlabRecBytes + (size_t)tb_tiles(g, t, steps) * sizeof(WavePartial);
+}
+
+prs_status prs_slab_pass_stats(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows,
+                               int32_t ty, const void* phi_in, void* phi_out, const void* pi_in, void* pi_out,
+                               void* scratch, size_t scratch_bytes, prs_stats* record, void* hip_stream)
+{
+    if (!record) return fail(PRS_EINVAL, "record is NULL");
+    return slab_pass(p, n0, steps, vec, rows, ty, phi_in, phi_out, pi_in, pi_out, scratch, scratch_bytes, record,
+                     hip_stream);
 }
 
 prs_status prs_set_recompute_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t ty, int32_t steps_per_pass)

@@ -97,13 +97,17 @@ constexpr int kMaxPassSteps = 8;   // most leapfrog steps fused into one pass
 // lattice sharded along y in 2D, z in 3D): the fields are stored with T halo
 // rows or planes below and above the g.M interior ones (row or plane z at
 // z + T), read in place of the periodic wrap; only the interior rows or
-// planes of phi_out and pi_out are written.
+// planes of phi_out and pi_out are written.  With diag, one WavePartial per
+// wave tile (tb_tiles of them) of the input state's interior diagnostics.
 hipError_t launch_tb_slab(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                          const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
+                          const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                          const DiagCoef& dc, hipStream_t s);
 hipError_t launch_tb_slab_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                              const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
+                              const void* pi_in, void* pi_out, const StepCoef64* k, bool diag,
+                              WavePartial* partials, const DiagCoef& dc, hipStream_t s);
 hipError_t launch_tb_slab_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                              const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s);
+                              const void* pi_in, void* pi_out, const StepCoef64* k, bool diag,
+                              WavePartial* partials, const DiagCoef& dc, hipStream_t s);
 
 // Reduces `count` partials in a fixed order into one record at `rec`.
 hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats* rec,

@@ -391,11 +391,12 @@ hipError_t launch_tb_f32(int T, const Geometry& g, const Tiling& t, const void* 
 }
 
 hipError_t launch_tb_slab_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                              const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+                              const void* pi_in, void* pi_out, const StepCoef64* k, bool diag,
+                              WavePartial* partials, const DiagCoef& dc, hipStream_t s)
 {
     if (g.ndim == 2)
-        return launch_tb2d_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, false, nullptr, DiagCoef{}, s, T);
-    return launch_tb3d_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, false, nullptr, DiagCoef{}, s, T);
+        return launch_tb2d_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, T);
+    return launch_tb3d_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, T);
 }
 
 hipError_t launch_adjoint_f32(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,
@@ -449,11 +450,12 @@ hipError_t launch_tb(int T, const Geometry& g, const Tiling& t, const void* phi_
 }
 
 hipError_t launch_tb_slab(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                          const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+                          const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
+                          const DiagCoef& dc, hipStream_t s)
 {
     if (!tb_pass_supported(g, t, T)) return hipErrorInvalidValue;
-    return g.f64 ? launch_tb_slab_f64(T, g, t, phi_in, phi_out, pi_in, pi_out, k, s)
-                 : launch_tb_slab_f32(T, g, t, phi_in, phi_out, pi_in, pi_out, k, s);
+    return g.f64 ? launch_tb_slab_f64(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s)
+                 : launch_tb_slab_f32(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s);
 }
 
 hipError_t launch_adjoint(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,

@@ -24,11 +24,12 @@ hipError_t launch_tb_f64(int T, const Geometry& g, const Tiling& t, const void* 
 }
 
 hipError_t launch_tb_slab_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
-                              const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
+                              const void* pi_in, void* pi_out, const StepCoef64* k, bool diag,
+                              WavePartial* partials, const DiagCoef& dc, hipStream_t s)
 {
     if (g.ndim == 2)
-        return launch_tb2d_r<double>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, false, nullptr, DiagCoef{}, s, T);
-    return launch_tb3d_r<double>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, false, nullptr, DiagCoef{}, s, T);
+        return launch_tb2d_r<double>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, T);
+    return launch_tb3d_r<double>(T, g, t, phi_in, phi_out, pi_in, pi_out, k, diag, partials, dc, s, T);
 }
 
 hipError_t launch_adjoint_f64(const Geometry& g, const Tiling& t, const void* w_in, void* w_out, void* mu,

@@ -152,6 +152,8 @@ _decl("prs_set_adjoint_time_blocking", _i32, _vp, _i32)
 _decl("prs_get_adjoint_time_blocking", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_set_recompute_tiling", _i32, _vp, _i32, _i32, _i32, _i32)
 _decl("prs_slab_pass", _i32, _P, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp)
+_decl("prs_slab_pass_stats", _i32, _P, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _S, _vp)
+_decl("prs_slab_scratch_bytes", _sz, _P, _i32, _i32, _i32, _i32)
 _decl("prs_get_recompute_tiling", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
       ctypes.POINTER(_i32))
 _decl("prs_strerror", ctypes.c_char_p, _i32)
@@ -169,6 +171,7 @@ EXPORTED = [
     "prs_get_adjoint_tiling", "prs_plan_passes", "prs_fill_uniform_f64",
     "prs_set_adjoint_time_blocking", "prs_get_adjoint_time_blocking",
     "prs_set_recompute_tiling", "prs_get_recompute_tiling", "prs_slab_pass",
+    "prs_slab_pass_stats", "prs_slab_scratch_bytes",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -318,6 +321,21 @@ def prs_slab_pass(p, n0, steps, tiling, phi_in, phi_out, pi_in, pi_out, stream):
     above (device pointers; see include/prs.h)."""
     _check(_lib.prs_slab_pass(ctypes.byref(p), n0, steps, tiling[0], tiling[1], tiling[2], phi_in, phi_out,
                               pi_in, pi_out, stream), "prs_slab_pass")
+
+
+def prs_slab_scratch_bytes(p, steps, tiling):
+    """Scratch bytes prs_slab_pass_stats needs (0: no such pass)."""
+    return int(_lib.prs_slab_scratch_bytes(ctypes.byref(p), steps, tiling[0], tiling[1], tiling[2]))
+
+
+def prs_slab_pass_stats(p, n0, steps, tiling, phi_in, phi_out, pi_in, pi_out, scratch, scratch_bytes, stream):
+    """prs_slab_pass with the input state's wall diagnostics over the slab's
+    interior; returns the record as a dict (synchronises the stream)."""
+    rec = prs_stats()
+    _check(_lib.prs_slab_pass_stats(ctypes.byref(p), n0, steps, tiling[0], tiling[1], tiling[2], phi_in, phi_out,
+                                    pi_in, pi_out, scratch, scratch_bytes, ctypes.byref(rec), stream),
+           "prs_slab_pass_stats")
+    return rec.as_dict()
 
 
 def prs_plan_passes(ctx, nsteps, with_records=True):
