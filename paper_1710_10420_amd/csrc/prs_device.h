@@ -2078,9 +2078,18 @@ hipError_t launch_tb_t(const Geometry& g, const Tiling& t, const void* phi_in, v
     for (int i = 0; i < T; ++i) A.k[i] = coef_as<R>(k[i]);
     A.dc = dc;
     const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (diag)
+    const bool unit = A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1);
+    if (diag) {
+        // float32 diagnostic passes also drop the unit factors (one VALU
+        // instruction per site-update)
+        if constexpr (sizeof(R) == 4) {
+            if (unit) {
+                hipLaunchKernelGGL((k_tb2d<VEC, T, true, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((k_tb2d<VEC, T, true, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
-    else if (A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1))
+    } else if (unit)
         hipLaunchKernelGGL((k_tb2d<VEC, T, false, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
     else
         hipLaunchKernelGGL((k_tb2d<VEC, T, false, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
