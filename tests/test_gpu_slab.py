@@ -89,8 +89,9 @@ def test_slab_pass_rejects_bad_arguments():
 def test_slab_full_size_in_the_benchmark_configurations(shape, T, tiling, nslab):
     """The slabs the benchmark times (one eighth of 8192^2 along y, eight-step
     passes; one eighth of 1024^3 along z, three-step passes), in its launch
-    configurations: the first, a middle and the last slab of the whole lattice
-    advance bit for bit as the whole lattice does."""
+    configurations: every slab of the whole lattice advances bit for bit as
+    the whole lattice does, and the slabs' records of the input state combine
+    into the whole lattice's record."""
     torch = torch_mod()
     prs = gpu_prs()
     say("slab full size", shape, T, tiling, nslab)
@@ -101,6 +102,7 @@ def test_slab_full_size_in_the_benchmark_configurations(shape, T, tiling, nslab)
     sim = prs.Sim(gp, seed=1)
     sim.set_time_blocking(1)
     sim.step_n(3, diag=False)                       # phi_dot != 0 from here
+    whole = sim.wall_stats()
     phi3, pi3 = (t.clone() for t in sim.state())
     sim.set_tiling(*tiling)
     sim.set_time_blocking(T)
@@ -109,19 +111,29 @@ def test_slab_full_size_in_the_benchmark_configurations(shape, T, tiling, nslab)
     nz = NZ // nslab
     stream = prs._stream_handle(torch.cuda.current_stream())
     ps = prs.make_params(tuple(shape[:-1]) + (nz,), **kw)
-    for sl in (0, nslab // 2, nslab - 1):
+    nb = prs.prs_slab_scratch_bytes(ps, T, tiling)
+    scratch = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    sites = gp.n[0] * gp.n[1] * (gp.n[2] if len(shape) == 3 else 1) // nslab
+    links, walls, area, ek = 0, 0, 0.0, 0.0
+    for sl in range(nslab):
         z0 = sl * nz
         planes = torch.tensor([(z0 - T + k) % NZ for k in range(nz + 2 * T)], device="cuda")
         phi_in = phi3.view(lay).index_select(0, planes).contiguous()
         pi_in = pi3.view(lay).index_select(0, planes).contiguous()
         phi_out = torch.zeros_like(phi_in)
         pi_out = torch.zeros_like(pi_in)
-        prs.prs_slab_pass(ps, 3, T, tiling, phi_in.data_ptr(), phi_out.data_ptr(), pi_in.data_ptr(),
-                          pi_out.data_ptr(), stream)
-        torch.cuda.synchronize()
+        rec = prs.prs_slab_pass_stats(ps, 3, T, tiling, phi_in.data_ptr(), phi_out.data_ptr(), pi_in.data_ptr(),
+                                      pi_out.data_ptr(), scratch.data_ptr(), nb, stream)
         assert torch.equal(phi_out[T:T + nz], ref_phi[z0:z0 + nz]), sl
         assert torch.equal(pi_out[T:T + nz], ref_pi[z0:z0 + nz]), sl
+        links += rec["links"]
+        walls += rec["wall_sites"]
+        area += rec["area_density"] * sites
+        ek += rec["gv2"] * rec["wall_sites"]
         del phi_in, pi_in, phi_out, pi_out
+    assert links == whole["links"] and walls == whole["wall_sites"] > 0
+    assert abs(area / (sites * nslab) - whole["area_density"]) <= 1e-12 * whole["area_density"]
+    assert abs(ek / walls - whole["gv2"]) <= 1e-12 * whole["gv2"]
     del sim, phi3, pi3, ref_phi, ref_pi
     torch.cuda.empty_cache()
 
