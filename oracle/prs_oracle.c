@@ -251,13 +251,15 @@ int64_t orc_run(const orc_params *p, int64_t n0, int64_t nsteps, int32_t diag_ev
 {
     int64_t N = sites_of(p), written = 0;
     double *tmp = malloc((size_t)N * sizeof(double));
+    double *cur = phi, *next = tmp;       /* ping-pong: phi^n in cur */
     for (int64_t k = 0; k < nsteps; ++k) {
         int64_t n = n0 + k;
         if (diag_every > 0 && n % diag_every == 0 && written < cap && series)
-            orc_stats(p, n, phi, pi, &series[written++]);
-        orc_step(p, n, phi, pi, tmp);
-        memcpy(phi, tmp, (size_t)N * sizeof(double));
+            orc_stats(p, n, cur, pi, &series[written++]);
+        orc_step(p, n, cur, pi, next);
+        double *t = cur; cur = next; next = t;
     }
+    if (cur != phi) memcpy(phi, cur, (size_t)N * sizeof(double));
     free(tmp);
     return written;
 }

@@ -42,6 +42,22 @@ MUTATIONS = [
     ("force with a^(beta/2)", "return pow(pow(orc_eta(p, n) / p->eta0, p->m), p->beta);",
      "return pow(pow(orc_eta(p, n) / p->eta0, p->m), 0.5 * p->beta);"),
     ("wall potential energy without a^beta", "double V = A * Vpot(p, phi[i]);", "double V = Vpot(p, phi[i]);"),
+    ("area gradient by forward difference", "double g = (phi[jf] - phi[jb]) / (2.0 * p->dx);",
+     "double g = (phi[jf] - phi[i]) / p->dx;"),
+    ("area weight at the upper endpoint",
+     "            if (crossings) {\n                double w = gabs > 0.0 ? sqrt(gsq) / gabs : 1.0;\n"
+     "                area += (double)crossings * w;\n            }",
+     "            for (int d2 = 0; d2 < p->ndim; ++d2) {\n"
+     "                int64_t j = neighbour(p, x, y, z, d2, +1);\n"
+     "                if (si == (phi[j] >= 0.0)) continue;\n"
+     "                int64_t jx = j % nx, jy = (j / nx) % ny, jz = j / (nx * ny);\n"
+     "                double s2 = 0.0, s1 = 0.0;\n"
+     "                for (int e = 0; e < p->ndim; ++e) {\n"
+     "                    double h = phi[neighbour(p, jx, jy, jz, e, +1)] - phi[neighbour(p, jx, jy, jz, e, -1)];\n"
+     "                    s2 += h * h; s1 += fabs(h);\n"
+     "                }\n"
+     "                area += s1 > 0.0 ? sqrt(s2) / s1 : 1.0;\n"
+     "            }"),
     ("adjoint V'' without a^beta", "mu[i] = mu[i] + b * (lw - A * d2V(p, ph[i]) * w[i]);",
      "mu[i] = mu[i] + b * (lw - d2V(p, ph[i]) * w[i]);"),
 ]
@@ -61,6 +77,8 @@ def pins():
         ("P9 zero", P.test_p9_zero_tiebreak),
         ("P10 diagonal", lambda: P.test_p10_diagonal_walls((32, 32))),
         ("P10 dx", P.test_p10_area_scales_with_dx),
+        ("P10 oblique", lambda: P.test_p10_oblique_sine_walls(32)),
+        ("P10 lower endpoint", lambda: P.test_p10_weight_at_lower_endpoint((16, 12))),
         ("P11 velocity", lambda: P.test_p11_boosted_wall_velocity((64, 8), 0.3)),
         ("P11 wall sites", P.test_p11_mean_over_wall_sites_only),
         ("P13 adjoint", lambda: P.test_adjoint_matches_finite_differences(16, 3.0, 0.0)),

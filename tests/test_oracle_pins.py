@@ -360,6 +360,59 @@ def test_p10_diagonal_walls(shape):
     assert r["area_density"] == pytest.approx(2.0 * math.sqrt(D) / N, rel=1e-14)
 
 
+@pytest.mark.parametrize("N", [16, 32, 64])
+def test_p10_oblique_sine_walls(N):
+    """P10c: walls normal to (1, 2).  phi = sin(theta (x + 2y + 1/2)) with
+    theta = 2 pi / N is a function of u = x + 2y with two zeros per period.
+    A centred difference of a single Fourier mode is exact up to a factor:
+    g_x = 2 cos(theta(u + 1/2)) sin(theta), g_y = 2 cos(theta(u + 1/2))
+    sin(2 theta), so at every site |g_y|/|g_x| = 2 cos(theta) and each
+    crossing link has weight w = sqrt(1 + 4c^2)/(1 + 2c), c = cos(theta).
+    Each row crosses the zero set twice along x and each column four times
+    along y (steps of 2 in u), so there are 2N + 4N crossing links and
+    rho = 6 w / N, which tends to the continuum 2 sqrt(5)/N.  A one-sided
+    difference makes the ratio depend on u and misses this value."""
+    shape = (N, N)
+    x, y = F.coords(shape)
+    th = 2.0 * math.pi / N
+    phi = np.sin(th * (x + 2.0 * y + 0.5))
+    r = O.stats(O.params(shape, deta=0.25), phi.reshape(-1), np.zeros(phi.size))
+    assert r["links_dir"][:2] == [2 * N, 4 * N]
+    c = math.cos(th)
+    w = math.sqrt(1.0 + 4.0 * c * c) / (1.0 + 2.0 * c)
+    assert r["area_density"] == pytest.approx(6.0 * w / N, rel=1e-12)
+    assert abs(r["area_density"] - 2.0 * math.sqrt(5.0) / N) < 4.0 * th * th / N
+
+
+@pytest.mark.parametrize("shape", [(16, 12), (12, 8, 6)])
+def test_p10_weight_at_lower_endpoint(shape):
+    """P10d: the gradient of a link's weight is taken at its lower-index
+    site.  Two walls normal to x between constant columns x = 3 | 4 and
+    x = 11 | 12 (shifted per lattice): the columns at the walls' lower sides
+    (x = 3 and x = 11) are uniform in y and z, so the centred gradient there
+    has no transverse part and every crossing link weighs exactly 1:
+    rho = 2/N_x.  The columns on the upper sides vary along y (keeping their
+    sign), so a weight evaluated at the upper endpoint would be below 1."""
+    nx = shape[0]
+    x, y = F.coords(shape)[:2]
+    ny = shape[1]
+    phi = np.where(x < nx // 4 + 1, -0.75, 0.0)
+    lo1, up1 = nx // 4 - 1 + 1, nx // 4 + 1          # wall 1 between columns lo1 and up1
+    lo2, up2 = 3 * nx // 4 - 1 + 1, 3 * nx // 4 + 1  # wall 2 between lo2 and up2
+    wave = 0.25 * np.sin(2.0 * math.pi * (y + 0.25) / ny)
+    phi = np.where(x < lo1, -0.75, phi)
+    phi = np.where(x == lo1, -0.5, phi)
+    phi = np.where(x == up1, 0.5 + wave, phi)
+    phi = np.where((x > up1) & (x < lo2), 0.75, phi)
+    phi = np.where(x == lo2, 0.5, phi)
+    phi = np.where(x == up2, -0.5 - wave, phi)
+    phi = np.where(x > up2, -0.75, phi)
+    r = O.stats(O.params(shape, deta=0.25), phi.reshape(-1), np.zeros(phi.size))
+    sites = int(np.prod(shape))
+    assert r["links_dir"][0] == 2 * sites // nx and sum(r["links_dir"][1:]) == 0
+    assert r["area_density"] == pytest.approx(2.0 / nx, rel=1e-15)
+
+
 def test_p10_area_scales_with_dx():
     """rho carries dx^(D-1)/dx^D = 1/dx for the same site pattern."""
     shape = (16, 16)
