@@ -25,23 +25,50 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-BYTES_PER_UPDATE = 16          # read phi, phi_dot; write phi^{n+1}, phi_dot (FP32)
-# HBM bytes of one launch of the dominant kernel on the 8192^2 lattice, by
-# (vec, rows, ty, steps per pass): rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB per
-# dispatch) scaled by what the same counters read for a plain 256 MiB copy
-# (factors 1.9998 and 1.0000); see profiles/k_tb2d_2d8192.md.  A
-# configuration without a measurement reports null.
+# MI355X vector-ALU issue rate without packed FP32 (the kernels are built
+# without it): 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic HBM bytes of one pass per site (FP32): phi and phi_dot read
+# once and written once, whatever the number of steps the pass fuses
+BYTES_PER_SITE_PASS = 16
+# The same 16 bytes per site-update is the traffic of a single-step pass: the
+# figure the site-update rate is compared with as "effective" bandwidth
+BYTES_PER_UPDATE = 16
+# HBM bytes of one launch of a pass kernel, by (lattice, vec, rows, ty, steps
+# per pass): rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB per dispatch) scaled by
+# what the same counters read for a plain 256 MiB copy (factors 2.00 and
+# 1.00), from the profile named in each entry, taken on kernel sources whose
+# digest (kernel_digest()) is recorded with it.  When the sources differ now
+# the counters no longer describe the kernel and the bench reports null.
 TRAFFIC_PER_LAUNCH = {
-    (2, 64, 1, 8): 1157492691,
-    (2, 128, 1, 8): 1133803299,
+    ("2d8192", 2, 64, 1, 8): {"bytes": 1157032874, "profile": "profiles/k_tb2d_2d8192.md",
+                              "sources": "1294b7d0a17ed25b"},
+    ("2d8192", 2, 128, 1, 8): {"bytes": 1133449051, "profile": "profiles/k_tb2d_2d8192.md",
+                               "sources": "1294b7d0a17ed25b"},
 }
 
 WORKLOAD = {
     "name": "2D PRS 8192^2, matter era m=2, W0=10, deta=0.25, eta 1->4096 (16380 steps), "
             "diagnostics every 64 steps + final, exponent fit over the last decade",
-    "shape": (8192, 8192), "m": 2.0, "W0": 10.0, "deta": 0.25, "eta_end": 4096.0,
+    "key": "2d8192", "shape": (8192, 8192), "m": 2.0, "W0": 10.0, "deta": 0.25, "eta_end": 4096.0,
     "diag_every": 64, "seed": 1,
 }
+WORKLOAD_3D = {
+    "name": "3D PRS 1024^3, radiation era m=1, W0=10, deta=0.2, eta 1->512 (2555 steps), "
+            "diagnostics every 50 steps + final, exponent fit over the last decade",
+    "key": "3d1024", "shape": (1024, 1024, 1024), "m": 1.0, "W0": 10.0, "deta": 0.2, "eta_end": 512.0,
+    "diag_every": 50, "seed": 1,
+}
+
+
+def kernel_digest():
+    """Digest of the kernel sources (device code and its launch templates)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("prs_device.h", "prs_kernels.hip", "prs_internal.h"):
+        with open(os.path.join(ROOT, "paper_1710_10420_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -64,11 +91,11 @@ def one_run(sim, prs, w, S, stream_handle):
     return recs, mu, nu
 
 
-def cpu_baseline(w, budget_s=20.0):
+def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle on the host cores over a bounded prefix of the same
-    run (the first steps from the same seeded field)."""
-    import numpy as np
-
+    run (the first steps from the same seeded field): once on every core the
+    process may use and once on a single thread (the paper's CPU baseline is
+    sequential code)."""
     from oracle import oracle as O
     from paper_1710_10420_amd.inputs import uniform_field
 
@@ -76,20 +103,193 @@ def cpu_baseline(w, budget_s=20.0):
     op = O.params(shape, deta=w["deta"], m=w["m"], W0=w["W0"])
     phi = uniform_field(shape, w["seed"]).astype(np.float64).reshape(-1)
     pi = np.zeros_like(phi)
-    threads = len(os.sched_getaffinity(0))
-    O.set_threads(threads)
     sites = phi.size
+    out = {}
+    cores = len(os.sched_getaffinity(0))
+    for label, threads in (("all_cores", cores), ("single_thread", 1)):
+        O.set_threads(threads)
+        t0 = time.perf_counter()
+        O.run(op, phi, pi, 1)                       # calibration step
+        per = time.perf_counter() - t0
+        steps = max(1, min(64, int(budget_s / max(per, 1e-6))))
+        t0 = time.perf_counter()
+        O.run(op, phi, pi, steps, diag_every=w["diag_every"])
+        dt = time.perf_counter() - t0
+        out[label] = {"value": sites * steps / dt, "cores": threads, "steps": steps, "seconds": dt}
+    O.set_threads(cores)
+    a = out["all_cores"]
+    return {"value": a["value"], "unit": "site-updates/s", "cores": a["cores"], "kind": "oracle",
+            "sample": "FP64 oracle, first %d of %d steps of the same %s run (diagnostics every %d included), "
+                      "%.1f s on %d threads" % (a["steps"], n_steps(w), "x".join(map(str, shape)),
+                                                 w["diag_every"], a["seconds"], a["cores"]),
+            "single_thread": dict(out["single_thread"], unit="site-updates/s",
+                                  sample="first %d steps on one thread" % out["single_thread"]["steps"])}
+
+
+def copy_ceiling(prs, torch, nbytes=1 << 30, reps=10):
+    """Bandwidth of the library's plain copy kernel (prs_copy) between two
+    1 GiB buffers: bytes read plus bytes written per second, the best of
+    `reps` timed copies."""
+    stream = torch.cuda.current_stream()
+    sh = prs._stream_handle(stream)
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    prs.prs_copy(dst.data_ptr(), src.data_ptr(), nbytes, sh)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        prs.prs_copy(dst.data_ptr(), src.data_ptr(), nbytes, sh)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    ok = bool(torch.equal(src[:1024], dst[:1024]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "k_copy16 (prs_copy)", "bytes_per_copy": 2 * nbytes, "best_us": best * 1e6,
+            "gbs": 2 * nbytes / best / 1e9, "frac_of_peak": 2 * nbytes / best / 1e9 / HBM_PEAK_GBS,
+            "checked": ok}
+
+
+def isa_counts():
+    path = os.path.join(ROOT, "paper_1710_10420_amd", "isa_counts.json")
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except OSError:
+        return None
+
+
+def pass_valu_lane_ops(shape, tiling, T, counts):
+    """Vector-ALU lane operations of one launch of the T-step pass over the
+    lattice, from the march loop's instruction count in this build: a wave
+    issues the loop's VALU instructions per iteration for every level that
+    has a row (2D) or plane (3D) at that iteration (level k starts 2(k-1)
+    iterations late; a tile of r rows or planes runs r + 2T - 2 iterations),
+    64 lanes each.  (None, None) when the counts are missing."""
+    vec, rows, ty = tiling
+    if counts is None:
+        return None, None
+    H = -(-T // vec)
+    W = (64 - 2 * H) * vec
+    tiles_x = -(-shape[0] // W)
+    M = shape[-1]
+    if len(shape) == 2:
+        own_rows = 1
+        c = counts.get("k_tb2d<%d,%d,0,1,f>" % (vec, T))
+        tiles_q = 1
+    else:
+        own_rows = 8 if ty == 4 else 4             # rows along y a wave owns
+        c = counts.get("k_tb3d<%d,%d,%d,0,1,f>" % (vec, T, own_rows))
+        tiles_q = -(-shape[1] // own_rows)
+    if not c or c["vmem_store"] < 2 * own_rows:
+        return None, None
+    iters_in_loop = c["vmem_store"] / (2.0 * own_rows)   # level T stores phi and phi_dot of the owned rows
+    per_iter = c["valu"] / iters_in_loop
+    level_iters = 0
+    for s0 in range(0, M, rows):
+        n = min(rows, M - s0) + 2 * T - 2
+        level_iters += sum(n - 2 * (k - 1) for k in range(1, T + 1))
+    lane_ops = per_iter / T * level_iters * tiles_x * tiles_q * 64
+    return lane_ops, {"valu_per_iteration": per_iter,
+                      "valu_per_owned_site_update": per_iter / (vec * own_rows * T),
+                      "loop_instructions": c}
+
+
+def forward_leg(prs, torch, w, runs, warmup, tiling=None, steps_per_pass=None, extra=True):
+    """Whole runs of a forward workload: tuned (or given) tiling and steps per
+    pass, `warmup` untimed runs, then `runs` timed runs bracketed by stream
+    events, with launch timing on, so that the average duration of the pass
+    kernel is measured live over the timed region."""
+    S = n_steps(w)
+    stream = torch.cuda.current_stream()
+    sh = prs._stream_handle(stream)
+    gp = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"], diag_every=w["diag_every"])
+    sites = prs.sites(gp)
+    sim = prs.Sim(gp, seed=w["seed"])
+    if tiling:
+        sim.set_tiling(*tiling)
+        sim.set_time_blocking(steps_per_pass or 1)
+    else:
+        prs.prs_autotune(sim.ctx, None, 0)    # tiling and steps per pass, before the timed region
+    log(w["key"], "tiling", sim.tiling(), "steps/pass", sim.time_blocking(), "steps/run", S)
+    for i in range(warmup):
+        log(w["key"], "warmup run", i)
+        one_run(sim, prs, w, S, sh)
+    torch.cuda.synchronize()
+    prs.prs_set_launch_timing(sim.ctx, True)
+    prs.prs_get_launch_timing(sim.ctx, reset=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    O.run(op, phi, pi, 1)                       # calibration step
-    per = time.perf_counter() - t0
-    steps = max(2, min(64, int(budget_s / max(per, 1e-6))))
-    t0 = time.perf_counter()
-    O.run(op, phi, pi, steps, diag_every=w["diag_every"])
-    dt = time.perf_counter() - t0
-    return {"value": sites * steps / dt, "unit": "site-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "FP64 oracle, first %d of %d steps of the same 8192^2 run "
-                      "(diagnostics every 64 included), %.1f s" % (steps, n_steps(w), dt)}
+    ev0.record(stream)
+    results = []
+    for i in range(runs):
+        results.append(one_run(sim, prs, w, S, sh))
+        log(w["key"], "timed run", i, "done")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    k_ms, k_launches = prs.prs_get_launch_timing(sim.ctx, reset=True)
+    prs.prs_set_launch_timing(sim.ctx, False)
+
+    updates = float(sites) * S * runs
+    T = sim.time_blocking()
+    til = tuple(sim.tiling())
+    multi, single = prs.prs_plan_passes(sim.ctx, S, True)
+    avg_launch_s = k_ms / 1e3 / k_launches if k_launches else None
+    per_launch_bytes = BYTES_PER_SITE_PASS * sites           # algorithmic bytes of one pass
+    achieved = per_launch_bytes / avg_launch_s / 1e9 if avg_launch_s else None
+    digest = kernel_digest()
+    tr = TRAFFIC_PER_LAUNCH.get((w["key"],) + til + (T,))
+    traffic = tr["bytes"] if tr and tr["sources"] == digest else None
+    lane_ops, isa = pass_valu_lane_ops(w["shape"], til, T, isa_counts()) if T > 1 else (None, None)
+    kernel = ("k_tb%dd<vec=%d,T=%d> (%d fused leapfrog steps per pass)" % (len(w["shape"]), til[0], T, T)
+              if T > 1 else "k_step (one fused leapfrog step per pass)")
+    recs, mu, nu = results[-1]
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic,
+            "kernel": kernel,
+            "algorithmic_bytes_per_launch": per_launch_bytes,
+            "algorithmic_bytes_per_site_per_pass": BYTES_PER_SITE_PASS,
+            "site_updates_per_launch": sites * T,
+            "avg_launch_us": avg_launch_s * 1e6 if avg_launch_s else None,
+            "timed_launches": k_launches,
+            "launch_timing": "HIP events on the library's stream around each run of consecutive pass-kernel "
+                             "launches inside the timed region (prs_set_launch_timing)",
+            # the site-update rate of the pass as the bandwidth a single-step
+            # pass (16 B per site-update) would need, over the HBM peak
+            "effective_single_step_gbs": (BYTES_PER_UPDATE * sites * T / avg_launch_s / 1e9
+                                          if avg_launch_s else None),
+            "effective_single_step_frac": (BYTES_PER_UPDATE * sites * T / avg_launch_s / 1e9 / HBM_PEAK_GBS
+                                           if avg_launch_s else None),
+            "passes_per_run": {"multi_step": multi, "single_step": single}}
+    if traffic:
+        roof["dram_gbs"] = traffic / avg_launch_s / 1e9
+        roof["dram_frac"] = roof["dram_gbs"] / HBM_PEAK_GBS
+        roof["traffic_over_algorithmic"] = traffic / per_launch_bytes
+        roof["traffic_source"] = tr["profile"] + " (kernel sources " + tr["sources"] + ")"
+    else:
+        roof["traffic_source"] = ("no counters for this tiling and these kernel sources (%s)" % digest)
+    if lane_ops and avg_launch_s:
+        roof["valu_lane_ops_per_launch"] = lane_ops
+        roof["valu_frac"] = lane_ops / avg_launch_s / VALU_PEAK_LANE_OPS
+        roof["valu_peak_lane_ops_per_s"] = VALU_PEAK_LANE_OPS
+        roof["valu_per_owned_site_update"] = isa["valu_per_owned_site_update"]
+        roof["valu_source"] = "march-loop instruction counts of this build (isa_counts.json)"
+    out = {"value": updates / wall, "wall_s": wall, "ms_per_run": wall / runs * 1e3,
+           "event_ms_per_run": ev_ms / runs, "sites": sites, "steps_per_run": S,
+           "records_per_run": len(recs), "tiling": list(til), "steps_per_pass": T,
+           "roofline": roof,
+           "result": {"mu": mu, "nu": nu, "final_links": recs[-1]["links"],
+                      "final_area_density": recs[-1]["area_density"]}}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
 
 
 ADJOINT = [
@@ -105,7 +305,7 @@ def adjoint_leg(prs, torch, reps=3):
     separately with stream events."""
     out = {"workload": "adjoint, 1024 steps from seed 7, m=1, W0=10, checkpoints every 64, "
                        "loss = sum V(phi)/V0; grad w.r.t. phi0 and W0",
-           "bytes_per_site_update": {"forward": 16, "reverse": 36}}
+           "single_step_bytes_per_site_update": {"forward": 16, "backward": 36}}
     stream = torch.cuda.current_stream()
     for cfg in ADJOINT:
         p = prs.make_params(cfg["shape"], deta=cfg["deta"], m=1.0, W0=10.0)
@@ -131,31 +331,14 @@ def adjoint_leg(prs, torch, reps=3):
                 fwd.append(e0.elapsed_time(e1))
                 bwd.append(e1.elapsed_time(e2))
         tf, tb = min(fwd), min(bwd)
-        # the same forward-with-checkpoints in single-step passes (16 B per
-        # site-update, the basis of the backward/forward target)
-        T_fwd = sim.time_blocking()
-        sim.set_time_blocking(1)
-        fwd1 = []
-        for r in range(reps + 1):
-            sim.set_state(phi0, torch.zeros_like(phi0), 0)
-            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
-            e0.record(stream)
-            prs.prs_adjoint_forward(sim.ctx, ADJ_STEPS, ADJ_K, work.data_ptr(), nb)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            if r > 0:
-                fwd1.append(e0.elapsed_time(e1))
-        sim.set_time_blocking(T_fwd)
-        tf1 = min(fwd1)
         su = float(sites) * ADJ_STEPS
         out[cfg["name"]] = {
             "forward_ms": tf, "backward_ms": tb, "backward_over_forward": tb / tf,
             "total_over_forward": (tf + tb) / tf,
-            "single_step_forward_ms": tf1, "backward_over_single_step_forward": tb / tf1,
             "forward_site_updates_per_s": su / (tf / 1e3),
             "adjoint_site_updates_per_s": su / (tb / 1e3),
-            "forward_hbm_frac": su * 16 / (tf / 1e3) / (HBM_PEAK_GBS * 1e9),
-            "reverse_hbm_frac": su * 36 / (tb / 1e3) / (HBM_PEAK_GBS * 1e9),
+            "forward_effective_single_step_frac": su * 16 / (tf / 1e3) / (HBM_PEAK_GBS * 1e9),
+            "backward_effective_single_step_frac": su * 36 / (tb / 1e3) / (HBM_PEAK_GBS * 1e9),
             "loss": loss, "grad_W0": gw, "tiling": list(sim.tiling()),
             "steps_per_pass": sim.time_blocking(),
             "adjoint_tiling": list(prs.prs_get_adjoint_tiling(sim.ctx)),
@@ -214,7 +397,8 @@ def batch_leg(prs, torch, reps=2):
                        "{512^2,1024^2,2048^2}, 16 3D from {128^3,256^3}, m in {0.5,1,2}, "
                        "W0 in {5,10}, each to eta = N/2, diagnostics every 64 (2D) / 50 (3D)",
            "realisations": len(specs), "site_updates": su, "ms_per_run": t * 1e3,
-           "site_updates_per_s": su / t, "hbm_frac": su * 16 / t / (HBM_PEAK_GBS * 1e9),
+           "site_updates_per_s": su / t,
+           "effective_single_step_frac": su * 16 / t / (HBM_PEAK_GBS * 1e9),
            "records": sum(len(r) for r in recs), "mode": "4 concurrent streams",
            "tilings": {"x".join(map(str, k)): {"tiling": list(v[0]), "steps_per_pass": v[1]}
                        for k, v in tuned.items()},
@@ -327,7 +511,7 @@ def f64_leg(prs, torch, w, reps=2):
     su = float(prs.sites(p)) * F64_STEPS
     out = {"workload": "8192^2 in float64, first %d steps of the run (records every 64)" % F64_STEPS,
            "site_updates_per_s": su / t, "ms": t * 1e3, "bytes_per_site_update": 32,
-           "hbm_frac_algorithmic": su * 32 / t / (HBM_PEAK_GBS * 1e9),
+           "effective_single_step_frac": su * 32 / t / (HBM_PEAK_GBS * 1e9),
            "tiling": list(sim.tiling()), "steps_per_pass": sim.time_blocking()}
     log("f64 %.1f ms for %d steps" % (t * 1e3, F64_STEPS))
     sim.close()
@@ -342,7 +526,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and ensemble legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip every leg after the headline and the copy")
     ap.add_argument("--tiling", default=None, help="vec,rows,ty for the main run (default: autotuned)")
     ap.add_argument("--steps-per-pass", type=int, default=2, help="with --tiling")
     args = ap.parse_args()
@@ -356,91 +540,40 @@ def main():
     from paper_1710_10420_amd import prs
 
     w = WORKLOAD
-    S = n_steps(w)
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    sh = prs._stream_handle(stream)
-    gp = prs.make_params(w["shape"], deta=w["deta"], m=w["m"], W0=w["W0"],
-                         diag_every=w["diag_every"])
-    sites = prs.sites(gp)
-    sim = prs.Sim(gp, seed=w["seed"])
-    if args.tiling:
-        sim.set_tiling(*[int(v) for v in args.tiling.split(",")])
-        sim.set_time_blocking(args.steps_per_pass)
-    else:
-        prs.prs_autotune(sim.ctx, None, 0)    # tiling and steps per pass, before the timed region
-    log("tiling", sim.tiling(), "steps/pass", sim.time_blocking(), "steps/run", S)
-
-    for i in range(args.warmup):
-        log("warmup run", i)
-        one_run(sim, prs, w, S, sh)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    results = []
-    for i in range(args.steps):
-        results.append(one_run(sim, prs, w, S, sh))
-        log("timed run", i, "done")
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
-
-    updates = float(sites) * S * args.steps
-    value = updates / wall
-    # dominant kernel: the T-step pass (k_tb2d; records only at pass
-    # starts).  Its launch duration is estimated from the stream events over
-    # the timed region as the time per step times T (the region also holds
-    # the single-step passes next to records, the record reductions and each
-    # run's initial field); the kernel-trace profile gives the exact average.
-    spp = sim.time_blocking()
-    multi, single = prs.prs_plan_passes(sim.ctx, S, True)
-    step_s = ev_ms / 1e3 / (S * args.steps)
-    avg_launch_s = step_s * spp
-    alg_bytes = BYTES_PER_UPDATE * sites * spp        # algorithmic bytes of one launch
-    achieved = alg_bytes / avg_launch_s / 1e9
-    recs, mu, nu = results[-1]
-    traffic = TRAFFIC_PER_LAUNCH.get(tuple(sim.tiling()) + (spp,))
+    tiling = [int(v) for v in args.tiling.split(",")] if args.tiling else None
+    c2 = forward_leg(prs, torch, w, args.steps, args.warmup, tiling, args.steps_per_pass)
+    roof = c2["roofline"]
+    copy = copy_ceiling(prs, torch)
+    if roof["achieved"]:
+        roof["copy_ceiling_gbs"] = copy["gbs"]
+        roof["frac_of_copy_ceiling"] = roof["achieved"] / copy["gbs"]
     out = {
         "metric": "site-updates/s (PRS forward step, fused wall diagnostics)",
-        "value": value,
+        "value": c2["value"],
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": c2["ms_per_run"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic: seeded uniform(-1,1) initial field (SplitMix64), phi_dot = 0",
-        "config": {"workload": w["name"], "sites": sites, "steps_per_run": S,
-                   "records_per_run": len(recs), "tiling": list(sim.tiling()),
-                   "steps_per_pass": sim.time_blocking()},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     # measured HBM bytes per launch over the live launch time:
-                     # the share of the 8 TB/s peak the pass really moves
-                     "dram_gbs": traffic / avg_launch_s / 1e9 if traffic else None,
-                     "dram_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS if traffic else None,
-                     "kernel": ("k_tb2d<vec=%d,T=%d> (%d fused leapfrog steps per pass)" % (
-                         sim.tiling()[0], spp, spp)) if spp > 1 else
-                               "k_step<2,%d,1> (fused leapfrog step)" % sim.tiling()[0],
-                     "passes_per_run": {"multi_step": multi, "single_step": single},
-                     "algorithmic_bytes_per_launch": alg_bytes, "site_updates_per_launch": sites * spp,
-                     "avg_launch_us": avg_launch_s * 1e6},
-        "result": {"mu": mu, "nu": nu, "final_links": recs[-1]["links"],
-                   "final_area_density": recs[-1]["area_density"]},
+        "config": {"workload": w["name"], "sites": c2["sites"], "steps_per_run": c2["steps_per_run"],
+                   "records_per_run": c2["records_per_run"], "tiling": c2["tiling"],
+                   "steps_per_pass": c2["steps_per_pass"]},
+        "roofline": roof,
+        "result": c2["result"],
+        "copy_ceiling": copy,
     }
     if not args.no_extra:
-        sim.close()
-        del sim
-        torch.cuda.empty_cache()
+        c3 = forward_leg(prs, torch, WORKLOAD_3D, 1, 1)
+        if c3["roofline"]["achieved"]:
+            c3["roofline"]["frac_of_copy_ceiling"] = c3["roofline"]["achieved"] / copy["gbs"]
+        c3["workload"] = WORKLOAD_3D["name"]
+        out["c3"] = c3
         out["adjoint"] = adjoint_leg(prs, torch)
         out["batch"] = batch_leg(prs, torch)
         out["f64"] = f64_leg(prs, torch, w)

@@ -121,13 +121,17 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi,
  * the count of n in [n0, n0+nsteps) with n % diag_every == 0. */
 int64_t prs_records_in(const prs_params* p, int64_t n0, int64_t nsteps);
 
-/* Advance nsteps steps (Eqs. 3-6), one fused kernel launch per step.  When
- * series is non-NULL the diagnostics of every state n with n % diag_every == 0
- * are computed inside that step's kernel (on its input state) and written to
- * series[0 .. *n_written-1]; cap must be at least prs_records_in(...), else
- * PRS_EINVAL.  With series == NULL no diagnostics are computed.  Splitting a
- * call into two consecutive calls gives bit-identical fields and records.
- * Synchronises the stream when series is non-NULL. */
+/* Advance nsteps steps (Eqs. 3-6).  The Laplacian, kick and drift of a step
+ * run fused in one kernel, and a launch advances up to steps_per_pass steps
+ * at once (prs_set_time_blocking: default 2 in 2D, 1 in 3D; the autotuner
+ * may choose up to 8 in 2D and 3 in 3D), never with a recorded state inside
+ * a pass.  When series is non-NULL the diagnostics (Eqs. 7-8) of every state
+ * n with n % diag_every == 0 are computed inside the pass that starts at n
+ * (on its input state) and written to series[0 .. *n_written-1]; cap must be
+ * at least prs_records_in(...), else PRS_EINVAL.  With series == NULL no
+ * diagnostics are computed.  Splitting a call into two consecutive calls
+ * gives bit-identical fields and records.  Synchronises the stream when
+ * series is non-NULL or launch timing is on. */
 prs_status prs_step_n(prs_ctx* ctx, int64_t nsteps, prs_stats* series, int64_t cap,
                       int64_t* n_written);
 
@@ -157,21 +161,55 @@ prs_status prs_set_state(prs_ctx* ctx, const void* phi, const void* dphi, int64_
 prs_status prs_set_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
 prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
 
-/* Autotuner.  Times every supported tiling for this lattice on the
- * context's own state (saved before and restored after each candidate; the
- * library allocates two temporary fields with hipMalloc for that), applies the
- * fastest to the context and records it in the JSON file cache_path (created
- * or updated; NULL or "" for no cache).  A cached entry for the same GPU
+/* Autotuner (Sec. IV: the kernels' work-group shapes were tuned for one
+ * card, and another card needs them chosen again; here the choice is made
+ * by timing on the card in use).  Times every supported tiling and steps per
+ * pass for this lattice on the context's own state (saved into the caller's
+ * workspace before and restored after each candidate), applies the fastest
+ * to the context and records it in the JSON file cache_path (created or
+ * updated; NULL or "" for no cache).  A cached entry for the same GPU
  * architecture, dimension, lattice size and tiling set is applied without
- * timing unless flags has PRS_TUNE_FORCE.  PRS_TUNE_BATCH restricts the
- * candidates to the tilings the persistent batch modes support (ty = 1, single
- * steps); the STREAMS batch modes take the ordinary choice (tiling and steps
- * per pass).  *best_us (may be NULL)
- * receives the time of one step with the chosen tiling.  Synchronises. */
+ * timing (and without touching the workspace, which may then be NULL) unless
+ * flags has PRS_TUNE_FORCE.  PRS_TUNE_BATCH restricts the candidates to the
+ * tilings the persistent batch modes support (ty = 1, single steps); the
+ * STREAMS batch modes take the ordinary choice (tiling and steps per pass).
+ * PRS_TUNE_ADJOINT tunes the reverse sweep's tiling and steps per pass
+ * instead, on scratch fields in the workspace.
+ *   work, work_bytes : device scratch owned by the caller, 256-byte aligned,
+ *                      at least prs_tune_workspace_bytes(ctx, flags) bytes
+ *                      (PRS_ENOMEM otherwise); the library allocates nothing.
+ *                      The adjoint tuner needs at least the size returned
+ *                      with PRS_TUNE_MIN_WORKSPACE added to its flags and
+ *                      fills what is beyond it with up to 32 distinct phi
+ *                      fields, which the timed reverse steps read in
+ *                      rotation as the backward does.
+ * *best_us (may be NULL) receives the time of one step with the chosen
+ * tiling.  Synchronises. */
 #define PRS_TUNE_FORCE 1
 #define PRS_TUNE_BATCH 2
 #define PRS_TUNE_ADJOINT 4   /* tune the reverse sweep's tiling and steps per pass instead */
-prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, double* best_us);
+#define PRS_TUNE_MIN_WORKSPACE 8   /* prs_tune_workspace_bytes: the least the tuner accepts */
+size_t prs_tune_workspace_bytes(const prs_ctx* ctx, int32_t flags);
+prs_status prs_autotune(prs_ctx* ctx, const char* cache_path, int32_t flags, void* work, size_t work_bytes,
+                        double* best_us);
+
+/* Launch timing, for measurement.  With on != 0, prs_step_n brackets every
+ * run of consecutive launches of its pass kernel (the steps_per_pass-step
+ * pass without diagnostics) with a pair of HIP events on the context's
+ * stream, synchronises the stream before returning and adds the runs'
+ * durations and launch counts to two totals.  prs_get_launch_timing reads
+ * the totals (milliseconds and launches; either pointer may be NULL) and
+ * clears them when reset != 0.  Off by default; timing adds two event
+ * records per run of launches and changes no result. */
+prs_status prs_set_launch_timing(prs_ctx* ctx, int32_t on);
+prs_status prs_get_launch_timing(prs_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
+
+/* Plain device-to-device copy of `bytes` bytes (a multiple of 16) between
+ * two 16-byte aligned, non-overlapping device buffers, enqueued on
+ * hip_stream: the bandwidth reference the passes are measured against (a
+ * pass moves its fields once, as a copy does).  PRS_EINVAL on a bad
+ * argument, PRS_EDEVICE on a launch failure. */
+prs_status prs_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 /* Cached tiling for these parameters (no GPU work); PRS_ESTATE if absent. */
 prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t flags, int32_t* vec,
@@ -209,12 +247,34 @@ prs_status prs_plan_passes(const prs_ctx* ctx, int64_t nsteps, int32_t with_reco
  * T = 2, 4 and, in float32, 8 and tilings with vec 1 or 2, and for 3D
  * lattices with T = 2 on the tilings of the 3D multi-step passes and, in
  * float32, T = 3 with vec 1 and ty 1 or 2; a pass runs the longest supported
- * length up to the setting, down to single reverse steps.  The default is the
- * forward's setting at prs_init (1 in 3D). */
+ * length up to the setting, down to single reverse steps.  The default
+ * tiling is the forward's at prs_init; the default steps per pass 4 in 2D,
+ * 1 in 3D. */
 prs_status prs_set_adjoint_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
 prs_status prs_get_adjoint_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty);
 prs_status prs_set_adjoint_time_blocking(prs_ctx* ctx, int32_t steps_per_pass);
 prs_status prs_get_adjoint_time_blocking(prs_ctx* ctx, int32_t* steps_per_pass);
+
+/* How the backward gets the fields phi^n its reverse steps need (the
+ * transposed Eqs. 3-6 read V''(phi^n) at every step n).
+ *   PRS_ADJ_STORED: per segment of ckpt_every steps a recomputation from the
+ *     checkpoint stores every step's field, and the reverse passes read them
+ *     (4 B written and 4 B read per site and step in float32, besides the
+ *     adjoint fields).
+ *   PRS_ADJ_FUSED (2D lattices): the recomputation stores only the states
+ *     (phi, phi_dot) at the starts of the reverse passes, steps_per_pass
+ *     steps apart (2, 3 or 4: the adjoint steps per pass, capped at 4), and
+ *     each reverse pass recomputes its fields in registers from its
+ *     pass-start state (16 + 8 B per site per pass in float32); the reverse
+ *     tiling then needs vec 1 or 2 (float64: vec 1) and ty 1.  A 3D lattice,
+ *     or a setting without such a kernel, runs the stored scheme.
+ * Gradient fields are bitwise equal in both schemes; dL/dW0 differs in
+ * summation order.  Default: PRS_ADJ_FUSED for 2D, PRS_ADJ_STORED for 3D.
+ * PRS_EINVAL for another value. */
+#define PRS_ADJ_STORED 0
+#define PRS_ADJ_FUSED 1
+prs_status prs_set_adjoint_scheme(prs_ctx* ctx, int32_t scheme);
+prs_status prs_get_adjoint_scheme(prs_ctx* ctx, int32_t* scheme);
 
 /* Tiling and steps per pass (1 .. 8; the longest supported length up to it
  * is used, as in prs_set_time_blocking) of the recomputation inside

@@ -109,6 +109,8 @@ def _load():
             lib.orc_adjoint.restype = ctypes.c_int
             lib.orc_delta.argtypes = [P, i64]
             lib.orc_delta.restype = ctypes.c_double
+            lib.orc_set_progress.argtypes = [ctypes.c_int]
+            lib.orc_set_progress.restype = None
             _lib = lib
     return _lib
 
@@ -152,6 +154,11 @@ def build_variant(source_text, out_path):
 def source_text():
     with open(_SRC) as f:
         return f.read()
+
+
+def set_progress(on):
+    """Print one line per segment of the adjoint's reverse sweep (stdout)."""
+    _load().orc_set_progress(1 if on else 0)
 
 
 def set_threads(n):

@@ -46,6 +46,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -129,6 +130,15 @@ static double Vpot(const orc_params *p, double f)
 {
     double q = f * f / (p->phi0 * p->phi0) - 1.0;
     return p->V0 * q * q;
+}
+
+/* When set, the long-running loops print one line per segment to stdout
+ * (progress of full-length runs; no effect on any result). */
+static int orc_progress = 0;
+
+void orc_set_progress(int on)
+{
+    orc_progress = on;
 }
 
 double orc_eta(const orc_params *p, int64_t n)
@@ -343,20 +353,21 @@ int orc_adjoint(const orc_params *p, int64_t n0, int64_t nsteps, int32_t ckpt_ev
     memcpy(phi, phi0, fb);
     memcpy(pi, pi0, fb);
 
-    /* forward sweep with checkpoints */
+    /* forward sweep with checkpoints (phi and tmp swap roles each step) */
     for (int64_t s = 0; s < nseg; ++s) {
         memcpy(ck_phi + (size_t)s * N, phi, fb);
         memcpy(ck_pi + (size_t)s * N, pi, fb);
         int64_t len = (s + 1) * K <= nsteps ? K : nsteps - s * K;
         for (int64_t k = 0; k < len; ++k) {
             orc_step(p, n0 + s * K + k, phi, pi, tmp);
-            memcpy(phi, tmp, fb);
+            double *t = phi; phi = tmp; tmp = t;
         }
     }
     *loss = orc_loss(p, phi);
 
     /* seed: dL/dphi^S = 4 phi (phi^2/phi0^2 - 1)/phi0^2; phi_dot^{S-1/2} does
      * not enter the loss */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double q = phi[i] * phi[i] / (p->phi0 * p->phi0) - 1.0;
         mu[i] = 4.0 * phi[i] * q / (p->phi0 * p->phi0);
@@ -367,6 +378,9 @@ int orc_adjoint(const orc_params *p, int64_t n0, int64_t nsteps, int32_t ckpt_ev
 
     for (int64_t s = nseg - 1; s >= 0; --s) {
         int64_t len = (s + 1) * K <= nsteps ? K : nsteps - s * K;
+        if (orc_progress)
+            fprintf(stdout, "oracle adjoint: segment %lld of %lld\n", (long long)(nseg - s), (long long)nseg),
+                fflush(stdout);
         /* recompute phi^n for the segment */
         memcpy(traj, ck_phi + (size_t)s * N, fb);
         memcpy(pi, ck_pi + (size_t)s * N, fb);
@@ -379,6 +393,7 @@ int orc_adjoint(const orc_params *p, int64_t n0, int64_t nsteps, int32_t ckpt_ev
             double a = (1.0 - delta) / (1.0 + delta);
             double b = p->deta / (1.0 + delta);
             double A = orc_force_scale(p, n);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) w[i] = nu[i] + p->deta * mu[i];
 #pragma omp parallel for schedule(static)
             for (int64_t zy = 0; zy < ny * nz; ++zy) {
@@ -397,6 +412,7 @@ int orc_adjoint(const orc_params *p, int64_t n0, int64_t nsteps, int32_t ckpt_ev
             for (int64_t r = 0; r < ny * nz; ++r) g += rowg[r];
             g *= A;
             G -= b * g;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < N; ++i) nu[i] = a * w[i];
         }
     }

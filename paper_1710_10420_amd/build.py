@@ -86,7 +86,30 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    write_isa_counts(objs)
     return LIB
+
+
+ISA_COUNTS = os.path.join(PKG, "isa_counts.json")
+
+
+def write_isa_counts(objs):
+    """Instruction counts of every pass kernel's march loop in this build
+    (isa.py), for the benchmark's issue-rate figure; removed when the tools
+    are missing so that no stale counts survive a rebuild."""
+    import json
+
+    from paper_1710_10420_amd import isa
+    try:
+        counts = isa.counts_for_objects(objs)
+    except (OSError, subprocess.CalledProcessError) as e:
+        print("isa counts not written: %s" % e, file=sys.stderr)
+        if os.path.exists(ISA_COUNTS):
+            os.remove(ISA_COUNTS)
+        return
+    with open(ISA_COUNTS + ".tmp", "w") as f:
+        json.dump(counts, f, indent=0, sort_keys=True)
+    os.replace(ISA_COUNTS + ".tmp", ISA_COUNTS)
 
 
 if __name__ == "__main__":

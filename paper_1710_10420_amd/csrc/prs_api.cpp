@@ -191,6 +191,7 @@ struct prs_ctx {
     void* pi_alt;      // second phi_dot buffer (workspace) for multi-step passes
     Tiling adj_til;    // tiling of the reverse-sweep kernel
     int32_t adj_tblock;   // steps per reverse pass
+    int32_t adj_scheme;   // PRS_ADJ_STORED or PRS_ADJ_FUSED
     Tiling rec_til;    // tiling and steps per pass of the adjoint's recomputation
     int32_t rec_tblock;   // (0: those of the forward)
     int32_t tblock;    // steps per pass (1: single steps)
@@ -207,6 +208,13 @@ struct prs_ctx {
     // the recomputation of the next-older segment overlaps the reverse sweep
     hipStream_t adj_aux;
     hipEvent_t adj_ev[5];   // 0: forward done, 1-2: segment recomputed, 3-4: segment swept
+    // launch timing (prs_set_launch_timing): event pairs bracketing each run
+    // of consecutive launches of the pass kernel, with the launches per run
+    bool lt_on;
+    std::vector<hipEvent_t> lt_ev;
+    std::vector<int64_t> lt_count;
+    double lt_ms;
+    int64_t lt_launches;
 };
 
 namespace {
@@ -330,7 +338,8 @@ prs_status prs_init(const prs_params* p, void* phi_a, void* phi_b, void* dphi, v
         static_cast<char*>(workspace) + align_up((size_t)c->partial_cap * sizeof(WavePartial)));
     c->pi_alt = nullptr;
     c->adj_til = c->til;
-    c->adj_tblock = p->ndim == 2 ? 2 : 1;
+    c->adj_tblock = p->ndim == 2 ? 4 : 1;
+    c->adj_scheme = p->ndim == 2 ? PRS_ADJ_FUSED : PRS_ADJ_STORED;
     c->pi_alt = reinterpret_cast<char*>(c->drec) + align_up((size_t)kRecCap * sizeof(prs_stats));
     c->tblock = p->ndim == 2 ? 2 : 1;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -377,9 +386,34 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
     void* pi_cur = c->pi;
     void* pi_oth = c->pi_alt;
     int64_t pending = 0, written = 0;
+    // launch timing: a run of consecutive pass-kernel launches (T steps, no
+    // diagnostics) is bracketed by one event pair
+    size_t spans = 0;
+    bool open = false;
     for (uint8_t L : plan) {
         const int64_t n = c->step;
         const bool diag = want && (n % K == 0);
+        if (c->lt_on) {
+            const bool dom = !diag && L == T;
+            if (dom && !open) {
+                if (2 * spans + 2 > c->lt_ev.size()) {
+                    for (int j = 0; j < 2; ++j) {
+                        hipEvent_t e;
+                        HIP_TRY(hipEventCreate(&e), "timing event");
+                        c->lt_ev.push_back(e);
+                    }
+                    c->lt_count.push_back(0);
+                }
+                HIP_TRY(hipEventRecord(c->lt_ev[2 * spans], c->stream), "timing event");
+                c->lt_count[spans] = 0;
+                open = true;
+            } else if (!dom && open) {
+                HIP_TRY(hipEventRecord(c->lt_ev[2 * spans + 1], c->stream), "timing event");
+                ++spans;
+                open = false;
+            }
+            if (dom) ++c->lt_count[spans];
+        }
         WavePartial* parts = diag ? c->partials : nullptr;
         const DiagCoef dc = diag_coef(c, n);
         int64_t ntiles = tc.ntiles;
@@ -415,7 +449,51 @@ prs_status prs_step_n(prs_ctx* c, int64_t nsteps, prs_stats* series, int64_t cap
         if (st != PRS_OK) return st;
         written += pending;
     }
+    if (open) {
+        HIP_TRY(hipEventRecord(c->lt_ev[2 * spans + 1], c->stream), "timing event");
+        ++spans;
+    }
+    if (spans > 0) {
+        HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronize");
+        for (size_t i = 0; i < spans; ++i) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, c->lt_ev[2 * i], c->lt_ev[2 * i + 1]), "timing event");
+            c->lt_ms += ms;
+            c->lt_launches += c->lt_count[i];
+        }
+    }
     if (n_written) *n_written = written;
+    return PRS_OK;
+}
+
+prs_status prs_set_launch_timing(prs_ctx* c, int32_t on)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    c->lt_on = on != 0;
+    return PRS_OK;
+}
+
+prs_status prs_get_launch_timing(prs_ctx* c, double* total_ms, int64_t* launches, int32_t reset)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (total_ms) *total_ms = c->lt_ms;
+    if (launches) *launches = c->lt_launches;
+    if (reset) {
+        c->lt_ms = 0.0;
+        c->lt_launches = 0;
+    }
+    return PRS_OK;
+}
+
+prs_status prs_copy(void* dst, const void* src, size_t bytes, void* hip_stream)
+{
+    if (!dst || !src) return fail(PRS_EINVAL, "NULL buffer");
+    if (bytes % 16 != 0 || !aligned16(dst) || !aligned16(src))
+        return fail(PRS_EINVAL, "prs_copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+    const char* d = static_cast<const char*>(dst);
+    const char* r = static_cast<const char*>(src);
+    if (d < r + bytes && r < d + bytes) return fail(PRS_EINVAL, "prs_copy buffers overlap");
+    HIP_TRY(launch_copy16(src, dst, (int64_t)(bytes / 16), static_cast<hipStream_t>(hip_stream)), "copy launch");
     return PRS_OK;
 }
 
@@ -637,6 +715,21 @@ prs_status prs_set_adjoint_time_blocking(prs_ctx* c, int32_t steps_per_pass)
     return PRS_OK;
 }
 
+prs_status prs_set_adjoint_scheme(prs_ctx* c, int32_t scheme)
+{
+    if (!c) return fail(PRS_EINVAL, "ctx is NULL");
+    if (scheme != PRS_ADJ_STORED && scheme != PRS_ADJ_FUSED) return fail(PRS_EINVAL, "unknown adjoint scheme %d", scheme);
+    c->adj_scheme = scheme;
+    return PRS_OK;
+}
+
+prs_status prs_get_adjoint_scheme(prs_ctx* c, int32_t* scheme)
+{
+    if (!c || !scheme) return fail(PRS_EINVAL, "NULL argument");
+    *scheme = c->adj_scheme;
+    return PRS_OK;
+}
+
 prs_status prs_get_adjoint_time_blocking(prs_ctx* c, int32_t* steps_per_pass)
 {
     if (!c || !steps_per_pass) return fail(PRS_EINVAL, "NULL argument");
@@ -671,6 +764,7 @@ void prs_destroy(prs_ctx* c)
         (void)hipStreamDestroy(c->adj_aux);
         for (hipEvent_t e : c->adj_ev) (void)hipEventDestroy(e);
     }
+    for (hipEvent_t e : c->lt_ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -920,6 +1014,15 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     const Tiling rt = c->rec_tblock > 0 ? c->rec_til : c->til;
     const int T = tb_supported(c->geo) ? (c->rec_tblock > 0 ? c->rec_tblock : c->tblock) : 1;
     const int TA = tb_supported(c->geo) ? c->adj_tblock : 1;
+    // The fused scheme (2D): per segment the recomputation keeps only the
+    // states at the starts of the reverse passes (TF steps apart, the last
+    // pass may be shorter), and each reverse pass recomputes its fields from
+    // its pass-start state.  Else every step's field is recomputed and stored.
+    const int TF = std::min(TA, 4);
+    const bool fused = c->adj_scheme == PRS_ADJ_FUSED && c->geo.ndim == 2 && tb_supported(c->geo) && TF >= 2 &&
+                       tbf_supported(c->geo, c->adj_til, TF) &&
+                       tbf_tiles(c->geo, c->adj_til, TF) <= c->partial_cap &&
+                       tb_pass_supported(c->geo, rt, TF);
     double* gacc = at<double>(work, L.gacc);
     HIP_TRY(launch_zero_f64(gacc, c->partial_cap, c->stream), "zero launch");
     char* mu = at<char>(work, L.mu);
@@ -934,11 +1037,35 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     };
     auto seg_len = [&](int64_t sg) { return std::min<int64_t>(L.K, c->adj_nsteps - sg * L.K); };
 
+    // fused scheme: field f of segment sg's buffer (pass-start state q >= 1
+    // holds phi in field 2(q-1) and phi_dot in field 2(q-1)+1)
+    auto seg_field = [&](int64_t sg, int64_t f) {
+        return at<char>(work, ((sg & 1) ? L.seg2 : L.seg) + L.fb * (size_t)f);
+    };
+    auto pass_start = [&](int64_t sg, int64_t q, bool pi) -> char* {
+        if (q == 0) return at<char>(work, (pi ? L.ck_pi : L.ck_phi) + L.fb * sg);
+        return seg_field(sg, 2 * (q - 1) + (pi ? 1 : 0));
+    };
+
     // recompute phi^{ns+1 .. ns+len-1} of segment sg from its checkpoint on
     // stream s: multi-step passes store every step's field; phi_dot goes to
-    // the scratch fields
+    // the scratch fields.  Fused: TF-step forward passes store the states
+    // at the reverse passes' starts instead.
     auto recompute = [&](int64_t sg, hipStream_t s) -> prs_status {
         const int64_t ns = n0 + sg * L.K;
+        if (fused) {
+            const int64_t len = seg_len(sg);
+            const int64_t Q = (len + TF - 1) / TF;
+            for (int64_t q = 0; q + 1 < Q; ++q) {
+                StepCoef64 kk[kMaxPassSteps];
+                for (int i = 0; i < TF; ++i) kk[i] = coef_for(c, ns + q * TF + i);
+                HIP_TRY(launch_tb(TF, c->geo, rt, pass_start(sg, q, false), pass_start(sg, q + 1, false),
+                                  pass_start(sg, q, true), pass_start(sg, q + 1, true), kk, false, nullptr,
+                                  DiagCoef{}, s),
+                        "recompute launch");
+            }
+            return PRS_OK;
+        }
         const int64_t len = seg_len(sg);
         const void* prev = at<char>(work, L.ck_phi + L.fb * sg);
         const void* ckpi = at<char>(work, L.ck_pi + L.fb * sg);
@@ -972,6 +1099,29 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     auto sweep = [&](int64_t sg) -> prs_status {
         const int64_t ns = n0 + sg * L.K;
         const int64_t len = seg_len(sg);
+        if (fused) {
+            const int64_t Q = (len + TF - 1) / TF;
+            for (int64_t q = Q - 1; q >= 0; --q) {
+                const int64_t st = ns + q * TF;                       // the pass's first step
+                const int Lq = (int)std::min<int64_t>(TF, len - q * TF);
+                if (Lq > 1) {
+                    StepCoef64 kk[kMaxPassSteps];
+                    AdjCoef64 cc[kMaxPassSteps];
+                    for (int i = 0; i + 1 < Lq; ++i) kk[i] = coef_for(c, st + i);
+                    for (int k = 1; k <= Lq; ++k) cc[k - 1] = adj_coef(c, st + Lq - k, st + Lq - k == n0);
+                    HIP_TRY(launch_tbf(Lq, c->geo, c->adj_til, pass_start(sg, q, false), pass_start(sg, q, true),
+                                       wcur, wnxt, mu, mu_oth, gacc, kk, cc, c->stream),
+                            "adjoint launch");
+                    std::swap(mu, mu_oth);
+                } else {
+                    HIP_TRY(launch_adjoint(c->geo, c->adj_til, wcur, wnxt, mu, pass_start(sg, q, false), gacc,
+                                           adj_coef(c, st, st == n0), c->stream),
+                            "adjoint launch");
+                }
+                std::swap(wcur, wnxt);
+            }
+            return PRS_OK;
+        }
         char* ckphi = at<char>(work, L.ck_phi + L.fb * sg);
         auto phi_at = [&](int64_t j) -> const void* { return j == 0 ? ckphi : seg_at(sg, j); };   // phi^{ns+j}
         for (int64_t k = len - 1; k >= 0;) {
@@ -1780,9 +1930,19 @@ namespace {
 // there and lose by 15 % inside the backward), and the forward's setting
 // was within 2 % of the best one measured inside the backward at 2048^2 and
 // 256^3.
-prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, double* best_us)
+size_t tune_field_bytes(const prs_ctx* c) { return align_up(field_bytes(c->p)); }
+
+// Least workspace of the adjoint tuner: w and mu twice, one dL/dV0
+// accumulator per wave tile.
+size_t tune_adjoint_min_bytes(const prs_ctx* c)
 {
-    const std::string key = tune_key(c->p, false) + "|adjoint";
+    return 4 * tune_field_bytes(c) + align_up((size_t)c->partial_cap * sizeof(double));
+}
+
+prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, void* work, size_t work_bytes,
+                            double* best_us)
+{
+    const std::string key = tune_key(c->p, false) + (c->adj_scheme == PRS_ADJ_FUSED ? "|adjoint-fused" : "|adjoint");
     auto cache = tune_read(cache_path);
     if (!(flags & PRS_TUNE_FORCE)) {
         const auto it = cache.find(key);
@@ -1794,36 +1954,33 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
         }
     }
     const std::vector<Tiling> cand = tune_candidates(c->geo, false);
+    const size_t need = tune_adjoint_min_bytes(c);
+    if (!work || work_bytes < need)
+        return fail(PRS_ENOMEM, "adjoint tuner workspace: %zu bytes given, at least %zu needed", work_bytes, need);
+    if (((uintptr_t)work % kAlign) != 0) return fail(PRS_EINVAL, "tuner workspace must be 256-byte aligned");
     const size_t bytes = field_bytes(c->p);
-    char* buf = nullptr;
-    double* gacc = nullptr;
-    // Each reverse step reads its own phi^n in the backward; with room, the
-    // tuner gives the steps 32 (else 8) distinct phi fields in rotation, more
-    // than the last-level cache holds at the lattices the adjoint is run on
-    // (one shared field would be served from cache and flatter the
-    // multi-step passes, which read T of them per pass).
-    size_t free_b = 0, total_b = 0;
-    int nphi = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-        for (int n : {32, kMaxPassSteps})
-            if ((4 + (size_t)n) * bytes <= free_b / 2) {
-                nphi = n;
-                break;
-            }
-    }
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), (4 + nphi) * bytes), "tuner allocation");
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&gacc), (size_t)c->partial_cap * sizeof(double));
+    const size_t fb = tune_field_bytes(c);
+    char* buf = static_cast<char*>(work);
+    double* gacc = reinterpret_cast<double*>(buf + 4 * fb);
+    // Each reverse step reads its own phi^n in the backward; the workspace
+    // beyond the least holds up to 32 distinct phi fields that the timed
+    // steps read in rotation, more than the last-level cache holds at the
+    // lattices the adjoint is run on (one shared field would be served from
+    // cache and flatter the multi-step passes, which read T of them per pass).
+    char* phis0 = buf + need;
+    const int nphi = (int)std::min<size_t>(32, (work_bytes - need) / fb);
+    hipError_t e = hipSuccess;
     char* w0 = buf;
-    char* w1 = buf + bytes;
-    char* mu0 = buf + 2 * bytes;
-    char* mu1 = buf + 3 * bytes;
+    char* w1 = buf + fb;
+    char* mu0 = buf + 2 * fb;
+    char* mu1 = buf + 3 * fb;
     auto phi_of = [&](int n) -> const void* {
-        return nphi > 0 ? static_cast<const void*>(buf + (4 + n % nphi) * bytes) : c->phi[c->cur];
+        return nphi > 0 ? static_cast<const void*>(phis0 + (size_t)(n % nphi) * fb) : c->phi[c->cur];
     };
     if (e == hipSuccess) e = hipMemcpyAsync(w0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(mu0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     for (int i = 0; i < nphi && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(buf + (4 + i) * bytes, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
+        e = hipMemcpyAsync(phis0 + (size_t)i * fb, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = launch_zero_f64(gacc, c->partial_cap, c->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
@@ -1835,9 +1992,67 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     Tiling best = c->adj_til;
     int best_T = 1;
     double best_t = 1e300;
+    // Fused scheme (2D): every reverse-pass tiling and length that has a
+    // kernel, each timed together with the forward pass that recomputes its
+    // pass-start state (the recomputation's tiling) -- what one reverse pass
+    // costs inside the backward.
+    const Tiling rt = c->rec_tblock > 0 ? c->rec_til : c->til;
+    const bool fused = c->adj_scheme == PRS_ADJ_FUSED && c->geo.ndim == 2 && tb_supported(c->geo) && nphi >= 4;
+    for (int T : {2, 3, 4}) {
+        if (!fused) break;
+        if (!tb_pass_supported(c->geo, rt, T)) continue;
+        for (const Tiling& t : cand) {
+            if (e != hipSuccess) break;
+            if (!tbf_supported(c->geo, t, T) || tbf_tiles(c->geo, t, T) > c->partial_cap) continue;
+            char* a = w0;
+            char* b = w1;
+            char* ma = mu0;
+            char* mb = mu1;
+            auto run = [&](int steps) -> hipError_t {
+                for (int k = 0; k < steps; k += T) {
+                    StepCoef64 kk[kMaxPassSteps];
+                    AdjCoef64 cc[kMaxPassSteps];
+                    for (int i = 0; i < T; ++i) {
+                        kk[i] = coef_for(c, c->step);
+                        cc[i] = adj_coef(c, c->step, false);
+                    }
+                    // pass-start states and the forward's outputs in rotation
+                    const void* ps = phi_of(k);
+                    const void* pp = phi_of(k + 1);
+                    hipError_t err = launch_tb(T, c->geo, rt, ps, const_cast<void*>(phi_of(k + 2)), pp,
+                                               const_cast<void*>(phi_of(k + 3)), kk, false, nullptr, DiagCoef{},
+                                               c->stream);
+                    if (err == hipSuccess)
+                        err = launch_tbf(T, c->geo, t, ps, pp, a, b, ma, mb, gacc, kk, cc, c->stream);
+                    if (err != hipSuccess) return err;
+                    std::swap(a, b);
+                    std::swap(ma, mb);
+                }
+                return hipSuccess;
+            };
+            e = run(2 * T);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = run(timed);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            const int done = (timed + T - 1) / T * T;
+            const double per_step = ms / done;
+            if (e == hipSuccess && log_each)
+                std::fprintf(stderr, "prs_autotune(adjoint, fused): vec=%d rows=%d steps/pass=%d %.2f us/step\n",
+                             t.vec, t.rows, T, per_step * 1e3);
+            if (e == hipSuccess && per_step < best_t) {
+                best_t = per_step;
+                best = t;
+                best_T = T;
+            }
+        }
+    }
     // single reverse steps for every tiling; multi-step reverse passes for
-    // the tilings and lengths that have kernels
+    // the tilings and lengths that have kernels (stored scheme)
     for (int T : {1, 2, 3, 4, 8}) {
+        if (fused) break;
         for (const Tiling& t : cand) {
             if (e != hipSuccess) break;
             if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
@@ -1891,8 +2106,6 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipFree(buf);
-    (void)hipFree(gacc);
     if (e != hipSuccess) return hip_fail(e, "adjoint autotune");
     c->adj_til = best;
     c->adj_tblock = best_T;
@@ -1908,10 +2121,19 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, d
 
 extern "C" {
 
-prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, double* best_us)
+size_t prs_tune_workspace_bytes(const prs_ctx* c, int32_t flags)
+{
+    if (!c) return 0;
+    if (flags & PRS_TUNE_ADJOINT)
+        return tune_adjoint_min_bytes(c) + ((flags & PRS_TUNE_MIN_WORKSPACE) ? 0 : 32 * tune_field_bytes(c));
+    return 2 * tune_field_bytes(c);
+}
+
+prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, void* work, size_t work_bytes,
+                        double* best_us)
 {
     if (!c) return fail(PRS_EINVAL, "ctx is NULL");
-    if (flags & PRS_TUNE_ADJOINT) return autotune_adjoint(c, cache_path, flags, best_us);
+    if (flags & PRS_TUNE_ADJOINT) return autotune_adjoint(c, cache_path, flags, work, work_bytes, best_us);
     const bool batch_set = (flags & PRS_TUNE_BATCH) != 0;
     const std::string key = tune_key(c->p, batch_set);
     auto cache = tune_read(cache_path);
@@ -1919,7 +2141,8 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
         const auto it = cache.find(key);
         if (it != cache.end()) {
             prs_status st = prs_set_tiling(c, it->second.vec, it->second.rows, it->second.ty);
-            if (st == PRS_OK && !batch_set && it->second.tb > 1) st = prs_set_time_blocking(c, it->second.tb);
+            // the cached steps per pass, also when it is 1 (single steps)
+            if (st == PRS_OK && !batch_set) st = prs_set_time_blocking(c, std::max(1, it->second.tb));
             if (st == PRS_OK) {
                 if (best_us) *best_us = it->second.us;
                 return PRS_OK;
@@ -1929,13 +2152,13 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     const std::vector<Tiling> cand = tune_candidates(c->geo, batch_set);
     if (cand.empty()) return fail(PRS_EUNSUPPORTED, "no tiling candidates");
     const size_t bytes = field_bytes(c->p);
-    void *save_phi = nullptr, *save_pi = nullptr;
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&save_phi), bytes), "tuner allocation");
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&save_pi), bytes);
-    if (e != hipSuccess) {
-        (void)hipFree(save_phi);
-        return hip_fail(e, "tuner allocation");
-    }
+    const size_t need = prs_tune_workspace_bytes(c, flags);
+    if (!work || work_bytes < need)
+        return fail(PRS_ENOMEM, "tuner workspace: %zu bytes given, %zu needed", work_bytes, need);
+    if (((uintptr_t)work % kAlign) != 0) return fail(PRS_EINVAL, "tuner workspace must be 256-byte aligned");
+    void* save_phi = work;
+    void* save_pi = static_cast<char*>(work) + tune_field_bytes(c);
+    hipError_t e = hipSuccess;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -2010,8 +2233,6 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, doubl
     if (e != hipSuccess) result = hip_fail(e, "autotune");
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipFree(save_phi);
-    (void)hipFree(save_pi);
     c->cur = cur0;
     c->step = n0;
     if (result != PRS_OK) return result;

@@ -41,6 +41,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <utility>
 
 #include "prs_internal.h"
 
@@ -1363,6 +1364,334 @@ __global__ __launch_bounds__(kBlock) void k_tba2d(TBAArgs<T, R> A)
     if (lane == 0) A.gacc[tile] += gsum;
 }
 
+// ---------------- reverse sweep recomputing its fields, T steps per pass (2D) --
+//
+// The reverse pass of k_tba2d without the stored fields: it reads the state
+// (phi^s, phi_dot^{s-1/2}) the forward held at the pass's first step s and
+// recomputes phi^{s+1} .. phi^{s+T-1} itself, as forward levels 1 .. T-1 of
+// the forward passes' pipeline (kick_drift, the same arithmetic, so the same
+// bits), while reverse levels 1 .. T run the steps s+T-1 .. s on them (the
+// arithmetic of k_adjoint).  Nothing but the pass-start state and (w, mu)
+// crosses memory: 24 B per site per pass in float32 instead of the 16 + 4T B
+// of k_tba2d plus the 8 + 4T B of storing every step's field.
+//
+// Rows march up.  With y the newest level-0 row of iteration i (y = y0 + i),
+// forward level j computes row y - j, reverse level 1 row y - T + 1 and
+// reverse level k row y - T - k + 2 from reverse level k-1 and forward level
+// T-k, whose row was computed 2k - 2 iterations earlier and waits in that
+// level's register ring (2T - 2j - 1 rows deep for level j).  The final
+// level writes row y - 2T + 2; a tile of n output rows runs n + 4T - 4
+// iterations, starting with y0 = s0 - 2T + 2.  Lanes: the forward levels
+// shrink the valid lanes by T - 1 sites per side and the reverse levels by T
+// more, so a wave owns its middle 64 VEC - 2 (2T - 1) sites... rounded to
+// whole lanes: H = ceil((2T - 1)/VEC) halo lanes per side.
+//
+// dL/dV0 is summed per level and lane in the field precision over one group
+// of iterations and then added to a double per level; the gradient fields
+// do not depend on it.
+
+// Rows a ring holds: level 0 of phi keeps 2T rows (the oldest read 2T - 2
+// iterations after it was loaded, one prefetched), forward level j
+// max(3, 2T - 2j - 1) (its successor reads three rows, reverse level T-j the
+// row of 2T - 2j - 2 iterations ago), the top level one.  Powers of two, so
+// that the unrolled iterations address them with compile-time slots.
+__host__ __device__ constexpr int tbf_pow2(int v) { return v <= 1 ? 1 : v <= 2 ? 2 : v <= 4 ? 4 : v <= 8 ? 8 : 16; }
+__host__ __device__ constexpr int tbf_ring0(int T) { return tbf_pow2(2 * T); }
+__host__ __device__ constexpr int tbf_ring(int T, int j)
+{
+    return j == T - 1 ? 1 : tbf_pow2(2 * T - 2 * j - 1 > 3 ? 2 * T - 2 * j - 1 : 3);
+}
+__host__ __device__ constexpr int tbf_halo(int vec, int T) { return (2 * T - 1 + vec - 1) / vec; }
+
+template <int T, typename R = float>
+struct TBFArgs {
+    const R* phi_s;             // phi^s (the pass-start field)
+    const R* pi_s;              // phi_dot^{s-1/2}
+    const R* w_in;
+    R* w_out;
+    const R* mu_in;
+    R* mu_out;
+    double* gacc;               // one accumulator per wave tile
+    int64_t nx, ny;
+    int64_t tiles_x, ntiles;
+    int64_t rows;
+    StepCoefT<R> k[T];          // forward level j runs step s + j - 1 with k[j-1] (j = 1 .. T-1)
+    R a[T], b[T], cw[T], F[T];  // reverse level k runs step s + T - k
+    R kc, inv_dx2;
+    double gscale[T];
+};
+
+template <int VEC, int T, typename R>
+struct TBFState {
+    R f0[tbf_ring0(T)][VEC];    // level 0 phi rows
+    R p0[2][VEC];               // level 0 phi_dot rows
+    R fl[T][8][VEC];            // forward level j phi rows (ring tbf_ring(T, j))
+    R pl[T][2][VEC];            // forward level j phi_dot rows (j = 1 .. T-2)
+    R wi[4][VEC];               // w_in rows
+    R mi[2][VEC];               // mu_in rows
+    R rw[T][4][VEC];            // reverse level k w rows (k = 1 .. T-1)
+    R rm[T][2][VEC];            // reverse level k mu rows
+};
+
+struct TBFRows {
+    int32_t phi, pi, w, mu;     // next rows to fetch, wrapped into [0, ny)
+};
+
+// One site of a reverse level: adj_site's update of (w, mu), with the
+// dL/dV0 term's phi (kc phi^2 - 1) returned for the caller to accumulate.
+template <bool UNIT, typename R>
+__device__ __forceinline__ R adj_site_pq(R w, R s, R mu, R phi, R a, R b, R cw, R F, R kc, R inv_dx2, R& w_new,
+                                         R& mu_new)
+{
+    const R pk = UNIT ? phi : phi * kc;
+    const R q = fmar(pk, phi, R(-1));
+    const R c1 = fmar(R(2), F, UNIT ? R(4) : R(4) * inv_dx2);
+    const R t = fmar(R(3) * F, q, c1);
+    const R x = fmar(-w, t, UNIT ? s : s * inv_dx2);
+    mu_new = fmar(b, x, mu);
+    w_new = fmar(cw, mu_new, a * w);
+    return phi * q;
+}
+
+// The 2D neighbour sum of element j of a row whose x-neighbours across the
+// lane boundary are `left` and `right`; the shifted value comes first in
+// each pair so that the DPP shift folds into the add (same bits: each pair
+// is one commutative addition).
+template <int VEC, typename R>
+__device__ __forceinline__ R row_nsum(const R* cc, R left, R right, int j, R ym, R yp)
+{
+    const R xm = j > 0 ? cc[j > 0 ? j - 1 : 0] : left;
+    const R xp = j < VEC - 1 ? cc[j < VEC - 1 ? j + 1 : j] : right;
+    const R xs = j == VEC - 1 ? (xp + xm) : (xm + xp);
+    return xs + (ym + yp);
+}
+
+template <int VEC, int T, bool UNIT, bool CHECK, int U, typename R>
+__device__ __forceinline__ void tbf_iter(const TBFArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
+                                         int32_t n_out, TBFRows& rw, TBFState<VEC, T, R>& S, R (&g32)[T])
+{
+    constexpr int R0 = tbf_ring0(T);
+    // prefetch for the next iteration: phi^s row y+1, phi_dot row y, w_in row
+    // y-T+3, mu_in row y-T+2 (none after the last iteration: size 0)
+    const uint32_t nb = i < last ? L.row_bytes : 0u;
+    tb_load<VEC>(A.phi_s, rw.phi, L, nb, S.f0[(U + 1) & (R0 - 1)]);
+    tb_load<VEC>(A.pi_s, rw.pi, L, nb, S.p0[U & 1]);
+    tb_load<VEC>(A.w_in, rw.w, L, nb, S.wi[U & 3]);
+    tb_load<VEC>(A.mu_in, rw.mu, L, nb, S.mi[U & 1]);
+    rw.phi = next_row(rw.phi, L.ny);
+    rw.pi = next_row(rw.pi, L.ny);
+    rw.w = next_row(rw.w, L.ny);
+    rw.mu = next_row(rw.mu, L.ny);
+
+    // forward levels j = 1 .. T-1: row y - j
+#pragma unroll
+    for (int j = 1; j < T; ++j) {
+        if (CHECK && i < 2 * j) continue;
+        const R* cm;
+        const R* cc;
+        const R* cp;
+        const R* pp;
+        if (j == 1) {
+            cm = S.f0[(U + R0 - 2) & (R0 - 1)];
+            cc = S.f0[(U + R0 - 1) & (R0 - 1)];
+            cp = S.f0[U & (R0 - 1)];
+            pp = S.p0[(U + 1) & 1];
+        } else {
+            constexpr int RP = 8;
+            const int rp = tbf_ring(T, j > 1 ? j - 1 : 1) - 1;
+            cm = S.fl[j - 1][(U + RP - 2) & rp];
+            cc = S.fl[j - 1][(U + RP - 1) & rp];
+            cp = S.fl[j - 1][U & rp];
+            pp = S.pl[j - 1][(U + 1) & 1];
+        }
+        const R left = from_left_lane(cc[VEC - 1]);
+        const R right = from_right_lane(cc[0]);
+        const int rj = tbf_ring(T, j) - 1;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            R pn, fn;
+            kick_drift<2, UNIT>(cc[e], row_nsum<VEC>(cc, left, right, e, cm[e], cp[e]), pp[e], A.k[j - 1], pn, fn);
+            S.fl[j][U & rj][e] = fn;
+            if (j < T - 1) S.pl[j][U & 1][e] = pn;
+        }
+    }
+
+    // reverse levels k = 1 .. T: row y - T - k + 2
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        if (CHECK && i < 2 * T + 2 * k - 4) continue;
+        const R* cm;
+        const R* cc;
+        const R* cp;
+        const R* mp;
+        if (k == 1) {
+            cm = S.wi[(U + 1) & 3];
+            cc = S.wi[(U + 2) & 3];
+            cp = S.wi[(U + 3) & 3];
+            mp = S.mi[(U + 1) & 1];
+        } else {
+            cm = S.rw[k - 1][(U + 2) & 3];
+            cc = S.rw[k - 1][(U + 3) & 3];
+            cp = S.rw[k - 1][U & 3];
+            mp = S.rm[k - 1][(U + 1) & 1];
+        }
+        // forward level T-k's row of 2k - 2 iterations ago
+        const R* ph;
+        if (k == T) {
+            ph = S.f0[(U + R0 - (2 * T - 2)) & (R0 - 1)];
+        } else {
+            constexpr int RP = 8;
+            ph = S.fl[T - k][(U + RP - (2 * k - 2)) & (tbf_ring(T, T - k) - 1)];
+        }
+        const R left = from_left_lane(cc[VEC - 1]);
+        const R right = from_right_lane(cc[0]);
+        // row y - T - k + 2 is output row e of the tile when inside [0, n_out)
+        const int32_t e_row = i - (3 * T + k - 4);
+        const bool own_row = e_row >= 0 && e_row < n_out;
+        R out_w[VEC], out_mu[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const R pq = adj_site_pq<UNIT>(cc[e], row_nsum<VEC>(cc, left, right, e, cm[e], cp[e]), mp[e], ph[e],
+                                           A.a[k - 1], A.b[k - 1], A.cw[k - 1], A.F[k - 1], A.kc, A.inv_dx2,
+                                           out_w[e], out_mu[e]);
+            if (own_row) g32[k - 1] = fmar(cc[e], pq, g32[k - 1]);
+        }
+        if (k < T) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                S.rw[k < T ? k : 0][U & 3][e] = out_w[e];
+                S.rm[k < T ? k : 0][U & 1][e] = out_mu[e];
+            }
+        } else {
+            const int32_t er = i - (4 * T - 4);
+            const uint32_t sb = (!CHECK || er >= 0) ? L.row_bytes : 0u;
+            const int32_t row = L.s0 + (er >= 0 ? er : 0);
+            tb_store<VEC>(A.w_out, row, L, sb, out_w);
+            tb_store<VEC>(A.mu_out, row, L, sb, out_mu);
+        }
+    }
+}
+
+// Iterations i .. i+U-1 (U the level-0 ring length, so ring slots are
+// compile-time); false once the last iteration has run.  The group's
+// dL/dV0 partials are then added to the per-level doubles of owned lanes.
+template <int VEC, int T, bool UNIT, bool CHECK, typename R, int... Us>
+__device__ __forceinline__ bool tbf_group_u(const TBFArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
+                                            int32_t n_out, TBFRows& rw, TBFState<VEC, T, R>& S, R (&g32)[T],
+                                            std::integer_sequence<int, Us...>)
+{
+    bool more = true;
+    ((more = more && (i + Us <= last) ? (tbf_iter<VEC, T, UNIT, CHECK, Us>(A, L, i + Us, last, n_out, rw, S, g32),
+                                         true)
+                                      : false),
+     ...);
+    return more && i + (int)sizeof...(Us) <= last;
+}
+
+template <int VEC, int T, bool UNIT, typename R>
+__global__ __launch_bounds__(kBlock) void k_tbf2d(TBFArgs<T, R> A)
+{
+    constexpr int H = tbf_halo(VEC, T);
+    constexpr int W = (kWave - 2 * H) * VEC;
+    constexpr int R0 = tbf_ring0(T);
+    constexpr int WARM = (4 * T - 4 + R0 - 1) / R0;
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t tx = tl % (uint32_t)A.tiles_x;
+    const uint32_t ts = tl / (uint32_t)A.tiles_x;
+    TBLane L;
+    L.nx = (uint32_t)A.nx;
+    L.ny = (int32_t)A.ny;
+    L.row_bytes = L.nx * (uint32_t)sizeof(R);
+    const int32_t x0 = (int32_t)(tx * (uint32_t)W) + (lane - H) * VEC;
+    L.voff = (uint32_t)wrap_row(x0, (int32_t)L.nx) * (uint32_t)sizeof(R);
+    L.soff = (lane >= H && lane < kWave - H && x0 < (int32_t)L.nx) ? L.voff : kPastRow;
+    const int32_t rows = (int32_t)A.rows;
+    L.s0 = (int32_t)ts * rows;
+    L.s1 = L.s0 + rows < L.ny ? L.s0 + rows : L.ny;
+    L.dir = 1;
+    L.yoff = 0;
+    L.wrap_at = L.ny;
+    L.wrap_to = 0;
+    const int32_t n_out = L.s1 - L.s0;
+
+    TBFState<VEC, T, R> S;
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+#pragma unroll
+        for (int a = 0; a < R0; ++a) S.f0[a][j] = R(0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) S.p0[a][j] = S.mi[a][j] = R(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) S.wi[a][j] = R(0);
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a) S.fl[k][a][j] = R(0);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) S.rw[k][a][j] = R(0);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) S.pl[k][a][j] = S.rm[k][a][j] = R(0);
+        }
+    }
+
+    // before iteration 0 (y = y0): phi^s rows y0-2 .. y0, phi_dot row y0-1,
+    // w_in rows y0-T .. y0-T+2, mu_in row y0-T+1
+    const int32_t y0 = L.s0 - 2 * T + 2;
+    tb_load<VEC>(A.phi_s, wrap_row(y0 - 2, L.ny), L, L.row_bytes, S.f0[R0 - 2]);
+    tb_load<VEC>(A.phi_s, wrap_row(y0 - 1, L.ny), L, L.row_bytes, S.f0[R0 - 1]);
+    tb_load<VEC>(A.phi_s, wrap_row(y0, L.ny), L, L.row_bytes, S.f0[0]);
+    tb_load<VEC>(A.pi_s, wrap_row(y0 - 1, L.ny), L, L.row_bytes, S.p0[1]);
+    tb_load<VEC>(A.w_in, wrap_row(y0 - T, L.ny), L, L.row_bytes, S.wi[1]);
+    tb_load<VEC>(A.w_in, wrap_row(y0 - T + 1, L.ny), L, L.row_bytes, S.wi[2]);
+    tb_load<VEC>(A.w_in, wrap_row(y0 - T + 2, L.ny), L, L.row_bytes, S.wi[3]);
+    tb_load<VEC>(A.mu_in, wrap_row(y0 - T + 1, L.ny), L, L.row_bytes, S.mi[1]);
+    TBFRows rw;
+    rw.phi = wrap_row(y0 + 1, L.ny);
+    rw.pi = wrap_row(y0, L.ny);
+    rw.w = wrap_row(y0 - T + 3, L.ny);
+    rw.mu = wrap_row(y0 - T + 2, L.ny);
+
+    R g32[T];
+    double gs[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        g32[k] = R(0);
+        gs[k] = 0.0;
+    }
+    const bool own_lane = L.soff != kPastRow;
+    auto flush = [&]() {
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            gs[k] += own_lane ? (double)g32[k] : 0.0;
+            g32[k] = R(0);
+        }
+    };
+
+    const int32_t last = n_out + 4 * T - 5;
+    int32_t i = 0;
+    bool more = true;
+#pragma unroll
+    for (int w = 0; w < WARM; ++w) {
+        if (more) more = tbf_group_u<VEC, T, UNIT, true>(A, L, i, last, n_out, rw, S, g32,
+                                                         std::make_integer_sequence<int, R0>{});
+        i += R0;
+    }
+    flush();
+    while (more) {
+        more = tbf_group_u<VEC, T, UNIT, false>(A, L, i, last, n_out, rw, S, g32,
+                                                std::make_integer_sequence<int, R0>{});
+        i += R0;
+        flush();
+    }
+    double gsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) gsum += A.gscale[k] * wave_sum_f64(gs[k]);
+    if (lane == 0) A.gacc[tile] += gsum;
+}
+
 // ----------------------------------------- T steps per HBM pass (3D) --------
 //
 // The 2D scheme with a second in-plane axis.  A wave marches along z; for
@@ -2241,6 +2570,75 @@ hipError_t launch_tba_t(const Geometry& g, const Tiling& t, const void* w_in, vo
     else
         hipLaunchKernelGGL((k_tba2d<VEC, T, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
     return hipGetLastError();
+}
+
+// The 2D reverse pass recomputing its fields (k_tbf2d): T = 2, 3, 4, vec 1
+// or 2 in float32, vec 1 in float64 (the register rings of eight-byte
+// values at two sites per lane would not fit).
+template <typename R>
+constexpr bool tbf_combo_ok(int vec, int T)
+{
+    return (vec == 1 || (sizeof(R) == 4 && vec == 2)) && (T == 2 || T == 3 || T == 4);
+}
+
+template <typename R, int VEC, int T>
+hipError_t launch_tbf_t(const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s, const void* w_in,
+                        void* w_out, const void* mu_in, void* mu_out, double* gacc, const StepCoef64* k,
+                        const AdjCoef64* c, hipStream_t s)
+{
+    TBFArgs<T, R> A;
+    A.phi_s = static_cast<const R*>(phi_s);
+    A.pi_s = static_cast<const R*>(pi_s);
+    A.w_in = static_cast<const R*>(w_in);
+    A.w_out = static_cast<R*>(w_out);
+    A.mu_in = static_cast<const R*>(mu_in);
+    A.mu_out = static_cast<R*>(mu_out);
+    for (int i = 0; i < T; ++i) {
+        A.k[i] = coef_as<R>(k[i < T - 1 ? i : 0]);
+        A.a[i] = (R)c[i].a;
+        A.b[i] = (R)c[i].b;
+        A.cw[i] = (R)c[i].cw;
+        A.F[i] = (R)c[i].F;
+        A.gscale[i] = c[i].gscale;
+    }
+    A.kc = (R)c[0].kc;
+    A.inv_dx2 = (R)c[0].inv_dx2;
+    A.gacc = gacc;
+    A.nx = g.nx;
+    A.ny = g.M;
+    const int64_t W = (int64_t)(kWave - 2 * tbf_halo(VEC, T)) * VEC;
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.ntiles = A.tiles_x * ((g.M + t.rows - 1) / t.rows);
+    A.rows = t.rows;
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    // the unit specialisation needs unit spacing and vacuum in both the
+    // forward and the reverse coefficients (they come from the same run)
+    if (A.inv_dx2 == R(1) && A.kc == R(1) && A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1))
+        hipLaunchKernelGGL((k_tbf2d<VEC, T, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tbf2d<VEC, T, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tbf_r(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
+                        const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
+                        const StepCoef64* k, const AdjCoef64* c, hipStream_t s)
+{
+    if (g.ndim != 2 || t.ty != 1 || !tbf_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
+#define PRS_TBF(V, TT)                                                                                  \
+    if (t.vec == V && T == TT) {                                                                         \
+        if constexpr (tbf_combo_ok<R>(V, TT))                                                            \
+            return launch_tbf_t<R, V, TT>(g, t, phi_s, pi_s, w_in, w_out, mu_in, mu_out, gacc, k, c, s);   \
+    }
+    PRS_TBF(1, 2)
+    PRS_TBF(1, 3)
+    PRS_TBF(1, 4)
+    PRS_TBF(2, 2)
+    PRS_TBF(2, 3)
+    PRS_TBF(2, 4)
+#undef PRS_TBF
+    return hipErrorInvalidValue;
 }
 
 template <typename R>

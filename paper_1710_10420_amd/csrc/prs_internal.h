@@ -156,10 +156,31 @@ hipError_t launch_tba_f64(int T, const Geometry& g, const Tiling& t, const void*
                           const void* mu_in, void* mu_out, const void* const* phi, double* gacc,
                           const AdjCoef64* c, hipStream_t s);
 
+// Reverse passes that recompute their fields (2D): T reverse steps m .. s =
+// m-T+1 from the pass-start state (phi_s = phi^s, pi_s = phi_dot^{s-1/2}),
+// recomputing phi^{s+1} .. phi^{s+T-1} in registers with the forward
+// coefficients k[0 .. T-2] (steps s .. s+T-2); c[k-1] and the adjoint
+// buffers as for launch_tba.  tbf_supported: 2D, ty 1, T = 2, 3, 4, vec 1 or
+// 2 (float64: vec 1).  tbf_tiles: wave tiles (and dL/dV0 accumulators) of
+// such a pass.
+bool tbf_supported(const Geometry& g, const Tiling& t, int T);
+int64_t tbf_tiles(const Geometry& g, const Tiling& t, int T);
+hipError_t launch_tbf(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
+                      const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
+                      const StepCoef64* k, const AdjCoef64* c, hipStream_t s);
+hipError_t launch_tbf_f32(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
+                          const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
+                          const StepCoef64* k, const AdjCoef64* c, hipStream_t s);
+hipError_t launch_tbf_f64(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
+                          const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
+                          const StepCoef64* k, const AdjCoef64* c, hipStream_t s);
+
 // mu = dL/dphi^S, w = deta*mu from the final field; FP64 loss partial per block.
 hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, double kc, double deta, void* mu,
                            void* w, double* partial, int nblocks, hipStream_t s);
 hipError_t launch_sum_f64(const double* v, int64_t count, double* out, hipStream_t s);
+// Device copy of n16 16-byte words (16-byte aligned buffers).
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s);
 
 // Per-precision instantiations behind the dispatchers above (one kernel file

@@ -64,6 +64,26 @@ __global__ __launch_bounds__(kWave) void k_finalize(const WavePartial* __restric
     finalize_wave(parts, count, rec, step, eta, area_scale);
 }
 
+// Plain device copy of n16 16-byte words (the reference ceiling that pass
+// bandwidths are compared with): each 256-lane workgroup moves 16 KiB, four
+// independent 16-byte loads per lane in flight before its stores.
+__global__ __launch_bounds__(kBlock) void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                   int64_t n16)
+{
+    const int64_t base = (int64_t)blockIdx.x * (4 * kBlock) + threadIdx.x;
+    uint4 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = base + (int64_t)j * kBlock;
+        if (i < n16) v[j] = src[i];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = base + (int64_t)j * kBlock;
+        if (i < n16) dst[i] = v[j];
+    }
+}
+
 // Sum of `count` doubles in a fixed order into *out.
 __global__ __launch_bounds__(kBlock) void k_sum_f64(const double* __restrict__ v, int64_t count,
                                                      double* __restrict__ out)
@@ -424,6 +444,13 @@ hipError_t launch_tba_f32(int T, const Geometry& g, const Tiling& t, const void*
     return launch_tba_r<float>(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
 }
 
+hipError_t launch_tbf_f32(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
+                          const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
+                          const StepCoef64* k, const AdjCoef64* c, hipStream_t s)
+{
+    return launch_tbf_r<float>(T, g, t, phi_s, pi_s, w_in, w_out, mu_in, mu_out, gacc, k, c, s);
+}
+
 hipError_t launch_fill_f32(void* phi, int64_t count, uint64_t seed, hipStream_t s)
 {
     return launch_fill_r<float>(phi, count, seed, s);
@@ -507,6 +534,27 @@ hipError_t launch_tba(int T, const Geometry& g, const Tiling& t, const void* w_i
                  : launch_tba_f32(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
 }
 
+bool tbf_supported(const Geometry& g, const Tiling& t, int T)
+{
+    if (g.ndim != 2 || !tb_supported(g) || !tiling_supported(g, t) || t.ty != 1) return false;
+    return g.f64 ? tbf_combo_ok<double>(t.vec, T) : tbf_combo_ok<float>(t.vec, T);
+}
+
+int64_t tbf_tiles(const Geometry& g, const Tiling& t, int T)
+{
+    const int64_t W = (int64_t)(kWave - 2 * tbf_halo(t.vec, T)) * t.vec;
+    return ((g.nx + W - 1) / W) * ((g.M + t.rows - 1) / t.rows);
+}
+
+hipError_t launch_tbf(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
+                      const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
+                      const StepCoef64* k, const AdjCoef64* c, hipStream_t s)
+{
+    if (!tbf_supported(g, t, T)) return hipErrorInvalidValue;
+    return g.f64 ? launch_tbf_f64(T, g, t, phi_s, pi_s, w_in, w_out, mu_in, mu_out, gacc, k, c, s)
+                 : launch_tbf_f32(T, g, t, phi_s, pi_s, w_in, w_out, mu_in, mu_out, gacc, k, c, s);
+}
+
 hipError_t launch_fill_uniform(void* phi, int64_t count, uint64_t seed, bool f64, hipStream_t s)
 {
     return f64 ? launch_fill_f64(phi, count, seed, s) : launch_fill_f32(phi, count, seed, s);
@@ -517,6 +565,16 @@ hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWave), 0, s, partials, count, rec, step, eta,
                        area_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s)
+{
+    if (n16 <= 0) return hipSuccess;
+    const int64_t blocks = (n16 + 4 * kBlock - 1) / (4 * kBlock);
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(kBlock), 0, s, static_cast<const uint4*>(src),
+                       static_cast<uint4*>(dst), n16);
     return hipGetLastError();
 }
 

@@ -57,6 +57,13 @@ hipError_t launch_tba_f64(int T, const Geometry& g, const Tiling& t, const void*
     return launch_tba_r<double>(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
 }
 
+hipError_t launch_tbf_f64(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
+                          const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
+                          const StepCoef64* k, const AdjCoef64* c, hipStream_t s)
+{
+    return launch_tbf_r<double>(T, g, t, phi_s, pi_s, w_in, w_out, mu_in, mu_out, gacc, k, c, s);
+}
+
 hipError_t launch_fill_f64(void* phi, int64_t count, uint64_t seed, hipStream_t s)
 {
     return launch_fill_r<double>(phi, count, seed, s);

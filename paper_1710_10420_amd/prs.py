@@ -140,7 +140,13 @@ _decl("prs_batch_set_time_blocking", _i32, _vp, _i32, _i32)
 _decl("prs_batch_state", _i32, _vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp))
 _decl("prs_batch_run", _i32, _vp, _S, _i64)
 _decl("prs_batch_destroy", None, _vp)
-_decl("prs_autotune", _i32, _vp, ctypes.c_char_p, _i32, ctypes.POINTER(_d))
+_decl("prs_autotune", _i32, _vp, ctypes.c_char_p, _i32, _vp, _sz, ctypes.POINTER(_d))
+_decl("prs_tune_workspace_bytes", _sz, _vp, _i32)
+_decl("prs_set_launch_timing", _i32, _vp, _i32)
+_decl("prs_get_launch_timing", _i32, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i64), _i32)
+_decl("prs_copy", _i32, _vp, _vp, _sz, _vp)
+_decl("prs_set_adjoint_scheme", _i32, _vp, _i32)
+_decl("prs_get_adjoint_scheme", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_tuned_tiling", _i32, _P, ctypes.c_char_p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
       ctypes.POINTER(_i32))
 _decl("prs_set_time_blocking", _i32, _vp, _i32)
@@ -171,12 +177,17 @@ EXPORTED = [
     "prs_get_adjoint_tiling", "prs_plan_passes", "prs_fill_uniform_f64",
     "prs_set_adjoint_time_blocking", "prs_get_adjoint_time_blocking",
     "prs_set_recompute_tiling", "prs_get_recompute_tiling", "prs_slab_pass",
-    "prs_slab_pass_stats", "prs_slab_scratch_bytes",
+    "prs_slab_pass_stats", "prs_slab_scratch_bytes", "prs_tune_workspace_bytes",
+    "prs_set_launch_timing", "prs_get_launch_timing", "prs_copy", "prs_set_adjoint_scheme",
+    "prs_get_adjoint_scheme",
 ]
 
 PRS_TUNE_FORCE = 1
 PRS_TUNE_BATCH = 2
 PRS_TUNE_ADJOINT = 4
+PRS_TUNE_MIN_WORKSPACE = 8
+PRS_ADJ_STORED = 0
+PRS_ADJ_FUSED = 1
 
 
 class PRSError(RuntimeError):
@@ -445,12 +456,56 @@ def prs_batch_destroy(b):
     _lib.prs_batch_destroy(b)
 
 
-def prs_autotune(ctx, cache_path=None, flags=0):
-    """Returns the time of one step (us) with the chosen tiling."""
+def prs_tune_workspace_bytes(ctx, flags=0):
+    return int(_lib.prs_tune_workspace_bytes(ctx, flags))
+
+
+def prs_autotune(ctx, cache_path=None, flags=0, work=None):
+    """Returns the time of one step (us) with the chosen tiling.  `work` is
+    a device tensor of scratch (the tuner allocates nothing); by default one
+    of prs_tune_workspace_bytes(ctx, flags) bytes is allocated here, or, for
+    the adjoint tuner when that does not fit, of the least size it takes."""
     us = _d()
     path = cache_path.encode() if cache_path else None
-    _check(_lib.prs_autotune(ctx, path, flags, ctypes.byref(us)), "prs_autotune")
+    if work is None:
+        try:
+            work = torch.empty(prs_tune_workspace_bytes(ctx, flags), dtype=torch.uint8, device="cuda")
+        except torch.OutOfMemoryError:
+            if not flags & PRS_TUNE_ADJOINT:
+                raise
+            torch.cuda.empty_cache()
+            work = torch.empty(prs_tune_workspace_bytes(ctx, flags | PRS_TUNE_MIN_WORKSPACE),
+                               dtype=torch.uint8, device="cuda")
+    _check(_lib.prs_autotune(ctx, path, flags, work.data_ptr(), work.numel() * work.element_size(),
+                             ctypes.byref(us)), "prs_autotune")
+    del work
     return us.value
+
+
+def prs_set_launch_timing(ctx, on):
+    _check(_lib.prs_set_launch_timing(ctx, 1 if on else 0), "prs_set_launch_timing")
+
+
+def prs_get_launch_timing(ctx, reset=True):
+    """(total milliseconds, launches) of the pass kernel since the last reset."""
+    ms, n = _d(), _i64()
+    _check(_lib.prs_get_launch_timing(ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0),
+           "prs_get_launch_timing")
+    return ms.value, n.value
+
+
+def prs_set_adjoint_scheme(ctx, scheme):
+    _check(_lib.prs_set_adjoint_scheme(ctx, scheme), "prs_set_adjoint_scheme")
+
+
+def prs_get_adjoint_scheme(ctx):
+    v = _i32()
+    _check(_lib.prs_get_adjoint_scheme(ctx, ctypes.byref(v)), "prs_get_adjoint_scheme")
+    return v.value
+
+
+def prs_copy(dst, src, nbytes, stream):
+    _check(_lib.prs_copy(dst, src, nbytes, stream), "prs_copy")
 
 
 def prs_tuned_tiling(p, cache_path, flags=0):

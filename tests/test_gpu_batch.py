@@ -93,6 +93,35 @@ def test_batch_records_match_oracle_on_final_state(singles):
     b.close()
 
 
+def test_batch_fields_match_oracle(singles):
+    """Every member's evolved field, run inside the ensemble, against the
+    oracle's run of the same realisation (its seed, size, era, width and
+    step count): relative L-inf <= 1e-5, and the records the ensemble wrote
+    along the way against the oracle's records of its own trajectory (counts
+    bit for bit while the float32 and float64 trajectories still give the
+    same signs, which at these lengths they do)."""
+    say("batch fields vs oracle")
+    prs = gpu_prs()
+    from tests.gpu_util import rel_linf
+    b = make_batch(prs)
+    recs = b.run()
+    for r, sp in enumerate(SPECS):
+        phi, dphi = b.final_state(r)
+        op = O.params(sp["shape"], deta=sp["deta"], m=sp["m"], W0=sp["W0"])
+        phi0 = uniform_field(sp["shape"], sp["seed"]).astype(np.float64).reshape(-1)
+        ophi, opi, orecs = O.run(op, phi0, np.zeros_like(phi0), sp["nsteps"], diag_every=sp["diag_every"])
+        if sp["nsteps"] > 0:
+            assert rel_linf(host(phi), ophi) <= 1e-5, sp
+            assert rel_linf(host(dphi), opi) <= 1e-5, sp
+        else:
+            np.testing.assert_array_equal(host(phi).astype(np.float64), ophi)
+        assert len(recs[r]) == len(orecs) + 1, sp
+        for g, o in zip(recs[r], orecs):
+            assert g["links_dir"] == o["links_dir"] and g["wall_sites"] == o["wall_sites"], (sp, g["step"])
+            assert g["area_density"] == pytest.approx(o["area_density"], rel=1e-5)
+    b.close()
+
+
 def test_batch_initial_fields_from_seeds():
     prs = gpu_prs()
     sp = dict(shape=(100, 60), deta=0.25, m=1.0, W0=10.0, nsteps=0, diag_every=1, seed=77)

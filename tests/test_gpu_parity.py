@@ -104,6 +104,48 @@ def test_c1_full_run_scaling_exponent():
         assert abs(gnu - onu) <= 0.05, (seed, gnu, onu)
 
 
+def c2_golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle_records.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("tuned", [True, False])
+def test_c2_full_run_scaling_exponent(tuned):
+    """The 2D matter-era run at full size and length (8192^2, W0 = 10, m = 2,
+    deta = 0.25, eta 1 -> 4096, seed 1, records every 64 steps and of the
+    final state) against the FP64 oracle's run of the same input, stored in
+    tests/golden/c2_oracle_records.json by tests/golden/make_c2_records.py:
+    the wall-area exponent fitted over the last decade within 0.02; the
+    record of n = 0 (both sides on the same seeded field) with counts bit for
+    bit and FP64 sums to summation order; with the benchmark's tuned launch
+    configuration and with the library default."""
+    gold = c2_golden()
+    run = gold["run"]
+    prs = gpu_prs()
+    shape = tuple(run["shape"])
+    gp = prs.make_params(shape, deta=run["deta"], m=run["m"], W0=run["W0"], alpha=run["alpha"],
+                         diag_every=run["diag_every"])
+    sim = prs.Sim(gp, seed=run["seed"])
+    if tuned:
+        prs.prs_autotune(sim.ctx, None, 0)
+    say("c2 full run", sim.tiling(), sim.time_blocking())
+    recs = sim.step_n(gold["steps"])
+    recs.append(sim.wall_stats())
+    orecs = gold["records"]
+    assert len(recs) == len(orecs) == 257
+    assert [r["step"] for r in recs] == [r["step"] for r in orecs]
+    assert_stats_match(recs[0], orecs[0], ctx="c2 n=0")
+    mu, nu = prs.prs_fit_scaling(recs, gold["fit_eta_min"])
+    say("  mu %.5f (oracle %.5f), nu %.5f (oracle %.5f)" % (mu, gold["mu"], nu, gold["nu"]))
+    assert abs(mu - gold["mu"]) <= 0.02
+    assert abs(nu - gold["nu"]) <= 0.05
+    sim.close()
+
+
 # ---------------------------------------------------- ragged / degenerate --
 
 SHAPES = [
@@ -343,8 +385,9 @@ def test_2d_lattice_past_2_32_sites(tiling, T):
 @pytest.mark.parametrize("tiling,T", [((2, 64, 2), 3), (None, None)])
 def test_full_size_3d_1024_sampled(tiling, T):
     """1024^3 radiation era in the fastest three-step configuration and the
-    library default: sampled patches after 10 steps and the full-lattice
-    diagnostics on the same field."""
+    library default: sampled patches after 50 steps (one diagnostic interval)
+    and the full-lattice diagnostics on the same field; the record of n = 0
+    against the oracle on the seeded initial field."""
     say("1024^3 full size", tiling, T)
     torch = torch_mod()
     prs = gpu_prs()
@@ -355,22 +398,26 @@ def test_full_size_3d_1024_sampled(tiling, T):
         sim.set_tiling(*tiling)
         sim.set_time_blocking(T)
     say("  tiling", sim.tiling(), "steps/pass", sim.time_blocking())
-    sim.step_n(10)
+    recs = sim.step_n(50)
+    assert len(recs) == 1 and recs[0]["step"] == 0
     phi, dphi = sim.state()
     rng = np.random.default_rng(6)
     centers = [(0, 0, 0), (1023, 1023, 1023), (511, 0, 1023)] + [
         tuple(int(v) for v in rng.integers(0, 1024, 3)) for _ in range(3)]
     pflat = phi.reshape(-1)
     for c in centers:
-        idx, ref = oracle_patch(op, shape, 1, c, 10, 3)
+        idx, ref = oracle_patch(op, shape, 1, c, 50, 3)
         got = host(pflat[torch.from_numpy(idx).cuda()])
         assert rel_linf(got, ref) <= 1e-5, c
     st = sim.wall_stats()
     g = host(phi).astype(np.float64)
     gd = host(dphi).astype(np.float64)
-    o = O.stats(op, g, gd, 10)
-    assert_stats_match(st, o, ctx="1024^3 n=10")
-    del g, gd, sim
+    o = O.stats(op, g, gd, 50)
+    assert_stats_match(st, o, ctx="1024^3 n=50")
+    del g, gd
+    phi0 = uniform_field(shape, 1).reshape(-1).astype(np.float64)
+    assert_stats_match(recs[0], O.stats(op, phi0, np.zeros_like(phi0), 0), ctx="1024^3 n=0")
+    del phi0, sim
     torch.cuda.empty_cache()
 
 
