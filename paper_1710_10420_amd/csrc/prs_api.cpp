@@ -1056,13 +1056,26 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
         if (fused) {
             const int64_t len = seg_len(sg);
             const int64_t Q = (len + TF - 1) / TF;
-            for (int64_t q = 0; q + 1 < Q; ++q) {
+            // forward passes of 2 TF steps that also store their middle
+            // state give two pass starts each; a last single one TF steps
+            const bool mid = tb_mid_supported(c->geo, rt, 2 * TF);
+            for (int64_t q = 0; q + 1 < Q;) {
                 StepCoef64 kk[kMaxPassSteps];
-                for (int i = 0; i < TF; ++i) kk[i] = coef_for(c, ns + q * TF + i);
-                HIP_TRY(launch_tb(TF, c->geo, rt, pass_start(sg, q, false), pass_start(sg, q + 1, false),
-                                  pass_start(sg, q, true), pass_start(sg, q + 1, true), kk, false, nullptr,
-                                  DiagCoef{}, s),
-                        "recompute launch");
+                if (mid && q + 2 < Q) {
+                    for (int i = 0; i < 2 * TF; ++i) kk[i] = coef_for(c, ns + q * TF + i);
+                    HIP_TRY(launch_tb_mid(2 * TF, c->geo, rt, pass_start(sg, q, false), pass_start(sg, q + 2, false),
+                                          pass_start(sg, q, true), pass_start(sg, q + 2, true),
+                                          pass_start(sg, q + 1, false), pass_start(sg, q + 1, true), kk, s),
+                            "recompute launch");
+                    q += 2;
+                } else {
+                    for (int i = 0; i < TF; ++i) kk[i] = coef_for(c, ns + q * TF + i);
+                    HIP_TRY(launch_tb(TF, c->geo, rt, pass_start(sg, q, false), pass_start(sg, q + 1, false),
+                                      pass_start(sg, q, true), pass_start(sg, q + 1, true), kk, false, nullptr,
+                                      DiagCoef{}, s),
+                            "recompute launch");
+                    q += 1;
+                }
             }
             return PRS_OK;
         }
@@ -1997,7 +2010,7 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
     // pass-start state (the recomputation's tiling) -- what one reverse pass
     // costs inside the backward.
     const Tiling rt = c->rec_tblock > 0 ? c->rec_til : c->til;
-    const bool fused = c->adj_scheme == PRS_ADJ_FUSED && c->geo.ndim == 2 && tb_supported(c->geo) && nphi >= 4;
+    const bool fused = c->adj_scheme == PRS_ADJ_FUSED && c->geo.ndim == 2 && tb_supported(c->geo) && nphi >= 6;
     for (int T : {2, 3, 4}) {
         if (!fused) break;
         if (!tb_pass_supported(c->geo, rt, T)) continue;
@@ -2009,19 +2022,25 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
             char* ma = mu0;
             char* mb = mu1;
             auto run = [&](int steps) -> hipError_t {
+                const bool mid = tb_mid_supported(c->geo, rt, 2 * T);
                 for (int k = 0; k < steps; k += T) {
                     StepCoef64 kk[kMaxPassSteps];
                     AdjCoef64 cc[kMaxPassSteps];
-                    for (int i = 0; i < T; ++i) {
-                        kk[i] = coef_for(c, c->step);
-                        cc[i] = adj_coef(c, c->step, false);
-                    }
-                    // pass-start states and the forward's outputs in rotation
+                    for (int i = 0; i < 2 * T && i < kMaxPassSteps; ++i) kk[i] = coef_for(c, c->step);
+                    for (int i = 0; i < T; ++i) cc[i] = adj_coef(c, c->step, false);
+                    // pass-start states and the forward's outputs in rotation;
+                    // one forward pass of 2T steps per two reverse passes
+                    // where it has a kernel, as in the backward
                     const void* ps = phi_of(k);
                     const void* pp = phi_of(k + 1);
-                    hipError_t err = launch_tb(T, c->geo, rt, ps, const_cast<void*>(phi_of(k + 2)), pp,
-                                               const_cast<void*>(phi_of(k + 3)), kk, false, nullptr, DiagCoef{},
-                                               c->stream);
+                    hipError_t err = hipSuccess;
+                    if (!mid)
+                        err = launch_tb(T, c->geo, rt, ps, const_cast<void*>(phi_of(k + 2)), pp,
+                                        const_cast<void*>(phi_of(k + 3)), kk, false, nullptr, DiagCoef{}, c->stream);
+                    else if ((k / T) % 2 == 0)
+                        err = launch_tb_mid(2 * T, c->geo, rt, ps, const_cast<void*>(phi_of(k + 2)), pp,
+                                            const_cast<void*>(phi_of(k + 3)), const_cast<void*>(phi_of(k + 4)),
+                                            const_cast<void*>(phi_of(k + 5)), kk, c->stream);
                     if (err == hipSuccess)
                         err = launch_tbf(T, c->geo, t, ps, pp, a, b, ma, mb, gacc, kk, cc, c->stream);
                     if (err != hipSuccess) return err;

@@ -778,7 +778,9 @@ struct TBArgs {
     R* phi_out;
     const R* pi_in;
     R* pi_out;
-    R* phi_lv[T];               // with ALL: phi^{n+k} of levels k = 1 .. T-1 (level T is phi_out)
+    R* phi_lv[T];               // with ALL: phi^{n+k} of levels k = 1 .. T-1 (level T is phi_out);
+                                // with MID: phi_lv[0] receives phi^{n+MID}
+    R* pi_mid;                  // with MID: phi_dot^{n+MID-1/2}
     WavePartial* partials;
     int64_t nx, ny;
     int64_t tiles_x, ntiles;
@@ -938,7 +940,7 @@ __device__ __forceinline__ void tb_store(R* f, int32_t row, const TBLane& L, uin
 // iteration is i = last for every level.  CHECK skips the levels that have no
 // row yet (the first 2T-2 iterations); without it those levels run on rows
 // that only ever feed rows outside the tile, which are never stored.
-template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, int U, bool ALL, typename R>
+template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, int U, bool ALL, typename R, int MID = 0>
 __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
                                         TBRows& rw, TBState<VEC, T, R>& S, DiagAcc& acc)
 {
@@ -999,6 +1001,16 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
                 const int32_t row = (L.dir > 0 ? L.s0 + e : L.s1 - 1 - e) + L.yoff;
                 tb_store<VEC>(A.phi_lv[k < T ? k - 1 : 0], in ? row : L.s0, L, in ? L.row_bytes : 0u, out_phi);
             }
+            if constexpr (MID > 0) {
+                if (k == MID) {
+                    // the state after MID steps, (phi, phi_dot) of the same row
+                    const int32_t e = i - (T + k - 2);
+                    const bool in = e >= 0 && e < L.s1 - L.s0;
+                    const int32_t row = (L.dir > 0 ? L.s0 + e : L.s1 - 1 - e) + L.yoff;
+                    tb_store<VEC>(A.phi_lv[0], in ? row : L.s0, L, in ? L.row_bytes : 0u, out_phi);
+                    tb_store<VEC>(A.pi_mid, in ? row : L.s0, L, in ? L.row_bytes : 0u, out_pi);
+                }
+            }
         } else {
             // level T: march row e = i - (2T - 2) of the tile, inside it once i >= 2T - 2
             const int32_t e = i - (2 * T - 2);
@@ -1012,24 +1024,24 @@ __device__ __forceinline__ void tb_iter(const TBArgs<T, R>& A, const TBLane& L, 
 
 // Iterations i .. i+3 (i a multiple of 4, so ring slots are compile-time);
 // false once the last iteration has run.
-template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, bool ALL, typename R>
+template <int VEC, int T, bool DIAG, bool UNIT, bool CHECK, bool ALL, typename R, int MID = 0>
 __device__ __forceinline__ bool tb_group(const TBArgs<T, R>& A, const TBLane& L, int32_t i, int32_t last,
                                          TBRows& rw, TBState<VEC, T, R>& S, DiagAcc& acc)
 {
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 0, ALL>(A, L, i, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 0, ALL, R, MID>(A, L, i, last, rw, S, acc);
     if (i + 1 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 1, ALL>(A, L, i + 1, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 1, ALL, R, MID>(A, L, i + 1, last, rw, S, acc);
     if (i + 2 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 2, ALL>(A, L, i + 2, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 2, ALL, R, MID>(A, L, i + 2, last, rw, S, acc);
     if (i + 3 > last) return false;
-    tb_iter<VEC, T, DIAG, UNIT, CHECK, 3, ALL>(A, L, i + 3, last, rw, S, acc);
+    tb_iter<VEC, T, DIAG, UNIT, CHECK, 3, ALL, R, MID>(A, L, i + 3, last, rw, S, acc);
     return i + 4 <= last;
 }
 
 // One wave's tile of a T-step pass; `tile` must be below A.ntiles and
 // wave-uniform.  ALL also stores the fields of the intermediate steps
 // (phi_lv), as the recomputation of the adjoint needs them.
-template <int VEC, int T, bool DIAG, bool UNIT = false, bool ALL = false, typename R = float>
+template <int VEC, int T, bool DIAG, bool UNIT = false, bool ALL = false, typename R = float, int MID = 0>
 __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
 {
     constexpr int H = (T + VEC - 1) / VEC;        // halo lanes per side
@@ -1107,11 +1119,11 @@ __device__ __forceinline__ void tb_tile(const TBArgs<T, R>& A, int64_t tile)
     bool more = true;
 #pragma unroll
     for (int w = 0; w < WARM; ++w) {
-        if (more) more = tb_group<VEC, T, DIAG, UNIT, true, ALL>(A, L, i, last, rw, S, acc);
+        if (more) more = tb_group<VEC, T, DIAG, UNIT, true, ALL, R, MID>(A, L, i, last, rw, S, acc);
         i += 4;
     }
     while (more) {
-        more = tb_group<VEC, T, DIAG, UNIT, false, ALL>(A, L, i, last, rw, S, acc);
+        more = tb_group<VEC, T, DIAG, UNIT, false, ALL, R, MID>(A, L, i, last, rw, S, acc);
         i += 4;
     }
 
@@ -1144,6 +1156,17 @@ __attribute__((amdgpu_waves_per_eu(tb2d_min_waves(VEC, T, (int)sizeof(R))))) voi
     const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
     if (tile >= A.ntiles) return;
     tb_tile<VEC, T, DIAG, UNIT>(A, tile);
+}
+
+// The T-step pass also storing the state after T/2 steps (the pass starts
+// of the fused adjoint's reverse passes, two per forward pass).
+template <int VEC, int T, bool UNIT, typename R>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(tb2d_min_waves(VEC, T, (int)sizeof(R))))) void k_tb2d_mid(TBArgs<T, R> A)
+{
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
+    if (tile >= A.ntiles) return;
+    tb_tile<VEC, T, false, UNIT, false, R, T / 2>(A, tile);
 }
 
 // The T-step pass storing every step's field (adjoint recomputation).
@@ -2570,6 +2593,68 @@ hipError_t launch_tba_t(const Geometry& g, const Tiling& t, const void* w_in, vo
     else
         hipLaunchKernelGGL((k_tba2d<VEC, T, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
     return hipGetLastError();
+}
+
+// 2D T-step passes that also store the state after T/2 steps: T = 4, 6, 8
+// where the forward pass has a kernel.
+template <typename R, int VEC, int T>
+hipError_t launch_tb_mid_t(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi_in,
+                           void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k, hipStream_t s)
+{
+    TBArgs<T, R> A;
+    A.yhalo = 0;
+    A.phi_in = static_cast<const R*>(phi_in);
+    A.phi_out = static_cast<R*>(phi_out);
+    A.pi_in = static_cast<const R*>(pi_in);
+    A.pi_out = static_cast<R*>(pi_out);
+    for (int i = 0; i < T; ++i) A.phi_lv[i] = static_cast<R*>(phi_mid);
+    A.pi_mid = static_cast<R*>(pi_mid);
+    A.partials = nullptr;
+    A.nx = g.nx;
+    A.ny = g.M;
+    const int64_t W = tb_owned_width_d(VEC, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.ntiles = A.tiles_x * ((g.M + t.rows - 1) / t.rows);
+    A.rows = t.rows;
+    for (int i = 0; i < T; ++i) A.k[i] = coef_as<R>(k[i]);
+    A.dc = DiagCoef{};
+    const int64_t blocks = (A.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1))
+        hipLaunchKernelGGL((k_tb2d_mid<VEC, T, true, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_tb2d_mid<VEC, T, false, R>), dim3((unsigned)blocks), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename R>
+constexpr bool tbmid_combo_ok(int vec, int T)
+{
+    return (T == 4 || T == 6 || T == 8) && (vec == 1 || vec == 2 || (sizeof(R) == 4 && vec == 4)) &&
+           (T == 4 || sizeof(R) == 4 || vec == 1);
+}
+
+template <typename R>
+hipError_t launch_tb_mid_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                           const void* pi_in, void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k,
+                           hipStream_t s)
+{
+    if (g.ndim != 2 || t.ty != 1 || !tbmid_combo_ok<R>(t.vec, T)) return hipErrorInvalidValue;
+#define PRS_TBMID(V, TT)                                                                                         \
+    if (t.vec == V && T == TT) {                                                                                  \
+        if constexpr (tbmid_combo_ok<R>(V, TT))                                                                   \
+            return launch_tb_mid_t<R, V, TT>(g, t, phi_in, phi_out, pi_in, pi_out, phi_mid, pi_mid, k, s);      \
+    }
+    PRS_TBMID(1, 4)
+    PRS_TBMID(1, 6)
+    PRS_TBMID(1, 8)
+    PRS_TBMID(2, 4)
+    PRS_TBMID(2, 6)
+    PRS_TBMID(2, 8)
+    PRS_TBMID(4, 4)
+    PRS_TBMID(4, 6)
+    PRS_TBMID(4, 8)
+#undef PRS_TBMID
+    return hipErrorInvalidValue;
 }
 
 // The 2D reverse pass recomputing its fields (k_tbf2d): T = 2, 3, 4, vec 1

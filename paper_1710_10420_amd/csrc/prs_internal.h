@@ -163,6 +163,18 @@ hipError_t launch_tba_f64(int T, const Geometry& g, const Tiling& t, const void*
 // buffers as for launch_tba.  tbf_supported: 2D, ty 1, T = 2, 3, 4, vec 1 or
 // 2 (float64: vec 1).  tbf_tiles: wave tiles (and dL/dV0 accumulators) of
 // such a pass.
+// 2D T-step forward pass (T = 4, 6, 8) that also stores the state after T/2
+// steps to (phi_mid, pi_mid).
+bool tb_mid_supported(const Geometry& g, const Tiling& t, int T);
+hipError_t launch_tb_mid(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                         const void* pi_in, void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k,
+                         hipStream_t s);
+hipError_t launch_tb_mid_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                             const void* pi_in, void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k,
+                             hipStream_t s);
+hipError_t launch_tb_mid_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                             const void* pi_in, void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k,
+                             hipStream_t s);
 bool tbf_supported(const Geometry& g, const Tiling& t, int T);
 int64_t tbf_tiles(const Geometry& g, const Tiling& t, int T);
 hipError_t launch_tbf(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,

@@ -444,6 +444,13 @@ hipError_t launch_tba_f32(int T, const Geometry& g, const Tiling& t, const void*
     return launch_tba_r<float>(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
 }
 
+hipError_t launch_tb_mid_f32(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                             const void* pi_in, void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k,
+                             hipStream_t s)
+{
+    return launch_tb_mid_r<float>(T, g, t, phi_in, phi_out, pi_in, pi_out, phi_mid, pi_mid, k, s);
+}
+
 hipError_t launch_tbf_f32(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
                           const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
                           const StepCoef64* k, const AdjCoef64* c, hipStream_t s)
@@ -532,6 +539,21 @@ hipError_t launch_tba(int T, const Geometry& g, const Tiling& t, const void* w_i
     if (!tba_supported(g, t, T)) return hipErrorInvalidValue;
     return g.f64 ? launch_tba_f64(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s)
                  : launch_tba_f32(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
+}
+
+bool tb_mid_supported(const Geometry& g, const Tiling& t, int T)
+{
+    if (g.ndim != 2 || !tb_supported(g) || !tiling_supported(g, t) || t.ty != 1) return false;
+    return g.f64 ? tbmid_combo_ok<double>(t.vec, T) : tbmid_combo_ok<float>(t.vec, T);
+}
+
+hipError_t launch_tb_mid(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                         const void* pi_in, void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k,
+                         hipStream_t s)
+{
+    if (!tb_mid_supported(g, t, T)) return hipErrorInvalidValue;
+    return g.f64 ? launch_tb_mid_f64(T, g, t, phi_in, phi_out, pi_in, pi_out, phi_mid, pi_mid, k, s)
+                 : launch_tb_mid_f32(T, g, t, phi_in, phi_out, pi_in, pi_out, phi_mid, pi_mid, k, s);
 }
 
 bool tbf_supported(const Geometry& g, const Tiling& t, int T)

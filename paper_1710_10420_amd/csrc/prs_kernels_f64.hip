@@ -57,6 +57,13 @@ hipError_t launch_tba_f64(int T, const Geometry& g, const Tiling& t, const void*
     return launch_tba_r<double>(T, g, t, w_in, w_out, mu_in, mu_out, phi, gacc, c, s);
 }
 
+hipError_t launch_tb_mid_f64(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                             const void* pi_in, void* pi_out, void* phi_mid, void* pi_mid, const StepCoef64* k,
+                             hipStream_t s)
+{
+    return launch_tb_mid_r<double>(T, g, t, phi_in, phi_out, pi_in, pi_out, phi_mid, pi_mid, k, s);
+}
+
 hipError_t launch_tbf_f64(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
                           const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
                           const StepCoef64* k, const AdjCoef64* c, hipStream_t s)
