@@ -327,6 +327,24 @@ prs_status prs_slab_pass_stats(const prs_params* p, int64_t n0, int32_t steps, i
  * tiling; 0 when the parameters are invalid or no such pass kernel exists. */
 size_t prs_slab_scratch_bytes(const prs_params* p, int32_t steps, int32_t vec, int32_t rows, int32_t ty);
 
+/* prs_slab_pass_stats for callers that cannot allocate memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same pass and the same record, but the scratch is a statically allocated
+ * device array of 4 MiB that the library holds on every device it runs on
+ * until the process ends, and the record is written to the device pointer
+ * record_dev (one prs_stats, 16-byte aligned) without synchronising
+ * hip_stream.  Nothing is allocated and no host copy is made.
+ *   Limits: prs_slab_scratch_bytes(p, steps, vec, rows, ty) must not
+ *   exceed 4 MiB (about 104,000 wave tiles); a larger pass returns
+ *   PRS_ENOMEM before any launch.  Other errors as prs_slab_pass_stats.
+ *   Sharing: every call on one device uses that device's one array, so
+ *   calls that overlap on one device (other streams, other threads) race and
+ *   may return wrong records; calls in sequence are safe (each pass writes
+ *   every scratch value it reads). */
+prs_status prs_slab_pass_stats_static(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows,
+                                      int32_t ty, const void* phi_in, void* phi_out, const void* pi_in,
+                                      void* pi_out, prs_stats* record_dev, void* hip_stream);
+
 /* Destroy a context (does not free caller-owned buffers).  NULL is a no-op. */
 void prs_destroy(prs_ctx* ctx);
 

@@ -602,9 +602,14 @@ namespace {
 // (the wave partials follow it).
 constexpr size_t kSlabRecBytes = 256;
 
+// One slab pass; with a record, the diagnostics of its input state: the
+// partials go to `scratch`, and the record to the host pointer `record`
+// (read back, synchronising the stream) or, with record_on_device, to the
+// device pointer `record` (no synchronisation; the record slot of scratch is
+// then unused).
 prs_status slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows, int32_t ty,
                      const void* phi_in, void* phi_out, const void* pi_in, void* pi_out, void* scratch,
-                     size_t scratch_bytes, prs_stats* record, void* hip_stream)
+                     size_t scratch_bytes, prs_stats* record, void* hip_stream, bool record_on_device = false)
 {
     prs_status st = validate(p);
     if (st != PRS_OK) return st;
@@ -643,8 +648,10 @@ prs_status slab_pass(const prs_params* p, int64_t n0, int32_t steps, int32_t vec
                            diag ? diag_coef(&tmp, n0) : DiagCoef{}, s),
             "slab pass launch");
     if (!diag) return PRS_OK;
-    HIP_TRY(launch_finalize(parts, ntiles, drec, n0, p->eta0 + (double)n0 * p->deta, area_scale(*p), s),
+    HIP_TRY(launch_finalize(parts, ntiles, record_on_device ? record : drec, n0, p->eta0 + (double)n0 * p->deta,
+                            area_scale(*p), s),
             "finalize launch");
+    if (record_on_device) return PRS_OK;
     HIP_TRY(hipMemcpyAsync(record, drec, sizeof(prs_stats), hipMemcpyDeviceToHost, s), "record copy");
     HIP_TRY(hipStreamSynchronize(s), "record sync");
     return PRS_OK;
@@ -676,6 +683,34 @@ prs_status prs_slab_pass_stats(const prs_params* p, int64_t n0, int32_t steps, i
     if (!record) return fail(PRS_EINVAL, "record is NULL");
     return slab_pass(p, n0, steps, vec, rows, ty, phi_in, phi_out, pi_in, pi_out, scratch, scratch_bytes, record,
                      hip_stream);
+}
+
+prs_status prs_slab_pass_stats_static(const prs_params* p, int64_t n0, int32_t steps, int32_t vec, int32_t rows,
+                                      int32_t ty, const void* phi_in, void* phi_out, const void* pi_in,
+                                      void* pi_out, prs_stats* record_dev, void* hip_stream)
+{
+    if (!record_dev || !aligned16(record_dev)) return fail(PRS_EINVAL, "record_dev must be a 16-byte aligned device pointer");
+    // the scratch of the stream's device, made current for the look-up
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipDevice_t dev = 0;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur), "device query");
+    HIP_TRY(hipStreamGetDevice(s, &dev), "stream device query");
+    if ((int)dev != cur) HIP_TRY(hipSetDevice((int)dev), "set device");
+    void* scratch = nullptr;
+    size_t bytes = 0;
+    hipError_t e = static_scratch(&scratch, &bytes);
+    if ((int)dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    const size_t need = prs_slab_scratch_bytes(p, steps, vec, rows, ty);
+    if (need == 0) return slab_pass(p, n0, steps, vec, rows, ty, phi_in, phi_out, pi_in, pi_out, nullptr, 0,
+                                    record_dev, hip_stream, true);   // reports the invalid argument
+    if (need > bytes)
+        return fail(PRS_ENOMEM, "the pass has %lld wave tiles; the static scratch holds %lld (%zu bytes, %zu needed)",
+                    (long long)((need - kSlabRecBytes) / sizeof(WavePartial)),
+                    (long long)((bytes - kSlabRecBytes) / sizeof(WavePartial)), bytes, need);
+    return slab_pass(p, n0, steps, vec, rows, ty, phi_in, phi_out, pi_in, pi_out, scratch, bytes, record_dev,
+                     hip_stream, true);
 }
 
 prs_status prs_set_recompute_tiling(prs_ctx* c, int32_t vec, int32_t rows, int32_t ty, int32_t steps_per_pass)

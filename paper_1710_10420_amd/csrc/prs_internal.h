@@ -191,6 +191,12 @@ hipError_t launch_tbf_f64(int T, const Geometry& g, const Tiling& t, const void*
 hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, double kc, double deta, void* mu,
                            void* w, double* partial, int nblocks, hipStream_t s);
 hipError_t launch_sum_f64(const double* v, int64_t count, double* out, hipStream_t s);
+// Statically allocated device scratch (4 MiB per device, resident for the
+// life of the process): its device address on the current device and size.
+// Every user on one device shares it.
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+hipError_t static_scratch(void** ptr, size_t* bytes);
+
 // Device copy of n16 16-byte words (16-byte aligned buffers).
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s);

@@ -2,6 +2,8 @@
 // templates are in prs_device.h), the record reduction, the batched-ensemble
 // kernels and the host-side dispatch by precision.
 
+#include <mutex>
+
 #include "prs_device.h"
 
 namespace prs {
@@ -63,6 +65,13 @@ __global__ __launch_bounds__(kWave) void k_finalize(const WavePartial* __restric
 {
     finalize_wave(parts, count, rec, step, eta, area_scale);
 }
+
+// Scratch of the allocation-free slab-diagnostics entry point: one record
+// slot and the wave partials of one pass, resident on every device the
+// library runs on.  Host code never passes this name to a kernel (in host
+// code it is only a stand-in for the symbol); static_scratch() hands out the
+// device address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 // Plain device copy of n16 16-byte words (the reference ceiling that pass
 // bandwidths are compared with): each 256-lane workgroup moves 16 KiB, four
@@ -588,6 +597,29 @@ hipError_t launch_finalize(const WavePartial* partials, int64_t count, prs_stats
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWave), 0, s, partials, count, rec, step, eta,
                        area_scale);
     return hipGetLastError();
+}
+
+hipError_t static_scratch(void** ptr, size_t* bytes)
+{
+    // the device address of `scratch` on each device, looked up once per
+    // device with that device current (each device holds its own copy)
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(lock);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kStaticScratchBytes;
+    return hipSuccess;
 }
 
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s)

@@ -146,6 +146,7 @@ _decl("prs_set_launch_timing", _i32, _vp, _i32)
 _decl("prs_get_launch_timing", _i32, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i64), _i32)
 _decl("prs_copy", _i32, _vp, _vp, _sz, _vp)
 _decl("prs_set_adjoint_scheme", _i32, _vp, _i32)
+_decl("prs_slab_pass_stats_static", _i32, _P, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp)
 _decl("prs_get_adjoint_scheme", _i32, _vp, ctypes.POINTER(_i32))
 _decl("prs_tuned_tiling", _i32, _P, ctypes.c_char_p, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
       ctypes.POINTER(_i32))
@@ -179,7 +180,7 @@ EXPORTED = [
     "prs_set_recompute_tiling", "prs_get_recompute_tiling", "prs_slab_pass",
     "prs_slab_pass_stats", "prs_slab_scratch_bytes", "prs_tune_workspace_bytes",
     "prs_set_launch_timing", "prs_get_launch_timing", "prs_copy", "prs_set_adjoint_scheme",
-    "prs_get_adjoint_scheme",
+    "prs_get_adjoint_scheme", "prs_slab_pass_stats_static",
 ]
 
 PRS_TUNE_FORCE = 1
@@ -346,6 +347,22 @@ def prs_slab_pass_stats(p, n0, steps, tiling, phi_in, phi_out, pi_in, pi_out, sc
     _check(_lib.prs_slab_pass_stats(ctypes.byref(p), n0, steps, tiling[0], tiling[1], tiling[2], phi_in, phi_out,
                                     pi_in, pi_out, scratch, scratch_bytes, ctypes.byref(rec), stream),
            "prs_slab_pass_stats")
+    return rec.as_dict()
+
+
+def prs_slab_pass_stats_static(p, n0, steps, tiling, phi_in, phi_out, pi_in, pi_out, record_dev, stream):
+    """prs_slab_pass_stats without any allocation: the library's static
+    scratch, the record written to the device pointer record_dev (one
+    prs_stats, no synchronisation)."""
+    _check(_lib.prs_slab_pass_stats_static(ctypes.byref(p), n0, steps, tiling[0], tiling[1], tiling[2], phi_in,
+                                           phi_out, pi_in, pi_out, record_dev, stream),
+           "prs_slab_pass_stats_static")
+
+
+def prs_stats_from_bytes(raw):
+    """A prs_stats record (as a dict) from its bytes, e.g. a device record
+    copied to the host."""
+    rec = prs_stats.from_buffer_copy(bytes(raw))
     return rec.as_dict()
 
 
