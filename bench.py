@@ -178,21 +178,32 @@ def pass_valu_lane_ops(shape, tiling, T, counts):
         own_rows = 1
         c = counts.get("k_tb2d<%d,%d,0,1,f>" % (vec, T))
         tiles_q = 1
+    elif ty in (8, 16, 32, 64):
+        # LDS-staged pass: workgroups of NW waves with R rows each, of which
+        # the middle NW R - 2T rows are stored; every wave computes its R rows
+        NW = 16 if ty >= 32 else 8
+        R = ty // 16 if ty >= 32 else ty // 4
+        own_rows = R
+        c = counts.get("k_tb3l<%d,%d,%d,%d,0,1,0,f>" % (vec, T, R, NW))
+        tiles_q = -(-shape[1] // (NW * R - 2 * T)) * NW
     else:
         own_rows = 8 if ty == 4 else 4             # rows along y a wave owns
         c = counts.get("k_tb3d<%d,%d,%d,0,1,f>" % (vec, T, own_rows))
         tiles_q = -(-shape[1] // own_rows)
     if not c or c["vmem_store"] < 2 * own_rows:
         return None, None
-    iters_in_loop = c["vmem_store"] / (2.0 * own_rows)   # level T stores phi and phi_dot of the owned rows
+    iters_in_loop = c["vmem_store"] / (2.0 * own_rows)   # level T stores phi and phi_dot of the wave's rows
     per_iter = c["valu"] / iters_in_loop
     level_iters = 0
     for s0 in range(0, M, rows):
         n = min(rows, M - s0) + 2 * T - 2
         level_iters += sum(n - 2 * (k - 1) for k in range(1, T + 1))
     lane_ops = per_iter / T * level_iters * tiles_x * tiles_q * 64
+    stored_rows = own_rows
+    if len(shape) == 3 and ty in (8, 16, 32, 64):
+        stored_rows = (NW * R - 2 * T) / float(NW)
     return lane_ops, {"valu_per_iteration": per_iter,
-                      "valu_per_owned_site_update": per_iter / (vec * own_rows * T),
+                      "valu_per_owned_site_update": per_iter / (vec * stored_rows * T),
                       "loop_instructions": c}
 
 

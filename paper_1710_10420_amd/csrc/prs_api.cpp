@@ -126,7 +126,11 @@ int64_t partial_capacity(const Geometry& g)
     Tiling t{1, (int)kMinRows, 1};
     int64_t n = tile_counts(g, t).ntiles;
     if (g.ndim == 2) n = std::max<int64_t>(n, tb_tiles(g, t, kMaxPassSteps));
-    else n = std::max<int64_t>(n, tb_tiles(g, t, 3));   // 3D: 4 owned rows, T <= 3
+    else {
+        n = std::max<int64_t>(n, tb_tiles(g, t, 3));    // 3D: 4 owned rows, T <= 3
+        // the LDS pass: one partial per wave, 2 rows per wave, T <= 4
+        n = std::max<int64_t>(n, tb_tiles(g, Tiling{1, (int)kMinRows, 8}, 4));
+    }
     return n;
 }
 
@@ -504,7 +508,7 @@ prs_status prs_set_time_blocking(prs_ctx* c, int32_t steps_per_pass)
         return fail(PRS_EINVAL, "steps per pass must be 1 .. %d", kMaxPassSteps);
     if (steps_per_pass > 1 && tb_supported(c->geo) && !tb_steps_supported(c->geo, steps_per_pass))
         return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, 6, 8; "
-                    "3D: 2, and 3 in float32)", steps_per_pass);
+                    "3D: 2, 3, 4)", steps_per_pass);
     c->tblock = steps_per_pass;
     return PRS_OK;
 }
@@ -1741,7 +1745,7 @@ prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps
                     "shorter than 2^31 bytes");
     if (steps_per_pass > 1 && !tb_steps_supported(b->geo[item], steps_per_pass))
         return fail(PRS_EINVAL, "no %d-step pass kernel for this lattice (2D: 2, 3, 4, 6, 8; "
-                    "3D: 2, and 3 in float32)", steps_per_pass);
+                    "3D: 2, 3, 4)", steps_per_pass);
     if (item_tiles_max(b->geo[item], b->til[item], std::max(2, steps_per_pass)) > b->part_cap[item])
         return fail(PRS_EINVAL, "steps per pass need more wave tiles than the workspace holds");
     b->tblock[item] = steps_per_pass;
@@ -1939,7 +1943,7 @@ std::vector<Tiling> tune_candidates(const Geometry& g, bool batch_set)
     std::vector<Tiling> out;
     for (int vec : {1, 2, 4})
         for (int rows : {8, 16, 32, 64, 128})
-            for (int ty : {1, 2, 4}) {
+            for (int ty : {1, 2, 4, 8, 16, 32, 64}) {
                 Tiling t{vec, rows, ty};
                 if (rows < kMinRows && rows < g.M) continue;
                 if (!tiling_supported(g, t)) continue;

@@ -65,6 +65,13 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
+// 3D tilings with ty 8, 16, 32 or 64 select the LDS-staged multi-step pass
+// (eight waves of 2 or 4 rows for ty 8, 16; sixteen waves of 2 or 4 rows for
+// ty 32, 64); their single steps and reverse steps run the kernels of ty 4.
+__host__ __device__ __forceinline__ bool tb3l_tiling(int ty) { return ty == 8 || ty == 16 || ty == 32 || ty == 64; }
+
+__host__ __device__ __forceinline__ int step_ty(int ty) { return ty > 4 ? 4 : ty; }
+
 // Index of this wave within its workgroup, as a wave-uniform (scalar) value:
 // the compiler cannot prove threadIdx.x / 64 uniform on its own, and every
 // address derived from it would otherwise be computed per lane.
@@ -1996,6 +2003,315 @@ __global__ __launch_bounds__(kBlock) void k_tb3d_all(TB3Args<T, R> A)
     tb3_tile<VEC, T, TY, false, UNIT, true>(A, tile);
 }
 
+// ------------------ T steps per pass (3D) with LDS-shared row halos ---------
+//
+// The 3D pass of k_tb3d with a workgroup of NW waves stacked along y
+// instead of independent waves: wave w holds R consecutive rows (workgroup
+// rows w R .. w R + R - 1, of which the first and last T are the
+// workgroup's halo) of 64 VEC sites along x for every level, and marches
+// along z with the register plane rings of k_tb3d.  The y-neighbours of a
+// wave's first and last row come from the waves next to it through LDS:
+// after a wave computes a plane of level k it writes that plane's first and
+// last row to LDS, and in the next iteration level k+1 reads the rows next
+// to its own from there.  One barrier per iteration puts each plane's
+// writes before its reads and its reads before the buffer is written again
+// (two buffers per level, by plane parity).  The workgroup's NW R rows
+// shrink by one per level at its edges, so level T is valid on the middle
+// NW R - 2T rows, the only ones stored.  A wave holds R rows per level
+// where k_tb3d holds R + 2T, and no row is computed twice inside a
+// workgroup: the registers no longer bound the pass length, and the
+// redundant work is 2T rows per NW R instead of per R.  NW is 8 or 16.
+
+template <int VEC, int T, int R, typename RT>
+struct TB3LState {
+    RT in[4][R][VEC];           // phi^n planes, ring over the march
+    RT pin[2][R][VEC];          // phi_dot^{n-1/2} planes
+    RT lv[T][4][R][VEC];        // level k planes (k = 1 .. T-1)
+    RT pl[T][2][R][VEC];        // level k phi_dot planes
+};
+
+template <int R>
+struct TB3LLane {
+    uint32_t lrow[R];           // byte offset in the plane of this lane's sites in each of the wave's rows
+    uint32_t srow[R];           // the same for stored rows and owned lanes, else past the plane
+    uint32_t plane_bytes;
+    uint64_t plane;
+    int32_t nz, zwrap, zoff;
+    int32_t s0, s1;             // output planes [s0, s1) of the tile
+    uint32_t own_rows;          // bit r: row r of this wave is stored (workgroup's middle rows, inside the lattice)
+    bool own_lane;
+    int wave;
+};
+
+// Rows R of one plane of field f at plane p for this wave.
+template <int VEC, int R, typename RT>
+__device__ __forceinline__ void tb3l_load(const RT* f, int32_t p, const TB3LLane<R>& L, uint32_t bytes,
+                                          RT (&v)[R][VEC])
+{
+    const RT* base = f + (size_t)(uint32_t)p * L.plane;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf_load<VEC>(base, bytes, L.lrow[r], v[r]);
+}
+
+// LDS slot of (level k, plane parity, wave w, side 0 first row / 1 last row)
+// for this lane.
+template <int VEC, int NW, typename RT>
+__device__ __forceinline__ RT* tb3l_slot(RT* lds, int k, int par, int w, int side)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    return lds + ((((k * 2 + par) * NW + w) * 2 + side) * kWave + lane) * VEC;
+}
+
+template <int VEC, typename RT>
+__device__ __forceinline__ void tb3l_put(RT* p, const RT (&v)[VEC])
+{
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) p[j] = v[j];
+}
+
+// Iteration i of the z-march (level k computes plane s0 - T - k + 2 + i, as
+// in k_tb3d).
+template <int VEC, int T, int R, int NW, bool DIAG, bool UNIT, bool CHECK, int U, bool ALL, typename RT>
+__device__ __forceinline__ void tb3l_iter(const TB3Args<T, RT>& A, const TB3LLane<R>& L, RT* lds, int32_t i,
+                                          int32_t last, TBRows& rw, TB3LState<VEC, T, R, RT>& S, DiagAcc& acc)
+{
+    // prefetch phi^n plane z+2 and phi_dot plane z+1 (none after the last)
+    const uint32_t nb = i < last ? L.plane_bytes : 0u;
+    tb3l_load<VEC, R>(A.phi_in, rw.phi, L, nb, S.in[(U + 2) & 3]);
+    tb3l_load<VEC, R>(A.pi_in, rw.pi, L, nb, S.pin[(U + 1) & 1]);
+    rw.phi = next_row(rw.phi, L.zwrap);
+    rw.pi = next_row(rw.pi, L.zwrap);
+    // the boundary rows of the phi^n plane level 1 computes next iteration
+    tb3l_put<VEC>(tb3l_slot<VEC, NW>(lds, 0, U & 1, L.wave, 0), S.in[(U + 1) & 3][0]);
+    tb3l_put<VEC>(tb3l_slot<VEC, NW>(lds, 0, U & 1, L.wave, 1), S.in[(U + 1) & 3][R - 1]);
+    const int wb = L.wave > 0 ? L.wave - 1 : 0;
+    const int wa = L.wave < NW - 1 ? L.wave + 1 : NW - 1;
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        if (CHECK && i < 2 * (k - 1)) continue;
+        const RT(*cm)[VEC];
+        const RT(*cc)[VEC];
+        const RT(*cp)[VEC];
+        const RT(*pp)[VEC];
+        if (k == 1) {
+            cm = S.in[(U + 3) & 3];
+            cc = S.in[U & 3];
+            cp = S.in[(U + 1) & 3];
+            pp = S.pin[U & 1];
+        } else {
+            cm = S.lv[k - 1][(U + 2) & 3];
+            cc = S.lv[k - 1][(U + 3) & 3];
+            cp = S.lv[k - 1][U & 3];
+            pp = S.pl[k - 1][(U + 1) & 1];
+        }
+        // the rows next to this wave's first and last row in level k-1's
+        // plane cc, written by the neighbouring waves last iteration (the
+        // edge waves read their own rows: those results are never valid)
+        RT yb[VEC], ya[VEC];
+        {
+            const RT* pb = tb3l_slot<VEC, NW>(lds, k - 1, (U + 1) & 1, wb, L.wave > 0 ? 1 : 0);
+            const RT* pa = tb3l_slot<VEC, NW>(lds, k - 1, (U + 1) & 1, wa, L.wave < NW - 1 ? 0 : 1);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                yb[j] = pb[j];
+                ya[j] = pa[j];
+            }
+        }
+        const bool diag_plane = DIAG && k == 1 && i >= T - 1 && i < T - 1 + (L.s1 - L.s0);
+        const int32_t zout = L.s0 + i - (2 * T - 2);
+        const uint32_t sb = (!CHECK || i >= 2 * T - 2) ? L.plane_bytes : 0u;
+        const size_t obase = (size_t)(uint32_t)((CHECK && i < 2 * T - 2 ? L.s0 : zout) + L.zoff) * L.plane;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const RT left = from_left_lane(cc[r][VEC - 1]);
+            const RT right = from_right_lane(cc[r][0]);
+            RT out_phi[VEC], out_pi[VEC];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const RT c = cc[r][j];
+                const RT xm = j > 0 ? cc[r][j > 0 ? j - 1 : 0] : left;
+                const RT xp = j < VEC - 1 ? cc[r][j < VEC - 1 ? j + 1 : j] : right;
+                const RT ym = r > 0 ? cc[r > 0 ? r - 1 : 0][j] : yb[j];
+                const RT yp = r < R - 1 ? cc[r < R - 1 ? r + 1 : r][j] : ya[j];
+                kick_drift<3, UNIT>(c, nsum3(xm, xp, ym, yp, cm[r][j], cp[r][j]), pp[r][j], A.k[k - 1], out_pi[j],
+                                    out_phi[j]);
+                if constexpr (DIAG) {
+                    if (k == 1 && diag_plane && ((L.own_rows >> r) & 1u) && L.own_lane) {
+                        const RT nm[3] = {xm, ym, cm[r][j]};
+                        const RT np[3] = {xp, yp, cp[r][j]};
+                        site_diag<3>(c, pp[r][j], nm, np, A.dc, acc);
+                    }
+                }
+            }
+            if (k < T) {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    S.lv[k < T ? k : 0][U & 3][r][j] = out_phi[j];
+                    S.pl[k < T ? k : 0][U & 1][r][j] = out_pi[j];
+                }
+                if constexpr (ALL) {
+                    // stored rows of level k, plane s0 + i - (T + k - 2) when inside [s0, s1)
+                    const int32_t e = i - (T + k - 2);
+                    const bool in = e >= 0 && e < L.s1 - L.s0;
+                    const size_t lb = (size_t)(uint32_t)((in ? L.s0 + e : L.s0) + L.zoff) * L.plane;
+                    buf_store<VEC>(A.phi_lv[k < T ? k - 1 : 0] + lb, in ? L.plane_bytes : 0u, L.srow[r], out_phi);
+                }
+            } else {
+                buf_store<VEC>(A.phi_out + obase, sb, L.srow[r], out_phi);
+                buf_store<VEC>(A.pi_out + obase, sb, L.srow[r], out_pi);
+            }
+        }
+        if (k < T) {
+            tb3l_put<VEC>(tb3l_slot<VEC, NW>(lds, k, U & 1, L.wave, 0), S.lv[k < T ? k : 0][U & 3][0]);
+            tb3l_put<VEC>(tb3l_slot<VEC, NW>(lds, k, U & 1, L.wave, 1), S.lv[k < T ? k : 0][U & 3][R - 1]);
+        }
+    }
+    __syncthreads();
+}
+
+template <int VEC, int T, int R, int NW, bool DIAG, bool UNIT, bool CHECK, bool ALL, typename RT>
+__device__ __forceinline__ bool tb3l_group(const TB3Args<T, RT>& A, const TB3LLane<R>& L, RT* lds, int32_t i,
+                                           int32_t last, TBRows& rw, TB3LState<VEC, T, R, RT>& S, DiagAcc& acc)
+{
+    tb3l_iter<VEC, T, R, NW, DIAG, UNIT, CHECK, 0, ALL>(A, L, lds, i, last, rw, S, acc);
+    if (i + 1 > last) return false;
+    tb3l_iter<VEC, T, R, NW, DIAG, UNIT, CHECK, 1, ALL>(A, L, lds, i + 1, last, rw, S, acc);
+    if (i + 2 > last) return false;
+    tb3l_iter<VEC, T, R, NW, DIAG, UNIT, CHECK, 2, ALL>(A, L, lds, i + 2, last, rw, S, acc);
+    if (i + 3 > last) return false;
+    tb3l_iter<VEC, T, R, NW, DIAG, UNIT, CHECK, 3, ALL>(A, L, lds, i + 3, last, rw, S, acc);
+    return i + 4 <= last;
+}
+
+// Rows a workgroup of the LDS pass stores along y.
+__host__ __device__ constexpr int tb3l_own_rows(int NW, int R, int T) { return NW * R - 2 * T; }
+
+// Waves per SIMD the LDS pass leaves room for: a sixteen-wave workgroup
+// needs four; with eight waves two workgroups per compute unit (four waves
+// per SIMD) where the plane rings fit 128 registers without spilling, else
+// one; diagnostic passes (one pass per record) take the registers they need.
+constexpr int tb3l_min_waves(int vec, int T, int R, int NW, int esize, bool diag)
+{
+    return NW == 16 ? 4 : (!diag && esize == 4 && vec * R * (2 * T + 2) <= 48) ? 4 : 2;
+}
+
+// One workgroup's tile of the LDS pass; all its waves run the same march.
+template <int VEC, int T, int R, int NW, bool DIAG, bool UNIT, bool ALL, typename RT>
+__device__ __forceinline__ void tb3l_tile(const TB3Args<T, RT>& A, int64_t tile, RT* lds)
+{
+    constexpr int H = (T + VEC - 1) / VEC;
+    constexpr int W = (kWave - 2 * H) * VEC;
+    constexpr int YOWN = tb3l_own_rows(NW, R, T);
+    constexpr int WARM = (2 * T - 2 + 3) / 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t tl = __builtin_amdgcn_readfirstlane((uint32_t)tile);
+    const uint32_t tx = tl % (uint32_t)A.tiles_x;
+    const uint32_t rest = tl / (uint32_t)A.tiles_x;
+    const uint32_t tyi = rest % (uint32_t)A.tiles_y;
+    const uint32_t tz = rest / (uint32_t)A.tiles_y;
+    const int32_t nx = (int32_t)A.nx, ny = (int32_t)A.ny;
+    TB3LLane<R> L;
+    L.wave = wave_in_block();
+    L.nz = (int32_t)A.nz;
+    L.plane = (uint64_t)A.nx * (uint64_t)A.ny;
+    L.plane_bytes = (uint32_t)(L.plane * sizeof(RT));
+    const int32_t x0 = (int32_t)(tx * (uint32_t)W) + (lane - H) * VEC;
+    const uint32_t xw = (uint32_t)wrap_row(x0, nx);
+    L.own_lane = lane >= H && lane < kWave - H && x0 < nx;
+    const int32_t y0 = (int32_t)tyi * YOWN;          // first stored row of the workgroup
+    L.own_rows = 0u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t wr = L.wave * R + r - T;      // row relative to y0
+        L.lrow[r] = ((uint32_t)wrap_row(y0 + wr, ny) * (uint32_t)nx + xw) * (uint32_t)sizeof(RT);
+        const bool own = wr >= 0 && wr < YOWN && y0 + wr < ny;
+        L.own_rows |= own ? (1u << r) : 0u;
+        L.srow[r] = (own && L.own_lane) ? L.lrow[r] : kPastRow;
+    }
+    const int32_t rows = (int32_t)A.rows;
+    L.s0 = (int32_t)tz * rows;
+    L.s1 = L.s0 + rows < L.nz ? L.s0 + rows : L.nz;
+    L.zoff = A.zhalo;
+    L.zwrap = L.nz + 2 * A.zhalo;
+    auto zplane = [&](int32_t z) { return A.zhalo ? z + A.zhalo : wrap_row(z, L.nz); };
+
+    TB3LState<VEC, T, R, RT> S;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.in[a][r][j] = RT(0);
+#pragma unroll
+                for (int k = 0; k < T; ++k) S.lv[k][a][r][j] = RT(0);
+            }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                S.pin[a][r][j] = RT(0);
+#pragma unroll
+                for (int k = 0; k < T; ++k) S.pl[k][a][r][j] = RT(0);
+            }
+
+    const int32_t z0 = L.s0 - T + 1;
+    tb3l_load<VEC, R>(A.phi_in, zplane(z0 - 1), L, L.plane_bytes, S.in[3]);
+    tb3l_load<VEC, R>(A.phi_in, zplane(z0), L, L.plane_bytes, S.in[0]);
+    tb3l_load<VEC, R>(A.phi_in, zplane(z0 + 1), L, L.plane_bytes, S.in[1]);
+    tb3l_load<VEC, R>(A.pi_in, zplane(z0), L, L.plane_bytes, S.pin[0]);
+    TBRows rw;
+    rw.phi = zplane(z0 + 2);
+    rw.pi = zplane(z0 + 1);
+    // level 1 of iteration 0 reads the boundary rows of plane z0 (parity 1)
+    tb3l_put<VEC>(tb3l_slot<VEC, NW>(lds, 0, 1, L.wave, 0), S.in[0][0]);
+    tb3l_put<VEC>(tb3l_slot<VEC, NW>(lds, 0, 1, L.wave, 1), S.in[0][R - 1]);
+    __syncthreads();
+
+    DiagAcc acc;
+    acc.links[0] = acc.links[1] = acc.links[2] = 0u;
+    acc.walls = acc.nonfinite = 0u;
+    acc.area = acc.ek = 0.0;
+
+    const int32_t last = (L.s1 - L.s0) + 2 * T - 3;
+    int32_t i = 0;
+    bool more = true;
+#pragma unroll
+    for (int w = 0; w < WARM; ++w) {
+        if (more) more = tb3l_group<VEC, T, R, NW, DIAG, UNIT, true, ALL>(A, L, lds, i, last, rw, S, acc);
+        i += 4;
+    }
+    while (more) {
+        more = tb3l_group<VEC, T, R, NW, DIAG, UNIT, false, ALL>(A, L, lds, i, last, rw, S, acc);
+        i += 4;
+    }
+
+    if constexpr (DIAG) {
+        WavePartial w;
+        w.links[0] = wave_sum_u32(acc.links[0]);
+        w.links[1] = wave_sum_u32(acc.links[1]);
+        w.links[2] = wave_sum_u32(acc.links[2]);
+        w.walls = wave_sum_u32(acc.walls);
+        w.nonfinite = wave_sum_u32(acc.nonfinite);
+        w.pad = 0u;
+        w.area = wave_sum_f64(acc.area);
+        w.ek = wave_sum_f64(acc.ek);
+        if (lane == 0) A.partials[tile * NW + L.wave] = w;
+    }
+}
+
+template <int VEC, int T, int R, int NW, bool DIAG, bool UNIT, bool ALL, typename RT>
+__global__ __launch_bounds__(NW * kWave)
+__attribute__((amdgpu_waves_per_eu(tb3l_min_waves(VEC, T, R, NW, (int)sizeof(RT), DIAG)))) void k_tb3l(TB3Args<T, RT> A)
+{
+    __shared__ RT lds[T * 2 * NW * 2 * kWave * VEC];
+    const int64_t tile = uniform64(xcd_remap(blockIdx.x, gridDim.x));
+    if (tile >= A.ntiles) return;
+    tb3l_tile<VEC, T, R, NW, DIAG, UNIT, ALL>(A, tile, lds);
+}
+
 // ------------------------------- reverse sweep, T steps per pass (3D) ------
 //
 // The 2D reverse pass (k_tba2d) on the 3D tile of k_tb3d: NY = TY + 2T rows
@@ -2307,10 +2623,10 @@ hipError_t launch_step_r(const Geometry& g, const Tiling& t, const void* phi_in,
         }
     } else {
         switch (t.vec) {
-        case 1: return launch_ty<R, 3, 1>(A, t.ty, update, diag, s);
-        case 2: return launch_ty<R, 3, 2>(A, t.ty, update, diag, s);
+        case 1: return launch_ty<R, 3, 1>(A, step_ty(t.ty), update, diag, s);
+        case 2: return launch_ty<R, 3, 2>(A, step_ty(t.ty), update, diag, s);
         case 4:
-            if constexpr (vec_ok<R>(4)) return launch_ty<R, 3, 4>(A, t.ty, update, diag, s);
+            if constexpr (vec_ok<R>(4)) return launch_ty<R, 3, 4>(A, step_ty(t.ty), update, diag, s);
             break;
         }
     }
@@ -2368,7 +2684,7 @@ hipError_t launch_adjoint_r(const Geometry& g, const Tiling& t, const void* w_in
     A.kc = (R)c.kc;
     A.inv_dx2 = (R)c.inv_dx2;
     A.gscale = c.gscale;
-    const int ty = g.ndim == 2 ? 1 : t.ty;
+    const int ty = g.ndim == 2 ? 1 : step_ty(t.ty);
     if (g.ndim == 2) {
         switch (t.vec) {
         case 1: return launch_adj_ty<R, 2, 1>(A, ty, s);
@@ -2748,10 +3064,110 @@ hipError_t launch_tba_r(int T, const Geometry& g, const Tiling& t, const void* w
     return hipErrorInvalidValue;
 }
 
-// Owned rows per wave of a 3D multi-step pass for the tiling's ty.
+// Owned rows per wave of a 3D multi-step pass for the tiling's ty (1, 2, 4:
+// waves of their own; 8, 16: the LDS pass with 2 or 4 rows per wave, whose
+// single steps and reverse steps run the kernels of ty 4).
 __host__ __device__ __forceinline__ int tb3_rows(int ty)
 {
     return ty == 4 ? 8 : 4;
+}
+
+
+// The LDS pass (k_tb3l): float32 vec 1 or 2 and float64 vec 1, 2 or 4 rows
+// per wave, T = 2, 3, 4; sixteen-wave workgroups (whose waves must fit 128
+// registers) with vec 1, or vec 2 and 2 rows per wave, in float32.
+template <typename R>
+constexpr bool tb3l_combo_ok(int vec, int T, int rows_per_wave, int nw = 8)
+{
+    if (nw == 16)
+        return sizeof(R) == 4 && (T == 2 || T == 3 || T == 4) &&
+               ((vec == 1 && (rows_per_wave == 2 || rows_per_wave == 4)) || (vec == 2 && rows_per_wave == 2));
+    return nw == 8 && (T == 2 || T == 3 || T == 4) && (rows_per_wave == 2 || rows_per_wave == 4) &&
+           (vec == 1 || (sizeof(R) == 4 && vec == 2));
+}
+
+// Waves and rows per wave of an LDS tiling: ty 8, 16 are eight waves of 2, 4
+// rows; ty 32, 64 sixteen waves of 2, 4 rows.
+__host__ __device__ __forceinline__ int tb3l_waves(int ty) { return ty >= 32 ? 16 : 8; }
+__host__ __device__ __forceinline__ int tb3l_rows_per_wave(int ty) { return ty >= 32 ? ty / 16 : ty / 4; }
+
+template <typename R, int VEC, int T, int RW, int NW>
+hipError_t launch_tb3l_t(const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out, const void* pi_in,
+                         void* pi_out, void* const* phi_lv, const StepCoef64* k, bool diag, WavePartial* partials,
+                         const DiagCoef& dc, hipStream_t s, int zhalo = 0)
+{
+    TB3Args<T, R> A;
+    A.zhalo = zhalo;
+    A.phi_in = static_cast<const R*>(phi_in);
+    A.phi_out = static_cast<R*>(phi_out);
+    A.pi_in = static_cast<const R*>(pi_in);
+    A.pi_out = static_cast<R*>(pi_out);
+    for (int i = 0; i < T; ++i) A.phi_lv[i] = phi_lv ? static_cast<R*>(phi_lv[i]) : nullptr;
+    A.partials = partials;
+    A.nx = g.nx;
+    A.ny = g.Q;
+    A.nz = g.M;
+    const int64_t W = tb_owned_width_d(VEC, T);
+    constexpr int YOWN = tb3l_own_rows(NW, RW, T);
+    A.tiles_x = (g.nx + W - 1) / W;
+    A.tiles_y = (g.Q + YOWN - 1) / YOWN;
+    A.ntiles = A.tiles_x * A.tiles_y * ((g.M + t.rows - 1) / t.rows);   // workgroups
+    A.rows = t.rows;
+    for (int i = 0; i < T; ++i) A.k[i] = coef_as<R>(k[i]);
+    A.dc = dc;
+    const unsigned blocks = (unsigned)A.ntiles;
+    const bool unit = A.k[0].inv_dx2 == R(1) && A.k[0].kc == R(1);
+    if (phi_lv) {
+        if (unit) hipLaunchKernelGGL((k_tb3l<VEC, T, RW, NW, false, true, true, R>), dim3(blocks), dim3(NW * kWave), 0, s, A);
+        else hipLaunchKernelGGL((k_tb3l<VEC, T, RW, NW, false, false, true, R>), dim3(blocks), dim3(NW * kWave), 0, s, A);
+    } else if (diag) {
+        hipLaunchKernelGGL((k_tb3l<VEC, T, RW, NW, true, false, false, R>), dim3(blocks), dim3(NW * kWave), 0, s, A);
+    } else if (unit) {
+        hipLaunchKernelGGL((k_tb3l<VEC, T, RW, NW, false, true, false, R>), dim3(blocks), dim3(NW * kWave), 0, s, A);
+    } else {
+        hipLaunchKernelGGL((k_tb3l<VEC, T, RW, NW, false, false, false, R>), dim3(blocks), dim3(NW * kWave), 0, s, A);
+    }
+    return hipGetLastError();
+}
+
+// phi_lv non-NULL: the recomputation storing every step's field (phi_out is
+// then phi_lv[T-1]).
+template <typename R>
+hipError_t launch_tb3l_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* phi_out,
+                         const void* pi_in, void* pi_out, void* const* phi_lv, const StepCoef64* k, bool diag,
+                         WavePartial* partials, const DiagCoef& dc, hipStream_t s, int zhalo = 0)
+{
+    const int RW = tb3l_rows_per_wave(t.ty), NW = tb3l_waves(t.ty);
+    if (!tb3l_tiling(t.ty) || !tb3l_combo_ok<R>(t.vec, T, RW, NW)) return hipErrorInvalidValue;
+#define PRS_TB3L(V, TT, RR, WW)                                                                                 \
+    if (t.vec == V && T == TT && RW == RR && NW == WW) {                                                         \
+        if constexpr (tb3l_combo_ok<R>(V, TT, RR, WW))                                                           \
+            return launch_tb3l_t<R, V, TT, RR, WW>(g, t, phi_in, phi_out, pi_in, pi_out, phi_lv, k, diag, partials, \
+                                                   dc, s, zhalo);                                                \
+    }
+    PRS_TB3L(1, 2, 2, 8)
+    PRS_TB3L(1, 3, 2, 8)
+    PRS_TB3L(1, 4, 2, 8)
+    PRS_TB3L(1, 2, 4, 8)
+    PRS_TB3L(1, 3, 4, 8)
+    PRS_TB3L(1, 4, 4, 8)
+    PRS_TB3L(2, 2, 2, 8)
+    PRS_TB3L(2, 3, 2, 8)
+    PRS_TB3L(2, 4, 2, 8)
+    PRS_TB3L(2, 2, 4, 8)
+    PRS_TB3L(2, 3, 4, 8)
+    PRS_TB3L(2, 4, 4, 8)
+    PRS_TB3L(1, 2, 2, 16)
+    PRS_TB3L(1, 3, 2, 16)
+    PRS_TB3L(1, 4, 2, 16)
+    PRS_TB3L(1, 2, 4, 16)
+    PRS_TB3L(1, 3, 4, 16)
+    PRS_TB3L(1, 4, 4, 16)
+    PRS_TB3L(2, 2, 2, 16)
+    PRS_TB3L(2, 3, 2, 16)
+    PRS_TB3L(2, 4, 2, 16)
+#undef PRS_TB3L
+    return hipErrorInvalidValue;
 }
 
 template <typename R, int VEC, int T, int TY>
@@ -2802,6 +3218,8 @@ hipError_t launch_tb3d_r(int T, const Geometry& g, const Tiling& t, const void* 
                          const void* pi_in, void* pi_out, const StepCoef64* k, bool diag, WavePartial* partials,
                          const DiagCoef& dc, hipStream_t s, int zhalo = 0)
 {
+    if (tb3l_tiling(t.ty))
+        return launch_tb3l_r<R>(T, g, t, phi_in, phi_out, pi_in, pi_out, nullptr, k, diag, partials, dc, s, zhalo);
     const int TY = tb3_rows(t.ty);
     if (!tb3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
 #define PRS_TB3(V, TT, YY)                                                                                   \
@@ -2899,6 +3317,9 @@ template <typename R>
 hipError_t launch_tb3_all_r(int T, const Geometry& g, const Tiling& t, const void* phi_in, void* const* phi_lv,
                             const void* pi_in, void* pi_out, const StepCoef64* k, hipStream_t s)
 {
+    if (tb3l_tiling(t.ty))
+        return launch_tb3l_r<R>(T, g, t, phi_in, phi_lv[T - 1], pi_in, pi_out, phi_lv, k, false, nullptr, DiagCoef{},
+                                s);
     const int TY = tb3_rows(t.ty);
     if (!tb3_combo_ok<R>(t.vec, T, TY)) return hipErrorInvalidValue;
 #define PRS_TB3ALL(V, TT, YY)                                                                     \

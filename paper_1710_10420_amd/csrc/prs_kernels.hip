@@ -386,7 +386,7 @@ TileCounts tile_counts(const Geometry& g, const Tiling& t)
 {
     TileCounts c;
     c.tiles_x = (g.nx + (int64_t)kWave * t.vec - 1) / ((int64_t)kWave * t.vec);
-    c.tiles_q = (g.Q + t.ty - 1) / t.ty;
+    c.tiles_q = (g.Q + step_ty(t.ty) - 1) / step_ty(t.ty);
     c.tiles_s = (g.M + t.rows - 1) / t.rows;
     c.ntiles = c.tiles_x * c.tiles_q * c.tiles_s;
     return c;
@@ -399,7 +399,7 @@ bool tiling_supported(const Geometry& g, const Tiling& t)
     if (g.nx % t.vec != 0) return false;
     if (t.rows < 1 || t.rows > 4096) return false;
     if (g.ndim == 2) return t.ty == 1;
-    return t.ty == 1 || t.ty == 2 || t.ty == 4;
+    return t.ty == 1 || t.ty == 2 || t.ty == 4 || tb3l_tiling(t.ty);
 }
 
 // ---- float32 instantiations ----
@@ -519,6 +519,7 @@ hipError_t launch_adj_seed(const Geometry& g, const void* phi, int64_t count, do
 bool tba_supported(const Geometry& g, const Tiling& t, int T)
 {
     if (!tb_supported(g) || !tiling_supported(g, t)) return false;
+    if (g.ndim == 3 && tb3l_tiling(t.ty)) return false;
     if (g.ndim == 3) {
         const int TY = tb3_rows(t.ty);
         return g.f64 ? tba3_combo_ok<double>(t.vec, T, TY) : tba3_combo_ok<float>(t.vec, T, TY);
@@ -782,7 +783,7 @@ bool tb_supported(const Geometry& g)
 bool tb_steps_supported(const Geometry& g, int T)
 {
     if (!tb_supported(g)) return false;
-    if (g.ndim == 3) return T == 2 || (!g.f64 && T == 3);
+    if (g.ndim == 3) return T == 2 || T == 3 || T == 4;
     return T == 2 || T == 3 || T == 4 || T == 6 || T == 8;
 }
 
@@ -790,6 +791,10 @@ bool tb_pass_supported(const Geometry& g, const Tiling& t, int T)
 {
     if (!tb_steps_supported(g, T) || !tiling_supported(g, t)) return false;
     if (g.ndim == 2) return t.ty == 1 && (g.f64 ? tb2_combo_ok<double>(t.vec, T) : tb2_combo_ok<float>(t.vec, T));
+    if (tb3l_tiling(t.ty)) {
+        const int rw = tb3l_rows_per_wave(t.ty), nw = tb3l_waves(t.ty);
+        return g.f64 ? tb3l_combo_ok<double>(t.vec, T, rw, nw) : tb3l_combo_ok<float>(t.vec, T, rw, nw);
+    }
     return g.f64 ? tb3_combo_ok<double>(t.vec, T, tb3_rows(t.ty)) : tb3_combo_ok<float>(t.vec, T, tb3_rows(t.ty));
 }
 
@@ -797,6 +802,12 @@ int64_t tb_tiles(const Geometry& g, const Tiling& t, int T)
 {
     const int64_t W = tb_owned_width(t.vec, T);
     const int64_t planes = (g.M + t.rows - 1) / t.rows;
+    if (g.ndim == 3 && tb3l_tiling(t.ty)) {
+        // one partial per wave of every workgroup
+        const int nw = tb3l_waves(t.ty);
+        const int64_t yown = tb3l_own_rows(nw, tb3l_rows_per_wave(t.ty), T);
+        return ((g.nx + W - 1) / W) * ((g.Q + yown - 1) / yown) * planes * nw;
+    }
     if (g.ndim == 3) {
         const int64_t TY = tb3_rows(t.ty);
         return ((g.nx + W - 1) / W) * ((g.Q + TY - 1) / TY) * planes;

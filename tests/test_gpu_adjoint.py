@@ -2,7 +2,14 @@
 adjoint.  The GPU differentiates its own float32 trajectory and the oracle
 its float64 one, so gradients agree to the trajectory's rounding: relative L2
 <= 1e-4 for runs of up to 64 steps (the oracle adjoint itself is pinned to
-central finite differences in test_oracle_pins)."""
+central finite differences in test_oracle_pins).
+
+dL/dW0 is -2 V0/W0 times dL/dV0 = -sum over steps n and sites i of
+b_n w_i phi_i (phi_i^2 - 1): every term carries the float32 trajectory's
+relative error (<= 1e-5 in the fields over these lengths, the north-star
+field gate) and the sum adds them with mixed signs, so its relative error
+is of that order unless the terms cancel; the gate is 1e-5 (the largest
+deviation seen over these cases is 1.2e-6)."""
 import math
 
 import numpy as np
@@ -53,7 +60,7 @@ def test_adjoint_matches_oracle(shape, nsteps, K):
     assert loss == pytest.approx(ref["loss"], rel=1e-5)
     assert rel_l2(gphi, ref["grad_phi"]) <= 1e-4
     assert rel_l2(gdphi, ref["grad_pi"]) <= 1e-4
-    assert gw == pytest.approx(ref["grad_W0"], rel=1e-3)
+    assert gw == pytest.approx(ref["grad_W0"], rel=1e-5)
 
 
 def gpu_adjoint_T(gp, phi0, nsteps, K, T, tiling=None, TA=None, rec=None, scheme=None, adj_tiling=None):
@@ -222,7 +229,7 @@ def test_prsloss_autograd():
                     ckpt_every=8)
     assert float(loss) == pytest.approx(ref["loss"], rel=1e-5)
     assert rel_l2(host(phi0.grad) / 2.0, ref["grad_phi"]) <= 1e-4
-    assert float(W0.grad) / 2.0 == pytest.approx(ref["grad_W0"], rel=1e-3)
+    assert float(W0.grad) / 2.0 == pytest.approx(ref["grad_W0"], rel=1e-5)
 
 
 @pytest.mark.parametrize("shape,nsteps,K,tuned", [
@@ -260,7 +267,7 @@ def test_adjoint_full_size(shape, nsteps, K, tuned):
         assert loss == pytest.approx(ref["loss"], rel=1e-5), cfg
         assert rel_l2(host(gphi), ref["grad_phi"]) <= 1e-4, cfg
         assert rel_l2(host(gdphi), ref["grad_pi"]) <= 1e-4, cfg
-        assert gw == pytest.approx(ref["grad_W0"], rel=1e-3), cfg
+        assert gw == pytest.approx(ref["grad_W0"], rel=1e-5), cfg
         del sim, work, gphi, gdphi
         torch.cuda.empty_cache()
 

@@ -460,6 +460,68 @@ def test_multi_step_passes_bitwise_equal_single_steps(shape, K, steps):
             assert sim.state()[1].data_ptr() == sim.dphi.data_ptr()
 
 
+@pytest.mark.parametrize("shape,K,steps", [
+    ((40, 30, 20), 5, 17), ((64, 9, 33), 8, 23), ((130, 6, 4), 3, 10), ((2, 3, 5), 64, 9),
+    ((1, 1, 1), 2, 7), ((62, 41, 12), 1, 6), ((128, 70, 45), 10, 26),
+])
+def test_lds_pass_bitwise_equal_single_steps(shape, K, steps):
+    """The LDS-staged 3D pass (a workgroup of waves stacked along y, row
+    halos shared through LDS; ty 8, 16: eight waves of 2, 4 rows; ty 32, 64:
+    sixteen waves of 2, 4 rows) with 2, 3 and 4 steps per pass, one and two
+    sites per lane: fields and record
+    counts bit for bit those of single steps, the FP64 record sums to
+    summation order, for lattices thinner than a workgroup's rows, ragged
+    row and plane tiles and split calls."""
+    say("lds pass", shape, K, steps)
+    prs = gpu_prs()
+    gp, _ = params_pair(shape, 0.2, m=2.0, W0=6.0, diag_every=K)
+    phi0 = uniform_field(shape, 32)
+    ref = prs.Sim(gp, phi0=to_dev(phi0))
+    ref.set_time_blocking(1)
+    r_ref = ref.step_n(steps)
+    rp, rd = (host(t) for t in ref.state())
+    for T in (2, 3, 4):
+        for vec in (1, 2):
+            if shape[0] % vec:
+                continue
+            for t in ((vec, 8, 8), (vec, 13, 16), (vec, 64, 16), (vec, 5, 8), (vec, 11, 32)) + \
+                    (((vec, 9, 64),) if vec == 1 else ()):
+                sim = prs.Sim(gp, phi0=to_dev(phi0))
+                sim.set_tiling(*t)
+                sim.set_time_blocking(T)
+                r1 = sim.step_n(steps // 2)
+                r2 = sim.step_n(steps - steps // 2)
+                p, d = (host(x) for x in sim.state())
+                np.testing.assert_array_equal(p, rp, err_msg=str((T, t)))
+                np.testing.assert_array_equal(d, rd, err_msg=str((T, t)))
+                assert [r["step"] for r in r1 + r2] == [r["step"] for r in r_ref]
+                for a, b in zip(r1 + r2, r_ref):
+                    assert_stats_match(a, b, rel=1e-13, ctx=str((T, t)))
+
+
+def test_lds_pass_f64():
+    """The LDS-staged 3D pass in float64 (one site per lane), T = 2, 3, 4."""
+    say("lds pass f64")
+    prs = gpu_prs()
+    shape = (48, 37, 20)
+    gp = prs.make_params(shape, deta=0.2, m=1.0, W0=6.0, diag_every=7, precision=prs.PRS_F64)
+    ref = prs.Sim(gp, seed=33)
+    ref.set_time_blocking(1)
+    r_ref = ref.step_n(19)
+    rp, rd = (host(t) for t in ref.state())
+    for T in (2, 3, 4):
+        for t in ((1, 8, 8), (1, 16, 16)):
+            sim = prs.Sim(gp, seed=33)
+            sim.set_tiling(*t)
+            sim.set_time_blocking(T)
+            recs = sim.step_n(19)
+            p, d = (host(x) for x in sim.state())
+            np.testing.assert_array_equal(p, rp, err_msg=str((T, t)))
+            np.testing.assert_array_equal(d, rd, err_msg=str((T, t)))
+            for a, b in zip(recs, r_ref):
+                assert_stats_match(a, b, rel=1e-13, ctx=str((T, t)))
+
+
 def test_multi_step_default_and_limits():
     prs = gpu_prs()
     gp, _ = params_pair((64, 64), 0.25)
@@ -480,15 +542,17 @@ def test_multi_step_default_and_limits():
     sim3 = prs.Sim(gp3, seed=1)
     assert sim3.time_blocking() == 1
     sim3.set_time_blocking(3)
-    for bad in (4, 6, 8):
+    sim3.set_time_blocking(4)           # the LDS-staged pass (ty 8, 16) runs four steps
+    for bad in (5, 6, 8):
         with pytest.raises(prs.PRSError) as e:
             sim3.set_time_blocking(bad)
         assert e.value.status == prs.PRS_EINVAL
     gp364 = prs.make_params((16, 16, 16), deta=0.2, precision=prs.PRS_F64)
     sim364 = prs.Sim(gp364, seed=1)
     sim364.set_time_blocking(2)
+    sim364.set_time_blocking(4)
     with pytest.raises(prs.PRSError) as e:
-        sim364.set_time_blocking(3)
+        sim364.set_time_blocking(5)
     assert e.value.status == prs.PRS_EINVAL
 
 
