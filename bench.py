@@ -36,15 +36,17 @@ BYTES_PER_SITE_PASS = 16
 BYTES_PER_UPDATE = 16
 # HBM bytes of one launch of a pass kernel, by (lattice, vec, rows, ty, steps
 # per pass): rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB per dispatch) scaled by
-# what the same counters read for a plain 256 MiB copy (factors 2.00 and
+# what the same counters read for a plain copy of known size (factors 2.00 and
 # 1.00), from the profile named in each entry, taken on kernel sources whose
 # digest (kernel_digest()) is recorded with it.  When the sources differ now
 # the counters no longer describe the kernel and the bench reports null.
 TRAFFIC_PER_LAUNCH = {
-    ("2d8192", 2, 64, 1, 8): {"bytes": 1157032874, "profile": "profiles/k_tb2d_2d8192.md",
-                              "sources": "1294b7d0a17ed25b"},
-    ("2d8192", 2, 128, 1, 8): {"bytes": 1133449051, "profile": "profiles/k_tb2d_2d8192.md",
-                               "sources": "1294b7d0a17ed25b"},
+    ("2d8192", 2, 64, 1, 8): {"bytes": 1158349282, "profile": "profiles/k_tb2d_2d8192.md",
+                              "sources": "8f7313174b557f8f"},
+    ("2d8192", 2, 128, 1, 8): {"bytes": 1134844850, "profile": "profiles/k_tb2d_2d8192.md",
+                               "sources": "8f7313174b557f8f"},
+    ("3d1024", 2, 32, 16, 4): {"bytes": 21622224782, "profile": "profiles/k_tb3l_3d1024.md",
+                               "sources": "8f7313174b557f8f"},
 }
 
 WORKLOAD = {
@@ -257,8 +259,13 @@ def forward_leg(prs, torch, w, runs, warmup, tiling=None, steps_per_pass=None, e
     tr = TRAFFIC_PER_LAUNCH.get((w["key"],) + til + (T,))
     traffic = tr["bytes"] if tr and tr["sources"] == digest else None
     lane_ops, isa = pass_valu_lane_ops(w["shape"], til, T, isa_counts()) if T > 1 else (None, None)
-    kernel = ("k_tb%dd<vec=%d,T=%d> (%d fused leapfrog steps per pass)" % (len(w["shape"]), til[0], T, T)
-              if T > 1 else "k_step (one fused leapfrog step per pass)")
+    if T == 1:
+        kernel = "k_step (one fused leapfrog step per pass)"
+    elif len(w["shape"]) == 3 and til[2] in (8, 16, 32, 64):
+        kernel = ("k_tb3l<vec=%d,T=%d,waves=%d> (%d fused leapfrog steps per pass, row halos through LDS)"
+                  % (til[0], T, 16 if til[2] >= 32 else 8, T))
+    else:
+        kernel = "k_tb%dd<vec=%d,T=%d> (%d fused leapfrog steps per pass)" % (len(w["shape"]), til[0], T, T)
     recs, mu, nu = results[-1]
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,

@@ -124,7 +124,7 @@ int64_t prs_records_in(const prs_params* p, int64_t n0, int64_t nsteps);
 /* Advance nsteps steps (Eqs. 3-6).  The Laplacian, kick and drift of a step
  * run fused in one kernel, and a launch advances up to steps_per_pass steps
  * at once (prs_set_time_blocking: default 2 in 2D, 1 in 3D; the autotuner
- * may choose up to 8 in 2D and 3 in 3D), never with a recorded state inside
+ * may choose up to 8 in 2D and 4 in 3D), never with a recorded state inside
  * a pass.  When series is non-NULL the diagnostics (Eqs. 7-8) of every state
  * n with n % diag_every == 0 are computed inside the pass that starts at n
  * (on its input state) and written to series[0 .. *n_written-1]; cap must be
@@ -155,7 +155,13 @@ prs_status prs_set_state(prs_ctx* ctx, const void* phi, const void* dphi, int64_
  * autotuner).  vec: sites per lane along x (1, 2 or 4 in float32, 1 or 2 in
  * float64; must divide nx);
  * rows: planes per wave along the marching axis (y in 2D, z in 3D), 1..4096;
- * ty: rows per wave along y in 3D (1, 2 or 4; must be 1 in 2D).
+ * ty: in 3D, how a workgroup covers y: 1, 2 or 4 for one-wave workgroups
+ * (single steps: 1, 2 or 4 rows per wave; multi-step passes: 4 rows per
+ * wave, 8 with ty = 4), or 8, 16, 32, 64 for the LDS-staged multi-step
+ * passes, whose workgroups stack waves along y and share their boundary rows
+ * through LDS (8 waves of 2 or 4 rows for ty 8 or 16, 16 waves of 2 or 4
+ * rows for ty 32 or 64; single steps on such a tiling use 4 rows per wave);
+ * must be 1 in 2D.
  * Results are bit-identical for every tiling except the rounding order of the
  * two floating-point diagnostic sums. */
 prs_status prs_set_tiling(prs_ctx* ctx, int32_t vec, int32_t rows, int32_t ty);
@@ -218,12 +224,16 @@ prs_status prs_tuned_tiling(const prs_params* p, const char* cache_path, int32_t
 /* Temporal blocking: with steps_per_pass = T > 1, prs_step_n advances up to
  * T steps per pass over HBM -- a pass never has a recorded state inside it --
  * so each value is read about once per T steps.  T may be 2, 3, 4, 6 or 8 for
- * 2D lattices (default 2), and 2, or 3 in float32, for 3D lattices (default
- * 1); other values give PRS_EINVAL.  A pass uses T steps only when the tiling
- * has a T-step kernel (2D: ty = 1, and in float64 vec 1 for T = 6, 8; 3D:
- * vec 1 with any ty, or vec 2 with ty 1 or 2; a wave owns 4 rows along y, 8
- * with ty = 4) and
- * otherwise the longest length that has one; the autotuner picks T with the
+ * 2D lattices (default 2), and 2, 3 or 4 for 3D lattices (default 1); other
+ * values give PRS_EINVAL.  A pass uses T steps only when the tiling has a
+ * T-step kernel, and otherwise the longest length that has one:
+ *   2D: ty = 1, any vec (in float64, T = 6 and 8 need vec 1).
+ *   3D, one-wave tilings (ty 1, 2, 4): T = 2, 3 in float32 with vec 1, or
+ *     vec 2 and ty 1 or 2; T = 2 in float64 with vec 1 and ty 1 or 2.
+ *   3D, LDS tilings: T = 2, 3, 4; ty 8 and 16 with vec 1 (float32 and
+ *     float64) or vec 2 (float32); ty 32 with vec 1 or 2 and ty 64 with vec 1,
+ *     float32 only.
+ * The autotuner picks T with the
  * tiling.  Results are bitwise those of single steps.  The second phi_dot
  * buffer this needs lives in the workspace; every prs_step_n call still ends
  * with phi_dot in the caller's dphi buffer.  Lattices whose rows (2D) reach
@@ -245,8 +255,9 @@ prs_status prs_plan_passes(const prs_ctx* ctx, int64_t nsteps, int32_t with_reco
  * prs_set_recompute_tiling sets its own (results depend on neither).
  * Multi-step reverse passes exist for 2D lattices with
  * T = 2, 4 and, in float32, 8 and tilings with vec 1 or 2, and for 3D
- * lattices with T = 2 on the tilings of the 3D multi-step passes and, in
- * float32, T = 3 with vec 1 and ty 1 or 2; a pass runs the longest supported
+ * lattices with T = 2 on the one-wave tilings of the 3D multi-step passes
+ * and, in float32, T = 3 with vec 1 and ty 1 or 2 (the LDS tilings, ty >= 8,
+ * have no reverse pass and run single reverse steps); a pass runs the longest supported
  * length up to the setting, down to single reverse steps.  The default
  * tiling is the forward's at prs_init; the default steps per pass 4 in 2D,
  * 1 in 3D. */
