@@ -67,7 +67,7 @@ def kernel_digest():
     """Digest of the kernel sources (device code and its launch templates)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("prs_device.h", "prs_kernels.hip", "prs_internal.h"):
+    for name in ("prs_device.h", "prs_kernels.hip", "prs_ensemble.hip", "prs_internal.h"):
         with open(os.path.join(ROOT, "paper_1710_10420_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -375,7 +375,8 @@ def batch_leg(prs, torch, reps=2):
     (128^3/256^3), m in {0.5,1,2}, W0 in {5,10}, each to eta = N/2.  Each
     realisation runs its tuned single-run pass sequence (tiling and steps per
     pass) on one of four concurrent streams.  The one-launch persistent mode
-    (replayed from a hipGraph) is timed beside it."""
+    (the ensemble kernel replayed from a hipGraph, with the tilings and steps
+    per pass the tuner picks among those it runs) is timed beside it."""
     from paper_1710_10420_amd.inputs import ensemble_draw
     items = ensemble_draw(2017)
     specs = [dict(shape=(it["N"],) * it["ndim"], deta=it["deta"], m=it["m"], W0=it["W0"],
@@ -397,8 +398,7 @@ def batch_leg(prs, torch, reps=2):
             til, T = tuned[key]
             b.set_time_blocking(r, 1)
             b.set_tiling(r, *til)
-            b.set_time_blocking(r, T if mode in (prs.PRS_BATCH_STREAMS_GRAPH, prs.PRS_BATCH_STREAMS)
-                                else (2 if len(key) == 2 else 1))
+            b.set_time_blocking(r, T)
         b.set_mode(mode)
         b.run()                                   # builds and instantiates the graph
         torch.cuda.synchronize()
@@ -421,7 +421,9 @@ def batch_leg(prs, torch, reps=2):
            "tilings": {"x".join(map(str, k)): {"tiling": list(v[0]), "steps_per_pass": v[1]}
                        for k, v in tuned.items()},
            "persistent_kernel": {"ms_per_run": t_p * 1e3, "site_updates_per_s": su / t_p,
-                                 "tilings": {"x".join(map(str, k)): list(v[0])
+                                 "over_streams": t_p / t,
+                                 "mode": "one persistent launch replayed from a hipGraph",
+                                 "tilings": {"x".join(map(str, k)): {"tiling": list(v[0]), "steps_per_pass": v[1]}
                                              for k, v in tuned_p.items()}}}
     log("batch %.1f ms (persistent kernel %.1f ms)" % (t * 1e3, t_p * 1e3))
     b.close()

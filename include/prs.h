@@ -176,9 +176,9 @@ prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty
  * updated; NULL or "" for no cache).  A cached entry for the same GPU
  * architecture, dimension, lattice size and tiling set is applied without
  * timing (and without touching the workspace, which may then be NULL) unless
- * flags has PRS_TUNE_FORCE.  PRS_TUNE_BATCH restricts the candidates to the
- * tilings the persistent batch modes support (ty = 1, single steps); the
- * STREAMS batch modes take the ordinary choice (tiling and steps per pass).
+ * flags has PRS_TUNE_FORCE.  PRS_TUNE_BATCH restricts the candidates
+ * (tilings and steps per pass) to those the persistent batch modes run
+ * (prs_batch_run); the STREAMS batch modes take the ordinary choice.
  * PRS_TUNE_ADJOINT tunes the reverse sweep's tiling and steps per pass
  * instead, on scratch fields in the workspace.
  *   work, work_bytes : device scratch owned by the caller, 256-byte aligned,
@@ -423,16 +423,23 @@ typedef struct prs_batch_item {
 
 typedef struct prs_batch prs_batch;
 
-/* Execution modes.  STREAMS runs every realisation with the single-run pass
- * sequence (its own tiling and steps per pass, up to 4 in 2D) on one of a few
- * concurrent streams, realisations assigned longest-first to the least
+/* Execution modes.  Every mode runs each realisation's single-run pass plan
+ * (its own tiling and steps per pass).  STREAMS launches the passes on one of
+ * a few concurrent streams, realisations assigned longest-first to the least
  * loaded stream (the default); STREAMS_GRAPH captures that launch sequence
- * once in a hipGraph and replays it.  The PERSISTENT modes run all
- * realisations inside one persistent kernel with a grid barrier per phase;
- * they take tilings with ty = 1 and at most 2 steps per pass. */
+ * once in a hipGraph and replays it.  The PERSISTENT modes run the whole
+ * ensemble inside one launch of a persistent kernel: the passes are cut into
+ * work items (eight wave tiles, or one workgroup tile of a 3D LDS-staged
+ * pass) numbered phase by phase (phase p: pass p of every realisation), the
+ * workgroups take items from one counter, and an item waits only until its
+ * own realisation has finished the previous pass (per-realisation counters,
+ * no grid barrier); the workgroup finishing a recorded pass reduces its
+ * record.  They run float32 items with, in 2D, ty 1 and vec 1 or 2 (up to 8
+ * steps per pass) or vec 4 (up to 4), and in 3D single steps with ty 1, or
+ * vec 1 with ty 8 (up to 4 steps per pass) or ty 16 (up to 3). */
 #define PRS_BATCH_PERSISTENT_GRAPH 0  /* one persistent launch, captured in a hipGraph */
-#define PRS_BATCH_PERSISTENT 1        /* the same launch sequence without the graph */
-#define PRS_BATCH_PER_STEP 2          /* one launch per phase over all realisations */
+#define PRS_BATCH_PERSISTENT 1        /* the same launch without the graph */
+#define PRS_BATCH_PER_STEP 2          /* the same kernel, one launch per phase */
 #define PRS_BATCH_STREAMS_GRAPH 3     /* concurrent streams, captured in a hipGraph */
 #define PRS_BATCH_STREAMS 4           /* concurrent streams, launched directly (default) */
 
@@ -451,14 +458,15 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
  * offsets has count+1 entries. */
 prs_status prs_batch_offsets(const prs_batch* b, int64_t* offsets);
 
-/* Tiling of one item (as prs_set_tiling; the persistent modes need ty = 1). */
+/* Tiling of one item (as prs_set_tiling; see the execution modes for the
+ * tilings the persistent modes run). */
 prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t rows, int32_t ty);
 
 /* Steps per pass of one item: 1, or a multi-step pass length as for
  * prs_set_time_blocking (2 is the default for 2D items, 1 for 3D items;
- * PRS_EUNSUPPORTED for rows or planes too long for multi-step passes; the
- * persistent modes take at most 2 in 2D and 1 in 3D).  The second phi_dot
- * field multi-step passes need lives in the workspace. */
+ * PRS_EUNSUPPORTED for rows or planes too long for multi-step passes; see
+ * the execution modes for the lengths the persistent modes run).  The
+ * second phi_dot field multi-step passes need lives in the workspace. */
 prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass);
 
 /* Device pointers of item `item`'s final phi and phi_dot after prs_batch_run
@@ -468,10 +476,11 @@ prs_status prs_batch_set_mode(prs_batch* b, int32_t mode);
 
 /* Runs the whole ensemble (initial fields if init_from_seed, all steps, all
  * records) and synchronises the stream.  series may be NULL; otherwise cap
- * must hold offsets[count] records.  The persistent kernel's grid barrier
- * waits at most 5 s per step; if the grid is not co-resident the run stops
- * with PRS_EDEVICE instead of hanging.  PRS_EINVAL if the mode cannot run an
- * item's tiling or steps per pass. */
+ * must hold offsets[count] records.  A wait of the persistent kernel lasts
+ * at most 5 s (it only waits for items that running workgroups hold, so it
+ * ends unless something has failed); past that the run stops with
+ * PRS_EDEVICE instead of hanging.  PRS_EINVAL if the mode cannot run an
+ * item's precision, tiling or steps per pass. */
 prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap);
 
 void prs_batch_destroy(prs_batch* b);

@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libprs.so")
 
-SOURCES = ["prs_kernels.hip", "prs_kernels_f64.hip", "prs_api.cpp"]
+SOURCES = ["prs_ensemble.hip", "prs_kernels.hip", "prs_kernels_f64.hip", "prs_api.cpp"]
 ARCH = os.environ.get("PRS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1287,7 +1287,11 @@ struct prs_batch {
     void* ws;
     size_t ws_bytes;
     size_t off_desc, off_coef, off_pass, off_alt, off_part, off_rec, off_ctl;
-    int64_t total_tiles, tmax, total_recs;
+    size_t off_phase, off_poff, off_ents;
+    int64_t max_phases;                  // room for this many phases
+    int64_t ctl_count;                   // 32-bit counters of the ensemble kernel
+    int64_t total_recs;
+    std::vector<int64_t> phase_start;    // host copy: items before each phase (nphase + 1)
     prs_stats* hrec;     // pinned
     int* herr;           // pinned
     int32_t mode;
@@ -1312,9 +1316,10 @@ struct PassEntry {
 };
 
 struct BatchLayout {
-    size_t desc, coef, pass, alt, part, rec, ctl, total;
+    size_t desc, coef, pass, alt, part, rec, phase, poff, ents, ctl, total;
     std::vector<size_t> coef_off, pass_off, alt_off, part_off;
     std::vector<int64_t> rec_off, part_cap;
+    int64_t max_phases, ctl_count;
 };
 
 int64_t batch_records_of(const prs_batch_item& it)
@@ -1335,20 +1340,32 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
         if (items[r].nsteps < 0) return fail(PRS_EINVAL, "batch item %d: nsteps < 0", r);
         if (items[r].nsteps > 0x3fffffff) return fail(PRS_EINVAL, "batch item %d: too many steps", r);
     }
-    size_t o = align_up(batch_desc_bytes() * (size_t)count);
+    // tables of the persistent ensemble kernel: a pass plan has at most
+    // nsteps + 1 entries (the last one the final diagnostics)
+    size_t o = align_up(sizeof(EnsDesc) * (size_t)count);
     L.desc = 0;
     L.coef = o;
     L.coef_off.assign(count, 0);
+    int64_t max_passes = 1, all_passes = 0;
     for (int32_t r = 0; r < count; ++r) {
         L.coef_off[r] = o - L.coef;
-        o += align_up((size_t)(items[r].nsteps + 1) * 2 * sizeof(float));
+        o += align_up((size_t)(items[r].nsteps + 1) * sizeof(EnsCoef));
+        max_passes = std::max<int64_t>(max_passes, items[r].nsteps + 1);
+        all_passes += items[r].nsteps + 1;
     }
     L.pass = o;
     L.pass_off.assign(count, 0);
     for (int32_t r = 0; r < count; ++r) {
         L.pass_off[r] = o - L.pass;
-        o += align_up((size_t)(items[r].nsteps + 1) * sizeof(PassEntry));
+        o += align_up((size_t)(items[r].nsteps + 1) * sizeof(EnsPass));
     }
+    L.max_phases = max_passes;
+    L.phase = o;
+    o += align_up((size_t)(max_passes + 1) * sizeof(int64_t));
+    L.poff = o;
+    o += align_up((size_t)(max_passes + 1) * sizeof(int32_t));
+    L.ents = o;
+    o += align_up((size_t)all_passes * sizeof(EnsEnt));
     L.alt = o;
     L.alt_off.assign(count, 0);
     for (int32_t r = 0; r < count; ++r) {
@@ -1367,8 +1384,12 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
     L.rec_off.assign(count + 1, 0);
     for (int32_t r = 0; r < count; ++r) L.rec_off[r + 1] = L.rec_off[r] + batch_records_of(items[r]);
     o += align_up((size_t)L.rec_off[count] * sizeof(prs_stats));
+    // counters: the error flag, one ticket counter per launch (the whole
+    // run, or one per phase), then per realisation the arrivals and the
+    // finished passes
     L.ctl = o;
-    o += align_up((size_t)batch_ctl_bytes());
+    L.ctl_count = 1 + (max_passes + 1) + 2 * (int64_t)count;
+    o += align_up((size_t)L.ctl_count * sizeof(uint32_t));
     L.total = o;
     return PRS_OK;
 }
@@ -1566,54 +1587,118 @@ prs_status batch_enqueue_streams(prs_batch* b, hipStream_t main)
     return PRS_OK;
 }
 
+// Tables of the persistent ensemble kernel, built on the host and copied
+// synchronously: per realisation its coefficients (the single run's FP64
+// schedule rounded to float32 as a launch rounds it), its single-run pass
+// plan with each pass's tile grid and work items, and its descriptor; then
+// the phase tables that number the items (phase p: pass p of every
+// realisation that has one, realisation by realisation).
 prs_status batch_upload(prs_batch* b)
 {
-    // coefficient tables, pass tables and descriptors, built on the host
-    // (same FP64 -> float32 schedule as a single run) and copied synchronously
-    std::vector<char> desc(batch_desc_bytes() * (size_t)b->count);
     char* base = static_cast<char*>(b->ws);
-    int64_t tile_base = 0;
-    b->tmax = 0;
+    std::vector<EnsDesc> desc((size_t)b->count);
+    std::vector<std::vector<EnsPass>> passes((size_t)b->count);
+    int64_t nphase = 0;
     for (int32_t r = 0; r < b->count; ++r) {
         const prs_batch_item& it = b->items[r];
+        const Geometry& g = b->geo[r];
+        const Tiling& t = b->til[r];
         prs_ctx tmp{};
         tmp.p = it.p;
         tmp.V0 = v0_of(it.p);
-        std::vector<float> coef((size_t)(it.nsteps + 1) * 2, 0.0f);
-        for (int64_t n = 0; n < it.nsteps; ++n) {
+        std::vector<EnsCoef> coef((size_t)it.nsteps + 1);
+        for (int64_t n = 0; n <= it.nsteps; ++n) {
             const StepCoef k = f32_of(coef_for(&tmp, n));
-            coef[2 * n] = k.a;
-            coef[2 * n + 1] = k.b;
+            coef[(size_t)n] = EnsCoef{k.a, k.b, k.F, 0.0f, diag_coef(&tmp, n).V0};
         }
-        float2* dcoef = reinterpret_cast<float2*>(base + b->off_coef + b->coef_off[r]);
-        HIP_TRY(hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice),
+        EnsCoef* dcoef = reinterpret_cast<EnsCoef*>(base + b->off_coef + b->coef_off[r]);
+        HIP_TRY(hipMemcpy(dcoef, coef.data(), coef.size() * sizeof(EnsCoef), hipMemcpyHostToDevice),
                 "coefficient upload");
-        const std::vector<PassEntry> plan = batch_plan(it, b->geo[r], b->til[r], b->part_cap[r], b->tblock[r]);
-        void* dpass = base + b->off_pass + b->pass_off[r];
-        HIP_TRY(hipMemcpy(dpass, plan.data(), plan.size() * sizeof(PassEntry), hipMemcpyHostToDevice),
+        const std::vector<PassEntry> plan = batch_plan(it, g, t, b->part_cap[r], b->tblock[r]);
+        std::vector<EnsPass>& ps = passes[(size_t)r];
+        ps.resize(plan.size());
+        int64_t cum = 0;
+        for (size_t i = 0; i < plan.size(); ++i) {
+            EnsPass& e = ps[i];
+            e = EnsPass{};
+            e.first = plan[i].first;
+            e.steps = plan[i].steps;
+            e.rec = plan[i].rec;
+            e.alt = plan[i].alt;
+            ens_pass_grid(g, t, plan[i].steps, e);
+            cum += e.items;
+            e.cum_end = cum;
+        }
+        if (cum >= ((int64_t)1 << 32))
+            return fail(PRS_EUNSUPPORTED, "batch item %d: %lld work items exceed the 32-bit counters", r,
+                        (long long)cum);
+        EnsPass* dpass = reinterpret_cast<EnsPass*>(base + b->off_pass + b->pass_off[r]);
+        HIP_TRY(hipMemcpy(dpass, ps.data(), ps.size() * sizeof(EnsPass), hipMemcpyHostToDevice),
                 "pass table upload");
         b->npasses[r] = (int64_t)plan.size();
-        b->tmax = std::max<int64_t>(b->tmax, (int64_t)plan.size() - 1);
-        float* alt = it.p.ndim == 2 ? reinterpret_cast<float*>(base + b->off_alt + b->alt_off[r]) : nullptr;
-        WavePartial* p0 = reinterpret_cast<WavePartial*>(base + b->off_part + b->part_off[r]);
-        WavePartial* p1 = p0 + (align_up((size_t)b->part_cap[r] * sizeof(WavePartial)) / sizeof(WavePartial));
-        prs_stats* recs = reinterpret_cast<prs_stats*>(base + b->off_rec) + b->rec_off[r];
-        batch_fill_desc(desc.data() + batch_desc_bytes() * r, b->geo[r], b->til[r],
-                        static_cast<float*>(it.phi_a), static_cast<float*>(it.phi_b),
-                        static_cast<float*>(it.dphi), alt, dcoef, dpass, (int64_t)plan.size(), p0, p1, recs,
-                        tile_base, it.p.eta0, it.p.deta, area_scale(it.p), f32_of(coef_for(&tmp, 0)),
-                        diag_coef(&tmp, 0));
-        tile_base += batch_tiles_max(b->geo[r], b->til[r]);
+        nphase = std::max<int64_t>(nphase, (int64_t)plan.size());
+        const StepCoef k0 = f32_of(coef_for(&tmp, 0));
+        EnsDesc& d = desc[(size_t)r];
+        d = EnsDesc{};
+        d.phi[0] = static_cast<float*>(it.phi_a);
+        d.phi[1] = static_cast<float*>(it.phi_b);
+        d.pi = static_cast<float*>(it.dphi);
+        d.pi_alt = reinterpret_cast<float*>(base + b->off_alt + b->alt_off[r]);
+        d.coef = dcoef;
+        d.passes = dpass;
+        d.part = reinterpret_cast<WavePartial*>(base + b->off_part + b->part_off[r]);
+        d.recs = reinterpret_cast<prs_stats*>(base + b->off_rec) + b->rec_off[r];
+        d.nx = g.nx;
+        d.Q = g.Q;
+        d.M = g.M;
+        d.ndim = g.ndim;
+        d.vec = t.vec;
+        d.ty = t.ty;
+        d.rows = t.rows;
+        d.npasses = (int32_t)plan.size();
+        d.unit = (k0.inv_dx2 == 1.0f && k0.kc == 1.0f) ? 1 : 0;
+        d.deta = k0.deta;
+        d.kc = k0.kc;
+        d.inv_dx2 = k0.inv_dx2;
+        d.eta0 = it.p.eta0;
+        d.deta64 = it.p.deta;
+        d.area_scale = area_scale(it.p);
+        d.dkc = diag_coef(&tmp, 0).kc;
     }
-    b->total_tiles = tile_base;
-    HIP_TRY(hipMemcpy(base + b->off_desc, desc.data(), desc.size(), hipMemcpyHostToDevice), "descriptor upload");
+    std::vector<int64_t> start((size_t)nphase + 1, 0);
+    std::vector<int32_t> off((size_t)nphase + 1, 0);
+    std::vector<EnsEnt> ents;
+    int64_t items = 0;
+    for (int64_t p = 0; p < nphase; ++p) {
+        start[(size_t)p] = items;
+        off[(size_t)p] = (int32_t)ents.size();
+        for (int32_t r = 0; r < b->count; ++r) {
+            if (p >= (int64_t)passes[(size_t)r].size()) continue;
+            ents.push_back(EnsEnt{r, 0, items});
+            items += passes[(size_t)r][(size_t)p].items;
+        }
+    }
+    start[(size_t)nphase] = items;
+    off[(size_t)nphase] = (int32_t)ents.size();
+    if (items >= ((int64_t)1 << 31))
+        return fail(PRS_EUNSUPPORTED, "%lld work items exceed the ticket counter", (long long)items);
+    HIP_TRY(hipMemcpy(base + b->off_phase, start.data(), start.size() * sizeof(int64_t), hipMemcpyHostToDevice),
+            "phase table upload");
+    HIP_TRY(hipMemcpy(base + b->off_poff, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+            "phase table upload");
+    HIP_TRY(hipMemcpy(base + b->off_ents, ents.data(), ents.size() * sizeof(EnsEnt), hipMemcpyHostToDevice),
+            "phase table upload");
+    HIP_TRY(hipMemcpy(base + b->off_desc, desc.data(), desc.size() * sizeof(EnsDesc), hipMemcpyHostToDevice),
+            "descriptor upload");
+    b->phase_start = start;
     return PRS_OK;
 }
 
-// The whole ensemble as a sequence on the stream: initial fields, then the
-// phases (one persistent launch, or one launch pair per phase), then the
-// records and the error flag to pinned host memory.
-prs_status batch_enqueue(prs_batch* b, bool persistent, hipStream_t stream)
+// The whole ensemble as a sequence on the stream: initial fields, the
+// counter reset, then the ensemble kernel (one launch over every item, or
+// with PRS_BATCH_PER_STEP one launch per phase), then the records and the
+// error flag to pinned host memory.
+prs_status batch_enqueue(prs_batch* b, bool per_phase, hipStream_t stream)
 {
     char* base = static_cast<char*>(b->ws);
     for (int32_t r = 0; r < b->count; ++r) {
@@ -1623,23 +1708,38 @@ prs_status batch_enqueue(prs_batch* b, bool persistent, hipStream_t stream)
         HIP_TRY(launch_fill_uniform(it.phi_a, n, it.seed, false, stream), "fill launch");
         HIP_TRY(launch_zero_f32(static_cast<float*>(it.dphi), n, stream), "zero launch");
     }
-    void* ctl = base + b->off_ctl;
-    HIP_TRY(launch_batch_reset(ctl, stream), "reset launch");
-    const void* desc = base + b->off_desc;
-    if (persistent) {
-        int blocks = (int)std::min<int64_t>(b->grid_blocks, (b->total_tiles + 3) / 4);
-        if (blocks < 1) blocks = 1;
-        HIP_TRY(launch_batch_persistent(desc, b->count, b->total_tiles, b->tmax, ctl, b->timeout_ticks, blocks,
-                                        stream),
-                "persistent launch");
+    uint32_t* ctl = reinterpret_cast<uint32_t*>(base + b->off_ctl);
+    HIP_TRY(launch_ens_reset(ctl, b->ctl_count, stream), "reset launch");
+    const int64_t nphase = (int64_t)b->phase_start.size() - 1;
+    EnsRun run;
+    run.desc = reinterpret_cast<const EnsDesc*>(base + b->off_desc);
+    run.phase_start = reinterpret_cast<const int64_t*>(base + b->off_phase);
+    run.phase_off = reinterpret_cast<const int32_t*>(base + b->off_poff);
+    run.ents = reinterpret_cast<const EnsEnt*>(base + b->off_ents);
+    run.err = reinterpret_cast<int32_t*>(ctl);
+    run.arrive = ctl + 2 + b->max_phases;
+    run.ready = run.arrive + b->count;
+    run.nphase = (int32_t)nphase;
+    run.pad = 0;
+    run.timeout = b->timeout_ticks;
+    if (per_phase) {
+        for (int64_t p = 0; p < nphase; ++p) {
+            run.ticket = ctl + 2 + p;
+            run.t0 = b->phase_start[(size_t)p];
+            run.t1 = b->phase_start[(size_t)p + 1];
+            const int blocks = (int)std::min<int64_t>(b->grid_blocks, run.t1 - run.t0);
+            HIP_TRY(launch_ens(run, blocks, stream), "ensemble phase launch");
+        }
     } else {
-        for (int64_t t = 0; t <= b->tmax; ++t)
-            HIP_TRY(launch_batch_step(desc, b->count, b->total_tiles, t, stream), "batch phase launch");
+        run.ticket = ctl + 1;
+        run.t0 = 0;
+        run.t1 = b->phase_start[(size_t)nphase];
+        const int blocks = (int)std::min<int64_t>(b->grid_blocks, run.t1);
+        HIP_TRY(launch_ens(run, blocks, stream), "ensemble launch");
     }
     HIP_TRY(hipMemcpyAsync(b->hrec, base + b->off_rec, (size_t)b->total_recs * sizeof(prs_stats),
                            hipMemcpyDeviceToHost, stream), "record copy");
-    HIP_TRY(hipMemcpyAsync(b->herr, static_cast<char*>(ctl) + 2 * sizeof(unsigned), sizeof(int),
-                           hipMemcpyDeviceToHost, stream), "flag copy");
+    HIP_TRY(hipMemcpyAsync(b->herr, ctl, sizeof(int), hipMemcpyDeviceToHost, stream), "flag copy");
     return PRS_OK;
 }
 
@@ -1686,6 +1786,11 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
     b->off_part = L.part;
     b->off_rec = L.rec;
     b->off_ctl = L.ctl;
+    b->off_phase = L.phase;
+    b->off_poff = L.poff;
+    b->off_ents = L.ents;
+    b->max_phases = L.max_phases;
+    b->ctl_count = L.ctl_count;
     b->coef_off = L.coef_off;
     b->pass_off = L.pass_off;
     b->alt_off = L.alt_off;
@@ -1704,7 +1809,7 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
     b->mode = PRS_BATCH_STREAMS;
     b->graph_mode = -1;
     int khz = 0;
-    hipError_t e = batch_max_blocks(&b->grid_blocks);
+    hipError_t e = ens_max_blocks(&b->grid_blocks);
     if (e == hipSuccess) e = batch_clock_rate_khz(&khz);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->hrec),
                                            (size_t)b->total_recs * sizeof(prs_stats), hipHostMallocDefault);
@@ -1713,8 +1818,8 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
         prs_batch_destroy(b);
         return hip_fail(e, "batch setup");
     }
-    // a phase of the largest ensemble takes well under 0.1 s; 5 s means the
-    // grid is not co-resident
+    // a pass of the largest realisation takes well under 0.1 s, and a wait
+    // never outlasts the pass it waits for; 5 s means something is wrong
     b->timeout_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 1000ull * 5ull;
     b->dirty = true;
     *out = b;
@@ -1796,11 +1901,11 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     }
     if (persistent) {
         for (int32_t r = 0; r < b->count; ++r)
-            if (b->til[r].ty != 1 || b->tblock[r] > (b->items[r].p.ndim == 2 ? 2 : 1) ||
-                b->items[r].p.precision != PRS_F32 || b->items[r].p.beta != 0.0)
+            if (b->items[r].p.precision != PRS_F32 || !ens_supported(b->geo[r], b->til[r], b->tblock[r]))
                 return fail(PRS_EINVAL,
-                            "item %d: the persistent modes need float32, beta = 0, ty = 1 and at most 2 steps per "
-                            "pass (single steps in 3D)", r);
+                            "item %d: the persistent modes run float32 items with, in 2D, ty 1 and vec 1 or 2 "
+                            "(up to 8 steps per pass) or vec 4 (up to 4); in 3D, single steps with ty 1, or vec 1 "
+                            "with ty 8 (up to 4 steps per pass) or ty 16 (up to 3)", r);
     }
     if (b->graph_mode != b->mode) batch_release_graph(b);
     if (b->dirty && persistent) {
@@ -1819,7 +1924,8 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
                 if (st != PRS_OK) return st;
             }
             HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "graph capture");
-            prs_status st = persistent ? batch_enqueue(b, true, b->capture) : batch_enqueue_streams(b, b->capture);
+            prs_status st = persistent ? batch_enqueue(b, b->mode == PRS_BATCH_PER_STEP, b->capture)
+                                       : batch_enqueue_streams(b, b->capture);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(b->capture, &g);
             if (st != PRS_OK) {
@@ -1837,7 +1943,7 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
         }
         HIP_TRY(hipGraphLaunch(b->exec, b->stream), "graph launch");
     } else if (persistent) {
-        prs_status st = batch_enqueue(b, b->mode == PRS_BATCH_PERSISTENT, b->stream);
+        prs_status st = batch_enqueue(b, b->mode == PRS_BATCH_PER_STEP, b->stream);
         if (st != PRS_OK) return st;
     } else {
         prs_status st = batch_enqueue_streams(b, b->stream);
@@ -1845,7 +1951,7 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     }
     HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
     if (*b->herr != 0)
-        return fail(PRS_EDEVICE, "batched run aborted: the grid barrier timed out (workgroups not co-resident)");
+        return fail(PRS_EDEVICE, "batched run aborted: a wait of the ensemble kernel timed out");
     if (series) std::memcpy(series, b->hrec, (size_t)b->total_recs * sizeof(prs_stats));
     return PRS_OK;
 }
@@ -1875,7 +1981,7 @@ void prs_batch_destroy(prs_batch* b)
 
 namespace {
 
-constexpr const char* kTuneVersion = "k2";
+constexpr const char* kTuneVersion = "k3";
 
 std::string tune_key(const prs_params& p, bool batch_set)
 {
@@ -1947,7 +2053,7 @@ std::vector<Tiling> tune_candidates(const Geometry& g, bool batch_set)
                 Tiling t{vec, rows, ty};
                 if (rows < kMinRows && rows < g.M) continue;
                 if (!tiling_supported(g, t)) continue;
-                if (batch_set && !batch_tiling_supported(g, t)) continue;
+                if (batch_set && !ens_supported(g, t, 1)) continue;
                 out.push_back(t);
             }
     return out;
@@ -2200,7 +2306,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, void*
         if (it != cache.end()) {
             prs_status st = prs_set_tiling(c, it->second.vec, it->second.rows, it->second.ty);
             // the cached steps per pass, also when it is 1 (single steps)
-            if (st == PRS_OK && !batch_set) st = prs_set_time_blocking(c, std::max(1, it->second.tb));
+            if (st == PRS_OK) st = prs_set_time_blocking(c, std::max(1, it->second.tb));
             if (st == PRS_OK) {
                 if (best_us) *best_us = it->second.us;
                 return PRS_OK;
@@ -2252,7 +2358,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, void*
         }
         return hipSuccess;
     };
-    const int max_T = (!batch_set && tb_supported(c->geo)) ? kMaxPassSteps : 1;
+    const int max_T = tb_supported(c->geo) ? kMaxPassSteps : 1;
     int best_T = c->tblock;
     e = hipMemcpyAsync(save_phi, c->phi[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(save_pi, c->pi, bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -2262,6 +2368,7 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, void*
         for (const Tiling& t : cand) {
             if (e != hipSuccess) break;
             if (T > 1 && !tb_pass_supported(c->geo, t, T)) continue;
+            if (batch_set && !ens_supported(c->geo, t, T)) continue;
             if (tile_counts(c->geo, t).ntiles > c->partial_cap) continue;
             if (T > 1 && tb_tiles(c->geo, t, T) > c->partial_cap) continue;
             e = run(t, 2);
@@ -2295,10 +2402,10 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, void*
     c->step = n0;
     if (result != PRS_OK) return result;
     c->til = best;
-    if (!batch_set) c->tblock = best_T;
+    c->tblock = best_T;
     if (best_us) *best_us = best_t * 1e3;
     if (cache_path && cache_path[0]) {
-        cache[key] = TuneEntry{best.vec, best.rows, best.ty, batch_set ? 1 : best_T, best_t * 1e3};
+        cache[key] = TuneEntry{best.vec, best.rows, best.ty, best_T, best_t * 1e3};
         if (!tune_write(cache_path, cache)) return fail(PRS_EINVAL, "cannot write tuning cache %s", cache_path);
     }
     return PRS_OK;

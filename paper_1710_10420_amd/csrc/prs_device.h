@@ -67,10 +67,11 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
 
 // 3D tilings with ty 8, 16, 32 or 64 select the LDS-staged multi-step pass
 // (eight waves of 2 or 4 rows for ty 8, 16; sixteen waves of 2 or 4 rows for
-// ty 32, 64); their single steps and reverse steps run the kernels of ty 4.
+// ty 32, 64); their single steps and reverse steps run the one-row kernels
+// of ty 1 (whose registers stay low enough for the ensemble kernel).
 __host__ __device__ __forceinline__ bool tb3l_tiling(int ty) { return ty == 8 || ty == 16 || ty == 32 || ty == 64; }
 
-__host__ __device__ __forceinline__ int step_ty(int ty) { return ty > 4 ? 4 : ty; }
+__host__ __device__ __forceinline__ int step_ty(int ty) { return ty > 4 ? 1 : ty; }
 
 // Index of this wave within its workgroup, as a wave-uniform (scalar) value:
 // the compiler cannot prove threadIdx.x / 64 uniform on its own, and every
@@ -306,6 +307,55 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
+}
+
+// Adds `count` wave partials into one record, with one wave, in a fixed
+// order: lane l sums partials l, l+64, l+128, ... and the 64 lane sums are
+// combined by a fixed butterfly.  Every path that produces a record (single
+// run, standalone diagnostics, batched ensemble) calls this function, so a
+// record depends only on the partials, never on which kernel reduced them.
+__device__ __forceinline__ void finalize_wave(const WavePartial* __restrict__ parts, int64_t count,
+                                              prs_stats* __restrict__ rec, int64_t step, double eta,
+                                              double area_scale)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t l0 = 0, l1 = 0, l2 = 0, wl = 0, nf = 0;
+    double ar = 0.0, ek = 0.0;
+#pragma unroll 8
+    for (int64_t i = lane; i < count; i += kWave) {
+        const WavePartial p = parts[i];
+        l0 += p.links[0];
+        l1 += p.links[1];
+        l2 += p.links[2];
+        wl += p.walls;
+        nf += p.nonfinite;
+        ar += p.area;
+        ek += p.ek;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        l0 += __shfl_xor(l0, o, kWave);
+        l1 += __shfl_xor(l1, o, kWave);
+        l2 += __shfl_xor(l2, o, kWave);
+        wl += __shfl_xor(wl, o, kWave);
+        nf += __shfl_xor(nf, o, kWave);
+        ar += __shfl_xor(ar, o, kWave);
+        ek += __shfl_xor(ek, o, kWave);
+    }
+    if (lane == 0) {
+        prs_stats r;
+        r.step = step;
+        r.eta = eta;
+        r.links_dir[0] = l0;
+        r.links_dir[1] = l1;
+        r.links_dir[2] = l2;
+        r.links = l0 + l1 + l2;
+        r.wall_sites = wl;
+        r.nonfinite = nf;
+        r.area_density = ar * area_scale;
+        r.gv2 = wl ? ek / (double)wl : 0.0;
+        *rec = r;
+    }
 }
 
 template <typename R>
@@ -902,6 +952,13 @@ __device__ __forceinline__ void buf_load(const R* base, uint32_t bytes, uint32_t
     }
 }
 
+// Cache policy of the multi-step passes' field stores (0: the default
+// write-back policy; a translation unit may define another before including
+// this header).
+#ifndef PRS_STORE_AUX
+#define PRS_STORE_AUX 0
+#endif
+
 template <int VEC, typename R>
 __device__ __forceinline__ void buf_store(R* base, uint32_t bytes, uint32_t soff, const R (&v)[VEC])
 {
@@ -920,11 +977,11 @@ __device__ __forceinline__ void buf_store(R* base, uint32_t bytes, uint32_t soff
         }
     }
     if constexpr (W == 4) {
-        __builtin_amdgcn_raw_buffer_store_b128(t, r, soff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(t, r, soff, 0, PRS_STORE_AUX);
     } else if constexpr (W == 2) {
-        __builtin_amdgcn_raw_buffer_store_b64(t, r, soff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, soff, 0, PRS_STORE_AUX);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(t[0], r, soff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(t[0], r, soff, 0, PRS_STORE_AUX);
     }
 }
 

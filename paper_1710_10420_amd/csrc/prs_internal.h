@@ -226,24 +226,85 @@ hipError_t launch_adj_seed_f64(const void* phi, int64_t count, double kc, double
 hipError_t launch_fill_f32(void* phi, int64_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_fill_f64(void* phi, int64_t count, uint64_t seed, hipStream_t s);
 
-// Batched ensemble (descriptor layout is private to the kernel file).
-size_t batch_desc_bytes();
-int batch_ctl_bytes();
-// passes: device array of int4 (first step, steps 0/1/2, record index or -1,
-// phi_dot read from pi_alt) with npasses entries (the last: diagnostics only).
-void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0, float* phi1, float* pi,
-                     float* pi_alt, const float2* coef, const void* passes, int64_t npasses,
-                     WavePartial* part0, WavePartial* part1, prs_stats* recs, int64_t tile_base,
-                     double eta0, double deta, double area_scale, const StepCoef& k, const DiagCoef& dc);
-// Tiles reserved per phase for one realisation.
-int64_t batch_tiles_max(const Geometry& g, const Tiling& t);
-bool batch_tiling_supported(const Geometry& g, const Tiling& t);
-hipError_t batch_max_blocks(int* blocks);
+// ---- batched ensemble: the persistent dataflow kernel (prs_ensemble.hip) ----
+//
+// Every realisation's single-run pass plan becomes a table of passes; each
+// pass is cut into work items (eight wave tiles, or one workgroup tile of the
+// LDS-staged 3D pass).  Items are numbered phase by phase (phase p holds pass
+// p of every realisation that has one) and handed out by one ticket counter;
+// an item of pass p waits until its own realisation has finished pass p-1.
+
+// Per-step coefficients of one realisation: a_n, b_n and the force
+// coefficient F_n rounded to float32 exactly as a single-run launch rounds
+// them, and V0 a(eta_n)^beta of the diagnostics in FP64.
+struct EnsCoef {
+    float a, b, F, pad;
+    double dV0;
+};
+
+struct EnsPass {
+    int32_t first;      // first step n of the pass
+    int32_t steps;      // 1 .. 8, or 0: diagnostics of the final state only
+    int32_t rec;        // record index, or -1
+    int32_t alt;        // 1: phi_dot is read from pi_alt
+    int32_t tiles_x, tiles_q;   // tile grid of the pass (tiles_q: along y in 3D)
+    int32_t items;      // work items of the pass
+    int32_t chunk;      // tiles per wave (workgroup tiles in 3D multi-step passes) per item
+    int64_t ntiles;     // wave tiles, or workgroup tiles of a 3D multi-step pass
+    int64_t nparts;     // wave partials the record reduces
+    int64_t cum_end;    // items of this realisation's passes up to this one
+};
+
+struct EnsDesc {
+    float* phi[2];      // pass p reads phi[p & 1] and writes phi[(p + 1) & 1]
+    float* pi;          // the caller's phi_dot
+    float* pi_alt;      // second phi_dot field of multi-step passes
+    const EnsCoef* coef;
+    const EnsPass* passes;
+    WavePartial* part;
+    prs_stats* recs;
+    int64_t nx, Q, M;
+    int32_t ndim, vec, ty, rows;
+    int32_t npasses, unit;      // unit: dx = 1 and phi0 = 1
+    float deta, kc, inv_dx2, pad;
+    double eta0, deta64, area_scale, dkc;
+};
+
+// The first item of realisation r in its phase.
+struct EnsEnt {
+    int32_t r, pad;
+    int64_t start;
+};
+
+struct EnsRun {
+    const EnsDesc* desc;
+    const int64_t* phase_start;     // nphase + 1 cumulative item counts
+    const int32_t* phase_off;       // nphase + 1 offsets into ents
+    const EnsEnt* ents;
+    uint32_t* ticket;               // ticket counter of this launch
+    uint32_t* arrive;               // per realisation: items finished
+    uint32_t* ready;                // per realisation: passes finished
+    int32_t* err;                   // raised when a wait times out
+    int64_t t0, t1;                 // items [t0, t1) of this launch
+    int32_t nphase, pad;
+    uint64_t timeout;               // wall-clock ticks a wait may take
+};
+
+// Waves per workgroup of the ensemble kernel.
+constexpr int kEnsWaves = 8;
+
+// Settings the ensemble kernel holds code for (float32): 2D ty 1 with vec 1
+// or 2 and T <= 8, or vec 4 and T <= 4; 3D single steps (T = 1) with ty 1 and
+// vec 1, 2 or 4; 3D LDS-staged passes with vec 1 and ty 8 (T <= 4) or ty 16
+// (T <= 3).
+bool ens_supported(const Geometry& g, const Tiling& t, int T);
+// Wave tiles, tile grid and items of one pass of length L (0: diagnostics only).
+void ens_pass_grid(const Geometry& g, const Tiling& t, int L, EnsPass& ps);
+hipError_t ens_max_blocks(int* blocks);
 hipError_t batch_clock_rate_khz(int* khz);
-hipError_t launch_batch_reset(void* ctl, hipStream_t s);
-hipError_t launch_batch_persistent(const void* descs, int nreal, int64_t total_tiles, int64_t tmax,
-                                   void* ctl, uint64_t timeout, int blocks, hipStream_t s);
-hipError_t launch_batch_step(const void* descs, int nreal, int64_t total_tiles, int64_t t, hipStream_t s);
+// Zeroes `count` 32-bit counters (a kernel, so that it can be captured).
+hipError_t launch_ens_reset(uint32_t* ctl, int64_t count, hipStream_t s);
+hipError_t launch_ens(const EnsRun& run, int blocks, hipStream_t s);
 hipError_t launch_zero_f32(float* v, int64_t count, hipStream_t s);
 
 }  // namespace prs

@@ -1,6 +1,6 @@
 // prs_kernels.hip -- float32 instantiation of the PRS kernels (the device
-// templates are in prs_device.h), the record reduction, the batched-ensemble
-// kernels and the host-side dispatch by precision.
+// templates are in prs_device.h), the record reduction and the host-side
+// dispatch by precision (the batched ensemble's kernel is in prs_ensemble.hip).
 
 #include <mutex>
 
@@ -9,55 +9,6 @@
 namespace prs {
 
 namespace {
-
-// Adds `count` wave partials into one record, with one wave, in a fixed
-// order: lane l sums partials l, l+64, l+128, ... and the 64 lane sums are
-// combined by a fixed butterfly.  Every path that produces a record (single
-// run, standalone diagnostics, batched ensemble) calls this function, so a
-// record depends only on the partials, never on which kernel reduced them.
-__device__ __forceinline__ void finalize_wave(const WavePartial* __restrict__ parts, int64_t count,
-                                              prs_stats* __restrict__ rec, int64_t step, double eta,
-                                              double area_scale)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    uint64_t l0 = 0, l1 = 0, l2 = 0, wl = 0, nf = 0;
-    double ar = 0.0, ek = 0.0;
-#pragma unroll 8
-    for (int64_t i = lane; i < count; i += kWave) {
-        const WavePartial p = parts[i];
-        l0 += p.links[0];
-        l1 += p.links[1];
-        l2 += p.links[2];
-        wl += p.walls;
-        nf += p.nonfinite;
-        ar += p.area;
-        ek += p.ek;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        l0 += __shfl_xor(l0, o, kWave);
-        l1 += __shfl_xor(l1, o, kWave);
-        l2 += __shfl_xor(l2, o, kWave);
-        wl += __shfl_xor(wl, o, kWave);
-        nf += __shfl_xor(nf, o, kWave);
-        ar += __shfl_xor(ar, o, kWave);
-        ek += __shfl_xor(ek, o, kWave);
-    }
-    if (lane == 0) {
-        prs_stats r;
-        r.step = step;
-        r.eta = eta;
-        r.links_dir[0] = l0;
-        r.links_dir[1] = l1;
-        r.links_dir[2] = l2;
-        r.links = l0 + l1 + l2;
-        r.wall_sites = wl;
-        r.nonfinite = nf;
-        r.area_density = ar * area_scale;
-        r.gv2 = wl ? ek / (double)wl : 0.0;
-        *rec = r;
-    }
-}
 
 __global__ __launch_bounds__(kWave) void k_finalize(const WavePartial* __restrict__ parts,
                                                      int64_t count, prs_stats* __restrict__ rec,
@@ -117,252 +68,11 @@ __global__ __launch_bounds__(kBlock) void k_zero_f64(double* __restrict__ v, int
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) v[i] = 0.0;
 }
 
-// ------------------------------------------------------- batched ensemble --
-//
-// Many independent realisations (different sizes, dimensions, eras, wall
-// widths and step counts) advance together.  Each realisation carries a
-// table of passes made on the host: a pass advances 1 or 2 steps (two-step
-// passes for 2D lattices, never with a recorded state inside), may record the
-// diagnostics of its input state, and the last entry is a diagnostics-only
-// pass over the final state.  Phase t runs pass t of every realisation that
-// has one; each tile runs step_tile or tb_tile, the code of a single run, so
-// a realisation's fields and records are bitwise those of the same
-// realisation run alone with the same tiling and steps per pass.
-//
-// Persistent mode: one launch whose workgroups stay resident for the whole
-// ensemble; a wave walks the global tile list with stride = number of waves,
-// then all workgroups meet at a software grid barrier before the next phase.
-// The records of phase t are reduced by one wave per realisation right after
-// that barrier.  The barrier's wait is bounded: if it does not complete
-// within the time limit (workgroups not co-resident), an error flag is raised
-// and every workgroup leaves, so the kernel always finishes.
-
-struct BatchDesc {
-    StepArgs A;              // geometry, tiling and constant coefficients
-    float* phi[2];           // phase t reads phi[t & 1]
-    float* pi_alt;           // second phi_dot buffer for two-step passes (2D)
-    const float2* coef;      // (a_n, b_n) for n = 0 .. nsteps-1
-    const int4* passes;      // (first step, steps (0: diagnostics only), record or -1, phi_dot in pi_alt)
-    WavePartial* part[2];    // alternate record partial buffers
-    prs_stats* recs;
-    int64_t npasses;         // including the final diagnostics-only pass
-    int64_t tile_base;       // first global tile of this realisation
-    int64_t tiles_max;       // tiles reserved per phase (the larger pass kind)
-    int64_t tiles_multi;     // tiles of a two-step pass (2D)
-    double eta0, deta, area_scale;
-    int32_t ndim, vec, ty, pad;
-};
-
-struct BatchCtl {
-    unsigned int arrive;
-    unsigned int gen;
-    int err;
-    int pad;
-};
-
-__device__ __forceinline__ int find_real(const BatchDesc* __restrict__ D, int nreal, int64_t tile)
-{
-    int lo = 0, hi = nreal - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (D[mid].tile_base <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <int D, int VEC, int TY>
-__device__ __forceinline__ void tile_mode(const StepArgs& A, int64_t tile, bool update, bool diag)
-{
-    if (update && diag) step_tile<D, VEC, TY, true, true>(A, tile);
-    else if (update) step_tile<D, VEC, TY, true, false>(A, tile);
-    else step_tile<D, VEC, TY, false, true>(A, tile);
-}
-
-// Tilings available inside the batched kernels (every instance is inlined
-// into them, so the set is kept small to bound register pressure).
-__device__ __forceinline__ void dispatch_tile(int ndim, int vec, const StepArgs& A, int64_t tile,
-                                              bool update, bool diag)
-{
-    if (ndim == 2) {
-        if (vec == 4) tile_mode<2, 4, 1>(A, tile, update, diag);
-        else if (vec == 2) tile_mode<2, 2, 1>(A, tile, update, diag);
-        else tile_mode<2, 1, 1>(A, tile, update, diag);
-    } else {
-        if (vec == 4) tile_mode<3, 4, 1>(A, tile, update, diag);
-        else if (vec == 2) tile_mode<3, 2, 1>(A, tile, update, diag);
-        else tile_mode<3, 1, 1>(A, tile, update, diag);
-    }
-}
-
-__device__ __forceinline__ void dispatch_pair(int vec, const TBArgs<2>& A, int64_t tile, bool diag)
-{
-    if (vec == 4) {
-        if (diag) tb_tile<4, 2, true>(A, tile);
-        else tb_tile<4, 2, false>(A, tile);
-    } else if (vec == 2) {
-        if (diag) tb_tile<2, 2, true>(A, tile);
-        else tb_tile<2, 2, false>(A, tile);
-    } else {
-        if (diag) tb_tile<1, 2, true>(A, tile);
-        else tb_tile<1, 2, false>(A, tile);
-    }
-}
-
-// Work of global tile i in phase t.
-__device__ __forceinline__ void batch_tile(const BatchDesc* __restrict__ Dd, int nreal, int64_t i,
-                                           int64_t t)
-{
-    const BatchDesc& d = Dd[find_real(Dd, nreal, i)];
-    if (t >= d.npasses) return;
-    const int4 ps = d.passes[t];
-    const int64_t local = i - d.tile_base;
-    const bool diag = ps.z >= 0;
-    const float* pin = ps.w ? d.pi_alt : d.A.pi_out;
-    if (ps.y == 2) {
-        if (local >= d.tiles_multi) return;
-        TBArgs<2> A;
-        A.phi_in = d.phi[t & 1];
-        A.phi_out = d.phi[(t + 1) & 1];
-        A.pi_in = pin;
-        A.pi_out = ps.w ? d.A.pi_out : d.pi_alt;
-        A.partials = diag ? d.part[ps.z & 1] : nullptr;
-        A.nx = d.A.nx;
-        A.ny = d.A.M;
-        A.tiles_x = (d.A.nx + tb_owned_width_d(d.vec, 2) - 1) / tb_owned_width_d(d.vec, 2);
-        A.ntiles = d.tiles_multi;
-        A.rows = d.A.rows;
-        A.k[0] = d.A.k;
-        A.k[1] = d.A.k;
-        const float2 c0 = d.coef[ps.x], c1 = d.coef[ps.x + 1];
-        A.k[0].a = c0.x;
-        A.k[0].b = c0.y;
-        A.k[1].a = c1.x;
-        A.k[1].b = c1.y;
-        A.dc = d.A.dc;
-        dispatch_pair(d.vec, A, local, diag);
-        return;
-    }
-    if (local >= d.A.ntiles) return;
-    StepArgs A = d.A;
-    A.phi_in = d.phi[t & 1];
-    A.phi_out = d.phi[(t + 1) & 1];
-    A.pi = pin;
-    A.pi_out = const_cast<float*>(pin);
-    const bool update = ps.y == 1;
-    if (update) {
-        const float2 c = d.coef[ps.x];
-        A.k.a = c.x;
-        A.k.b = c.y;
-    }
-    A.partials = diag ? d.part[ps.z & 1] : nullptr;
-    dispatch_tile(d.ndim, d.vec, A, local, update, diag);
-}
-
-// Records of phase t, one wave per realisation (waves w, w+nw, ...).
-__device__ __forceinline__ void batch_records(const BatchDesc* __restrict__ Dd, int nreal, int64_t t,
-                                              int64_t wave, int64_t nwaves)
-{
-    for (int64_t r = wave; r < nreal; r += nwaves) {
-        const BatchDesc& d = Dd[r];
-        if (t >= d.npasses) continue;
-        const int4 ps = d.passes[t];
-        if (ps.z < 0) continue;
-        const int64_t count = ps.y == 2 ? d.tiles_multi : d.A.ntiles;
-        finalize_wave(d.part[ps.z & 1], count, d.recs + ps.z, ps.x, d.eta0 + (double)ps.x * d.deta,
-                      d.area_scale);
-    }
-}
-
-// Grid-wide barrier for a resident grid.  Arrivals count up monotonically;
-// the last arrival of generation g publishes g+1.  Release/acquire fences at
-// agent scope make every field written before the barrier visible to every
-// XCD after it.  Returns false (and raises ctl->err) when the wait exceeds
-// `timeout` wall-clock ticks or another workgroup has already failed.
-__device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned gen,
-                                             uint64_t timeout)
-{
-    __shared__ int s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        __threadfence();
-        const unsigned prev =
-            __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev + 1u == (gen + 1u) * nblocks) {
-            __hip_atomic_store(&ctl->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <= gen) {
-                if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    ok = 0;
-                    break;
-                }
-                if (wall_clock64() - t0 > timeout) {
-                    __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        __threadfence();
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
-
-__global__ __launch_bounds__(kBlock) void k_batch_persistent(const BatchDesc* __restrict__ Dd,
-                                                              int nreal, int64_t total_tiles,
-                                                              int64_t tmax, BatchCtl* ctl,
-                                                              uint64_t timeout)
-{
-    const int64_t wave = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    unsigned gen = 0;
-    for (int64_t t = 0; t <= tmax + 1; ++t) {
-        if (t > 0) batch_records(Dd, nreal, t - 1, wave, nwaves);
-        if (t > tmax) break;
-        for (int64_t i = wave; i < total_tiles; i += nwaves) batch_tile(Dd, nreal, i, t);
-        if (!grid_barrier(ctl, gridDim.x, gen, timeout)) return;
-        ++gen;
-    }
-}
-
-// Fallback without a resident grid: one launch per phase over all tiles,
-// then one launch for that phase's records.
-__global__ __launch_bounds__(kBlock) void k_batch_step(const BatchDesc* __restrict__ Dd, int nreal,
-                                                        int64_t total_tiles, int64_t t)
-{
-    const int64_t i = uniform64(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block());
-    if (i >= total_tiles) return;
-    batch_tile(Dd, nreal, i, t);
-}
-
-__global__ __launch_bounds__(kBlock) void k_batch_records(const BatchDesc* __restrict__ Dd, int nreal,
-                                                           int64_t t)
-{
-    const int64_t wave = uniform64((int64_t)blockIdx.x * kWavesPerBlock + wave_in_block());
-    batch_records(Dd, nreal, t, wave, (int64_t)gridDim.x * kWavesPerBlock);
-}
-
 __global__ __launch_bounds__(kBlock) void k_zero_f32(float* __restrict__ v, int64_t count)
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) v[i] = 0.0f;
 }
-
-__global__ void k_batch_reset(BatchCtl* ctl)
-{
-    if (threadIdx.x == 0) {
-        ctl->arrive = 0u;
-        ctl->gen = 0u;
-        ctl->err = 0;
-        ctl->pad = 0;
-    }
-}
-
 
 }  // namespace
 
@@ -648,111 +358,12 @@ hipError_t launch_zero_f64(double* v, int64_t count, hipStream_t s)
     return hipGetLastError();
 }
 
-// ---- batched ensemble launchers ----
-
-size_t batch_desc_bytes() { return sizeof(BatchDesc); }
-
-void batch_fill_desc(void* out, const Geometry& g, const Tiling& t, float* phi0, float* phi1, float* pi,
-                     float* pi_alt, const float2* coef, const void* passes, int64_t npasses,
-                     WavePartial* part0, WavePartial* part1, prs_stats* recs, int64_t tile_base,
-                     double eta0, double deta, double area_scale, const StepCoef& k, const DiagCoef& dc)
-{
-    const TileCounts c = tile_counts(g, t);
-    BatchDesc d;
-    d.A.phi_in = nullptr;
-    d.A.phi_out = nullptr;
-    d.A.pi = pi;
-    d.A.pi_out = pi;
-    d.A.partials = nullptr;
-    d.A.nx = g.nx;
-    d.A.Q = g.Q;
-    d.A.M = g.M;
-    d.A.tiles_x = c.tiles_x;
-    d.A.tiles_q = c.tiles_q;
-    d.A.ntiles = c.ntiles;
-    d.A.rows = t.rows;
-    d.A.k = k;
-    d.A.dc = dc;
-    d.phi[0] = phi0;
-    d.phi[1] = phi1;
-    d.pi_alt = pi_alt;
-    d.coef = coef;
-    d.passes = static_cast<const int4*>(passes);
-    d.part[0] = part0;
-    d.part[1] = part1;
-    d.recs = recs;
-    d.npasses = npasses;
-    d.tile_base = tile_base;
-    d.tiles_multi = g.ndim == 2 ? tb_tiles(g, t, 2) : 0;
-    d.tiles_max = std::max<int64_t>(c.ntiles, d.tiles_multi);
-    d.eta0 = eta0;
-    d.deta = deta;
-    d.area_scale = area_scale;
-    d.ndim = g.ndim;
-    d.vec = t.vec;
-    d.ty = t.ty;
-    d.pad = 0;
-    *static_cast<BatchDesc*>(out) = d;
-}
-
-int64_t batch_tiles_max(const Geometry& g, const Tiling& t)
-{
-    const int64_t a = tile_counts(g, t).ntiles;
-    return g.ndim == 2 ? std::max<int64_t>(a, tb_tiles(g, t, 2)) : a;
-}
-
-bool batch_tiling_supported(const Geometry& g, const Tiling& t)
-{
-    return tiling_supported(g, t) && t.ty == 1;
-}
-
-hipError_t batch_max_blocks(int* blocks)
-{
-    int dev = 0, cus = 0, per = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_persistent, kBlock, 0);
-    if (e != hipSuccess) return e;
-    *blocks = cus * per;
-    return hipSuccess;
-}
-
 hipError_t batch_clock_rate_khz(int* khz)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     return hipDeviceGetAttribute(khz, hipDeviceAttributeWallClockRate, dev);
-}
-
-hipError_t launch_batch_reset(void* ctl, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kWave), 0, s, static_cast<BatchCtl*>(ctl));
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_persistent(const void* descs, int nreal, int64_t total_tiles, int64_t tmax,
-                                   void* ctl, uint64_t timeout, int blocks, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_batch_persistent, dim3(blocks), dim3(kBlock), 0, s,
-                       static_cast<const BatchDesc*>(descs), nreal, total_tiles, tmax,
-                       static_cast<BatchCtl*>(ctl), timeout);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_step(const void* descs, int nreal, int64_t total_tiles, int64_t t, hipStream_t s)
-{
-    const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(k_batch_step, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                       static_cast<const BatchDesc*>(descs), nreal, total_tiles, t);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int rb = (nreal + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(k_batch_records, dim3(rb), dim3(kBlock), 0, s, static_cast<const BatchDesc*>(descs),
-                       nreal, t);
-    return hipGetLastError();
 }
 
 hipError_t launch_zero_f32(float* v, int64_t count, hipStream_t s)
@@ -764,7 +375,6 @@ hipError_t launch_zero_f32(float* v, int64_t count, hipStream_t s)
     return hipGetLastError();
 }
 
-int batch_ctl_bytes() { return (int)sizeof(BatchCtl); }
 
 
 int64_t tb_owned_width(int vec, int T)

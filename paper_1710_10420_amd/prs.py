@@ -684,7 +684,7 @@ class Batch:
     specs: list of dicts with keys shape, deta, nsteps and optionally m, W0,
     alpha, beta, dx, eta0, diag_every, seed (the initial field is drawn from
     the seed at every run, dphi = 0) and precision (PRS_F32 or PRS_F64;
-    float64 items and beta != 0 run in the stream modes)."""
+    float64 items run in the stream modes)."""
 
     def __init__(self, specs, device="cuda", stream=None):
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)

@@ -1,9 +1,10 @@
 """Batched ensemble: every realisation inside the batch reproduces the same
 realisation run alone (fields, counts and records bit for bit with the same
 tiling and steps per pass), for uneven sizes, dimensions, eras and step
-counts, in every launch mode (persistent kernel with and without a graph, one
-launch per phase, concurrent streams with and without a graph), across graph
-replays and mode switches."""
+counts, in every launch mode (the persistent kernel in one launch with and
+without a graph and in one launch per phase, concurrent streams with and
+without a graph), across graph replays and mode switches; and every member's
+evolved field against the oracle's run of the same realisation."""
 import numpy as np
 import pytest
 
@@ -188,20 +189,97 @@ def test_stream_modes_wide_settings(singles_wide, mode):
     b.close()
 
 
-def test_persistent_modes_reject_stream_only_settings():
+# Multi-step settings of the persistent kernel: 2D eight-, six-, four- and
+# three-step passes (records on and off pass boundaries, ragged tiles), and
+# 3D LDS-staged passes of four and three steps with workgroups of eight
+# waves of 2 or 4 rows, next to 3D single steps.
+SPECS_PK = [
+    dict(shape=(256, 256), deta=0.25, m=0.5, W0=5.0, nsteps=70, diag_every=16, seed=3000, T=8),
+    dict(shape=(300, 70), deta=0.25, m=1.0, W0=10.0, nsteps=45, diag_every=10, seed=3001, T=8),
+    dict(shape=(200, 96), deta=0.25, m=2.0, W0=10.0, nsteps=40, diag_every=0, seed=3002, T=6),
+    dict(shape=(128, 100), deta=0.25, m=1.0, W0=5.0, nsteps=29, diag_every=7, seed=3003, T=4),
+    dict(shape=(96, 90), deta=0.25, m=1.0, W0=10.0, nsteps=23, diag_every=9, seed=3004, T=3),
+    dict(shape=(64, 64, 64), deta=0.2, m=0.5, W0=10.0, nsteps=33, diag_every=12, seed=3005, T=4),
+    dict(shape=(40, 30, 20), deta=0.2, m=1.0, W0=5.0, nsteps=25, diag_every=5, seed=3006, T=3),
+    dict(shape=(48, 56, 40), deta=0.2, m=1.0, W0=10.0, nsteps=19, diag_every=6, seed=3007, T=4),
+    dict(shape=(32, 32, 24), deta=0.2, m=2.0, W0=5.0, nsteps=11, diag_every=4, seed=3008, T=1),
+    dict(shape=(33, 17), deta=0.25, m=1.0, W0=5.0, nsteps=0, diag_every=4, seed=3009, T=8),
+]
+TILINGS_PK = [(2, 16, 1), (2, 8, 1), (1, 32, 1), (4, 16, 1), (4, 8, 1), (1, 16, 8), (1, 8, 16), (1, 12, 8),
+              (2, 8, 1), (1, 8, 1)]
+
+
+@pytest.fixture(scope="module")
+def singles_pk():
     prs = gpu_prs()
-    b = prs.Batch(SPECS_WIDE[:3])
-    b.set_tiling(0, 1, 16, 1)
+    out = []
+    for sp, t in zip(SPECS_PK, TILINGS_PK):
+        say("single", sp["shape"], sp["nsteps"], t, steps_per_pass(sp))
+        out.append(single_run(prs, sp, t))
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_persistent_multi_step_settings(singles_pk, mode):
+    """The persistent kernel with multi-step passes (2D up to eight steps,
+    3D LDS-staged passes up to four): every realisation bit for bit its
+    single run, records included, across graph replays."""
+    say("persistent batch mode", mode)
+    prs = gpu_prs()
+    b = prs.Batch(SPECS_PK)
+    for r, t in enumerate(TILINGS_PK):
+        b.set_tiling(r, *t)
+        b.set_time_blocking(r, steps_per_pass(SPECS_PK[r]))
+    b.set_mode(mode)
+    for rep in range(3):
+        recs = b.run()
+        for r in range(len(SPECS_PK)):
+            phi, dphi = b.final_state(r)
+            s_phi, s_dphi, s_recs = singles_pk[r]
+            np.testing.assert_array_equal(host(phi), s_phi)
+            np.testing.assert_array_equal(host(dphi), s_dphi)
+            if SPECS_PK[r]["diag_every"] > 0:
+                assert recs[r] == s_recs, (mode, rep, r)
+            else:
+                assert recs[r] == s_recs[-1:], (mode, rep, r)
+    b.close()
+
+
+def test_persistent_modes_reject_other_settings():
+    """Settings the persistent kernel holds no code for are refused before
+    any launch, naming the item: 2D vec 4 beyond four steps per pass, the
+    one-wave 3D tilings with ty 2 or 4, 3D ty 16 at four steps per pass and
+    float64 items."""
+    prs = gpu_prs()
+    b = prs.Batch(SPECS_WIDE[:4])
+    b.set_mode(prs.PRS_BATCH_PERSISTENT)
+    b.set_tiling(0, 4, 16, 1)
+    b.set_time_blocking(0, 8)
+    with pytest.raises(prs.PRSError) as e:
+        b.run()
+    assert e.value.status == prs.PRS_EINVAL and "item 0" in str(e.value)
     b.set_time_blocking(0, 4)
+    b.set_tiling(2, 2, 16, 2)
+    b.set_time_blocking(2, 1)
+    with pytest.raises(prs.PRSError) as e:
+        b.run()
+    assert e.value.status == prs.PRS_EINVAL and "item 2" in str(e.value)
+    b.set_tiling(2, 1, 8, 16)
+    b.set_time_blocking(2, 4)
+    with pytest.raises(prs.PRSError) as e:
+        b.run()
+    assert e.value.status == prs.PRS_EINVAL and "item 2" in str(e.value)
+    b.set_time_blocking(2, 3)
+    b.set_tiling(3, 1, 8, 8)
+    b.set_time_blocking(3, 4)
+    b.run()
+    b.close()
+    f64 = [dict(SPECS_WIDE[0], precision=prs.PRS_F64)]
+    b = prs.Batch(f64)
     b.set_mode(prs.PRS_BATCH_PERSISTENT)
     with pytest.raises(prs.PRSError) as e:
         b.run()
     assert e.value.status == prs.PRS_EINVAL and "item 0" in str(e.value)
-    b.set_time_blocking(0, 2)
-    b.set_tiling(2, 2, 16, 2)
-    with pytest.raises(prs.PRSError) as e:
-        b.run()
-    assert e.value.status == prs.PRS_EINVAL and "item 2" in str(e.value)
     b.close()
 
 

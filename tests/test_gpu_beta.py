@@ -142,10 +142,13 @@ def test_beta_stability_checked_before_launch():
     sim.step_n(10)                                              # eta 1 -> 3.5 is stable
 
 
-def test_beta_batch_stream_mode():
-    """A physical-force realisation in an ensemble (stream mode) equals the
-    same run alone; the persistent modes refuse it."""
-    say("beta batch")
+@pytest.mark.parametrize("mode", ["STREAMS", "PERSISTENT", "PERSISTENT_GRAPH", "PER_STEP"])
+def test_beta_batch_modes(mode):
+    """A physical-force realisation in an ensemble equals the same run alone
+    (fields and records bit for bit), in the stream mode and in the
+    persistent kernel, whose per-step coefficient table carries the force's
+    a^beta factor."""
+    say("beta batch", mode)
     prs = gpu_prs()
     specs = [dict(shape=(128, 96), deta=0.1, m=1.0, W0=10.0, nsteps=31, diag_every=5, seed=3),
              dict(shape=(96, 64), deta=0.1, m=1.0, W0=10.0, nsteps=17, diag_every=4, seed=4)]
@@ -159,7 +162,7 @@ def test_beta_batch_stream_mode():
         b.set_tiling(r, *sim.tiling())
         b.set_time_blocking(r, sim.time_blocking())
         sims.append(sim)
-    b.set_mode(prs.PRS_BATCH_STREAMS)
+    b.set_mode(getattr(prs, "PRS_BATCH_" + mode))
     recs = b.run()
     for r, sp in enumerate(specs):
         srecs = sims[r].step_n(sp["nsteps"])
@@ -167,8 +170,4 @@ def test_beta_batch_stream_mode():
         phi, _ = b.final_state(r)
         np.testing.assert_array_equal(host(phi), host(sims[r].state()[0]))
         assert recs[r] == srecs
-    b.set_mode(prs.PRS_BATCH_PERSISTENT)
-    with pytest.raises(prs.PRSError) as e:
-        b.run()
-    assert e.value.status == prs.PRS_EINVAL
     b.close()
