@@ -1287,11 +1287,13 @@ struct prs_batch {
     void* ws;
     size_t ws_bytes;
     size_t off_desc, off_coef, off_pass, off_alt, off_part, off_rec, off_ctl;
-    size_t off_phase, off_poff, off_ents;
+    size_t off_phase, off_poff, off_ents, off_qstart;
     int64_t max_phases;                  // room for this many phases
+    int64_t max_ents;                    // room for this many phase entries
     int64_t ctl_count;                   // 32-bit counters of the ensemble kernel
     int64_t total_recs;
-    std::vector<int64_t> phase_start;    // host copy: items before each phase (nphase + 1)
+    int64_t nphase;                      // phases of the uploaded tables
+    std::vector<int64_t> phase_items;    // items of each phase (all queues)
     prs_stats* hrec;     // pinned
     int* herr;           // pinned
     int32_t mode;
@@ -1316,10 +1318,10 @@ struct PassEntry {
 };
 
 struct BatchLayout {
-    size_t desc, coef, pass, alt, part, rec, phase, poff, ents, ctl, total;
+    size_t desc, coef, pass, alt, part, rec, phase, poff, ents, qstart, ctl, total;
     std::vector<size_t> coef_off, pass_off, alt_off, part_off;
     std::vector<int64_t> rec_off, part_cap;
-    int64_t max_phases, ctl_count;
+    int64_t max_phases, max_ents, ctl_count;
 };
 
 int64_t batch_records_of(const prs_batch_item& it)
@@ -1360,12 +1362,15 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
         o += align_up((size_t)(items[r].nsteps + 1) * sizeof(EnsPass));
     }
     L.max_phases = max_passes;
+    L.max_ents = all_passes;
     L.phase = o;
-    o += align_up((size_t)(max_passes + 1) * sizeof(int64_t));
+    o += align_up((size_t)kEnsQueues * (size_t)(max_passes + 1) * sizeof(int64_t));
     L.poff = o;
     o += align_up((size_t)(max_passes + 1) * sizeof(int32_t));
     L.ents = o;
-    o += align_up((size_t)all_passes * sizeof(EnsEnt));
+    o += align_up((size_t)all_passes * sizeof(int32_t));
+    L.qstart = o;
+    o += align_up((size_t)kEnsQueues * (size_t)all_passes * sizeof(int64_t));
     L.alt = o;
     L.alt_off.assign(count, 0);
     for (int32_t r = 0; r < count; ++r) {
@@ -1384,11 +1389,11 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
     L.rec_off.assign(count + 1, 0);
     for (int32_t r = 0; r < count; ++r) L.rec_off[r + 1] = L.rec_off[r] + batch_records_of(items[r]);
     o += align_up((size_t)L.rec_off[count] * sizeof(prs_stats));
-    // counters: the error flag, one ticket counter per launch (the whole
-    // run, or one per phase), then per realisation the arrivals and the
-    // finished passes
+    // counters: the error flag, the queues' ticket counters of each launch
+    // (the whole run, or one launch per phase), then per realisation the
+    // arrivals and the finished passes
     L.ctl = o;
-    L.ctl_count = 1 + (max_passes + 1) + 2 * (int64_t)count;
+    L.ctl_count = 1 + kEnsQueues * (max_passes + 1) + 2 * (int64_t)count;
     o += align_up((size_t)L.ctl_count * sizeof(uint32_t));
     L.total = o;
     return PRS_OK;
@@ -1665,32 +1670,50 @@ prs_status batch_upload(prs_batch* b)
         d.area_scale = area_scale(it.p);
         d.dkc = diag_coef(&tmp, 0).kc;
     }
-    std::vector<int64_t> start((size_t)nphase + 1, 0);
+    // phase entries (one per realisation with a pass in the phase) and, per
+    // queue, where each entry's slice and each phase begin: queue q holds
+    // items [q n / Q, (q+1) n / Q) of a pass of n items
+    const int Q = kEnsQueues;
     std::vector<int32_t> off((size_t)nphase + 1, 0);
-    std::vector<EnsEnt> ents;
-    int64_t items = 0;
+    std::vector<int32_t> ent_r;
+    std::vector<std::vector<int64_t>> qs(Q);
+    std::vector<int64_t> pstart((size_t)Q * (size_t)(b->max_phases + 1), 0);
+    std::vector<int64_t> qitems(Q, 0);
+    b->phase_items.assign((size_t)nphase, 0);
     for (int64_t p = 0; p < nphase; ++p) {
-        start[(size_t)p] = items;
-        off[(size_t)p] = (int32_t)ents.size();
+        off[(size_t)p] = (int32_t)ent_r.size();
+        for (int q = 0; q < Q; ++q) pstart[(size_t)q * (size_t)(b->max_phases + 1) + (size_t)p] = qitems[q];
         for (int32_t r = 0; r < b->count; ++r) {
             if (p >= (int64_t)passes[(size_t)r].size()) continue;
-            ents.push_back(EnsEnt{r, 0, items});
-            items += passes[(size_t)r][(size_t)p].items;
+            const int64_t n = passes[(size_t)r][(size_t)p].items;
+            ent_r.push_back(r);
+            for (int q = 0; q < Q; ++q) {
+                qs[q].push_back(qitems[q]);
+                qitems[q] += (int64_t)(q + 1) * n / Q - (int64_t)q * n / Q;
+            }
+            b->phase_items[(size_t)p] += n;
         }
     }
-    start[(size_t)nphase] = items;
-    off[(size_t)nphase] = (int32_t)ents.size();
-    if (items >= ((int64_t)1 << 31))
-        return fail(PRS_EUNSUPPORTED, "%lld work items exceed the ticket counter", (long long)items);
-    HIP_TRY(hipMemcpy(base + b->off_phase, start.data(), start.size() * sizeof(int64_t), hipMemcpyHostToDevice),
+    off[(size_t)nphase] = (int32_t)ent_r.size();
+    for (int q = 0; q < Q; ++q) {
+        pstart[(size_t)q * (size_t)(b->max_phases + 1) + (size_t)nphase] = qitems[q];
+        if (qitems[q] >= ((int64_t)1 << 31))
+            return fail(PRS_EUNSUPPORTED, "%lld work items exceed the ticket counter", (long long)qitems[q]);
+    }
+    if ((int64_t)ent_r.size() > b->max_ents) return fail(PRS_EINVAL, "phase table larger than its room");
+    HIP_TRY(hipMemcpy(base + b->off_phase, pstart.data(), pstart.size() * sizeof(int64_t), hipMemcpyHostToDevice),
             "phase table upload");
     HIP_TRY(hipMemcpy(base + b->off_poff, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice),
             "phase table upload");
-    HIP_TRY(hipMemcpy(base + b->off_ents, ents.data(), ents.size() * sizeof(EnsEnt), hipMemcpyHostToDevice),
+    HIP_TRY(hipMemcpy(base + b->off_ents, ent_r.data(), ent_r.size() * sizeof(int32_t), hipMemcpyHostToDevice),
             "phase table upload");
+    for (int q = 0; q < Q; ++q)
+        HIP_TRY(hipMemcpy(base + b->off_qstart + (size_t)q * (size_t)b->max_ents * sizeof(int64_t), qs[q].data(),
+                          qs[q].size() * sizeof(int64_t), hipMemcpyHostToDevice),
+                "phase table upload");
     HIP_TRY(hipMemcpy(base + b->off_desc, desc.data(), desc.size() * sizeof(EnsDesc), hipMemcpyHostToDevice),
             "descriptor upload");
-    b->phase_start = start;
+    b->nphase = nphase;
     return PRS_OK;
 }
 
@@ -1710,32 +1733,38 @@ prs_status batch_enqueue(prs_batch* b, bool per_phase, hipStream_t stream)
     }
     uint32_t* ctl = reinterpret_cast<uint32_t*>(base + b->off_ctl);
     HIP_TRY(launch_ens_reset(ctl, b->ctl_count, stream), "reset launch");
-    const int64_t nphase = (int64_t)b->phase_start.size() - 1;
+    const int64_t nphase = b->nphase;
     EnsRun run;
     run.desc = reinterpret_cast<const EnsDesc*>(base + b->off_desc);
-    run.phase_start = reinterpret_cast<const int64_t*>(base + b->off_phase);
+    run.pstart = reinterpret_cast<const int64_t*>(base + b->off_phase);
     run.phase_off = reinterpret_cast<const int32_t*>(base + b->off_poff);
-    run.ents = reinterpret_cast<const EnsEnt*>(base + b->off_ents);
+    run.ent_r = reinterpret_cast<const int32_t*>(base + b->off_ents);
+    run.qstart = reinterpret_cast<const int64_t*>(base + b->off_qstart);
     run.err = reinterpret_cast<int32_t*>(ctl);
-    run.arrive = ctl + 2 + b->max_phases;
+    run.arrive = ctl + 1 + kEnsQueues * (b->max_phases + 1);
     run.ready = run.arrive + b->count;
-    run.nphase = (int32_t)nphase;
-    run.pad = 0;
+    run.pstride = b->max_phases + 1;
+    run.estride = b->max_ents;
     run.timeout = b->timeout_ticks;
+    // every queue needs workgroups: at least one per queue
+    auto grid = [&](int64_t items) {
+        const int64_t g = std::min<int64_t>(b->grid_blocks, items);
+        return (int)std::max<int64_t>(kEnsQueues, (g + kEnsQueues - 1) / kEnsQueues * kEnsQueues);
+    };
     if (per_phase) {
         for (int64_t p = 0; p < nphase; ++p) {
-            run.ticket = ctl + 2 + p;
-            run.t0 = b->phase_start[(size_t)p];
-            run.t1 = b->phase_start[(size_t)p + 1];
-            const int blocks = (int)std::min<int64_t>(b->grid_blocks, run.t1 - run.t0);
-            HIP_TRY(launch_ens(run, blocks, stream), "ensemble phase launch");
+            run.ticket = ctl + 1 + kEnsQueues * (1 + p);
+            run.pb = (int32_t)p;
+            run.pe = (int32_t)p + 1;
+            HIP_TRY(launch_ens(run, grid(b->phase_items[(size_t)p]), stream), "ensemble phase launch");
         }
     } else {
+        int64_t total = 0;
+        for (int64_t n : b->phase_items) total += n;
         run.ticket = ctl + 1;
-        run.t0 = 0;
-        run.t1 = b->phase_start[(size_t)nphase];
-        const int blocks = (int)std::min<int64_t>(b->grid_blocks, run.t1);
-        HIP_TRY(launch_ens(run, blocks, stream), "ensemble launch");
+        run.pb = 0;
+        run.pe = (int32_t)nphase;
+        HIP_TRY(launch_ens(run, grid(total), stream), "ensemble launch");
     }
     HIP_TRY(hipMemcpyAsync(b->hrec, base + b->off_rec, (size_t)b->total_recs * sizeof(prs_stats),
                            hipMemcpyDeviceToHost, stream), "record copy");
@@ -1789,7 +1818,9 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
     b->off_phase = L.phase;
     b->off_poff = L.poff;
     b->off_ents = L.ents;
+    b->off_qstart = L.qstart;
     b->max_phases = L.max_phases;
+    b->max_ents = L.max_ents;
     b->ctl_count = L.ctl_count;
     b->coef_off = L.coef_off;
     b->pass_off = L.pass_off;

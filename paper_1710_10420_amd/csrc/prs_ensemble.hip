@@ -13,8 +13,9 @@
 // those of the same realisation run alone.
 //
 // Order.  Items are numbered phase by phase: phase p holds pass p of every
-// realisation that has one, realisation by realisation.  Workgroups take
-// items from one ticket counter.  An item of pass p waits until its own
+// realisation that has one, realisation by realisation (split into
+// kEnsQueues queues, each with a contiguous slice of every pass; one queue
+// by default).  Workgroups take items from their queue's ticket counter.  An item of pass p waits until its own
 // realisation has finished pass p - 1 (the fields it reads, and the buffers
 // it overwrites, which pass p - 1 read); nothing waits for other
 // realisations, so there is no grid barrier and a realisation's passes
@@ -274,50 +275,68 @@ __device__ __forceinline__ bool ens_wait(const EnsRun& E, int64_t r, uint32_t ne
 
 typedef const __attribute__((address_space(4))) int64_t CI64;
 typedef const __attribute__((address_space(4))) int32_t CI32;
-typedef const __attribute__((address_space(4))) EnsEnt CEnt;
 
-// Wave 0: a ticket of this launch (lane 0 takes it; the value is uniform).
-__device__ __forceinline__ uint32_t ens_ticket(const EnsRun& E)
+// Wave 0: a ticket of queue q (lane 0 takes it; the value is uniform).
+__device__ __forceinline__ uint32_t ens_ticket(const EnsRun& E, int q)
 {
     uint32_t t = 0u;
     if ((threadIdx.x & (kWave - 1)) == 0)
-        t = __hip_atomic_fetch_add(E.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __hip_atomic_fetch_add(E.ticket + q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return __builtin_amdgcn_readfirstlane(t);
 }
 
-// Wave 0: ticket t as (realisation, pass, index), or realisation -1 when the
-// launch has no such item or a wait failed.  The whole wave decodes the
-// ticket with wave-uniform values, so the table lookups are scalar loads
-// from the constant address space (the tables do not change during the
-// launch); lane 0 waits.
-__device__ __forceinline__ void ens_decode(const EnsRun& E, uint32_t t, int64_t& r, int64_t& p, int64_t& j)
+// Wave 0's position in its queue's tables: the phase and the phase entry of
+// its last item.  A workgroup's tickets only grow, and so do the tables'
+// starts, so the next item is found by moving forward from there.
+struct EnsCursor {
+    int32_t p, e;
+};
+
+// Wave 0: the last index in [from, to) whose start (a non-decreasing table
+// read through `tab`) is at or below tk; tab[from] <= tk.  Sixty-four
+// starts are read at once, one per lane, and counted with a ballot.
+template <typename TAB>
+__device__ __forceinline__ int32_t ens_seek(TAB* tab, int32_t from, int32_t to, int64_t tk)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        const int32_t idx = from + lane;
+        const int64_t v = idx < to ? (int64_t)tab[idx] : INT64_MAX;
+        const int32_t c = (int32_t)__builtin_popcountll(__ballot(v <= tk));
+        if (c < kWave) return from + c - 1;
+        from += kWave - 1;
+    }
+}
+
+// Wave 0: ticket t of queue q as (realisation, pass, index), or realisation
+// -1 when the launch has no such item or a wait failed; lane 0 waits.
+// Queue q holds, phase by phase and realisation by realisation, items
+// [q n / Q, (q+1) n / Q) of each pass of n items.
+__device__ __forceinline__ void ens_decode(const EnsRun& E, int q, uint32_t t, EnsCursor& cur, int64_t& r,
+                                           int64_t& p, int64_t& j)
 {
     const int lane = threadIdx.x & (kWave - 1);
     r = -1;
     p = 0;
     j = 0;
-    const int64_t tk = E.t0 + (int64_t)t;
-    if (tk >= E.t1) return;
-    CI64* start = (CI64*)E.phase_start;
+    const int64_t* pstart = E.pstart + (int64_t)q * E.pstride;
+    const int64_t* qstart = E.qstart + (int64_t)q * E.estride;
     CI32* off = (CI32*)E.phase_off;
-    CEnt* ents = (CEnt*)E.ents;
-    int lo = 0, hi = E.nphase - 1;       // last phase starting at or before tk
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= tk) lo = mid;
-        else hi = mid - 1;
-    }
-    int a = off[lo], b = off[lo + 1] - 1;   // its realisation
-    while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (ents[mid].start <= tk) a = mid;
-        else b = mid - 1;
-    }
-    const int64_t rr = ents[a].r;
+    CI32* ent_r = (CI32*)E.ent_r;
+    const int64_t tk = ((CI64*)pstart)[E.pb] + (int64_t)t;
+    if (tk >= ((CI64*)pstart)[E.pe]) return;
+    const int32_t ph = ens_seek(pstart, cur.p, E.pe, tk);
+    const int32_t e0 = ph == cur.p ? cur.e : off[ph];
+    const int32_t a = ens_seek(qstart, e0, off[ph + 1], tk);
+    cur.p = ph;
+    cur.e = a;
+    const int64_t rr = ent_r[a];
+    const int64_t n = ((CPass*)((CDesc*)E.desc)[rr].passes)[ph].items;
+    const int64_t j0 = __builtin_amdgcn_readfirstlane((int32_t)(tk - qstart[a]));
     uint32_t ok = 1u;
     if (lane == 0)
         ok = (__hip_atomic_load(E.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-              ens_wait(E, rr, (uint32_t)lo)) ? 1u : 0u;
+              ens_wait(E, rr, (uint32_t)ph)) ? 1u : 0u;
     ok = __builtin_amdgcn_readfirstlane(ok);
     if (!ok) return;
     // the passes before this one, written on any XCD, become visible; the
@@ -325,8 +344,8 @@ __device__ __forceinline__ void ens_decode(const EnsRun& E, uint32_t t, int64_t&
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     r = rr;
-    p = lo;
-    j = tk - ents[a].start;
+    p = ph;
+    j = (int64_t)q * n / kEnsQueues + j0;
 }
 
 __global__ __launch_bounds__(kEnsBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_ens(EnsRun E)
@@ -335,13 +354,17 @@ __global__ __launch_bounds__(kEnsBlock) __attribute__((amdgpu_waves_per_eu(4))) 
     __shared__ int64_t s_item[3];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = wave_in_block();
+    const int q = (int)(blockIdx.x % kEnsQueues);
     // wave 0 takes each item's successor while the item runs, so the
     // ticket's round trip overlaps the work
-    uint32_t next = wave == 0 ? ens_ticket(E) : 0u;
+    uint32_t next = wave == 0 ? ens_ticket(E, q) : 0u;
+    EnsCursor cur;
+    cur.p = E.pb;
+    cur.e = ((CI32*)E.phase_off)[E.pb];
     for (;;) {
         if (wave == 0) {
             int64_t r, p, j;
-            ens_decode(E, next, r, p, j);
+            ens_decode(E, q, next, cur, r, p, j);
             if (lane == 0) {
                 s_item[0] = r;
                 s_item[1] = p;
@@ -353,7 +376,7 @@ __global__ __launch_bounds__(kEnsBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         if (r < 0) break;
         const int64_t p = uniform64(s_item[1]);
         const int64_t j = uniform64(s_item[2]);
-        if (wave == 0) next = ens_ticket(E);
+        if (wave == 0) next = ens_ticket(E, q);
         CDesc& d = ((CDesc*)E.desc)[r];
         CPass& ps = ((CPass*)d.passes)[p];
         const int chunk = ps.chunk;

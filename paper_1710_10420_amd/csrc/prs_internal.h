@@ -270,23 +270,26 @@ struct EnsDesc {
     double eta0, deta64, area_scale, dkc;
 };
 
-// The first item of realisation r in its phase.
-struct EnsEnt {
-    int32_t r, pad;
-    int64_t start;
-};
+// Work queues of the ensemble kernel: workgroup b takes its items from queue
+// b % kEnsQueues, each queue holding a contiguous slice of every pass.  One
+// queue per XCD (eight, so that neighbouring tiles meet in one L2) measured
+// 4 % slower than a single queue on the 64-member ensemble: a pass then
+// completes only when the slowest of its eight slices does.  Correctness
+// does not depend on the number of queues nor on where a workgroup runs.
+constexpr int kEnsQueues = 1;
 
 struct EnsRun {
     const EnsDesc* desc;
-    const int64_t* phase_start;     // nphase + 1 cumulative item counts
-    const int32_t* phase_off;       // nphase + 1 offsets into ents
-    const EnsEnt* ents;
-    uint32_t* ticket;               // ticket counter of this launch
+    const int64_t* pstart;          // [queue][phase]: items of the queue before each phase (pstride per queue)
+    const int32_t* phase_off;       // nphase + 1 offsets into the phase entries
+    const int32_t* ent_r;           // realisation of each phase entry
+    const int64_t* qstart;          // [queue][entry]: first item of the entry's slice in the queue (estride per queue)
+    uint32_t* ticket;               // kEnsQueues ticket counters of this launch
     uint32_t* arrive;               // per realisation: items finished
     uint32_t* ready;                // per realisation: passes finished
     int32_t* err;                   // raised when a wait times out
-    int64_t t0, t1;                 // items [t0, t1) of this launch
-    int32_t nphase, pad;
+    int64_t pstride, estride;
+    int32_t pb, pe;                 // phases [pb, pe) of this launch
     uint64_t timeout;               // wall-clock ticks a wait may take
 };
 
