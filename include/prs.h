@@ -429,12 +429,15 @@ typedef struct prs_batch prs_batch;
  * loaded stream (the default); STREAMS_GRAPH captures that launch sequence
  * once in a hipGraph and replays it.  The PERSISTENT modes run the whole
  * ensemble inside one launch of a persistent kernel: the passes are cut into
- * work items (eight wave tiles, or one workgroup tile of a 3D LDS-staged
- * pass) numbered phase by phase (phase p: pass p of every realisation), the
- * workgroups take items from one counter, and an item waits only until its
- * own realisation has finished the previous pass (per-realisation counters,
- * no grid barrier); the workgroup finishing a recorded pass reduces its
- * record.  They run float32 items with, in 2D, ty 1 and vec 1 or 2 (up to 8
+ * work items (one to four wave tiles per wave of an 8-wave workgroup, or
+ * workgroup tiles of a 3D LDS-staged pass), the realisations are dealt,
+ * longest first, onto 16 sequences that each run their realisations' passes
+ * one after another, the items are numbered round by round (round k: the
+ * k-th pass of every sequence) and the workgroups take them from one
+ * counter; an item waits only until its own realisation has finished the
+ * previous pass (per-realisation counters, no grid barrier), and the
+ * workgroup finishing a recorded pass reduces its record.  PER_STEP launches
+ * the same kernel once per phase (phase p: pass p of every realisation).  They run float32 items with, in 2D, ty 1 and vec 1 or 2 (up to 8
  * steps per pass) or vec 4 (up to 4), and in 3D single steps with ty 1, or
  * vec 1 with ty 8 (up to 4 steps per pass) or ty 16 (up to 3). */
 #define PRS_BATCH_PERSISTENT_GRAPH 0  /* one persistent launch, captured in a hipGraph */

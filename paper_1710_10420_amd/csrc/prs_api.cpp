@@ -1287,13 +1287,15 @@ struct prs_batch {
     void* ws;
     size_t ws_bytes;
     size_t off_desc, off_coef, off_pass, off_alt, off_part, off_rec, off_ctl;
-    size_t off_phase, off_poff, off_ents, off_qstart;
-    int64_t max_phases;                  // room for this many phases
-    int64_t max_ents;                    // room for this many phase entries
+    size_t off_phase, off_poff, off_ents, off_entp, off_qstart;
+    int64_t max_phases;                  // room for this many ticket counters of per-phase launches
+    int64_t max_rounds;                  // room for this many rounds in the tables
+    int64_t max_ents;                    // room for this many round entries
+    int32_t tables_seq;                  // sequences the uploaded tables were built with (-1: none)
     int64_t ctl_count;                   // 32-bit counters of the ensemble kernel
     int64_t total_recs;
-    int64_t nphase;                      // phases of the uploaded tables
-    std::vector<int64_t> phase_items;    // items of each phase (all queues)
+    int64_t nphase;                      // rounds of the uploaded tables
+    std::vector<int64_t> phase_items;    // items of each round (all queues)
     prs_stats* hrec;     // pinned
     int* herr;           // pinned
     int32_t mode;
@@ -1318,10 +1320,10 @@ struct PassEntry {
 };
 
 struct BatchLayout {
-    size_t desc, coef, pass, alt, part, rec, phase, poff, ents, qstart, ctl, total;
+    size_t desc, coef, pass, alt, part, rec, phase, poff, ents, entp, qstart, ctl, total;
     std::vector<size_t> coef_off, pass_off, alt_off, part_off;
     std::vector<int64_t> rec_off, part_cap;
-    int64_t max_phases, max_ents, ctl_count;
+    int64_t max_phases, max_rounds, max_ents, ctl_count;
 };
 
 int64_t batch_records_of(const prs_batch_item& it)
@@ -1362,12 +1364,15 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
         o += align_up((size_t)(items[r].nsteps + 1) * sizeof(EnsPass));
     }
     L.max_phases = max_passes;
+    L.max_rounds = all_passes;
     L.max_ents = all_passes;
     L.phase = o;
-    o += align_up((size_t)kEnsQueues * (size_t)(max_passes + 1) * sizeof(int64_t));
+    o += align_up((size_t)kEnsQueues * (size_t)(all_passes + 1) * sizeof(int64_t));
     L.poff = o;
-    o += align_up((size_t)(max_passes + 1) * sizeof(int32_t));
+    o += align_up((size_t)(all_passes + 1) * sizeof(int32_t));
     L.ents = o;
+    o += align_up((size_t)all_passes * sizeof(int32_t));
+    L.entp = o;
     o += align_up((size_t)all_passes * sizeof(int32_t));
     L.qstart = o;
     o += align_up((size_t)kEnsQueues * (size_t)all_passes * sizeof(int64_t));
@@ -1393,7 +1398,7 @@ prs_status batch_layout(const prs_batch_item* items, int32_t count, BatchLayout&
     // (the whole run, or one launch per phase), then per realisation the
     // arrivals and the finished passes
     L.ctl = o;
-    L.ctl_count = 1 + kEnsQueues * (max_passes + 1) + 2 * (int64_t)count;
+    L.ctl_count = (1 + kEnsQueues * (max_passes + 1) + 2 * (int64_t)count) * kCtlStride;
     o += align_up((size_t)L.ctl_count * sizeof(uint32_t));
     L.total = o;
     return PRS_OK;
@@ -1598,7 +1603,7 @@ prs_status batch_enqueue_streams(prs_batch* b, hipStream_t main)
 // plan with each pass's tile grid and work items, and its descriptor; then
 // the phase tables that number the items (phase p: pass p of every
 // realisation that has one, realisation by realisation).
-prs_status batch_upload(prs_batch* b)
+prs_status batch_upload(prs_batch* b, int32_t nseq)
 {
     char* base = static_cast<char*>(b->ws);
     std::vector<EnsDesc> desc((size_t)b->count);
@@ -1670,33 +1675,63 @@ prs_status batch_upload(prs_batch* b)
         d.area_scale = area_scale(it.p);
         d.dkc = diag_coef(&tmp, 0).kc;
     }
-    // phase entries (one per realisation with a pass in the phase) and, per
-    // queue, where each entry's slice and each phase begin: queue q holds
-    // items [q n / Q, (q+1) n / Q) of a pass of n items
+    // The order of the items: the realisations are dealt, longest first
+    // (sites x steps), onto nseq sequences (the least loaded first; nseq = 0:
+    // one sequence per realisation), a sequence runs its realisations' passes
+    // one after another, and round k holds the k-th pass of every sequence.
+    // With one sequence per realisation round k is phase k (pass k of every
+    // realisation); with a few sequences only a few realisations are active
+    // at a time, as on concurrent streams.  Per queue, where each entry's
+    // slice and each round begin: queue q holds items [q n / Q, (q+1) n / Q)
+    // of a pass of n items.
+    const int32_t S = nseq > 0 ? std::min<int32_t>(nseq, b->count) : b->count;
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> seq((size_t)S);
+    {
+        std::vector<int32_t> order((size_t)b->count);
+        for (int32_t r = 0; r < b->count; ++r) order[(size_t)r] = r;
+        auto work = [&](int32_t r) { return (double)sites_of(b->items[r].p) * (double)(b->items[r].nsteps + 1); };
+        if (nseq > 0)
+            std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
+        std::vector<double> load((size_t)S, 0.0);
+        for (int32_t k = 0; k < b->count; ++k) {
+            const int32_t r = order[(size_t)k];
+            size_t sbest = (size_t)(nseq > 0 ? 0 : r);
+            if (nseq > 0)
+                for (size_t x = 1; x < (size_t)S; ++x)
+                    if (load[x] < load[sbest]) sbest = x;
+            load[sbest] += work(r);
+            for (int32_t pp = 0; pp < (int32_t)passes[(size_t)r].size(); ++pp) seq[sbest].push_back({r, pp});
+        }
+    }
+    nphase = 0;
+    for (const auto& q : seq) nphase = std::max<int64_t>(nphase, (int64_t)q.size());
+    if (nphase > b->max_rounds) return fail(PRS_EINVAL, "round table larger than its room");
     const int Q = kEnsQueues;
     std::vector<int32_t> off((size_t)nphase + 1, 0);
-    std::vector<int32_t> ent_r;
+    std::vector<int32_t> ent_r, ent_p;
     std::vector<std::vector<int64_t>> qs(Q);
-    std::vector<int64_t> pstart((size_t)Q * (size_t)(b->max_phases + 1), 0);
+    std::vector<int64_t> pstart((size_t)Q * (size_t)(b->max_rounds + 1), 0);
     std::vector<int64_t> qitems(Q, 0);
     b->phase_items.assign((size_t)nphase, 0);
-    for (int64_t p = 0; p < nphase; ++p) {
-        off[(size_t)p] = (int32_t)ent_r.size();
-        for (int q = 0; q < Q; ++q) pstart[(size_t)q * (size_t)(b->max_phases + 1) + (size_t)p] = qitems[q];
-        for (int32_t r = 0; r < b->count; ++r) {
-            if (p >= (int64_t)passes[(size_t)r].size()) continue;
-            const int64_t n = passes[(size_t)r][(size_t)p].items;
+    for (int64_t k = 0; k < nphase; ++k) {
+        off[(size_t)k] = (int32_t)ent_r.size();
+        for (int q = 0; q < Q; ++q) pstart[(size_t)q * (size_t)(b->max_rounds + 1) + (size_t)k] = qitems[q];
+        for (const auto& sq : seq) {
+            if (k >= (int64_t)sq.size()) continue;
+            const int32_t r = sq[(size_t)k].first, pp = sq[(size_t)k].second;
+            const int64_t n = passes[(size_t)r][(size_t)pp].items;
             ent_r.push_back(r);
+            ent_p.push_back(pp);
             for (int q = 0; q < Q; ++q) {
                 qs[q].push_back(qitems[q]);
                 qitems[q] += (int64_t)(q + 1) * n / Q - (int64_t)q * n / Q;
             }
-            b->phase_items[(size_t)p] += n;
+            b->phase_items[(size_t)k] += n;
         }
     }
     off[(size_t)nphase] = (int32_t)ent_r.size();
     for (int q = 0; q < Q; ++q) {
-        pstart[(size_t)q * (size_t)(b->max_phases + 1) + (size_t)nphase] = qitems[q];
+        pstart[(size_t)q * (size_t)(b->max_rounds + 1) + (size_t)nphase] = qitems[q];
         if (qitems[q] >= ((int64_t)1 << 31))
             return fail(PRS_EUNSUPPORTED, "%lld work items exceed the ticket counter", (long long)qitems[q]);
     }
@@ -1707,6 +1742,8 @@ prs_status batch_upload(prs_batch* b)
             "phase table upload");
     HIP_TRY(hipMemcpy(base + b->off_ents, ent_r.data(), ent_r.size() * sizeof(int32_t), hipMemcpyHostToDevice),
             "phase table upload");
+    HIP_TRY(hipMemcpy(base + b->off_entp, ent_p.data(), ent_p.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+            "phase table upload");
     for (int q = 0; q < Q; ++q)
         HIP_TRY(hipMemcpy(base + b->off_qstart + (size_t)q * (size_t)b->max_ents * sizeof(int64_t), qs[q].data(),
                           qs[q].size() * sizeof(int64_t), hipMemcpyHostToDevice),
@@ -1714,6 +1751,7 @@ prs_status batch_upload(prs_batch* b)
     HIP_TRY(hipMemcpy(base + b->off_desc, desc.data(), desc.size() * sizeof(EnsDesc), hipMemcpyHostToDevice),
             "descriptor upload");
     b->nphase = nphase;
+    b->tables_seq = nseq;
     return PRS_OK;
 }
 
@@ -1739,11 +1777,12 @@ prs_status batch_enqueue(prs_batch* b, bool per_phase, hipStream_t stream)
     run.pstart = reinterpret_cast<const int64_t*>(base + b->off_phase);
     run.phase_off = reinterpret_cast<const int32_t*>(base + b->off_poff);
     run.ent_r = reinterpret_cast<const int32_t*>(base + b->off_ents);
+    run.ent_p = reinterpret_cast<const int32_t*>(base + b->off_entp);
     run.qstart = reinterpret_cast<const int64_t*>(base + b->off_qstart);
     run.err = reinterpret_cast<int32_t*>(ctl);
-    run.arrive = ctl + 1 + kEnsQueues * (b->max_phases + 1);
-    run.ready = run.arrive + b->count;
-    run.pstride = b->max_phases + 1;
+    run.arrive = ctl + (1 + kEnsQueues * (b->max_phases + 1)) * kCtlStride;
+    run.ready = run.arrive + (int64_t)b->count * kCtlStride;
+    run.pstride = b->max_rounds + 1;
     run.estride = b->max_ents;
     run.timeout = b->timeout_ticks;
     // every queue needs workgroups: at least one per queue
@@ -1753,7 +1792,7 @@ prs_status batch_enqueue(prs_batch* b, bool per_phase, hipStream_t stream)
     };
     if (per_phase) {
         for (int64_t p = 0; p < nphase; ++p) {
-            run.ticket = ctl + 1 + kEnsQueues * (1 + p);
+            run.ticket = ctl + (1 + kEnsQueues * (1 + p)) * kCtlStride;
             run.pb = (int32_t)p;
             run.pe = (int32_t)p + 1;
             HIP_TRY(launch_ens(run, grid(b->phase_items[(size_t)p]), stream), "ensemble phase launch");
@@ -1761,7 +1800,7 @@ prs_status batch_enqueue(prs_batch* b, bool per_phase, hipStream_t stream)
     } else {
         int64_t total = 0;
         for (int64_t n : b->phase_items) total += n;
-        run.ticket = ctl + 1;
+        run.ticket = ctl + kCtlStride;
         run.pb = 0;
         run.pe = (int32_t)nphase;
         HIP_TRY(launch_ens(run, grid(total), stream), "ensemble launch");
@@ -1818,9 +1857,12 @@ prs_status prs_batch_create(const prs_batch_item* items, int32_t count, void* wo
     b->off_phase = L.phase;
     b->off_poff = L.poff;
     b->off_ents = L.ents;
+    b->off_entp = L.entp;
     b->off_qstart = L.qstart;
     b->max_phases = L.max_phases;
+    b->max_rounds = L.max_rounds;
     b->max_ents = L.max_ents;
+    b->tables_seq = -1;
     b->ctl_count = L.ctl_count;
     b->coef_off = L.coef_off;
     b->pass_off = L.pass_off;
@@ -1939,8 +1981,13 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
                             "with ty 8 (up to 4 steps per pass) or ty 16 (up to 3)", r);
     }
     if (b->graph_mode != b->mode) batch_release_graph(b);
-    if (b->dirty && persistent) {
-        prs_status st = batch_upload(b);
+    // the per-phase launches keep the phase order (one sequence per
+    // realisation); the one-launch modes deal the realisations onto a few
+    // sequences
+    const int32_t nseq = b->mode == PRS_BATCH_PER_STEP ? 0 : kEnsSequences;
+    if (persistent && (b->dirty || b->tables_seq != nseq)) {
+        batch_release_graph(b);
+        prs_status st = batch_upload(b, nseq);
         if (st != PRS_OK) return st;
         b->dirty = false;
     }

@@ -12,15 +12,19 @@
 // tb3l_tile, step_tile), so a realisation's fields and records are bitwise
 // those of the same realisation run alone.
 //
-// Order.  Items are numbered phase by phase: phase p holds pass p of every
-// realisation that has one, realisation by realisation (split into
-// kEnsQueues queues, each with a contiguous slice of every pass; one queue
-// by default).  Workgroups take items from their queue's ticket counter.  An item of pass p waits until its own
+// Order.  The realisations are dealt, longest first, onto a few sequences,
+// each running its realisations' passes one after another; items are
+// numbered round by round, round k holding the k-th pass of every sequence
+// (with one sequence per realisation, round p is phase p: pass p of every
+// realisation), optionally split into kEnsQueues queues with a contiguous
+// slice of every pass each (one queue by default).  Workgroups take items
+// from their queue's ticket counter.  An item of pass p waits until its own
 // realisation has finished pass p - 1 (the fields it reads, and the buffers
 // it overwrites, which pass p - 1 read); nothing waits for other
 // realisations, so there is no grid barrier and a realisation's passes
 // overlap the neighbouring phases of the others.  Every item an item waits
-// for holds an earlier ticket, taken by a workgroup that is running, so the
+// for (an earlier pass of its realisation, in an earlier round) holds an
+// earlier ticket, taken by a workgroup that is running, so the
 // wait always ends whether or not the grid is co-resident; it is still
 // bounded, and raises an error flag instead of hanging.
 //
@@ -48,6 +52,12 @@ namespace prs {
 namespace {
 
 constexpr int kEnsBlock = kEnsWaves * kWave;
+
+// Most tiles per wave (workgroup tiles in 3D LDS passes) in one work item.
+#ifndef PRS_ENS_MAX_CHUNK
+#define PRS_ENS_MAX_CHUNK 4
+#endif
+constexpr int kEnsMaxChunk = PRS_ENS_MAX_CHUNK;
 
 // The descriptors, pass tables and coefficients are read through the
 // constant address space: they do not change during a launch, and loads
@@ -206,11 +216,17 @@ __device__ __forceinline__ void ens_tb2_len(CDesc& d, CPass& ps, int64_t p, int6
     }
 }
 
-// Tile c of item j of pass p (a chunk of ps.chunk tiles per wave, or of
-// workgroup tiles in the 3D LDS pass).  Uniform across the workgroup.
-__device__ __forceinline__ void ens_tile(CDesc& d, CPass& ps, int64_t p, int64_t t, float* lds)
+// Step c of item j of pass p.  Uniform across the workgroup.  A 3D LDS
+// pass's item is ps.chunk consecutive workgroup tiles, one per step.  A 2D
+// multi-step pass's item is a block of kEnsWaves row tiles (one per wave)
+// by ps.chunk tile columns (one per step), so that the tiles above and below
+// one another, which read each other's halo rows, run side by side and meet
+// in L2.  A single step's item is ps.chunk runs of kEnsWaves consecutive
+// wave tiles.
+__device__ __forceinline__ void ens_tile(CDesc& d, CPass& ps, int64_t p, int64_t j, int c, float* lds)
 {
     const bool diag = ps.rec >= 0;
+    const int64_t t = j * ps.chunk + c;
     if (d.ndim == 3 && ps.steps > 1) {
         if (t >= ps.ntiles) return;
         if (d.ty == 8) {
@@ -229,9 +245,11 @@ __device__ __forceinline__ void ens_tile(CDesc& d, CPass& ps, int64_t p, int64_t
         }
         return;
     }
-    const int64_t w = t * kEnsWaves + wave_in_block();
-    if (w >= ps.ntiles) return;
     if (ps.steps > 1) {
+        const int64_t by = j / ps.blocks_x, bx = j - by * ps.blocks_x;
+        const int64_t ty = by * kEnsWaves + wave_in_block(), tx = bx * ps.chunk + c;
+        if (tx >= ps.tiles_x || ty * ps.tiles_x >= ps.ntiles) return;
+        const int64_t w = ty * ps.tiles_x + tx;
         switch (d.vec) {
         case 1: ens_tb2_len<1>(d, ps, p, w, diag); break;
         case 2: ens_tb2_len<2>(d, ps, p, w, diag); break;
@@ -239,6 +257,8 @@ __device__ __forceinline__ void ens_tile(CDesc& d, CPass& ps, int64_t p, int64_t
         }
         return;
     }
+    const int64_t w = t * kEnsWaves + wave_in_block();
+    if (w >= ps.ntiles) return;
     const bool update = ps.steps == 1;
     if (d.ndim == 2) {
         switch (d.vec) {
@@ -260,9 +280,9 @@ __device__ __forceinline__ void ens_tile(CDesc& d, CPass& ps, int64_t p, int64_t
 // (the error flag is then raised) or another wait already did.
 __device__ __forceinline__ bool ens_wait(const EnsRun& E, int64_t r, uint32_t need)
 {
-    if (__hip_atomic_load(E.ready + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+    if (__hip_atomic_load(E.ready + r * kCtlStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(E.ready + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    while (__hip_atomic_load(E.ready + r * kCtlStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
         if (__hip_atomic_load(E.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         if (wall_clock64() - t0 > E.timeout) {
             __hip_atomic_store(E.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -281,7 +301,7 @@ __device__ __forceinline__ uint32_t ens_ticket(const EnsRun& E, int q)
 {
     uint32_t t = 0u;
     if ((threadIdx.x & (kWave - 1)) == 0)
-        t = __hip_atomic_fetch_add(E.ticket + q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __hip_atomic_fetch_add(E.ticket + q * kCtlStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return __builtin_amdgcn_readfirstlane(t);
 }
 
@@ -310,7 +330,7 @@ __device__ __forceinline__ int32_t ens_seek(TAB* tab, int32_t from, int32_t to, 
 
 // Wave 0: ticket t of queue q as (realisation, pass, index), or realisation
 // -1 when the launch has no such item or a wait failed; lane 0 waits.
-// Queue q holds, phase by phase and realisation by realisation, items
+// Queue q holds, round by round and sequence by sequence, items
 // [q n / Q, (q+1) n / Q) of each pass of n items.
 __device__ __forceinline__ void ens_decode(const EnsRun& E, int q, uint32_t t, EnsCursor& cur, int64_t& r,
                                            int64_t& p, int64_t& j)
@@ -331,12 +351,13 @@ __device__ __forceinline__ void ens_decode(const EnsRun& E, int q, uint32_t t, E
     cur.p = ph;
     cur.e = a;
     const int64_t rr = ent_r[a];
-    const int64_t n = ((CPass*)((CDesc*)E.desc)[rr].passes)[ph].items;
+    const int32_t pp = ((CI32*)E.ent_p)[a];
+    const int64_t n = ((CPass*)((CDesc*)E.desc)[rr].passes)[pp].items;
     const int64_t j0 = __builtin_amdgcn_readfirstlane((int32_t)(tk - qstart[a]));
     uint32_t ok = 1u;
     if (lane == 0)
         ok = (__hip_atomic_load(E.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-              ens_wait(E, rr, (uint32_t)ph)) ? 1u : 0u;
+              ens_wait(E, rr, (uint32_t)pp)) ? 1u : 0u;
     ok = __builtin_amdgcn_readfirstlane(ok);
     if (!ok) return;
     // the passes before this one, written on any XCD, become visible; the
@@ -344,7 +365,7 @@ __device__ __forceinline__ void ens_decode(const EnsRun& E, int q, uint32_t t, E
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     r = rr;
-    p = ph;
+    p = pp;
     j = (int64_t)q * n / kEnsQueues + j0;
 }
 
@@ -380,7 +401,7 @@ __global__ __launch_bounds__(kEnsBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         CDesc& d = ((CDesc*)E.desc)[r];
         CPass& ps = ((CPass*)d.passes)[p];
         const int chunk = ps.chunk;
-        for (int c = 0; c < chunk; ++c) ens_tile(d, ps, p, j * chunk + c, lds);
+        for (int c = 0; c < chunk; ++c) ens_tile(d, ps, p, j, c, lds);
         // every wave waits for its own stores of the item to reach L2 (the
         // barrier alone does not), so that wave 0's release covers them all
         __builtin_amdgcn_s_waitcnt(0);
@@ -396,8 +417,8 @@ __global__ __launch_bounds__(kEnsBlock) __attribute__((amdgpu_waves_per_eu(4))) 
                 // the write-back L2, and release it first.
                 const bool coherent = ps.steps > 1 && ps.rec < 0;
                 const uint32_t old =
-                    coherent ? __hip_atomic_fetch_add(E.arrive + r, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                             : __hip_atomic_fetch_add(E.arrive + r, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    coherent ? __hip_atomic_fetch_add(E.arrive + r * kCtlStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : __hip_atomic_fetch_add(E.arrive + r * kCtlStride, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 last = (int64_t)old + 1 == ps.cum_end ? 1u : 0u;
             }
             last = __builtin_amdgcn_readfirstlane(last);
@@ -408,7 +429,7 @@ __global__ __launch_bounds__(kEnsBlock) __attribute__((amdgpu_waves_per_eu(4))) 
                     finalize_wave(d.part, ps.nparts, d.recs + ps.rec, ps.first,
                                   d.eta0 + (double)ps.first * d.deta64, d.area_scale);
                 if (lane == 0)
-                    __hip_atomic_store(E.ready + r, (uint32_t)(p + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(E.ready + r * kCtlStride, (uint32_t)(p + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -441,7 +462,7 @@ void ens_pass_grid(const Geometry& g, const Tiling& t, int L, EnsPass& ps)
         ps.tiles_q = (int32_t)tq;
         ps.ntiles = tx * tq * ((g.M + t.rows - 1) / t.rows);
         ps.nparts = ps.ntiles * kEnsWaves;
-        ps.chunk = ps.ntiles >= 1024 ? 4 : ps.ntiles >= 512 ? 2 : 1;
+        ps.chunk = std::min(kEnsMaxChunk, ps.ntiles >= 1024 ? 4 : ps.ntiles >= 512 ? 2 : 1);
         ps.items = (int32_t)((ps.ntiles + ps.chunk - 1) / ps.chunk);
         return;
     }
@@ -459,10 +480,18 @@ void ens_pass_grid(const Geometry& g, const Tiling& t, int L, EnsPass& ps)
     }
     ps.nparts = ps.ntiles;
     // large passes hand out several tiles per wave at a time, so that the
-    // cost of taking an item (a ticket, a lookup, one acquire and one
-    // release) is spread over more work; every pass still has many items
-    ps.chunk = ps.ntiles >= 8 * 4 * 64 ? 4 : ps.ntiles >= 8 * 2 * 64 ? 2 : 1;
-    ps.items = (int32_t)((ps.ntiles + kEnsWaves * ps.chunk - 1) / (kEnsWaves * ps.chunk));
+    // cost of taking an item (a ticket, a lookup, an acquire) is spread over
+    // more work; every pass still has many items
+    ps.chunk = std::min(kEnsMaxChunk, ps.ntiles >= 8 * 4 * 64 ? 4 : ps.ntiles >= 8 * 2 * 64 ? 2 : 1);
+    if (L > 1) {
+        // blocks of kEnsWaves row tiles by chunk columns
+        const int64_t rows_t = ps.ntiles / ps.tiles_x;
+        ps.blocks_x = (int32_t)((ps.tiles_x + ps.chunk - 1) / ps.chunk);
+        ps.items = (int32_t)(ps.blocks_x * ((rows_t + kEnsWaves - 1) / kEnsWaves));
+    } else {
+        ps.blocks_x = 0;
+        ps.items = (int32_t)((ps.ntiles + kEnsWaves * ps.chunk - 1) / (kEnsWaves * ps.chunk));
+    }
 }
 
 hipError_t ens_max_blocks(int* blocks)

@@ -250,6 +250,8 @@ struct EnsPass {
     int32_t tiles_x, tiles_q;   // tile grid of the pass (tiles_q: along y in 3D)
     int32_t items;      // work items of the pass
     int32_t chunk;      // tiles per wave (workgroup tiles in 3D multi-step passes) per item
+    int32_t blocks_x;   // 2D multi-step passes: items along x (an item is kEnsWaves row tiles x chunk columns)
+    int32_t pad;
     int64_t ntiles;     // wave tiles, or workgroup tiles of a 3D multi-step pass
     int64_t nparts;     // wave partials the record reduces
     int64_t cum_end;    // items of this realisation's passes up to this one
@@ -276,17 +278,37 @@ struct EnsDesc {
 // 4 % slower than a single queue on the 64-member ensemble: a pass then
 // completes only when the slowest of its eight slices does.  Correctness
 // does not depend on the number of queues nor on where a workgroup runs.
-constexpr int kEnsQueues = 1;
+#ifndef PRS_ENS_QUEUES
+#define PRS_ENS_QUEUES 1
+#endif
+constexpr int kEnsQueues = PRS_ENS_QUEUES;
+
+// Sequences the one-launch ensemble deals its realisations onto (0: one per
+// realisation, i.e. phase order: pass p of every realisation, then pass
+// p + 1).  A sequence runs its realisations' passes one after another and
+// the tickets take the sequences' passes in turn, so only about this many
+// realisations are in flight at a time.
+#ifndef PRS_ENS_SEQUENCES
+#define PRS_ENS_SEQUENCES 16
+#endif
+constexpr int kEnsSequences = PRS_ENS_SEQUENCES;
+
+// Distance in 32-bit words between the ensemble kernel's counters: one
+// 128-byte cache line each, so that atomics on different counters (the
+// tickets, each realisation's arrivals and finished passes) never queue
+// behind one another on a shared line.
+constexpr int kCtlStride = 32;
 
 struct EnsRun {
     const EnsDesc* desc;
     const int64_t* pstart;          // [queue][phase]: items of the queue before each phase (pstride per queue)
-    const int32_t* phase_off;       // nphase + 1 offsets into the phase entries
-    const int32_t* ent_r;           // realisation of each phase entry
+    const int32_t* phase_off;       // nphase + 1 offsets into the round entries
+    const int32_t* ent_r;           // realisation of each round entry
+    const int32_t* ent_p;           // its pass
     const int64_t* qstart;          // [queue][entry]: first item of the entry's slice in the queue (estride per queue)
-    uint32_t* ticket;               // kEnsQueues ticket counters of this launch
-    uint32_t* arrive;               // per realisation: items finished
-    uint32_t* ready;                // per realisation: passes finished
+    uint32_t* ticket;               // kEnsQueues ticket counters of this launch (kCtlStride apart)
+    uint32_t* arrive;               // per realisation: items finished (kCtlStride apart)
+    uint32_t* ready;                // per realisation: passes finished (kCtlStride apart)
     int32_t* err;                   // raised when a wait times out
     int64_t pstride, estride;
     int32_t pb, pe;                 // phases [pb, pe) of this launch
