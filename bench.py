@@ -41,12 +41,12 @@ BYTES_PER_UPDATE = 16
 # digest (kernel_digest()) is recorded with it.  When the sources differ now
 # the counters no longer describe the kernel and the bench reports null.
 TRAFFIC_PER_LAUNCH = {
-    ("2d8192", 2, 64, 1, 8): {"bytes": 1158349282, "profile": "profiles/k_tb2d_2d8192.md",
-                              "sources": "8f7313174b557f8f"},
-    ("2d8192", 2, 128, 1, 8): {"bytes": 1134844850, "profile": "profiles/k_tb2d_2d8192.md",
-                               "sources": "8f7313174b557f8f"},
-    ("3d1024", 2, 32, 16, 4): {"bytes": 21622224782, "profile": "profiles/k_tb3l_3d1024.md",
-                               "sources": "8f7313174b557f8f"},
+    ("2d8192", 2, 64, 1, 8): {"bytes": 1158421670, "profile": "profiles/k_tb2d_2d8192.md",
+                              "sources": "3aa4af90161d06b9"},
+    ("2d8192", 2, 128, 1, 8): {"bytes": 1134860959, "profile": "profiles/k_tb2d_2d8192.md",
+                               "sources": "3aa4af90161d06b9"},
+    ("3d1024", 2, 32, 16, 4): {"bytes": 23485829245, "profile": "profiles/k_tb3l_3d1024.md",
+                               "sources": "3aa4af90161d06b9"},
 }
 
 WORKLOAD = {
@@ -549,6 +549,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip every leg after the headline and the copy")
     ap.add_argument("--tiling", default=None, help="vec,rows,ty for the main run (default: autotuned)")
     ap.add_argument("--steps-per-pass", type=int, default=2, help="with --tiling")
+    ap.add_argument("--leg", choices=("c2", "c3"), default="c2",
+                    help="c3: only the 1024^3 forward leg (with --tiling, --steps, --warmup) and the copy "
+                         "kernel, as one JSON line, for profiling that leg's pass kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the PRS path is built and timed on a single "
@@ -562,6 +565,12 @@ def main():
     w = WORKLOAD
     torch.cuda.set_device(0)
     tiling = [int(v) for v in args.tiling.split(",")] if args.tiling else None
+    if args.leg == "c3":
+        c3 = forward_leg(prs, torch, WORKLOAD_3D, args.steps, args.warmup, tiling, args.steps_per_pass)
+        c3["copy_ceiling"] = copy_ceiling(prs, torch)
+        c3["workload"] = WORKLOAD_3D["name"]
+        print(json.dumps(c3), flush=True)
+        return
     c2 = forward_leg(prs, torch, w, args.steps, args.warmup, tiling, args.steps_per_pass)
     roof = c2["roofline"]
     copy = copy_ceiling(prs, torch)

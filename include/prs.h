@@ -154,13 +154,17 @@ prs_status prs_set_state(prs_ctx* ctx, const void* phi, const void* dphi, int64_
 /* Choose the kernel tiling of this context (mainly for tests and the
  * autotuner).  vec: sites per lane along x (1, 2 or 4 in float32, 1 or 2 in
  * float64; must divide nx);
- * rows: planes per wave along the marching axis (y in 2D, z in 3D), 1..4096;
+ * rows: planes per wave along the marching axis (y in 2D, z in 3D), 1..4096
+ *   (the workspace holds the diagnostic partials of every tiling with rows
+ *   >= 8, and of shorter ones only where the tiles still fit: PRS_EINVAL
+ *   otherwise);
  * ty: in 3D, how a workgroup covers y: 1, 2 or 4 for one-wave workgroups
  * (single steps: 1, 2 or 4 rows per wave; multi-step passes: 4 rows per
  * wave, 8 with ty = 4), or 8, 16, 32, 64 for the LDS-staged multi-step
  * passes, whose workgroups stack waves along y and share their boundary rows
  * through LDS (8 waves of 2 or 4 rows for ty 8 or 16, 16 waves of 2 or 4
- * rows for ty 32 or 64; single steps on such a tiling use 4 rows per wave);
+ * rows for ty 32 or 64; single steps on such a tiling use one row per
+ * wave);
  * must be 1 in 2D.
  * Results are bit-identical for every tiling except the rounding order of the
  * two floating-point diagnostic sums. */

@@ -484,7 +484,7 @@ def test_lds_pass_bitwise_equal_single_steps(shape, K, steps):
         for vec in (1, 2):
             if shape[0] % vec:
                 continue
-            for t in ((vec, 8, 8), (vec, 13, 16), (vec, 64, 16), (vec, 5, 8), (vec, 11, 32)) + \
+            for t in ((vec, 8, 8), (vec, 13, 16), (vec, 64, 16), (vec, 9, 8), (vec, 11, 32)) + \
                     (((vec, 9, 64),) if vec == 1 else ()):
                 sim = prs.Sim(gp, phi0=to_dev(phi0))
                 sim.set_tiling(*t)

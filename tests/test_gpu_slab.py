@@ -24,6 +24,10 @@ pytestmark = pytest.mark.gpu
     ((48, 36, 30), 3, (1, 8, 4), 3, False, 2.0),
     ((40, 24, 20), 2, (1, 8, 2), 2, True, 0.0),
     ((32, 16, 8), 3, (1, 8, 1), 4, False, 0.0),   # slabs of 2 planes, thinner than their halos
+    ((64, 40, 32), 4, (2, 8, 16), 2, False, 0.0),  # the LDS-staged pass (eight waves of four rows)
+    ((48, 36, 30), 3, (1, 8, 8), 3, False, 2.0),   # eight waves of two rows
+    ((40, 24, 20), 4, (1, 8, 8), 2, True, 0.0),
+    ((48, 44, 24), 4, (1, 8, 64), 3, False, 0.0),  # sixteen waves of four rows, slabs of 8 planes
 ])
 def test_slab_passes_equal_the_whole_lattice(shape, T, tiling, nslab, f64, beta):
     torch = torch_mod()
@@ -145,6 +149,8 @@ def test_slab_full_size_in_the_benchmark_configurations(shape, T, tiling, nslab)
     ((64, 40, 32), 3, (1, 8, 2), 2, False, 0.0),
     ((48, 36, 30), 3, (1, 8, 4), 3, False, 2.0),
     ((40, 24, 20), 2, (1, 8, 2), 2, True, 0.0),
+    ((64, 40, 32), 4, (2, 8, 16), 2, False, 0.0),
+    ((40, 24, 20), 3, (1, 8, 8), 2, True, 2.0),
 ])
 def test_slab_pass_stats_add_up_to_the_whole_lattice(shape, T, tiling, nslab, f64, beta):
     """The slabs' records of their input state combine into the whole
