@@ -476,6 +476,10 @@ prs_status prs_batch_set_tiling(prs_batch* b, int32_t item, int32_t vec, int32_t
  * second phi_dot field multi-step passes need lives in the workspace. */
 prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps_per_pass);
 
+/* Current tiling and steps per pass of one item (any pointer may be NULL). */
+prs_status prs_batch_get_tiling(const prs_batch* b, int32_t item, int32_t* vec, int32_t* rows, int32_t* ty,
+                                int32_t* steps_per_pass);
+
 /* Device pointers of item `item`'s final phi and phi_dot after prs_batch_run
  * (phi_dot is always the item's dphi buffer). */
 prs_status prs_batch_state(const prs_batch* b, int32_t item, void** phi, void** dphi);
@@ -489,6 +493,23 @@ prs_status prs_batch_set_mode(prs_batch* b, int32_t mode);
  * PRS_EDEVICE instead of hanging.  PRS_EINVAL if the mode cannot run an
  * item's precision, tiling or steps per pass. */
 prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap);
+
+/* Ensemble-level tuning (Sec. IV: settings re-chosen by measurement on the
+ * card in use).  A realisation's own tuned setting is the fastest for it
+ * alone; inside an ensemble the other realisations also fill the GPU, and in
+ * the persistent modes taller marching tiles, which re-read fewer halo rows
+ * per stored row, can win.  Starting from the current settings, for each
+ * group of realisations that share a lattice and a setting (largest work
+ * first) the tuner doubles the rows (2D) or planes (3D) of the tiling, up
+ * to 128, while the whole ensemble in the current mode runs more than 2 %
+ * faster (each setting timed as the faster of two runs after one untimed
+ * run), keeping vec, ty and steps per pass; tilings the mode cannot run are
+ * skipped.  Every item must have init_from_seed = 1 (PRS_EINVAL otherwise),
+ * since the ensemble is run several times; the records of those runs are
+ * discarded and the buffers hold the last run's final fields.  *best_ms (may
+ * be NULL) receives the time of one run with the settings kept.
+ * Synchronises; allocates nothing on the device. */
+prs_status prs_batch_autotune(prs_batch* b, double* best_ms);
 
 void prs_batch_destroy(prs_batch* b);
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1932,6 +1933,17 @@ prs_status prs_batch_set_time_blocking(prs_batch* b, int32_t item, int32_t steps
     return PRS_OK;
 }
 
+prs_status prs_batch_get_tiling(const prs_batch* b, int32_t item, int32_t* vec, int32_t* rows, int32_t* ty,
+                                int32_t* steps_per_pass)
+{
+    if (!b || item < 0 || item >= b->count) return fail(PRS_EINVAL, "invalid batch or item");
+    if (vec) *vec = b->til[item].vec;
+    if (rows) *rows = b->til[item].rows;
+    if (ty) *ty = b->til[item].ty;
+    if (steps_per_pass) *steps_per_pass = b->tblock[item];
+    return PRS_OK;
+}
+
 prs_status prs_batch_set_mode(prs_batch* b, int32_t mode)
 {
     if (!b) return fail(PRS_EINVAL, "batch is NULL");
@@ -2031,6 +2043,92 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap)
     if (*b->herr != 0)
         return fail(PRS_EDEVICE, "batched run aborted: a wait of the ensemble kernel timed out");
     if (series) std::memcpy(series, b->hrec, (size_t)b->total_recs * sizeof(prs_stats));
+    return PRS_OK;
+}
+
+prs_status prs_batch_autotune(prs_batch* b, double* best_ms)
+{
+    if (!b) return fail(PRS_EINVAL, "batch is NULL");
+    for (int32_t r = 0; r < b->count; ++r)
+        if (!b->items[r].init_from_seed)
+            return fail(PRS_EINVAL, "item %d: the tuner reruns the ensemble, so every item must start from its seed",
+                        r);
+    // the fastest of two timed runs, after one that uploads the tables and
+    // captures the graph of the current settings
+    auto time_runs = [&](double* ms) -> prs_status {
+        prs_status st = prs_batch_run(b, nullptr, 0);
+        double best = 1e300;
+        for (int k = 0; k < 2 && st == PRS_OK; ++k) {
+            const auto t0 = std::chrono::steady_clock::now();
+            st = prs_batch_run(b, nullptr, 0);
+            const auto t1 = std::chrono::steady_clock::now();
+            best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        *ms = best;
+        return st;
+    };
+    // realisations with the same lattice and the same setting move together
+    struct Group {
+        std::vector<int32_t> items;
+        double work;
+    };
+    std::vector<Group> groups;
+    for (int32_t r = 0; r < b->count; ++r) {
+        const Geometry& g = b->geo[r];
+        const Tiling& t = b->til[r];
+        double work = (double)g.nx * (double)g.Q * (double)g.M * (double)b->items[r].nsteps;
+        bool placed = false;
+        for (Group& G : groups) {
+            const int32_t q = G.items[0];
+            const Geometry& h = b->geo[q];
+            const Tiling& u = b->til[q];
+            if (h.ndim == g.ndim && h.f64 == g.f64 && h.nx == g.nx && h.Q == g.Q && h.M == g.M && u.vec == t.vec &&
+                u.rows == t.rows && u.ty == t.ty && b->tblock[q] == b->tblock[r]) {
+                G.items.push_back(r);
+                G.work += work;
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) groups.push_back(Group{{r}, work});
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& c) { return a.work > c.work; });
+    const bool persistent = persistent_mode(b->mode);
+    double best = 0.0;
+    prs_status st = time_runs(&best);
+    if (st != PRS_OK) return st;
+    for (const Group& G : groups) {
+        const int32_t q = G.items[0];
+        const Geometry& g = b->geo[q];
+        const int T = b->tblock[q];
+        for (;;) {
+            const Tiling cur = b->til[q];
+            const Tiling next{cur.vec, cur.rows * 2, cur.ty};
+            // marching tiles longer than the tuner's longest, or than the
+            // lattice, are not tried
+            if (next.rows > 128 || cur.rows >= g.M) break;
+            if (!tiling_supported(g, next) || (T > 1 && !tb_pass_supported(g, next, T)) ||
+                (persistent && !ens_supported(g, next, T)) ||
+                item_tiles_max(g, next, std::max(2, T)) > b->part_cap[q])
+                break;
+            for (int32_t r : G.items) b->til[r] = next;
+            batch_release_graph(b);
+            b->dirty = true;
+            double ms = 0.0;
+            st = time_runs(&ms);
+            // a change must gain more than the runs' spread to be kept
+            if (st == PRS_OK && ms < best * 0.98) {
+                best = ms;
+                continue;
+            }
+            for (int32_t r : G.items) b->til[r] = cur;
+            batch_release_graph(b);
+            b->dirty = true;
+            if (st != PRS_OK) return st;
+            break;
+        }
+    }
+    if (best_ms) *best_ms = best;
     return PRS_OK;
 }
 

@@ -139,6 +139,9 @@ _decl("prs_batch_set_mode", _i32, _vp, _i32)
 _decl("prs_batch_set_time_blocking", _i32, _vp, _i32, _i32)
 _decl("prs_batch_state", _i32, _vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp))
 _decl("prs_batch_run", _i32, _vp, _S, _i64)
+_decl("prs_batch_autotune", _i32, _vp, ctypes.POINTER(_d))
+_decl("prs_batch_get_tiling", _i32, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+      ctypes.POINTER(_i32))
 _decl("prs_batch_destroy", None, _vp)
 _decl("prs_autotune", _i32, _vp, ctypes.c_char_p, _i32, _vp, _sz, ctypes.POINTER(_d))
 _decl("prs_tune_workspace_bytes", _sz, _vp, _i32)
@@ -173,7 +176,7 @@ EXPORTED = [
     "prs_adjoint_workspace_bytes", "prs_adjoint_forward", "prs_adjoint_backward", "prs_adjoint",
     "prs_batch_workspace_bytes", "prs_batch_create", "prs_batch_offsets", "prs_batch_set_tiling",
     "prs_batch_set_mode", "prs_batch_run", "prs_batch_destroy", "prs_batch_set_time_blocking",
-    "prs_batch_state", "prs_autotune", "prs_tuned_tiling",
+    "prs_batch_state", "prs_batch_autotune", "prs_batch_get_tiling", "prs_autotune", "prs_tuned_tiling",
     "prs_set_time_blocking", "prs_get_time_blocking", "prs_set_adjoint_tiling",
     "prs_get_adjoint_tiling", "prs_plan_passes", "prs_fill_uniform_f64",
     "prs_set_adjoint_time_blocking", "prs_get_adjoint_time_blocking",
@@ -469,6 +472,20 @@ def prs_batch_run(b, total_records):
     return [series[i].as_dict() for i in range(total_records)]
 
 
+def prs_batch_autotune(b):
+    """Time of one ensemble run (ms) with the settings the tuner kept."""
+    ms = _d()
+    _check(_lib.prs_batch_autotune(b, ctypes.byref(ms)), "prs_batch_autotune")
+    return ms.value
+
+
+def prs_batch_get_tiling(b, item):
+    """((vec, rows, ty), steps_per_pass) of one item."""
+    v = [_i32() for _ in range(4)]
+    _check(_lib.prs_batch_get_tiling(b, item, *(ctypes.byref(x) for x in v)), "prs_batch_get_tiling")
+    return (v[0].value, v[1].value, v[2].value), v[3].value
+
+
 def prs_batch_destroy(b):
     _lib.prs_batch_destroy(b)
 
@@ -723,6 +740,15 @@ class Batch:
 
     def set_time_blocking(self, item, steps_per_pass):
         prs_batch_set_time_blocking(self.b, item, steps_per_pass)
+
+    def tiling(self, item):
+        """((vec, rows, ty), steps_per_pass) of one realisation."""
+        return prs_batch_get_tiling(self.b, item)
+
+    def autotune(self):
+        """Refines the marching-tile lengths by timing the whole ensemble in
+        the current mode; returns the time of one run (ms)."""
+        return prs_batch_autotune(self.b)
 
     def run(self):
         """Runs the ensemble; returns one record list per realisation."""

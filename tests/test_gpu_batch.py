@@ -299,3 +299,43 @@ def test_mode_switches_keep_results(singles):
             np.testing.assert_array_equal(host(dphi), s_dphi)
             assert recs[r] == s_recs, (mode, r)
     b.close()
+
+
+@pytest.mark.parametrize("mode", [0, 4])
+def test_batch_autotune_keeps_results(singles_pk, mode):
+    """The ensemble-level tuner only lengthens marching tiles (doubling,
+    up to 128) and keeps vec, ty and steps per pass; afterwards every
+    realisation's field is still bit for bit its single run (fields do not
+    depend on the tiling), its counts too, and its two floating-point means
+    equal up to summation order."""
+    say("batch autotune mode", mode)
+    prs = gpu_prs()
+    specs = SPECS_PK if mode == 0 else SPECS_PK[:5]
+    b = prs.Batch(specs)
+    for r in range(len(specs)):
+        b.set_tiling(r, *TILINGS_PK[r])
+        b.set_time_blocking(r, steps_per_pass(specs[r]))
+    b.set_mode(mode)
+    ms = b.autotune()
+    assert ms > 0.0
+    for r in range(len(specs)):
+        (vec, rows, ty), T = b.tiling(r)
+        v0, r0, t0 = TILINGS_PK[r]
+        assert (vec, ty, T) == (v0, t0, steps_per_pass(specs[r])), r
+        assert rows >= r0 and rows % r0 == 0 and (rows // r0) & (rows // r0 - 1) == 0, (r, rows)
+        assert rows == r0 or rows <= 128, (r, rows)
+    for rep in range(2):
+        recs = b.run()
+        for r in range(len(specs)):
+            phi, dphi = b.final_state(r)
+            s_phi, s_dphi, s_recs = singles_pk[r]
+            np.testing.assert_array_equal(host(phi), s_phi)
+            np.testing.assert_array_equal(host(dphi), s_dphi)
+            want = s_recs if specs[r]["diag_every"] > 0 else s_recs[-1:]
+            assert len(recs[r]) == len(want), r
+            for g, o in zip(recs[r], want):
+                for k in ("step", "eta", "links", "links_dir", "wall_sites", "nonfinite"):
+                    assert g[k] == o[k], (r, k)
+                assert g["area_density"] == pytest.approx(o["area_density"], rel=1e-12, abs=1e-300)
+                assert g["gv2"] == pytest.approx(o["gv2"], rel=1e-12, abs=1e-300)
+    b.close()
