@@ -497,13 +497,15 @@ prs_status prs_batch_run(prs_batch* b, prs_stats* series, int64_t cap);
 /* Ensemble-level tuning (Sec. IV: settings re-chosen by measurement on the
  * card in use).  A realisation's own tuned setting is the fastest for it
  * alone; inside an ensemble the other realisations also fill the GPU, and in
- * the persistent modes taller marching tiles, which re-read fewer halo rows
- * per stored row, can win.  Starting from the current settings, for each
- * group of realisations that share a lattice and a setting (largest work
- * first) the tuner doubles the rows (2D) or planes (3D) of the tiling, up
- * to 128, while the whole ensemble in the current mode runs more than 2 %
- * faster (each setting timed as the faster of two runs after one untimed
- * run), keeping vec, ty and steps per pass; tilings the mode cannot run are
+ * the persistent modes taller tiles, which re-read fewer halo rows per
+ * stored row, can win.  Starting from the current settings, for each group
+ * of realisations that share a lattice and a setting (largest work first)
+ * the tuner times the candidates -- the rows (2D) or planes (3D) of the
+ * tiling doubled, up to 128, and for a 3D workgroup-stacked tiling (ty 8,
+ * 16, 32, 64) each other such ty with the longest pass the mode runs for
+ * it -- and keeps the fastest while the whole ensemble in the current mode
+ * runs more than 2 % faster (each setting timed as the faster of two runs
+ * after one untimed run); vec is kept, and settings the mode cannot run are
  * skipped.  Every item must have init_from_seed = 1 (PRS_EINVAL otherwise),
  * since the ensemble is run several times; the records of those runs are
  * discarded and the buffers hold the last run's final fields.  *best_ms (may

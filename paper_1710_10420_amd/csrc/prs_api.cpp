@@ -2100,31 +2100,63 @@ prs_status prs_batch_autotune(prs_batch* b, double* best_ms)
     for (const Group& G : groups) {
         const int32_t q = G.items[0];
         const Geometry& g = b->geo[q];
-        const int T = b->tblock[q];
+        // a setting the mode runs and the item's partial buffer holds
+        auto usable = [&](const Tiling& t, int T) {
+            if (!tiling_supported(g, t) || (T > 1 && !tb_pass_supported(g, t, T))) return false;
+            if (persistent && !ens_supported(g, t, T)) return false;
+            return item_tiles_max(g, t, std::max(2, T)) <= b->part_cap[q];
+        };
+        auto apply = [&](const Tiling& t, int T) {
+            for (int32_t r : G.items) {
+                b->til[r] = t;
+                b->tblock[r] = T;
+            }
+            batch_release_graph(b);
+            b->dirty = true;
+        };
         for (;;) {
             const Tiling cur = b->til[q];
-            const Tiling next{cur.vec, cur.rows * 2, cur.ty};
-            // marching tiles longer than the tuner's longest, or than the
-            // lattice, are not tried
-            if (next.rows > 128 || cur.rows >= g.M) break;
-            if (!tiling_supported(g, next) || (T > 1 && !tb_pass_supported(g, next, T)) ||
-                (persistent && !ens_supported(g, next, T)) ||
-                item_tiles_max(g, next, std::max(2, T)) > b->part_cap[q])
-                break;
-            for (int32_t r : G.items) b->til[r] = next;
-            batch_release_graph(b);
-            b->dirty = true;
-            double ms = 0.0;
-            st = time_runs(&ms);
+            const int T = b->tblock[q];
+            // candidates: the marching tile doubled (up to the tuner's
+            // longest, 128, and not past the lattice); in 3D, when the
+            // current tiling is a workgroup-stacked one, the other
+            // workgroup shapes, each with the longest pass the mode runs
+            std::vector<std::pair<Tiling, int>> cand;
+            const Tiling taller{cur.vec, cur.rows * 2, cur.ty};
+            if (taller.rows <= 128 && cur.rows < g.M && usable(taller, T)) cand.push_back({taller, T});
+            if (g.ndim == 3 && cur.ty >= 8 && T > 1) {
+                for (int ty : {8, 16, 32, 64}) {
+                    if (ty == cur.ty) continue;
+                    const Tiling t{cur.vec, cur.rows, ty};
+                    for (int U = 4; U >= 2; --U)
+                        if (usable(t, U)) {
+                            cand.push_back({t, U});
+                            break;
+                        }
+                }
+            }
+            double round_best = 1e300;
+            size_t pick = cand.size();
+            for (size_t c = 0; c < cand.size(); ++c) {
+                apply(cand[c].first, cand[c].second);
+                double ms = 0.0;
+                st = time_runs(&ms);
+                if (st != PRS_OK) {
+                    apply(cur, T);
+                    return st;
+                }
+                if (ms < round_best) {
+                    round_best = ms;
+                    pick = c;
+                }
+            }
             // a change must gain more than the runs' spread to be kept
-            if (st == PRS_OK && ms < best * 0.98) {
-                best = ms;
+            if (pick < cand.size() && round_best < best * 0.98) {
+                apply(cand[pick].first, cand[pick].second);
+                best = round_best;
                 continue;
             }
-            for (int32_t r : G.items) b->til[r] = cur;
-            batch_release_graph(b);
-            b->dirty = true;
-            if (st != PRS_OK) return st;
+            apply(cur, T);
             break;
         }
     }

@@ -304,10 +304,11 @@ def test_mode_switches_keep_results(singles):
 @pytest.mark.parametrize("mode", [0, 4])
 def test_batch_autotune_keeps_results(singles_pk, mode):
     """The ensemble-level tuner only lengthens marching tiles (doubling,
-    up to 128) and keeps vec, ty and steps per pass; afterwards every
-    realisation's field is still bit for bit its single run (fields do not
-    depend on the tiling), its counts too, and its two floating-point means
-    equal up to summation order."""
+    up to 128) and, for 3D workgroup-stacked tilings, changes the workgroup
+    shape and steps per pass; vec, and in 2D ty and steps per pass, stay.
+    Afterwards every realisation's field is still bit for bit its single run
+    (fields depend on neither tiling nor steps per pass), its counts too,
+    and its two floating-point means equal up to summation order."""
     say("batch autotune mode", mode)
     prs = gpu_prs()
     specs = SPECS_PK if mode == 0 else SPECS_PK[:5]
@@ -321,7 +322,10 @@ def test_batch_autotune_keeps_results(singles_pk, mode):
     for r in range(len(specs)):
         (vec, rows, ty), T = b.tiling(r)
         v0, r0, t0 = TILINGS_PK[r]
-        assert (vec, ty, T) == (v0, t0, steps_per_pass(specs[r])), r
+        if len(specs[r]["shape"]) == 3 and t0 >= 8 and steps_per_pass(specs[r]) > 1:
+            assert vec == v0 and ty in (8, 16, 32, 64) and T in (2, 3, 4), (r, ty, T)
+        else:
+            assert (vec, ty, T) == (v0, t0, steps_per_pass(specs[r])), r
         assert rows >= r0 and rows % r0 == 0 and (rows // r0) & (rows // r0 - 1) == 0, (r, rows)
         assert rows == r0 or rows <= 128, (r, rows)
     for rep in range(2):
@@ -338,4 +342,27 @@ def test_batch_autotune_keeps_results(singles_pk, mode):
                     assert g[k] == o[k], (r, k)
                 assert g["area_density"] == pytest.approx(o["area_density"], rel=1e-12, abs=1e-300)
                 assert g["gv2"] == pytest.approx(o["gv2"], rel=1e-12, abs=1e-300)
+    b.close()
+
+
+def test_batch_autotune_requires_seeded_items():
+    """The ensemble tuner reruns the ensemble, so it refuses an ensemble
+    whose items start from their buffers' contents (before any launch)."""
+    prs = gpu_prs()
+    torch = torch_mod()
+    b = prs.Batch(SPECS[:2])
+    items = []
+    for it in b.items:
+        c = prs.prs_batch_item.from_buffer_copy(it)
+        c.init_from_seed = 0
+        items.append(c)
+    nb = prs.prs_batch_workspace_bytes(items)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    h = prs.prs_batch_create(items, ws.data_ptr(), nb, prs._stream_handle(torch.cuda.current_stream()))
+    try:
+        with pytest.raises(prs.PRSError) as e:
+            prs.prs_batch_autotune(h)
+        assert e.value.status == prs.PRS_EINVAL and "item 0" in str(e.value)
+    finally:
+        prs.prs_batch_destroy(h)
     b.close()
