@@ -2189,7 +2189,7 @@ void prs_batch_destroy(prs_batch* b)
 
 namespace {
 
-constexpr const char* kTuneVersion = "k3";
+constexpr const char* kTuneVersion = "k4";
 
 std::string tune_key(const prs_params& p, bool batch_set)
 {
@@ -2364,10 +2364,39 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
     // costs inside the backward.
     const Tiling rt = c->rec_tblock > 0 ? c->rec_til : c->til;
     const bool fused = c->adj_scheme == PRS_ADJ_FUSED && c->geo.ndim == 2 && tb_supported(c->geo) && nphi >= 6;
+    // Besides the power-of-two row tiles: on lattices whose reverse pass has
+    // only a few workgroups per compute unit, the heights that make the
+    // workgroup count a whole number of rounds over the compute units (a
+    // partial last round leaves the units that got one workgroup fewer idle
+    // while it runs): for each vec and k = 1 .. 8, the shortest tile of at
+    // most k workgroups per unit.
+    int ncu = 0;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 0;
+    }
     for (int T : {2, 3, 4}) {
         if (!fused) break;
         if (!tb_pass_supported(c->geo, rt, T)) continue;
-        for (const Tiling& t : cand) {
+        std::vector<Tiling> fcand = cand;
+        for (int vec : {1, 2, 4}) {
+            if (ncu <= 0) break;
+            for (int k = 1; k <= 8; ++k) {
+                for (int r = (int)kMinRows; r <= 128; ++r) {
+                    const Tiling t{vec, r, 1};
+                    if (!tbf_supported(c->geo, t, T)) break;
+                    if (tbf_workgroups(c->geo, t, T) <= (int64_t)k * ncu) {
+                        bool seen = false;
+                        for (const Tiling& u : fcand) seen = seen || (u.vec == t.vec && u.rows == t.rows && u.ty == 1);
+                        if (!seen) fcand.push_back(t);
+                        break;
+                    }
+                }
+            }
+        }
+        for (const Tiling& t : fcand) {
             if (e != hipSuccess) break;
             if (!tbf_supported(c->geo, t, T) || tbf_tiles(c->geo, t, T) > c->partial_cap) continue;
             char* a = w0;

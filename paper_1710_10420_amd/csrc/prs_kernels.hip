@@ -288,6 +288,11 @@ int64_t tbf_tiles(const Geometry& g, const Tiling& t, int T)
     return ((g.nx + W - 1) / W) * ((g.M + t.rows - 1) / t.rows);
 }
 
+int64_t tbf_workgroups(const Geometry& g, const Tiling& t, int T)
+{
+    return (tbf_tiles(g, t, T) + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
 hipError_t launch_tbf(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
                       const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
                       const StepCoef64* k, const AdjCoef64* c, hipStream_t s)
