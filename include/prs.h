@@ -175,7 +175,11 @@ prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty
  * card, and another card needs them chosen again; here the choice is made
  * by timing on the card in use).  Times every supported tiling and steps per
  * pass for this lattice on the context's own state (saved into the caller's
- * workspace before and restored after each candidate), applies the fastest
+ * workspace before and restored after each candidate) -- rows 8 to 128 in
+ * powers of two and, for 2D multi-step passes (and the 2D reverse pass),
+ * the row heights that make a pass's workgroup count a whole number of
+ * rounds over the device's compute units where that count is small (up to
+ * four workgroups per unit; eight for the reverse pass) -- applies the fastest
  * to the context and records it in the JSON file cache_path (created or
  * updated; NULL or "" for no cache).  A cached entry for the same GPU
  * architecture, dimension, lattice size and tiling set is applied without

@@ -2252,6 +2252,39 @@ bool tune_write(const char* path, const std::map<std::string, TuneEntry>& m)
     return std::rename(tmp.c_str(), path) == 0;
 }
 
+int device_compute_units()
+{
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return ncu;
+}
+
+// Row heights that make a pass's workgroup count a whole number of rounds
+// over the compute units: for each vec and k = 1 .. kmax, the shortest tile
+// (kMinRows .. 128 rows) with at most k workgroups per unit, when the
+// setting is usable and not already among `have`.  On lattices whose pass
+// has only a few waves per SIMD, a partial last round leaves the units that
+// got one workgroup fewer idle while it runs.
+template <typename Usable, typename Workgroups>
+void add_balanced_rows(std::vector<Tiling>& have, int kmax, int ncu, Usable usable, Workgroups workgroups)
+{
+    if (ncu <= 0) return;
+    for (int vec : {1, 2, 4})
+        for (int k = 1; k <= kmax; ++k)
+            for (int r = (int)kMinRows; r <= 128; ++r) {
+                const Tiling t{vec, r, 1};
+                if (!usable(t)) break;
+                if (workgroups(t) <= (int64_t)k * ncu) {
+                    bool seen = false;
+                    for (const Tiling& u : have) seen = seen || (u.vec == t.vec && u.rows == t.rows && u.ty == t.ty);
+                    if (!seen) have.push_back(t);
+                    break;
+                }
+            }
+}
+
 std::vector<Tiling> tune_candidates(const Geometry& g, bool batch_set)
 {
     std::vector<Tiling> out;
@@ -2364,38 +2397,17 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
     // costs inside the backward.
     const Tiling rt = c->rec_tblock > 0 ? c->rec_til : c->til;
     const bool fused = c->adj_scheme == PRS_ADJ_FUSED && c->geo.ndim == 2 && tb_supported(c->geo) && nphi >= 6;
-    // Besides the power-of-two row tiles: on lattices whose reverse pass has
-    // only a few workgroups per compute unit, the heights that make the
-    // workgroup count a whole number of rounds over the compute units (a
-    // partial last round leaves the units that got one workgroup fewer idle
-    // while it runs): for each vec and k = 1 .. 8, the shortest tile of at
-    // most k workgroups per unit.
-    int ncu = 0;
-    {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            ncu = 0;
-    }
+    // Besides the power-of-two row tiles, the heights that give the reverse
+    // pass a whole number of workgroup rounds (at 2048^2 it has two or three
+    // waves per SIMD).
+    const int ncu = device_compute_units();
     for (int T : {2, 3, 4}) {
         if (!fused) break;
         if (!tb_pass_supported(c->geo, rt, T)) continue;
         std::vector<Tiling> fcand = cand;
-        for (int vec : {1, 2, 4}) {
-            if (ncu <= 0) break;
-            for (int k = 1; k <= 8; ++k) {
-                for (int r = (int)kMinRows; r <= 128; ++r) {
-                    const Tiling t{vec, r, 1};
-                    if (!tbf_supported(c->geo, t, T)) break;
-                    if (tbf_workgroups(c->geo, t, T) <= (int64_t)k * ncu) {
-                        bool seen = false;
-                        for (const Tiling& u : fcand) seen = seen || (u.vec == t.vec && u.rows == t.rows && u.ty == 1);
-                        if (!seen) fcand.push_back(t);
-                        break;
-                    }
-                }
-            }
-        }
+        add_balanced_rows(
+            fcand, 8, ncu, [&](const Tiling& t) { return tbf_supported(c->geo, t, T); },
+            [&](const Tiling& t) { return tbf_workgroups(c->geo, t, T); });
         for (const Tiling& t : fcand) {
             if (e != hipSuccess) break;
             if (!tbf_supported(c->geo, t, T) || tbf_tiles(c->geo, t, T) > c->partial_cap) continue;
@@ -2599,10 +2611,22 @@ prs_status prs_autotune(prs_ctx* c, const char* cache_path, int32_t flags, void*
     int best_T = c->tblock;
     e = hipMemcpyAsync(save_phi, c->phi[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(save_pi, c->pi, bytes, hipMemcpyDeviceToDevice, c->stream);
+    const int ncu = device_compute_units();
     for (int T = 1; T <= max_T; ++T) {
         if (T > 1 && !tb_steps_supported(c->geo, T)) continue;
         per = T;
-        for (const Tiling& t : cand) {
+        // 2D multi-step passes also try the heights that give a whole number
+        // of workgroup rounds, up to four per compute unit (lattices whose
+        // pass fills the units many times over get none)
+        std::vector<Tiling> tcand = cand;
+        if (c->geo.ndim == 2 && T > 1)
+            add_balanced_rows(
+                tcand, 4, ncu,
+                [&](const Tiling& t) {
+                    return tb_pass_supported(c->geo, t, T) && (!batch_set || ens_supported(c->geo, t, T));
+                },
+                [&](const Tiling& t) { return tb2_workgroups(c->geo, t, T); });
+        for (const Tiling& t : tcand) {
             if (e != hipSuccess) break;
             if (T > 1 && !tb_pass_supported(c->geo, t, T)) continue;
             if (batch_set && !ens_supported(c->geo, t, T)) continue;

@@ -178,6 +178,7 @@ hipError_t launch_tb_mid_f64(int T, const Geometry& g, const Tiling& t, const vo
 bool tbf_supported(const Geometry& g, const Tiling& t, int T);
 int64_t tbf_tiles(const Geometry& g, const Tiling& t, int T);
 int64_t tbf_workgroups(const Geometry& g, const Tiling& t, int T);   // of one launch
+int64_t tb2_workgroups(const Geometry& g, const Tiling& t, int T);   // of one 2D T-step launch
 hipError_t launch_tbf(int T, const Geometry& g, const Tiling& t, const void* phi_s, const void* pi_s,
                       const void* w_in, void* w_out, const void* mu_in, void* mu_out, double* gacc,
                       const StepCoef64* k, const AdjCoef64* c, hipStream_t s);

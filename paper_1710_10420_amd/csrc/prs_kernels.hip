@@ -288,6 +288,11 @@ int64_t tbf_tiles(const Geometry& g, const Tiling& t, int T)
     return ((g.nx + W - 1) / W) * ((g.M + t.rows - 1) / t.rows);
 }
 
+int64_t tb2_workgroups(const Geometry& g, const Tiling& t, int T)
+{
+    return (tb_tiles(g, t, T) + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
 int64_t tbf_workgroups(const Geometry& g, const Tiling& t, int T)
 {
     return (tbf_tiles(g, t, T) + kWavesPerBlock - 1) / kWavesPerBlock;
