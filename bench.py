@@ -41,12 +41,12 @@ BYTES_PER_UPDATE = 16
 # digest (kernel_digest()) is recorded with it.  When the sources differ now
 # the counters no longer describe the kernel and the bench reports null.
 TRAFFIC_PER_LAUNCH = {
-    ("2d8192", 2, 64, 1, 8): {"bytes": 1158421670, "profile": "profiles/k_tb2d_2d8192.md",
-                              "sources": "3aa4af90161d06b9"},
-    ("2d8192", 2, 128, 1, 8): {"bytes": 1134860959, "profile": "profiles/k_tb2d_2d8192.md",
-                               "sources": "3aa4af90161d06b9"},
-    ("3d1024", 2, 32, 16, 4): {"bytes": 23485829245, "profile": "profiles/k_tb3l_3d1024.md",
-                               "sources": "3aa4af90161d06b9"},
+    ("2d8192", 4, 71, 1, 8): {"bytes": 1132171638, "profile": "profiles/k_tb2d_2d8192.md",
+                              "sources": "b7b7a7ed00d3f01c"},
+    ("2d8192", 2, 64, 1, 8): {"bytes": 1158439244, "profile": "profiles/k_tb2d_2d8192.md",
+                              "sources": "b7b7a7ed00d3f01c"},
+    ("3d1024", 2, 32, 16, 4): {"bytes": 23574425145, "profile": "profiles/k_tb3l_3d1024.md",
+                               "sources": "b7b7a7ed00d3f01c"},
 }
 
 WORKLOAD = {
