@@ -196,7 +196,11 @@ prs_status prs_get_tiling(prs_ctx* ctx, int32_t* vec, int32_t* rows, int32_t* ty
  *                      with PRS_TUNE_MIN_WORKSPACE added to its flags and
  *                      fills what is beyond it with up to 32 distinct phi
  *                      fields, which the timed reverse steps read in
- *                      rotation as the backward does.
+ *                      rotation as the backward does; with twelve or more,
+ *                      the fused scheme's candidates are timed with the
+ *                      recomputation running on a second stream beside the
+ *                      reverse passes, each on half of the fields, as in
+ *                      the backward.
  * *best_us (may be NULL) receives the time of one step with the chosen
  * tiling.  Synchronises. */
 #define PRS_TUNE_FORCE 1

@@ -1039,6 +1039,41 @@ int adj_pass_len(const Geometry& g, const Tiling& t, int64_t cap, int T, int64_t
 
 }  // namespace
 
+}  // extern "C"
+
+namespace {
+
+// The second stream and events of the backward (the recomputation of the
+// next-older segment runs on it beside the reverse sweep), created on first
+// use on the device of the context's stream, at the default priority.
+prs_status adj_aux_ready(prs_ctx* c)
+{
+    if (c->adj_aux) return PRS_OK;
+    int cur = 0;
+    hipDevice_t dev = 0;
+    HIP_TRY(hipGetDevice(&cur), "device query");
+    HIP_TRY(hipStreamGetDevice(c->stream, &dev), "stream device query");
+    HIP_TRY(hipSetDevice((int)dev), "set device");
+    hipError_t e = hipStreamCreateWithFlags(&c->adj_aux, hipStreamNonBlocking);
+    for (hipEvent_t& ev : c->adj_ev)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+        if (c->adj_aux) (void)hipStreamDestroy(c->adj_aux);
+        for (hipEvent_t& ev : c->adj_ev) {
+            if (ev) (void)hipEventDestroy(ev);
+            ev = nullptr;
+        }
+        c->adj_aux = nullptr;
+        return hip_fail(e, "stream/event create");
+    }
+    return PRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void* grad_phi0, void* grad_dphi0,
                                 double* grad_W0)
 {
@@ -1206,26 +1241,9 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     // sweep of sg waits for its own recomputation.  The results do not depend
     // on the overlap (each kernel's inputs are complete when it starts).
     const bool overlap = L.nseg > 1;
-    if (overlap && !c->adj_aux) {
-        // on the device of the context's stream, whatever device is current
-        int cur = 0;
-        hipDevice_t dev = 0;
-        HIP_TRY(hipGetDevice(&cur), "device query");
-        HIP_TRY(hipStreamGetDevice(c->stream, &dev), "stream device query");
-        HIP_TRY(hipSetDevice((int)dev), "set device");
-        hipError_t e = hipStreamCreateWithFlags(&c->adj_aux, hipStreamNonBlocking);
-        for (hipEvent_t& ev : c->adj_ev)
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        (void)hipSetDevice(cur);
-        if (e != hipSuccess) {
-            if (c->adj_aux) (void)hipStreamDestroy(c->adj_aux);
-            for (hipEvent_t& ev : c->adj_ev) {
-                if (ev) (void)hipEventDestroy(ev);
-                ev = nullptr;
-            }
-            c->adj_aux = nullptr;
-            return hip_fail(e, "stream/event create");
-        }
+    if (overlap) {
+        prs_status st = adj_aux_ready(c);
+        if (st != PRS_OK) return st;
     }
     hipStream_t rs = overlap ? c->adj_aux : c->stream;
     if (overlap) {
@@ -2376,6 +2394,18 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
     auto phi_of = [&](int n) -> const void* {
         return nphi > 0 ? static_cast<const void*>(phis0 + (size_t)(n % nphi) * fb) : c->phi[c->cur];
     };
+    // With twelve or more fields the fused scheme's reverse passes and its
+    // recomputation each rotate through half of them (their own fields, so
+    // that the two streams share no data); otherwise both use them all.
+    bool split = false;
+    auto phi_rev = [&](int n) -> const void* {
+        return split ? static_cast<const void*>(phis0 + (size_t)(n % (nphi / 2)) * fb) : phi_of(n);
+    };
+    auto phi_fwd = [&](int n) -> void* {
+        const int h = nphi / 2;
+        return const_cast<void*>(split ? static_cast<const void*>(phis0 + (size_t)(h + n % (nphi - h)) * fb)
+                                       : phi_of(n));
+    };
     if (e == hipSuccess) e = hipMemcpyAsync(w0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(mu0, c->phi[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream);
     for (int i = 0; i < nphi && e == hipSuccess; ++i)
@@ -2401,6 +2431,15 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
     // pass a whole number of workgroup rounds (at 2048^2 it has two or three
     // waves per SIMD).
     const int ncu = device_compute_units();
+    if (fused && nphi >= 12) {
+        prs_status st = adj_aux_ready(c);
+        if (st != PRS_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+        }
+        split = true;
+    }
     for (int T : {2, 3, 4}) {
         if (!fused) break;
         if (!tb_pass_supported(c->geo, rt, T)) continue;
@@ -2417,7 +2456,15 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
             char* mb = mu1;
             auto run = [&](int steps) -> hipError_t {
                 const bool mid = tb_mid_supported(c->geo, rt, 2 * T);
-                for (int k = 0; k < steps; k += T) {
+                // as in the backward, the recomputation runs on the second
+                // stream beside the reverse passes, on fields of its own
+                // (the second half of the rotation), when there are enough
+                hipError_t err = hipSuccess;
+                if (split) {
+                    err = hipEventRecord(c->adj_ev[0], c->stream);
+                    if (err == hipSuccess) err = hipStreamWaitEvent(c->adj_aux, c->adj_ev[0], 0);
+                }
+                for (int k = 0; k < steps && err == hipSuccess; k += T) {
                     StepCoef64 kk[kMaxPassSteps];
                     AdjCoef64 cc[kMaxPassSteps];
                     for (int i = 0; i < 2 * T && i < kMaxPassSteps; ++i) kk[i] = coef_for(c, c->step);
@@ -2425,23 +2472,25 @@ prs_status autotune_adjoint(prs_ctx* c, const char* cache_path, int32_t flags, v
                     // pass-start states and the forward's outputs in rotation;
                     // one forward pass of 2T steps per two reverse passes
                     // where it has a kernel, as in the backward
-                    const void* ps = phi_of(k);
-                    const void* pp = phi_of(k + 1);
-                    hipError_t err = hipSuccess;
+                    const void* ps = phi_rev(k);
+                    const void* pp = phi_rev(k + 1);
+                    auto fwd = [&](int i) { return phi_fwd(k + i); };
+                    hipStream_t fs = split ? c->adj_aux : c->stream;
                     if (!mid)
-                        err = launch_tb(T, c->geo, rt, ps, const_cast<void*>(phi_of(k + 2)), pp,
-                                        const_cast<void*>(phi_of(k + 3)), kk, false, nullptr, DiagCoef{}, c->stream);
+                        err = launch_tb(T, c->geo, rt, fwd(0), fwd(2), fwd(1), fwd(3), kk, false, nullptr, DiagCoef{},
+                                        fs);
                     else if ((k / T) % 2 == 0)
-                        err = launch_tb_mid(2 * T, c->geo, rt, ps, const_cast<void*>(phi_of(k + 2)), pp,
-                                            const_cast<void*>(phi_of(k + 3)), const_cast<void*>(phi_of(k + 4)),
-                                            const_cast<void*>(phi_of(k + 5)), kk, c->stream);
+                        err = launch_tb_mid(2 * T, c->geo, rt, fwd(0), fwd(2), fwd(1), fwd(3), fwd(4), fwd(5), kk, fs);
                     if (err == hipSuccess)
                         err = launch_tbf(T, c->geo, t, ps, pp, a, b, ma, mb, gacc, kk, cc, c->stream);
-                    if (err != hipSuccess) return err;
                     std::swap(a, b);
                     std::swap(ma, mb);
                 }
-                return hipSuccess;
+                if (split && err == hipSuccess) {
+                    err = hipEventRecord(c->adj_ev[1], c->adj_aux);
+                    if (err == hipSuccess) err = hipStreamWaitEvent(c->stream, c->adj_ev[1], 0);
+                }
+                return err;
             };
             e = run(2 * T);
             if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
