@@ -1239,8 +1239,12 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
     // segment sg-1 runs on a second stream while segment sg is swept: it
     // waits for the sweep of sg+1 (the last reader of its buffer), and the
     // sweep of sg waits for its own recomputation.  The results do not depend
-    // on the overlap (each kernel's inputs are complete when it starts).
-    const bool overlap = L.nseg > 1;
+    // on the overlap (each kernel's inputs are complete when it starts).  Only
+    // the fused scheme overlaps: its kernels are bound by arithmetic and leave
+    // room for each other, while the stored scheme's recomputation and
+    // reverse passes are both bound by HBM and gain nothing side by side, so
+    // they run in line on the one stream.
+    const bool overlap = L.nseg > 1 && fused;
     if (overlap) {
         prs_status st = adj_aux_ready(c);
         if (st != PRS_OK) return st;
@@ -1259,6 +1263,10 @@ prs_status prs_adjoint_backward(prs_ctx* c, void* work, size_t work_bytes, void*
             st = recompute(sg - 1, rs);
             if (st != PRS_OK) return st;
             HIP_TRY(hipEventRecord(c->adj_ev[1 + ((sg - 1) & 1)], rs), "event record");
+        } else if (!overlap && sg + 1 < L.nseg) {
+            // in line: segment sg is recomputed after segment sg+1 is swept
+            st = recompute(sg, c->stream);
+            if (st != PRS_OK) return st;
         }
         if (overlap) HIP_TRY(hipStreamWaitEvent(c->stream, c->adj_ev[1 + (sg & 1)], 0), "stream wait");
         st = sweep(sg);
